@@ -1,0 +1,207 @@
+"""CPU oracle for the CRBM Gibbs sampler of the Shastry-Sutherland Ising lattice.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg of
+the benchmark may import this package; the product path never does.  It wraps
+the plain single-threaded C oracle (``crbm_oracle.c``) with ctypes and adds the
+numpy parts (autoregressive network, Metropolis-Hastings, autocorrelation
+statistics).  Nothing here is shared with the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "crbm_oracle.c")
+
+SCHED = {"const": 0, "linear": 1, "geometric": 2, "explicit": 3}
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (-O2, no intrinsics, single-threaded)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"]
+        )
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Instance(ct.Structure):
+    _fields_ = [
+        ("L", ct.c_int32),
+        ("J1", ct.c_double),
+        ("J2", ct.c_double),
+        ("h", ct.c_double),
+        ("sched_kind", ct.c_int32),
+        ("T0", ct.c_double),
+        ("T1", ct.c_double),
+        ("T_explicit", ct.POINTER(ct.c_double)),
+        ("id", ct.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        L = ct.CDLL(_LIB_PATH)
+        u32, i64, i32, dbl = ct.c_uint32, ct.c_int64, ct.c_int32, ct.c_double
+        p = ct.POINTER
+        L.oracle_philox4x32_10.argtypes = [p(u32), p(u32), p(u32)]
+        L.oracle_uniform_hidden.argtypes = [ct.c_uint64, u32, u32, u32, ct.c_int, ct.c_int, ct.c_int, ct.c_int]
+        L.oracle_uniform_hidden.restype = u32
+        L.oracle_uniform_visible.argtypes = [ct.c_uint64, u32, u32, u32, ct.c_int, ct.c_int, ct.c_int]
+        L.oracle_uniform_visible.restype = u32
+        L.oracle_quantise.argtypes = [dbl]
+        L.oracle_quantise.restype = i64
+        L.oracle_schedule_T.argtypes = [ct.c_int, dbl, dbl, p(dbl), i64, i64]
+        L.oracle_schedule_T.restype = dbl
+        L.oracle_bond_weight.argtypes = [i64, dbl, p(i64), p(ct.c_int)]
+        L.oracle_visible_bias.argtypes = [i64, dbl]
+        L.oracle_visible_bias.restype = i64
+        L.oracle_threshold.argtypes = [i64]
+        L.oracle_threshold.restype = u32
+        L.oracle_bond_sites.argtypes = [ct.c_int] * 4 + [p(ct.c_int)] * 5
+        L.oracle_counts.argtypes = [ct.c_int, p(ct.c_int8), p(i64), p(i64), p(i64)]
+        L.oracle_corr.argtypes = [ct.c_int, p(ct.c_int8), p(i64)]
+        L.oracle_init_spins.argtypes = [p(_Instance), ct.c_uint64, u32, p(ct.c_int8)]
+        L.oracle_run_chain.argtypes = [p(_Instance), i64, ct.c_uint64, u32, i64, i64,
+                                       p(ct.c_int8), p(i32), i32, i64, p(i64)]
+        L.oracle_run_chain.restype = ct.c_int
+        L.oracle_log_marginal.argtypes = [p(_Instance), i64, i64, p(ct.c_int8)]
+        L.oracle_log_marginal.restype = dbl
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ct.POINTER(ctype))
+
+
+class Instance:
+    """One Hamiltonian point: lattice side L, couplings, schedule, RNG id."""
+
+    def __init__(self, L, J1=1.0, J2=0.5, h=0.0, sched="const", T0=1.0, T1=None,
+                 T_explicit=None, id=0):
+        self.L, self.J1, self.J2, self.h = int(L), float(J1), float(J2), float(h)
+        self.sched = sched
+        self.T0 = float(T0)
+        self.T1 = float(T0 if T1 is None else T1)
+        self.T_explicit = None if T_explicit is None else np.ascontiguousarray(T_explicit, np.float64)
+        self.id = int(id)
+
+    def c(self) -> _Instance:
+        te = None if self.T_explicit is None else _ptr(self.T_explicit, ct.c_double)
+        return _Instance(self.L, self.J1, self.J2, self.h, SCHED[self.sched], self.T0, self.T1, te, self.id)
+
+
+# ------------------------------------------------------------------ primitives
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    o = np.zeros(4, np.uint32)
+    lib().oracle_philox4x32_10(_ptr(c, ct.c_uint32), _ptr(k, ct.c_uint32), _ptr(o, ct.c_uint32))
+    return o
+
+
+def uniform_hidden(seed, id, chain, sweep, L, k, i, j) -> int:
+    return int(lib().oracle_uniform_hidden(seed, id, chain, sweep, L, k, i, j))
+
+
+def uniform_visible(seed, id, chain, sweep, L, r, c) -> int:
+    return int(lib().oracle_uniform_visible(seed, id, chain, sweep, L, r, c))
+
+
+def quantise(J) -> int:
+    return int(lib().oracle_quantise(float(J)))
+
+
+def schedule_T(inst: Instance, S: int, s: int) -> float:
+    te = None if inst.T_explicit is None else _ptr(inst.T_explicit, ct.c_double)
+    return float(lib().oracle_schedule_T(SCHED[inst.sched], inst.T0, inst.T1, te, S, s))
+
+
+def bond_weight(Jq: int, T: float):
+    wq = ct.c_int64()
+    sg = ct.c_int()
+    lib().oracle_bond_weight(int(Jq), float(T), ct.byref(wq), ct.byref(sg))
+    return int(wq.value), int(sg.value)
+
+
+def visible_bias(hq: int, T: float) -> int:
+    return int(lib().oracle_visible_bias(int(hq), float(T)))
+
+
+def threshold(y: int) -> int:
+    return int(lib().oracle_threshold(int(y)))
+
+
+def bond_sites(L, k, i, j):
+    v = [ct.c_int() for _ in range(5)]
+    lib().oracle_bond_sites(L, k, i, j, *[ct.byref(x) for x in v])
+    ra, ca, rb, cb, t = (x.value for x in v)
+    return (ra, ca), (rb, cb), t
+
+
+def counts(L, spins) -> tuple[int, int, int]:
+    s = np.ascontiguousarray(spins, np.int8).reshape(L * L)
+    M, B1, B2 = ct.c_int64(), ct.c_int64(), ct.c_int64()
+    lib().oracle_counts(L, _ptr(s, ct.c_int8), ct.byref(M), ct.byref(B1), ct.byref(B2))
+    return M.value, B1.value, B2.value
+
+
+def corr(L, spins) -> np.ndarray:
+    s = np.ascontiguousarray(spins, np.int8).reshape(L * L)
+    out = np.zeros(L * L, np.int64)
+    lib().oracle_corr(L, _ptr(s, ct.c_int8), _ptr(out, ct.c_int64))
+    return out.reshape(L, L)
+
+
+def init_spins(inst: Instance, seed: int, chain: int) -> np.ndarray:
+    s = np.zeros(inst.L * inst.L, np.int8)
+    ci = inst.c()
+    lib().oracle_init_spins(ct.byref(ci), seed, chain, _ptr(s, ct.c_int8))
+    return s.reshape(inst.L, inst.L)
+
+
+def log_marginal(inst: Instance, S: int, sweep: int, spins) -> float:
+    s = np.ascontiguousarray(spins, np.int8).reshape(inst.L * inst.L)
+    ci = inst.c()
+    return float(lib().oracle_log_marginal(ct.byref(ci), S, sweep, _ptr(s, ct.c_int8)))
+
+
+N_ACC = 11  # n, M, B1, B2, MM, B1B1, B2B2, MB1, MB2, B1B2, |M|
+
+
+def run_chain(inst: Instance, S: int, seed: int, chain: int, sweep_begin: int, sweep_end: int,
+              spins=None, trace=False, measure_every=0, burn_in=0, acc=None):
+    """Run sweeps [sweep_begin, sweep_end) of one chain.
+
+    spins: None -> initialise from the init stream; else an (L, L) int8 array
+    of +-1 (copied).  Returns (spins, trace or None, acc)."""
+    L = inst.L
+    if spins is None:
+        s = init_spins(inst, seed, chain).reshape(L * L).copy()
+    else:
+        s = np.ascontiguousarray(spins, np.int8).reshape(L * L).copy()
+    n = sweep_end - sweep_begin
+    tr = np.zeros((n, 3), np.int32) if trace else None
+    a = np.zeros(N_ACC, np.int64) if acc is None else acc
+    ci = inst.c()
+    rc = lib().oracle_run_chain(
+        ct.byref(ci), S, seed, chain, sweep_begin, sweep_end, _ptr(s, ct.c_int8),
+        _ptr(tr, ct.c_int32) if trace else None, measure_every, burn_in, _ptr(a, ct.c_int64))
+    if rc != 0:
+        raise RuntimeError(f"oracle_run_chain failed: {rc}")
+    return s.reshape(L, L), tr, a

@@ -1,0 +1,39 @@
+/*
+ * crbm_oracle.h -- interface of the CPU oracle (test infrastructure only).
+ * Not included by, and not sharing anything with, the HIP library.
+ * All conventions are stated at the top of crbm_oracle.c.
+ */
+#ifndef CRBM_ORACLE_H
+#define CRBM_ORACLE_H
+#include <stdint.h>
+
+typedef struct {
+    int32_t L;             /* even lattice side */
+    double J1, J2, h;      /* H = J1 sum_sq s s + J2 sum_dimer s s - h sum s */
+    int32_t sched_kind;    /* 0 const, 1 linear, 2 geometric, 3 explicit */
+    double T0, T1;
+    const double* T_explicit;
+    uint32_t id;           /* instance id in the random-number counter */
+} oracle_instance;
+
+void     oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+uint32_t oracle_uniform_hidden(uint64_t seed, uint32_t id, uint32_t chain, uint32_t sweep,
+                               int L, int k, int i, int j);
+uint32_t oracle_uniform_visible(uint64_t seed, uint32_t id, uint32_t chain, uint32_t sweep,
+                                int L, int r, int c);
+int64_t  oracle_quantise(double J);
+double   oracle_schedule_T(int kind, double T0, double T1, const double* T_explicit,
+                           int64_t S, int64_t s);
+void     oracle_bond_weight(int64_t Jq, double T, int64_t* wq, int* sig);
+int64_t  oracle_visible_bias(int64_t hq, double T);
+uint32_t oracle_threshold(int64_t y);
+void     oracle_bond_sites(int L, int k, int i, int j, int* ra, int* ca, int* rb, int* cb, int* type);
+void     oracle_counts(int L, const int8_t* s, int64_t* M, int64_t* B1, int64_t* B2);
+void     oracle_corr(int L, const int8_t* s, int64_t* corr);
+void     oracle_init_spins(const oracle_instance* in, uint64_t seed, uint32_t chain, int8_t* s);
+int      oracle_run_chain(const oracle_instance* in, int64_t S, uint64_t seed, uint32_t chain,
+                          int64_t sweep_begin, int64_t sweep_end, int8_t* s,
+                          int32_t* trace, int32_t measure_every, int64_t burn_in, int64_t* acc);
+double   oracle_log_marginal(const oracle_instance* in, int64_t S, int64_t sweep, const int8_t* s);
+
+#endif

@@ -1,0 +1,147 @@
+"""Independent numpy statement of the Shastry-Sutherland Ising model, used to pin
+the oracle.  Nothing here is imported by the oracle or by the HIP library.
+
+Geometry (Sec. I Eq. (1), lattice of Fig. 1a): L x L square lattice, periodic.
+  J1 bonds: every nearest-neighbour edge of the square lattice (2N of them).
+  J2 bonds: one diagonal on every other plaquette in a checkerboard pattern,
+            orthogonal on neighbouring dimer plaquettes: the plaquette with
+            top-left site (2i, 2j) carries the '\\' diagonal, the plaquette
+            with top-left site (2i+1, 2j+1) carries the '/' diagonal (N/2 dimers,
+            every site on exactly one).
+Energy with the field favouring up spins: H = J1 sum s s + J2 sum s s - h sum s.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def nn_bonds(L):
+    out = []
+    for r in range(L):
+        for c in range(L):
+            out.append(((r, c), (r, (c + 1) % L)))
+            out.append(((r, c), ((r + 1) % L, c)))
+    return out
+
+
+def dimer_bonds(L):
+    out = []
+    for i in range(L // 2):
+        for j in range(L // 2):
+            out.append(((2 * i, 2 * j), (2 * i + 1, 2 * j + 1)))
+            out.append(((2 * i + 1, (2 * j + 2) % L), ((2 * i + 2) % L, 2 * j + 1)))
+    return out
+
+
+def bond_counts(spins):
+    """spins: [..., L, L] of +-1.  Returns (M, B1, B2) as int64 arrays."""
+    s = np.asarray(spins, np.int64)
+    M = s.sum(axis=(-1, -2))
+    B1 = (s * np.roll(s, -1, axis=-1)).sum(axis=(-1, -2)) + (s * np.roll(s, -1, axis=-2)).sum(axis=(-1, -2))
+    L = s.shape[-1]
+    B2 = np.zeros(s.shape[:-2], np.int64)
+    for (a, b) in dimer_bonds(L):
+        B2 = B2 + s[..., a[0], a[1]] * s[..., b[0], b[1]]
+    return M, B1, B2
+
+
+def energy(spins, J1, J2, h):
+    M, B1, B2 = bond_counts(spins)
+    return J1 * B1 + J2 * B2 - h * M
+
+
+def all_states(L):
+    """All 2^(L*L) configurations (only sensible for L = 4)."""
+    n = L * L
+    idx = np.arange(1 << n, dtype=np.int64)
+    bits = (idx[:, None] >> np.arange(n)[None, :]) & 1
+    return (2 * bits - 1).astype(np.int8).reshape(-1, L, L)
+
+
+def exact_averages(L, J1, J2, h, T, states=None):
+    """Exact <E>/N, <m>, <|m|> by enumeration."""
+    st = all_states(L) if states is None else states
+    M, B1, B2 = bond_counts(st)
+    E = J1 * B1 + J2 * B2 - h * M
+    N = L * L
+    lw = -(E - E.min()) / T
+    w = np.exp(lw)
+    Z = w.sum()
+    return {
+        "E": float((w * E).sum() / Z / N),
+        "m": float((w * M).sum() / Z / N),
+        "abs_m": float((w * np.abs(M)).sum() / Z / N),
+        "E_min": float(E.min() / N),
+    }
+
+
+# --------------------------------------------------------- transfer matrix
+
+def _row_states(L):
+    idx = np.arange(1 << L, dtype=np.int64)
+    bits = (idx[:, None] >> np.arange(L)[None, :]) & 1
+    return (2 * bits - 1).astype(np.int64)
+
+
+def transfer_parts(L, J1, J2, h):
+    """Row transfer energies.  Every bond joins two sites of one row or of two
+    consecutive rows, so the periodic lattice is a ring of rows.
+
+    e_row[a]      : horizontal J1 bonds and field of a row in state a;
+    e_even[a, b]  : bonds between an even row 2i (state a) and row 2i+1 (b):
+                    vertical J1 and the '\\' dimers (2i, 2j)-(2i+1, 2j+1);
+    e_odd[a, b]   : bonds between an odd row 2i+1 (a) and row 2i+2 (b):
+                    vertical J1 and the '/' dimers (2i+1, 2j+2)-(2i+2, 2j+1)."""
+    st = _row_states(L)
+    e_row = J1 * (st * np.roll(st, -1, 1)).sum(1) - h * st.sum(1)
+    vert = st @ st.T
+    e_even = J1 * vert + J2 * (st[:, 0::2] @ st[:, 1::2].T)
+    e_odd = J1 * vert + J2 * (np.roll(st, -2, 1)[:, 0::2] @ st[:, 1::2].T)
+    return st, e_row.astype(np.float64), e_even.astype(np.float64), e_odd.astype(np.float64)
+
+
+def tm_averages(L, J1, J2, h, T):
+    """Exact <E>/N and <m> of the periodic L x L lattice (row transfer matrix;
+    L <= 12)."""
+    st, e_row, e_even, e_odd = transfer_parts(L, J1, J2, h)
+    Ee = e_row[:, None] + e_even          # row 2i's own energy + link to row 2i+1
+    Eo = e_row[:, None] + e_odd
+    shift = min(Ee.min(), Eo.min())
+    Te = np.exp(-(Ee - shift) / T)
+    To = np.exp(-(Eo - shift) / T)
+    Mr = st.sum(1).astype(np.float64)
+    pair = Te @ To
+    nb = L // 2
+    P = np.linalg.matrix_power(pair, nb - 1)
+    Z = np.trace(P @ pair)
+    dE = (Te * Ee) @ To + Te @ (To * Eo)
+    dM = (Te * Mr[:, None]) @ To + Te @ (To * Mr[:, None])
+    N = L * L
+    return {"E": float(nb * np.trace(P @ dE) / Z / N), "m": float(nb * np.trace(P @ dM) / Z / N)}
+
+
+def tm_ground_energy(L, J1, J2, h):
+    """Exact ground-state energy per spin by a min-plus row transfer (L <= 8)."""
+    st, e_row, e_even, e_odd = transfer_parts(L, J1, J2, h)
+    Ee = e_row[:, None] + e_even
+    Eo = e_row[:, None] + e_odd
+    pair = _minplus(Ee, Eo)
+    D = pair
+    for _ in range(L // 2 - 1):
+        D = _minplus(D, pair)
+    return float(np.min(np.diag(D)) / (L * L))
+
+
+def _minplus(A, B):
+    return (A[:, :, None] + B[None, :, :]).min(axis=1)
+
+
+# ------------------------------------------------------- structure factor
+
+def structure_factor(corr_sum, n_samples, L):
+    """S(q)/N from summed C(dr, dc) = sum_i s_i s_{i+d}: S(q) = sum_d C(d) e^{i q d} / N,
+    returned as S(q)/N on the L x L grid q = 2 pi (a, b)/L."""
+    C = np.asarray(corr_sum, np.float64) / n_samples
+    F = np.fft.fft2(C).real  # sum_d C(d) e^{-i q d}; C is inversion symmetric
+    N = L * L
+    return F / N / N
