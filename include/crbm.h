@@ -1,0 +1,161 @@
+/*
+ * crbm.h -- C ABI of the MI355X (gfx950) CRBM Gibbs sampler for the classical
+ * Shastry-Sutherland (SS) Ising lattice.
+ *
+ * The operation (Brahma et al., arXiv 2511.20911):
+ *   - the lattice Hamiltonian of Sec. I Eq. (1), read with the field
+ *     favouring up spins:  H = J1 sum_sq s s + J2 sum_dimer s s - h sum s;
+ *   - its exact CRBM encoding, Sec. II.A Eqs. (4)-(10): one hidden unit per
+ *     bond, 10 filters on the 3x3 unit-cell window, stride 2;
+ *   - block Gibbs sampling, Sec. II.B Eqs. (11)-(12): all hidden units from
+ *     the spins, then all spins from the hidden units (zero-inserted hidden
+ *     planes, flipped filters, accumulated over the 10 filters plus the
+ *     visible bias, App. A Zero Padder / Convoluter-Reverse / Accumulator);
+ *   - the sigmoid as a table of closest values compared against a uniform
+ *     random number (App. A Sigmoid and LFSR), here 32-bit thresholds and
+ *     counter-based Philox4x32-10 uniforms;
+ *   - host-side energies of the sampled states (App. A I/O Programming Logic)
+ *     and the static structure factor of Sec. III.B Eq. (13).
+ *
+ * Every unit update is an integer compare; couplings, weights and the visible
+ * bias are 16.16 fixed point; all counts are exact integers.  The random
+ * stream of a unit depends only on (seed, instance id, chain, sweep, unit), so
+ * results do not depend on tiling, launch shape or batch composition.
+ *
+ * Errors: every function returns CRBM_OK (0) or a negative code and never
+ * throws; crbm_last_error() returns a message for the calling thread.
+ * Threading: a handle may be used from one thread at a time.
+ * Streams: work is enqueued on the hipStream_t given in crbm_config.stream
+ * (NULL = the default stream).  Functions that return host data synchronise
+ * that stream first.
+ */
+#ifndef CRBM_H
+#define CRBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CRBM_OK = 0,
+    CRBM_EINVAL = -1,      /* invalid argument (odd L, T <= 0, NULL pointer, ...) */
+    CRBM_ERANGE = -2,      /* a fixed-point weight or bias does not fit in int32 */
+    CRBM_ENOMEM = -3,      /* device or host allocation failed */
+    CRBM_EHIP = -4,        /* a HIP runtime call failed */
+    CRBM_EUNSUPPORTED = -5,/* valid request this build does not implement (open boundaries, L > CRBM_MAX_L) */
+    CRBM_ESTATE = -6       /* misuse of a handle (e.g. sampling past the end of the schedule) */
+};
+
+enum {
+    CRBM_SCHED_CONST = 0,     /* T_s = T0 */
+    CRBM_SCHED_LINEAR = 1,    /* T_s = T0 + (T1 - T0) * (s / (S - 1)) */
+    CRBM_SCHED_GEOMETRIC = 2, /* T_s = T0 * pow(T1 / T0, s / (S - 1)) */
+    CRBM_SCHED_EXPLICIT = 3   /* T_s = T_explicit[s] */
+};
+
+#define CRBM_MAX_L 32      /* largest lattice side supported by this build */
+#define CRBM_N_ACC 11      /* per-chain accumulator words, see crbm_obs */
+
+/* One Hamiltonian point (one "instance").  Host memory, copied at create. */
+typedef struct {
+    int32_t L;                 /* lattice side: even, 4 <= L <= CRBM_MAX_L */
+    int32_t periodic;          /* must be 1 (periodic in both directions) */
+    double J1, J2, h;          /* couplings and field; |J| * 2^16 < 2^31 */
+    int32_t n_chains;          /* independent chains, >= 1 */
+    int32_t sched_kind;        /* CRBM_SCHED_* */
+    double T0, T1;             /* temperatures, finite and > 0 */
+    const double* T_explicit;  /* host array of n_sweeps temperatures (EXPLICIT only) */
+    uint32_t id;               /* instance id in the random-number counter, < 2^29 */
+} crbm_instance;
+
+typedef struct {
+    uint64_t seed;             /* Philox key */
+    int64_t n_sweeps;          /* schedule length S; crbm_sample may run at most S sweeps in total */
+    int32_t measure_every;     /* 0 = accumulate nothing; k > 0 = accumulate every k-th sweep at or after burn_in */
+    int64_t burn_in;           /* first sweep that may be accumulated */
+    void* stream;              /* hipStream_t (NULL = default stream) */
+    int32_t tile_rows;         /* cell rows per lane: 0 = library choice, else must divide L/2 */
+} crbm_config;
+
+/* Per-instance observables, host memory, filled by crbm_observables.
+ * Sums run over chains and accumulated sweeps.  Counts of one state:
+ *   M  = sum of spins,  B1 = sum over J1 bonds of s_a s_b,  B2 = same over dimers.
+ * Energy per spin E/N = (J1q B1 + J2q B2 - hq M) / (2^16 N) with Jq = llround(J 2^16). */
+typedef struct {
+    int64_t n_samples;                        /* chains x accumulated sweeps */
+    int64_t sum_M, sum_B1, sum_B2;
+    int64_t sum_MM, sum_B1B1, sum_B2B2, sum_MB1, sum_MB2, sum_B1B2;
+    int64_t sum_absM;
+    double E_per_spin;                        /* <E>/N from the exact sums */
+    double m;                                 /* <M>/N */
+    double abs_m;                             /* <|M|>/N */
+    double dimer;                             /* -<B2>/(N/2): +1 for antiparallel dimers */
+    double E_var_per_spin;                    /* (<E^2> - <E>^2)/N from the exact second moments */
+} crbm_obs;
+
+typedef struct crbm_s crbm_t;
+
+/* Create a sampler for n_inst instances (each with its own L, couplings,
+ * schedule and chain count) sharing one config.  Quantises the couplings,
+ * builds the per-sweep weight and threshold tables on the host, allocates the
+ * device state (bit-packed spins, tables, accumulators) and enqueues the
+ * seeded initialisation of every chain on cfg->stream.
+ * Returns CRBM_EINVAL for invalid parameters, CRBM_ERANGE for fixed-point
+ * overflow, CRBM_EUNSUPPORTED for open boundaries or L > CRBM_MAX_L. */
+int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cfg, crbm_t** out);
+
+/* Run the next n_sweeps sweeps of the schedule (asynchronous on the stream).
+ * spins_out: device pointer or NULL; if given, receives the final state as
+ *   int8 +-1 values, layout [chain][L][L] with chains of all instances
+ *   concatenated in instance order (sizes may differ per instance).
+ * counts_trace: device pointer or NULL; if given, receives int32 (M, B1, B2)
+ *   after every sweep of this call, layout [sweep][chain][3] with the chains
+ *   of all instances concatenated.
+ * Returns CRBM_ESTATE if the schedule would be exceeded. */
+int crbm_sample(crbm_t* h, int64_t n_sweeps, int8_t* spins_out, int32_t* counts_trace);
+
+/* Synchronise the stream and fill out[n_inst] from the exact int64
+ * accumulators.  corr_out: host pointer or NULL; if given, receives for each
+ * instance the sum over its chains of C(dr,dc) = sum_{r,c} s(r,c) s(r+dr,c+dc)
+ * of the CURRENT state, int64 [L][L] per instance, instances concatenated
+ * (S(q) of Eq. (13) is its 2-D Fourier transform). */
+int crbm_observables(crbm_t* h, crbm_obs* out, int64_t* corr_out);
+
+/* Checkpoint / resume.  spins: device pointer, int8 +-1, same layout as
+ * crbm_sample's spins_out.  sweep_index: global index of the next sweep. */
+int crbm_get_state(crbm_t* h, int8_t* spins_dev, int64_t* sweep_index);
+int crbm_set_state(crbm_t* h, const int8_t* spins_dev, int64_t sweep_index);
+
+/* Total number of chains over all instances. */
+int64_t crbm_total_chains(const crbm_t* h);
+
+/* Zero the accumulators (e.g. after a burn-in phase). */
+int crbm_reset_observables(crbm_t* h);
+
+/* Free everything the handle owns.  NULL is allowed. */
+void crbm_destroy(crbm_t* h);
+
+/* Message of the last error on this thread ("" if none). */
+const char* crbm_last_error(void);
+
+/* Host-side helpers that expose the library's own tables (used by tests to
+ * check them against the oracle).
+ * crbm_threshold: the 32-bit sigmoid threshold t(y) for an integer field
+ *   magnitude y >= 0 in 2^16 units (App. A sigmoid module, closest value).
+ * crbm_sweep_table: the 16-word table the device reads for sweep s of
+ *   instance i (see the kernel source for the layout). */
+uint32_t crbm_threshold(int64_t y);
+int crbm_sweep_table(const crbm_t* h, int32_t i, int64_t s, uint32_t out[16]);
+
+/* Host only, no device needed: the 16-word table for couplings (J1, J2, h) at
+ * temperature T, exactly as crbm_create builds it.  Returns CRBM_EINVAL for
+ * T <= 0 or non-finite input, CRBM_ERANGE on fixed-point overflow. */
+int crbm_table_for(double J1, double J2, double h, double T, uint32_t out[16]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CRBM_H */

@@ -1,0 +1,229 @@
+"""Python binding of libcrbm.so: CRBM block-Gibbs sampling of the classical
+Shastry-Sutherland Ising lattice on MI355X (gfx950).
+
+This module only marshals arguments to the C ABI of ``include/crbm.h``; every
+step of the sampler runs in the library's HIP kernels.  PyTorch provides device
+memory and the stream.  Importing works without a GPU; creating a sampler
+needs the built library and a GPU, and fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcrbm.so")
+
+CRBM_OK, CRBM_EINVAL, CRBM_ERANGE, CRBM_ENOMEM, CRBM_EHIP, CRBM_EUNSUPPORTED, CRBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
+SCHED = {"const": 0, "linear": 1, "geometric": 2, "explicit": 3}
+N_ACC = 11
+MAX_L = 32
+
+
+class CrbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"crbm error {code}: {msg}")
+        self.code = code
+
+
+class _Instance(ct.Structure):
+    _fields_ = [
+        ("L", ct.c_int32), ("periodic", ct.c_int32),
+        ("J1", ct.c_double), ("J2", ct.c_double), ("h", ct.c_double),
+        ("n_chains", ct.c_int32), ("sched_kind", ct.c_int32),
+        ("T0", ct.c_double), ("T1", ct.c_double),
+        ("T_explicit", ct.POINTER(ct.c_double)),
+        ("id", ct.c_uint32),
+    ]
+
+
+class _Config(ct.Structure):
+    _fields_ = [
+        ("seed", ct.c_uint64), ("n_sweeps", ct.c_int64), ("measure_every", ct.c_int32),
+        ("burn_in", ct.c_int64), ("stream", ct.c_void_p), ("tile_rows", ct.c_int32),
+    ]
+
+
+class _Obs(ct.Structure):
+    _fields_ = [
+        ("n_samples", ct.c_int64),
+        ("sum_M", ct.c_int64), ("sum_B1", ct.c_int64), ("sum_B2", ct.c_int64),
+        ("sum_MM", ct.c_int64), ("sum_B1B1", ct.c_int64), ("sum_B2B2", ct.c_int64),
+        ("sum_MB1", ct.c_int64), ("sum_MB2", ct.c_int64), ("sum_B1B2", ct.c_int64),
+        ("sum_absM", ct.c_int64),
+        ("E_per_spin", ct.c_double), ("m", ct.c_double), ("abs_m", ct.c_double),
+        ("dimer", ct.c_double), ("E_var_per_spin", ct.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ct.CDLL:
+    """Load libcrbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2511_20911_amd.build`")
+        L = ct.CDLL(LIB_PATH)
+        p = ct.POINTER
+        L.crbm_create.argtypes = [p(_Instance), ct.c_int32, p(_Config), p(ct.c_void_p)]
+        L.crbm_sample.argtypes = [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p]
+        L.crbm_observables.argtypes = [ct.c_void_p, p(_Obs), ct.c_void_p]
+        L.crbm_get_state.argtypes = [ct.c_void_p, ct.c_void_p, p(ct.c_int64)]
+        L.crbm_set_state.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64]
+        L.crbm_total_chains.argtypes = [ct.c_void_p]
+        L.crbm_total_chains.restype = ct.c_int64
+        L.crbm_reset_observables.argtypes = [ct.c_void_p]
+        L.crbm_destroy.argtypes = [ct.c_void_p]
+        L.crbm_destroy.restype = None
+        L.crbm_last_error.restype = ct.c_char_p
+        L.crbm_threshold.argtypes = [ct.c_int64]
+        L.crbm_threshold.restype = ct.c_uint32
+        L.crbm_sweep_table.argtypes = [ct.c_void_p, ct.c_int32, ct.c_int64, p(ct.c_uint32)]
+        L.crbm_table_for.argtypes = [ct.c_double, ct.c_double, ct.c_double, ct.c_double, p(ct.c_uint32)]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != CRBM_OK:
+        raise CrbmError(rc, lib().crbm_last_error().decode())
+
+
+@dataclass
+class Instance:
+    """One Hamiltonian point H = J1 sum s s + J2 sum_dimer s s - h sum s on an L x L lattice."""
+    L: int
+    J1: float = 1.0
+    J2: float = 0.5
+    h: float = 0.0
+    n_chains: int = 1
+    sched: str = "const"
+    T0: float = 1.0
+    T1: Optional[float] = None
+    T_explicit: Optional[np.ndarray] = None
+    id: int = 0
+    periodic: int = 1
+
+
+def threshold(y: int) -> int:
+    """The library's 32-bit sigmoid threshold t(y) (y in 2^16 units)."""
+    return int(lib().crbm_threshold(int(y)))
+
+
+def table_for(J1: float, J2: float, h: float, T: float) -> np.ndarray:
+    """The library's 16-word device table for one sweep (host computation)."""
+    out = np.zeros(16, np.uint32)
+    _check(lib().crbm_table_for(J1, J2, h, T, out.ctypes.data_as(ct.POINTER(ct.c_uint32))))
+    return out
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ct.c_void_p(stream.cuda_stream)
+
+
+class Sampler:
+    """Handle on crbm_create / crbm_sample / crbm_observables."""
+
+    def __init__(self, instances: Sequence[Instance], seed: int, n_sweeps: int, measure_every: int = 0,
+                 burn_in: int = 0, stream=None, tile_rows: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the CRBM sampler runs only on the HIP device")
+        self.instances = list(instances)
+        self._texp = []
+        arr = (_Instance * len(self.instances))()
+        for k, I in enumerate(self.instances):
+            te = None
+            if I.sched == "explicit":
+                t = np.ascontiguousarray(I.T_explicit, np.float64)
+                self._texp.append(t)
+                te = t.ctypes.data_as(ct.POINTER(ct.c_double))
+            arr[k] = _Instance(I.L, I.periodic, I.J1, I.J2, I.h, I.n_chains, SCHED[I.sched], I.T0,
+                               I.T0 if I.T1 is None else I.T1, te, I.id)
+        self.stream = stream
+        cfg = _Config(seed, n_sweeps, measure_every, burn_in, _stream_handle(stream), tile_rows)
+        h = ct.c_void_p()
+        _check(lib().crbm_create(arr, len(self.instances), ct.byref(cfg), ct.byref(h)))
+        self._h = h
+        self.n_sweeps = n_sweeps
+        self.total_chains = int(lib().crbm_total_chains(h))
+        self.spin_offsets = np.cumsum([0] + [I.n_chains * I.L * I.L for I in self.instances])
+        self.chain_offsets = np.cumsum([0] + [I.n_chains for I in self.instances])
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.crbm_destroy(h)
+            self._h = None
+
+    def close(self):
+        self.__del__()
+
+    @property
+    def total_spins(self) -> int:
+        return int(self.spin_offsets[-1])
+
+    def sample(self, n_sweeps: int, spins_out=None, trace=None):
+        """Enqueue n_sweeps sweeps.  spins_out: int8 CUDA tensor of total_spins
+        elements; trace: int32 CUDA tensor [n_sweeps, total_chains, 3]."""
+        if spins_out is not None:
+            assert spins_out.is_cuda and spins_out.dtype.itemsize == 1 and spins_out.numel() == self.total_spins
+        if trace is not None:
+            assert trace.is_cuda and trace.numel() == n_sweeps * self.total_chains * 3 and trace.element_size() == 4
+        _check(lib().crbm_sample(self._h, n_sweeps,
+                                 ct.c_void_p(spins_out.data_ptr()) if spins_out is not None else None,
+                                 ct.c_void_p(trace.data_ptr()) if trace is not None else None))
+
+    def observables(self, corr: bool = False):
+        obs = (_Obs * len(self.instances))()
+        cbuf = None
+        if corr:
+            cbuf = np.zeros(sum(I.L * I.L for I in self.instances), np.int64)
+        _check(lib().crbm_observables(self._h, obs, cbuf.ctypes.data_as(ct.c_void_p) if corr else None))
+        out = []
+        for o in obs:
+            out.append({f: getattr(o, f) for f, _ in _Obs._fields_})
+        if corr:
+            parts, off = [], 0
+            for I in self.instances:
+                parts.append(cbuf[off:off + I.L * I.L].reshape(I.L, I.L))
+                off += I.L * I.L
+            return out, parts
+        return out
+
+    def reset_observables(self):
+        _check(lib().crbm_reset_observables(self._h))
+
+    def get_state(self):
+        import torch
+        spins = torch.empty(self.total_spins, dtype=torch.int8, device="cuda")
+        idx = ct.c_int64()
+        _check(lib().crbm_get_state(self._h, ct.c_void_p(spins.data_ptr()), ct.byref(idx)))
+        return spins, int(idx.value)
+
+    def set_state(self, spins, sweep_index: int):
+        assert spins is None or (spins.is_cuda and spins.numel() == self.total_spins)
+        _check(lib().crbm_set_state(self._h, ct.c_void_p(spins.data_ptr()) if spins is not None else None,
+                                    int(sweep_index)))
+
+    def split_spins(self, flat):
+        """Split a flat [total_spins] tensor into per-instance [n_chains, L, L] views."""
+        out = []
+        for k, I in enumerate(self.instances):
+            a, b = int(self.spin_offsets[k]), int(self.spin_offsets[k + 1])
+            out.append(flat[a:b].view(I.n_chains, I.L, I.L))
+        return out
+
+    def sweep_table(self, i: int, s: int) -> np.ndarray:
+        out = np.zeros(16, np.uint32)
+        _check(lib().crbm_sweep_table(self._h, i, s, out.ctypes.data_as(ct.POINTER(ct.c_uint32))))
+        return out

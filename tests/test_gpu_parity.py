@@ -1,0 +1,171 @@
+"""GPU parity: the HIP sampler equals the CPU oracle bit for bit, trajectory by
+trajectory, from the same seed (spins and exact int64 counts), through the C ABI.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+crbm = pytest.importorskip("paper_2511_20911_amd")
+
+
+def _oi(I: "crbm.Instance"):
+    return oracle.Instance(I.L, I.J1, I.J2, I.h, I.sched, I.T0, I.T1, I.T_explicit, id=I.id)
+
+
+def _run_gpu(insts, seed, S, n_run=None, trace=True, tile_rows=0, measure_every=0, burn_in=0):
+    n_run = S if n_run is None else n_run
+    smp = crbm.Sampler(insts, seed=seed, n_sweeps=S, measure_every=measure_every, burn_in=burn_in,
+                       tile_rows=tile_rows)
+    spins = torch.empty(smp.total_spins, dtype=torch.int8, device="cuda")
+    tr = torch.empty((n_run, smp.total_chains, 3), dtype=torch.int32, device="cuda") if trace else None
+    smp.sample(n_run, spins_out=spins, trace=tr)
+    torch.cuda.synchronize()
+    parts = [p.cpu().numpy() for p in smp.split_spins(spins)]
+    return smp, parts, (tr.cpu().numpy() if trace else None)
+
+
+def _check_chains(I, parts_k, trace, chain_off, seed, S, chains, n_run=None):
+    n_run = S if n_run is None else n_run
+    oi = _oi(I)
+    for ch in chains:
+        s, t, _ = oracle.run_chain(oi, S, seed, ch, 0, n_run, trace=trace is not None)
+        assert np.array_equal(parts_k[ch], s), f"L={I.L} chain {ch}: spins differ"
+        if trace is not None:
+            assert np.array_equal(trace[:, chain_off + ch, :], t), f"L={I.L} chain {ch}: trace differs"
+
+
+def test_config1_all_chains_bit_exact():
+    """6x6, J2/J1 = 0.5, h = 0, 256 chains, linear anneal 3.0 -> 0.1 over 2000
+    sweeps: every chain's final spins and per-sweep (M, B1, B2) equal the oracle."""
+    I = crbm.Instance(L=6, J1=1.0, J2=0.5, h=0.0, n_chains=256, sched="linear", T0=3.0, T1=0.1, id=0)
+    seed = 0x5EED000000000001
+    S = 2000
+    smp, parts, tr = _run_gpu([I], seed, S)
+    _check_chains(I, parts[0], tr, 0, seed, S, range(256))
+    # every chain ends in the Neel state of this point (E/N = -1.75)
+    M, B1, B2 = tr[-1, :, 0], tr[-1, :, 1], tr[-1, :, 2]
+    E = (B1 + 0.5 * B2) / 36
+    assert np.all(M == 0) and np.all(np.abs(E + 1.75) < 1e-12)
+
+
+@pytest.mark.parametrize("tile_rows", [1, 3, 9])
+def test_18x18_geometric_bit_exact_any_tiling(tile_rows):
+    """18x18 (the paper's 324 spins), geometric anneal 5.0 -> 0.05 over 10^4
+    sweeps at two (J2/J1, h) points: sampled chains equal the oracle for every
+    lanes-per-chain tiling (G = 9, 3, 1)."""
+    S = 10000
+    seed = 0x5EED000000000002
+    insts = [crbm.Instance(L=18, J1=1.0, J2=1.0, h=3.0, n_chains=32, sched="geometric", T0=5.0, T1=0.05, id=5),
+             crbm.Instance(L=18, J1=1.0, J2=2.0, h=0.6, n_chains=21, sched="geometric", T0=5.0, T1=0.05, id=61)]
+    n_run = 1500
+    smp, parts, tr = _run_gpu(insts, seed, S, n_run=n_run, tile_rows=tile_rows)
+    _check_chains(insts[0], parts[0], tr, 0, seed, S, [0, 7, 31], n_run)
+    _check_chains(insts[1], parts[1], tr, 32, seed, S, [0, 20], n_run)
+
+
+def test_18x18_full_schedule_sampled_chains():
+    """Full 10^4-sweep schedule at 18x18, J2/J1 = 1, h = 3 (the plateau point):
+    two sampled chains equal the oracle at the end."""
+    S = 10000
+    seed = 0x5EED000000000002
+    I = crbm.Instance(L=18, J1=1.0, J2=1.0, h=3.0, n_chains=64, sched="geometric", T0=5.0, T1=0.05, id=9)
+    smp, parts, _ = _run_gpu([I], seed, S, trace=False)
+    _check_chains(I, parts[0], None, 0, seed, S, [0, 63])
+
+
+def test_mixed_sizes_in_one_handle():
+    """Instances of different L, couplings and schedules in one handle; ragged
+    chain counts (not multiples of the chains per wavefront)."""
+    seed = 77
+    S = 300
+    insts = [
+        crbm.Instance(L=4, J1=1.0, J2=0.5, h=0.0, n_chains=5, sched="const", T0=1.0, id=1),
+        crbm.Instance(L=6, J1=1.0, J2=2.5, h=0.0, n_chains=70, sched="linear", T0=3.0, T1=0.2, id=2),
+        crbm.Instance(L=12, J1=1.0, J2=1.0, h=3.0, n_chains=33, sched="geometric", T0=5.0, T1=0.1, id=3),
+        crbm.Instance(L=24, J1=1.0, J2=1.5, h=-1.0, n_chains=17, sched="const", T0=0.7, id=4),
+        crbm.Instance(L=32, J1=-1.0, J2=0.0, h=0.25, n_chains=3, sched="const", T0=2.0, id=5),
+        crbm.Instance(L=10, J1=1.0, J2=1.0, h=2.0, n_chains=9, sched="explicit",
+                      T_explicit=np.linspace(4.0, 0.3, S), id=6),
+    ]
+    smp, parts, tr = _run_gpu(insts, seed, S)
+    off = smp.chain_offsets
+    for k, I in enumerate(insts):
+        chains = sorted({0, I.n_chains // 2, I.n_chains - 1})
+        _check_chains(I, parts[k], tr, int(off[k]), seed, S, chains)
+
+
+def test_batch_composition_invariance():
+    """An instance gives the same chains alone or inside a batch (the random
+    stream depends on the instance id, not on its position)."""
+    seed = 99
+    S = 200
+    A = crbm.Instance(L=12, J1=1.0, J2=1.0, h=2.0, n_chains=40, sched="const", T0=0.8, id=17)
+    B = crbm.Instance(L=18, J1=1.0, J2=0.5, h=0.0, n_chains=30, sched="const", T0=1.5, id=4)
+    _, p1, _ = _run_gpu([A], seed, S, trace=False)
+    _, p2, _ = _run_gpu([B, A], seed, S, trace=False)
+    assert np.array_equal(p1[0], p2[1])
+
+
+def test_resume_is_bit_exact():
+    """get_state / set_state at any sweep: 2 x 150 sweeps == 300 sweeps."""
+    seed = 5
+    S = 300
+    I = crbm.Instance(L=18, J1=1.0, J2=1.5, h=1.0, n_chains=50, sched="linear", T0=3.0, T1=0.3, id=2)
+    _, full, _ = _run_gpu([I], seed, S, trace=False)
+    smp = crbm.Sampler([I], seed=seed, n_sweeps=S)
+    smp.sample(150)
+    st, idx = smp.get_state()
+    assert idx == 150
+    smp2 = crbm.Sampler([I], seed=seed, n_sweeps=S)
+    smp2.set_state(st, 150)
+    out = torch.empty(smp2.total_spins, dtype=torch.int8, device="cuda")
+    smp2.sample(150, spins_out=out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().reshape(50, 18, 18), full[0])
+    with pytest.raises(crbm.CrbmError) as e:
+        smp2.sample(1)
+    assert e.value.code == crbm.CRBM_ESTATE
+
+
+def test_accumulators_and_structure_factor_match_oracle():
+    """Exact int64 sums of (M, B1, B2) and their second moments, and the summed
+    correlation C(dr, dc) of the final state, equal the oracle's."""
+    seed = 31
+    S = 400
+    I = crbm.Instance(L=12, J1=1.0, J2=1.0, h=3.0, n_chains=24, sched="const", T0=0.6, id=8)
+    smp = crbm.Sampler([I], seed=seed, n_sweeps=S, measure_every=3, burn_in=100)
+    smp.sample(S)
+    obs, corr = smp.observables(corr=True)
+    acc = np.zeros(oracle.N_ACC, np.int64)
+    csum = np.zeros((12, 12), np.int64)
+    oi = _oi(I)
+    for ch in range(24):
+        s, _, a = oracle.run_chain(oi, S, seed, ch, 0, S, measure_every=3, burn_in=100)
+        acc += a
+        csum += oracle.corr(12, s)
+    keys = ["n_samples", "sum_M", "sum_B1", "sum_B2", "sum_MM", "sum_B1B1", "sum_B2B2", "sum_MB1", "sum_MB2",
+            "sum_B1B2", "sum_absM"]
+    assert [obs[0][k] for k in keys] == acc.tolist()
+    assert np.array_equal(corr[0], csum)
+    n = acc[0]
+    E = (acc[2] + acc[3] - 3 * acc[1]) / n / 144
+    assert abs(obs[0]["E_per_spin"] - E) < 1e-12
+
+
+def test_invalid_arguments_fail_cleanly():
+    bad = [
+        (crbm.Instance(L=7, n_chains=1), crbm.CRBM_EINVAL),
+        (crbm.Instance(L=6, n_chains=0), crbm.CRBM_EINVAL),
+        (crbm.Instance(L=6, n_chains=1, T0=-1.0), crbm.CRBM_EINVAL),
+        (crbm.Instance(L=64, n_chains=1), crbm.CRBM_EUNSUPPORTED),
+        (crbm.Instance(L=6, n_chains=1, periodic=0), crbm.CRBM_EUNSUPPORTED),
+        (crbm.Instance(L=6, n_chains=1, T0=1e-7), crbm.CRBM_ERANGE),
+    ]
+    for I, code in bad:
+        with pytest.raises(crbm.CrbmError) as e:
+            crbm.Sampler([I], seed=1, n_sweeps=10)
+        assert e.value.code == code, I

@@ -1,0 +1,77 @@
+"""Host-side checks of the HIP library that need no GPU: it loads, exports
+every symbol of include/crbm.h, and its host-built tables equal what the
+oracle computes from the same conventions."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2511_20911_amd as crbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(crbm_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = crbm.lib()
+    names = _declared_functions()
+    assert "crbm_create" in names and "crbm_sample" in names and "crbm_observables" in names
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+
+
+def test_threshold_equals_oracle():
+    ys = np.unique(np.concatenate([np.arange(0, 5000), np.geomspace(1, 5e7, 3000).astype(np.int64)]))
+    for y in ys:
+        assert crbm.threshold(int(y)) == oracle.threshold(int(y)), y
+
+
+def _oracle_table(J1, J2, h, T):
+    wq1, s1 = oracle.bond_weight(oracle.quantise(J1), T)
+    wq2, s2 = oracle.bond_weight(oracle.quantise(J2), T)
+    aq = oracle.visible_bias(oracle.quantise(h), T)
+    tab = np.zeros(16, np.uint32)
+    tab[0] = oracle.threshold(2 * wq1)
+    tab[1] = oracle.threshold(2 * wq2)
+    kge = [5, 5]
+    for d in (0, 1):
+        for n in range(5):
+            x = aq + wq1 * (2 * n - 4) + wq2 * (2 * d - 1)
+            tab[3 + 2 * n + d] = oracle.threshold(abs(x))
+            if x >= 0 and kge[d] == 5:
+                kge[d] = n
+    tab[2] = (s1 < 0) | ((s2 < 0) << 1) | ((wq1 != 0) << 2) | ((wq2 != 0) << 3) | (kge[0] << 8) | (kge[1] << 12)
+    return tab
+
+
+@pytest.mark.parametrize("J1,J2,h", [(1.0, 0.5, 0.0), (1.0, 1.0, 3.0), (1.0, 2.5, -1.25), (-0.5, 0.0, 7.0),
+                                     (1.0, 1.5, 4.5), (0.0, 1.0, 0.3)])
+def test_tables_equal_oracle(J1, J2, h):
+    for T in np.geomspace(0.05, 5.0, 37):
+        assert np.array_equal(crbm.table_for(J1, J2, h, float(T)), _oracle_table(J1, J2, h, float(T))), T
+
+
+def test_table_errors():
+    with pytest.raises(crbm.CrbmError) as e:
+        crbm.table_for(1.0, 0.5, 0.0, 0.0)
+    assert e.value.code == crbm.CRBM_EINVAL
+    with pytest.raises(crbm.CrbmError) as e:
+        crbm.table_for(1.0, 0.5, 0.0, float("nan"))
+    assert e.value.code == crbm.CRBM_EINVAL
+    with pytest.raises(crbm.CrbmError) as e:
+        crbm.table_for(40000.0, 0.5, 0.0, 1.0)
+    assert e.value.code == crbm.CRBM_ERANGE
+    with pytest.raises(crbm.CrbmError) as e:
+        crbm.table_for(1.0, 0.5, 0.0, 1e-6)  # weights beyond int32 in 16.16
+    assert e.value.code == crbm.CRBM_ERANGE

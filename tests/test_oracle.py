@@ -326,3 +326,23 @@ def test_critical_point_closed_forms():
     assert abs(neel(1.0, 2.0) - third(1.0, 2.0)) < 1e-15
     assert abs(P.tm_ground_energy(6, 1.0, 1.0, 1.5) - neel(1.0, 1.5)) < 1e-12
     assert abs(P.tm_ground_energy(6, 1.0, 1.0, 2.5) - third(1.0, 2.5)) < 1e-12
+
+
+def test_philox_matches_rocrand_engine():
+    """Strong pin of the oracle's Philox4x32-10: equal to rocRAND's engine
+    (called as a library on the host) on random counters and keys."""
+    import ctypes as ct
+    path = os.path.join(os.path.dirname(__file__), "librocrand_probe.so")
+    if not os.path.exists(path):
+        from tests import helpers_build
+        helpers_build.build()
+    lib = ct.CDLL(path)
+    rng = np.random.default_rng(12345)
+    for _ in range(2000):
+        c = rng.integers(0, 2 ** 32, 4, dtype=np.uint64).astype(np.uint32)
+        c[1] &= (1 << 30) - 1  # the probe reaches word 1 through a 64-bit offset
+        k = rng.integers(0, 2 ** 32, 2, dtype=np.uint64).astype(np.uint32)
+        o = np.zeros(4, np.uint32)
+        lib.rocrand_philox_block(c.ctypes.data_as(ct.c_void_p), k.ctypes.data_as(ct.c_void_p),
+                                 o.ctypes.data_as(ct.c_void_p))
+        assert np.array_equal(o, oracle.philox(c, k)), (c, k)
