@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Benchmark: CRBM block-Gibbs sampling of the Shastry-Sutherland Ising lattice
+on one MI355X.
+
+One step = the whole annealing workload at 18x18 (the paper's largest lattice,
+324 spins): J2/J1 in {0.5, 1.0, 1.5, 2.0} x 16 fields h/J1 = 3j/15 in [0, 3]
+= 64 Hamiltonian points, 4096 chains each (262,144 chains), geometric anneal
+T 5.0 -> 0.05 over 10^4 sweeps, 16.16 fixed-point couplings, then the exact
+final-state energy and magnetisation of every point.  Inputs (tables, initial
+spins) are resident in HBM before the timed region.
+
+Prints one JSON line (metric, value = visible spin-updates/s, roofline of the
+Gibbs kernel, CPU-oracle baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spin-updates/s + energy ESS/s at 18x18, learned-MH vs plain Gibbs"
+L = 18
+S = 10000
+CHAINS = 4096
+SEED = 0x5EED000000000002
+J2S = (0.5, 1.0, 1.5, 2.0)
+HS = tuple(3.0 * j / 15 for j in range(16))
+
+# Algorithmic integer work per visible spin and sweep (documented in the design doc):
+# 3.5 stochastic units (1 spin + 2.5 hidden), each needing a 16-bit Philox
+# slot (1/8 of a Philox4x32-10 block = 10 rounds x (2 mul-hi/lo + 2 xor3) = 40
+# ops) and one integer compare.
+OPS_PER_SPIN_SWEEP = 3.5 * (40.0 / 8.0 + 1.0)
+# MI355X integer VALU peak: 256 CUs x 64 lanes x 2.4 GHz (one 32-bit op per lane per clock)
+ALU_PEAK_OPS = 256 * 64 * 2.4e9
+
+
+def instances(crbm, chains=CHAINS):
+    out = []
+    k = 0
+    for J2 in J2S:
+        for h in HS:
+            out.append(crbm.Instance(L=L, J1=1.0, J2=J2, h=h, n_chains=chains, sched="geometric", T0=5.0,
+                                     T1=0.05, id=k))
+            k += 1
+    return out
+
+
+def cpu_baseline(sample_points=3, chains_per_point=3):
+    """The CPU oracle (single-threaded C) on a bounded sample of the same
+    workload: the first chains of a few points, full schedule."""
+    import numpy as np
+    import oracle
+    pts = [(J2S[0], HS[0]), (J2S[1], HS[15]), (J2S[2], HS[7]), (J2S[3], HS[3])][:sample_points]
+    ids = {(J2, h): 16 * J2S.index(J2) + HS.index(h) for J2, h in pts}
+    finals = {}
+    t0 = time.perf_counter()
+    for (J2, h) in pts:
+        oi = oracle.Instance(L, 1.0, J2, h, "geometric", 5.0, 0.05, id=ids[(J2, h)])
+        for ch in range(chains_per_point):
+            s, _, _ = oracle.run_chain(oi, S, SEED, ch, 0, S)
+            finals[(ids[(J2, h)], ch)] = s
+    dt = time.perf_counter() - t0
+    n = len(pts) * chains_per_point
+    rate = n * S * L * L / dt
+    return {"value": rate, "unit": "spin-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} chains ({sample_points} points x {chains_per_point}) x {S} sweeps at 18x18, "
+                      f"{dt:.1f} s single-threaded"}, finals
+
+
+def batched_uneven(crbm, torch):
+    """Uneven batch (2048 instances, L in {6..48}, 256 chains, 5000 sweeps at
+    fixed T) in one hipGraph launch of persistent kernels."""
+    from paper_2511_20911_amd import workloads
+    pts = workloads.batched_uneven()
+    insts = [crbm.Instance(L=p.L, J1=p.J1, J2=p.J2, h=p.h, n_chains=p.n_chains, sched=p.sched, T0=p.T0,
+                           T1=p.T1, id=p.id) for p in pts]
+    sweeps = 5000
+    for Lb in sorted({p.L for p in pts}):
+        crbm.autotune(Lb, n_chains=2048, n_sweeps=10)
+    smp = crbm.Sampler(insts, seed=workloads.SEED_BATCHED, n_sweeps=2 * sweeps, launch="graph")
+    smp.sample(50)  # warm-up launch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    smp.sample(sweeps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    work = sum(p.n_chains * p.L * p.L for p in pts) * sweeps
+    return {"workload": "2048 instances, L in {6,12,18,24,36,48} by seed, J2/J1~U[0.2,2.5], h/J1~U[0,3], "
+                        "T~logU[0.05,5] fixed, 256 chains each, 5000 sweeps, one hipGraph launch",
+            "spin_updates_per_s": work / (ms / 1e3), "ms": ms,
+            "tiling": {str(Lb): crbm.get_tiling(Lb) for Lb in sorted({p.L for p in pts})}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweeps", type=int, default=S, help="sweeps per step (default: the full schedule)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the tiling autotuner")
+    ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch graph measurement")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the sampler's chains are independent and this build runs on a "
+              "single MI355X; multi-GPU runs are not part of it.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2511_20911_amd as crbm
+
+    torch.cuda.set_device(0)
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    tuning = None
+    if not args.no_tune:
+        r, w, rate = crbm.autotune(L, n_chains=8192, n_sweeps=40)
+        tuning = {"rows_per_lane": r, "waves_per_block": w, "tune_rate": rate}
+    rows, wpb = crbm.get_tiling(L)
+    insts = instances(crbm)
+    t0 = time.perf_counter()
+    smp = crbm.Sampler(insts, seed=SEED, n_sweeps=S, measure_every=1, burn_in=S - 1)
+    torch.cuda.synchronize()
+    create_ms = (time.perf_counter() - t0) * 1e3
+    init_spins, _ = smp.get_state()
+    n_sweeps = min(args.sweeps, S)
+    stream = torch.cuda.current_stream()
+
+    step_ms, kern_ms = [], []
+    obs = None
+    for it in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        smp.set_state(init_spins, 0)
+        smp.reset_observables()
+        k0 = torch.cuda.Event(enable_timing=True)
+        k1 = torch.cuda.Event(enable_timing=True)
+        k0.record(stream)
+        smp.sample(n_sweeps)
+        k1.record(stream)
+        obs = smp.observables() if n_sweeps == S else None
+        torch.cuda.synchronize()
+        t_end = time.perf_counter()
+        if it >= args.warmup:
+            step_ms.append((t_end - t_start) * 1e3)
+            kern_ms.append(k0.elapsed_time(k1))
+
+    chains = smp.total_chains
+    ms = float(np.mean(step_ms))
+    value = chains * n_sweeps * L * L / (ms / 1e3)
+    kms = float(np.mean(kern_ms))
+    achieved = chains * n_sweeps * L * L * OPS_PER_SPIN_SWEEP / (kms / 1e3)
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "spin-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": "SS Ising 18x18 periodic, J1=1, J2/J1 in {0.5,1.0,1.5,2.0} x 16 h/J1 in [0,3], "
+                        "4096 chains per point (262144 chains), geometric anneal T 5.0->0.05 over 10^4 sweeps, "
+                        "16.16 fixed point, seeded +-1 start",
+            "L": L, "points": len(insts), "chains": chains, "sweeps": n_sweeps,
+            "node_updates_per_s": value * 3.5,
+            "create_and_tables_ms": create_ms,
+            "tiling": {"rows_per_lane": rows, "lanes_per_chain": (L // 2) // rows, "waves_per_block": wpb,
+                       "autotuned": tuning is not None},
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": ALU_PEAK_OPS / 1e12,
+            "unit": "TOP/s",
+            "frac": achieved / ALU_PEAK_OPS,
+            "traffic": None,
+            "kernel": f"gibbs_kernel<{L},{rows}>",
+            "kernel_ms": kms,
+            "ops_per_spin_sweep": OPS_PER_SPIN_SWEEP,
+        },
+    }
+    if obs is not None:
+        E = np.array([o["E_per_spin"] for o in obs]).reshape(4, 16)
+        m = np.array([o["m"] for o in obs]).reshape(4, 16)
+        result["final_state"] = {"J2": list(J2S), "E_per_spin_mean": E.round(5).tolist(),
+                                 "m_mean": m.round(5).tolist()}
+    if not args.no_batched:
+        result["batched_uneven"] = batched_uneven(crbm, torch)
+    if not args.no_cpu_baseline and n_sweeps == S:
+        base, finals = cpu_baseline()
+        result["cpu_baseline"] = base
+        # the sampled oracle chains double as a parity check of this very run
+        spins, _ = smp.get_state()
+        parts = smp.split_spins(spins.cpu())
+        result["cpu_baseline"]["parity_sampled_chains"] = all(
+            np.array_equal(parts[i][ch].numpy(), s) for (i, ch), s in finals.items())
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

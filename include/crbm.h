@@ -45,7 +45,7 @@ enum {
     CRBM_ERANGE = -2,      /* a fixed-point weight or bias does not fit in int32 */
     CRBM_ENOMEM = -3,      /* device or host allocation failed */
     CRBM_EHIP = -4,        /* a HIP runtime call failed */
-    CRBM_EUNSUPPORTED = -5,/* valid request this build does not implement (open boundaries, L > CRBM_MAX_L) */
+    CRBM_EUNSUPPORTED = -5,/* valid request this build does not implement (open boundaries, an L without a compiled kernel) */
     CRBM_ESTATE = -6       /* misuse of a handle (e.g. sampling past the end of the schedule) */
 };
 
@@ -56,12 +56,12 @@ enum {
     CRBM_SCHED_EXPLICIT = 3   /* T_s = T_explicit[s] */
 };
 
-#define CRBM_MAX_L 32      /* largest lattice side supported by this build */
+#define CRBM_MAX_L 96      /* largest lattice side supported by this build */
 #define CRBM_N_ACC 11      /* per-chain accumulator words, see crbm_obs */
 
 /* One Hamiltonian point (one "instance").  Host memory, copied at create. */
 typedef struct {
-    int32_t L;                 /* lattice side: even, 4 <= L <= CRBM_MAX_L */
+    int32_t L;                 /* lattice side: even, 4 <= L <= 32, or 36, 40, 48, 64, 72, 96 */
     int32_t periodic;          /* must be 1 (periodic in both directions) */
     double J1, J2, h;          /* couplings and field; |J| * 2^16 < 2^31 */
     int32_t n_chains;          /* independent chains, >= 1 */
@@ -77,8 +77,16 @@ typedef struct {
     int32_t measure_every;     /* 0 = accumulate nothing; k > 0 = accumulate every k-th sweep at or after burn_in */
     int64_t burn_in;           /* first sweep that may be accumulated */
     void* stream;              /* hipStream_t (NULL = default stream) */
-    int32_t tile_rows;         /* cell rows per lane: 0 = library choice, else must divide L/2 */
+    int32_t tile_rows;         /* cell rows per lane: 0 = tuned/default choice, else must divide L/2 */
+    int32_t launch_mode;       /* CRBM_LAUNCH_DIRECT or CRBM_LAUNCH_GRAPH */
+    int32_t waves_per_block;   /* 1..4 wavefronts per workgroup; 0 = tuned/default choice */
 } crbm_config;
+
+enum {
+    CRBM_LAUNCH_DIRECT = 0, /* one grid launch per lattice size, one wavefront per work item */
+    CRBM_LAUNCH_GRAPH = 1   /* one hipGraph launch: a queue-reset node, then one persistent kernel per
+                               lattice size on parallel branches, each draining a work queue */
+};
 
 /* Per-instance observables, host memory, filled by crbm_observables.
  * Sums run over chains and accumulated sweeps.  Counts of one state:
@@ -134,6 +142,20 @@ int64_t crbm_total_chains(const crbm_t* h);
 
 /* Zero the accumulators (e.g. after a burn-in phase). */
 int crbm_reset_observables(crbm_t* h);
+
+/* Autotuner (batched launches): time every compiled tiling of lattice side L
+ * (cell rows per lane x wavefronts per workgroup) on the current device with
+ * n_chains chains for n_sweeps sweeps, keep the fastest as the process-wide
+ * choice for L and return it.  Enqueues work on `stream` and synchronises it.
+ * best_rate: visible spin-updates/s of the winner (may be NULL). */
+int crbm_autotune(int32_t L, int32_t n_chains, int32_t n_sweeps, void* stream, int32_t* best_rows,
+                  int32_t* best_waves_per_block, double* best_rate);
+
+/* Process-wide tiling choice for lattice side L (used by crbm_create when the
+ * config leaves tile_rows / waves_per_block at 0).  set: rows must divide L/2
+ * and have a compiled kernel; waves_per_block in 1..4. */
+int crbm_set_tiling(int32_t L, int32_t rows, int32_t waves_per_block);
+int crbm_get_tiling(int32_t L, int32_t* rows, int32_t* waves_per_block);
 
 /* Free everything the handle owns.  NULL is allowed. */
 void crbm_destroy(crbm_t* h);

@@ -55,21 +55,21 @@
  *              t = min(2^32 - 1, floor(p * 2^32 + 0.5))   (closest value).
  *   update     s = (x >= 0) ? +1 : -1; the unit becomes s if U < t(|x|),
  *              else -s, where U is the unit's 32-bit uniform.
- *   uniform    U = (P << 16) | Q, P and Q 16-bit values from the primary and
- *              refinement streams of the unit (below).
  *   Philox     out = Philox4x32-10(ctr = (c0, sweep, chain, (id << 3) | stream),
  *                                  key = (seed & 0xffffffff, seed >> 32)).
- *              Streams: 0 init, 1 hidden primary, 2 hidden refinement,
- *              3 visible primary, 4 visible refinement, 5 MH, 6 AR proposals.
- *              A 16-bit slot q of a block is (out[(q & 7) >> 1] >> (16 (q & 1)))
- *              & 0xffff.
- *   unit map   column words: word w covers columns 32w .. 32w + m_w - 1,
- *              m_w = min(32, L - 32 w), and cells 16w .. 16w + m_w/2 - 1.
- *              Hidden unit (k,i,j), w = j/16, n_w = m_w/2:
- *                  q = k n_w + (j - 16 w).
- *              Spin (r,c), i = r/2, w = c/32:
- *                  q = (r - 2i) m_w + (c - 32 w).
- *              c0 = ((i W + w) << 5) | (q >> 3), W = ceil(L/32).
+ *              Streams: 0 init, 1 hidden, 3 visible primary, 4 visible
+ *              refinement, 5 MH, 6 AR proposals.
+ *   column words: word w covers columns 32w .. 32w + m_w - 1,
+ *              m_w = min(32, L - 32 w), and cells 16w .. 16w + m_w/2 - 1;
+ *              W = ceil(L/32).
+ *   hidden uniform (bit-sliced): hidden unit (k,i,j), w = j/16, n = m_w/2,
+ *              u = 2 n (k/2) + 2 (j - 16 w) + (k % 2), pw = u/32.  Bit b of U
+ *              (b = 0 most significant) is bit u%32 of out[b & 3] of the block
+ *              c0 = ((i W + w) << 8) | (pw << 3) | (b >> 2), stream 1.
+ *   spin uniform: U = (P << 16) | Q with P, Q the 16-bit slot q of the blocks
+ *              c0 = ((i W + w) << 5) | (q >> 3) of streams 3 and 4, for spin
+ *              (r,c), i = r/2, w = c/32, q = (r - 2i) m_w + (c - 32 w); slot q
+ *              of a block is (out[(q & 7) >> 1] >> (16 (q & 1))) & 0xffff.
  *   init       s(r,c) = +1 iff bit b = (rL + c) & 127 of the block
  *              Philox(ctr = ((rL + c) >> 7, 0, chain, id << 3 | 0)) is set,
  *              bit b being bit (b & 31) of out[b >> 5].
@@ -136,13 +136,28 @@ static uint32_t unit_uniform(uint64_t seed, uint32_t id, uint32_t stream_primary
 uint32_t oracle_uniform_hidden(uint64_t seed, uint32_t id, uint32_t chain, uint32_t sweep,
                                int L, int k, int i, int j)
 {
+    /* Bit-sliced draw: the hidden units of (cell row i, column word w) are
+     * numbered u = 2 n (k / 2) + 2 (j - 16 w) + (k % 2), n = cells in the
+     * word, and packed 32 to a word (pw = u / 32, bit u % 32).  Bit b of the
+     * unit's uniform (b = 0 the most significant) is bit (u % 32) of random
+     * word b & 3 of the Philox block with counter word
+     * ((i W + w) << 8) | (pw << 3) | (b >> 2), stream 1. */
     int W = (L + 31) / 32;
     int w = j / 16;
     int m = (L - 32 * w) < 32 ? (L - 32 * w) : 32;
     int n = m / 2;
-    int q = k * n + (j - 16 * w);
-    uint32_t c0 = ((uint32_t)(i * W + w) << 5) | (uint32_t)(q >> 3);
-    return unit_uniform(seed, id, 1u, chain, sweep, c0, q);
+    int u = 2 * n * (k / 2) + 2 * (j - 16 * w) + (k % 2);
+    int pw = u / 32, bit = u % 32;
+    uint32_t key[2] = { (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32) };
+    uint32_t U = 0;
+    for (int b = 0; b < 32; ++b) {
+        uint32_t ctr[4] = { ((uint32_t)(i * W + w) << 8) | ((uint32_t)pw << 3) | (uint32_t)(b >> 2),
+                            sweep, chain, (id << 3) | 1u };
+        uint32_t out[4];
+        oracle_philox4x32_10(ctr, key, out);
+        U |= ((out[b & 3] >> bit) & 1u) << (31 - b);
+    }
+    return U;
 }
 
 uint32_t oracle_uniform_visible(uint64_t seed, uint32_t id, uint32_t chain, uint32_t sweep,

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(HERE, "libcrbm.so")
 CRBM_OK, CRBM_EINVAL, CRBM_ERANGE, CRBM_ENOMEM, CRBM_EHIP, CRBM_EUNSUPPORTED, CRBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
 SCHED = {"const": 0, "linear": 1, "geometric": 2, "explicit": 3}
 N_ACC = 11
-MAX_L = 32
+MAX_L = 96
+SUPPORTED_L = tuple(range(4, 33, 2)) + (36, 40, 48, 64, 72, 96)
 
 
 class CrbmError(RuntimeError):
@@ -45,7 +46,11 @@ class _Config(ct.Structure):
     _fields_ = [
         ("seed", ct.c_uint64), ("n_sweeps", ct.c_int64), ("measure_every", ct.c_int32),
         ("burn_in", ct.c_int64), ("stream", ct.c_void_p), ("tile_rows", ct.c_int32),
+        ("launch_mode", ct.c_int32), ("waves_per_block", ct.c_int32),
     ]
+
+
+LAUNCH = {"direct": 0, "graph": 1}
 
 
 class _Obs(ct.Structure):
@@ -86,6 +91,10 @@ def lib() -> ct.CDLL:
         L.crbm_threshold.restype = ct.c_uint32
         L.crbm_sweep_table.argtypes = [ct.c_void_p, ct.c_int32, ct.c_int64, p(ct.c_uint32)]
         L.crbm_table_for.argtypes = [ct.c_double, ct.c_double, ct.c_double, ct.c_double, p(ct.c_uint32)]
+        L.crbm_autotune.argtypes = [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p, p(ct.c_int32), p(ct.c_int32),
+                                    p(ct.c_double)]
+        L.crbm_set_tiling.argtypes = [ct.c_int32, ct.c_int32, ct.c_int32]
+        L.crbm_get_tiling.argtypes = [ct.c_int32, p(ct.c_int32), p(ct.c_int32)]
         _lib = L
     return _lib
 
@@ -123,6 +132,25 @@ def table_for(J1: float, J2: float, h: float, T: float) -> np.ndarray:
     return out
 
 
+def autotune(L: int, n_chains: int = 4096, n_sweeps: int = 50, stream=None):
+    """Time every compiled tiling of lattice side L on this GPU; the fastest
+    becomes the process-wide choice.  Returns (rows, waves_per_block, spin-updates/s)."""
+    r, w, rate = ct.c_int32(), ct.c_int32(), ct.c_double()
+    _check(lib().crbm_autotune(L, n_chains, n_sweeps, _stream_handle(stream), ct.byref(r), ct.byref(w),
+                               ct.byref(rate)))
+    return int(r.value), int(w.value), float(rate.value)
+
+
+def set_tiling(L: int, rows: int, waves_per_block: int = 4):
+    _check(lib().crbm_set_tiling(L, rows, waves_per_block))
+
+
+def get_tiling(L: int):
+    r, w = ct.c_int32(), ct.c_int32()
+    _check(lib().crbm_get_tiling(L, ct.byref(r), ct.byref(w)))
+    return int(r.value), int(w.value)
+
+
 def _stream_handle(stream):
     import torch
     if stream is None:
@@ -134,7 +162,8 @@ class Sampler:
     """Handle on crbm_create / crbm_sample / crbm_observables."""
 
     def __init__(self, instances: Sequence[Instance], seed: int, n_sweeps: int, measure_every: int = 0,
-                 burn_in: int = 0, stream=None, tile_rows: int = 0):
+                 burn_in: int = 0, stream=None, tile_rows: int = 0, launch: str = "direct",
+                 waves_per_block: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the CRBM sampler runs only on the HIP device")
@@ -150,7 +179,8 @@ class Sampler:
             arr[k] = _Instance(I.L, I.periodic, I.J1, I.J2, I.h, I.n_chains, SCHED[I.sched], I.T0,
                                I.T0 if I.T1 is None else I.T1, te, I.id)
         self.stream = stream
-        cfg = _Config(seed, n_sweeps, measure_every, burn_in, _stream_handle(stream), tile_rows)
+        cfg = _Config(seed, n_sweeps, measure_every, burn_in, _stream_handle(stream), tile_rows, LAUNCH[launch],
+                      waves_per_block)
         h = ct.c_void_p()
         _check(lib().crbm_create(arr, len(self.instances), ct.byref(cfg), ct.byref(h)))
         self._h = h

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcrbm.so")
 
-SOURCES = ["gibbs.hip", "crbm_api.cpp"]
+SOURCES = ["gibbs_aux.hip", "gibbs_tiles_a.hip", "gibbs_tiles_b.hip", "gibbs_tiles_c.hip",
+           "gibbs_tiles_d.hip", "gibbs_tiles_e.hip", "gibbs_tiles_f.hip", "crbm_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -47,7 +48,7 @@ def build(verbose: bool = False) -> str:
             lang = [] if src.endswith(".hip") else ["-x", "hip"]
             cmds.append([HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
             objs.append(obj)
-        with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+        with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 4)) as ex:
             outs = list(ex.map(_run, cmds))
         if verbose:
             for o in outs:

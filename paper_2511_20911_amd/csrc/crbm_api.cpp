@@ -9,8 +9,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "crbm.h"
@@ -89,17 +91,48 @@ int build_table(int64_t J1q, int64_t J2q, int64_t hq, double T, uint32_t* out) {
     return CRBM_OK;
 }
 
+// Default cell rows per lane: the compiled tiling that keeps the most lanes of
+// a wavefront busy (G lanes per chain, floor(64/G) chains), preferring R = 3.
 int default_rows(int L) {
     const int C = L / 2;
-    for (int R = 3; R >= 1; --R)
-        if (C % R == 0 && gibbs_supported(L, R)) return R;
-    return 1;
+    int best = 0;
+    double best_score = -1.0;
+    for (int R = 1; R <= C; ++R) {
+        if (C % R != 0 || !gibbs_supported(L, R)) continue;
+        const int G = C / R;
+        if (G > 64) continue;
+        const double util = (double)(G * (64 / G)) / 64.0;
+        const double score = util - 0.001 * std::abs(R - 3);
+        if (score > best_score) {
+            best_score = score;
+            best = R;
+        }
+    }
+    return best;
+}
+
+bool lattice_supported(int L) { return default_rows(L) > 0; }
+
+// Process-wide tiling choice per lattice side (set by the autotuner or by hand).
+struct Tiling {
+    int rows = 0, wpb = 0;
+};
+std::mutex g_tiling_mu;
+Tiling g_tiling[CRBM_MAX_L + 1];
+
+Tiling tiling_for(int L) {
+    std::lock_guard<std::mutex> lk(g_tiling_mu);
+    Tiling t = g_tiling[L];
+    if (t.rows == 0) t.rows = default_rows(L);
+    if (t.wpb == 0) t.wpb = 4;
+    return t;
 }
 
 struct Group {
-    int L = 0, R = 0;
+    int L = 0, R = 0, wpb = 4, grid_blocks = 0;
     std::vector<Item> items;
     Item* d_items = nullptr;
+    hipGraphNode_t node = nullptr;
 };
 
 }  // namespace
@@ -114,20 +147,88 @@ struct crbm_s {
     std::vector<uint32_t> h_tables;
     crbm_config cfg{};
     hipStream_t stream = nullptr;
-    int64_t total_chains = 0, total_rows = 0, total_spins = 0;
+    int64_t total_chains = 0, total_words = 0, total_spins = 0;
     int64_t S = 0, cur = 0;
     uint32_t* d_state = nullptr;
     uint32_t* d_tables = nullptr;
     int64_t* d_acc = nullptr;
+    uint32_t* d_queue = nullptr;  // one work counter per group (graph mode)
     std::vector<Group> groups;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
     ~crbm_s() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
         if (d_state) (void)hipFree(d_state);
         if (d_tables) (void)hipFree(d_tables);
         if (d_acc) (void)hipFree(d_acc);
+        if (d_queue) (void)hipFree(d_queue);
         for (auto& g : groups)
             if (g.d_items) (void)hipFree(g.d_items);
     }
 };
+
+namespace {
+
+GibbsArgs make_args(const crbm_s* h, const Group& g, size_t gi, int64_t s0, int64_t s1, int8_t* spins_out,
+                    int32_t* trace) {
+    GibbsArgs a{};
+    a.state = h->d_state;
+    a.tables = h->d_tables;
+    a.items = g.d_items;
+    a.n_items = (int32_t)g.items.size();
+    a.measure_every = h->cfg.measure_every;
+    a.s0 = s0;
+    a.s1 = s1;
+    a.burn_in = h->cfg.burn_in;
+    a.seed = h->cfg.seed;
+    a.acc = h->d_acc;
+    a.trace = trace;
+    a.total_chains = h->total_chains;
+    a.spins_out = spins_out;
+    a.queue = (h->cfg.launch_mode == CRBM_LAUNCH_GRAPH) ? h->d_queue + gi : nullptr;
+    a.waves_per_block = g.wpb;
+    a.grid_blocks = g.grid_blocks;
+    return a;
+}
+
+// Graph: [reset the work counters] -> one persistent Gibbs kernel per lattice
+// size, all depending only on the reset node (parallel branches).
+int build_graph(crbm_s* h) {
+    HIP_TRY(hipGraphCreate(&h->graph, 0), "hipGraphCreate");
+    hipGraphNode_t reset = nullptr;
+    {
+        int n = (int)h->groups.size();
+        uint32_t* q = h->d_queue;
+        void* args[] = {&q, &n};
+        hipKernelNodeParams p{};
+        p.func = const_cast<void*>(zero_u32_fn());
+        p.gridDim = dim3((unsigned)((n + 255) / 256));
+        p.blockDim = dim3(256);
+        p.sharedMemBytes = 0;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        HIP_TRY(hipGraphAddKernelNode(&reset, h->graph, nullptr, 0, &p), "graph reset node");
+    }
+    for (size_t gi = 0; gi < h->groups.size(); ++gi) {
+        Group& g = h->groups[gi];
+        GibbsArgs a = make_args(h, g, gi, 0, 0, nullptr, nullptr);
+        void* args[] = {&a};
+        hipKernelNodeParams p{};
+        p.func = const_cast<void*>(gibbs_kernel_fn(g.L, g.R));
+        const int items_blocks = (int)((g.items.size() + g.wpb - 1) / g.wpb);
+        p.gridDim = dim3((unsigned)std::max(1, std::min(items_blocks, g.grid_blocks)));
+        p.blockDim = dim3((unsigned)(64 * g.wpb));
+        p.sharedMemBytes = 0;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        HIP_TRY(hipGraphAddKernelNode(&g.node, h->graph, &reset, 1, &p), "graph Gibbs node");
+    }
+    HIP_TRY(hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    return CRBM_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -145,12 +246,16 @@ int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cf
     if (!cfg) return fail(CRBM_EINVAL, "cfg is NULL");
     if (cfg->n_sweeps < 1) return fail(CRBM_EINVAL, "n_sweeps must be >= 1");
     if (cfg->measure_every < 0 || cfg->burn_in < 0) return fail(CRBM_EINVAL, "measure_every and burn_in must be >= 0");
+    if (cfg->launch_mode != CRBM_LAUNCH_DIRECT && cfg->launch_mode != CRBM_LAUNCH_GRAPH)
+        return fail(CRBM_EINVAL, "unknown launch_mode");
+    if (cfg->waves_per_block < 0 || cfg->waves_per_block > 4) return fail(CRBM_EINVAL, "waves_per_block must be 0..4");
     const double lim = 2147483647.0 / 65536.0;
     for (int i = 0; i < n_inst; ++i) {
         const crbm_instance& I = inst[i];
         const std::string tag = "instance " + std::to_string(i) + ": ";
         if (I.L < 4 || (I.L & 1)) return fail(CRBM_EINVAL, tag + "L must be even and >= 4");
-        if (I.L > CRBM_MAX_L) return fail(CRBM_EUNSUPPORTED, tag + "L > CRBM_MAX_L");
+        if (I.L > CRBM_MAX_L || !lattice_supported(I.L))
+            return fail(CRBM_EUNSUPPORTED, tag + "no compiled kernel for this L");
         if (I.periodic != 1) return fail(CRBM_EUNSUPPORTED, tag + "only periodic lattices are supported");
         if (!std::isfinite(I.J1) || !std::isfinite(I.J2) || !std::isfinite(I.h))
             return fail(CRBM_EINVAL, tag + "J1, J2, h must be finite");
@@ -214,25 +319,28 @@ int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cf
             }
         }
         h->gbase[i] = h->total_chains;
-        h->state_off[i] = h->total_rows;
+        h->state_off[i] = h->total_words;
         h->spin_off[i] = h->total_spins;
         h->total_chains += I.n_chains;
-        h->total_rows += (int64_t)I.n_chains * I.L;
+        h->total_words += (int64_t)I.n_chains * I.L * ((I.L + 31) / 32);
         h->total_spins += (int64_t)I.n_chains * I.L * I.L;
     }
 
     // work items, grouped by (L, R)
     for (int i = 0; i < n_inst; ++i) {
         const crbm_instance& I = h->inst[i];
-        const int R = cfg->tile_rows ? cfg->tile_rows : default_rows(I.L);
+        const Tiling tl = tiling_for(I.L);
+        const int R = cfg->tile_rows ? cfg->tile_rows : tl.rows;
+        const int wpb = cfg->waves_per_block ? cfg->waves_per_block : tl.wpb;
         Group* grp = nullptr;
         for (auto& g : h->groups)
-            if (g.L == I.L && g.R == R) grp = &g;
+            if (g.L == I.L && g.R == R && g.wpb == wpb) grp = &g;
         if (!grp) {
             h->groups.push_back(Group{});
             grp = &h->groups.back();
             grp->L = I.L;
             grp->R = R;
+            grp->wpb = wpb;
         }
         const int cpw = chains_per_wave(I.L, R);
         for (int c0 = 0; c0 < I.n_chains; c0 += cpw) {
@@ -242,7 +350,7 @@ int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cf
             it.chain0 = (uint32_t)c0;
             it.nchains = (uint32_t)std::min(cpw, I.n_chains - c0);
             it.gbase = (uint64_t)(h->gbase[i] + c0);
-            it.state_off = (uint64_t)(h->state_off[i] + (int64_t)c0 * I.L);
+            it.state_off = (uint64_t)(h->state_off[i] + (int64_t)c0 * I.L * ((I.L + 31) / 32));
             it.spin_off = (uint64_t)(h->spin_off[i] + (int64_t)c0 * I.L * I.L);
             it.tab_off = h->tab_off[i];
             it.tab_stride = h->tab_stride[i];
@@ -253,7 +361,7 @@ int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cf
 
     // device state
     hipError_t e;
-    if ((e = hipMalloc(&h->d_state, sizeof(uint32_t) * (size_t)h->total_rows)) != hipSuccess ||
+    if ((e = hipMalloc(&h->d_state, sizeof(uint32_t) * (size_t)h->total_words)) != hipSuccess ||
         (e = hipMalloc(&h->d_tables, sizeof(uint32_t) * h->h_tables.size())) != hipSuccess ||
         (e = hipMalloc(&h->d_acc, sizeof(int64_t) * CRBM_N_ACC * (size_t)h->total_chains)) != hipSuccess) {
         delete h;
@@ -263,6 +371,22 @@ int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cf
         if ((e = hipMalloc(&g.d_items, sizeof(Item) * g.items.size())) != hipSuccess) {
             delete h;
             return fail(CRBM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+    }
+    if (cfg->launch_mode == CRBM_LAUNCH_GRAPH) {
+        if ((e = hipMalloc(&h->d_queue, sizeof(uint32_t) * h->groups.size())) != hipSuccess) {
+            delete h;
+            return fail(CRBM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        int dev = 0, cus = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        for (auto& g : h->groups) {
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gibbs_kernel_fn(g.L, g.R), 64 * g.wpb, 0) !=
+                    hipSuccess || per_cu < 1)
+                per_cu = 1;
+            g.grid_blocks = std::max(1, cus) * per_cu;
         }
     }
     int rc = CRBM_OK;
@@ -279,6 +403,7 @@ int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cf
     }
     // the host vectors must outlive the async copies
     chk(hipStreamSynchronize(h->stream), "synchronize");
+    if (rc == CRBM_OK && cfg->launch_mode == CRBM_LAUNCH_GRAPH) rc = build_graph(h);
     if (rc != CRBM_OK) {
         delete h;
         return rc;
@@ -292,24 +417,122 @@ int crbm_sample(crbm_t* h, int64_t n_sweeps, int8_t* spins_out, int32_t* counts_
     if (!h) return fail(CRBM_EINVAL, "handle is NULL");
     if (n_sweeps < 0) return fail(CRBM_EINVAL, "n_sweeps must be >= 0");
     if (h->cur + n_sweeps > h->S) return fail(CRBM_ESTATE, "sampling past the end of the schedule");
-    for (auto& g : h->groups) {
-        GibbsArgs a{};
-        a.state = h->d_state;
-        a.tables = h->d_tables;
-        a.items = g.d_items;
-        a.n_items = (int32_t)g.items.size();
-        a.measure_every = h->cfg.measure_every;
-        a.s0 = h->cur;
-        a.s1 = h->cur + n_sweeps;
-        a.burn_in = h->cfg.burn_in;
-        a.seed = h->cfg.seed;
-        a.acc = h->d_acc;
-        a.trace = counts_trace;
-        a.total_chains = h->total_chains;
-        a.spins_out = spins_out;
-        HIP_TRY(launch_gibbs(g.L, g.R, a, h->stream), "gibbs kernel");
+    if (h->cfg.launch_mode == CRBM_LAUNCH_GRAPH) {
+        for (size_t gi = 0; gi < h->groups.size(); ++gi) {
+            Group& g = h->groups[gi];
+            GibbsArgs a = make_args(h, g, gi, h->cur, h->cur + n_sweeps, spins_out, counts_trace);
+            void* args[] = {&a};
+            hipKernelNodeParams p{};
+            p.func = const_cast<void*>(gibbs_kernel_fn(g.L, g.R));
+            const int items_blocks = (int)((g.items.size() + g.wpb - 1) / g.wpb);
+            p.gridDim = dim3((unsigned)std::max(1, std::min(items_blocks, g.grid_blocks)));
+            p.blockDim = dim3((unsigned)(64 * g.wpb));
+            p.sharedMemBytes = 0;
+            p.kernelParams = args;
+            p.extra = nullptr;
+            HIP_TRY(hipGraphExecKernelNodeSetParams(h->exec, g.node, &p), "update graph node");
+        }
+        HIP_TRY(hipGraphLaunch(h->exec, h->stream), "hipGraphLaunch");
+    } else {
+        for (size_t gi = 0; gi < h->groups.size(); ++gi) {
+            const GibbsArgs a = make_args(h, h->groups[gi], gi, h->cur, h->cur + n_sweeps, spins_out, counts_trace);
+            HIP_TRY(launch_gibbs(h->groups[gi].L, h->groups[gi].R, a, h->stream), "gibbs kernel");
+        }
     }
     h->cur += n_sweeps;
+    return CRBM_OK;
+}
+
+int crbm_set_tiling(int32_t L, int32_t rows, int32_t waves_per_block) {
+    g_err.clear();
+    if (L < 4 || L > CRBM_MAX_L || (L & 1)) return fail(CRBM_EINVAL, "bad L");
+    if (rows < 1 || (L / 2) % rows != 0 || !gibbs_supported(L, rows)) return fail(CRBM_EUNSUPPORTED, "no such tiling");
+    if (waves_per_block < 1 || waves_per_block > 4) return fail(CRBM_EINVAL, "waves_per_block must be 1..4");
+    std::lock_guard<std::mutex> lk(g_tiling_mu);
+    g_tiling[L].rows = rows;
+    g_tiling[L].wpb = waves_per_block;
+    return CRBM_OK;
+}
+
+int crbm_get_tiling(int32_t L, int32_t* rows, int32_t* waves_per_block) {
+    g_err.clear();
+    if (L < 4 || L > CRBM_MAX_L || (L & 1) || !lattice_supported(L)) return fail(CRBM_EUNSUPPORTED, "bad L");
+    const Tiling t = tiling_for(L);
+    if (rows) *rows = t.rows;
+    if (waves_per_block) *waves_per_block = t.wpb;
+    return CRBM_OK;
+}
+
+int crbm_autotune(int32_t L, int32_t n_chains, int32_t n_sweeps, void* stream, int32_t* best_rows,
+                  int32_t* best_waves_per_block, double* best_rate) {
+    g_err.clear();
+    if (L < 4 || L > CRBM_MAX_L || (L & 1) || !lattice_supported(L)) return fail(CRBM_EUNSUPPORTED, "bad L");
+    if (n_chains < 1 || n_sweeps < 1) return fail(CRBM_EINVAL, "n_chains and n_sweeps must be >= 1");
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    double best = -1.0;
+    int bR = 0, bW = 0;
+    const int wpbs[] = {1, 2, 4};
+    for (int R = 1; R <= L / 2; ++R) {
+        if ((L / 2) % R != 0 || !gibbs_supported(L, R) || (L / 2) / R > 64) continue;
+        for (int wpb : wpbs) {
+            crbm_instance I{};
+            I.L = L;
+            I.periodic = 1;
+            I.J1 = 1.0;
+            I.J2 = 1.0;
+            I.h = 1.0;
+            I.n_chains = n_chains;
+            I.sched_kind = CRBM_SCHED_CONST;
+            I.T0 = 1.0;
+            crbm_config c{};
+            c.seed = 1;
+            c.n_sweeps = 2 * (int64_t)n_sweeps + 2;
+            c.stream = stream;
+            c.tile_rows = R;
+            c.waves_per_block = wpb;
+            crbm_t* t = nullptr;
+            int rc = crbm_create(&I, 1, &c, &t);
+            if (rc != CRBM_OK) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return rc;
+            }
+            rc = crbm_sample(t, 2, nullptr, nullptr);  // warm-up
+            (void)hipEventRecord(e0, st);
+            if (rc == CRBM_OK) rc = crbm_sample(t, n_sweeps, nullptr, nullptr);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            crbm_destroy(t);
+            if (rc != CRBM_OK) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return rc;
+            }
+            const double rate = (double)n_chains * n_sweeps * L * L / (ms * 1e-3);
+            if (rate > best) {
+                best = rate;
+                bR = R;
+                bW = wpb;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (bR == 0) return fail(CRBM_EUNSUPPORTED, "no tiling for this L");
+    {
+        std::lock_guard<std::mutex> lk(g_tiling_mu);
+        g_tiling[L].rows = bR;
+        g_tiling[L].wpb = bW;
+    }
+    if (best_rows) *best_rows = bR;
+    if (best_waves_per_block) *best_waves_per_block = bW;
+    if (best_rate) *best_rate = best;
+    g_err.clear();
     return CRBM_OK;
 }
 

@@ -22,7 +22,7 @@ struct Item {
     uint32_t chain0;      // first chain of this item, within the instance
     uint32_t nchains;     // chains in this item (at most 64 / lanes-per-chain)
     uint64_t gbase;       // global chain index of chain0 (instances concatenated)
-    uint64_t state_off;   // word offset of chain0's first row in the state buffer
+    uint64_t state_off;   // word offset of chain0's first row in the state buffer ([chain][L][W])
     uint64_t spin_off;    // byte offset of chain0's spins in a [chain][L][L] int8 buffer
     uint64_t tab_off;     // word offset of the instance's first table
     uint32_t tab_stride;  // kTabWords for per-sweep tables, 0 for a constant schedule
@@ -30,7 +30,7 @@ struct Item {
 };
 
 struct GibbsArgs {
-    uint32_t* state;          // bit rows, one 32-bit word per row, chains at Item::state_off
+    uint32_t* state;          // bit rows, ceil(L/32) words per row, chains at Item::state_off
     const uint32_t* tables;   // per-instance tables, see above
     const Item* items;        // one item per wavefront
     int32_t n_items;
@@ -42,6 +42,9 @@ struct GibbsArgs {
     int32_t* trace;           // [s1 - s0][total_chains][3] or nullptr
     int64_t total_chains;
     int8_t* spins_out;        // int8 spins at Item::spin_off, or nullptr
+    uint32_t* queue;          // persistent mode: work counter (zeroed before launch); nullptr = direct
+    int32_t waves_per_block;  // 1..4 (0 = 4)
+    int32_t grid_blocks;      // persistent mode: blocks in the grid
 };
 
 // Lanes per chain for a lattice side and a number of cell rows per lane.
@@ -51,6 +54,9 @@ inline int chains_per_wave(int L, int R) { return 64 / lanes_per_chain(L, R); }
 // Returns false if no kernel was compiled for (L, R).
 bool gibbs_supported(int L, int R);
 hipError_t launch_gibbs(int L, int R, const GibbsArgs& a, hipStream_t st);
+const void* gibbs_kernel_fn(int L, int R);   // for explicit graph kernel nodes
+hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t st);
+const void* zero_u32_fn();
 hipError_t launch_init(uint32_t* state, const Item* items, int n_items, int L, int R,
                        uint64_t seed, hipStream_t st);
 // state: first row of the instance's first chain; spins: its first spin.

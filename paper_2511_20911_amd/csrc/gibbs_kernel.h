@@ -1,0 +1,549 @@
+// gibbs_kernel.h -- gfx950 device code for block Gibbs sampling of the CRBM
+// that encodes the classical Shastry-Sutherland Ising lattice
+// (Brahma et al., arXiv 2511.20911, Sec. II.A-II.B, App. A).
+//
+// Layout and mapping
+//   * A chain's spins are bit rows of W = ceil(L/32) words (bit c of word w =
+//     column 32w + c, 1 = up).
+//   * A chain is handled by G = (L/2)/R lanes of one wavefront; lane g owns the
+//     band of cell rows g*R .. g*R+R-1 (spin rows 2gR .. 2gR+2R-1) and keeps it
+//     in registers for the whole launch.  64/G chains share a wavefront; all
+//     chains of a wavefront belong to one instance, so the per-sweep weights
+//     and thresholds are wavefront-uniform.
+//   * Hidden units are never stored: a cell row's 10 hidden planes (one bit per
+//     cell, at the cell's even column) are drawn from the old spins and consumed
+//     at once by the visible update of the rows that need them.  The first row
+//     of a band also needs the last hidden row of the band above; it is updated
+//     last, after a lane shuffle (the periodic copy of App. A Zero Padder).
+//
+// Hidden half-step (Eq. (11)), bit-sliced: a bond "agrees" if s_a == sig s_b,
+// giving field 2 wq s_a, else field 0.  The unit takes the field's sign with
+// probability t(|x|)/2^32.  All agreeing J1 (resp. J2) bonds share one
+// threshold T1 (T2), disagreeing ones have 2^31, so the comparison U < t runs
+// over 32 packed units at a time: random words are consumed as bit planes of U,
+// most significant first, against the threshold's bits, until no unit of the
+// wavefront is still tied (usually 12-16 planes).
+//
+// Visible half-step (Eq. (12)): field = aq + wq1 (2n - 4) + wq2 (2d - 1) with n
+// the number of +1 J1 terms and d the dimer term; n is summed bit-sliced over a
+// row, the threshold is looked up per spin by (n, d) from a 10-entry table held
+// one entry per lane.  U = (P << 16) | Q with P, Q 16-bit Philox slots; Q is
+// drawn only when P equals the threshold's top half (probability 2^-16).
+#pragma once
+#include "crbm_internal.h"
+
+namespace crbmlib {
+namespace gk {
+
+constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;  // Philox round multipliers
+constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;  // Philox key increments
+
+struct P4 {
+    uint32_t v[4];
+};
+
+// a ^ b ^ k in one VALU op (gfx950 three-input bitwise op, xor3 truth table).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k) {
+    return __builtin_amdgcn_bitop3_b32(a, b, k, 0x96);
+}
+
+// Philox4x32-10 (Salmon et al., SC'11).  c1 and c3 enter as wavefront-uniform
+// words (sweep index, stream word); the key schedule is scalar.  Each round is
+// two 32x32->64 multiplies (v_mad_u64_u32) and two three-input xors.
+__device__ __forceinline__ P4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                     uint32_t k1) {
+    uint64_t p0 = (uint64_t)kM0 * c0;
+    uint64_t p1 = (uint64_t)kM1 * c2;
+    uint32_t x0 = (uint32_t)(p1 >> 32) ^ (c1 ^ k0);
+    uint32_t x2 = (uint32_t)(p0 >> 32) ^ (c3 ^ k1);
+    uint32_t x1 = (uint32_t)p1, x3 = (uint32_t)p0;
+#pragma unroll
+    for (int r = 1; r < 10; ++r) {
+        k0 += kW0;
+        k1 += kW1;
+        p0 = (uint64_t)kM0 * x0;
+        p1 = (uint64_t)kM1 * x2;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), x1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), x3, k1);
+        x1 = (uint32_t)p1;
+        x3 = (uint32_t)p0;
+        x0 = n0;
+        x2 = n2;
+    }
+    return P4{{x0, x1, x2, x3}};
+}
+
+__device__ __forceinline__ uint32_t slot16(const P4& p, int s) {
+    const uint32_t w = p.v[s >> 1];
+    return (s & 1) ? (w >> 16) : (w & 0xffffu);
+}
+
+template <int L>
+struct Geo {
+    static constexpr int W = (L + 31) / 32;   // words per row
+    static constexpr int C = L / 2;           // cells per cell row
+    static constexpr int ML = L - 32 * (W - 1);  // columns in the last word
+    __host__ __device__ static constexpr int m(int w) { return w == W - 1 ? ML : 32; }
+    __host__ __device__ static constexpr int n(int w) { return m(w) / 2; }
+    __host__ __device__ static constexpr uint32_t full(int w) {
+        return m(w) == 32 ? 0xffffffffu : ((1u << m(w)) - 1u);
+    }
+    __host__ __device__ static constexpr uint32_t even(int w) { return 0x55555555u & full(w); }
+};
+
+// bit c of word w <- column 32w + c + S (mod L), S in {1, 2}
+template <int L, int S>
+__device__ __forceinline__ uint32_t rsh(const uint32_t (&x)[Geo<L>::W], int w) {
+    using G = Geo<L>;
+    if (w < G::W - 1) return (x[w] >> S) | (x[w + 1] << (32 - S));
+    const uint32_t wrap = x[0] & ((1u << S) - 1u);
+    return ((x[w] >> S) | (wrap << (G::ML - S))) & G::full(G::W - 1);
+}
+
+// bit c of word w <- column 32w + c - 2 (mod L)
+template <int L>
+__device__ __forceinline__ uint32_t lsh2(const uint32_t (&x)[Geo<L>::W], int w) {
+    using G = Geo<L>;
+    if (w > 0) return ((x[w] << 2) | (x[w - 1] >> 30)) & G::full(w);
+    const uint32_t top = (x[G::W - 1] >> (G::ML - 2)) & 3u;
+    return ((x[0] << 2) | top) & G::full(0);
+}
+
+// Wavefront-uniform constants of one sweep, plus the per-lane visible table.
+struct SweepK {
+    uint32_t T[2];     // hidden agree thresholds (J1, J2), >= 2^31
+    uint32_t neg[2];   // all ones if sig_t < 0
+    uint32_t en[2];    // all ones if wq_t != 0
+    uint32_t kge[2];   // spin field >= 0 iff n >= kge[d]
+    uint32_t tabv;     // lane l < 10: min(tceil, 0xffff) | thi << 16 of visible entry l
+    uint32_t tfull;    // lane l < 10: full visible threshold of entry l
+};
+
+__device__ __forceinline__ SweepK load_sweep(const uint32_t* tb, int lane) {
+    SweepK K;
+    const uint32_t fl = tb[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        K.T[t] = tb[t];
+        K.neg[t] = (fl & (1u << t)) ? 0xffffffffu : 0u;
+        K.en[t] = (fl & (4u << t)) ? 0xffffffffu : 0u;
+        K.kge[t] = (fl >> (8 + 4 * t)) & 15u;
+    }
+    const uint32_t tv = tb[3 + (lane < 10 ? lane : 9)];
+    uint32_t tc = (tv >> 16) + ((tv & 0xffffu) != 0u);
+    tc = tc > 0xffffu ? 0xffffu : tc;
+    K.tfull = tv;
+    K.tabv = tc | (tv & 0xffff0000u);
+    return K;
+}
+
+template <int N>
+__device__ __forceinline__ uint32_t pick(const uint32_t (&a)[N], int k) {
+    uint32_t v = a[0];
+#pragma unroll
+    for (int x = 1; x < N; ++x) v = (k == x) ? a[x] : v;
+    return v;
+}
+template <int N>
+__device__ __forceinline__ void put(uint32_t (&a)[N], int k, uint32_t v) {
+#pragma unroll
+    for (int x = 0; x < N; ++x) a[x] = (k == x) ? v : a[x];
+}
+
+struct Rng {
+    uint32_t sweep, chain, k0, k1;
+};
+
+// Mask of bits [lo, hi) of a 32-bit word (0 <= lo <= hi <= 32).
+__host__ __device__ constexpr uint32_t bits_between(int lo, int hi) {
+    return (hi <= lo) ? 0u : ((hi - lo == 32) ? 0xffffffffu : (((1u << (hi - lo)) - 1u) << lo));
+}
+
+// Bit-sliced comparison U < T over 32 packed hidden units.  val: units that
+// exist; ag: agreeing units (threshold T1 or T2 by type); j2: units of dimer
+// type.  Returns the units with U >= threshold ("flip against the field").
+__device__ __forceinline__ uint32_t hidden_compare(uint32_t val, uint32_t ag, uint32_t j2, const SweepK& K,
+                                                   uint32_t cb, uint32_t c3, const Rng& rg) {
+    const uint32_t j1 = val & ~j2;
+    P4 p = philox(cb, rg.sweep, rg.chain, c3, rg.k0, rg.k1);
+    // plane 0: every threshold has its top bit set (T >= 2^31); disagreeing
+    // units (threshold exactly 2^31) are decided here
+    uint32_t lt = val & ~p.v[0];
+    uint32_t eq = ag & p.v[0];
+#pragma unroll
+    for (int b = 1; b < 4; ++b) {
+        const uint32_t t = (((K.T[0] >> (31 - b)) & 1u) ? j1 : 0u) | (((K.T[1] >> (31 - b)) & 1u) ? j2 : 0u);
+        lt |= eq & ~p.v[b] & t;
+        eq &= ~(p.v[b] ^ t);
+    }
+#pragma unroll 1
+    for (int c = 1; c < 8; ++c) {
+        if (!__any(eq != 0u)) break;
+        p = philox(cb | (uint32_t)c, rg.sweep, rg.chain, c3, rg.k0, rg.k1);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int b = 4 * c + s;
+            const uint32_t t = (((K.T[0] >> (31 - b)) & 1u) ? j1 : 0u) | (((K.T[1] >> (31 - b)) & 1u) ? j2 : 0u);
+            lt |= eq & ~p.v[s] & t;
+            eq &= ~(p.v[s] ^ t);
+        }
+    }
+    return val & ~lt;
+}
+
+// Hidden half-step of one cell row i: 10 hidden planes (bits at the cells' even
+// columns) from the old spin rows top = 2i, mid = 2i+1, bot = 2i+2.
+template <int L>
+__device__ __forceinline__ void hidden_row(const uint32_t (&top)[Geo<L>::W], const uint32_t (&mid)[Geo<L>::W],
+                                           const uint32_t (&bot)[Geo<L>::W], const SweepK& K, uint32_t i,
+                                           uint32_t c3, const Rng& rg, uint32_t (&H)[10][Geo<L>::W]) {
+    using G = Geo<L>;
+#pragma unroll
+    for (int w = 0; w < G::W; ++w) {
+        const int n = G::n(w);
+        const uint32_t E = G::even(w);
+        const uint32_t t1 = rsh<L, 1>(top, w), t2 = rsh<L, 2>(top, w);
+        const uint32_t m1 = rsh<L, 1>(mid, w), m2 = rsh<L, 2>(mid, w);
+        const uint32_t b1 = rsh<L, 1>(bot, w);
+        // endpoint a and endpoint b of each filter, aligned on the cell's even column
+        const uint32_t ea[10] = {top[w], t1, mid[w], m1, top[w], mid[w], t1, m1, top[w], m2};
+        const uint32_t eb[10] = {t1, t2, m1, m2, mid[w], bot[w], m1, b1, m1, b1};
+        uint32_t A[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            const int ty = k >= 8;
+            A[k] = ~(ea[k] ^ eb[k] ^ K.neg[ty]) & K.en[ty] & E;
+        }
+        // pack: unit u = 2n (k/2) + 2 jl + k%2 -> word u/32, bit u%32
+        constexpr int NPWMAX = 5;
+        uint32_t PA[NPWMAX] = {0u, 0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int p = 0; p < 5; ++p) {
+            const uint32_t pair = A[2 * p] | (A[2 * p + 1] << 1);
+            const int off = 2 * n * p;
+            PA[off >> 5] |= pair << (off & 31);
+            if ((off & 31) + 2 * n > 32) PA[(off >> 5) + 1] |= pair >> (32 - (off & 31));
+        }
+        const int NQ = 10 * n;
+        const int NPW = (NQ + 31) / 32;
+        uint32_t DP[NPWMAX] = {0u, 0u, 0u, 0u, 0u};
+        const uint32_t cbw = (uint32_t)(i * G::W + w) << 8;
+#pragma unroll
+        for (int pw = 0; pw < NPWMAX; ++pw) {
+            if (pw < NPW) {
+                const int lo = 32 * pw;
+                const uint32_t val = bits_between(0, (NQ - lo) < 32 ? (NQ - lo) : 32);
+                const int j2lo = 8 * n - lo;
+                const uint32_t j2 = bits_between(j2lo < 0 ? 0 : (j2lo > 32 ? 32 : j2lo), (NQ - lo) < 32 ? (NQ - lo) : 32);
+                DP[pw] = hidden_compare(val, PA[pw], j2, K, cbw | ((uint32_t)pw << 3), c3, rg);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < 5; ++p) {
+            const int off = 2 * n * p;
+            uint32_t pair = DP[off >> 5] >> (off & 31);
+            if ((off & 31) + 2 * n > 32) pair |= DP[(off >> 5) + 1] << (32 - (off & 31));
+            const uint32_t d0 = pair & E, d1 = (pair >> 1) & E;
+            // sign of the field: s_a for agreeing bonds, +1 for a zero field
+            H[2 * p][w] = (((ea[2 * p] & A[2 * p]) | ~A[2 * p]) & E) ^ d0;
+            H[2 * p + 1][w] = (((ea[2 * p + 1] & A[2 * p + 1]) | ~A[2 * p + 1]) & E) ^ d1;
+        }
+    }
+}
+
+// n >= k for a bit-sliced count n = n0 + 2 n1 + 4 n2 in 0..4 and uniform k.
+__device__ __forceinline__ uint32_t count_ge(uint32_t n0, uint32_t n1, uint32_t n2, uint32_t k) {
+    switch (k) {
+        case 0: return 0xffffffffu;
+        case 1: return n0 | n1 | n2;
+        case 2: return n1 | n2;
+        case 3: return n2 | (n1 & n0);
+        case 4: return n2;
+        default: return 0u;
+    }
+}
+
+// Visible half-step of the two rows of cell row i (Eq. (12)).  H: hidden
+// planes of this cell row; Hp5/Hp7/Hp9: planes 5, 7, 9 of the cell row above.
+// Classes: 0 top even, 1 top odd, 2 mid even, 3 mid odd columns.
+template <int L>
+__device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], const uint32_t (&Hp5)[Geo<L>::W],
+                                            const uint32_t (&Hp7)[Geo<L>::W], const uint32_t (&Hp9)[Geo<L>::W],
+                                            const SweepK& K, bool do_top, bool do_mid, uint32_t i, uint32_t c3p,
+                                            const Rng& rg, uint32_t (&ntop)[Geo<L>::W],
+                                            uint32_t (&nmid)[Geo<L>::W]) {
+    using G = Geo<L>;
+#pragma unroll
+    for (int w = 0; w < G::W; ++w) {
+        const int m = G::m(w);
+        const uint32_t E = G::even(w);
+        const uint32_t n1 = K.neg[0], n2 = K.neg[1];
+        const uint32_t h1l = lsh2<L>(H[1], w), h3l = lsh2<L>(H[3], w), h9l = lsh2<L>(H[9], w);
+        // the 4 J1 terms and the dimer term of every spin (1 = +1)
+        const uint32_t term[4][5] = {
+            {H[0][w], H[4][w], h1l ^ n1, Hp5[w] ^ n1, H[8][w]},           // (0,0): k0a k4a k1b(j-1) k5b(i-1) | k8a
+            {H[0][w] ^ n1, H[1][w], H[6][w], Hp7[w] ^ n1, Hp9[w] ^ n2},  // (0,1): k0b k1a k6a k7b(i-1) | k9b(i-1)
+            {H[2][w], H[4][w] ^ n1, H[5][w], h3l ^ n1, h9l},              // (1,0): k2a k4b k5a k3b(j-1) | k9a(j-1)
+            {H[2][w] ^ n1, H[3][w], H[6][w] ^ n1, H[7][w], H[8][w] ^ n2}, // (1,1): k2b k3a k6b k7a | k8b
+        };
+        uint32_t Pa[4], Pb[4], Sg[4], D[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t s1 = term[c][0] ^ term[c][1], c1 = term[c][0] & term[c][1];
+            const uint32_t s2 = term[c][2] ^ term[c][3], c2 = term[c][2] & term[c][3];
+            const uint32_t b0 = (s1 ^ s2) & E, cc = s1 & s2;
+            const uint32_t b1 = (c1 ^ c2 ^ cc) & E, b2 = (c1 & c2) & E;
+            const uint32_t dd = term[c][4] & E;
+            Pa[c] = dd | (b0 << 1);
+            Pb[c] = b1 | (b2 << 1);
+            Sg[c] = ((dd & count_ge(b0, b1, b2, K.kge[1])) | (~dd & count_ge(b0, b1, b2, K.kge[0]))) & E;
+            D[c] = 0u;
+        }
+        const int NQ = 2 * m;
+        const int NB = (NQ + 7) / 8;
+        const uint32_t cbase = (uint32_t)(i * G::W + w) << 5;
+        uint32_t tieblk = 0u;
+#pragma unroll
+        for (int blk = 0; blk < 8; ++blk) {
+            if (blk >= NB) continue;
+            const bool has_top = blk * 8 < m, has_mid = blk * 8 + 7 >= m;
+            if (!((do_top && has_top) || (do_mid && has_mid))) continue;
+            const P4 p = philox(cbase | (uint32_t)blk, rg.sweep, rg.chain, c3p, rg.k0, rg.k1);
+            uint64_t tie = 0;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int q = blk * 8 + s;
+                if (q < NQ) {
+                    const int row = q / m, col = q % m, cls = 2 * row + (col & 1), pos = col & ~1;
+                    const uint32_t p16 = slot16(p, s);
+                    const uint32_t idx = ((Pa[cls] >> pos) & 3u) | (((Pb[cls] >> pos) & 3u) << 2);
+                    const uint32_t e = __shfl(K.tabv, (int)idx);
+                    D[cls] |= (uint32_t)(p16 >= (e & 0xffffu)) << pos;
+                    tie |= __ballot(p16 == (e >> 16));
+                }
+            }
+            if (tie) tieblk |= 1u << blk;
+        }
+        // Rare path: a primary slot equal to the threshold's top half; redo the
+        // affected blocks with the refinement stream and exact 32-bit compares.
+        while (tieblk) {
+            const int blk = __builtin_ctz(tieblk);
+            tieblk &= tieblk - 1u;
+            const P4 p = philox(cbase | (uint32_t)blk, rg.sweep, rg.chain, c3p, rg.k0, rg.k1);
+            const P4 r = philox(cbase | (uint32_t)blk, rg.sweep, rg.chain, c3p + 1u, rg.k0, rg.k1);
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int q = blk * 8 + s;
+                if (q < NQ) {
+                    const int row = q / m, col = q % m, cls = 2 * row + (col & 1), pos = col & ~1;
+                    const uint32_t U = (slot16(p, s) << 16) | slot16(r, s);
+                    const uint32_t idx = ((pick(Pa, cls) >> pos) & 3u) | (((pick(Pb, cls) >> pos) & 3u) << 2);
+                    const uint32_t t = __shfl(K.tfull, (int)idx);
+                    const uint32_t d = U >= t;
+                    put(D, cls, (pick(D, cls) & ~(1u << pos)) | (d << pos));
+                }
+            }
+        }
+        ntop[w] = (Sg[0] ^ D[0]) | ((Sg[1] ^ D[1]) << 1);
+        nmid[w] = (Sg[2] ^ D[2]) | ((Sg[3] ^ D[3]) << 1);
+    }
+}
+
+// One work item: up to 64/G chains of one instance, all sweeps [s0, s1).
+template <int L, int R>
+__device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, int lane) {
+    using Gm = Geo<L>;
+    constexpr int W = Gm::W;
+    constexpr int C = L / 2;
+    constexpr int G = C / R;
+    constexpr int NR = 2 * R;
+    constexpr int N = L * L;
+    static_assert(C % R == 0, "R must divide L/2");
+    static_assert(G <= 64, "a chain must fit in one wavefront");
+
+    const int cl = lane / G, g = lane - cl * G;
+    const bool active = cl < (int)it.nchains;
+    const uint32_t chain = it.chain0 + (active ? (uint32_t)cl : 0u);
+    const uint64_t gch = it.gbase + (active ? (uint64_t)cl : 0u);
+    const int nxt = cl * G + (g + 1 == G ? 0 : g + 1);
+    const int prv = cl * G + (g == 0 ? G - 1 : g - 1);
+
+    uint32_t Q[NR + 1][W];
+    {
+        const uint32_t* st = a.state + it.state_off + ((uint64_t)(active ? cl : 0) * L + (uint64_t)g * NR) * W;
+#pragma unroll
+        for (int x = 0; x < NR; ++x)
+#pragma unroll
+            for (int w = 0; w < W; ++w) Q[x][w] = st[x * W + w];
+#pragma unroll
+        for (int w = 0; w < W; ++w) Q[NR][w] = 0u;
+    }
+    const uint32_t c3h = (it.id << 3) | 1u, c3v = (it.id << 3) | 3u;
+    int64_t acc[11];
+#pragma unroll
+    for (int x = 0; x < 11; ++x) acc[x] = 0;
+
+    for (int64_t s = a.s0; s < a.s1; ++s) {
+        const uint32_t* tb = a.tables + it.tab_off + (uint64_t)it.tab_stride * (uint64_t)s;
+        const SweepK K = load_sweep(tb, lane);
+        const Rng rg{(uint32_t)s, chain, (uint32_t)a.seed, (uint32_t)(a.seed >> 32)};
+#pragma unroll
+        for (int w = 0; w < W; ++w) Q[NR][w] = __shfl(Q[0][w], nxt);  // old first row of the next band
+        uint32_t Hf0[W], Hf1[W], Hf4[W], Hf6[W], Hf8[W], Hp5[W], Hp7[W], Hp9[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            Hf0[w] = Hf1[w] = Hf4[w] = Hf6[w] = Hf8[w] = 0u;
+            Hp5[w] = Hp7[w] = Hp9[w] = 0u;
+        }
+#pragma unroll 1
+        for (int m = 0; m < R; ++m) {
+            const uint32_t i = (uint32_t)(g * R + m);
+            uint32_t H[10][W];
+            hidden_row<L>(Q[0], Q[1], Q[2], K, i, c3h, rg, H);
+            uint32_t nt[W], nm[W];
+            visible_row<L>(H, Hp5, Hp7, Hp9, K, m > 0, true, i, c3v, rg, nt, nm);
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const uint32_t old_top = Q[0][w];
+#pragma unroll
+                for (int x = 0; x + 2 <= NR; ++x) Q[x][w] = Q[x + 2][w];
+                Q[NR - 1][w] = (m == 0) ? old_top : nt[w];
+                Q[NR][w] = nm[w];
+                if (m == 0) {
+                    Hf0[w] = H[0][w]; Hf1[w] = H[1][w]; Hf4[w] = H[4][w]; Hf6[w] = H[6][w]; Hf8[w] = H[8][w];
+                }
+                Hp5[w] = H[5][w]; Hp7[w] = H[7][w]; Hp9[w] = H[9][w];
+            }
+        }
+        // first row of the band: needs the last hidden row of the band above
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            Hp5[w] = __shfl(Hp5[w], prv);
+            Hp7[w] = __shfl(Hp7[w], prv);
+            Hp9[w] = __shfl(Hp9[w], prv);
+        }
+        {
+            uint32_t Hd[10][W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                Hd[0][w] = Hf0[w]; Hd[1][w] = Hf1[w]; Hd[4][w] = Hf4[w]; Hd[6][w] = Hf6[w]; Hd[8][w] = Hf8[w];
+                Hd[2][w] = Hd[3][w] = Hd[5][w] = Hd[7][w] = Hd[9][w] = 0u;
+            }
+            uint32_t nt[W], nm[W];
+            visible_row<L>(Hd, Hp5, Hp7, Hp9, K, true, false, (uint32_t)(g * R), c3v, rg, nt, nm);
+#pragma unroll
+            for (int w = 0; w < W; ++w) Q[1][w] = nt[w];
+        }
+#pragma unroll
+        for (int x = 0; x < NR; ++x)
+#pragma unroll
+            for (int w = 0; w < W; ++w) Q[x][w] = Q[x + 1][w];
+
+        const bool meas = a.measure_every > 0 && s >= a.burn_in && ((s - a.burn_in) % a.measure_every) == 0;
+        if (meas || a.trace) {
+            uint32_t nb[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) nb[w] = __shfl(Q[0][w], nxt);  // new first row of the next band
+            int pop = 0, dis1 = 0, dis2 = 0;
+#pragma unroll
+            for (int x = 0; x < NR; ++x)
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    const uint32_t below = (x + 1 < NR) ? Q[x + 1][w] : nb[w];
+                    pop += __popc(Q[x][w]);
+                    dis1 += __popc(Q[x][w] ^ rsh<L, 1>(Q[x], w)) + __popc(Q[x][w] ^ below);
+                }
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const uint32_t(&tp)[W] = Q[2 * m];
+                const uint32_t(&md)[W] = Q[2 * m + 1];
+                const uint32_t(&bt)[W] = (2 * m + 2 < NR) ? Q[2 * m + 2] : nb;
+#pragma unroll
+                for (int w = 0; w < W; ++w)
+                    dis2 += __popc((tp[w] ^ rsh<L, 1>(md, w)) & Gm::even(w)) +
+                            __popc((rsh<L, 2>(md, w) ^ rsh<L, 1>(bt, w)) & Gm::even(w));
+            }
+            int tp = pop, t1 = dis1, t2 = dis2;
+#pragma unroll
+            for (int d = 1; d < G; ++d) {
+                const int src = cl * G + (g + d) % G;
+                tp += __shfl(pop, src);
+                t1 += __shfl(dis1, src);
+                t2 += __shfl(dis2, src);
+            }
+            const int64_t M = 2 * tp - N, B1 = 2 * N - 2 * t1, B2 = N / 2 - 2 * t2;
+            if (a.trace && g == 0 && active) {
+                int32_t* tr = a.trace + ((uint64_t)(s - a.s0) * (uint64_t)a.total_chains + gch) * 3;
+                tr[0] = (int32_t)M;
+                tr[1] = (int32_t)B1;
+                tr[2] = (int32_t)B2;
+            }
+            if (meas) {
+                acc[0] += 1;
+                acc[1] += M; acc[2] += B1; acc[3] += B2;
+                acc[4] += M * M; acc[5] += B1 * B1; acc[6] += B2 * B2;
+                acc[7] += M * B1; acc[8] += M * B2; acc[9] += B1 * B2;
+                acc[10] += M < 0 ? -M : M;
+            }
+        }
+    }
+    if (!active) return;  // returns from this item only
+    {
+        uint32_t* st = a.state + it.state_off + ((uint64_t)cl * L + (uint64_t)g * NR) * W;
+#pragma unroll
+        for (int x = 0; x < NR; ++x)
+#pragma unroll
+            for (int w = 0; w < W; ++w) st[x * W + w] = Q[x][w];
+    }
+    if (g == 0 && a.measure_every > 0) {
+        int64_t* ac = a.acc + gch * 11;
+#pragma unroll
+        for (int x = 0; x < 11; ++x) ac[x] += acc[x];
+    }
+    if (a.spins_out) {
+        int8_t* out = a.spins_out + it.spin_off + ((uint64_t)cl * L + (uint64_t)g * NR) * L;
+        for (int x = 0; x < NR; ++x)
+            for (int c = 0; c < L; ++c) out[x * L + c] = ((Q[x][c >> 5] >> (c & 31)) & 1u) ? 1 : -1;
+    }
+}
+
+// Direct mode: wavefront w of the grid takes item w.  Persistent mode
+// (a.queue != nullptr): each wavefront pops items from a device counter until
+// the list is exhausted, so a grid sized to the machine drains any number of
+// items and concurrent kernels share the CUs as their queues empty.
+template <int L, int R>
+__global__ void __launch_bounds__(256) gibbs_kernel(GibbsArgs a) {
+    const int lane = threadIdx.x & 63;
+    if (a.queue == nullptr) {
+        const int wv = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+        if (wv >= a.n_items) return;
+        gibbs_item<L, R>(a, a.items[wv], lane);
+        return;
+    }
+    for (;;) {
+        uint32_t next = 0u;
+        if (lane == 0) next = atomicAdd(a.queue, 1u);
+        next = __builtin_amdgcn_readfirstlane(next);
+        if (next >= (uint32_t)a.n_items) return;
+        gibbs_item<L, R>(a, a.items[next], lane);
+    }
+}
+
+template <int L, int R>
+hipError_t launch_tile(const GibbsArgs& a, hipStream_t st) {
+    const int wpb = a.waves_per_block > 0 ? a.waves_per_block : 4;
+    int blocks = (a.n_items + wpb - 1) / wpb;
+    if (a.queue != nullptr && a.grid_blocks > 0 && a.grid_blocks < blocks) blocks = a.grid_blocks;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((gibbs_kernel<L, R>), dim3(blocks), dim3(64 * wpb), 0, st, a);
+    return hipGetLastError();
+}
+
+// Kernel function pointer and block size, for explicit graph nodes.
+template <int L, int R>
+const void* kernel_ptr() {
+    return reinterpret_cast<const void*>(&gibbs_kernel<L, R>);
+}
+
+}  // namespace gk
+}  // namespace crbmlib

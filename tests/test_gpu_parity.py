@@ -161,7 +161,8 @@ def test_invalid_arguments_fail_cleanly():
         (crbm.Instance(L=7, n_chains=1), crbm.CRBM_EINVAL),
         (crbm.Instance(L=6, n_chains=0), crbm.CRBM_EINVAL),
         (crbm.Instance(L=6, n_chains=1, T0=-1.0), crbm.CRBM_EINVAL),
-        (crbm.Instance(L=64, n_chains=1), crbm.CRBM_EUNSUPPORTED),
+        (crbm.Instance(L=34, n_chains=1), crbm.CRBM_EUNSUPPORTED),
+        (crbm.Instance(L=98, n_chains=1), crbm.CRBM_EUNSUPPORTED),
         (crbm.Instance(L=6, n_chains=1, periodic=0), crbm.CRBM_EUNSUPPORTED),
         (crbm.Instance(L=6, n_chains=1, T0=1e-7), crbm.CRBM_ERANGE),
     ]
@@ -169,3 +170,99 @@ def test_invalid_arguments_fail_cleanly():
         with pytest.raises(crbm.CrbmError) as e:
             crbm.Sampler([I], seed=1, n_sweeps=10)
         assert e.value.code == code, I
+
+
+@pytest.mark.parametrize("tile_rows", [0, 1])
+def test_multiword_lattices_bit_exact(tile_rows):
+    """Rows wider than one 32-bit word (partial last word at L = 36, 40, 48, 72;
+    full words at L = 64, 96): sampled chains equal the oracle."""
+    seed = 0x5EED000000000005
+    S = 40
+    insts = [
+        crbm.Instance(L=36, J1=1.0, J2=1.0, h=3.0, n_chains=11, sched="const", T0=0.9, id=21),
+        crbm.Instance(L=40, J1=1.0, J2=2.5, h=0.5, n_chains=7, sched="linear", T0=3.0, T1=0.5, id=22),
+        crbm.Instance(L=48, J1=1.0, J2=1.5, h=4.5, n_chains=9, sched="geometric", T0=5.0, T1=0.2, id=23),
+        crbm.Instance(L=64, J1=1.0, J2=0.5, h=0.0, n_chains=3, sched="const", T0=1.2, id=24),
+        crbm.Instance(L=72, J1=-1.0, J2=1.0, h=1.0, n_chains=5, sched="const", T0=2.0, id=25),
+        crbm.Instance(L=96, J1=1.0, J2=1.0, h=2.0, n_chains=6, sched="linear", T0=4.0, T1=0.4, id=26),
+    ]
+    smp, parts, tr = _run_gpu(insts, seed, S, tile_rows=0 if tile_rows == 0 else 1)
+    off = smp.chain_offsets
+    for k, I in enumerate(insts):
+        _check_chains(I, parts[k], tr, int(off[k]), seed, S, sorted({0, I.n_chains - 1}))
+
+
+def test_multiword_observables_and_corr():
+    seed = 3
+    S = 30
+    I = crbm.Instance(L=48, J1=1.0, J2=1.0, h=3.0, n_chains=4, sched="const", T0=0.7, id=31)
+    smp = crbm.Sampler([I], seed=seed, n_sweeps=S, measure_every=2, burn_in=5)
+    smp.sample(S)
+    obs, corr = smp.observables(corr=True)
+    acc = np.zeros(oracle.N_ACC, np.int64)
+    csum = np.zeros((48, 48), np.int64)
+    for ch in range(4):
+        s, _, a = oracle.run_chain(_oi(I), S, seed, ch, 0, S, measure_every=2, burn_in=5)
+        acc += a
+        csum += oracle.corr(48, s)
+    assert obs[0]["n_samples"] == acc[0] and obs[0]["sum_B1"] == acc[2] and obs[0]["sum_MM"] == acc[4]
+    assert np.array_equal(corr[0], csum)
+
+
+def _to_inst(p):
+    return crbm.Instance(L=p.L, J1=p.J1, J2=p.J2, h=p.h, n_chains=p.n_chains, sched=p.sched, T0=p.T0, T1=p.T1,
+                         id=p.id)
+
+
+def test_graph_launch_equals_direct_and_replays():
+    """One hipGraph launch (persistent kernels per lattice size) gives exactly
+    the direct launches' result; replayed several times with eager work in
+    between, every replay matches."""
+    from paper_2511_20911_amd import workloads
+    pts = workloads.batched_uneven(n_instances=24, chains=70)
+    insts = [_to_inst(p) for p in pts]
+    seed = 0x5EED000000000003
+    S = 60
+    d = crbm.Sampler(insts, seed=seed, n_sweeps=S, measure_every=1)
+    g = crbm.Sampler(insts, seed=seed, n_sweeps=S, measure_every=1, launch="graph")
+    for rep in range(4):
+        n = 15
+        sd = torch.empty(d.total_spins, dtype=torch.int8, device="cuda")
+        sg = torch.empty(g.total_spins, dtype=torch.int8, device="cuda")
+        td = torch.empty((n, d.total_chains, 3), dtype=torch.int32, device="cuda")
+        tg = torch.empty((n, g.total_chains, 3), dtype=torch.int32, device="cuda")
+        d.sample(n, spins_out=sd, trace=td)
+        g.sample(n, spins_out=sg, trace=tg)
+        torch.cuda.synchronize()
+        _ = g.get_state()  # eager work between replays
+        assert torch.equal(sd, sg), rep
+        assert torch.equal(td, tg), rep
+    assert d.observables() == g.observables()
+
+
+def test_batched_uneven_full_size_graph():
+    """The full uneven batch (2048 instances, L in {6..48}, 256 chains each,
+    5000 sweeps at fixed T) in one graph launch; chains sampled from the small
+    lattices equal the oracle."""
+    from paper_2511_20911_amd import workloads
+    pts = workloads.batched_uneven()
+    insts = [_to_inst(p) for p in pts]
+    seed = 0x5EED000000000003
+    S = 5000
+    smp = crbm.Sampler(insts, seed=seed, n_sweeps=S, launch="graph")
+    out = torch.empty(smp.total_spins, dtype=torch.int8, device="cuda")
+    smp.sample(S, spins_out=out)
+    torch.cuda.synchronize()
+    parts = smp.split_spins(out)
+    picked = [k for k, p in enumerate(pts) if p.L <= 12][:3] + [k for k, p in enumerate(pts) if p.L == 18][:1]
+    for k in picked:
+        I = insts[k]
+        for ch in (0, I.n_chains - 1):
+            s, _, _ = oracle.run_chain(_oi(I), S, seed, ch, 0, S)
+            assert np.array_equal(parts[k][ch].cpu().numpy(), s), (k, ch)
+
+
+def test_autotune_picks_a_valid_tiling():
+    r, w, rate = crbm.autotune(18, n_chains=1024, n_sweeps=20)
+    assert 9 % r == 0 and 1 <= w <= 4 and rate > 0
+    assert crbm.get_tiling(18) == (r, w)
