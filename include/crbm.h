@@ -157,6 +157,78 @@ int crbm_autotune(int32_t L, int32_t n_chains, int32_t n_sweeps, void* stream, i
 int crbm_set_tiling(int32_t L, int32_t rows, int32_t waves_per_block);
 int crbm_get_tiling(int32_t L, int32_t* rows, int32_t* waves_per_block);
 
+/* Integrated autocorrelation time and effective sample size of the
+ * observable O = w[0] M + w[1] B1 + w[2] B2 (e.g. the energy with
+ * w = (-hq, J1q, J2q)) over a counts trace written by crbm_sample
+ * (trace_dev: device, int32 [n_samples][trace_chains][3]), for chains
+ * [c0, c1), after dropping the first `discard` samples.  With per-chain means
+ * removed, Gamma(k) = sum over chains and t of x_t x_{t+k} / ((n - k) n_chains),
+ * rho(k) = Gamma(k)/Gamma(0), tau_int = 1 + 2 sum_{k=1}^{W} rho(k) with the
+ * automatic window W = min{W : W >= c_window tau_int(W)} (Sokal), and
+ * ESS = n_chains (n_samples - discard) / tau_int.  rho_out (host, may be NULL)
+ * receives rho(0..min(max_lag, n-discard-1)).  Synchronises `stream`. */
+int crbm_tau_int(const int32_t* trace_dev, int64_t n_samples, int64_t trace_chains, int64_t c0, int64_t c1,
+                 int64_t discard, const double w[3], int32_t max_lag, double c_window, void* stream,
+                 double* tau_out, double* ess_out, int32_t* window_out, double* rho_out);
+
+/* ---------------------------------------------------------------------------
+ * Learned proposal (an addition to the paper's Gibbs sampler): a masked-
+ * convolution autoregressive network q(s) over the spins in raster order
+ * (12 layers of 3x3 masked convolutions, 32 channels, bf16 weights and
+ * activations on the matrix cores, fp32 accumulation), used as an independent
+ * Metropolis-Hastings proposal.  Acceptance uses the exact integer counts of
+ * the current and proposed states under the CRBM marginal the Gibbs chain
+ * samples, log pi = a M + c1 n1 + c2 n2 + const (c_t = log cosh(2 w_t), n_t =
+ * number of type-t bonds whose hidden unit "agrees", Sec. II.A Eq. (4) with the
+ * hidden units summed out), so interleaving keeps the stationary law.
+ *
+ * Parameter layout (fp32, host arrays of crbm_ar_num_params() values): for
+ * layers l = 0..11: weights [taps][cin][cout] then bias [cout], with 4 taps
+ * (mask A: offsets (-1,-1) (-1,0) (-1,1) (0,-1)) for l = 0 and 5 taps (plus
+ * (0,0)) otherwise; cin = 1 for l = 0 else 32; cout = 1 for l = 11 else 32.
+ * All device pointers are caller-owned.  Calls are asynchronous on the
+ * network's stream unless they return host data.
+ * ------------------------------------------------------------------------- */
+typedef struct crbm_ar_s crbm_ar_t;
+typedef struct {
+    int32_t L;          /* lattice side */
+    int32_t channels;   /* must be 32 */
+    int32_t layers;     /* must be 12 */
+    uint64_t seed;      /* random stream of the sequential scorer (unused by training) */
+    void* stream;       /* hipStream_t */
+} crbm_ar_config;
+
+int crbm_ar_create(const crbm_ar_config* c, crbm_ar_t** out);   /* parameters start at zero */
+int64_t crbm_ar_num_params(const crbm_ar_t* a);
+int crbm_ar_set_params(crbm_ar_t* a, const float* host, int64_t n); /* also resets the Adam state */
+int crbm_ar_get_params(crbm_ar_t* a, float* host, int64_t n);
+/* Gradient of the mean negative log-likelihood over a batch of samples
+ * (device int8 +-1 [batch][L][L]); grad_host (may be NULL) receives it in the
+ * parameter layout, loss_out (may be NULL) the loss.  Synchronises. */
+int crbm_ar_grad(crbm_ar_t* a, const int8_t* samples_dev, int64_t batch, float* grad_host, double* loss_out);
+/* One Adam step (beta = 0.9, 0.999, eps = 1e-8) at learning rate lr on a batch. */
+int crbm_ar_train_step(crbm_ar_t* a, const int8_t* samples_dev, int64_t batch, float lr, double* loss_out);
+/* log q of n configurations (device int8 [n][L][L]) into logq_dev (device fp64 [n])
+ * by one forward pass over all sites.  The per-site arithmetic, and the fp64 sum
+ * over sites in raster order, are those of crbm_ar_sample, so a proposal scored
+ * here gets the log q its sampler returned, bit for bit.  Asynchronous. */
+int crbm_ar_logq(crbm_ar_t* a, const int8_t* spins_dev, int64_t n, double* logq_dev);
+/* n independent proposals (ancestral sampling: spin i = +1 iff u < sigmoid(logit_i),
+ * u = 24-bit uniform from Philox (ctr = (site, step, chain, id << 3 | 6), key = seed))
+ * into spins_dev (int8 [n][L][L]) with their log q into logq_dev (fp64 [n]). */
+int crbm_ar_sample(crbm_ar_t* a, int64_t n, uint64_t seed, int64_t step, uint32_t id, int8_t* spins_dev,
+                   double* logq_dev);
+/* n_cycles of: gibbs_per_mh Gibbs sweeps of h (crbm_sample), then one
+ * independent MH step per chain with a's proposals; h must hold one instance
+ * with a constant temperature and the same L, on the same stream.  Cycle k of
+ * the network's life draws its proposals with step = k and its MH uniform from
+ * Philox (ctr = (0, k, chain, id << 3 | 5)).  counts_trace
+ * (device, may be NULL): int32 (M, B1, B2) after each cycle, [n_cycles][chains][3].
+ * n_accepted (host, may be NULL): accepted moves (synchronises). */
+int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_mh, int32_t* counts_trace,
+                   int64_t* n_accepted);
+void crbm_ar_destroy(crbm_ar_t* a);
+
 /* Free everything the handle owns.  NULL is allowed. */
 void crbm_destroy(crbm_t* h);
 

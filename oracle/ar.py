@@ -1,0 +1,177 @@
+"""Oracle for the learned proposal (test infrastructure only).
+
+A PixelCNN-style masked-convolution autoregressive network over the spins in
+raster order, the independent Metropolis-Hastings step that uses it, and the
+target distribution both samplers share.  Plain numpy, fp64 arithmetic; the
+operands are rounded to bfloat16 at exactly the points where the HIP kernels
+round them (matrix-core inputs and stored activations), so kernel and oracle
+differ only by fp32 summation order.  Nothing here is shared with the library.
+
+Network (channels C, 12 layers, 3x3 masked kernels, zero padding):
+  h0 = sigma (+-1)
+  z1 = convA(h0) + b1,           h1 = bf16(relu(z1))
+  zl = convB(h_{l-1}) + bl,      hl = bf16(h_{l-1} + relu(zl))     l = 2..11
+  logit = convB(h11) + b12
+  log q(sigma) = sum_i log sigmoid(sigma_i logit_i)
+Mask A taps (dr, dc): (-1,-1) (-1,0) (-1,1) (0,-1) (sites strictly before the
+current one in raster order); mask B adds the centre (0,0).  The logit at a
+site therefore depends only on earlier sites.
+
+Target of the Gibbs chain (the CRBM marginal with the fixed-point weights):
+  log pi(v) = a' M + sum_t c_t n_t(v) + const,  c_t = log cosh(2 w'_t),
+n_t = number of type-t bonds with s_a = sig_t s_b, w' = wq / 2^16,
+a' = aq / 2^16 (Sec. II.A Eq. (4) with the hidden units summed out).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+TAPS_A = [(-1, -1), (-1, 0), (-1, 1), (0, -1)]
+TAPS_B = TAPS_A + [(0, 0)]
+N_LAYERS = 12
+
+
+def bf16(x):
+    """Round to the nearest bfloat16 (ties to even) via float32, as the kernels do."""
+    a = np.ascontiguousarray(np.asarray(x, np.float32))
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return (u.astype(np.uint32)).view(np.float32).astype(np.float64)
+
+
+def init_params(C=32, seed=0, scale=1.0):
+    """Seeded initial parameters (fan-in scaled normal weights, zero biases)."""
+    rng = np.random.default_rng(seed)
+    P = []
+    for l in range(N_LAYERS):
+        taps = TAPS_A if l == 0 else TAPS_B
+        cin = 1 if l == 0 else C
+        cout = 1 if l == N_LAYERS - 1 else C
+        std = scale * math.sqrt(2.0 / (len(taps) * cin)) * (0.1 if l == N_LAYERS - 1 else 1.0)
+        W = rng.standard_normal((len(taps), cin, cout)) * std
+        b = np.zeros(cout)
+        P.append((W, b))
+    return P
+
+
+def _conv(x, W, taps):
+    """x [B, L, L, Cin], W [T, Cin, Cout] -> [B, L, L, Cout], zero padding."""
+    B, L, _, _ = x.shape
+    out = np.zeros((B, L, L, W.shape[2]))
+    for t, (dr, dc) in enumerate(taps):
+        sh = np.zeros_like(x)
+        r0, r1 = max(0, -dr), min(L, L - dr)
+        c0, c1 = max(0, -dc), min(L, L - dc)
+        sh[:, r0:r1, c0:c1, :] = x[:, r0 + dr:r1 + dr, c0 + dc:c1 + dc, :]
+        out += sh @ W[t]
+    return out
+
+
+def _conv_t(g, W, taps):
+    """Adjoint of _conv with respect to its input."""
+    B, L, _, _ = g.shape
+    out = np.zeros((B, L, L, W.shape[1]))
+    for t, (dr, dc) in enumerate(taps):
+        contrib = g @ W[t].T  # [B, L, L, Cin] at the output pixel
+        r0, r1 = max(0, -dr), min(L, L - dr)
+        c0, c1 = max(0, -dc), min(L, L - dc)
+        out[:, r0 + dr:r1 + dr, c0 + dc:c1 + dc, :] += contrib[:, r0:r1, c0:c1, :]
+    return out
+
+
+def _conv_w(x, g, taps):
+    """Gradient of sum(g * conv(x, W)) with respect to W: [T, Cin, Cout]."""
+    B, L, _, Cin = x.shape
+    Cout = g.shape[3]
+    dW = np.zeros((len(taps), Cin, Cout))
+    for t, (dr, dc) in enumerate(taps):
+        sh = np.zeros_like(x)
+        r0, r1 = max(0, -dr), min(L, L - dr)
+        c0, c1 = max(0, -dc), min(L, L - dc)
+        sh[:, r0:r1, c0:c1, :] = x[:, r0 + dr:r1 + dr, c0 + dc:c1 + dc, :]
+        dW[t] = sh.reshape(-1, Cin).T @ g.reshape(-1, Cout)
+    return dW
+
+
+def forward(params, spins, emulate_bf16=True):
+    """spins [B, L, L] of +-1 -> (log q [B], cache for backward)."""
+    rb = bf16 if emulate_bf16 else (lambda v: np.asarray(v, np.float64))
+    s = np.asarray(spins, np.float64)
+    h = s[..., None]
+    hs, zs = [h], []
+    for l in range(N_LAYERS):
+        W, b = params[l]
+        taps = TAPS_A if l == 0 else TAPS_B
+        z = _conv(h, rb(W), taps) + b
+        zs.append(z)
+        if l == N_LAYERS - 1:
+            logit = z[..., 0]
+        elif l == 0:
+            h = rb(np.maximum(z, 0.0))
+        else:
+            h = rb(h + np.maximum(z, 0.0))
+        if l < N_LAYERS - 1:
+            hs.append(h)
+    x = s * logit
+    logq = -np.logaddexp(0.0, -x).sum(axis=(1, 2))
+    return logq, {"hs": hs, "zs": zs, "logit": logit, "spins": s, "rb": rb}
+
+
+def loss_and_grad(params, spins, emulate_bf16=True):
+    """Mean negative log-likelihood over the batch and its gradient
+    (hand-derived backward, straight through the bf16 roundings)."""
+    logq, c = forward(params, spins, emulate_bf16)
+    rb = c["rb"]
+    B = spins.shape[0]
+    s, logit = c["spins"], c["logit"]
+    # d(-log sigmoid(s l))/dl = -s (1 - sigmoid(s l))
+    g = -s * (1.0 / (1.0 + np.exp(s * logit))) / B
+    grads = [None] * N_LAYERS
+    dz = g[..., None]
+    for l in range(N_LAYERS - 1, -1, -1):
+        W, b = params[l]
+        taps = TAPS_A if l == 0 else TAPS_B
+        hin = c["hs"][l]
+        dzb = rb(dz)
+        grads[l] = (_conv_w(hin, dzb, taps), dz.sum(axis=(0, 1, 2)))
+        if l == 0:
+            break
+        dh_in = _conv_t(dzb, rb(W), taps)
+        if l < N_LAYERS - 1 and l > 0:
+            dh_in = dh_in + dh  # residual path of layer l (l >= 1, not the output layer)
+        dh = dh_in
+        zprev = c["zs"][l - 1]
+        dz = dh * (zprev > 0)
+    return -logq.mean(), grads
+
+
+def sample(params, n, L, uniforms, emulate_bf16=True):
+    """Ancestral sampling in raster order; uniforms [n, L*L] in [0, 1):
+    sigma_i = +1 iff u_i < sigmoid(logit_i).  Returns spins and log q."""
+    s = np.zeros((n, L, L))
+    for i in range(L * L):
+        r, c = divmod(i, L)
+        logq, cache = forward(params, s, emulate_bf16)
+        p = 1.0 / (1.0 + np.exp(-cache["logit"][:, r, c]))
+        s[:, r, c] = np.where(uniforms[:, i] < p, 1.0, -1.0)
+    logq, _ = forward(params, s, emulate_bf16)
+    return s.astype(np.int8), logq
+
+
+def log_target(counts, wq1, sg1, wq2, sg2, aq, L):
+    """log pi (up to a constant) from integer counts (M, B1, B2)."""
+    M, B1, B2 = (np.asarray(x, np.int64) for x in counts)
+    N = L * L
+    n1 = (2 * N - B1) // 2 if sg1 < 0 else (2 * N + B1) // 2
+    n2 = (N // 2 - B2) // 2 if sg2 < 0 else (N // 2 + B2) // 2
+    c1 = math.log(math.cosh(2.0 * wq1 / 65536.0))
+    c2 = math.log(math.cosh(2.0 * wq2 / 65536.0))
+    return aq / 65536.0 * M + c1 * n1 + c2 * n2
+
+
+def mh_accept(logpi_cur, logq_cur, logpi_prop, logq_prop, u):
+    """Independent MH: accept iff log u < [log pi' - log pi] + [log q - log q']."""
+    log_alpha = (logpi_prop - logpi_cur) + (logq_cur - logq_prop)
+    return np.log(u) < log_alpha

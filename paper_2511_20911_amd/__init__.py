@@ -65,6 +65,11 @@ class _Obs(ct.Structure):
     ]
 
 
+class _ARConfig(ct.Structure):
+    _fields_ = [("L", ct.c_int32), ("channels", ct.c_int32), ("layers", ct.c_int32), ("seed", ct.c_uint64),
+                ("stream", ct.c_void_p)]
+
+
 _lib = None
 
 
@@ -94,6 +99,22 @@ def lib() -> ct.CDLL:
         L.crbm_autotune.argtypes = [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p, p(ct.c_int32), p(ct.c_int32),
                                     p(ct.c_double)]
         L.crbm_set_tiling.argtypes = [ct.c_int32, ct.c_int32, ct.c_int32]
+        L.crbm_ar_create.argtypes = [p(_ARConfig), p(ct.c_void_p)]
+        L.crbm_ar_num_params.argtypes = [ct.c_void_p]
+        L.crbm_ar_num_params.restype = ct.c_int64
+        L.crbm_ar_set_params.argtypes = [ct.c_void_p, p(ct.c_float), ct.c_int64]
+        L.crbm_ar_get_params.argtypes = [ct.c_void_p, p(ct.c_float), ct.c_int64]
+        L.crbm_ar_grad.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64, p(ct.c_float), p(ct.c_double)]
+        L.crbm_ar_train_step.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_float, p(ct.c_double)]
+        L.crbm_ar_logq.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p]
+        L.crbm_ar_sample.argtypes = [ct.c_void_p, ct.c_int64, ct.c_uint64, ct.c_int64, ct.c_uint32, ct.c_void_p,
+                                     ct.c_void_p]
+        L.crbm_sample_mh.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p, p(ct.c_int64)]
+        L.crbm_ar_destroy.argtypes = [ct.c_void_p]
+        L.crbm_ar_destroy.restype = None
+        L.crbm_tau_int.argtypes = [ct.c_void_p, ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int64,
+                                   p(ct.c_double), ct.c_int32, ct.c_double, ct.c_void_p, p(ct.c_double),
+                                   p(ct.c_double), p(ct.c_int32), p(ct.c_double)]
         L.crbm_get_tiling.argtypes = [ct.c_int32, p(ct.c_int32), p(ct.c_int32)]
         _lib = L
     return _lib
@@ -139,6 +160,24 @@ def autotune(L: int, n_chains: int = 4096, n_sweeps: int = 50, stream=None):
     _check(lib().crbm_autotune(L, n_chains, n_sweeps, _stream_handle(stream), ct.byref(r), ct.byref(w),
                                ct.byref(rate)))
     return int(r.value), int(w.value), float(rate.value)
+
+
+def tau_int(trace, weights, c0: int = 0, c1: Optional[int] = None, discard: int = 0, max_lag: int = 2000,
+            c_window: float = 5.0, stream=None):
+    """tau_int, ESS, window and rho(k) of O = w0 M + w1 B1 + w2 B2 over a
+    device counts trace [n_samples, chains, 3] (int32)."""
+    assert trace.is_cuda and trace.dim() == 3 and trace.shape[2] == 3 and trace.element_size() == 4
+    trace = trace.contiguous()
+    n, nch = int(trace.shape[0]), int(trace.shape[1])
+    c1 = nch if c1 is None else c1
+    w = (ct.c_double * 3)(*[float(x) for x in weights])
+    K = min(max_lag, n - discard - 1)
+    rho = np.zeros(K + 1, np.float64)
+    tau, ess, win = ct.c_double(), ct.c_double(), ct.c_int32()
+    _check(lib().crbm_tau_int(ct.c_void_p(trace.data_ptr()), n, nch, c0, c1, discard, w, max_lag, c_window,
+                              _stream_handle(stream), ct.byref(tau), ct.byref(ess), ct.byref(win),
+                              rho.ctypes.data_as(ct.POINTER(ct.c_double))))
+    return float(tau.value), float(ess.value), int(win.value), rho
 
 
 def set_tiling(L: int, rows: int, waves_per_block: int = 4):
@@ -257,3 +296,72 @@ class Sampler:
         out = np.zeros(16, np.uint32)
         _check(lib().crbm_sweep_table(self._h, i, s, out.ctypes.data_as(ct.POINTER(ct.c_uint32))))
         return out
+
+
+class ARNet:
+    """Handle on the learned autoregressive proposal (crbm_ar_*)."""
+
+    def __init__(self, L: int, seed: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the network runs only on the HIP device")
+        self.L = L
+        cfg = _ARConfig(L, 32, 12, seed, _stream_handle(stream))
+        h = ct.c_void_p()
+        _check(lib().crbm_ar_create(ct.byref(cfg), ct.byref(h)))
+        self._h = h
+        self.num_params = int(lib().crbm_ar_num_params(h))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.crbm_ar_destroy(h)
+            self._h = None
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, np.float32)
+        assert a.size == self.num_params
+        _check(lib().crbm_ar_set_params(self._h, a.ctypes.data_as(ct.POINTER(ct.c_float)), a.size))
+
+    def get_params(self) -> np.ndarray:
+        a = np.zeros(self.num_params, np.float32)
+        _check(lib().crbm_ar_get_params(self._h, a.ctypes.data_as(ct.POINTER(ct.c_float)), a.size))
+        return a
+
+    def grad(self, samples):
+        assert samples.is_cuda and samples.dtype.itemsize == 1
+        g = np.zeros(self.num_params, np.float32)
+        loss = ct.c_double()
+        _check(lib().crbm_ar_grad(self._h, ct.c_void_p(samples.data_ptr()), samples.shape[0],
+                                  g.ctypes.data_as(ct.POINTER(ct.c_float)), ct.byref(loss)))
+        return g, float(loss.value)
+
+    def train_step(self, samples, lr: float) -> float:
+        loss = ct.c_double()
+        _check(lib().crbm_ar_train_step(self._h, ct.c_void_p(samples.data_ptr()), samples.shape[0], lr,
+                                        ct.byref(loss)))
+        return float(loss.value)
+
+    def logq(self, spins):
+        import torch
+        out = torch.empty(spins.shape[0], dtype=torch.float64, device="cuda")
+        _check(lib().crbm_ar_logq(self._h, ct.c_void_p(spins.data_ptr()), spins.shape[0],
+                                  ct.c_void_p(out.data_ptr())))
+        return out
+
+    def sample(self, n: int, seed: int, step: int = 0, id: int = 0):
+        import torch
+        spins = torch.empty((n, self.L, self.L), dtype=torch.int8, device="cuda")
+        lq = torch.empty(n, dtype=torch.float64, device="cuda")
+        _check(lib().crbm_ar_sample(self._h, n, seed, step, id, ct.c_void_p(spins.data_ptr()),
+                                    ct.c_void_p(lq.data_ptr())))
+        return spins, lq
+
+
+def sample_mh(sampler: Sampler, net: ARNet, n_cycles: int, gibbs_per_mh: int, trace=None) -> int:
+    """n_cycles of gibbs_per_mh Gibbs sweeps then one independent-MH step with
+    the network's proposals.  Returns the number of accepted moves."""
+    acc = ct.c_int64()
+    _check(lib().crbm_sample_mh(sampler._h, net._h, n_cycles, gibbs_per_mh,
+                                ct.c_void_p(trace.data_ptr()) if trace is not None else None, ct.byref(acc)))
+    return int(acc.value)

@@ -1,0 +1,960 @@
+// ar.hip -- learned proposal for independent Metropolis-Hastings: a masked-
+// convolution autoregressive network over the spins in raster order, with
+// bf16 matrix-core (MFMA) kernels accumulating in fp32 for training and for
+// sequential sampling / scoring, and the MH accept step on exact integer
+// energies so the chain keeps the CRBM's stationary law.  (The paper samples
+// its CRBM by Gibbs only, Sec. II.B; this proposal is an addition on top.)
+//
+// Network: C = 32 channels, 12 layers of 3x3 masked convolutions, zero
+// padding.  Layer 1 uses mask A (the 4 sites before the centre in raster
+// order), layers 2-12 mask B (plus the centre).  Layers 2-11 are residual,
+// h_l = bf16(h_{l-1} + relu(z_l)); layer 12 gives one logit per site.
+// log q(s) = sum_i log sigmoid(s_i logit_i).
+//
+// Layouts: activations [pixel][32] bf16 (pixel = (b L + r) L + c), channel
+// dimension padded to 32 for the 1-channel input and output; weights per layer
+// and tap as 32x32 bf16 blocks, "fwd" [tap][cout][cin] (matrix-core B operand
+// for the forward conv) and "bwd" [tap][cin][cout] (for the data gradient).
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "crbm.h"
+#include "crbm_internal.h"
+#include "gibbs_kernel.h"
+
+namespace crbmlib {
+namespace ar {
+
+constexpr int C = 32;
+constexpr int NL = 12;
+constexpr int NT = 5;  // taps per layer (mask A uses the first 4)
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+struct Taps {
+    int n;
+    int dr[NT], dc[NT];
+};
+
+// Mask A / B taps; "mirrored" taps (negated) give the adjoint convolution.
+inline Taps taps_for(int layer, bool mirrored) {
+    const int dr[NT] = {-1, -1, -1, 0, 0};
+    const int dc[NT] = {-1, 0, 1, -1, 0};
+    Taps t{};
+    t.n = (layer == 0) ? 4 : 5;
+    for (int k = 0; k < t.n; ++k) {
+        t.dr[k] = mirrored ? -dr[k] : dr[k];
+        t.dc[k] = mirrored ? -dc[k] : dc[k];
+    }
+    return t;
+}
+
+__device__ __forceinline__ Taps taps_for_dev(int layer) {
+    Taps t;
+    t.n = (layer == 0) ? 4 : 5;
+    t.dr[0] = -1; t.dc[0] = -1;
+    t.dr[1] = -1; t.dc[1] = 0;
+    t.dr[2] = -1; t.dc[2] = 1;
+    t.dr[3] = 0;  t.dc[3] = -1;
+    t.dr[4] = 0;  t.dc[4] = 0;
+    return t;
+}
+
+__device__ __forceinline__ float bf2f(__bf16 x) { return (float)x; }
+__device__ __forceinline__ __bf16 f2bf(float x) { return (__bf16)x; }  // round to nearest even
+
+__device__ __forceinline__ bf16x8 load8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+__device__ __forceinline__ bf16x8 zero8() {
+    bf16x8 z;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.0f;
+    return z;
+}
+
+// Neighbour pixel of p shifted by (dr, dc) inside the same lattice, or -1.
+__device__ __forceinline__ int64_t shift_pixel(int64_t p, int dr, int dc, int L) {
+    const int64_t LL = (int64_t)L * L;
+    const int64_t b = p / LL;
+    const int rc = (int)(p - b * LL);
+    const int r = rc / L + dr, c = rc % L + dc;
+    if (r < 0 || r >= L || c < 0 || c >= L) return -1;
+    return b * LL + (int64_t)r * L + c;
+}
+
+// Epilogue modes of the generic conv kernel.
+enum { EP_RELU = 0, EP_RESID = 1, EP_LOGIT = 2, EP_DGRAD = 3, EP_DGRAD_RESID = 4 };
+
+// out tile of 32 pixels x 32 channels per wavefront:
+//   acc[p][j] = sum_t sum_k in[p + tap_t][k] * Wop[t][j][k]
+// with the matrix-core layout: A row i = pixel, B column j = out channel,
+// k = 16-element chunks of the 32 input channels of each tap.
+__global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ Wop,
+                                                     const float* __restrict__ bias, Taps taps, int L, int64_t P,
+                                                     int mode, const __bf16* __restrict__ resid_bf,
+                                                     const float* __restrict__ resid_f, __bf16* out_bf,
+                                                     uint8_t* out_mask, float* out_f) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int li = lane & 31, half = lane >> 5;
+    // B fragments stay in registers for the whole launch
+    bf16x8 Bf[NT][2];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int kh = 0; kh < 2; ++kh)
+            Bf[t][kh] = (t < taps.n) ? load8(Wop + ((int64_t)t * C + li) * C + kh * 16 + half * 8) : zero8();
+    const float bj = (mode == EP_DGRAD || mode == EP_DGRAD_RESID) ? 0.f : bias[li];
+    const int64_t ntiles = (P + 31) / 32;
+    for (int64_t tile = w0; tile < ntiles; tile += nw) {
+        const int64_t p = tile * 32 + li;
+        f32x16 acc;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            if (t >= taps.n) break;
+            const int64_t q = (p < P) ? shift_pixel(p, taps.dr[t], taps.dc[t], L) : -1;
+#pragma unroll
+            for (int kh = 0; kh < 2; ++kh) {
+                const bf16x8 a = (q >= 0) ? load8(in + q * C + kh * 16 + half * 8) : zero8();
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, Bf[t][kh], acc, 0, 0, 0);
+            }
+        }
+        // D[i][j]: j = lane & 31, i = 8 (v / 4) + 4 half + (v % 4)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int i = 8 * (v >> 2) + 4 * half + (v & 3);
+            const int64_t pi = tile * 32 + i;
+            if (pi >= P) continue;
+            const float z = acc[v] + bj;
+            const int64_t o = pi * C + li;
+            switch (mode) {
+                case EP_RELU:
+                    out_bf[o] = f2bf(z > 0.f ? z : 0.f);
+                    if (out_mask) out_mask[o] = z > 0.f;
+                    break;
+                case EP_RESID:
+                    out_bf[o] = f2bf(bf2f(resid_bf[o]) + (z > 0.f ? z : 0.f));
+                    if (out_mask) out_mask[o] = z > 0.f;
+                    break;
+                case EP_LOGIT:
+                    if (li == 0) out_f[pi] = z;
+                    break;
+                case EP_DGRAD:
+                    out_f[o] = z;
+                    break;
+                default:  // EP_DGRAD_RESID
+                    out_f[o] = z + resid_f[o];
+                    break;
+            }
+        }
+    }
+}
+
+// Partial weight gradient of one tap over a chunk of pixels:
+//   part[chunk][i][j] = sum_{p in chunk} in[p + tap][i] * dz[p][j]
+// (A row i = input channel, k = pixel; B column j = output channel).
+__global__ void __launch_bounds__(256) wgrad_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ dz,
+                                                    Taps taps, int L, int64_t P, int64_t chunk, int nchunks,
+                                                    float* __restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (wid >= (int64_t)nchunks) return;
+    const int li = lane & 31, half = lane >> 5;
+    const int64_t p_begin = wid * chunk, p_end = (p_begin + chunk < P) ? p_begin + chunk : P;
+    f32x16 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[t][v] = 0.f;
+    for (int64_t k0 = p_begin; k0 < p_end; k0 += 16) {
+        bf16x8 b;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t p = k0 + half * 8 + e;
+            b[e] = (p < p_end) ? dz[p * C + li] : (__bf16)0.0f;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            if (t >= taps.n) break;
+            bf16x8 a;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int64_t p = k0 + half * 8 + e;
+                const int64_t q = (p < p_end) ? shift_pixel(p, taps.dr[t], taps.dc[t], L) : -1;
+                a[e] = (q >= 0) ? in[q * C + li] : (__bf16)0.0f;
+            }
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        if (t >= taps.n) break;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int i = 8 * (v >> 2) + 4 * half + (v & 3);
+            part[(((int64_t)wid * NT + t) * C + i) * C + li] = acc[t][v];
+        }
+    }
+}
+
+// sum over chunks: dW[t][i][j] = sum_c part[c][t][i][j]
+__global__ void reduce_chunks_kernel(const float* part, int nchunks, int n, float* out) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * n + x];
+    out[x] = (float)s;
+}
+
+// spins int8 [P] -> bf16 [P][32] with the spin in channel 0
+__global__ void embed_kernel(const int8_t* spins, int64_t P, __bf16* h0) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * C) return;
+    const int64_t p = i / C;
+    h0[i] = ((i % C) == 0) ? f2bf((float)spins[p]) : (__bf16)0.0f;
+}
+
+// loss: per sample log q (fp64) and the logit gradient of -mean log q
+// (bf16, channel 0 of a [P][32] buffer)
+__global__ void __launch_bounds__(256) loss_kernel(const float* logit, const int8_t* spins, int L, float inv_batch,
+                                                   double* logq, __bf16* g, float* g32) {
+    const int b = blockIdx.x;
+    const int N = L * L;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int64_t p = (int64_t)b * N + i;
+        const float sg = (float)spins[p];
+        const float x = sg * logit[p];
+        s += -log1p(exp(-(double)x));
+        const float gi = -sg * (1.f / (1.f + expf(x))) * inv_batch;
+        g[p * C] = f2bf(gi);
+        g32[p] = gi;
+        for (int c = 1; c < C; ++c) g[p * C + c] = (__bf16)0.0f;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) logq[b] = red[0];
+}
+
+// log q per chain from the logits of a full forward pass, one thread per
+// chain, summed over the sites in raster order in fp64 with the same
+// expression as the sequential sampler, so both give identical values.
+__global__ void logq_kernel(const float* __restrict__ logit, const int8_t* __restrict__ spins, int64_t n, int N,
+                            double* __restrict__ logq) {
+    const int64_t ch = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch >= n) return;
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) {
+        const float sg = (float)spins[ch * N + i];
+        s += -log1p(exp(-(double)(sg * logit[ch * N + i])));
+    }
+    logq[ch] = s;
+}
+
+// dz = bf16(dh * mask), plus per-block partial bias gradients sum dh * mask
+__global__ void __launch_bounds__(256) mask_kernel(const float* dh, const uint8_t* mask, int64_t P, __bf16* dz,
+                                                   float* bias_part) {
+    // block handles 256 / 32 = 8 pixels per step, thread = (pixel slot, channel)
+    const int c = threadIdx.x & 31, slot = threadIdx.x >> 5;
+    float s = 0.f;
+    for (int64_t p = (int64_t)blockIdx.x * 8 + slot; p < P; p += (int64_t)gridDim.x * 8) {
+        const int64_t o = p * C + c;
+        const float v = mask[o] ? dh[o] : 0.f;
+        dz[o] = f2bf(v);
+        s += v;
+    }
+    __shared__ float red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (slot == 0) {
+        float t = 0.f;
+        for (int k = 0; k < 8; ++k) t += red[k * 32 + c];
+        bias_part[(int64_t)blockIdx.x * C + c] = t;
+    }
+}
+
+// bias gradient of the logit layer: sum over pixels of the fp32 logit gradient
+__global__ void __launch_bounds__(256) colsum0_kernel(const float* g32, int64_t P, float* part) {
+    float s = 0.f;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x)
+        s += g32[p];
+    __shared__ float red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Adam on the fp32 master parameters (Kingma & Ba, 2015)
+__global__ void adam_kernel(float* th, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                            float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// master fp32 parameters -> padded bf16 operand blocks and padded biases
+__global__ void pack_kernel(const float* th, __bf16* wf, __bf16* wb, float* bias) {
+    // one thread per (layer, tap, a, b) with a, b in 0..31
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= NL * NT * C * C) return;
+    const int b = x % C, a = (x / C) % C, t = (x / (C * C)) % NT, l = x / (NT * C * C);
+    int64_t off = 0;
+    for (int k = 0; k < l; ++k) {
+        const int T = (k == 0) ? 4 : 5, ci = (k == 0) ? 1 : C, co = (k == NL - 1) ? 1 : C;
+        off += (int64_t)T * ci * co + co;
+    }
+    const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
+    // wf[l][t][cout=a][cin=b], wb[l][t][cin=a][cout=b]
+    float vf = 0.f, vb = 0.f;
+    if (t < T) {
+        if (a < co && b < ci) vf = th[off + ((int64_t)t * ci + b) * co + a];
+        if (a < ci && b < co) vb = th[off + ((int64_t)t * ci + a) * co + b];
+    }
+    const int64_t o = (((int64_t)l * NT + t) * C + a) * C + b;
+    wf[o] = f2bf(vf);
+    wb[o] = f2bf(vb);
+    if (t == 0 && b == 0) bias[l * C + a] = (a < co) ? th[off + (int64_t)T * ci * co + a] : 0.f;
+}
+
+// Sequential sampler / scorer: one wavefront per 32 chains; sites in raster
+// order; at each site all 12 layers are evaluated at that site only.  The
+// taps of a layer read (r-1, c-1..c+1) from hs[l] in global memory (written
+// during the previous row; one device-scope fence per row makes them visible),
+// (r, c-1) from an LDS copy of the previous site's activations of every layer,
+// and the centre from an LDS tile holding the current site's previous-layer
+// output.  The previous-row fragments of layer l+1 are loaded while layer l
+// computes.  Spin i is drawn as +1 iff u < sigmoid(logit) with u from Philox
+// stream 6.  The per-site arithmetic (tap and k order of the matrix-core
+// accumulation, bias, ReLU, residual, bf16 rounding) is that of conv32_kernel,
+// so the logits, and log q, equal those of a full forward pass bit for bit.
+__global__ void __launch_bounds__(64) seq_kernel(int64_t n_chains, int L, const __bf16* __restrict__ wf,
+                                                 const float* __restrict__ bias, __bf16* hs, int8_t* spins,
+                                                 double* logq, uint64_t seed, uint32_t step, uint32_t id) {
+    const int lane = threadIdx.x;
+    const int li = lane & 31, half = lane >> 5;
+    const int N = L * L;
+    const int64_t base = (int64_t)blockIdx.x * 32;
+    const bool valid = base + li < n_chains;
+    const int64_t cA = valid ? base + li : base;  // clamp reads of padding rows
+    // prev[buf][l][chain][ch]: activations h_l at the previous site (buf = site parity)
+    __shared__ __bf16 prev[2][NL][32 * C];
+    __shared__ __bf16 tile[32 * C];
+    const int64_t LS = (int64_t)n_chains * N * C;  // layer stride in hs
+    double lqr[16];                                // lanes 0 and 32: log q of 16 chains each
+#pragma unroll
+    for (int v = 0; v < 16; ++v) lqr[v] = 0.0;
+    for (int site = 0; site < N; ++site) {
+        const int r = site / L, c = site % L;
+        const int cur = site & 1, old = cur ^ 1;
+        if (c == 0) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");  // the previous row is visible
+        // previous-row fragments of layer 0
+        bf16x8 pr[3][2];
+        auto load_row = [&](int l, bf16x8 (&dst)[3][2]) {
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const int rr = r - 1, cc = c - 1 + t;
+                const bool inside = rr >= 0 && cc >= 0 && cc < L;
+#pragma unroll
+                for (int kh = 0; kh < 2; ++kh)
+                    dst[t][kh] = inside ? load8(hs + (int64_t)l * LS + (cA * N + rr * L + cc) * C + kh * 16 + half * 8)
+                                        : zero8();
+            }
+        };
+        load_row(0, pr);
+        for (int l = 0; l < NL; ++l) {
+            bf16x8 nx[3][2];
+            if (l + 1 < NL) load_row(l + 1, nx);
+            f32x16 acc;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+            const __bf16* W = wf + (int64_t)l * NT * C * C;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                if (t == 4 && l == 0) break;  // mask A: no centre tap
+#pragma unroll
+                for (int kh = 0; kh < 2; ++kh) {
+                    bf16x8 a;
+                    if (t < 3)
+                        a = pr[t][kh];
+                    else if (t == 3)
+                        a = (c > 0) ? *reinterpret_cast<const bf16x8*>(&prev[old][l][li * C + kh * 16 + half * 8])
+                                    : zero8();
+                    else
+                        a = *reinterpret_cast<const bf16x8*>(&tile[li * C + kh * 16 + half * 8]);
+                    const bf16x8 b = load8(W + ((int64_t)t * C + li) * C + kh * 16 + half * 8);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+                }
+            }
+            const float bj = bias[l * C + li];
+            if (l < NL - 1) {
+                float hnew[16];
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int i = 8 * (v >> 2) + 4 * half + (v & 3);
+                    const float z = acc[v] + bj;
+                    const float rz = z > 0.f ? z : 0.f;
+                    hnew[v] = (l == 0) ? rz : bf2f(tile[i * C + li]) + rz;
+                }
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int i = 8 * (v >> 2) + 4 * half + (v & 3);
+                    const __bf16 hb = f2bf(hnew[v]);
+                    tile[i * C + li] = hb;
+                    prev[cur][l + 1][i * C + li] = hb;
+                    if (base + i < n_chains) hs[(int64_t)(l + 1) * LS + ((base + i) * N + site) * C + li] = hb;
+                }
+                __builtin_amdgcn_wave_barrier();
+            } else {
+                // logits live in column j = 0 (lanes 0 and 32)
+                if (li == 0) {
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const int i = 8 * (v >> 2) + 4 * half + (v & 3);
+                        const int64_t ch = base + i;
+                        float s = 0.f;
+                        const float x = acc[v] + bj;
+                        if (ch < n_chains) {
+                            const gk::P4 u4 = gk::philox((uint32_t)site, step, (uint32_t)ch, (id << 3) | 6u,
+                                                         (uint32_t)seed, (uint32_t)(seed >> 32));
+                            const float u = (float)(u4.v[0] >> 8) * (1.0f / 16777216.0f);
+                            const float p = 1.f / (1.f + expf(-x));
+                            s = (u < p) ? 1.f : -1.f;
+                            spins[ch * N + site] = (int8_t)s;
+                            hs[(ch * N + site) * C] = f2bf(s);
+                            lqr[v] += -log1p(exp(-(double)(s * x)));
+                        }
+                        // the spin is layer 0's input at this site (channel 0; other channels stay 0)
+                        prev[cur][0][i * C] = f2bf(s);
+                    }
+                }
+                if (li != 0) {
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const int i = 8 * (v >> 2) + 4 * half + (v & 3);
+                        prev[cur][0][i * C + li] = (__bf16)0.0f;
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+            if (l + 1 < NL) {
+#pragma unroll
+                for (int t = 0; t < 3; ++t)
+#pragma unroll
+                    for (int kh = 0; kh < 2; ++kh) pr[t][kh] = nx[t][kh];
+            }
+        }
+    }
+    if (li == 0) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int i = 8 * (v >> 2) + 4 * half + (v & 3);
+            if (base + i < n_chains) logq[base + i] = lqr[v];
+        }
+    }
+}
+
+}  // namespace ar
+}  // namespace crbmlib
+
+// ---------------------------------------------------------------- host side
+
+namespace crbmlib {
+namespace ar {
+
+__global__ void counts_int8_kernel(const int8_t* s, int64_t n, int L, int32_t* out) {
+    const int64_t ch = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch >= n) return;
+    const int8_t* x = s + ch * L * L;
+    int M = 0, B1 = 0, B2 = 0;
+    for (int r = 0; r < L; ++r)
+        for (int c = 0; c < L; ++c) {
+            const int v = x[r * L + c];
+            M += v;
+            B1 += v * x[r * L + (c + 1) % L] + v * x[((r + 1) % L) * L + c];
+            if ((r & 1) == 0 && (c & 1) == 0) B2 += v * x[(r + 1) * L + c + 1];          // '\' dimer
+            if ((r & 1) == 1 && (c & 1) == 0) B2 += v * x[((r + 1) % L) * L + (c + L - 1) % L];  // '/' dimer
+        }
+    out[ch * 3] = M;
+    out[ch * 3 + 1] = B1;
+    out[ch * 3 + 2] = B2;
+}
+
+// Independent MH (one thread per chain): log alpha = [log pi' - log pi] +
+// [log q - log q'], log pi from the exact integer counts; accept iff
+// log u < log alpha with u from Philox stream 5.
+__global__ void mh_kernel(int64_t n, int L, int8_t* cur, const int8_t* prop, int32_t* cnt_cur,
+                          const int32_t* cnt_prop, double* lq_cur, const double* lq_prop, double a, double c1,
+                          double c2, int sg1, int sg2, uint64_t seed, uint32_t step, uint32_t id,
+                          unsigned long long* n_acc) {
+    const int64_t ch = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch >= n) return;
+    const int64_t N = (int64_t)L * L;
+    auto logpi = [&](const int32_t* k) {
+        const int64_t M = k[0], B1 = k[1], B2 = k[2];
+        const int64_t n1 = sg1 < 0 ? (2 * N - B1) / 2 : (2 * N + B1) / 2;
+        const int64_t n2 = sg2 < 0 ? (N / 2 - B2) / 2 : (N / 2 + B2) / 2;
+        return a * (double)M + c1 * (double)n1 + c2 * (double)n2;
+    };
+    const double la = (logpi(cnt_prop + ch * 3) - logpi(cnt_cur + ch * 3)) + (lq_cur[ch] - lq_prop[ch]);
+    const gk::P4 r = gk::philox(0u, step, (uint32_t)ch, (id << 3) | 5u, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double u = ((double)(((uint64_t)r.v[0] << 21) ^ (r.v[1] >> 11)) + 0.5) * (1.0 / 9007199254740992.0);
+    if (log(u) < la) {
+        for (int64_t i = 0; i < N; ++i) cur[ch * N + i] = prop[ch * N + i];
+        for (int k = 0; k < 3; ++k) cnt_cur[ch * 3 + k] = cnt_prop[ch * 3 + k];
+        lq_cur[ch] = lq_prop[ch];
+        atomicAdd(n_acc, 1ull);
+    }
+}
+
+__global__ void scatter_grad_kernel(const float* dW, int l, float* grad) {
+    // dW [T][32][32] padded -> grad layout of layer l
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
+    if (x >= T * ci * co) return;
+    int64_t off = 0;
+    for (int k = 0; k < l; ++k) {
+        const int Tk = (k == 0) ? 4 : 5, cik = (k == 0) ? 1 : C, cok = (k == NL - 1) ? 1 : C;
+        off += (int64_t)Tk * cik * cok + cok;
+    }
+    const int o = x % co, i = (x / co) % ci, t = x / (co * ci);
+    grad[off + x] = dW[((int64_t)t * C + i) * C + o];
+}
+
+__global__ void scatter_bias_kernel(const float* part, int nparts, int l, float* grad) {
+    const int j = threadIdx.x;
+    const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
+    if (j >= co) return;
+    int64_t off = 0;
+    for (int k = 0; k < l; ++k) {
+        const int Tk = (k == 0) ? 4 : 5, cik = (k == 0) ? 1 : C, cok = (k == NL - 1) ? 1 : C;
+        off += (int64_t)Tk * cik * cok + cok;
+    }
+    double s = 0.0;
+    for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * (co == 1 ? 1 : C) + j];
+    grad[off + (int64_t)T * ci * co + j] = (float)s;
+}
+
+int64_t n_params() {
+    int64_t n = 0;
+    for (int l = 0; l < NL; ++l) {
+        const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
+        n += (int64_t)T * ci * co + co;
+    }
+    return n;
+}
+
+}  // namespace ar
+}  // namespace crbmlib
+
+using namespace crbmlib;
+using namespace crbmlib::ar;
+
+struct crbm_ar_s {
+    int L = 0;
+    uint64_t seed = 0;
+    hipStream_t stream = nullptr;
+    int64_t np = 0;
+    int64_t t_adam = 0;
+    uint64_t mh_step = 0;  // MH cycles run so far: the counter word of their random streams
+    float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr, *bias = nullptr;
+    __bf16 *wf = nullptr, *wb = nullptr;
+    // training buffers (capacity in samples)
+    int64_t tcap = 0;
+    __bf16* hs = nullptr;       // [NL][P][C]
+    uint8_t* mask = nullptr;    // [NL-1][P][C]
+    float* logit = nullptr;     // [P]
+    float* g32 = nullptr;       // [P]
+    float *dh0 = nullptr, *dh1 = nullptr;  // [P][C]
+    __bf16 *dz = nullptr, *g = nullptr;    // [P][C]
+    double* logq = nullptr;     // [B]
+    float *part = nullptr, *dW = nullptr, *bpart = nullptr;
+    int8_t* spins_copy = nullptr;
+    // sequential sampler buffers (capacity in chains)
+    int64_t scap = 0;
+    __bf16* shs = nullptr;      // [NL][n][N][C]
+    // scoring buffers (capacity in chains): ping-pong activations and logits
+    int64_t icap = 0;
+    __bf16 *ih0 = nullptr, *ih1 = nullptr;  // [n N][C]
+    float* ilogit = nullptr;                // [n N]
+    // MH buffers
+    int64_t mcap = 0;
+    int8_t *cur = nullptr, *prop = nullptr;
+    int32_t *ccur = nullptr, *cprop = nullptr;
+    double *lqc = nullptr, *lqp = nullptr;
+    unsigned long long* nacc = nullptr;
+    ~crbm_ar_s() {
+        void* ps[] = {theta, grad, m, v, bias, wf, wb, hs, mask, logit, g32, dh0, dh1, dz, g, logq, part, dW, bpart,
+                      spins_copy, shs, ih0, ih1, ilogit, cur, prop, ccur, cprop, lqc, lqp, nacc};
+        for (void* p : ps)
+            if (p) (void)hipFree(p);
+    }
+};
+
+namespace {
+
+int fail_ar(int code, const char* msg) { return set_error(code, msg); }
+
+#define AR_TRY(expr, what)                                                              \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) return fail_ar(CRBM_EHIP, (std::string(what) + ": " + hipGetErrorString(e_)).c_str()); \
+    } while (0)
+
+template <class T>
+hipError_t alloc(T** p, int64_t n) {
+    return hipMalloc((void**)p, sizeof(T) * (size_t)(n > 0 ? n : 1));
+}
+
+constexpr int64_t kChunk = 1024;
+
+int ensure_train(crbm_ar_t* a, int64_t B) {
+    if (B <= a->tcap) return CRBM_OK;
+    void* ps[] = {a->hs, a->mask, a->logit, a->g32, a->dh0, a->dh1, a->dz, a->g, a->logq, a->part, a->bpart, a->spins_copy};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    const int64_t P = B * a->L * a->L;
+    const int64_t nch = (P + kChunk - 1) / kChunk;
+    if (alloc(&a->hs, (int64_t)NL * P * C) || alloc(&a->mask, (int64_t)(NL - 1) * P * C) || alloc(&a->logit, P) ||
+        alloc(&a->g32, P) || alloc(&a->dh0, P * C) || alloc(&a->dh1, P * C) || alloc(&a->dz, P * C) ||
+        alloc(&a->g, P * C) || alloc(&a->logq, B) || alloc(&a->part, nch * NT * C * C) ||
+        alloc(&a->bpart, (int64_t)4096 * C) || alloc(&a->spins_copy, P)) {
+        a->tcap = 0;
+        return fail_ar(CRBM_ENOMEM, "training buffers");
+    }
+    a->tcap = B;
+    return CRBM_OK;
+}
+
+int ensure_seq(crbm_ar_t* a, int64_t n) {
+    if (n <= a->scap) return CRBM_OK;
+    if (a->shs) (void)hipFree(a->shs);
+    if (alloc(&a->shs, (int64_t)NL * n * a->L * a->L * C)) {
+        a->scap = 0;
+        return fail_ar(CRBM_ENOMEM, "sampler buffers");
+    }
+    a->scap = n;
+    return CRBM_OK;
+}
+
+int pack(crbm_ar_t* a) {
+    hipLaunchKernelGGL(pack_kernel, dim3((NL * NT * C * C + 255) / 256), dim3(256), 0, a->stream, a->theta, a->wf, a->wb,
+                       a->bias);
+    AR_TRY(hipGetLastError(), "pack");
+    return CRBM_OK;
+}
+
+int conv_blocks(int64_t P) {
+    const int64_t tiles = (P + 31) / 32;
+    const int64_t b = (tiles + 3) / 4;
+    return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+// forward + loss + backward into a->grad; per-sample log q into a->logq
+int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B) {
+    const int L = a->L;
+    const int64_t P = B * L * L;
+    const size_t LSZ = (size_t)P * C;
+    hipStream_t st = a->stream;
+    hipLaunchKernelGGL(embed_kernel, dim3((unsigned)((P * C + 255) / 256)), dim3(256), 0, st, spins, P, a->hs);
+    for (int l = 0; l < NL; ++l) {
+        const Taps tp = taps_for(l, false);
+        const __bf16* W = a->wf + (size_t)l * NT * C * C;
+        const int mode = (l == NL - 1) ? EP_LOGIT : (l == 0 ? EP_RELU : EP_RESID);
+        __bf16* out = (l < NL - 1) ? a->hs + (size_t)(l + 1) * LSZ : nullptr;
+        uint8_t* mk = (l < NL - 1) ? a->mask + (size_t)l * LSZ : nullptr;
+        hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P)), dim3(256), 0, st, a->hs + (size_t)l * LSZ, W,
+                           a->bias + l * C, tp, L, P, mode, a->hs + (size_t)l * LSZ, (const float*)nullptr, out, mk,
+                           a->logit);
+    }
+    hipLaunchKernelGGL(loss_kernel, dim3((unsigned)B), dim3(256), 0, st, a->logit, spins, L, 1.0f / (float)B, a->logq,
+                       a->g, a->g32);
+    const int nch = (int)((P + kChunk - 1) / kChunk);
+    float* dh = a->dh0;
+    float* dh_alt = a->dh1;
+    for (int l = NL - 1; l >= 0; --l) {
+        const Taps tp = taps_for(l, false), tm = taps_for(l, true);
+        const __bf16* dzl;
+        int nbp;
+        if (l == NL - 1) {
+            dzl = a->g;
+            nbp = 256;
+            hipLaunchKernelGGL(colsum0_kernel, dim3(nbp), dim3(256), 0, st, a->g32, P, a->bpart);
+        } else {
+            nbp = (int)std::min<int64_t>(4096, (P + 7) / 8);
+            hipLaunchKernelGGL(mask_kernel, dim3(nbp), dim3(256), 0, st, dh, a->mask + (size_t)l * LSZ, P, a->dz,
+                               a->bpart);
+            dzl = a->dz;
+        }
+        hipLaunchKernelGGL(scatter_bias_kernel, dim3(1), dim3(32), 0, st, a->bpart, nbp, l, a->grad);
+        hipLaunchKernelGGL(wgrad_kernel, dim3((unsigned)((nch + 3) / 4)), dim3(256), 0, st, a->hs + (size_t)l * LSZ, dzl,
+                           tp, L, P, kChunk, nch, a->part);
+        hipLaunchKernelGGL(reduce_chunks_kernel, dim3((NT * C * C + 255) / 256), dim3(256), 0, st, a->part, nch,
+                           NT * C * C, a->dW);
+        const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
+        hipLaunchKernelGGL(scatter_grad_kernel, dim3((T * ci * co + 255) / 256), dim3(256), 0, st, a->dW, l, a->grad);
+        if (l > 0) {
+            const __bf16* Wb = a->wb + (size_t)l * NT * C * C;
+            const int mode = (l == NL - 1) ? EP_DGRAD : EP_DGRAD_RESID;
+            hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P)), dim3(256), 0, st, dzl, Wb, a->bias, tm, L, P, mode,
+                               (const __bf16*)nullptr, (const float*)dh, (__bf16*)nullptr, (uint8_t*)nullptr, dh_alt);
+            std::swap(dh, dh_alt);
+        }
+    }
+    AR_TRY(hipGetLastError(), "training kernels");
+    return CRBM_OK;
+}
+
+// ancestral sampling of n configurations (spins and their log q)
+int run_seq(crbm_ar_t* a, int64_t n, int8_t* spins, double* logq, uint64_t seed, uint32_t step, uint32_t id) {
+    int rc = ensure_seq(a, n);
+    if (rc != CRBM_OK) return rc;
+    const int64_t N = (int64_t)a->L * a->L;
+    hipStream_t st = a->stream;
+    AR_TRY(hipMemsetAsync(a->shs, 0, sizeof(__bf16) * (size_t)n * N * C, st), "clear sampler input");
+    hipLaunchKernelGGL(seq_kernel, dim3((unsigned)((n + 31) / 32)), dim3(64), 0, st, n, a->L, a->wf, a->bias, a->shs,
+                       spins, logq, seed, step, id);
+    AR_TRY(hipGetLastError(), "sequential kernel");
+    return CRBM_OK;
+}
+
+int ensure_infer(crbm_ar_t* a, int64_t n) {
+    if (n <= a->icap) return CRBM_OK;
+    void* ps[] = {a->ih0, a->ih1, a->ilogit};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    a->ih0 = a->ih1 = nullptr;
+    a->ilogit = nullptr;
+    const int64_t P = n * a->L * a->L;
+    if (alloc(&a->ih0, P * C) || alloc(&a->ih1, P * C) || alloc(&a->ilogit, P)) {
+        a->icap = 0;
+        return fail_ar(CRBM_ENOMEM, "scoring buffers");
+    }
+    a->icap = n;
+    return CRBM_OK;
+}
+
+// log q of n given configurations by one full forward pass over all sites
+int run_score(crbm_ar_t* a, int64_t n, const int8_t* spins, double* logq) {
+    int rc = ensure_infer(a, n);
+    if (rc != CRBM_OK) return rc;
+    const int L = a->L;
+    const int64_t P = n * L * L;
+    hipStream_t st = a->stream;
+    hipLaunchKernelGGL(embed_kernel, dim3((unsigned)((P * C + 255) / 256)), dim3(256), 0, st, spins, P, a->ih0);
+    __bf16* in = a->ih0;
+    __bf16* out = a->ih1;
+    for (int l = 0; l < NL; ++l) {
+        const Taps tp = taps_for(l, false);
+        const __bf16* W = a->wf + (size_t)l * NT * C * C;
+        const int mode = (l == NL - 1) ? EP_LOGIT : (l == 0 ? EP_RELU : EP_RESID);
+        hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P)), dim3(256), 0, st, in, W, a->bias + l * C, tp, L, P,
+                           mode, in, (const float*)nullptr, out, (uint8_t*)nullptr, a->ilogit);
+        std::swap(in, out);
+    }
+    hipLaunchKernelGGL(logq_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a->ilogit, spins, n, L * L,
+                       logq);
+    AR_TRY(hipGetLastError(), "scoring kernels");
+    return CRBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t crbm_ar_num_params(const crbm_ar_t* a) { return a ? a->np : 0; }
+
+int crbm_ar_create(const crbm_ar_config* c, crbm_ar_t** out) {
+    if (!c || !out) return fail_ar(CRBM_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (c->L < 4 || c->L > CRBM_MAX_L || (c->L & 1)) return fail_ar(CRBM_EINVAL, "bad L");
+    if (c->channels != C || c->layers != NL) return fail_ar(CRBM_EUNSUPPORTED, "kernels are built for 32 channels, 12 layers");
+    crbm_ar_s* a = new (std::nothrow) crbm_ar_s();
+    if (!a) return fail_ar(CRBM_ENOMEM, "host allocation");
+    a->L = c->L;
+    a->seed = c->seed;
+    a->stream = (hipStream_t)c->stream;
+    a->np = n_params();
+    if (alloc(&a->theta, a->np) || alloc(&a->grad, a->np) || alloc(&a->m, a->np) || alloc(&a->v, a->np) ||
+        alloc(&a->bias, NL * C) || alloc(&a->wf, (int64_t)NL * NT * C * C) || alloc(&a->wb, (int64_t)NL * NT * C * C) ||
+        alloc(&a->dW, NT * C * C)) {
+        delete a;
+        return fail_ar(CRBM_ENOMEM, "parameter buffers");
+    }
+    (void)hipMemsetAsync(a->theta, 0, sizeof(float) * a->np, a->stream);
+    (void)hipMemsetAsync(a->m, 0, sizeof(float) * a->np, a->stream);
+    (void)hipMemsetAsync(a->v, 0, sizeof(float) * a->np, a->stream);
+    (void)hipMemsetAsync(a->grad, 0, sizeof(float) * a->np, a->stream);
+    int rc = pack(a);
+    if (rc == CRBM_OK && hipStreamSynchronize(a->stream) != hipSuccess) rc = fail_ar(CRBM_EHIP, "synchronize");
+    if (rc != CRBM_OK) {
+        delete a;
+        return rc;
+    }
+    *out = a;
+    return CRBM_OK;
+}
+
+int crbm_ar_set_params(crbm_ar_t* a, const float* host, int64_t n) {
+    if (!a || !host || n != a->np) return fail_ar(CRBM_EINVAL, "parameter count mismatch");
+    AR_TRY(hipMemcpyAsync(a->theta, host, sizeof(float) * n, hipMemcpyHostToDevice, a->stream), "copy params");
+    (void)hipMemsetAsync(a->m, 0, sizeof(float) * a->np, a->stream);
+    (void)hipMemsetAsync(a->v, 0, sizeof(float) * a->np, a->stream);
+    a->t_adam = 0;
+    int rc = pack(a);
+    if (rc != CRBM_OK) return rc;
+    AR_TRY(hipStreamSynchronize(a->stream), "synchronize");
+    return CRBM_OK;
+}
+
+int crbm_ar_get_params(crbm_ar_t* a, float* host, int64_t n) {
+    if (!a || !host || n != a->np) return fail_ar(CRBM_EINVAL, "parameter count mismatch");
+    AR_TRY(hipMemcpyAsync(host, a->theta, sizeof(float) * n, hipMemcpyDeviceToHost, a->stream), "copy params");
+    AR_TRY(hipStreamSynchronize(a->stream), "synchronize");
+    return CRBM_OK;
+}
+
+int crbm_ar_grad(crbm_ar_t* a, const int8_t* samples_dev, int64_t batch, float* grad_host, double* loss_out) {
+    if (!a || !samples_dev || batch < 1) return fail_ar(CRBM_EINVAL, "bad arguments");
+    int rc = ensure_train(a, batch);
+    if (rc != CRBM_OK) return rc;
+    rc = grad_pass(a, samples_dev, batch);
+    if (rc != CRBM_OK) return rc;
+    if (grad_host)
+        AR_TRY(hipMemcpyAsync(grad_host, a->grad, sizeof(float) * a->np, hipMemcpyDeviceToHost, a->stream), "copy grad");
+    if (loss_out) {
+        std::vector<double> lq(batch);
+        AR_TRY(hipMemcpyAsync(lq.data(), a->logq, sizeof(double) * batch, hipMemcpyDeviceToHost, a->stream), "copy logq");
+        AR_TRY(hipStreamSynchronize(a->stream), "synchronize");
+        double s = 0.0;
+        for (double x : lq) s += x;
+        *loss_out = -s / (double)batch;
+    }
+    AR_TRY(hipStreamSynchronize(a->stream), "synchronize");
+    return CRBM_OK;
+}
+
+int crbm_ar_train_step(crbm_ar_t* a, const int8_t* samples_dev, int64_t batch, float lr, double* loss_out) {
+    if (!a || !samples_dev || batch < 1 || !(lr > 0.f)) return fail_ar(CRBM_EINVAL, "bad arguments");
+    int rc = ensure_train(a, batch);
+    if (rc != CRBM_OK) return rc;
+    rc = grad_pass(a, samples_dev, batch);
+    if (rc != CRBM_OK) return rc;
+    a->t_adam += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - powf(b1, (float)a->t_adam), c2 = 1.f - powf(b2, (float)a->t_adam);
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((a->np + 255) / 256)), dim3(256), 0, a->stream, a->theta, a->grad,
+                       a->m, a->v, a->np, lr, b1, b2, 1e-8f, c1, c2);
+    rc = pack(a);
+    if (rc != CRBM_OK) return rc;
+    if (loss_out) {
+        std::vector<double> lq(batch);
+        AR_TRY(hipMemcpyAsync(lq.data(), a->logq, sizeof(double) * batch, hipMemcpyDeviceToHost, a->stream), "copy logq");
+        AR_TRY(hipStreamSynchronize(a->stream), "synchronize");
+        double s = 0.0;
+        for (double x : lq) s += x;
+        *loss_out = -s / (double)batch;
+    }
+    return CRBM_OK;
+}
+
+int crbm_ar_logq(crbm_ar_t* a, const int8_t* spins_dev, int64_t n, double* logq_dev) {
+    if (!a || !spins_dev || !logq_dev || n < 1) return fail_ar(CRBM_EINVAL, "bad arguments");
+    return run_score(a, n, spins_dev, logq_dev);
+}
+
+int crbm_ar_sample(crbm_ar_t* a, int64_t n, uint64_t seed, int64_t step, uint32_t id, int8_t* spins_dev,
+                   double* logq_dev) {
+    if (!a || !spins_dev || !logq_dev || n < 1) return fail_ar(CRBM_EINVAL, "bad arguments");
+    return run_seq(a, n, spins_dev, logq_dev, seed, (uint32_t)step, id);
+}
+
+void crbm_ar_destroy(crbm_ar_t* a) {
+    if (!a) return;
+    (void)hipStreamSynchronize(a->stream);
+    delete a;
+}
+
+int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_mh, int32_t* counts_trace,
+                   int64_t* n_accepted) {
+    if (!h || !a || n_cycles < 0 || gibbs_per_mh < 0) return fail_ar(CRBM_EINVAL, "bad arguments");
+    HandleView v{};
+    if (handle_view(h, &v) != CRBM_OK) return fail_ar(CRBM_EINVAL, "bad handle");
+    if (v.n_inst != 1 || v.sched_kind != CRBM_SCHED_CONST)
+        return fail_ar(CRBM_EUNSUPPORTED, "MH needs a handle with one instance at a constant temperature");
+    if (v.L != a->L) return fail_ar(CRBM_EINVAL, "lattice size of the network and the handle differ");
+    if (v.stream != a->stream) return fail_ar(CRBM_EINVAL, "handle and network must use the same stream");
+    const int64_t n = v.n_chains, N = (int64_t)v.L * v.L;
+    hipStream_t st = a->stream;
+    if (n > a->mcap) {
+        void* ps[] = {a->cur, a->prop, a->ccur, a->cprop, a->lqc, a->lqp, a->nacc};
+        for (void* p : ps)
+            if (p) (void)hipFree(p);
+        if (alloc(&a->cur, n * N) || alloc(&a->prop, n * N) || alloc(&a->ccur, n * 3) || alloc(&a->cprop, n * 3) ||
+            alloc(&a->lqc, n) || alloc(&a->lqp, n) || alloc(&a->nacc, 1)) {
+            a->mcap = 0;
+            return fail_ar(CRBM_ENOMEM, "MH buffers");
+        }
+        a->mcap = n;
+    }
+    AR_TRY(hipMemsetAsync(a->nacc, 0, sizeof(unsigned long long), st), "zero counter");
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    for (int64_t cyc = 0; cyc < n_cycles; ++cyc) {
+        if (gibbs_per_mh > 0) {
+            const int rc = crbm_sample(h, gibbs_per_mh, nullptr, nullptr);
+            if (rc != CRBM_OK) return rc;
+        }
+        int rc = CRBM_OK;
+        // the current state changes only by MH itself when no Gibbs sweeps
+        // are interleaved; then its counts and log q carry over
+        if (cyc == 0 || gibbs_per_mh > 0) {
+            if (handle_view(h, &v) != CRBM_OK) return fail_ar(CRBM_EINVAL, "bad handle");
+            AR_TRY(launch_unpack(v.state, a->cur, n, v.L, st), "unpack state");
+            hipLaunchKernelGGL(counts_int8_kernel, dim3(nb), dim3(256), 0, st, a->cur, n, v.L, a->ccur);
+            rc = run_score(a, n, a->cur, a->lqc);
+            if (rc != CRBM_OK) return rc;
+        }
+        const uint32_t step = (uint32_t)(a->mh_step++);
+        rc = run_seq(a, n, a->prop, a->lqp, v.seed, step, v.id);
+        if (rc != CRBM_OK) return rc;
+        hipLaunchKernelGGL(counts_int8_kernel, dim3(nb), dim3(256), 0, st, a->prop, n, v.L, a->cprop);
+        hipLaunchKernelGGL(mh_kernel, dim3(nb), dim3(256), 0, st, n, v.L, a->cur, a->prop, a->ccur, a->cprop, a->lqc,
+                           a->lqp, v.a, v.c1, v.c2, v.sg1, v.sg2, v.seed, step, v.id, a->nacc);
+        AR_TRY(launch_pack(v.state, a->cur, n, v.L, st), "pack state");
+        if (counts_trace)
+            AR_TRY(hipMemcpyAsync(counts_trace + cyc * n * 3, a->ccur, sizeof(int32_t) * n * 3, hipMemcpyDeviceToDevice, st),
+                   "trace");
+        AR_TRY(hipGetLastError(), "MH kernels");
+    }
+    if (n_accepted) {
+        unsigned long long acc = 0;
+        AR_TRY(hipMemcpyAsync(&acc, a->nacc, sizeof(acc), hipMemcpyDeviceToHost, st), "copy counter");
+        AR_TRY(hipStreamSynchronize(st), "synchronize");
+        *n_accepted = (int64_t)acc;
+    }
+    return CRBM_OK;
+}
+
+}  // extern "C"

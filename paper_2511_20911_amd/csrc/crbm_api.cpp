@@ -21,8 +21,15 @@
 using namespace crbmlib;
 
 namespace {
-
 thread_local std::string g_err;
+}
+
+int crbmlib::set_error(int code, const char* msg) {
+    g_err = msg ? msg : "";
+    return code;
+}
+
+namespace {
 
 int fail(int code, const std::string& msg) {
     g_err = msg;
@@ -229,6 +236,29 @@ int build_graph(crbm_s* h) {
 }
 
 }  // namespace
+
+int crbmlib::handle_view(crbm_t* h, HandleView* v) {
+    if (!h || !v) return CRBM_EINVAL;
+    const crbm_instance& I = h->inst[0];
+    v->state = h->d_state + h->state_off[0];
+    v->L = I.L;
+    v->n_chains = I.n_chains;
+    v->id = I.id;
+    v->seed = h->cfg.seed;
+    v->n_inst = (int)h->inst.size();
+    v->sched_kind = I.sched_kind;
+    v->T0 = I.T0;
+    v->cur = h->cur;
+    v->S = h->S;
+    v->stream = h->stream;
+    int64_t wq1, wq2;
+    hidden_weight(h->Jq[0][0], I.T0, &wq1, &v->sg1);
+    hidden_weight(h->Jq[1][0], I.T0, &wq2, &v->sg2);
+    v->a = (double)llround((double)h->Jq[2][0] / I.T0) / 65536.0;
+    v->c1 = log(cosh(2.0 * (double)wq1 / 65536.0));
+    v->c2 = log(cosh(2.0 * (double)wq2 / 65536.0));
+    return CRBM_OK;
+}
 
 extern "C" {
 

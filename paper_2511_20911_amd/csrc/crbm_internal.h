@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "crbm.h"
+
 namespace crbmlib {
 
 // Words per sweep in the device table of one instance:
@@ -46,6 +48,27 @@ struct GibbsArgs {
     int32_t waves_per_block;  // 1..4 (0 = 4)
     int32_t grid_blocks;      // persistent mode: blocks in the grid
 };
+
+// What the learned-proposal code needs from a Gibbs handle.
+struct HandleView {
+    uint32_t* state;   // bit rows of the handle's first instance
+    int L;
+    int64_t n_chains;
+    uint32_t id;
+    uint64_t seed;
+    int n_inst;
+    int sched_kind;
+    double T0;
+    int64_t cur, S;
+    hipStream_t stream;
+    // MH target: log pi = a M + c1 n1 + c2 n2 (+ const) at the constant temperature
+    double a, c1, c2;
+    int sg1, sg2;
+};
+int handle_view(crbm_t* h, HandleView* v);
+
+// Records the message returned by crbm_last_error() on this thread; returns code.
+int set_error(int code, const char* msg);
 
 // Lanes per chain for a lattice side and a number of cell rows per lane.
 inline int lanes_per_chain(int L, int R) { return (L / 2) / R; }

@@ -1,0 +1,128 @@
+// stats.hip -- integrated autocorrelation time and effective sample size of
+// an observable of the per-sweep counts trace, for the ESS/s comparison of
+// samplers (the paper itself reports time-to-solution, Sec. III.C Eq. (14)).
+//
+// O[t][c] = wM M + wB1 B1 + wB2 B2 from the trace record (M, B1, B2) of chain
+// c at sample t.  Per chain the mean is removed; the autocovariance at lag k
+// is summed over chains and samples in fp64 and normalised by (n - k); the
+// host turns it into rho(k) and applies the automatic window.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "crbm.h"
+#include "crbm_internal.h"
+
+namespace crbmlib {
+namespace {
+
+// one thread per chain: mean of O over samples [discard, n)
+__global__ void chain_mean_kernel(const int32_t* trace, int64_t n, int64_t stride_chains, int64_t c0, int64_t nc,
+                                  int64_t discard, double w0, double w1, double w2, double* mean) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    double s = 0.0;
+    for (int64_t t = discard; t < n; ++t) {
+        const int32_t* r = trace + (t * stride_chains + c0 + c) * 3;
+        s += w0 * r[0] + w1 * r[1] + w2 * r[2];
+    }
+    mean[c] = s / (double)(n - discard);
+}
+
+// centred series, layout [t][c] so that consecutive threads read consecutive words
+__global__ void centre_kernel(const int32_t* trace, int64_t n, int64_t stride_chains, int64_t c0, int64_t nc,
+                              int64_t discard, double w0, double w1, double w2, const double* mean, double* x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t m = n - discard;
+    if (i >= m * nc) return;
+    const int64_t t = i / nc, c = i % nc;
+    const int32_t* r = trace + ((t + discard) * stride_chains + c0 + c) * 3;
+    x[i] = w0 * r[0] + w1 * r[1] + w2 * r[2] - mean[c];
+}
+
+// block (lag k, chain block b): partial[k][b] = sum over its chains and t of x[t] x[t+k]
+__global__ void __launch_bounds__(256) autocov_kernel(const double* x, int64_t m, int64_t nc, int max_lag,
+                                                      double* partial, int nblk) {
+    const int k = blockIdx.x;
+    const int b = blockIdx.y;
+    const int64_t c = (int64_t)b * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (c < nc)
+        for (int64_t t = 0; t + k < m; ++t) s += x[t * nc + c] * x[(t + k) * nc + c];
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(int64_t)k * nblk + b] = red[0];
+    (void)max_lag;
+}
+
+}  // namespace
+}  // namespace crbmlib
+
+using namespace crbmlib;
+
+extern "C" int crbm_tau_int(const int32_t* trace_dev, int64_t n_samples, int64_t trace_chains, int64_t c0,
+                            int64_t c1, int64_t discard, const double w[3], int32_t max_lag, double c_window,
+                            void* stream, double* tau_out, double* ess_out, int32_t* window_out,
+                            double* rho_out) {
+    if (!trace_dev || !w || !tau_out || n_samples < 2 || trace_chains < 1 || c0 < 0 || c1 > trace_chains ||
+        c1 <= c0 || discard < 0 || n_samples - discard < 2 || max_lag < 1 || !(c_window > 0.0))
+        return set_error(CRBM_EINVAL, "crbm_tau_int: bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nc = c1 - c0, m = n_samples - discard;
+    const int K = (int)std::min<int64_t>(max_lag, m - 1);
+    double *d_mean = nullptr, *d_x = nullptr, *d_part = nullptr;
+    const int nblk = (int)((nc + 255) / 256);
+    if (hipMalloc(&d_mean, sizeof(double) * nc) != hipSuccess) return set_error(CRBM_ENOMEM, "hipMalloc");
+    if (hipMalloc(&d_x, sizeof(double) * m * nc) != hipSuccess) {
+        (void)hipFree(d_mean);
+        return set_error(CRBM_ENOMEM, "hipMalloc");
+    }
+    if (hipMalloc(&d_part, sizeof(double) * (int64_t)(K + 1) * nblk) != hipSuccess) {
+        (void)hipFree(d_mean);
+        (void)hipFree(d_x);
+        return set_error(CRBM_ENOMEM, "hipMalloc");
+    }
+    hipLaunchKernelGGL(chain_mean_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, trace_dev,
+                       n_samples, trace_chains, c0, nc, discard, w[0], w[1], w[2], d_mean);
+    hipLaunchKernelGGL(centre_kernel, dim3((unsigned)((m * nc + 255) / 256)), dim3(256), 0, st, trace_dev,
+                       n_samples, trace_chains, c0, nc, discard, w[0], w[1], w[2], d_mean, d_x);
+    hipLaunchKernelGGL(autocov_kernel, dim3((unsigned)(K + 1), (unsigned)nblk), dim3(256), 0, st, d_x, m, nc, K,
+                       d_part, nblk);
+    std::vector<double> part((size_t)(K + 1) * nblk);
+    hipError_t e = hipMemcpyAsync(part.data(), d_part, sizeof(double) * part.size(), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d_mean);
+    (void)hipFree(d_x);
+    (void)hipFree(d_part);
+    if (e != hipSuccess) return set_error(CRBM_EHIP, hipGetErrorString(e));
+    std::vector<double> gam(K + 1);
+    for (int k = 0; k <= K; ++k) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += part[(size_t)k * nblk + b];
+        gam[k] = s / (double)(m - k) / (double)nc;
+    }
+    double tau = 1.0;
+    int W = K;
+    if (gam[0] > 0.0) {
+        for (int k = 1; k <= K; ++k) {
+            tau += 2.0 * gam[k] / gam[0];
+            if ((double)k >= c_window * tau) {
+                W = k;
+                break;
+            }
+        }
+    }
+    if (rho_out)
+        for (int k = 0; k <= K; ++k) rho_out[k] = gam[0] > 0.0 ? gam[k] / gam[0] : (k == 0 ? 1.0 : 0.0);
+    *tau_out = tau;
+    if (ess_out) *ess_out = (double)nc * (double)m / tau;
+    if (window_out) *window_out = W;
+    set_error(CRBM_OK, "");
+    return CRBM_OK;
+}
