@@ -161,10 +161,12 @@ int crbm_get_tiling(int32_t L, int32_t* rows, int32_t* waves_per_block);
  * observable O = w[0] M + w[1] B1 + w[2] B2 (e.g. the energy with
  * w = (-hq, J1q, J2q)) over a counts trace written by crbm_sample
  * (trace_dev: device, int32 [n_samples][trace_chains][3]), for chains
- * [c0, c1), after dropping the first `discard` samples.  With per-chain means
- * removed, Gamma(k) = sum over chains and t of x_t x_{t+k} / ((n - k) n_chains),
- * rho(k) = Gamma(k)/Gamma(0), tau_int = 1 + 2 sum_{k=1}^{W} rho(k) with the
- * automatic window W = min{W : W >= c_window tau_int(W)} (Sokal), and
+ * [c0, c1), after dropping the first `discard` samples.  With the grand mean
+ * over all kept samples removed (chains stuck at different levels then count
+ * as correlated, not as independent), Gamma(k) = sum over chains and t of
+ * x_t x_{t+k} / ((n - k) n_chains), rho(k) = Gamma(k)/Gamma(0),
+ * tau_int = 1 + 2 sum_{k=1}^{W} rho(k) with the automatic window
+ * W = min{W : W >= c_window tau_int(W)} (Sokal), else the largest lag, and
  * ESS = n_chains (n_samples - discard) / tau_int.  rho_out (host, may be NULL)
  * receives rho(0..min(max_lag, n-discard-1)).  Synchronises `stream`. */
 int crbm_tau_int(const int32_t* trace_dev, int64_t n_samples, int64_t trace_chains, int64_t c0, int64_t c1,

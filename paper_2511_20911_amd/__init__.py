@@ -163,7 +163,7 @@ def autotune(L: int, n_chains: int = 4096, n_sweeps: int = 50, stream=None):
 
 
 def tau_int(trace, weights, c0: int = 0, c1: Optional[int] = None, discard: int = 0, max_lag: int = 2000,
-            c_window: float = 5.0, stream=None):
+            c_window: float = 6.0, stream=None):
     """tau_int, ESS, window and rho(k) of O = w0 M + w1 B1 + w2 B2 over a
     device counts trace [n_samples, chains, 3] (int32)."""
     assert trace.is_cuda and trace.dim() == 3 and trace.shape[2] == 3 and trace.element_size() == 4

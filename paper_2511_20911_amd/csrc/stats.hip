@@ -3,9 +3,11 @@
 // samplers (the paper itself reports time-to-solution, Sec. III.C Eq. (14)).
 //
 // O[t][c] = wM M + wB1 B1 + wB2 B2 from the trace record (M, B1, B2) of chain
-// c at sample t.  Per chain the mean is removed; the autocovariance at lag k
-// is summed over chains and samples in fp64 and normalised by (n - k); the
-// host turns it into rho(k) and applies the automatic window.
+// c at sample t.  The grand mean over chains and kept samples is removed, so
+// that chains stuck at different levels appear as correlation that does not
+// decay; the autocovariance at lag k is summed over chains and samples in
+// fp64 and normalised by (n - k); the host turns it into rho(k) and applies
+// the automatic window.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,15 +32,29 @@ __global__ void chain_mean_kernel(const int32_t* trace, int64_t n, int64_t strid
     mean[c] = s / (double)(n - discard);
 }
 
+// one block: grand mean = mean of the per-chain means (equal sample counts)
+__global__ void __launch_bounds__(256) grand_mean_kernel(const double* mean, int64_t nc, double* gm) {
+    double s = 0.0;
+    for (int64_t c = threadIdx.x; c < nc; c += blockDim.x) s += mean[c];
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *gm = red[0] / (double)nc;
+}
+
 // centred series, layout [t][c] so that consecutive threads read consecutive words
 __global__ void centre_kernel(const int32_t* trace, int64_t n, int64_t stride_chains, int64_t c0, int64_t nc,
-                              int64_t discard, double w0, double w1, double w2, const double* mean, double* x) {
+                              int64_t discard, double w0, double w1, double w2, const double* gm, double* x) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t m = n - discard;
     if (i >= m * nc) return;
     const int64_t t = i / nc, c = i % nc;
     const int32_t* r = trace + ((t + discard) * stride_chains + c0 + c) * 3;
-    x[i] = w0 * r[0] + w1 * r[1] + w2 * r[2] - mean[c];
+    x[i] = w0 * r[0] + w1 * r[1] + w2 * r[2] - *gm;
 }
 
 // block (lag k, chain block b): partial[k][b] = sum over its chains and t of x[t] x[t+k]
@@ -78,7 +94,7 @@ extern "C" int crbm_tau_int(const int32_t* trace_dev, int64_t n_samples, int64_t
     const int K = (int)std::min<int64_t>(max_lag, m - 1);
     double *d_mean = nullptr, *d_x = nullptr, *d_part = nullptr;
     const int nblk = (int)((nc + 255) / 256);
-    if (hipMalloc(&d_mean, sizeof(double) * nc) != hipSuccess) return set_error(CRBM_ENOMEM, "hipMalloc");
+    if (hipMalloc(&d_mean, sizeof(double) * (nc + 1)) != hipSuccess) return set_error(CRBM_ENOMEM, "hipMalloc");
     if (hipMalloc(&d_x, sizeof(double) * m * nc) != hipSuccess) {
         (void)hipFree(d_mean);
         return set_error(CRBM_ENOMEM, "hipMalloc");
@@ -90,8 +106,9 @@ extern "C" int crbm_tau_int(const int32_t* trace_dev, int64_t n_samples, int64_t
     }
     hipLaunchKernelGGL(chain_mean_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, trace_dev,
                        n_samples, trace_chains, c0, nc, discard, w[0], w[1], w[2], d_mean);
+    hipLaunchKernelGGL(grand_mean_kernel, dim3(1), dim3(256), 0, st, d_mean, nc, d_mean + nc);
     hipLaunchKernelGGL(centre_kernel, dim3((unsigned)((m * nc + 255) / 256)), dim3(256), 0, st, trace_dev,
-                       n_samples, trace_chains, c0, nc, discard, w[0], w[1], w[2], d_mean, d_x);
+                       n_samples, trace_chains, c0, nc, discard, w[0], w[1], w[2], d_mean + nc, d_x);
     hipLaunchKernelGGL(autocov_kernel, dim3((unsigned)(K + 1), (unsigned)nblk), dim3(256), 0, st, d_x, m, nc, K,
                        d_part, nblk);
     std::vector<double> part((size_t)(K + 1) * nblk);

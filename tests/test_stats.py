@@ -28,11 +28,29 @@ def test_ar1_closed_form(phi):
     assert abs(ess - 64 * 4000 / tau) < 1e-6
 
 
-def test_constant_chain_means_removed():
-    x = _ar1(0.3, 500, 8, 1) + np.arange(8)[None, :] * 100.0  # per-chain offsets must not matter
-    tau1 = stats.tau_int(x)[0]
-    tau2 = stats.tau_int(x - np.arange(8)[None, :] * 100.0)[0]
-    assert abs(tau1 - tau2) < 1e-9
+def test_chains_at_different_levels_count_as_correlated():
+    """Chains frozen at different constants (a non-ergodic sampler): rho(k) = 1
+    at every lag, the window never closes, tau_int = 1 + 2 max_lag."""
+    x = np.ones((300, 8)) * np.arange(8)[None, :]
+    tau, ess, W, rho = stats.tau_int(x, max_lag=100)
+    assert np.allclose(rho, 1.0)
+    assert W == 100 and abs(tau - 201.0) < 1e-9
+
+
+def test_offsets_enter_through_the_grand_mean():
+    """AR(1) chains plus random per-chain offsets d_c: with the grand mean
+    removed, rho(k) = (phi^k s2 + v_d) / (s2 + v_d), where s2 = 1 / (1 - phi^2)
+    is the AR(1) variance and v_d the offsets' variance about their mean."""
+    phi, n, nc = 0.6, 4000, 400
+    rng = np.random.default_rng(5)
+    d = rng.standard_normal(nc) * 0.5
+    x = _ar1(phi, n, nc, 9) + d[None, :]
+    s2 = 1 / (1 - phi * phi)
+    vd = d.var()
+    rho = stats.autocorr(x)
+    for k in (1, 2, 5, 20):
+        exact = (phi ** k * s2 + vd) / (s2 + vd)
+        assert abs(rho[k] - exact) < 0.02, (k, rho[k], exact)
 
 
 @pytest.mark.gpu
