@@ -338,141 +338,196 @@ __global__ void pack_kernel(const float* th, __bf16* wf, __bf16* wb, float* bias
     if (t == 0 && b == 0) bias[l * C + a] = (a < co) ? th[off + (int64_t)T * ci * co + a] : 0.f;
 }
 
-// Sequential sampler / scorer: one wavefront per 32 chains; sites in raster
-// order; at each site all 12 layers are evaluated at that site only.  The
-// taps of a layer read (r-1, c-1..c+1) from hs[l] in global memory (written
-// during the previous row; one device-scope fence per row makes them visible),
-// (r, c-1) from an LDS copy of the previous site's activations of every layer,
-// and the centre from an LDS tile holding the current site's previous-layer
-// output.  The previous-row fragments of layer l+1 are loaded while layer l
-// computes.  Spin i is drawn as +1 iff u < sigmoid(logit) with u from Philox
-// stream 6.  The per-site arithmetic (tap and k order of the matrix-core
-// accumulation, bias, ReLU, residual, bf16 rounding) is that of conv32_kernel,
-// so the logits, and log q, equal those of a full forward pass bit for bit.
-__global__ void __launch_bounds__(64) seq_kernel(int64_t n_chains, int L, const __bf16* __restrict__ wf,
-                                                 const float* __restrict__ bias, __bf16* hs, int8_t* spins,
-                                                 double* logq, uint64_t seed, uint32_t step, uint32_t id) {
-    const int lane = threadIdx.x;
-    const int li = lane & 31, half = lane >> 5;
-    const int N = L * L;
-    const int64_t base = (int64_t)blockIdx.x * 32;
-    const bool valid = base + li < n_chains;
-    const int64_t cA = valid ? base + li : base;  // clamp reads of padding rows
-    // prev[buf][l][chain][ch]: activations h_l at the previous site (buf = site parity)
-    __shared__ __bf16 prev[2][NL][32 * C];
-    __shared__ __bf16 tile[32 * C];
-    const int64_t LS = (int64_t)n_chains * N * C;  // layer stride in hs
-    double lqr[16];                                // lanes 0 and 32: log q of 16 chains each
+// ------------------------------------------------------------------------
+// Sampling and scoring share one per-element arithmetic: for every output
+// (configuration, site, channel) the five taps are accumulated in order
+// (-1,-1), (-1,0), (-1,1), (0,-1), (0,0) by one 16x16x32 bf16 matrix-core
+// instruction each (all 32 input channels at once), starting from zero; then
+// bias, ReLU and the residual add in fp32 and one rounding to bf16.  The
+// logits of both paths are therefore bit-identical, and so is log q, which
+// logq_kernel sums from them.
+
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// hidden activation of one element: relu(z) for layer 1, h + relu(z) after
+__device__ __forceinline__ __bf16 hidden_out(bool first, float acc, float bias, __bf16 resid) {
+    const float z = acc + bias;
+    const float rz = z > 0.f ? z : 0.f;
+    return f2bf(first ? rz : bf2f(resid) + rz);
+}
+
+// Scorer layer: one wavefront per 16 pixels x 32 output channels.
+// 16x16x32 operand layout: A row = lane % 16 (pixel), k = 8 (lane / 16) + e;
+// B column = lane % 16 (channel within a 16-block), same k; D column
+// lane % 16, rows 4 (lane / 16) + v.
+__global__ void __launch_bounds__(256) conv16_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ Wl,
+                                                     const float* __restrict__ bias, int layer, int L, int64_t P,
+                                                     __bf16* __restrict__ out, float* __restrict__ logit) {
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, kg = lane >> 4;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const bool first = layer == 0, last = layer == NL - 1;
+    const Taps taps = taps_for_dev(layer);
+    bf16x8 Bf[NT][2];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) lqr[v] = 0.0;
-    for (int site = 0; site < N; ++site) {
-        const int r = site / L, c = site % L;
-        const int cur = site & 1, old = cur ^ 1;
-        if (c == 0) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");  // the previous row is visible
-        // previous-row fragments of layer 0
-        bf16x8 pr[3][2];
-        auto load_row = [&](int l, bf16x8 (&dst)[3][2]) {
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int t = 0; t < 3; ++t) {
-                const int rr = r - 1, cc = c - 1 + t;
-                const bool inside = rr >= 0 && cc >= 0 && cc < L;
+        for (int cb = 0; cb < 2; ++cb)
+            Bf[t][cb] = (t < taps.n) ? load8(Wl + ((int64_t)t * C + 16 * cb + r16) * C + kg * 8) : zero8();
+    const float bj0 = bias[r16], bj1 = bias[16 + r16];
+    const int64_t ntiles = (P + 15) / 16;
+    for (int64_t tile = w0; tile < ntiles; tile += nw) {
+        const int64_t p = tile * 16 + r16;
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int kh = 0; kh < 2; ++kh)
-                    dst[t][kh] = inside ? load8(hs + (int64_t)l * LS + (cA * N + rr * L + cc) * C + kh * 16 + half * 8)
-                                        : zero8();
-            }
-        };
-        load_row(0, pr);
-        for (int l = 0; l < NL; ++l) {
-            bf16x8 nx[3][2];
-            if (l + 1 < NL) load_row(l + 1, nx);
-            f32x16 acc;
+        for (int t = 0; t < NT; ++t) {
+            if (t >= taps.n) break;
+            const int64_t q = (p < P) ? shift_pixel(p, taps.dr[t], taps.dc[t], L) : -1;
+            const bf16x8 a = (q >= 0) ? load8(in + q * C + kg * 8) : zero8();
+            acc0 = mfma16(a, Bf[t][0], acc0);
+            if (!last) acc1 = mfma16(a, Bf[t][1], acc1);
+        }
 #pragma unroll
-            for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-            const __bf16* W = wf + (int64_t)l * NT * C * C;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                if (t == 4 && l == 0) break;  // mask A: no centre tap
-#pragma unroll
-                for (int kh = 0; kh < 2; ++kh) {
-                    bf16x8 a;
-                    if (t < 3)
-                        a = pr[t][kh];
-                    else if (t == 3)
-                        a = (c > 0) ? *reinterpret_cast<const bf16x8*>(&prev[old][l][li * C + kh * 16 + half * 8])
-                                    : zero8();
-                    else
-                        a = *reinterpret_cast<const bf16x8*>(&tile[li * C + kh * 16 + half * 8]);
-                    const bf16x8 b = load8(W + ((int64_t)t * C + li) * C + kh * 16 + half * 8);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-                }
-            }
-            const float bj = bias[l * C + li];
-            if (l < NL - 1) {
-                float hnew[16];
-#pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    const int i = 8 * (v >> 2) + 4 * half + (v & 3);
-                    const float z = acc[v] + bj;
-                    const float rz = z > 0.f ? z : 0.f;
-                    hnew[v] = (l == 0) ? rz : bf2f(tile[i * C + li]) + rz;
-                }
-                __builtin_amdgcn_wave_barrier();
-#pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    const int i = 8 * (v >> 2) + 4 * half + (v & 3);
-                    const __bf16 hb = f2bf(hnew[v]);
-                    tile[i * C + li] = hb;
-                    prev[cur][l + 1][i * C + li] = hb;
-                    if (base + i < n_chains) hs[(int64_t)(l + 1) * LS + ((base + i) * N + site) * C + li] = hb;
-                }
-                __builtin_amdgcn_wave_barrier();
+        for (int v = 0; v < 4; ++v) {
+            const int64_t pi = tile * 16 + 4 * kg + v;
+            if (pi >= P) continue;
+            if (last) {
+                if (r16 == 0) logit[pi] = acc0[v] + bj0;
             } else {
-                // logits live in column j = 0 (lanes 0 and 32)
-                if (li == 0) {
-#pragma unroll
-                    for (int v = 0; v < 16; ++v) {
-                        const int i = 8 * (v >> 2) + 4 * half + (v & 3);
-                        const int64_t ch = base + i;
-                        float s = 0.f;
-                        const float x = acc[v] + bj;
-                        if (ch < n_chains) {
-                            const gk::P4 u4 = gk::philox((uint32_t)site, step, (uint32_t)ch, (id << 3) | 6u,
-                                                         (uint32_t)seed, (uint32_t)(seed >> 32));
-                            const float u = (float)(u4.v[0] >> 8) * (1.0f / 16777216.0f);
-                            const float p = 1.f / (1.f + expf(-x));
-                            s = (u < p) ? 1.f : -1.f;
-                            spins[ch * N + site] = (int8_t)s;
-                            hs[(ch * N + site) * C] = f2bf(s);
-                            lqr[v] += -log1p(exp(-(double)(s * x)));
-                        }
-                        // the spin is layer 0's input at this site (channel 0; other channels stay 0)
-                        prev[cur][0][i * C] = f2bf(s);
-                    }
-                }
-                if (li != 0) {
-#pragma unroll
-                    for (int v = 0; v < 16; ++v) {
-                        const int i = 8 * (v >> 2) + 4 * half + (v & 3);
-                        prev[cur][0][i * C + li] = (__bf16)0.0f;
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
-            }
-            if (l + 1 < NL) {
-#pragma unroll
-                for (int t = 0; t < 3; ++t)
-#pragma unroll
-                    for (int kh = 0; kh < 2; ++kh) pr[t][kh] = nx[t][kh];
+                const int64_t o0 = pi * C + r16, o1 = o0 + 16;
+                out[o0] = hidden_out(first, acc0[v], bj0, first ? (__bf16)0.0f : in[o0]);
+                out[o1] = hidden_out(first, acc1[v], bj1, first ? (__bf16)0.0f : in[o1]);
             }
         }
     }
-    if (li == 0) {
+}
+
+// LDS rows of 32 bf16 channels with their four 16-byte groups XOR-swizzled
+// by the row index (spreads the 16-byte reads of a wavefront over the banks).
+__device__ __forceinline__ int swz(int row, int grp) { return row * C + ((grp ^ (row & 3)) << 3); }
+__device__ __forceinline__ int swz_el(int row, int ch) { return swz(row, ch >> 3) + (ch & 7); }
+
+constexpr int kSeqChains = 32;
+constexpr int kSeqLdsBytes = (NL * NT * C * C + NL * kSeqChains * C + 2 * kSeqChains * C) * 2 + kSeqChains * 4;
+
+// Ancestral sampler: a workgroup of four wavefronts draws 32 configurations
+// site by site in raster order.  Wavefront w computes chains 16 (w & 1) ..+15
+// times output channels 16 (w >> 1) ..+15 of every layer at the current
+// site; the layers are separated by workgroup barriers.  LDS holds all
+// weights (120 KB), the activations of every layer at the previous site
+// (the (0,-1) tap) and at the current site (the centre tap, double-buffered
+// by layer parity).  The three taps in the row above come from a two-row ring
+// in global memory, prefetched one site ahead.  Spin i is +1 iff u < sigmoid
+// (logit) with u the top 24 bits of Philox (ctr = (site, step, chain,
+// id << 3 | 6)); the logits go to logit_out for the log q sum.
+__global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int L, const __bf16* __restrict__ wf,
+                                                    const float* __restrict__ bias, __bf16* __restrict__ ring,
+                                                    int8_t* __restrict__ spins, float* __restrict__ logit_out,
+                                                    uint64_t seed, uint32_t step, uint32_t id) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __bf16* wl = reinterpret_cast<__bf16*>(smem);
+    __bf16* prev = wl + NL * NT * C * C;      // [NL][32 chains][C]: h_l at the previous site
+    __bf16* tile = prev + NL * kSeqChains * C;  // [2][32 chains][C]: h_l at the current site
+    float* xl = reinterpret_cast<float*>(tile + 2 * kSeqChains * C);  // [32] logits
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int chh = w & 1, coh = w >> 1;
+    const int r16 = lane & 15, kg = lane >> 4;
+    const int N = L * L;
+    const int64_t base = (int64_t)blockIdx.x * kSeqChains;
+    for (int g = tid; g < NL * NT * C * 4; g += blockDim.x) {
+        const int row = g >> 2, grp = g & 3;
+        *reinterpret_cast<bf16x8*>(wl + swz(row, grp)) = load8(wf + (int64_t)row * C + grp * 8);
+    }
+    for (int g = tid; g < NL * kSeqChains * 4; g += blockDim.x) *reinterpret_cast<bf16x8*>(prev + g * 8) = zero8();
+    const int oc = 16 * coh + r16;  // B column / D column: output channel of this lane
+    const int ca = 16 * chh + r16;  // A row: chain within the workgroup
+    const int64_t gca = (base + ca < n) ? base + ca : base;  // padding rows read a valid chain
+    float bj[NL];
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int i = 8 * (v >> 2) + 4 * half + (v & 3);
-            if (base + i < n_chains) logq[base + i] = lqr[v];
+    for (int l = 0; l < NL; ++l) bj[l] = bias[l * C + oc];
+    // ring element (layer, chain, row, column): [NL][n][2][L][C]
+    auto ridx = [&](int l, int64_t chain, int r, int c) -> int64_t {
+        return ((((int64_t)l * n + chain) * 2 + (r & 1)) * L + c) * C;
+    };
+    bf16x8 pr[NL][3];
+    auto fetch = [&](int l, int r, int c) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int cc = c - 1 + t;
+            const bool inside = r > 0 && cc >= 0 && cc < L;
+            pr[l][t] = inside ? load8(ring + ridx(l, gca, r - 1, cc) + kg * 8) : zero8();
         }
+    };
+#pragma unroll
+    for (int l = 0; l < NL; ++l) fetch(l, 0, 0);
+    __bf16 pend[NL][4];
+    __syncthreads();
+    for (int site = 0; site < N; ++site) {
+        const int r = site / L, c = site - r * L;
+        const int sn = site + 1, rn = sn / L, cn = sn - rn * L;
+        const bool more = sn < N;
+        float u = 0.f;
+        if (w == 0) {
+            const gk::P4 q = gk::philox((uint32_t)site, step, (uint32_t)(base + (lane & 31)), (id << 3) | 6u,
+                                        (uint32_t)seed, (uint32_t)(seed >> 32));
+            u = (float)(q.v[0] >> 8) * (1.0f / 16777216.0f);
+        }
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const __bf16* tl = tile + (l & 1) * kSeqChains * C;
+            __bf16* tn = tile + ((l + 1) & 1) * kSeqChains * C;
+            if (l < NL - 1 || coh == 0) {
+                const __bf16* Wl = wl + l * NT * C * C;
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int t = 0; t < 3; ++t) acc = mfma16(pr[l][t], load8(Wl + t * C * C + swz(oc, kg)), acc);
+                const bf16x8 a3 = (c > 0) ? load8(prev + l * kSeqChains * C + swz(ca, kg)) : zero8();
+                acc = mfma16(a3, load8(Wl + 3 * C * C + swz(oc, kg)), acc);
+                if (l > 0) acc = mfma16(load8(tl + swz(ca, kg)), load8(Wl + 4 * C * C + swz(oc, kg)), acc);
+                if (l < NL - 1) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int ci = 16 * chh + 4 * kg + v;
+                        const __bf16 hn =
+                            hidden_out(l == 0, acc[v], bj[l], l == 0 ? (__bf16)0.0f : tl[swz_el(ci, oc)]);
+                        tn[swz_el(ci, oc)] = hn;
+                        pend[l + 1][v] = hn;
+                        if (base + ci < n) ring[ridx(l + 1, base + ci, r, c) + oc] = hn;
+                    }
+                } else if (r16 == 0) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) xl[16 * chh + 4 * kg + v] = acc[v] + bj[l];
+                }
+            }
+            // every wavefront has read prev[l - 1] (before the last barrier): store this site's h_{l-1}
+            if (l >= 2) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) prev[(l - 1) * kSeqChains * C + swz_el(16 * chh + 4 * kg + v, oc)] = pend[l - 1][v];
+            }
+            if (more) fetch(l, rn, cn);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            prev[(NL - 1) * kSeqChains * C + swz_el(16 * chh + 4 * kg + v, oc)] = pend[NL - 1][v];
+        if (w == 0 && lane < kSeqChains) {
+            const int64_t ch = base + lane;
+            const float x = xl[lane];
+            const float p = 1.f / (1.f + expf(-x));
+            const float sg = (u < p) ? 1.f : -1.f;
+            prev[swz_el(lane, 0)] = f2bf(sg);  // layer-1 input at this site (channel 0; the rest stay 0)
+            if (ch < n) {
+                spins[ch * N + site] = (int8_t)sg;
+                logit_out[ch * N + site] = x;
+                ring[ridx(0, ch, r, c)] = f2bf(sg);
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -594,7 +649,8 @@ struct crbm_ar_s {
     int8_t* spins_copy = nullptr;
     // sequential sampler buffers (capacity in chains)
     int64_t scap = 0;
-    __bf16* shs = nullptr;      // [NL][n][N][C]
+    __bf16* ring = nullptr;     // [NL][n][2][L][C]: activations of the last two rows
+    float* slogit = nullptr;    // [n][N]
     // scoring buffers (capacity in chains): ping-pong activations and logits
     int64_t icap = 0;
     __bf16 *ih0 = nullptr, *ih1 = nullptr;  // [n N][C]
@@ -607,7 +663,7 @@ struct crbm_ar_s {
     unsigned long long* nacc = nullptr;
     ~crbm_ar_s() {
         void* ps[] = {theta, grad, m, v, bias, wf, wb, hs, mask, logit, g32, dh0, dh1, dz, g, logq, part, dW, bpart,
-                      spins_copy, shs, ih0, ih1, ilogit, cur, prop, ccur, cprop, lqc, lqp, nacc};
+                      spins_copy, ring, slogit, ih0, ih1, ilogit, cur, prop, ccur, cprop, lqc, lqp, nacc};
         for (void* p : ps)
             if (p) (void)hipFree(p);
     }
@@ -650,8 +706,11 @@ int ensure_train(crbm_ar_t* a, int64_t B) {
 
 int ensure_seq(crbm_ar_t* a, int64_t n) {
     if (n <= a->scap) return CRBM_OK;
-    if (a->shs) (void)hipFree(a->shs);
-    if (alloc(&a->shs, (int64_t)NL * n * a->L * a->L * C)) {
+    if (a->ring) (void)hipFree(a->ring);
+    if (a->slogit) (void)hipFree(a->slogit);
+    a->ring = nullptr;
+    a->slogit = nullptr;
+    if (alloc(&a->ring, (int64_t)NL * n * 2 * a->L * C) || alloc(&a->slogit, n * a->L * a->L)) {
         a->scap = 0;
         return fail_ar(CRBM_ENOMEM, "sampler buffers");
     }
@@ -731,12 +790,18 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B) {
 int run_seq(crbm_ar_t* a, int64_t n, int8_t* spins, double* logq, uint64_t seed, uint32_t step, uint32_t id) {
     int rc = ensure_seq(a, n);
     if (rc != CRBM_OK) return rc;
-    const int64_t N = (int64_t)a->L * a->L;
+    const int L = a->L;
     hipStream_t st = a->stream;
-    AR_TRY(hipMemsetAsync(a->shs, 0, sizeof(__bf16) * (size_t)n * N * C, st), "clear sampler input");
-    hipLaunchKernelGGL(seq_kernel, dim3((unsigned)((n + 31) / 32)), dim3(64), 0, st, n, a->L, a->wf, a->bias, a->shs,
-                       spins, logq, seed, step, id);
-    AR_TRY(hipGetLastError(), "sequential kernel");
+    // layer-1 input ring: channels 1..31 stay zero, channel 0 receives the spins
+    AR_TRY(hipMemsetAsync(a->ring, 0, sizeof(__bf16) * (size_t)n * 2 * L * C, st), "clear sampler input");
+    AR_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&seq16_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kSeqLdsBytes),
+           "sampler LDS size");
+    hipLaunchKernelGGL(seq16_kernel, dim3((unsigned)((n + kSeqChains - 1) / kSeqChains)), dim3(256), kSeqLdsBytes,
+                       st, n, L, a->wf, a->bias, a->ring, spins, a->slogit, seed, step, id);
+    hipLaunchKernelGGL(logq_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a->slogit, spins, n, L * L,
+                       logq);
+    AR_TRY(hipGetLastError(), "sampler kernels");
     return CRBM_OK;
 }
 
@@ -766,12 +831,11 @@ int run_score(crbm_ar_t* a, int64_t n, const int8_t* spins, double* logq) {
     hipLaunchKernelGGL(embed_kernel, dim3((unsigned)((P * C + 255) / 256)), dim3(256), 0, st, spins, P, a->ih0);
     __bf16* in = a->ih0;
     __bf16* out = a->ih1;
+    const int64_t tiles = (P + 15) / 16;
+    const int blocks = (int)std::min<int64_t>(4096, (tiles + 3) / 4);
     for (int l = 0; l < NL; ++l) {
-        const Taps tp = taps_for(l, false);
-        const __bf16* W = a->wf + (size_t)l * NT * C * C;
-        const int mode = (l == NL - 1) ? EP_LOGIT : (l == 0 ? EP_RELU : EP_RESID);
-        hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P)), dim3(256), 0, st, in, W, a->bias + l * C, tp, L, P,
-                           mode, in, (const float*)nullptr, out, (uint8_t*)nullptr, a->ilogit);
+        hipLaunchKernelGGL(conv16_kernel, dim3(blocks), dim3(256), 0, st, in, a->wf + (size_t)l * NT * C * C,
+                           a->bias + l * C, l, L, P, out, a->ilogit);
         std::swap(in, out);
     }
     hipLaunchKernelGGL(logq_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a->ilogit, spins, n, L * L,
