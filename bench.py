@@ -51,6 +51,26 @@ def instances(crbm, chains=CHAINS):
     return out
 
 
+def measured_traffic():
+    """HBM bytes per launch of the 18x18 Gibbs kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None once the kernel sources
+    differ from the ones that were profiled."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "gibbs_kernel_18x18_anneal_64pts.md")
+    h = hashlib.sha256()
+    for f in ("gibbs_kernel.h", "crbm_internal.h"):
+        with open(os.path.join(ROOT, "paper_2511_20911_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    try:
+        fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines()
+                      if line.startswith(("traffic_bytes_per_launch: ", "kernel_sources_sha256_12: ")))
+    except OSError:
+        return None
+    if fields.get("kernel_sources_sha256_12", "").strip() != h.hexdigest()[:12]:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(sample_points=3, chains_per_point=3):
     """The CPU oracle (single-threaded C) on a bounded sample of the same
     workload: the first chains of a few points, full schedule."""
@@ -100,6 +120,48 @@ def batched_uneven(crbm, torch):
             "tiling": {str(Lb): crbm.get_tiling(Lb) for Lb in sorted({p.L for p in pts})}}
 
 
+def learned_mh(crbm, torch, temps=(0.4, 0.2, 0.1), steps=800, cycles=500):
+    """Learned MH vs plain Gibbs at 18x18 on the 1/3 plateau (J2/J1 = 1, h/J1 = 3):
+    per temperature, train the 12-layer 32-channel proposal on 2^20 Gibbs
+    samples, then run 1 MH : 10 Gibbs sweeps on 8192 chains and plain Gibbs for
+    the same wall time from the same seeded start; energy ESS/s of both and
+    the bias of <E>/N against the exact transfer-matrix value."""
+    from paper_2511_20911_amd import learned
+    ref_path = os.path.join(ROOT, "tests", "golden", "plateau_reference.json")
+    with open(ref_path) as f:
+        ref = {v["T"]: v["E_per_spin"] for v in json.load(f)["values"] if v["L"] == 12}
+    out = {"workload": "SS Ising 18x18, J1=1, J2/J1=1.0, h/J1=3.0 (1/3 plateau); proposal: 12 masked 3x3 conv "
+                       "layers, 32 channels, bf16 weights, fp32 accumulation, trained on 2^20 Gibbs samples "
+                       "(4096 chains annealed 5->T over 2e4 sweeps, 256 snapshots 20 sweeps apart, translation "
+                       "and transpose augmentation); 8192 chains, 1 MH : 10 Gibbs vs plain Gibbs at equal wall "
+                       "time, seeded +-1 start, first 20% discarded",
+           "reference": "exact <E>/N by 12x12 row transfer matrix", "points": []}
+    for T in temps:
+        t0 = time.perf_counter()
+        data = learned.training_set(L, 1.0, 1.0, 3.0, T)
+        torch.cuda.synchronize()
+        t_data = time.perf_counter() - t0
+        net = crbm.ARNet(L, seed=5)
+        net.init_params(seed=5, scale=0.5)
+        t0 = time.perf_counter()
+        loss = learned.train(net, data, steps=steps)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        del data
+        r = learned.compare(net, L, 1.0, 1.0, 3.0, T, cycles=cycles)
+        for k in ("learned", "gibbs"):
+            d = r[k]["E_per_spin"] - ref[T]
+            # se = 0: every kept sample has the same energy; then report the bias only if it is not rounding
+            r[k]["bias_se"] = d / r[k]["se"] if r[k]["se"] > 0 else (0.0 if abs(d) < 1e-12 else None)
+        r.update({"T": T, "E_ref": ref[T], "data_s": t_data, "train_s": t_train, "train_steps": steps,
+                  "final_loss_per_site": loss,
+                  "ess_ratio": r["learned"]["ess_per_s"] / r["gibbs"]["ess_per_s"]})
+        out["points"].append(r)
+        del net
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,7 +172,10 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     ap.add_argument("--no-tune", action="store_true", help="skip the tiling autotuner")
+    ap.add_argument("--tiling", type=str, default="",
+                    help="R,W: use R cell rows per lane and W wavefronts per workgroup at 18x18 instead of tuning")
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch graph measurement")
+    ap.add_argument("--no-mh", action="store_true", help="skip the learned-MH vs Gibbs ESS comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the sampler's chains are independent and this build runs on a "
@@ -129,7 +194,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     tuning = None
-    if not args.no_tune:
+    if args.tiling:
+        r_, w_ = (int(x) for x in args.tiling.split(","))
+        crbm.set_tiling(L, r_, w_)
+    elif not args.no_tune:
         r, w, rate = crbm.autotune(L, n_chains=8192, n_sweeps=40)
         tuning = {"rows_per_lane": r, "waves_per_block": w, "tune_rate": rate}
     rows, wpb = crbm.get_tiling(L)
@@ -195,7 +263,8 @@ def main():
             "peak": ALU_PEAK_OPS / 1e12,
             "unit": "TOP/s",
             "frac": achieved / ALU_PEAK_OPS,
-            "traffic": None,
+            "traffic": measured_traffic() if n_sweeps == S else None,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
             "kernel": f"gibbs_kernel<{L},{rows}>",
             "kernel_ms": kms,
             "ops_per_spin_sweep": OPS_PER_SPIN_SWEEP,
@@ -208,6 +277,8 @@ def main():
                                  "m_mean": m.round(5).tolist()}
     if not args.no_batched:
         result["batched_uneven"] = batched_uneven(crbm, torch)
+    if not args.no_mh:
+        result["learned_mh"] = learned_mh(crbm, torch)
     if not args.no_cpu_baseline and n_sweeps == S:
         base, finals = cpu_baseline()
         result["cpu_baseline"] = base

@@ -125,6 +125,14 @@ int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cf
  * Returns CRBM_ESTATE if the schedule would be exceeded. */
 int crbm_sample(crbm_t* h, int64_t n_sweeps, int8_t* spins_out, int32_t* counts_trace);
 
+/* As crbm_sample, with the counts trace thinned: (M, B1, B2) is recorded
+ * after every trace_every-th sweep of this call only, layout
+ * [n_sweeps / trace_every][chain][3] (for autocorrelation estimates over long
+ * runs).  trace_every must be >= 1 and divide n_sweeps, else CRBM_EINVAL.
+ * crbm_sample is the case trace_every = 1. */
+int crbm_sample_thinned(crbm_t* h, int64_t n_sweeps, int8_t* spins_out, int32_t* counts_trace,
+                        int32_t trace_every);
+
 /* Synchronise the stream and fill out[n_inst] from the exact int64
  * accumulators.  corr_out: host pointer or NULL; if given, receives for each
  * instance the sum over its chains of C(dr,dc) = sum_{r,c} s(r,c) s(r+dr,c+dc)
@@ -204,6 +212,11 @@ int crbm_ar_create(const crbm_ar_config* c, crbm_ar_t** out);   /* parameters st
 int64_t crbm_ar_num_params(const crbm_ar_t* a);
 int crbm_ar_set_params(crbm_ar_t* a, const float* host, int64_t n); /* also resets the Adam state */
 int crbm_ar_get_params(crbm_ar_t* a, float* host, int64_t n);
+/* Seeded initial parameters: every weight N(0, sd^2) with sd = scale *
+ * sqrt(2 / fan-in) (fan-in = taps x input channels), times 0.1 in the logit
+ * layer, drawn by SplitMix64 + Box-Muller from `seed`; biases zero.  Resets
+ * the Adam state.  Synchronises.  CRBM_EINVAL for scale < 0. */
+int crbm_ar_init_params(crbm_ar_t* a, uint64_t seed, double scale);
 /* Gradient of the mean negative log-likelihood over a batch of samples
  * (device int8 +-1 [batch][L][L]); grad_host (may be NULL) receives it in the
  * parameter layout, loss_out (may be NULL) the loss.  Synchronises. */

@@ -83,6 +83,7 @@ def lib() -> ct.CDLL:
         p = ct.POINTER
         L.crbm_create.argtypes = [p(_Instance), ct.c_int32, p(_Config), p(ct.c_void_p)]
         L.crbm_sample.argtypes = [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p]
+        L.crbm_sample_thinned.argtypes = [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_int32]
         L.crbm_observables.argtypes = [ct.c_void_p, p(_Obs), ct.c_void_p]
         L.crbm_get_state.argtypes = [ct.c_void_p, ct.c_void_p, p(ct.c_int64)]
         L.crbm_set_state.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64]
@@ -104,6 +105,7 @@ def lib() -> ct.CDLL:
         L.crbm_ar_num_params.restype = ct.c_int64
         L.crbm_ar_set_params.argtypes = [ct.c_void_p, p(ct.c_float), ct.c_int64]
         L.crbm_ar_get_params.argtypes = [ct.c_void_p, p(ct.c_float), ct.c_int64]
+        L.crbm_ar_init_params.argtypes = [ct.c_void_p, ct.c_uint64, ct.c_double]
         L.crbm_ar_grad.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64, p(ct.c_float), p(ct.c_double)]
         L.crbm_ar_train_step.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_float, p(ct.c_double)]
         L.crbm_ar_logq.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p]
@@ -241,16 +243,19 @@ class Sampler:
     def total_spins(self) -> int:
         return int(self.spin_offsets[-1])
 
-    def sample(self, n_sweeps: int, spins_out=None, trace=None):
+    def sample(self, n_sweeps: int, spins_out=None, trace=None, trace_every: int = 1):
         """Enqueue n_sweeps sweeps.  spins_out: int8 CUDA tensor of total_spins
-        elements; trace: int32 CUDA tensor [n_sweeps, total_chains, 3]."""
+        elements; trace: int32 CUDA tensor [n_sweeps // trace_every, total_chains, 3]
+        recording the counts after every trace_every-th sweep."""
         if spins_out is not None:
             assert spins_out.is_cuda and spins_out.dtype.itemsize == 1 and spins_out.numel() == self.total_spins
         if trace is not None:
-            assert trace.is_cuda and trace.numel() == n_sweeps * self.total_chains * 3 and trace.element_size() == 4
-        _check(lib().crbm_sample(self._h, n_sweeps,
-                                 ct.c_void_p(spins_out.data_ptr()) if spins_out is not None else None,
-                                 ct.c_void_p(trace.data_ptr()) if trace is not None else None))
+            assert trace.is_cuda and trace.element_size() == 4
+            assert trace.numel() == (n_sweeps // trace_every) * self.total_chains * 3
+        _check(lib().crbm_sample_thinned(self._h, n_sweeps,
+                                         ct.c_void_p(spins_out.data_ptr()) if spins_out is not None else None,
+                                         ct.c_void_p(trace.data_ptr()) if trace is not None else None,
+                                         int(trace_every)))
 
     def observables(self, corr: bool = False):
         obs = (_Obs * len(self.instances))()
@@ -322,6 +327,10 @@ class ARNet:
         a = np.ascontiguousarray(flat, np.float32)
         assert a.size == self.num_params
         _check(lib().crbm_ar_set_params(self._h, a.ctypes.data_as(ct.POINTER(ct.c_float)), a.size))
+
+    def init_params(self, seed: int, scale: float = 0.5):
+        """Seeded fan-in-scaled normal weights, zero biases (library-side)."""
+        _check(lib().crbm_ar_init_params(self._h, int(seed), float(scale)))
 
     def get_params(self) -> np.ndarray:
         a = np.zeros(self.num_params, np.float32)

@@ -893,6 +893,34 @@ int crbm_ar_set_params(crbm_ar_t* a, const float* host, int64_t n) {
     return CRBM_OK;
 }
 
+int crbm_ar_init_params(crbm_ar_t* a, uint64_t seed, double scale) {
+    if (!a || !(scale >= 0.0)) return fail_ar(CRBM_EINVAL, "bad arguments");
+    // N(0, std^2) by SplitMix64 + Box-Muller; std = scale sqrt(2 / fan-in),
+    // times 0.1 for the logit layer; biases zero
+    std::vector<float> th((size_t)a->np, 0.f);
+    uint64_t x = seed;
+    auto next = [&]() {
+        x += 0x9E3779B97F4A7C15ull;
+        uint64_t z = x;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    auto normal = [&]() {
+        const double u1 = ((next() >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+        const double u2 = (next() >> 11) * (1.0 / 9007199254740992.0);
+        return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+    };
+    size_t off = 0;
+    for (int l = 0; l < NL; ++l) {
+        const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
+        const double sd = scale * std::sqrt(2.0 / (T * ci)) * (l == NL - 1 ? 0.1 : 1.0);
+        for (int k = 0; k < T * ci * co; ++k) th[off + k] = (float)(sd * normal());
+        off += (size_t)T * ci * co + co;
+    }
+    return crbm_ar_set_params(a, th.data(), a->np);
+}
+
 int crbm_ar_get_params(crbm_ar_t* a, float* host, int64_t n) {
     if (!a || !host || n != a->np) return fail_ar(CRBM_EINVAL, "parameter count mismatch");
     AR_TRY(hipMemcpyAsync(host, a->theta, sizeof(float) * n, hipMemcpyDeviceToHost, a->stream), "copy params");

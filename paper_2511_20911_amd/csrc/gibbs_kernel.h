@@ -440,7 +440,8 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
             for (int w = 0; w < W; ++w) Q[x][w] = Q[x + 1][w];
 
         const bool meas = a.measure_every > 0 && s >= a.burn_in && ((s - a.burn_in) % a.measure_every) == 0;
-        if (meas || a.trace) {
+        const bool rec = a.trace != nullptr && ((s - a.s0 + 1) % a.trace_every) == 0;
+        if (meas || rec) {
             uint32_t nb[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) nb[w] = __shfl(Q[0][w], nxt);  // new first row of the next band
@@ -472,8 +473,8 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
                 t2 += __shfl(dis2, src);
             }
             const int64_t M = 2 * tp - N, B1 = 2 * N - 2 * t1, B2 = N / 2 - 2 * t2;
-            if (a.trace && g == 0 && active) {
-                int32_t* tr = a.trace + ((uint64_t)(s - a.s0) * (uint64_t)a.total_chains + gch) * 3;
+            if (rec && g == 0 && active) {
+                int32_t* tr = a.trace + ((uint64_t)((s - a.s0) / a.trace_every) * (uint64_t)a.total_chains + gch) * 3;
                 tr[0] = (int32_t)M;
                 tr[1] = (int32_t)B1;
                 tr[2] = (int32_t)B2;

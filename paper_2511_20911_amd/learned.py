@@ -1,0 +1,150 @@
+"""Learned independent-Metropolis-Hastings proposal: training set, training
+loop and the comparison with plain Gibbs sampling.
+
+The proposal network, its training kernels and the MH step live in the HIP
+library (crbm_ar_* and crbm_sample_mh); this module only orchestrates them
+and moves data between device tensors:
+
+* training_set: configurations drawn by the library's own Gibbs sampler
+  (geometric anneal to the target temperature, then spaced snapshots at it);
+* augment: symmetries of the periodic Shastry-Sutherland lattice with the
+  dimer layout of Fig. 1a -- translations by two sites in either direction
+  and the transpose (r, c) -> (c, r), which maps the '\\' dimers of the
+  plaquettes (2i, 2j) and the '/' dimers of the plaquettes (2i+1, 2j+1) onto
+  themselves;
+* train: Adam steps of the library's fused forward / backward kernels on
+  random augmented mini-batches;
+* compare: learned MH (1 MH step per `gibbs_per_mh` Gibbs sweeps) against
+  plain Gibbs given the same wall-clock time, both from the same seeded start,
+  with tau_int / ESS of the energy from the library's estimator.
+
+The paper samples its CRBM by Gibbs only (Sec. II.B); the learned proposal is
+an addition that leaves the stationary law unchanged (exact MH acceptance on
+integer bond counts).
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+
+from . import ARNet, Instance, Sampler, sample_mh, tau_int
+
+
+def energy_weights(J1: float, J2: float, h: float):
+    """(w_M, w_B1, w_B2) such that w . (M, B1, B2) = H in 2^-16 units (16.16 couplings)."""
+    q = lambda x: int(round(x * 65536.0))
+    return (-q(h), q(J1), q(J2))
+
+
+def training_set(L, J1, J2, h, T, n_chains=4096, anneal_sweeps=20000, snapshots=256, spacing=20,
+                 seed=77, T_start=5.0, id=1):
+    """Gibbs samples at temperature T: a geometric anneal T_start -> T over
+    anneal_sweeps sweeps, then `snapshots` states of every chain spaced by
+    `spacing` sweeps at T.  Returns an int8 CUDA tensor [snapshots * n_chains, L, L]."""
+    import torch
+    N = L * L
+    ann = Sampler([Instance(L=L, J1=J1, J2=J2, h=h, n_chains=n_chains, sched="geometric", T0=T_start, T1=T,
+                            id=id)], seed=seed, n_sweeps=anneal_sweeps)
+    ann.sample(anneal_sweeps)
+    st, _ = ann.get_state()
+    fixed = Sampler([Instance(L=L, J1=J1, J2=J2, h=h, n_chains=n_chains, sched="const", T0=T, id=id)],
+                    seed=seed + 1, n_sweeps=snapshots * spacing)
+    fixed.set_state(st, 0)
+    out = torch.empty((snapshots, n_chains * N), dtype=torch.int8, device="cuda")
+    for k in range(snapshots):
+        fixed.sample(spacing, spins_out=out[k])
+    return out.view(-1, L, L)
+
+
+def augment(batch, gen):
+    """A random lattice symmetry (translation by an even vector, optional
+    transpose) applied to a whole batch [B, L, L]."""
+    import torch
+    L = batch.shape[1]
+    a = 2 * int(torch.randint(0, L // 2, (1,), generator=gen))
+    c = 2 * int(torch.randint(0, L // 2, (1,), generator=gen))
+    b = torch.roll(batch, shifts=(a, c), dims=(1, 2))
+    if int(torch.randint(0, 2, (1,), generator=gen)):
+        b = b.transpose(1, 2)
+    return b.contiguous()
+
+
+def train(net: ARNet, data, steps=800, batch=1024, lr=1e-3, lr_late=3e-4, late_from=0.625, seed=1):
+    """Maximum-likelihood training on random augmented mini-batches of `data`.
+    Returns the per-site loss of the last step."""
+    import torch
+    gen = torch.Generator()
+    gen.manual_seed(seed)
+    gidx = torch.Generator(device="cuda")
+    gidx.manual_seed(seed + 1)
+    N = data.shape[1] * data.shape[2]
+    loss = float("nan")
+    for it in range(steps):
+        idx = torch.randint(0, data.shape[0], (batch,), device="cuda", generator=gidx)
+        loss = net.train_step(augment(data[idx], gen), lr if it < late_from * steps else lr_late)
+    return loss / N
+
+
+@dataclass
+class ChainStats:
+    E_per_spin: float      # mean over chains and kept samples
+    se: float              # standard error from the spread of the chain means
+    tau: float             # integrated autocorrelation time (in samples)
+    ess: float             # effective sample size (chains x kept samples / tau)
+    seconds: float         # wall time of the sampling phase
+
+
+def _stats(trace, weights, N, discard, seconds, max_lag):
+    t = trace[discard:].double()
+    E = (weights[0] * t[..., 0] + weights[1] * t[..., 1] + weights[2] * t[..., 2]) / 65536.0 / N
+    cm = E.mean(0)
+    tau, ess, _, _ = tau_int(trace, weights, discard=discard, max_lag=max_lag)
+    return ChainStats(float(cm.mean()), float(cm.std() / math.sqrt(cm.numel())), tau, ess, seconds)
+
+
+def compare(net: ARNet, L, J1, J2, h, T, n_chains=8192, cycles=500, gibbs_per_mh=10, trace_every=50,
+            seed=123, id=0):
+    """Learned MH (cycles of gibbs_per_mh Gibbs sweeps + one MH step) against
+    plain Gibbs run for the same wall time, both from the same seeded start;
+    the first fifth of each run is discarded as burn-in.  Returns a dict with
+    both samplers' energy statistics and ESS per second."""
+    import torch
+    N = L * L
+    w = energy_weights(J1, J2, h)
+    inst = Instance(L=L, J1=J1, J2=J2, h=h, n_chains=n_chains, sched="const", T0=T, id=id)
+    mh = Sampler([inst], seed=seed, n_sweeps=max(1, cycles * gibbs_per_mh))
+    tr = torch.empty((cycles, n_chains, 3), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    acc = sample_mh(mh, net, cycles, gibbs_per_mh, trace=tr)
+    torch.cuda.synchronize()
+    t_mh = time.perf_counter() - t0
+    learned = _stats(tr, w, N, cycles // 5, t_mh, cycles // 2)
+    del tr, mh
+    # Gibbs sweep time at this size, then a run of the same wall time
+    probe = Sampler([inst], seed=seed, n_sweeps=1100)
+    probe.sample(100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    probe.sample(1000)
+    torch.cuda.synchronize()
+    per_sweep = (time.perf_counter() - t0) / 1000
+    del probe
+    n_s = max(10, int(t_mh / per_sweep) // trace_every)
+    sweeps = n_s * trace_every
+    gb = Sampler([inst], seed=seed, n_sweeps=sweeps)
+    trg = torch.empty((n_s, n_chains, 3), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gb.sample(sweeps, trace=trg, trace_every=trace_every)
+    torch.cuda.synchronize()
+    t_g = time.perf_counter() - t0
+    gibbs = _stats(trg, w, N, n_s // 5, t_g, n_s // 2)
+    return {
+        "learned": {"cycles": cycles, "gibbs_per_mh": gibbs_per_mh, "acceptance": acc / (cycles * n_chains),
+                    "ms_per_cycle": 1e3 * t_mh / cycles, **learned.__dict__,
+                    "ess_per_s": learned.ess / t_mh, "tau_unit": "MH cycles"},
+        "gibbs": {"sweeps": sweeps, "trace_every": trace_every, "us_per_sweep": 1e6 * per_sweep,
+                  **gibbs.__dict__, "ess_per_s": gibbs.ess / t_g, "tau_unit": f"{trace_every} sweeps"},
+    }

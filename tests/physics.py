@@ -75,67 +75,6 @@ def exact_averages(L, J1, J2, h, T, states=None):
     }
 
 
-# --------------------------------------------------------- transfer matrix
-
-def _row_states(L):
-    idx = np.arange(1 << L, dtype=np.int64)
-    bits = (idx[:, None] >> np.arange(L)[None, :]) & 1
-    return (2 * bits - 1).astype(np.int64)
-
-
-def transfer_parts(L, J1, J2, h):
-    """Row transfer energies.  Every bond joins two sites of one row or of two
-    consecutive rows, so the periodic lattice is a ring of rows.
-
-    e_row[a]      : horizontal J1 bonds and field of a row in state a;
-    e_even[a, b]  : bonds between an even row 2i (state a) and row 2i+1 (b):
-                    vertical J1 and the '\\' dimers (2i, 2j)-(2i+1, 2j+1);
-    e_odd[a, b]   : bonds between an odd row 2i+1 (a) and row 2i+2 (b):
-                    vertical J1 and the '/' dimers (2i+1, 2j+2)-(2i+2, 2j+1)."""
-    st = _row_states(L)
-    e_row = J1 * (st * np.roll(st, -1, 1)).sum(1) - h * st.sum(1)
-    vert = st @ st.T
-    e_even = J1 * vert + J2 * (st[:, 0::2] @ st[:, 1::2].T)
-    e_odd = J1 * vert + J2 * (np.roll(st, -2, 1)[:, 0::2] @ st[:, 1::2].T)
-    return st, e_row.astype(np.float64), e_even.astype(np.float64), e_odd.astype(np.float64)
-
-
-def tm_averages(L, J1, J2, h, T):
-    """Exact <E>/N and <m> of the periodic L x L lattice (row transfer matrix;
-    L <= 12)."""
-    st, e_row, e_even, e_odd = transfer_parts(L, J1, J2, h)
-    Ee = e_row[:, None] + e_even          # row 2i's own energy + link to row 2i+1
-    Eo = e_row[:, None] + e_odd
-    shift = min(Ee.min(), Eo.min())
-    Te = np.exp(-(Ee - shift) / T)
-    To = np.exp(-(Eo - shift) / T)
-    Mr = st.sum(1).astype(np.float64)
-    pair = Te @ To
-    nb = L // 2
-    P = np.linalg.matrix_power(pair, nb - 1)
-    Z = np.trace(P @ pair)
-    dE = (Te * Ee) @ To + Te @ (To * Eo)
-    dM = (Te * Mr[:, None]) @ To + Te @ (To * Mr[:, None])
-    N = L * L
-    return {"E": float(nb * np.trace(P @ dE) / Z / N), "m": float(nb * np.trace(P @ dM) / Z / N)}
-
-
-def tm_ground_energy(L, J1, J2, h):
-    """Exact ground-state energy per spin by a min-plus row transfer (L <= 8)."""
-    st, e_row, e_even, e_odd = transfer_parts(L, J1, J2, h)
-    Ee = e_row[:, None] + e_even
-    Eo = e_row[:, None] + e_odd
-    pair = _minplus(Ee, Eo)
-    D = pair
-    for _ in range(L // 2 - 1):
-        D = _minplus(D, pair)
-    return float(np.min(np.diag(D)) / (L * L))
-
-
-def _minplus(A, B):
-    return (A[:, :, None] + B[None, :, :]).min(axis=1)
-
-
 # ------------------------------------------------------- structure factor
 
 def structure_factor(corr_sum, n_samples, L):

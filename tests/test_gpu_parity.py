@@ -98,6 +98,33 @@ def test_mixed_sizes_in_one_handle():
         _check_chains(I, parts[k], tr, int(off[k]), seed, S, chains)
 
 
+@pytest.mark.parametrize("every", [1, 4, 25])
+def test_thinned_trace_is_every_kth_row(every):
+    """crbm_sample_thinned records (M, B1, B2) after sweeps k, 2k, ... of the
+    call: exactly rows k-1, 2k-1, ... of the oracle's per-sweep trace, across
+    two calls (the second starting mid-schedule); the spins are unchanged."""
+    seed, S = 0x5EED000000000004, 200
+    I = crbm.Instance(L=18, J1=1.0, J2=1.0, h=3.0, n_chains=40, sched="const", T0=0.4, id=9)
+    smp = crbm.Sampler([I], seed=seed, n_sweeps=S)
+    spins = torch.empty(smp.total_spins, dtype=torch.int8, device="cuda")
+    tr1 = torch.empty((100 // every, 40, 3), dtype=torch.int32, device="cuda")
+    tr2 = torch.empty((100 // every, 40, 3), dtype=torch.int32, device="cuda")
+    smp.sample(100, trace=tr1, trace_every=every)
+    smp.sample(100, spins_out=spins, trace=tr2, trace_every=every)
+    torch.cuda.synchronize()
+    got = np.concatenate([tr1.cpu().numpy(), tr2.cpu().numpy()])
+    sp = spins.cpu().numpy().reshape(40, 18, 18)
+    oi = _oi(I)
+    for ch in (0, 17, 39):
+        s, t, _ = oracle.run_chain(oi, S, seed, ch, 0, S, trace=True)
+        assert np.array_equal(sp[ch], s)
+        assert np.array_equal(got[:, ch, :], t[every - 1::every]), (every, ch)
+    with pytest.raises(crbm.CrbmError) as e:
+        smp2 = crbm.Sampler([I], seed=seed, n_sweeps=S)
+        smp2.sample(10, trace=torch.empty((3, 40, 3), dtype=torch.int32, device="cuda"), trace_every=3)
+    assert e.value.code == crbm.CRBM_EINVAL
+
+
 def test_batch_composition_invariance():
     """An instance gives the same chains alone or inside a batch (the random
     stream depends on the instance id, not on its position)."""

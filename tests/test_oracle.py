@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 import physics as P
+from oracle import exact as EX
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_facts.json")))
 
@@ -270,6 +271,22 @@ def test_gibbs_matches_exact_4x4(J2, h, T):
         assert abs(v.mean() - ref) < 4 * se + 1e-12, (v.mean(), ref, se)
 
 
+@pytest.mark.parametrize("J2,h,T", [(1.0, 3.0, 1.0), (0.5, 0.0, 0.7), (2.5, 1.0, 2.0), (1.5, -2.0, 0.4)])
+def test_transfer_matrix_equals_enumeration_4x4(J2, h, T):
+    """The row transfer matrix of oracle.exact reproduces brute-force
+    enumeration of all 2^16 states of the 4x4 lattice."""
+    tm = EX.tm_averages(4, 1.0, J2, h, T)
+    en = P.exact_averages(4, 1.0, J2, h, T)
+    assert abs(tm["E"] - en["E"]) < 1e-12 and abs(tm["m"] - en["m"]) < 1e-12
+
+
+def test_transfer_matrix_low_temperature_plateau():
+    """6x6 at (J2, h) = (1, 3): as T -> 0 the transfer matrix reaches the 1/3
+    plateau's closed form E/N = -2 J1/3 - J2/6 - h/3 = -11/6, m = 1/3."""
+    tm = EX.tm_averages(6, 1.0, 1.0, 3.0, 0.15)
+    assert abs(tm["E"] + 11.0 / 6.0) < 1e-9 and abs(tm["m"] - 1.0 / 3.0) < 1e-9
+
+
 def test_gibbs_matches_transfer_matrix_6x6():
     """The 1/3 plateau at J2 = 1, h = 3 (Sec. III.A) in equilibrium at 6x6:
     Gibbs averages agree with the exact transfer-matrix values."""
@@ -282,7 +299,7 @@ def test_gibbs_matches_transfer_matrix_6x6():
         tr = tr[burn:].astype(np.float64)
         E_means.append(((tr[:, 1] + tr[:, 2] - 3 * tr[:, 0]) / 36).mean())
         m_means.append(tr[:, 0].mean() / 36)
-    ex = P.tm_averages(6, 1.0, 1.0, 3.0, T)
+    ex = EX.tm_averages(6, 1.0, 1.0, 3.0, T)
     for vals, ref in ((E_means, ex["E"]), (m_means, ex["m"])):
         v = np.array(vals)
         se = v.std(ddof=1) / math.sqrt(len(v))
@@ -305,7 +322,7 @@ def test_annealing_reaches_paper_phases():
             if best is None or E < best[0]:
                 best = (E, s)
         E, s = best
-        assert abs(E - P.tm_ground_energy(L, 1.0, J2, h)) < 1e-12, pt
+        assert abs(E - EX.tm_ground_energy(L, 1.0, J2, h)) < 1e-12, pt
         if "m" in pt:
             assert abs(s.mean() - pt["m"]) < 1e-12, pt
         if pt["phase"] in ("neel", "dimer"):
@@ -324,8 +341,8 @@ def test_critical_point_closed_forms():
     neel = lambda J2, h: -2 + J2 / 2
     third = lambda J2, h: -2 / 3 - J2 / 6 - h / 3
     assert abs(neel(1.0, 2.0) - third(1.0, 2.0)) < 1e-15
-    assert abs(P.tm_ground_energy(6, 1.0, 1.0, 1.5) - neel(1.0, 1.5)) < 1e-12
-    assert abs(P.tm_ground_energy(6, 1.0, 1.0, 2.5) - third(1.0, 2.5)) < 1e-12
+    assert abs(EX.tm_ground_energy(6, 1.0, 1.0, 1.5) - neel(1.0, 1.5)) < 1e-12
+    assert abs(EX.tm_ground_energy(6, 1.0, 1.0, 2.5) - third(1.0, 2.5)) < 1e-12
 
 
 def test_philox_matches_rocrand_engine():
