@@ -120,6 +120,38 @@ def batched_uneven(crbm, torch):
             "tiling": {str(Lb): crbm.get_tiling(Lb) for Lb in sorted({p.L for p in pts})}}
 
 
+def scale_gibbs(crbm, torch, sizes=((48, 2000), (96, 500))):
+    """Plain Gibbs at 48x48 and 96x96: 64 (J2/J1, h, T) points clustered on the
+    T = 0 phase boundaries, 512 chains each, fixed T per point."""
+    from paper_2511_20911_amd import workloads
+    out = []
+    for Ls, sweeps in sizes:
+        pts = workloads.scale_points(Ls)
+        insts = [crbm.Instance(L=p.L, J1=p.J1, J2=p.J2, h=p.h, n_chains=p.n_chains, sched=p.sched, T0=p.T0,
+                               T1=p.T1, id=p.id) for p in pts]
+        crbm.autotune(Ls, n_chains=4096, n_sweeps=10)
+        smp = crbm.Sampler(insts, seed=workloads.SEED_SCALE, n_sweeps=sweeps + 20, measure_every=1,
+                           burn_in=20 + sweeps // 2)
+        smp.sample(20)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        smp.sample(sweeps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        obs = smp.observables()
+        out.append({"L": Ls, "points": len(pts), "chains": smp.total_chains, "sweeps": sweeps,
+                    "spin_updates_per_s": smp.total_chains * Ls * Ls * sweeps / (ms / 1e3), "ms": ms,
+                    "tiling": crbm.get_tiling(Ls),
+                    "E_per_spin_first4": [round(o["E_per_spin"], 5) for o in obs[:4]]})
+        del smp
+    return {"workload": "SS Ising 48x48 and 96x96, 64 points on the T=0 phase boundaries (offsets N(0,0.1)), "
+                        "T~logU[0.1,1] fixed, 512 chains each; measured over the second half of the sweeps",
+            "sizes": out}
+
+
 def learned_mh(crbm, torch, temps=(0.4, 0.2, 0.1), steps=800, cycles=500):
     """Learned MH vs plain Gibbs at 18x18 on the 1/3 plateau (J2/J1 = 1, h/J1 = 3):
     per temperature, train the 12-layer 32-channel proposal on 2^20 Gibbs
@@ -176,6 +208,7 @@ def main():
                     help="R,W: use R cell rows per lane and W wavefronts per workgroup at 18x18 instead of tuning")
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch graph measurement")
     ap.add_argument("--no-mh", action="store_true", help="skip the learned-MH vs Gibbs ESS comparison")
+    ap.add_argument("--no-scale", action="store_true", help="skip the 48x48 / 96x96 Gibbs measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the sampler's chains are independent and this build runs on a "
@@ -277,6 +310,8 @@ def main():
                                  "m_mean": m.round(5).tolist()}
     if not args.no_batched:
         result["batched_uneven"] = batched_uneven(crbm, torch)
+    if not args.no_scale:
+        result["scale"] = scale_gibbs(crbm, torch)
     if not args.no_mh:
         result["learned_mh"] = learned_mh(crbm, torch)
     if not args.no_cpu_baseline and n_sweeps == S:

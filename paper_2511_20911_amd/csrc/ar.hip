@@ -174,11 +174,28 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const __bf16* __restrict__ i
     for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[t][v] = 0.f;
+    const int64_t LL = (int64_t)L * L;
     for (int64_t k0 = p_begin; k0 < p_end; k0 += 16) {
+        // coordinates of this lane's 8 pixels: one division, then step along the row
+        const int64_t p0 = k0 + half * 8;
+        int rr[8], cc[8];
+        {
+            const int rc = (int)(p0 % LL);
+            int r = rc / L, c = rc - (rc / L) * L;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                rr[e] = r;
+                cc[e] = c;
+                if (++c == L) {
+                    c = 0;
+                    if (++r == L) r = 0;
+                }
+            }
+        }
         bf16x8 b;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const int64_t p = k0 + half * 8 + e;
+            const int64_t p = p0 + e;
             b[e] = (p < p_end) ? dz[p * C + li] : (__bf16)0.0f;
         }
 #pragma unroll
@@ -187,9 +204,10 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const __bf16* __restrict__ i
             bf16x8 a;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const int64_t p = k0 + half * 8 + e;
-                const int64_t q = (p < p_end) ? shift_pixel(p, taps.dr[t], taps.dc[t], L) : -1;
-                a[e] = (q >= 0) ? in[q * C + li] : (__bf16)0.0f;
+                const int64_t p = p0 + e;
+                const int r = rr[e] + taps.dr[t], c = cc[e] + taps.dc[t];
+                const bool ok = p < p_end && r >= 0 && r < L && c >= 0 && c < L;
+                a[e] = ok ? in[(p + (int64_t)taps.dr[t] * L + taps.dc[t]) * C + li] : (__bf16)0.0f;
             }
             acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
         }
@@ -412,6 +430,82 @@ __global__ void __launch_bounds__(256) conv16_kernel(const __bf16* __restrict__ 
 __device__ __forceinline__ int swz(int row, int grp) { return row * C + ((grp ^ (row & 3)) << 3); }
 __device__ __forceinline__ int swz_el(int row, int ch) { return swz(row, ch >> 3) + (ch & 7); }
 
+// Fused scorer: one workgroup of four wavefronts per configuration, all 12
+// layers with the activations of the whole lattice in LDS (two [N][32] bf16
+// buffers, rows XOR-swizzled), so only the spins are read and the logits
+// written.  Wavefront w takes the 16-pixel tiles w, w + 4, ... of each layer;
+// per tile it runs the same five 16x16x32 instructions per 16-channel block,
+// in the same order and with the same epilogue as conv16_kernel and the
+// sampler.  Used for L <= kFuseMaxL (LDS = 128 N bytes).
+constexpr int kFuseMaxL = 32;
+
+__global__ void __launch_bounds__(256) score_fused_kernel(int64_t n, int L, const int8_t* __restrict__ spins,
+                                                          const __bf16* __restrict__ wf,
+                                                          const float* __restrict__ bias,
+                                                          float* __restrict__ logit) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = L * L;
+    __bf16* buf0 = reinterpret_cast<__bf16*>(smem);
+    __bf16* buf1 = buf0 + N * C;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int r16 = lane & 15, kg = lane >> 4;
+    const int64_t b = blockIdx.x;
+    if (b >= n) return;  // uniform per workgroup
+    const int8_t* sp = spins + b * N;
+    for (int g = tid; g < N * 4; g += blockDim.x) {  // layer-1 input: spin in channel 0
+        const int p = g >> 2, grp = g & 3;
+        bf16x8 v = zero8();
+        if (grp == 0) v[0] = f2bf((float)sp[p]);
+        *reinterpret_cast<bf16x8*>(buf0 + swz(p, grp)) = v;
+    }
+    __syncthreads();
+    const int ntiles = (N + 15) / 16;
+    __bf16* in = buf0;
+    __bf16* out = buf1;
+    for (int l = 0; l < NL; ++l) {
+        const bool first = l == 0, last = l == NL - 1;
+        const Taps taps = taps_for_dev(l);
+        const __bf16* Wl = wf + (int64_t)l * NT * C * C;
+        bf16x8 Bf[NT][2];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+                Bf[t][cb] = (t < taps.n) ? load8(Wl + ((int64_t)t * C + 16 * cb + r16) * C + kg * 8) : zero8();
+        const float bj0 = bias[l * C + r16], bj1 = bias[l * C + 16 + r16];
+        for (int tile = w; tile < ntiles; tile += 4) {
+            const int p = tile * 16 + r16;
+            const int r = p / L, c = p - (p / L) * L;
+            f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                if (t >= taps.n) break;
+                const int rr = r + taps.dr[t], cc = c + taps.dc[t];
+                const bool ok = p < N && rr >= 0 && rr < L && cc >= 0 && cc < L;
+                const bf16x8 a = ok ? *reinterpret_cast<const bf16x8*>(in + swz(rr * L + cc, kg)) : zero8();
+                acc0 = mfma16(a, Bf[t][0], acc0);
+                if (!last) acc1 = mfma16(a, Bf[t][1], acc1);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int pi = tile * 16 + 4 * kg + v;
+                if (pi >= N) continue;
+                if (last) {
+                    if (r16 == 0) logit[b * N + pi] = acc0[v] + bj0;
+                } else {
+                    const int o0 = swz_el(pi, r16), o1 = swz_el(pi, 16 + r16);
+                    out[o0] = hidden_out(first, acc0[v], bj0, first ? (__bf16)0.0f : in[o0]);
+                    out[o1] = hidden_out(first, acc1[v], bj1, first ? (__bf16)0.0f : in[o1]);
+                }
+            }
+        }
+        __syncthreads();
+        __bf16* t_ = in;
+        in = out;
+        out = t_;
+    }
+}
+
 constexpr int kSeqChains = 32;
 constexpr int kSeqLdsBytes = (NL * NT * C * C + NL * kSeqChains * C + 2 * kSeqChains * C) * 2 + kSeqChains * 4;
 
@@ -598,18 +692,27 @@ __global__ void scatter_grad_kernel(const float* dW, int l, float* grad) {
     grad[off + x] = dW[((int64_t)t * C + i) * C + o];
 }
 
-__global__ void scatter_bias_kernel(const float* part, int nparts, int l, float* grad) {
-    const int j = threadIdx.x;
+// bias gradient of layer l: sum of nparts partial sums per output channel;
+// 256 threads = 8 slices x 32 channels, slices reduced in LDS
+__global__ void __launch_bounds__(256) scatter_bias_kernel(const float* part, int nparts, int l, float* grad) {
+    const int j = threadIdx.x & 31, slice = threadIdx.x >> 5;
     const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
-    if (j >= co) return;
-    int64_t off = 0;
-    for (int k = 0; k < l; ++k) {
-        const int Tk = (k == 0) ? 4 : 5, cik = (k == 0) ? 1 : C, cok = (k == NL - 1) ? 1 : C;
-        off += (int64_t)Tk * cik * cok + cok;
-    }
+    const int stride = (co == 1) ? 1 : C;
     double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * (co == 1 ? 1 : C) + j];
-    grad[off + (int64_t)T * ci * co + j] = (float)s;
+    if (j < co)
+        for (int p = slice; p < nparts; p += 8) s += part[(int64_t)p * stride + j];
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (slice == 0 && j < co) {
+        for (int k = 1; k < 8; ++k) s += red[k * 32 + j];
+        int64_t off = 0;
+        for (int k = 0; k < l; ++k) {
+            const int Tk = (k == 0) ? 4 : 5, cik = (k == 0) ? 1 : C, cok = (k == NL - 1) ? 1 : C;
+            off += (int64_t)Tk * cik * cok + cok;
+        }
+        grad[off + (int64_t)T * ci * co + j] = (float)s;
+    }
 }
 
 int64_t n_params() {
@@ -762,12 +865,12 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B) {
             nbp = 256;
             hipLaunchKernelGGL(colsum0_kernel, dim3(nbp), dim3(256), 0, st, a->g32, P, a->bpart);
         } else {
-            nbp = (int)std::min<int64_t>(4096, (P + 7) / 8);
+            nbp = (int)std::min<int64_t>(1024, (P + 7) / 8);
             hipLaunchKernelGGL(mask_kernel, dim3(nbp), dim3(256), 0, st, dh, a->mask + (size_t)l * LSZ, P, a->dz,
                                a->bpart);
             dzl = a->dz;
         }
-        hipLaunchKernelGGL(scatter_bias_kernel, dim3(1), dim3(32), 0, st, a->bpart, nbp, l, a->grad);
+        hipLaunchKernelGGL(scatter_bias_kernel, dim3(1), dim3(256), 0, st, a->bpart, nbp, l, a->grad);
         hipLaunchKernelGGL(wgrad_kernel, dim3((unsigned)((nch + 3) / 4)), dim3(256), 0, st, a->hs + (size_t)l * LSZ, dzl,
                            tp, L, P, kChunk, nch, a->part);
         hipLaunchKernelGGL(reduce_chunks_kernel, dim3((NT * C * C + 255) / 256), dim3(256), 0, st, a->part, nch,
@@ -813,7 +916,8 @@ int ensure_infer(crbm_ar_t* a, int64_t n) {
     a->ih0 = a->ih1 = nullptr;
     a->ilogit = nullptr;
     const int64_t P = n * a->L * a->L;
-    if (alloc(&a->ih0, P * C) || alloc(&a->ih1, P * C) || alloc(&a->ilogit, P)) {
+    const bool layered = a->L > kFuseMaxL;  // the fused scorer needs only the logits
+    if ((layered && (alloc(&a->ih0, P * C) || alloc(&a->ih1, P * C))) || alloc(&a->ilogit, P)) {
         a->icap = 0;
         return fail_ar(CRBM_ENOMEM, "scoring buffers");
     }
@@ -828,6 +932,18 @@ int run_score(crbm_ar_t* a, int64_t n, const int8_t* spins, double* logq) {
     const int L = a->L;
     const int64_t P = n * L * L;
     hipStream_t st = a->stream;
+    if (L <= kFuseMaxL) {
+        const int lds = 2 * L * L * C * (int)sizeof(__bf16);
+        AR_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&score_fused_kernel),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds),
+               "scorer LDS size");
+        hipLaunchKernelGGL(score_fused_kernel, dim3((unsigned)n), dim3(256), lds, st, n, L, spins, a->wf, a->bias,
+                           a->ilogit);
+        hipLaunchKernelGGL(logq_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a->ilogit, spins, n,
+                           L * L, logq);
+        AR_TRY(hipGetLastError(), "scoring kernels");
+        return CRBM_OK;
+    }
     hipLaunchKernelGGL(embed_kernel, dim3((unsigned)((P * C + 255) / 256)), dim3(256), 0, st, spins, P, a->ih0);
     __bf16* in = a->ih0;
     __bf16* out = a->ih1;
