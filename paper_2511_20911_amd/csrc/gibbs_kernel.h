@@ -266,12 +266,17 @@ __device__ __forceinline__ uint32_t count_ge(uint32_t n0, uint32_t n1, uint32_t 
 // Visible half-step of the two rows of cell row i (Eq. (12)).  H: hidden
 // planes of this cell row; Hp5/Hp7/Hp9: planes 5, 7, 9 of the cell row above.
 // Classes: 0 top even, 1 top odd, 2 mid even, 3 mid odd columns.
+// A row that is not updated in this call is skipped slot by slot.  When the
+// two rows of a cell row are updated in two calls (mid only, later top only),
+// the Philox block that holds slots of both rows (word width not a multiple
+// of 8) is drawn once: the mid-only call stores it in `straddle`, the
+// top-only call reuses it.
 template <int L>
 __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], const uint32_t (&Hp5)[Geo<L>::W],
                                             const uint32_t (&Hp7)[Geo<L>::W], const uint32_t (&Hp9)[Geo<L>::W],
                                             const SweepK& K, bool do_top, bool do_mid, uint32_t i, uint32_t c3p,
                                             const Rng& rg, uint32_t (&ntop)[Geo<L>::W],
-                                            uint32_t (&nmid)[Geo<L>::W]) {
+                                            uint32_t (&nmid)[Geo<L>::W], P4 (&straddle)[Geo<L>::W]) {
     using G = Geo<L>;
 #pragma unroll
     for (int w = 0; w < G::W; ++w) {
@@ -308,13 +313,21 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
             if (blk >= NB) continue;
             const bool has_top = blk * 8 < m, has_mid = blk * 8 + 7 >= m;
             if (!((do_top && has_top) || (do_mid && has_mid))) continue;
-            const P4 p = philox(cbase | (uint32_t)blk, rg.sweep, rg.chain, c3p, rg.k0, rg.k1);
+            const bool shared = has_top && has_mid;  // the straddling block (m % 8 != 0)
+            P4 p;
+            if (shared && do_top && !do_mid) {
+                p = straddle[w];
+            } else {
+                p = philox(cbase | (uint32_t)blk, rg.sweep, rg.chain, c3p, rg.k0, rg.k1);
+                if (shared && do_mid && !do_top) straddle[w] = p;
+            }
             uint64_t tie = 0;
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
                 const int q = blk * 8 + s;
                 if (q < NQ) {
                     const int row = q / m, col = q % m, cls = 2 * row + (col & 1), pos = col & ~1;
+                    if (!(row == 0 ? do_top : do_mid)) continue;
                     const uint32_t p16 = slot16(p, s);
                     const uint32_t idx = ((Pa[cls] >> pos) & 3u) | (((Pb[cls] >> pos) & 3u) << 2);
                     const uint32_t e = __shfl(K.tabv, (int)idx);
@@ -336,6 +349,7 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
                 const int q = blk * 8 + s;
                 if (q < NQ) {
                     const int row = q / m, col = q % m, cls = 2 * row + (col & 1), pos = col & ~1;
+                    if (!(row == 0 ? do_top : do_mid)) continue;
                     const uint32_t U = (slot16(p, s) << 16) | slot16(r, s);
                     const uint32_t idx = ((pick(Pa, cls) >> pos) & 3u) | (((pick(Pb, cls) >> pos) & 3u) << 2);
                     const uint32_t t = __shfl(K.tfull, (int)idx);
@@ -390,6 +404,7 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
 #pragma unroll
         for (int w = 0; w < W; ++w) Q[NR][w] = __shfl(Q[0][w], nxt);  // old first row of the next band
         uint32_t Hf0[W], Hf1[W], Hf4[W], Hf6[W], Hf8[W], Hp5[W], Hp7[W], Hp9[W];
+        P4 straddle[W];  // Philox block shared by the two rows of the band's first cell row
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             Hf0[w] = Hf1[w] = Hf4[w] = Hf6[w] = Hf8[w] = 0u;
@@ -401,7 +416,7 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
             uint32_t H[10][W];
             hidden_row<L>(Q[0], Q[1], Q[2], K, i, c3h, rg, H);
             uint32_t nt[W], nm[W];
-            visible_row<L>(H, Hp5, Hp7, Hp9, K, m > 0, true, i, c3v, rg, nt, nm);
+            visible_row<L>(H, Hp5, Hp7, Hp9, K, m > 0, true, i, c3v, rg, nt, nm, straddle);
 #pragma unroll
             for (int w = 0; w < W; ++w) {
                 const uint32_t old_top = Q[0][w];
@@ -430,7 +445,7 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
                 Hd[2][w] = Hd[3][w] = Hd[5][w] = Hd[7][w] = Hd[9][w] = 0u;
             }
             uint32_t nt[W], nm[W];
-            visible_row<L>(Hd, Hp5, Hp7, Hp9, K, true, false, (uint32_t)(g * R), c3v, rg, nt, nm);
+            visible_row<L>(Hd, Hp5, Hp7, Hp9, K, true, false, (uint32_t)(g * R), c3v, rg, nt, nm, straddle);
 #pragma unroll
             for (int w = 0; w < W; ++w) Q[1][w] = nt[w];
         }
