@@ -516,7 +516,7 @@ constexpr int kSeqLdsBytes = (NL * NT * C * C + NL * kSeqChains * C + 2 * kSeqCh
 // weights (120 KB), the activations of every layer at the previous site
 // (the (0,-1) tap) and at the current site (the centre tap, double-buffered
 // by layer parity).  The three taps in the row above come from a two-row ring
-// in global memory, prefetched one site ahead.  Spin i is +1 iff u < sigmoid
+// in global memory, prefetched three layers ahead.  Spin i is +1 iff u < sigmoid
 // (logit) with u the top 24 bits of Philox (ctr = (site, step, chain,
 // id << 3 | 6)); the logits go to logit_out for the log q sum.
 __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int L, const __bf16* __restrict__ wf,
@@ -548,23 +548,28 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int L, const __bf
     auto ridx = [&](int l, int64_t chain, int r, int c) -> int64_t {
         return ((((int64_t)l * n + chain) * 2 + (r & 1)) * L + c) * C;
     };
-    bf16x8 pr[NL][3];
-    auto fetch = [&](int l, int r, int c) {
+    // row-above fragments, prefetched three layers ahead: slot l % 3 holds layer l
+    constexpr int kAhead = 3;
+    bf16x8 pr[kAhead][3];
+    auto fetch = [&](bf16x8 (&dst)[3], int l, int r, int c) {
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
             const int cc = c - 1 + t;
             const bool inside = r > 0 && cc >= 0 && cc < L;
-            pr[l][t] = inside ? load8(ring + ridx(l, gca, r - 1, cc) + kg * 8) : zero8();
+            dst[t] = inside ? load8(ring + ridx(l, gca, r - 1, cc) + kg * 8) : zero8();
         }
     };
 #pragma unroll
-    for (int l = 0; l < NL; ++l) fetch(l, 0, 0);
+    for (int l = 0; l < kAhead; ++l) fetch(pr[l], l, 0, 0);
     __bf16 pend[NL][4];
     __syncthreads();
     for (int site = 0; site < N; ++site) {
         const int r = site / L, c = site - r * L;
         const int sn = site + 1, rn = sn / L, cn = sn - rn * L;
         const bool more = sn < N;
+        // ring offset of this lane's first output (layer 0, chain 16 chh + 4 kg)
+        const int64_t ring_lane = ridx(0, base + 16 * chh + 4 * kg, r, c) + oc;
+        const int64_t ring_layer = (int64_t)n * 2 * L * C, ring_chain = (int64_t)2 * L * C;
         float u = 0.f;
         if (w == 0) {
             const gk::P4 q = gk::philox((uint32_t)site, step, (uint32_t)(base + (lane & 31)), (id << 3) | 6u,
@@ -577,21 +582,29 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int L, const __bf
             __bf16* tn = tile + ((l + 1) & 1) * kSeqChains * C;
             if (l < NL - 1 || coh == 0) {
                 const __bf16* Wl = wl + l * NT * C * C;
+                // all LDS operands of the layer first, so their latencies overlap
+                bf16x8 bw[NT];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) bw[t] = (t < 4 || l > 0) ? load8(Wl + t * C * C + swz(oc, kg)) : zero8();
+                const bf16x8 a3 = (c > 0) ? load8(prev + l * kSeqChains * C + swz(ca, kg)) : zero8();
+                const bf16x8 a4 = (l > 0) ? load8(tl + swz(ca, kg)) : zero8();
+                __bf16 res[4];  // residual inputs of this lane's four outputs
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    res[v] = (l > 0 && l < NL - 1) ? tl[swz_el(16 * chh + 4 * kg + v, oc)] : (__bf16)0.0f;
                 f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int t = 0; t < 3; ++t) acc = mfma16(pr[l][t], load8(Wl + t * C * C + swz(oc, kg)), acc);
-                const bf16x8 a3 = (c > 0) ? load8(prev + l * kSeqChains * C + swz(ca, kg)) : zero8();
-                acc = mfma16(a3, load8(Wl + 3 * C * C + swz(oc, kg)), acc);
-                if (l > 0) acc = mfma16(load8(tl + swz(ca, kg)), load8(Wl + 4 * C * C + swz(oc, kg)), acc);
+                for (int t = 0; t < 3; ++t) acc = mfma16(pr[l % kAhead][t], bw[t], acc);
+                acc = mfma16(a3, bw[3], acc);
+                if (l > 0) acc = mfma16(a4, bw[4], acc);
                 if (l < NL - 1) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int ci = 16 * chh + 4 * kg + v;
-                        const __bf16 hn =
-                            hidden_out(l == 0, acc[v], bj[l], l == 0 ? (__bf16)0.0f : tl[swz_el(ci, oc)]);
+                        const __bf16 hn = hidden_out(l == 0, acc[v], bj[l], res[v]);
                         tn[swz_el(ci, oc)] = hn;
                         pend[l + 1][v] = hn;
-                        if (base + ci < n) ring[ridx(l + 1, base + ci, r, c) + oc] = hn;
+                        if (base + ci < n) ring[ring_lane + (l + 1) * ring_layer + v * ring_chain] = hn;
                     }
                 } else if (r16 == 0) {
 #pragma unroll
@@ -603,7 +616,11 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int L, const __bf
 #pragma unroll
                 for (int v = 0; v < 4; ++v) prev[(l - 1) * kSeqChains * C + swz_el(16 * chh + 4 * kg + v, oc)] = pend[l - 1][v];
             }
-            if (more) fetch(l, rn, cn);
+            // refill this slot with the layer three ahead (of this site or the next)
+            if (l + kAhead < NL)
+                fetch(pr[l % kAhead], l + kAhead, r, c);
+            else if (more)
+                fetch(pr[l % kAhead], l + kAhead - NL, rn, cn);
             __syncthreads();
         }
 #pragma unroll
