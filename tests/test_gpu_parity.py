@@ -183,6 +183,36 @@ def test_accumulators_and_structure_factor_match_oracle():
     assert abs(obs[0]["E_per_spin"] - E) < 1e-12
 
 
+def test_degenerate_couplings_bit_exact():
+    """Edge cases of the mapping in one handle: zero J1 (no square bonds),
+    zero J2, a pure field, ferromagnetic (negative) couplings, a temperature
+    low enough to saturate every threshold, a very high one (near fair coins),
+    and a single chain on the smallest lattice; every chain and trace equals
+    the oracle."""
+    seed, S = 0x5EED000000000006, 120
+    insts = [
+        crbm.Instance(L=6, J1=0.0, J2=1.0, h=0.5, n_chains=9, sched="const", T0=0.7, id=1),
+        crbm.Instance(L=12, J1=1.0, J2=0.0, h=-1.0, n_chains=9, sched="linear", T0=2.0, T1=0.3, id=2),
+        crbm.Instance(L=6, J1=0.0, J2=0.0, h=2.0, n_chains=9, sched="const", T0=1.5, id=3),
+        crbm.Instance(L=18, J1=-1.0, J2=-0.5, h=0.0, n_chains=9, sched="geometric", T0=4.0, T1=0.5, id=4),
+        crbm.Instance(L=12, J1=1.0, J2=1.0, h=3.0, n_chains=9, sched="const", T0=0.01, id=5),
+        crbm.Instance(L=6, J1=1.0, J2=2.0, h=1.0, n_chains=9, sched="const", T0=1e4, id=6),
+        crbm.Instance(L=4, J1=1.0, J2=0.5, h=0.2, n_chains=1, sched="const", T0=1.0, id=7),
+    ]
+    smp, parts, tr = _run_gpu(insts, seed, S)
+    for k, I in enumerate(insts):
+        _check_chains(I, parts[k], tr, int(smp.chain_offsets[k]), seed, S, range(I.n_chains))
+    # zero sweeps is a no-op that still returns the state
+    out = torch.empty(smp.total_spins, dtype=torch.int8, device="cuda")
+    with pytest.raises(crbm.CrbmError):
+        smp.sample(1)  # the schedule is exhausted
+    smp2 = crbm.Sampler(insts, seed=seed, n_sweeps=S)
+    smp2.sample(0, spins_out=out)
+    st, idx = smp2.get_state()
+    torch.cuda.synchronize()
+    assert idx == 0 and torch.equal(out, st)
+
+
 def test_invalid_arguments_fail_cleanly():
     bad = [
         (crbm.Instance(L=7, n_chains=1), crbm.CRBM_EINVAL),
