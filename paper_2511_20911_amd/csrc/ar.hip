@@ -267,19 +267,24 @@ __global__ void __launch_bounds__(256) loss_kernel(const float* logit, const int
     if (threadIdx.x == 0) logq[b] = red[0];
 }
 
-// log q per chain from the logits of a full forward pass, one thread per
-// chain, summed over the sites in raster order in fp64 with the same
-// expression as the sequential sampler, so both give identical values.
-__global__ void logq_kernel(const float* __restrict__ logit, const int8_t* __restrict__ spins, int64_t n, int N,
-                            double* __restrict__ logq) {
-    const int64_t ch = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (ch >= n) return;
+// log q per chain from per-site logits: log q = sum_i -log1p(exp(-s_i l_i))
+// in fp64.  One wavefront per chain: lane k sums the sites k, k + 64, ... in
+// order, then a fixed butterfly over the 64 lane sums.  The sampler and the
+// scorer both reduce their logits with this kernel, so equal logits give
+// bit-identical log q.
+__global__ void __launch_bounds__(256) logq_kernel(const float* __restrict__ logit, const int8_t* __restrict__ spins,
+                                                   int64_t n, int N, double* __restrict__ logq) {
+    const int lane = threadIdx.x & 63;
+    const int64_t ch = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (ch >= n) return;  // uniform per wavefront
     double s = 0.0;
-    for (int i = 0; i < N; ++i) {
+    for (int i = lane; i < N; i += 64) {
         const float sg = (float)spins[ch * N + i];
         s += -log1p(exp(-(double)(sg * logit[ch * N + i])));
     }
-    logq[ch] = s;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d);
+    if (lane == 0) logq[ch] = s;
 }
 
 // dz = bf16(dh * mask), plus per-block partial bias gradients sum dh * mask
@@ -507,7 +512,7 @@ __global__ void __launch_bounds__(256) score_fused_kernel(int64_t n, int L, cons
 }
 
 constexpr int kSeqChains = 32;
-constexpr int kSeqLdsBytes = (NL * NT * C * C + NL * kSeqChains * C + 2 * kSeqChains * C) * 2 + kSeqChains * 4;
+constexpr int kSeqLdsBytes = (NL * NT * C * C + NL * kSeqChains * C + 2 * kSeqChains * C + C) * 2 + kSeqChains * 4;
 
 // Ancestral sampler: a workgroup of four wavefronts draws 32 configurations
 // site by site in raster order.  Wavefront w computes chains 16 (w & 1) ..+15
@@ -519,15 +524,17 @@ constexpr int kSeqLdsBytes = (NL * NT * C * C + NL * kSeqChains * C + 2 * kSeqCh
 // in global memory, prefetched three layers ahead.  Spin i is +1 iff u < sigmoid
 // (logit) with u the top 24 bits of Philox (ctr = (site, step, chain,
 // id << 3 | 6)); the logits go to logit_out for the log q sum.
-__global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int L, const __bf16* __restrict__ wf,
+__global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int64_t npad, int L, const __bf16* __restrict__ wf,
                                                     const float* __restrict__ bias, __bf16* __restrict__ ring,
-                                                    int8_t* __restrict__ spins, float* __restrict__ logit_out,
-                                                    uint64_t seed, uint32_t step, uint32_t id) {
+                                                    const __bf16* __restrict__ zpad, int8_t* __restrict__ spins,
+                                                    float* __restrict__ logit_out, uint64_t seed, uint32_t step,
+                                                    uint32_t id) {
     extern __shared__ __align__(16) unsigned char smem[];
     __bf16* wl = reinterpret_cast<__bf16*>(smem);
     __bf16* prev = wl + NL * NT * C * C;      // [NL][32 chains][C]: h_l at the previous site
     __bf16* tile = prev + NL * kSeqChains * C;  // [2][32 chains][C]: h_l at the current site
-    float* xl = reinterpret_cast<float*>(tile + 2 * kSeqChains * C);  // [32] logits
+    __bf16* zrow = tile + 2 * kSeqChains * C;   // [C] zeros: operand of taps outside the lattice
+    float* xl = reinterpret_cast<float*>(zrow + C);  // [32] logits
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int chh = w & 1, coh = w >> 1;
     const int r16 = lane & 15, kg = lane >> 4;
@@ -538,15 +545,16 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int L, const __bf
         *reinterpret_cast<bf16x8*>(wl + swz(row, grp)) = load8(wf + (int64_t)row * C + grp * 8);
     }
     for (int g = tid; g < NL * kSeqChains * 4; g += blockDim.x) *reinterpret_cast<bf16x8*>(prev + g * 8) = zero8();
+    if (tid < 4) *reinterpret_cast<bf16x8*>(zrow + tid * 8) = zero8();
     const int oc = 16 * coh + r16;  // B column / D column: output channel of this lane
     const int ca = 16 * chh + r16;  // A row: chain within the workgroup
-    const int64_t gca = (base + ca < n) ? base + ca : base;  // padding rows read a valid chain
+    const int64_t gca = base + ca;  // the ring has npad >= n chains: padding rows have their own slots
     float bj[NL];
 #pragma unroll
     for (int l = 0; l < NL; ++l) bj[l] = bias[l * C + oc];
-    // ring element (layer, chain, row, column): [NL][n][2][L][C]
+    // ring element (layer, chain, row, column): [NL][npad][2][L][C]
     auto ridx = [&](int l, int64_t chain, int r, int c) -> int64_t {
-        return ((((int64_t)l * n + chain) * 2 + (r & 1)) * L + c) * C;
+        return ((((int64_t)l * npad + chain) * 2 + (r & 1)) * L + c) * C;
     };
     // row-above fragments, prefetched three layers ahead: slot l % 3 holds layer l
     constexpr int kAhead = 3;
@@ -555,8 +563,9 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int L, const __bf
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
             const int cc = c - 1 + t;
-            const bool inside = r > 0 && cc >= 0 && cc < L;
-            dst[t] = inside ? load8(ring + ridx(l, gca, r - 1, cc) + kg * 8) : zero8();
+            const bool inside = r > 0 && cc >= 0 && cc < L;  // wavefront-uniform
+            const __bf16* src = inside ? ring + ridx(l, gca, r - 1, cc) : zpad;
+            dst[t] = load8(src + kg * 8);
         }
     };
 #pragma unroll
@@ -569,7 +578,7 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int L, const __bf
         const bool more = sn < N;
         // ring offset of this lane's first output (layer 0, chain 16 chh + 4 kg)
         const int64_t ring_lane = ridx(0, base + 16 * chh + 4 * kg, r, c) + oc;
-        const int64_t ring_layer = (int64_t)n * 2 * L * C, ring_chain = (int64_t)2 * L * C;
+        const int64_t ring_layer = (int64_t)npad * 2 * L * C, ring_chain = (int64_t)2 * L * C;
         float u = 0.f;
         if (w == 0) {
             const gk::P4 q = gk::philox((uint32_t)site, step, (uint32_t)(base + (lane & 31)), (id << 3) | 6u,
@@ -586,7 +595,7 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int L, const __bf
                 bf16x8 bw[NT];
 #pragma unroll
                 for (int t = 0; t < NT; ++t) bw[t] = (t < 4 || l > 0) ? load8(Wl + t * C * C + swz(oc, kg)) : zero8();
-                const bf16x8 a3 = (c > 0) ? load8(prev + l * kSeqChains * C + swz(ca, kg)) : zero8();
+                const bf16x8 a3 = load8((c > 0) ? prev + l * kSeqChains * C + swz(ca, kg) : zrow + kg * 8);
                 const bf16x8 a4 = (l > 0) ? load8(tl + swz(ca, kg)) : zero8();
                 __bf16 res[4];  // residual inputs of this lane's four outputs
 #pragma unroll
@@ -604,7 +613,7 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int L, const __bf
                         const __bf16 hn = hidden_out(l == 0, acc[v], bj[l], res[v]);
                         tn[swz_el(ci, oc)] = hn;
                         pend[l + 1][v] = hn;
-                        if (base + ci < n) ring[ring_lane + (l + 1) * ring_layer + v * ring_chain] = hn;
+                        ring[ring_lane + (l + 1) * ring_layer + v * ring_chain] = hn;
                     }
                 } else if (r16 == 0) {
 #pragma unroll
@@ -632,10 +641,10 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int L, const __bf
             const float p = 1.f / (1.f + expf(-x));
             const float sg = (u < p) ? 1.f : -1.f;
             prev[swz_el(lane, 0)] = f2bf(sg);  // layer-1 input at this site (channel 0; the rest stay 0)
+            ring[ridx(0, ch, r, c)] = f2bf(sg);
             if (ch < n) {
                 spins[ch * N + site] = (int8_t)sg;
                 logit_out[ch * N + site] = x;
-                ring[ridx(0, ch, r, c)] = f2bf(sg);
             }
         }
         __syncthreads();
@@ -650,22 +659,32 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int L, const __bf
 namespace crbmlib {
 namespace ar {
 
-__global__ void counts_int8_kernel(const int8_t* s, int64_t n, int L, int32_t* out) {
-    const int64_t ch = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (ch >= n) return;
+// Exact integer (M, B1, B2) of int8 configurations, one wavefront per chain.
+__global__ void __launch_bounds__(256) counts_int8_kernel(const int8_t* s, int64_t n, int L, int32_t* out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t ch = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (ch >= n) return;  // uniform per wavefront
     const int8_t* x = s + ch * L * L;
     int M = 0, B1 = 0, B2 = 0;
-    for (int r = 0; r < L; ++r)
-        for (int c = 0; c < L; ++c) {
-            const int v = x[r * L + c];
-            M += v;
-            B1 += v * x[r * L + (c + 1) % L] + v * x[((r + 1) % L) * L + c];
-            if ((r & 1) == 0 && (c & 1) == 0) B2 += v * x[(r + 1) * L + c + 1];          // '\' dimer
-            if ((r & 1) == 1 && (c & 1) == 0) B2 += v * x[((r + 1) % L) * L + (c + L - 1) % L];  // '/' dimer
-        }
-    out[ch * 3] = M;
-    out[ch * 3 + 1] = B1;
-    out[ch * 3 + 2] = B2;
+    for (int i = lane; i < L * L; i += 64) {
+        const int r = i / L, c = i - (i / L) * L;
+        const int v = x[i];
+        M += v;
+        B1 += v * x[r * L + (c + 1) % L] + v * x[((r + 1) % L) * L + c];
+        if ((r & 1) == 0 && (c & 1) == 0) B2 += v * x[(r + 1) * L + c + 1];          // '\\' dimer
+        if ((r & 1) == 1 && (c & 1) == 0) B2 += v * x[((r + 1) % L) * L + (c + L - 1) % L];  // '/' dimer
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        M += __shfl_xor(M, d);
+        B1 += __shfl_xor(B1, d);
+        B2 += __shfl_xor(B2, d);
+    }
+    if (lane == 0) {
+        out[ch * 3] = M;
+        out[ch * 3 + 1] = B1;
+        out[ch * 3 + 2] = B2;
+    }
 }
 
 // Independent MH (one thread per chain): log alpha = [log pi' - log pi] +
@@ -771,6 +790,7 @@ struct crbm_ar_s {
     int64_t scap = 0;
     __bf16* ring = nullptr;     // [NL][n][2][L][C]: activations of the last two rows
     float* slogit = nullptr;    // [n][N]
+    __bf16* zpad = nullptr;     // [C] zeros: row-above operand outside the lattice
     // scoring buffers (capacity in chains): ping-pong activations and logits
     int64_t icap = 0;
     __bf16 *ih0 = nullptr, *ih1 = nullptr;  // [n N][C]
@@ -783,7 +803,7 @@ struct crbm_ar_s {
     unsigned long long* nacc = nullptr;
     ~crbm_ar_s() {
         void* ps[] = {theta, grad, m, v, bias, wf, wb, hs, mask, logit, g32, dh0, dh1, dz, g, logq, part, dW, bpart,
-                      spins_copy, ring, slogit, ih0, ih1, ilogit, cur, prop, ccur, cprop, lqc, lqp, nacc};
+                      spins_copy, ring, slogit, zpad, ih0, ih1, ilogit, cur, prop, ccur, cprop, lqc, lqp, nacc};
         for (void* p : ps)
             if (p) (void)hipFree(p);
     }
@@ -830,7 +850,8 @@ int ensure_seq(crbm_ar_t* a, int64_t n) {
     if (a->slogit) (void)hipFree(a->slogit);
     a->ring = nullptr;
     a->slogit = nullptr;
-    if (alloc(&a->ring, (int64_t)NL * n * 2 * a->L * C) || alloc(&a->slogit, n * a->L * a->L)) {
+    const int64_t npad = (n + kSeqChains - 1) / kSeqChains * kSeqChains;
+    if (alloc(&a->ring, (int64_t)NL * npad * 2 * a->L * C) || alloc(&a->slogit, n * a->L * a->L)) {
         a->scap = 0;
         return fail_ar(CRBM_ENOMEM, "sampler buffers");
     }
@@ -913,13 +934,14 @@ int run_seq(crbm_ar_t* a, int64_t n, int8_t* spins, double* logq, uint64_t seed,
     const int L = a->L;
     hipStream_t st = a->stream;
     // layer-1 input ring: channels 1..31 stay zero, channel 0 receives the spins
-    AR_TRY(hipMemsetAsync(a->ring, 0, sizeof(__bf16) * (size_t)n * 2 * L * C, st), "clear sampler input");
+    const int64_t npad = (n + kSeqChains - 1) / kSeqChains * kSeqChains;
+    AR_TRY(hipMemsetAsync(a->ring, 0, sizeof(__bf16) * (size_t)npad * 2 * L * C, st), "clear sampler input");
     AR_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&seq16_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, kSeqLdsBytes),
            "sampler LDS size");
     hipLaunchKernelGGL(seq16_kernel, dim3((unsigned)((n + kSeqChains - 1) / kSeqChains)), dim3(256), kSeqLdsBytes,
-                       st, n, L, a->wf, a->bias, a->ring, spins, a->slogit, seed, step, id);
-    hipLaunchKernelGGL(logq_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a->slogit, spins, n, L * L,
+                       st, n, npad, L, a->wf, a->bias, a->ring, a->zpad, spins, a->slogit, seed, step, id);
+    hipLaunchKernelGGL(logq_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->slogit, spins, n, L * L,
                        logq);
     AR_TRY(hipGetLastError(), "sampler kernels");
     return CRBM_OK;
@@ -956,7 +978,7 @@ int run_score(crbm_ar_t* a, int64_t n, const int8_t* spins, double* logq) {
                "scorer LDS size");
         hipLaunchKernelGGL(score_fused_kernel, dim3((unsigned)n), dim3(256), lds, st, n, L, spins, a->wf, a->bias,
                            a->ilogit);
-        hipLaunchKernelGGL(logq_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a->ilogit, spins, n,
+        hipLaunchKernelGGL(logq_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->ilogit, spins, n,
                            L * L, logq);
         AR_TRY(hipGetLastError(), "scoring kernels");
         return CRBM_OK;
@@ -971,7 +993,7 @@ int run_score(crbm_ar_t* a, int64_t n, const int8_t* spins, double* logq) {
                            a->bias + l * C, l, L, P, out, a->ilogit);
         std::swap(in, out);
     }
-    hipLaunchKernelGGL(logq_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a->ilogit, spins, n, L * L,
+    hipLaunchKernelGGL(logq_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->ilogit, spins, n, L * L,
                        logq);
     AR_TRY(hipGetLastError(), "scoring kernels");
     return CRBM_OK;
@@ -996,10 +1018,11 @@ int crbm_ar_create(const crbm_ar_config* c, crbm_ar_t** out) {
     a->np = n_params();
     if (alloc(&a->theta, a->np) || alloc(&a->grad, a->np) || alloc(&a->m, a->np) || alloc(&a->v, a->np) ||
         alloc(&a->bias, NL * C) || alloc(&a->wf, (int64_t)NL * NT * C * C) || alloc(&a->wb, (int64_t)NL * NT * C * C) ||
-        alloc(&a->dW, NT * C * C)) {
+        alloc(&a->dW, NT * C * C) || alloc(&a->zpad, C)) {
         delete a;
         return fail_ar(CRBM_ENOMEM, "parameter buffers");
     }
+    (void)hipMemsetAsync(a->zpad, 0, sizeof(__bf16) * C, a->stream);
     (void)hipMemsetAsync(a->theta, 0, sizeof(float) * a->np, a->stream);
     (void)hipMemsetAsync(a->m, 0, sizeof(float) * a->np, a->stream);
     (void)hipMemsetAsync(a->v, 0, sizeof(float) * a->np, a->stream);
@@ -1157,14 +1180,14 @@ int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_
         if (cyc == 0 || gibbs_per_mh > 0) {
             if (handle_view(h, &v) != CRBM_OK) return fail_ar(CRBM_EINVAL, "bad handle");
             AR_TRY(launch_unpack(v.state, a->cur, n, v.L, st), "unpack state");
-            hipLaunchKernelGGL(counts_int8_kernel, dim3(nb), dim3(256), 0, st, a->cur, n, v.L, a->ccur);
+            hipLaunchKernelGGL(counts_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->cur, n, v.L, a->ccur);
             rc = run_score(a, n, a->cur, a->lqc);
             if (rc != CRBM_OK) return rc;
         }
         const uint32_t step = (uint32_t)(a->mh_step++);
         rc = run_seq(a, n, a->prop, a->lqp, v.seed, step, v.id);
         if (rc != CRBM_OK) return rc;
-        hipLaunchKernelGGL(counts_int8_kernel, dim3(nb), dim3(256), 0, st, a->prop, n, v.L, a->cprop);
+        hipLaunchKernelGGL(counts_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->prop, n, v.L, a->cprop);
         hipLaunchKernelGGL(mh_kernel, dim3(nb), dim3(256), 0, st, n, v.L, a->cur, a->prop, a->ccur, a->cprop, a->lqc,
                            a->lqp, v.a, v.c1, v.c2, v.sg1, v.sg2, v.seed, step, v.id, a->nacc);
         AR_TRY(launch_pack(v.state, a->cur, n, v.L, st), "pack state");
