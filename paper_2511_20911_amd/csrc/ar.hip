@@ -383,10 +383,29 @@ __device__ __forceinline__ __bf16 hidden_out(bool first, float acc, float bias, 
     return f2bf(first ? rz : bf2f(resid) + rz);
 }
 
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+
+// four consecutive output channels of one pixel / chain (the D layout below)
+__device__ __forceinline__ bf16x4 hidden_out4(bool first, f32x4 acc, f32x4 bias, bf16x4 resid) {
+    bf16x4 h;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) h[v] = hidden_out(first, acc[v], bias[v], resid[v]);
+    return h;
+}
+
+__device__ __forceinline__ bf16x4 zero4() {
+    bf16x4 z;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) z[v] = (__bf16)0.0f;
+    return z;
+}
+
 // Scorer layer: one wavefront per 16 pixels x 32 output channels.
-// 16x16x32 operand layout: A row = lane % 16 (pixel), k = 8 (lane / 16) + e;
-// B column = lane % 16 (channel within a 16-block), same k; D column
-// lane % 16, rows 4 (lane / 16) + v.
+// 16x16x32 operand layout: A row = lane % 16, k = 8 (lane / 16) + e; B column
+// = lane % 16, same k; D column lane % 16, rows 4 (lane / 16) + v.  The
+// weights are the A operand (rows = output channels of a 16-block) and the
+// activations the B operand (columns = pixels), so a lane's D values are four
+// consecutive output channels of its own pixel.
 __global__ void __launch_bounds__(256) conv16_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ Wl,
                                                      const float* __restrict__ bias, int layer, int L, int64_t P,
                                                      __bf16* __restrict__ out, float* __restrict__ logit) {
@@ -396,13 +415,14 @@ __global__ void __launch_bounds__(256) conv16_kernel(const __bf16* __restrict__ 
     const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const bool first = layer == 0, last = layer == NL - 1;
     const Taps taps = taps_for_dev(layer);
-    bf16x8 Bf[NT][2];
+    bf16x8 Wa[NT][2];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
-            Bf[t][cb] = (t < taps.n) ? load8(Wl + ((int64_t)t * C + 16 * cb + r16) * C + kg * 8) : zero8();
-    const float bj0 = bias[r16], bj1 = bias[16 + r16];
+            Wa[t][cb] = (t < taps.n) ? load8(Wl + ((int64_t)t * C + 16 * cb + r16) * C + kg * 8) : zero8();
+    const f32x4 bj0 = *reinterpret_cast<const f32x4*>(bias + 4 * kg);
+    const f32x4 bj1 = *reinterpret_cast<const f32x4*>(bias + 16 + 4 * kg);
     const int64_t ntiles = (P + 15) / 16;
     for (int64_t tile = w0; tile < ntiles; tile += nw) {
         const int64_t p = tile * 16 + r16;
@@ -412,20 +432,18 @@ __global__ void __launch_bounds__(256) conv16_kernel(const __bf16* __restrict__ 
             if (t >= taps.n) break;
             const int64_t q = (p < P) ? shift_pixel(p, taps.dr[t], taps.dc[t], L) : -1;
             const bf16x8 a = (q >= 0) ? load8(in + q * C + kg * 8) : zero8();
-            acc0 = mfma16(a, Bf[t][0], acc0);
-            if (!last) acc1 = mfma16(a, Bf[t][1], acc1);
+            acc0 = mfma16(Wa[t][0], a, acc0);
+            if (!last) acc1 = mfma16(Wa[t][1], a, acc1);
         }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t pi = tile * 16 + 4 * kg + v;
-            if (pi >= P) continue;
-            if (last) {
-                if (r16 == 0) logit[pi] = acc0[v] + bj0;
-            } else {
-                const int64_t o0 = pi * C + r16, o1 = o0 + 16;
-                out[o0] = hidden_out(first, acc0[v], bj0, first ? (__bf16)0.0f : in[o0]);
-                out[o1] = hidden_out(first, acc1[v], bj1, first ? (__bf16)0.0f : in[o1]);
-            }
+        if (p >= P) continue;
+        if (last) {
+            if (kg == 0) logit[p] = acc0[0] + bj0[0];
+        } else {
+            const int64_t o0 = p * C + 4 * kg, o1 = o0 + 16;
+            const bf16x4 r0 = first ? zero4() : *reinterpret_cast<const bf16x4*>(in + o0);
+            const bf16x4 r1 = first ? zero4() : *reinterpret_cast<const bf16x4*>(in + o1);
+            *reinterpret_cast<bf16x4*>(out + o0) = hidden_out4(first, acc0, bj0, r0);
+            *reinterpret_cast<bf16x4*>(out + o1) = hidden_out4(first, acc1, bj1, r1);
         }
     }
 }
@@ -436,72 +454,89 @@ __device__ __forceinline__ int swz(int row, int grp) { return row * C + ((grp ^ 
 __device__ __forceinline__ int swz_el(int row, int ch) { return swz(row, ch >> 3) + (ch & 7); }
 
 // Fused scorer: one workgroup of four wavefronts per configuration, all 12
-// layers with the activations of the whole lattice in LDS (two [N][32] bf16
-// buffers, rows XOR-swizzled), so only the spins are read and the logits
-// written.  Wavefront w takes the 16-pixel tiles w, w + 4, ... of each layer;
-// per tile it runs the same five 16x16x32 instructions per 16-channel block,
-// in the same order and with the same epilogue as conv16_kernel and the
-// sampler.  Used for L <= kFuseMaxL (LDS = 128 N bytes).
+// layers with the activations of the whole lattice in LDS, so only the spins
+// are read and the logits written.  Both activation buffers carry a zero
+// border (one row above, one column on each side: (L+1) x (L+2) pixels of 32
+// bf16 channels, rows XOR-swizzled), so every tap reads a valid address and
+// out-of-lattice taps read zeros, as in the sampler.  Wavefront w takes the
+// 16-pixel tiles w, w + 4, ... of each layer; per tile it runs the same five
+// 16x16x32 instructions per 16-channel block, in the same order and with the
+// same epilogue as conv16_kernel and the sampler.  Used for L <= kFuseMaxL.
 constexpr int kFuseMaxL = 32;
+
+__host__ __device__ constexpr int fused_pixels(int L) { return (L + 1) * (L + 2); }
 
 __global__ void __launch_bounds__(256) score_fused_kernel(int64_t n, int L, const int8_t* __restrict__ spins,
                                                           const __bf16* __restrict__ wf,
                                                           const float* __restrict__ bias,
                                                           float* __restrict__ logit) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int N = L * L;
+    const int N = L * L, W2 = L + 2, PP = fused_pixels(L);
     __bf16* buf0 = reinterpret_cast<__bf16*>(smem);
-    __bf16* buf1 = buf0 + N * C;
+    __bf16* buf1 = buf0 + PP * C;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int r16 = lane & 15, kg = lane >> 4;
     const int64_t b = blockIdx.x;
     if (b >= n) return;  // uniform per workgroup
     const int8_t* sp = spins + b * N;
-    for (int g = tid; g < N * 4; g += blockDim.x) {  // layer-1 input: spin in channel 0
-        const int p = g >> 2, grp = g & 3;
-        bf16x8 v = zero8();
-        if (grp == 0) v[0] = f2bf((float)sp[p]);
-        *reinterpret_cast<bf16x8*>(buf0 + swz(p, grp)) = v;
-    }
+    // both buffers: zeros everywhere (the border stays zero), then the spins
+    for (int g = tid; g < 2 * PP * 4; g += blockDim.x) *reinterpret_cast<bf16x8*>(buf0 + g * 8) = zero8();
     __syncthreads();
+    for (int p = tid; p < N; p += blockDim.x) {
+        const int r = p / L, c = p - (p / L) * L;
+        buf0[swz_el((r + 1) * W2 + c + 1, 0)] = f2bf((float)sp[p]);
+    }
     const int ntiles = (N + 15) / 16;
+    // this lane's A-row pixel in its wavefront's first tile, and the step to
+    // the next tile (64 pixels on) in rows and columns
+    const int p0 = w * 16 + r16, r0 = p0 / L, c0 = p0 - r0 * L;
+    const int dr64 = 64 / L, dc64 = 64 - dr64 * L;
+    const int plast = (L + 1) * W2 - 2;  // padded index of pixel N - 1 (row L-1, column L-1)
+    __syncthreads();
     __bf16* in = buf0;
     __bf16* out = buf1;
     for (int l = 0; l < NL; ++l) {
         const bool first = l == 0, last = l == NL - 1;
-        const Taps taps = taps_for_dev(l);
+        const int nt = first ? 4 : 5;
         const __bf16* Wl = wf + (int64_t)l * NT * C * C;
-        bf16x8 Bf[NT][2];
+        bf16x8 Wa[NT][2];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
-                Bf[t][cb] = (t < taps.n) ? load8(Wl + ((int64_t)t * C + 16 * cb + r16) * C + kg * 8) : zero8();
-        const float bj0 = bias[l * C + r16], bj1 = bias[l * C + 16 + r16];
+            for (int cb = 0; cb < 2; ++cb) Wa[t][cb] = load8(Wl + ((int64_t)t * C + 16 * cb + r16) * C + kg * 8);
+        const f32x4 bj0 = *reinterpret_cast<const f32x4*>(bias + l * C + 4 * kg);
+        const f32x4 bj1 = *reinterpret_cast<const f32x4*>(bias + l * C + 16 + 4 * kg);
+        const int toff[NT] = {-W2 - 1, -W2, -W2 + 1, -1, 0};
+        int r = r0, c = c0;
+#pragma unroll 1
         for (int tile = w; tile < ntiles; tile += 4) {
-            const int p = tile * 16 + r16;
-            const int r = p / L, c = p - (p / L) * L;
+            // the ragged tail reads a valid pixel; its outputs are dropped
+            const int pid = (tile * 16 + r16 < N) ? (r + 1) * W2 + c + 1 : plast;
             f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                if (t >= taps.n) break;
-                const int rr = r + taps.dr[t], cc = c + taps.dc[t];
-                const bool ok = p < N && rr >= 0 && rr < L && cc >= 0 && cc < L;
-                const bf16x8 a = ok ? *reinterpret_cast<const bf16x8*>(in + swz(rr * L + cc, kg)) : zero8();
-                acc0 = mfma16(a, Bf[t][0], acc0);
-                if (!last) acc1 = mfma16(a, Bf[t][1], acc1);
+                if (t >= nt) break;
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(in + swz(pid + toff[t], kg));
+                acc0 = mfma16(Wa[t][0], a, acc0);
+                if (!last) acc1 = mfma16(Wa[t][1], a, acc1);
             }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int pi = tile * 16 + 4 * kg + v;
-                if (pi >= N) continue;
+            const int pi = tile * 16 + r16;  // this lane's pixel (its D column)
+            if (pi < N) {
                 if (last) {
-                    if (r16 == 0) logit[b * N + pi] = acc0[v] + bj0;
+                    if (kg == 0) logit[b * N + pi] = acc0[0] + bj0[0];
                 } else {
-                    const int o0 = swz_el(pi, r16), o1 = swz_el(pi, 16 + r16);
-                    out[o0] = hidden_out(first, acc0[v], bj0, first ? (__bf16)0.0f : in[o0]);
-                    out[o1] = hidden_out(first, acc1[v], bj1, first ? (__bf16)0.0f : in[o1]);
+                    const int o0 = swz_el(pid, 4 * kg), o1 = swz_el(pid, 16 + 4 * kg);
+                    const bf16x4 r0 = first ? zero4() : *reinterpret_cast<const bf16x4*>(in + o0);
+                    const bf16x4 r1 = first ? zero4() : *reinterpret_cast<const bf16x4*>(in + o1);
+                    *reinterpret_cast<bf16x4*>(out + o0) = hidden_out4(first, acc0, bj0, r0);
+                    *reinterpret_cast<bf16x4*>(out + o1) = hidden_out4(first, acc1, bj1, r1);
                 }
+            }
+            r += dr64;
+            c += dc64;
+            if (c >= L) {
+                c -= L;
+                ++r;
             }
         }
         __syncthreads();
@@ -512,7 +547,8 @@ __global__ void __launch_bounds__(256) score_fused_kernel(int64_t n, int L, cons
 }
 
 constexpr int kSeqChains = 32;
-constexpr int kSeqLdsBytes = (NL * NT * C * C + NL * kSeqChains * C + 2 * kSeqChains * C + C) * 2 + kSeqChains * 4;
+constexpr int kSeqLdsBytes =
+    (NL * NT * C * C + NL * kSeqChains * C + 2 * kSeqChains * C + C) * 2 + kSeqChains * 4 + NL * C * 4;
 
 // Ancestral sampler: a workgroup of four wavefronts draws 32 configurations
 // site by site in raster order.  Wavefront w computes chains 16 (w & 1) ..+15
@@ -521,7 +557,9 @@ constexpr int kSeqLdsBytes = (NL * NT * C * C + NL * kSeqChains * C + 2 * kSeqCh
 // weights (120 KB), the activations of every layer at the previous site
 // (the (0,-1) tap) and at the current site (the centre tap, double-buffered
 // by layer parity).  The three taps in the row above come from a two-row ring
-// in global memory, prefetched three layers ahead.  Spin i is +1 iff u < sigmoid
+// in global memory, prefetched three layers ahead.  The weights are the A
+// operand and the activations the B operand, so each lane ends a layer with
+// four consecutive channels of one chain (8-byte LDS and global stores).  Spin i is +1 iff u < sigmoid
 // (logit) with u the top 24 bits of Philox (ctr = (site, step, chain,
 // id << 3 | 6)); the logits go to logit_out for the log q sum.
 __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int64_t npad, int L, const __bf16* __restrict__ wf,
@@ -535,6 +573,7 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int64_t npad, int
     __bf16* tile = prev + NL * kSeqChains * C;  // [2][32 chains][C]: h_l at the current site
     __bf16* zrow = tile + 2 * kSeqChains * C;   // [C] zeros: operand of taps outside the lattice
     float* xl = reinterpret_cast<float*>(zrow + C);  // [32] logits
+    float* bl = xl + kSeqChains;                     // [NL][C] biases
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int chh = w & 1, coh = w >> 1;
     const int r16 = lane & 15, kg = lane >> 4;
@@ -546,12 +585,15 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int64_t npad, int
     }
     for (int g = tid; g < NL * kSeqChains * 4; g += blockDim.x) *reinterpret_cast<bf16x8*>(prev + g * 8) = zero8();
     if (tid < 4) *reinterpret_cast<bf16x8*>(zrow + tid * 8) = zero8();
-    const int oc = 16 * coh + r16;  // B column / D column: output channel of this lane
-    const int ca = 16 * chh + r16;  // A row: chain within the workgroup
+    for (int g = tid; g < NL * C; g += blockDim.x) bl[g] = bias[g];
+    // Operand roles: the weights are the A operand (row = output channel of
+    // this wavefront's 16-channel half), the activations the B operand
+    // (column = chain); a lane's D values are the four consecutive output
+    // channels oc4 .. oc4 + 3 of its own chain ca.
+    const int oc = 16 * coh + r16;  // A row: output channel of this lane's weight fragment
+    const int ca = 16 * chh + r16;  // B / D column: chain within the workgroup
+    const int oc4 = 16 * coh + 4 * kg;
     const int64_t gca = base + ca;  // the ring has npad >= n chains: padding rows have their own slots
-    float bj[NL];
-#pragma unroll
-    for (int l = 0; l < NL; ++l) bj[l] = bias[l * C + oc];
     // ring element (layer, chain, row, column): [NL][npad][2][L][C]
     auto ridx = [&](int l, int64_t chain, int r, int c) -> int64_t {
         return ((((int64_t)l * npad + chain) * 2 + (r & 1)) * L + c) * C;
@@ -570,15 +612,15 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int64_t npad, int
     };
 #pragma unroll
     for (int l = 0; l < kAhead; ++l) fetch(pr[l], l, 0, 0);
-    __bf16 pend[NL][4];
+    bf16x4 pend[NL];
     __syncthreads();
     for (int site = 0; site < N; ++site) {
         const int r = site / L, c = site - r * L;
         const int sn = site + 1, rn = sn / L, cn = sn - rn * L;
         const bool more = sn < N;
-        // ring offset of this lane's first output (layer 0, chain 16 chh + 4 kg)
-        const int64_t ring_lane = ridx(0, base + 16 * chh + 4 * kg, r, c) + oc;
-        const int64_t ring_layer = (int64_t)npad * 2 * L * C, ring_chain = (int64_t)2 * L * C;
+        // ring offset of this lane's outputs at layer 0 (chain ca, channels oc4..)
+        const int64_t ring_lane = ridx(0, gca, r, c) + oc4;
+        const int64_t ring_layer = (int64_t)npad * 2 * L * C;
         float u = 0.f;
         if (w == 0) {
             const gk::P4 q = gk::philox((uint32_t)site, step, (uint32_t)(base + (lane & 31)), (id << 3) | 6u,
@@ -597,34 +639,25 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int64_t npad, int
                 for (int t = 0; t < NT; ++t) bw[t] = (t < 4 || l > 0) ? load8(Wl + t * C * C + swz(oc, kg)) : zero8();
                 const bf16x8 a3 = load8((c > 0) ? prev + l * kSeqChains * C + swz(ca, kg) : zrow + kg * 8);
                 const bf16x8 a4 = (l > 0) ? load8(tl + swz(ca, kg)) : zero8();
-                __bf16 res[4];  // residual inputs of this lane's four outputs
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    res[v] = (l > 0 && l < NL - 1) ? tl[swz_el(16 * chh + 4 * kg + v, oc)] : (__bf16)0.0f;
+                const f32x4 bj = *reinterpret_cast<const f32x4*>(bl + l * C + oc4);
+                const bf16x4 res = (l > 0 && l < NL - 1) ? *reinterpret_cast<const bf16x4*>(tl + swz_el(ca, oc4))
+                                                         : zero4();  // residual inputs of the four outputs
                 f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int t = 0; t < 3; ++t) acc = mfma16(pr[l % kAhead][t], bw[t], acc);
-                acc = mfma16(a3, bw[3], acc);
-                if (l > 0) acc = mfma16(a4, bw[4], acc);
+                for (int t = 0; t < 3; ++t) acc = mfma16(bw[t], pr[l % kAhead][t], acc);
+                acc = mfma16(bw[3], a3, acc);
+                if (l > 0) acc = mfma16(bw[4], a4, acc);
                 if (l < NL - 1) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int ci = 16 * chh + 4 * kg + v;
-                        const __bf16 hn = hidden_out(l == 0, acc[v], bj[l], res[v]);
-                        tn[swz_el(ci, oc)] = hn;
-                        pend[l + 1][v] = hn;
-                        ring[ring_lane + (l + 1) * ring_layer + v * ring_chain] = hn;
-                    }
-                } else if (r16 == 0) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) xl[16 * chh + 4 * kg + v] = acc[v] + bj[l];
+                    const bf16x4 hn = hidden_out4(l == 0, acc, bj, res);
+                    *reinterpret_cast<bf16x4*>(tn + swz_el(ca, oc4)) = hn;
+                    pend[l + 1] = hn;
+                    *reinterpret_cast<bf16x4*>(ring + ring_lane + (l + 1) * ring_layer) = hn;
+                } else if (kg == 0) {
+                    xl[ca] = acc[0] + bj[0];  // the logit: output channel 0
                 }
             }
             // every wavefront has read prev[l - 1] (before the last barrier): store this site's h_{l-1}
-            if (l >= 2) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) prev[(l - 1) * kSeqChains * C + swz_el(16 * chh + 4 * kg + v, oc)] = pend[l - 1][v];
-            }
+            if (l >= 2) *reinterpret_cast<bf16x4*>(prev + (l - 1) * kSeqChains * C + swz_el(ca, oc4)) = pend[l - 1];
             // refill this slot with the layer three ahead (of this site or the next)
             if (l + kAhead < NL)
                 fetch(pr[l % kAhead], l + kAhead, r, c);
@@ -632,9 +665,7 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int64_t npad, int
                 fetch(pr[l % kAhead], l + kAhead - NL, rn, cn);
             __syncthreads();
         }
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-            prev[(NL - 1) * kSeqChains * C + swz_el(16 * chh + 4 * kg + v, oc)] = pend[NL - 1][v];
+        *reinterpret_cast<bf16x4*>(prev + (NL - 1) * kSeqChains * C + swz_el(ca, oc4)) = pend[NL - 1];
         if (w == 0 && lane < kSeqChains) {
             const int64_t ch = base + lane;
             const float x = xl[lane];
@@ -972,7 +1003,7 @@ int run_score(crbm_ar_t* a, int64_t n, const int8_t* spins, double* logq) {
     const int64_t P = n * L * L;
     hipStream_t st = a->stream;
     if (L <= kFuseMaxL) {
-        const int lds = 2 * L * L * C * (int)sizeof(__bf16);
+        const int lds = 2 * fused_pixels(L) * C * (int)sizeof(__bf16);
         AR_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&score_fused_kernel),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds),
                "scorer LDS size");
