@@ -74,6 +74,7 @@ def lib():
         L.oracle_bond_sites.argtypes = [ct.c_int] * 4 + [p(ct.c_int)] * 5
         L.oracle_counts.argtypes = [ct.c_int, p(ct.c_int8), p(i64), p(i64), p(i64)]
         L.oracle_corr.argtypes = [ct.c_int, p(ct.c_int8), p(i64)]
+        L.oracle_order.argtypes = [ct.c_int, p(ct.c_int8), p(i64)]
         L.oracle_init_spins.argtypes = [p(_Instance), ct.c_uint64, u32, p(ct.c_int8)]
         L.oracle_run_chain.argtypes = [p(_Instance), i64, ct.c_uint64, u32, i64, i64,
                                        p(ct.c_int8), p(i32), i32, i64, p(i64)]
@@ -166,6 +167,14 @@ def corr(L, spins) -> np.ndarray:
     out = np.zeros(L * L, np.int64)
     lib().oracle_corr(L, _ptr(s, ct.c_int8), _ptr(out, ct.c_int64))
     return out.reshape(L, L)
+
+
+def order(L, spins) -> tuple[int, int, int]:
+    """(max, |S(pi, 2pi/3)|^2, |S(2pi/3, pi)|^2) of one configuration (exact integers)."""
+    s = np.ascontiguousarray(spins, np.int8).reshape(L * L)
+    out = np.zeros(3, np.int64)
+    lib().oracle_order(L, _ptr(s, ct.c_int8), _ptr(out, ct.c_int64))
+    return int(out[0]), int(out[1]), int(out[2])
 
 
 def init_spins(inst: Instance, seed: int, chain: int) -> np.ndarray:

@@ -275,6 +275,29 @@ void oracle_corr(int L, const int8_t* s, int64_t* corr)
         }
 }
 
+/* Plateau structure factor (Sec. III.B Eq. (13) at the 1/3-plateau wave
+ * vectors): out[1] = |sum_{r,c} s(r,c) exp(i (pi r + 2 pi c / 3))|^2,
+ * out[2] = |sum s(r,c) exp(i (2 pi r / 3 + pi c))|^2, out[0] = max of the two.
+ * The true values are integers (the sums lie in Z[e^{2 pi i/3}]); they are
+ * evaluated here with cos/sin in double and rounded. */
+void oracle_order(int L, const int8_t* s, int64_t out[3])
+{
+    const double pi = 3.14159265358979323846;
+    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+    for (int r = 0; r < L; ++r)
+        for (int c = 0; c < L; ++c) {
+            const double v = s[r * L + c];
+            const double pa = pi * r + 2.0 * pi * c / 3.0, pb = 2.0 * pi * r / 3.0 + pi * c;
+            ar += v * cos(pa);
+            ai += v * sin(pa);
+            br += v * cos(pb);
+            bi += v * sin(pb);
+        }
+    out[1] = llround(ar * ar + ai * ai);
+    out[2] = llround(br * br + bi * bi);
+    out[0] = out[1] > out[2] ? out[1] : out[2];
+}
+
 /* ------------------------------------------------------------- one chain */
 
 static int sweep_params(const oracle_instance* in, int64_t S, int64_t s,

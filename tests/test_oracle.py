@@ -227,6 +227,47 @@ def test_structure_factor_of_perfect_states():
 
 # --------------------------------------------------------- dynamics pins
 
+def _uud(L, transpose=False, shift=0):
+    """The 1/3-plateau UUD pattern: ferromagnetic rows (all up) every third row,
+    between them two antiferromagnetic rows (Sec. III.A)."""
+    s = np.zeros((L, L), np.int8)
+    for r in range(L):
+        k = (r + shift) % 3
+        s[r] = 1 if k == 0 else (2 * ((np.arange(L) + k) % 2) - 1)
+    return s.T.copy() if transpose else s
+
+
+@pytest.mark.parametrize("L", [6, 12, 18])
+def test_order_parameter_closed_forms(L):
+    """Plateau structure factor |S(q*)|^2 at q* = (pi, 2pi/3) and (2pi/3, pi):
+    the ferromagnet and the Neel state have none; each UUD state puts N^2/3 on
+    its own orientation's wave vector (S(q*)/N = N/3, Sec. III.B), for every
+    translation, and the transpose swaps the two components."""
+    N = L * L
+    assert oracle.order(L, np.ones((L, L), np.int8)) == (0, 0, 0)
+    neel = (2 * ((np.arange(L)[:, None] + np.arange(L)[None, :]) % 2) - 1).astype(np.int8)
+    assert oracle.order(L, neel) == (0, 0, 0)
+    for shift in range(3):
+        s = _uud(L, shift=shift)  # period 3 along rows, antiferromagnetic along columns
+        assert oracle.order(L, s) == (N * N // 3, 0, N * N // 3)
+        assert oracle.order(L, s.T.copy()) == (N * N // 3, N * N // 3, 0)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_order_parameter_matches_fft(seed):
+    """On random states the two components equal |DFT|^2 of the spins at the
+    two wave vectors (numpy FFT on 6x6 and 12x12, where 2pi/3 is a lattice
+    momentum)."""
+    rng = np.random.default_rng(seed)
+    for L in (6, 12):
+        s = (2 * rng.integers(0, 2, (L, L)) - 1).astype(np.int8)
+        F = np.fft.fft2(s.astype(np.float64))
+        a = abs(F[L // 2, (2 * L // 3) % L]) ** 2  # q = (pi, -2pi/3): same modulus as (pi, 2pi/3)
+        b = abs(F[(2 * L // 3) % L, L // 2]) ** 2
+        m, oa, ob = oracle.order(L, s)
+        assert oa == round(a) and ob == round(b) and m == max(oa, ob)
+
+
 def test_trajectory_is_resumable_and_deterministic():
     inst = oracle.Instance(6, 1.0, 0.5, 0.0, "linear", 3.0, 0.1, id=4)
     s1, t1, _ = oracle.run_chain(inst, 400, 123, 2, 0, 400, trace=True)
