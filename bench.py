@@ -167,7 +167,9 @@ def learned_mh(crbm, torch, temps=(0.4, 0.2, 0.1), steps=800, cycles=500):
                        "(4096 chains annealed 5->T over 2e4 sweeps, 256 snapshots 20 sweeps apart, translation "
                        "and transpose augmentation); 8192 chains, 1 MH : 10 Gibbs vs plain Gibbs at equal wall "
                        "time, seeded +-1 start, first 20% discarded",
-           "reference": "exact <E>/N by 12x12 row transfer matrix", "points": []}
+           "reference": "exact <E>/N by 12x12 row transfer matrix",
+           "ess": "energy ESS (ess_per_s) and min over {energy, O_1/3 = max |S(q*)|^2/N^2} (ess_min_per_s)",
+           "points": []}
     for T in temps:
         t0 = time.perf_counter()
         data = learned.training_set(L, 1.0, 1.0, 3.0, T)
@@ -187,7 +189,8 @@ def learned_mh(crbm, torch, temps=(0.4, 0.2, 0.1), steps=800, cycles=500):
             r[k]["bias_se"] = d / r[k]["se"] if r[k]["se"] > 0 else (0.0 if abs(d) < 1e-12 else None)
         r.update({"T": T, "E_ref": ref[T], "data_s": t_data, "train_s": t_train, "train_steps": steps,
                   "final_loss_per_site": loss,
-                  "ess_ratio": r["learned"]["ess_per_s"] / r["gibbs"]["ess_per_s"]})
+                  "ess_ratio": r["learned"]["ess_per_s"] / r["gibbs"]["ess_per_s"],
+                  "ess_min_ratio": r["learned"]["ess_min_per_s"] / r["gibbs"]["ess_min_per_s"]})
         out["points"].append(r)
         del net
         torch.cuda.empty_cache()

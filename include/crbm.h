@@ -128,10 +128,14 @@ int crbm_sample(crbm_t* h, int64_t n_sweeps, int8_t* spins_out, int32_t* counts_
 /* As crbm_sample, with the counts trace thinned: (M, B1, B2) is recorded
  * after every trace_every-th sweep of this call only, layout
  * [n_sweeps / trace_every][chain][3] (for autocorrelation estimates over long
- * runs).  trace_every must be >= 1 and divide n_sweeps, else CRBM_EINVAL.
- * crbm_sample is the case trace_every = 1. */
+ * runs).  order_trace (device, may be NULL; needs counts_trace): at the same
+ * sweeps, the 1/3-plateau structure factor of Sec. III.B Eq. (13) as exact
+ * integers (max, |S_A|^2, |S_B|^2) with S_A = sum s(r,c) e^{i(pi r + 2 pi c/3)}
+ * and S_B = sum s(r,c) e^{i(2 pi r/3 + pi c)}, same layout; O_1/3 = max / N^2.
+ * trace_every must be >= 1 and divide n_sweeps, else CRBM_EINVAL.
+ * crbm_sample is the case trace_every = 1, no order trace. */
 int crbm_sample_thinned(crbm_t* h, int64_t n_sweeps, int8_t* spins_out, int32_t* counts_trace,
-                        int32_t trace_every);
+                        int32_t* order_trace, int32_t trace_every);
 
 /* Synchronise the stream and fill out[n_inst] from the exact int64
  * accumulators.  corr_out: host pointer or NULL; if given, receives for each
@@ -239,9 +243,11 @@ int crbm_ar_sample(crbm_ar_t* a, int64_t n, uint64_t seed, int64_t step, uint32_
  * the network's life draws its proposals with step = k and its MH uniform from
  * Philox (ctr = (0, k, chain, id << 3 | 5)).  counts_trace
  * (device, may be NULL): int32 (M, B1, B2) after each cycle, [n_cycles][chains][3].
+ * order_trace (device, may be NULL): the plateau structure factor record of
+ * crbm_sample_thinned after each cycle, same layout.
  * n_accepted (host, may be NULL): accepted moves (synchronises). */
 int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_mh, int32_t* counts_trace,
-                   int64_t* n_accepted);
+                   int32_t* order_trace, int64_t* n_accepted);
 void crbm_ar_destroy(crbm_ar_t* a);
 
 /* Free everything the handle owns.  NULL is allowed. */

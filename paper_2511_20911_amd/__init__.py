@@ -83,7 +83,7 @@ def lib() -> ct.CDLL:
         p = ct.POINTER
         L.crbm_create.argtypes = [p(_Instance), ct.c_int32, p(_Config), p(ct.c_void_p)]
         L.crbm_sample.argtypes = [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p]
-        L.crbm_sample_thinned.argtypes = [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_int32]
+        L.crbm_sample_thinned.argtypes = [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int32]
         L.crbm_observables.argtypes = [ct.c_void_p, p(_Obs), ct.c_void_p]
         L.crbm_get_state.argtypes = [ct.c_void_p, ct.c_void_p, p(ct.c_int64)]
         L.crbm_set_state.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64]
@@ -111,7 +111,8 @@ def lib() -> ct.CDLL:
         L.crbm_ar_logq.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p]
         L.crbm_ar_sample.argtypes = [ct.c_void_p, ct.c_int64, ct.c_uint64, ct.c_int64, ct.c_uint32, ct.c_void_p,
                                      ct.c_void_p]
-        L.crbm_sample_mh.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p, p(ct.c_int64)]
+        L.crbm_sample_mh.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p, ct.c_void_p,
+                                     p(ct.c_int64)]
         L.crbm_ar_destroy.argtypes = [ct.c_void_p]
         L.crbm_ar_destroy.restype = None
         L.crbm_tau_int.argtypes = [ct.c_void_p, ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int64,
@@ -243,18 +244,22 @@ class Sampler:
     def total_spins(self) -> int:
         return int(self.spin_offsets[-1])
 
-    def sample(self, n_sweeps: int, spins_out=None, trace=None, trace_every: int = 1):
+    def sample(self, n_sweeps: int, spins_out=None, trace=None, trace_every: int = 1, order=None):
         """Enqueue n_sweeps sweeps.  spins_out: int8 CUDA tensor of total_spins
         elements; trace: int32 CUDA tensor [n_sweeps // trace_every, total_chains, 3]
-        recording the counts after every trace_every-th sweep."""
+        recording the counts after every trace_every-th sweep; order (needs
+        trace): same shape, the plateau structure factor (max, |S_A|^2, |S_B|^2)."""
         if spins_out is not None:
             assert spins_out.is_cuda and spins_out.dtype.itemsize == 1 and spins_out.numel() == self.total_spins
         if trace is not None:
             assert trace.is_cuda and trace.element_size() == 4
             assert trace.numel() == (n_sweeps // trace_every) * self.total_chains * 3
+        if order is not None:
+            assert trace is not None and order.is_cuda and order.element_size() == 4 and order.numel() == trace.numel()
         _check(lib().crbm_sample_thinned(self._h, n_sweeps,
                                          ct.c_void_p(spins_out.data_ptr()) if spins_out is not None else None,
                                          ct.c_void_p(trace.data_ptr()) if trace is not None else None,
+                                         ct.c_void_p(order.data_ptr()) if order is not None else None,
                                          int(trace_every)))
 
     def observables(self, corr: bool = False):
@@ -367,10 +372,13 @@ class ARNet:
         return spins, lq
 
 
-def sample_mh(sampler: Sampler, net: ARNet, n_cycles: int, gibbs_per_mh: int, trace=None) -> int:
+def sample_mh(sampler: Sampler, net: ARNet, n_cycles: int, gibbs_per_mh: int, trace=None, order=None) -> int:
     """n_cycles of gibbs_per_mh Gibbs sweeps then one independent-MH step with
-    the network's proposals.  Returns the number of accepted moves."""
+    the network's proposals.  trace / order: int32 CUDA tensors [n_cycles,
+    chains, 3] for the counts and the plateau structure factor after each
+    cycle.  Returns the number of accepted moves."""
     acc = ct.c_int64()
     _check(lib().crbm_sample_mh(sampler._h, net._h, n_cycles, gibbs_per_mh,
-                                ct.c_void_p(trace.data_ptr()) if trace is not None else None, ct.byref(acc)))
+                                ct.c_void_p(trace.data_ptr()) if trace is not None else None,
+                                ct.c_void_p(order.data_ptr()) if order is not None else None, ct.byref(acc)))
     return int(acc.value)

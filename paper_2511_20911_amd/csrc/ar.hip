@@ -690,16 +690,27 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int64_t npad, int
 namespace crbmlib {
 namespace ar {
 
-// Exact integer (M, B1, B2) of int8 configurations, one wavefront per chain.
-__global__ void __launch_bounds__(256) counts_int8_kernel(const int8_t* s, int64_t n, int L, int32_t* out) {
+// Exact integer (M, B1, B2) of int8 configurations, one wavefront per chain;
+// with ord != nullptr also the plateau structure factor record
+// (max, |S_A|^2, |S_B|^2) from A_k = sum (-1)^r s over columns = k (mod 3) and
+// B_k = sum (-1)^c s over rows = k (mod 3).
+__global__ void __launch_bounds__(256) counts_int8_kernel(const int8_t* s, int64_t n, int L, int32_t* out,
+                                                          int32_t* ord) {
     const int lane = threadIdx.x & 63;
     const int64_t ch = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (ch >= n) return;  // uniform per wavefront
     const int8_t* x = s + ch * L * L;
     int M = 0, B1 = 0, B2 = 0;
+    int A[3] = {0, 0, 0}, B[3] = {0, 0, 0};
     for (int i = lane; i < L * L; i += 64) {
         const int r = i / L, c = i - (i / L) * L;
         const int v = x[i];
+        const int va = (r & 1) ? -v : v, vb = (c & 1) ? -v : v, cm = c % 3, rm = r % 3;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            A[k] += (cm == k) ? va : 0;
+            B[k] += (rm == k) ? vb : 0;
+        }
         M += v;
         B1 += v * x[r * L + (c + 1) % L] + v * x[((r + 1) % L) * L + c];
         if ((r & 1) == 0 && (c & 1) == 0) B2 += v * x[(r + 1) * L + c + 1];          // '\\' dimer
@@ -710,11 +721,26 @@ __global__ void __launch_bounds__(256) counts_int8_kernel(const int8_t* s, int64
         M += __shfl_xor(M, d);
         B1 += __shfl_xor(B1, d);
         B2 += __shfl_xor(B2, d);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            A[k] += __shfl_xor(A[k], d);
+            B[k] += __shfl_xor(B[k], d);
+        }
     }
     if (lane == 0) {
         out[ch * 3] = M;
         out[ch * 3 + 1] = B1;
         out[ch * 3 + 2] = B2;
+        if (ord) {
+            auto sq3 = [](const int (&v)[3]) {
+                const int64_t p = v[0], q = v[1], t = v[2];
+                return p * p + q * q + t * t - p * q - q * t - t * p;
+            };
+            const int64_t sa = sq3(A), sb = sq3(B);
+            ord[ch * 3] = (int32_t)(sa > sb ? sa : sb);
+            ord[ch * 3 + 1] = (int32_t)sa;
+            ord[ch * 3 + 2] = (int32_t)sb;
+        }
     }
 }
 
@@ -1177,7 +1203,7 @@ void crbm_ar_destroy(crbm_ar_t* a) {
 }
 
 int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_mh, int32_t* counts_trace,
-                   int64_t* n_accepted) {
+                   int32_t* order_trace, int64_t* n_accepted) {
     if (!h || !a || n_cycles < 0 || gibbs_per_mh < 0) return fail_ar(CRBM_EINVAL, "bad arguments");
     HandleView v{};
     if (handle_view(h, &v) != CRBM_OK) return fail_ar(CRBM_EINVAL, "bad handle");
@@ -1211,17 +1237,22 @@ int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_
         if (cyc == 0 || gibbs_per_mh > 0) {
             if (handle_view(h, &v) != CRBM_OK) return fail_ar(CRBM_EINVAL, "bad handle");
             AR_TRY(launch_unpack(v.state, a->cur, n, v.L, st), "unpack state");
-            hipLaunchKernelGGL(counts_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->cur, n, v.L, a->ccur);
+            hipLaunchKernelGGL(counts_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->cur, n, v.L, a->ccur,
+                               (int32_t*)nullptr);
             rc = run_score(a, n, a->cur, a->lqc);
             if (rc != CRBM_OK) return rc;
         }
         const uint32_t step = (uint32_t)(a->mh_step++);
         rc = run_seq(a, n, a->prop, a->lqp, v.seed, step, v.id);
         if (rc != CRBM_OK) return rc;
-        hipLaunchKernelGGL(counts_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->prop, n, v.L, a->cprop);
+        hipLaunchKernelGGL(counts_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->prop, n, v.L, a->cprop,
+                           (int32_t*)nullptr);
         hipLaunchKernelGGL(mh_kernel, dim3(nb), dim3(256), 0, st, n, v.L, a->cur, a->prop, a->ccur, a->cprop, a->lqc,
                            a->lqp, v.a, v.c1, v.c2, v.sg1, v.sg2, v.seed, step, v.id, a->nacc);
         AR_TRY(launch_pack(v.state, a->cur, n, v.L, st), "pack state");
+        if (order_trace)  // recounts the current states (same counts) with the structure factor
+            hipLaunchKernelGGL(counts_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->cur, n, v.L,
+                               a->ccur, order_trace + cyc * n * 3);
         if (counts_trace)
             AR_TRY(hipMemcpyAsync(counts_trace + cyc * n * 3, a->ccur, sizeof(int32_t) * n * 3, hipMemcpyDeviceToDevice, st),
                    "trace");

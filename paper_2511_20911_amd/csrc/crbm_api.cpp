@@ -178,7 +178,7 @@ struct crbm_s {
 namespace {
 
 GibbsArgs make_args(const crbm_s* h, const Group& g, size_t gi, int64_t s0, int64_t s1, int8_t* spins_out,
-                    int32_t* trace, int32_t trace_every = 1) {
+                    int32_t* trace, int32_t trace_every = 1, int32_t* order = nullptr) {
     GibbsArgs a{};
     a.state = h->d_state;
     a.tables = h->d_tables;
@@ -192,6 +192,7 @@ GibbsArgs make_args(const crbm_s* h, const Group& g, size_t gi, int64_t s0, int6
     a.acc = h->d_acc;
     a.trace = trace;
     a.trace_every = trace_every;
+    a.order = order;
     a.total_chains = h->total_chains;
     a.spins_out = spins_out;
     a.queue = (h->cfg.launch_mode == CRBM_LAUNCH_GRAPH) ? h->d_queue + gi : nullptr;
@@ -444,21 +445,23 @@ int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cf
 }
 
 int crbm_sample(crbm_t* h, int64_t n_sweeps, int8_t* spins_out, int32_t* counts_trace) {
-    return crbm_sample_thinned(h, n_sweeps, spins_out, counts_trace, 1);
+    return crbm_sample_thinned(h, n_sweeps, spins_out, counts_trace, nullptr, 1);
 }
 
 int crbm_sample_thinned(crbm_t* h, int64_t n_sweeps, int8_t* spins_out, int32_t* counts_trace,
-                        int32_t trace_every) {
+                        int32_t* order_trace, int32_t trace_every) {
     g_err.clear();
     if (!h) return fail(CRBM_EINVAL, "handle is NULL");
     if (n_sweeps < 0) return fail(CRBM_EINVAL, "n_sweeps must be >= 0");
     if (trace_every < 1 || n_sweeps % trace_every != 0)
         return fail(CRBM_EINVAL, "trace_every must be >= 1 and divide n_sweeps");
+    if (order_trace && !counts_trace) return fail(CRBM_EINVAL, "order_trace needs counts_trace");
     if (h->cur + n_sweeps > h->S) return fail(CRBM_ESTATE, "sampling past the end of the schedule");
     if (h->cfg.launch_mode == CRBM_LAUNCH_GRAPH) {
         for (size_t gi = 0; gi < h->groups.size(); ++gi) {
             Group& g = h->groups[gi];
-            GibbsArgs a = make_args(h, g, gi, h->cur, h->cur + n_sweeps, spins_out, counts_trace, trace_every);
+            GibbsArgs a =
+                make_args(h, g, gi, h->cur, h->cur + n_sweeps, spins_out, counts_trace, trace_every, order_trace);
             void* args[] = {&a};
             hipKernelNodeParams p{};
             p.func = const_cast<void*>(gibbs_kernel_fn(g.L, g.R));
@@ -474,7 +477,7 @@ int crbm_sample_thinned(crbm_t* h, int64_t n_sweeps, int8_t* spins_out, int32_t*
     } else {
         for (size_t gi = 0; gi < h->groups.size(); ++gi) {
             const GibbsArgs a = make_args(h, h->groups[gi], gi, h->cur, h->cur + n_sweeps, spins_out, counts_trace,
-                                          trace_every);
+                                          trace_every, order_trace);
             HIP_TRY(launch_gibbs(h->groups[gi].L, h->groups[gi].R, a, h->stream), "gibbs kernel");
         }
     }

@@ -43,6 +43,7 @@ struct GibbsArgs {
     int64_t* acc;             // [global chain][11] int64 accumulators
     int32_t* trace;           // [(s1 - s0) / trace_every][total_chains][3] or nullptr
     int32_t trace_every;      // record after every trace_every-th sweep of the call
+    int32_t* order;           // plateau structure factor trace, same layout as trace, or nullptr
     int64_t total_chains;
     int8_t* spins_out;        // int8 spins at Item::spin_off, or nullptr
     uint32_t* queue;          // persistent mode: work counter (zeroed before launch); nullptr = direct

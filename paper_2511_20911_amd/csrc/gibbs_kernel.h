@@ -89,6 +89,14 @@ struct Geo {
         return m(w) == 32 ? 0xffffffffu : ((1u << m(w)) - 1u);
     }
     __host__ __device__ static constexpr uint32_t even(int w) { return 0x55555555u & full(w); }
+    // columns 32 w + b with (32 w + b) mod 3 == k
+    __host__ __device__ static constexpr uint32_t mod3(int w, int k) {
+        uint32_t m = 0u;
+        for (int b = 0; b < 32; ++b)
+            if ((32 * w + b) % 3 == k) m |= 1u << b;
+        return m & full(w);
+    }
+    __host__ __device__ static constexpr int cnt3(int k) { return (L - k + 2) / 3; }  // columns c < L, c % 3 == k
 };
 
 // bit c of word w <- column 32w + c + S (mod L), S in {1, 2}
@@ -479,7 +487,44 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
                     dis2 += __popc((tp[w] ^ rsh<L, 1>(md, w)) & Gm::even(w)) +
                             __popc((rsh<L, 2>(md, w) ^ rsh<L, 1>(bt, w)) & Gm::even(w));
             }
+            // plateau structure factor sums: A_k = sum (-1)^r s over columns = k (mod 3),
+            // B_k = sum (-1)^c s over rows = k (mod 3)
+            const bool want_order = rec && a.order != nullptr;
+            int oa[3] = {0, 0, 0}, ob[3] = {0, 0, 0};
+            if (want_order) {
+#pragma unroll
+                for (int x = 0; x < NR; ++x) {
+                    const int row = g * NR + x;
+                    int pk[3] = {0, 0, 0}, pe = 0, po = 0;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) pk[k] += __popc(Q[x][w] & Gm::mod3(w, k));
+                        pe += __popc(Q[x][w] & Gm::even(w));
+                        po += __popc(Q[x][w] & ~Gm::even(w) & Gm::full(w));
+                    }
+                    const int sg = (row & 1) ? -1 : 1;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) oa[k] += sg * (2 * pk[k] - Gm::cnt3(k));
+                    const int rm = row % 3, e = 2 * (pe - po);
+                    ob[0] += (rm == 0) ? e : 0;
+                    ob[1] += (rm == 1) ? e : 0;
+                    ob[2] += (rm == 2) ? e : 0;
+                }
+            }
             int tp = pop, t1 = dis1, t2 = dis2;
+            int sa3[3] = {oa[0], oa[1], oa[2]}, sb3[3] = {ob[0], ob[1], ob[2]};  // chain totals
+            if (want_order) {
+#pragma unroll
+                for (int d = 1; d < G; ++d) {
+                    const int src = cl * G + (g + d) % G;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        sa3[k] += __shfl(oa[k], src);  // the other lanes' own partial sums
+                        sb3[k] += __shfl(ob[k], src);
+                    }
+                }
+            }
 #pragma unroll
             for (int d = 1; d < G; ++d) {
                 const int src = cl * G + (g + d) % G;
@@ -489,10 +534,23 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
             }
             const int64_t M = 2 * tp - N, B1 = 2 * N - 2 * t1, B2 = N / 2 - 2 * t2;
             if (rec && g == 0 && active) {
-                int32_t* tr = a.trace + ((uint64_t)((s - a.s0) / a.trace_every) * (uint64_t)a.total_chains + gch) * 3;
+                const uint64_t rix = ((uint64_t)((s - a.s0) / a.trace_every) * (uint64_t)a.total_chains + gch) * 3;
+                int32_t* tr = a.trace + rix;
                 tr[0] = (int32_t)M;
                 tr[1] = (int32_t)B1;
                 tr[2] = (int32_t)B2;
+                if (want_order) {
+                    // |A0 + A1 w + A2 w^2|^2 with w = exp(2 pi i / 3)
+                    auto sq3 = [](const int (&v)[3]) {
+                        const int64_t x = v[0], y = v[1], z = v[2];
+                        return x * x + y * y + z * z - x * y - y * z - z * x;
+                    };
+                    const int64_t sa = sq3(sa3), sb = sq3(sb3);
+                    int32_t* od = a.order + rix;
+                    od[0] = (int32_t)(sa > sb ? sa : sb);
+                    od[1] = (int32_t)sa;
+                    od[2] = (int32_t)sb;
+                }
             }
             if (meas) {
                 acc[0] += 1;

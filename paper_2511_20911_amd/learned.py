@@ -16,7 +16,9 @@ and moves data between device tensors:
   random augmented mini-batches;
 * compare: learned MH (1 MH step per `gibbs_per_mh` Gibbs sweeps) against
   plain Gibbs given the same wall-clock time, both from the same seeded start,
-  with tau_int / ESS of the energy from the library's estimator.
+  with tau_int / ESS of the energy and of the plateau order parameter
+  O_1/3 = max |S(q*)|^2 / N^2 (q* = (pi, 2pi/3), (2pi/3, pi); Sec. III.B) from
+  the library's estimator.
 
 The paper samples its CRBM by Gibbs only (Sec. II.B); the learned proposal is
 an addition that leaves the stationary law unchanged (exact MH acceptance on
@@ -89,18 +91,27 @@ def train(net: ARNet, data, steps=800, batch=1024, lr=1e-3, lr_late=3e-4, late_f
 @dataclass
 class ChainStats:
     E_per_spin: float      # mean over chains and kept samples
-    se: float              # standard error from the spread of the chain means
-    tau: float             # integrated autocorrelation time (in samples)
-    ess: float             # effective sample size (chains x kept samples / tau)
+    se: float              # standard error of <E>/N from the spread of the chain means
+    tau: float             # integrated autocorrelation time of the energy (in samples)
+    ess: float             # energy effective sample size (chains x kept samples / tau)
+    O: float               # mean plateau order parameter O_1/3 = max |S(q*)|^2 / N^2
+    O_se: float
+    tau_O: float           # integrated autocorrelation time of O_1/3
+    ess_min: float         # chains x kept samples / max(tau, tau_O)
     seconds: float         # wall time of the sampling phase
 
 
-def _stats(trace, weights, N, discard, seconds, max_lag):
+def _stats(trace, order, weights, N, discard, seconds, max_lag):
     t = trace[discard:].double()
     E = (weights[0] * t[..., 0] + weights[1] * t[..., 1] + weights[2] * t[..., 2]) / 65536.0 / N
     cm = E.mean(0)
     tau, ess, _, _ = tau_int(trace, weights, discard=discard, max_lag=max_lag)
-    return ChainStats(float(cm.mean()), float(cm.std() / math.sqrt(cm.numel())), tau, ess, seconds)
+    o = order[discard:, :, 0].double() / float(N * N)
+    om = o.mean(0)
+    tau_o, _, _, _ = tau_int(order, (1, 0, 0), discard=discard, max_lag=max_lag)
+    n_kept = t.shape[0] * t.shape[1]
+    return ChainStats(float(cm.mean()), float(cm.std() / math.sqrt(cm.numel())), tau, ess, float(om.mean()),
+                      float(om.std() / math.sqrt(om.numel())), tau_o, n_kept / max(tau, tau_o), seconds)
 
 
 def compare(net: ARNet, L, J1, J2, h, T, n_chains=8192, cycles=500, gibbs_per_mh=10, trace_every=50,
@@ -115,13 +126,14 @@ def compare(net: ARNet, L, J1, J2, h, T, n_chains=8192, cycles=500, gibbs_per_mh
     inst = Instance(L=L, J1=J1, J2=J2, h=h, n_chains=n_chains, sched="const", T0=T, id=id)
     mh = Sampler([inst], seed=seed, n_sweeps=max(1, cycles * gibbs_per_mh))
     tr = torch.empty((cycles, n_chains, 3), dtype=torch.int32, device="cuda")
+    od = torch.empty_like(tr)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    acc = sample_mh(mh, net, cycles, gibbs_per_mh, trace=tr)
+    acc = sample_mh(mh, net, cycles, gibbs_per_mh, trace=tr, order=od)
     torch.cuda.synchronize()
     t_mh = time.perf_counter() - t0
-    learned = _stats(tr, w, N, cycles // 5, t_mh, cycles // 2)
-    del tr, mh
+    learned = _stats(tr, od, w, N, cycles // 5, t_mh, cycles // 2)
+    del tr, od, mh
     # Gibbs sweep time at this size, then a run of the same wall time
     probe = Sampler([inst], seed=seed, n_sweeps=1100)
     probe.sample(100)
@@ -135,16 +147,19 @@ def compare(net: ARNet, L, J1, J2, h, T, n_chains=8192, cycles=500, gibbs_per_mh
     sweeps = n_s * trace_every
     gb = Sampler([inst], seed=seed, n_sweeps=sweeps)
     trg = torch.empty((n_s, n_chains, 3), dtype=torch.int32, device="cuda")
+    odg = torch.empty_like(trg)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    gb.sample(sweeps, trace=trg, trace_every=trace_every)
+    gb.sample(sweeps, trace=trg, trace_every=trace_every, order=odg)
     torch.cuda.synchronize()
     t_g = time.perf_counter() - t0
-    gibbs = _stats(trg, w, N, n_s // 5, t_g, n_s // 2)
+    gibbs = _stats(trg, odg, w, N, n_s // 5, t_g, n_s // 2)
     return {
         "learned": {"cycles": cycles, "gibbs_per_mh": gibbs_per_mh, "acceptance": acc / (cycles * n_chains),
                     "ms_per_cycle": 1e3 * t_mh / cycles, **learned.__dict__,
-                    "ess_per_s": learned.ess / t_mh, "tau_unit": "MH cycles"},
+                    "ess_per_s": learned.ess / t_mh, "ess_min_per_s": learned.ess_min / t_mh,
+                    "tau_unit": "MH cycles"},
         "gibbs": {"sweeps": sweeps, "trace_every": trace_every, "us_per_sweep": 1e6 * per_sweep,
-                  **gibbs.__dict__, "ess_per_s": gibbs.ess / t_g, "tau_unit": f"{trace_every} sweeps"},
+                  **gibbs.__dict__, "ess_per_s": gibbs.ess / t_g, "ess_min_per_s": gibbs.ess_min / t_g,
+                  "tau_unit": f"{trace_every} sweeps"},
     }

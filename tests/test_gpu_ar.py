@@ -123,11 +123,15 @@ def _trained_net(L, J2, h, T, steps=150, batch=1024, seed=61):
     return net
 
 
-def _mh_run(net, L, J2, h, T, gibbs_per_mh, cycles, n_chains=256, seed=11):
+def _mh_run(net, L, J2, h, T, gibbs_per_mh, cycles, n_chains=256, seed=11, with_order=False):
     inst = crbm.Instance(L=L, J1=1.0, J2=J2, h=h, n_chains=n_chains, sched="const", T0=T, id=3)
     smp = crbm.Sampler([inst], seed=seed, n_sweeps=cycles * max(gibbs_per_mh, 1) + 10)
     tr = torch.empty((cycles, n_chains, 3), dtype=torch.int32, device="cuda")
-    acc = crbm.sample_mh(smp, net, cycles, gibbs_per_mh, trace=tr)
+    od = torch.empty_like(tr) if with_order else None
+    acc = crbm.sample_mh(smp, net, cycles, gibbs_per_mh, trace=tr, order=od)
+    if with_order:
+        st, _ = smp.get_state()
+        return acc, tr.cpu().numpy().astype(np.float64), od.cpu().numpy(), st.cpu().numpy().reshape(n_chains, L, L)
     return acc, tr.cpu().numpy().astype(np.float64)
 
 
@@ -168,3 +172,16 @@ def test_training_gains_over_untrained_proposal():
     e = J1q * t1[100:, :, 1] + J2q * t1[100:, :, 2] - hq * t1[100:, :, 0]
     tau1 = stats.tau_int(e, max_lag=200)[0]
     assert tau1 < 5.0, tau1
+
+
+def test_mh_order_trace_is_the_states_structure_factor():
+    """The order trace of crbm_sample_mh after the last cycle equals the
+    oracle's plateau structure factor of the final states, and its counts
+    trace equals their bond counts."""
+    L, J2, h, T = 6, 1.0, 3.0, 0.7
+    net = crbm.ARNet(L)
+    net.set_params(flatten(ar.init_params(seed=61, scale=INIT_SCALE)))
+    acc, tr, od, st = _mh_run(net, L, J2, h, T, 2, 20, n_chains=64, with_order=True)
+    for ch in range(64):
+        assert tuple(od[-1, ch]) == oracle.order(L, st[ch])
+        assert tuple(tr[-1, ch].astype(int)) == oracle.counts(L, st[ch])

@@ -125,6 +125,31 @@ def test_thinned_trace_is_every_kth_row(every):
     assert e.value.code == crbm.CRBM_EINVAL
 
 
+@pytest.mark.parametrize("L,every,rows", [(18, 5, 1), (18, 5, 3), (18, 5, 9), (12, 1, 2), (8, 3, 4), (36, 4, 1),
+                                          (36, 4, 3)])
+def test_order_trace_matches_oracle(L, every, rows):
+    """The plateau structure-factor trace (max, |S_A|^2, |S_B|^2) of
+    crbm_sample_thinned equals the oracle's definition (cos/sin sums) on the
+    oracle's own trajectory at every recorded sweep, for every lanes-per-chain
+    tiling (the sums are reduced across the chain's lanes); L = 8 (not a
+    multiple of 3) and 36 (two words per row) included."""
+    seed, S = 0x5EED000000000007, 60
+    I = crbm.Instance(L=L, J1=1.0, J2=1.0, h=3.0, n_chains=10, sched="linear", T0=2.0, T1=0.3, id=11)
+    smp = crbm.Sampler([I], seed=seed, n_sweeps=S, tile_rows=rows)
+    tr = torch.empty((S // every, 10, 3), dtype=torch.int32, device="cuda")
+    od = torch.empty_like(tr)
+    smp.sample(S, trace=tr, trace_every=every, order=od)
+    torch.cuda.synchronize()
+    got, tgot = od.cpu().numpy(), tr.cpu().numpy()
+    oi = _oi(I)
+    for ch in (0, 3, 9):
+        sp = None
+        for k in range(S // every):
+            sp, t, _ = oracle.run_chain(oi, S, seed, ch, k * every, (k + 1) * every, spins=sp, trace=True)
+            assert np.array_equal(tgot[k, ch], t[-1])
+            assert tuple(got[k, ch]) == oracle.order(L, sp), (L, ch, k)
+
+
 def test_batch_composition_invariance():
     """An instance gives the same chains alone or inside a batch (the random
     stream depends on the instance id, not on its position)."""
