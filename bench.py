@@ -101,8 +101,8 @@ def batched_uneven(crbm, torch):
     insts = [crbm.Instance(L=p.L, J1=p.J1, J2=p.J2, h=p.h, n_chains=p.n_chains, sched=p.sched, T0=p.T0,
                            T1=p.T1, id=p.id) for p in pts]
     sweeps = 5000
-    for Lb in sorted({p.L for p in pts}):
-        crbm.autotune(Lb, n_chains=2048, n_sweeps=10)
+    for Lb in sorted({p.L for p in pts}):  # tuned on this size's share of the batch
+        crbm.autotune(Lb, n_chains=sum(p.n_chains for p in pts if p.L == Lb), n_sweeps=20)
     smp = crbm.Sampler(insts, seed=workloads.SEED_BATCHED, n_sweeps=2 * sweeps, launch="graph")
     smp.sample(50)  # warm-up launch
     torch.cuda.synchronize()
@@ -114,9 +114,30 @@ def batched_uneven(crbm, torch):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     work = sum(p.n_chains * p.L * p.L for p in pts) * sweeps
+    del smp
+    # load balance: each lattice size of the batch alone (its own instances, same
+    # tiling, direct launch), timed over the same sweeps; the sum of those times
+    # is what a perfectly balanced batch would take
+    alone = {}
+    for Lb in sorted({p.L for p in pts}):
+        sub = [I for I in insts if I.L == Lb]
+        s1 = crbm.Sampler(sub, seed=workloads.SEED_BATCHED, n_sweeps=sweeps + 50)
+        s1.sample(50)
+        torch.cuda.synchronize()
+        e0.record()
+        s1.sample(sweeps)
+        e1.record()
+        torch.cuda.synchronize()
+        alone[str(Lb)] = {"instances": len(sub), "ms": e0.elapsed_time(e1),
+                          "spin_updates_per_s": sum(I.n_chains for I in sub) * Lb * Lb * sweeps /
+                          (e0.elapsed_time(e1) / 1e3)}
+        del s1
+    sum_alone = sum(v["ms"] for v in alone.values())
     return {"workload": "2048 instances, L in {6,12,18,24,36,48} by seed, J2/J1~U[0.2,2.5], h/J1~U[0,3], "
                         "T~logU[0.05,5] fixed, 256 chains each, 5000 sweeps, one hipGraph launch",
             "spin_updates_per_s": work / (ms / 1e3), "ms": ms,
+            "per_L_alone": alone, "sum_of_per_L_ms": sum_alone,
+            "load_balance_efficiency": sum_alone / ms,
             "tiling": {str(Lb): crbm.get_tiling(Lb) for Lb in sorted({p.L for p in pts})}}
 
 
@@ -129,7 +150,7 @@ def scale_gibbs(crbm, torch, sizes=((48, 2000), (96, 500))):
         pts = workloads.scale_points(Ls)
         insts = [crbm.Instance(L=p.L, J1=p.J1, J2=p.J2, h=p.h, n_chains=p.n_chains, sched=p.sched, T0=p.T0,
                                T1=p.T1, id=p.id) for p in pts]
-        crbm.autotune(Ls, n_chains=4096, n_sweeps=10)
+        crbm.autotune(Ls, n_chains=sum(p.n_chains for p in pts), n_sweeps=20)
         smp = crbm.Sampler(insts, seed=workloads.SEED_SCALE, n_sweeps=sweeps + 20, measure_every=1,
                            burn_in=20 + sweeps // 2)
         smp.sample(20)

@@ -15,6 +15,7 @@ bool tiles_f(int L, int R, const GibbsArgs* a, hipStream_t st, hipError_t* err,
     TILE(72, 1)
     TILE(72, 2)
     TILE(72, 3)
+    TILE(72, 4)
     TILE(96, 1)
     TILE(96, 2)
     TILE(96, 3)

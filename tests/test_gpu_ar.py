@@ -185,3 +185,25 @@ def test_mh_order_trace_is_the_states_structure_factor():
     for ch in range(64):
         assert tuple(od[-1, ch]) == oracle.order(L, st[ch])
         assert tuple(tr[-1, ch].astype(int)) == oracle.counts(L, st[ch])
+
+
+def test_full_size_proposals_18x18():
+    """The benchmark's proposal batch: 8192 configurations at 18x18.  Sampler
+    and scorer log q are identical for all of them; sampled chains (first,
+    last, a middle one in a ragged position) match the oracle's log q within
+    tolerance and follow the documented uniforms."""
+    L, n = 18, 8192
+    params = ar.init_params(seed=77, scale=INIT_SCALE)
+    net = crbm.ARNet(L)
+    net.set_params(flatten(params))
+    s, lq = net.sample(n, seed=99, step=5, id=0)
+    assert torch.equal(lq, net.logq(s))
+    pick = [0, 4097, n - 1]
+    sn = s.cpu().numpy()[pick]
+    ref, c = ar.forward(unflatten(flatten(params), params), sn)
+    assert np.all(np.abs(lq.cpu().numpy()[pick] - ref) < LOGQ_TOL_PER_SITE * L * L)
+    p = 1 / (1 + np.exp(-c["logit"].reshape(len(pick), L * L)))
+    for k, ch in enumerate(pick):
+        u = np.array([(int(oracle.philox([i, 5, ch, 6], [99, 0])[0]) >> 8) / 16777216.0 for i in range(L * L)])
+        agree = (sn[k].reshape(-1) == 1) == (u < p[k])
+        assert np.all(agree | (np.abs(u - p[k]) < 1e-3)), ch

@@ -238,6 +238,28 @@ def test_degenerate_couplings_bit_exact():
     assert idx == 0 and torch.equal(out, st)
 
 
+def test_every_compiled_tiling_bit_exact():
+    """Every compiled (L, rows-per-lane) kernel variant -- whichever one the
+    autotuner picks for a workload -- gives the oracle's trajectories: first
+    and last chain of a ragged chain count, per-sweep counts and final spins."""
+    seed, S = 0x5EED000000000008, 24
+    tried = 0
+    for L in crbm.SUPPORTED_L:
+        for R in range(1, L // 2 + 1):
+            if (L // 2) % R:
+                continue
+            I = crbm.Instance(L=L, J1=1.0, J2=1.25, h=1.5, n_chains=13, sched="linear", T0=3.0, T1=0.4,
+                              id=(L * 7 + R) % 1000)
+            try:
+                smp, parts, tr = _run_gpu([I], seed, S, tile_rows=R)
+            except crbm.CrbmError as e:
+                assert e.code == crbm.CRBM_EUNSUPPORTED
+                continue
+            _check_chains(I, parts[0], tr, 0, seed, S, [0, 12])
+            tried += 1
+    assert tried >= 68, tried
+
+
 def test_invalid_arguments_fail_cleanly():
     bad = [
         (crbm.Instance(L=7, n_chains=1), crbm.CRBM_EINVAL),
