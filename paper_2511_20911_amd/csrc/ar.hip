@@ -158,63 +158,81 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
     }
 }
 
-// Partial weight gradient of one tap over a chunk of pixels:
-//   part[chunk][i][j] = sum_{p in chunk} in[p + tap][i] * dz[p][j]
+// Weight-gradient operands in channel-major form.  For each tap t of the
+// layer, the layer input shifted by the tap (zero outside the lattice), and
+// the output gradient, each as [channel][Ppad] bf16 (Ppad = P rounded up to
+// kTP, padding zero), transposed through an LDS tile of kTP pixels.  The
+// contraction over pixels then reads 16-byte runs of consecutive pixels.
+constexpr int kTP = 64;
+constexpr int kTRow = kTP + 8;  // LDS row stride (16-byte aligned rows)
+
+__global__ void __launch_bounds__(256) transpose_taps_kernel(const __bf16* __restrict__ in,
+                                                             const __bf16* __restrict__ dz, Taps taps, int L,
+                                                             int64_t P, int64_t Ppad, __bf16* __restrict__ xt,
+                                                             __bf16* __restrict__ dzt) {
+    __shared__ __align__(16) __bf16 tl[(NT + 1) * C * kTRow];  // slots 0..NT-1 taps, slot NT the gradient
+    const int tid = threadIdx.x;
+    const int64_t p0 = (int64_t)blockIdx.x * kTP;
+    const int px = tid >> 2, grp = tid & 3;
+    const int64_t p = p0 + px;
+    {
+        const bf16x8 v = (p < P) ? load8(dz + p * C + grp * 8) : zero8();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) tl[(NT * C + grp * 8 + e) * kTRow + px] = v[e];
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        if (t >= taps.n) break;
+        const int64_t q = (p < P) ? shift_pixel(p, taps.dr[t], taps.dc[t], L) : -1;
+        const bf16x8 v = (q >= 0) ? load8(in + q * C + grp * 8) : zero8();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) tl[(t * C + grp * 8 + e) * kTRow + px] = v[e];
+    }
+    __syncthreads();
+    constexpr int kSeg = kTP / 8;
+    const int nrows = (taps.n + 1) * C;
+    for (int k = tid; k < nrows * kSeg; k += blockDim.x) {
+        const int row = k / kSeg, seg = k - (k / kSeg) * kSeg;
+        const int slot = row / C, ch = row - slot * C;
+        const bool grad = slot == taps.n;
+        const bf16x8 v = *reinterpret_cast<const bf16x8*>(tl + ((grad ? NT : slot) * C + ch) * kTRow + seg * 8);
+        __bf16* dst = grad ? dzt + (int64_t)ch * Ppad : xt + ((int64_t)slot * C + ch) * Ppad;
+        *reinterpret_cast<bf16x8*>(dst + p0 + seg * 8) = v;
+    }
+}
+
+// Partial weight gradients from the channel-major operands, one wavefront per
+// chunk of kWChunk pixels, all taps at once (they share the gradient operand):
+//   part[chunk][t][i][j] = sum_{p in chunk} xt[t][i][p] dzt[j][p]
 // (A row i = input channel, k = pixel; B column j = output channel).
-__global__ void __launch_bounds__(256) wgrad_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ dz,
-                                                    Taps taps, int L, int64_t P, int64_t chunk, int nchunks,
-                                                    float* __restrict__ part) {
+constexpr int kWChunk = 512;
+
+__global__ void __launch_bounds__(256) wgrad_kernel(const __bf16* __restrict__ xt, const __bf16* __restrict__ dzt,
+                                                    int ntaps, int64_t Ppad, int nchunks, float* __restrict__ part) {
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (wid >= (int64_t)nchunks) return;
     const int li = lane & 31, half = lane >> 5;
-    const int64_t p_begin = wid * chunk, p_end = (p_begin + chunk < P) ? p_begin + chunk : P;
+    const int64_t k_begin = wid * kWChunk;
+    const int64_t k_end = (k_begin + kWChunk < Ppad) ? k_begin + kWChunk : Ppad;
     f32x16 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[t][v] = 0.f;
-    const int64_t LL = (int64_t)L * L;
-    for (int64_t k0 = p_begin; k0 < p_end; k0 += 16) {
-        // coordinates of this lane's 8 pixels: one division, then step along the row
-        const int64_t p0 = k0 + half * 8;
-        int rr[8], cc[8];
-        {
-            const int rc = (int)(p0 % LL);
-            int r = rc / L, c = rc - (rc / L) * L;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                rr[e] = r;
-                cc[e] = c;
-                if (++c == L) {
-                    c = 0;
-                    if (++r == L) r = 0;
-                }
-            }
-        }
-        bf16x8 b;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int64_t p = p0 + e;
-            b[e] = (p < p_end) ? dz[p * C + li] : (__bf16)0.0f;
-        }
+    const __bf16* brow = dzt + (int64_t)li * Ppad + half * 8;
+    for (int64_t k0 = k_begin; k0 < k_end; k0 += 16) {
+        const bf16x8 b = load8(brow + k0);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            if (t >= taps.n) break;
-            bf16x8 a;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int64_t p = p0 + e;
-                const int r = rr[e] + taps.dr[t], c = cc[e] + taps.dc[t];
-                const bool ok = p < p_end && r >= 0 && r < L && c >= 0 && c < L;
-                a[e] = ok ? in[(p + (int64_t)taps.dr[t] * L + taps.dc[t]) * C + li] : (__bf16)0.0f;
-            }
+            if (t >= ntaps) break;
+            const bf16x8 a = load8(xt + ((int64_t)t * C + li) * Ppad + half * 8 + k0);
             acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
         }
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        if (t >= taps.n) break;
+        if (t >= ntaps) break;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int i = 8 * (v >> 2) + 4 * half + (v & 3);
@@ -223,12 +241,26 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const __bf16* __restrict__ i
     }
 }
 
-// sum over chunks: dW[t][i][j] = sum_c part[c][t][i][j]
-__global__ void reduce_chunks_kernel(const float* part, int nchunks, int n, float* out) {
+// Two-stage deterministic sum over chunks: stage 1 (block = 256 entries x one
+// of S slices) sums chunks s, s + S, ... in fp64; stage 2 sums the S slices.
+constexpr int kRedSlices = 32;
+
+__global__ void __launch_bounds__(256) reduce_slices_kernel(const float* __restrict__ part, int nchunks, int n,
+                                                            double* __restrict__ part2) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int sl = blockIdx.y;
+    if (x >= n) return;
+    double s = 0.0;
+    for (int c = sl; c < nchunks; c += kRedSlices) s += part[(int64_t)c * n + x];
+    part2[(int64_t)sl * n + x] = s;
+}
+
+__global__ void reduce_final_kernel(const double* __restrict__ part2, int n, float* __restrict__ out) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * n + x];
+#pragma unroll 4
+    for (int k = 0; k < kRedSlices; ++k) s += part2[(int64_t)k * n + x];
     out[x] = (float)s;
 }
 
@@ -842,6 +874,8 @@ struct crbm_ar_s {
     __bf16 *dz = nullptr, *g = nullptr;    // [P][C]
     double* logq = nullptr;     // [B]
     float *part = nullptr, *dW = nullptr, *bpart = nullptr;
+    double* part2 = nullptr;                // [kRedSlices][NT][C][C]
+    __bf16 *xt = nullptr, *dzt = nullptr;   // [NT][C][Ppad], [C][Ppad]: channel-major weight-gradient operands
     int8_t* spins_copy = nullptr;
     // sequential sampler buffers (capacity in chains)
     int64_t scap = 0;
@@ -860,6 +894,7 @@ struct crbm_ar_s {
     unsigned long long* nacc = nullptr;
     ~crbm_ar_s() {
         void* ps[] = {theta, grad, m, v, bias, wf, wb, hs, mask, logit, g32, dh0, dh1, dz, g, logq, part, dW, bpart,
+                      part2, xt, dzt,
                       spins_copy, ring, slogit, zpad, ih0, ih1, ilogit, cur, prop, ccur, cprop, lqc, lqp, nacc};
         for (void* p : ps)
             if (p) (void)hipFree(p);
@@ -881,19 +916,24 @@ hipError_t alloc(T** p, int64_t n) {
     return hipMalloc((void**)p, sizeof(T) * (size_t)(n > 0 ? n : 1));
 }
 
-constexpr int64_t kChunk = 1024;
+int64_t padded_pixels(int64_t P) { return (P + kTP - 1) / kTP * kTP; }
 
 int ensure_train(crbm_ar_t* a, int64_t B) {
     if (B <= a->tcap) return CRBM_OK;
-    void* ps[] = {a->hs, a->mask, a->logit, a->g32, a->dh0, a->dh1, a->dz, a->g, a->logq, a->part, a->bpart, a->spins_copy};
+    void* ps[] = {a->hs, a->mask, a->logit, a->g32, a->dh0, a->dh1, a->dz, a->g, a->logq, a->part, a->bpart,
+                  a->spins_copy, a->part2, a->xt, a->dzt};
     for (void* p : ps)
         if (p) (void)hipFree(p);
-    const int64_t P = B * a->L * a->L;
-    const int64_t nch = (P + kChunk - 1) / kChunk;
+    a->part2 = nullptr;
+    a->xt = a->dzt = nullptr;
+    const int64_t P = B * a->L * a->L, Ppad = padded_pixels(P);
+    const int64_t nch = (Ppad + kWChunk - 1) / kWChunk;
     if (alloc(&a->hs, (int64_t)NL * P * C) || alloc(&a->mask, (int64_t)(NL - 1) * P * C) || alloc(&a->logit, P) ||
         alloc(&a->g32, P) || alloc(&a->dh0, P * C) || alloc(&a->dh1, P * C) || alloc(&a->dz, P * C) ||
         alloc(&a->g, P * C) || alloc(&a->logq, B) || alloc(&a->part, nch * NT * C * C) ||
-        alloc(&a->bpart, (int64_t)4096 * C) || alloc(&a->spins_copy, P)) {
+        alloc(&a->bpart, (int64_t)4096 * C) || alloc(&a->spins_copy, P) ||
+        alloc(&a->part2, (int64_t)kRedSlices * NT * C * C) || alloc(&a->xt, (int64_t)NT * C * Ppad) ||
+        alloc(&a->dzt, (int64_t)C * Ppad)) {
         a->tcap = 0;
         return fail_ar(CRBM_ENOMEM, "training buffers");
     }
@@ -948,7 +988,8 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B) {
     }
     hipLaunchKernelGGL(loss_kernel, dim3((unsigned)B), dim3(256), 0, st, a->logit, spins, L, 1.0f / (float)B, a->logq,
                        a->g, a->g32);
-    const int nch = (int)((P + kChunk - 1) / kChunk);
+    const int64_t Ppad = padded_pixels(P);
+    const int nch = (int)((Ppad + kWChunk - 1) / kWChunk);
     float* dh = a->dh0;
     float* dh_alt = a->dh1;
     for (int l = NL - 1; l >= 0; --l) {
@@ -966,9 +1007,13 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B) {
             dzl = a->dz;
         }
         hipLaunchKernelGGL(scatter_bias_kernel, dim3(1), dim3(256), 0, st, a->bpart, nbp, l, a->grad);
-        hipLaunchKernelGGL(wgrad_kernel, dim3((unsigned)((nch + 3) / 4)), dim3(256), 0, st, a->hs + (size_t)l * LSZ, dzl,
-                           tp, L, P, kChunk, nch, a->part);
-        hipLaunchKernelGGL(reduce_chunks_kernel, dim3((NT * C * C + 255) / 256), dim3(256), 0, st, a->part, nch,
+        hipLaunchKernelGGL(transpose_taps_kernel, dim3((unsigned)(Ppad / kTP)), dim3(256), 0, st,
+                           a->hs + (size_t)l * LSZ, dzl, tp, L, P, Ppad, a->xt, a->dzt);
+        hipLaunchKernelGGL(wgrad_kernel, dim3((unsigned)((nch + 3) / 4)), dim3(256), 0, st, a->xt, a->dzt, tp.n, Ppad,
+                           nch, a->part);
+        hipLaunchKernelGGL(reduce_slices_kernel, dim3((NT * C * C + 255) / 256, kRedSlices), dim3(256), 0, st,
+                           a->part, nch, NT * C * C, a->part2);
+        hipLaunchKernelGGL(reduce_final_kernel, dim3((NT * C * C + 255) / 256), dim3(256), 0, st, a->part2,
                            NT * C * C, a->dW);
         const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
         hipLaunchKernelGGL(scatter_grad_kernel, dim3((T * ci * co + 255) / 256), dim3(256), 0, st, a->dW, l, a->grad);
