@@ -579,8 +579,7 @@ __global__ void __launch_bounds__(256) score_fused_kernel(int64_t n, int L, cons
 }
 
 constexpr int kSeqChains = 32;
-constexpr int kSeqLdsBytes =
-    (NL * NT * C * C + NL * kSeqChains * C + 2 * kSeqChains * C + C) * 2 + kSeqChains * 4 + NL * C * 4;
+constexpr int kSeqLdsBytes = (NL * NT * C * C + NL * kSeqChains * C + 2 * kSeqChains * C + C) * 2 + NL * C * 4;
 
 // Ancestral sampler: a workgroup of four wavefronts draws 32 configurations
 // site by site in raster order.  Wavefront w computes chains 16 (w & 1) ..+15
@@ -591,9 +590,11 @@ constexpr int kSeqLdsBytes =
 // by layer parity).  The three taps in the row above come from a two-row ring
 // in global memory, prefetched three layers ahead.  The weights are the A
 // operand and the activations the B operand, so each lane ends a layer with
-// four consecutive channels of one chain (8-byte LDS and global stores).  Spin i is +1 iff u < sigmoid
-// (logit) with u the top 24 bits of Philox (ctr = (site, step, chain,
-// id << 3 | 6)); the logits go to logit_out for the log q sum.
+// four consecutive channels of one chain (8-byte LDS and global stores).
+// Spin i is +1 iff u < sigmoid(logit) with u the top 24 bits of Philox
+// (ctr = (site, step, chain, id << 3 | 6)), drawn by the lanes that hold the
+// logit at the end of the last layer; the logits go to logit_out for the log q
+// sum.
 __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int64_t npad, int L, const __bf16* __restrict__ wf,
                                                     const float* __restrict__ bias, __bf16* __restrict__ ring,
                                                     const __bf16* __restrict__ zpad, int8_t* __restrict__ spins,
@@ -604,8 +605,7 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int64_t npad, int
     __bf16* prev = wl + NL * NT * C * C;      // [NL][32 chains][C]: h_l at the previous site
     __bf16* tile = prev + NL * kSeqChains * C;  // [2][32 chains][C]: h_l at the current site
     __bf16* zrow = tile + 2 * kSeqChains * C;   // [C] zeros: operand of taps outside the lattice
-    float* xl = reinterpret_cast<float*>(zrow + C);  // [32] logits
-    float* bl = xl + kSeqChains;                     // [NL][C] biases
+    float* bl = reinterpret_cast<float*>(zrow + C);  // [NL][C] biases
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int chh = w & 1, coh = w >> 1;
     const int r16 = lane & 15, kg = lane >> 4;
@@ -653,10 +653,11 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int64_t npad, int
         // ring offset of this lane's outputs at layer 0 (chain ca, channels oc4..)
         const int64_t ring_lane = ridx(0, gca, r, c) + oc4;
         const int64_t ring_layer = (int64_t)npad * 2 * L * C;
+        // the draw of this lane's chain at this site (the wavefronts holding the logit channel)
         float u = 0.f;
-        if (w == 0) {
-            const gk::P4 q = gk::philox((uint32_t)site, step, (uint32_t)(base + (lane & 31)), (id << 3) | 6u,
-                                        (uint32_t)seed, (uint32_t)(seed >> 32));
+        if (coh == 0) {
+            const gk::P4 q = gk::philox((uint32_t)site, step, (uint32_t)gca, (id << 3) | 6u, (uint32_t)seed,
+                                        (uint32_t)(seed >> 32));
             u = (float)(q.v[0] >> 8) * (1.0f / 16777216.0f);
         }
 #pragma unroll
@@ -685,11 +686,23 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int64_t npad, int
                     pend[l + 1] = hn;
                     *reinterpret_cast<bf16x4*>(ring + ring_lane + (l + 1) * ring_layer) = hn;
                 } else if (kg == 0) {
-                    xl[ca] = acc[0] + bj[0];  // the logit: output channel 0
+                    // the logit (output channel 0 of this lane's chain) and the spin it draws
+                    const float x = acc[0] + bj[0];
+                    const float p = 1.f / (1.f + expf(-x));
+                    const float sg = (u < p) ? 1.f : -1.f;
+                    prev[swz_el(ca, 0)] = f2bf(sg);  // first layer's input at this site (channel 0; the rest stay 0)
+                    ring[ridx(0, gca, r, c)] = f2bf(sg);
+                    if (gca < n) {
+                        spins[gca * N + site] = (int8_t)sg;
+                        logit_out[gca * N + site] = x;
+                    }
                 }
             }
-            // every wavefront has read prev[l - 1] (before the last barrier): store this site's h_{l-1}
+            // every wavefront has read prev[l - 1] (before the last barrier): store this site's h_{l-1};
+            // h_11 of the previous site goes in at the first layer of the next one
             if (l >= 2) *reinterpret_cast<bf16x4*>(prev + (l - 1) * kSeqChains * C + swz_el(ca, oc4)) = pend[l - 1];
+            if (l == 0 && site > 0)
+                *reinterpret_cast<bf16x4*>(prev + (NL - 1) * kSeqChains * C + swz_el(ca, oc4)) = pend[NL - 1];
             // refill this slot with the layer three ahead (of this site or the next)
             if (l + kAhead < NL)
                 fetch(pr[l % kAhead], l + kAhead, r, c);
@@ -697,20 +710,6 @@ __global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int64_t npad, int
                 fetch(pr[l % kAhead], l + kAhead - NL, rn, cn);
             __syncthreads();
         }
-        *reinterpret_cast<bf16x4*>(prev + (NL - 1) * kSeqChains * C + swz_el(ca, oc4)) = pend[NL - 1];
-        if (w == 0 && lane < kSeqChains) {
-            const int64_t ch = base + lane;
-            const float x = xl[lane];
-            const float p = 1.f / (1.f + expf(-x));
-            const float sg = (u < p) ? 1.f : -1.f;
-            prev[swz_el(lane, 0)] = f2bf(sg);  // layer-1 input at this site (channel 0; the rest stay 0)
-            ring[ridx(0, ch, r, c)] = f2bf(sg);
-            if (ch < n) {
-                spins[ch * N + site] = (int8_t)sg;
-                logit_out[ch * N + site] = x;
-            }
-        }
-        __syncthreads();
     }
 }
 
