@@ -26,6 +26,8 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
+# matrix-core results in ordinary VGPRs (no accumulator-register copies in the epilogues)
+EXTRA = {"ar.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _run(cmd):
@@ -46,7 +48,7 @@ def build(verbose: bool = False) -> str:
         for src in SOURCES:
             obj = os.path.join(tmp, src + ".o")
             lang = [] if src.endswith(".hip") else ["-x", "hip"]
-            cmds.append([HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
+            cmds.append([HIPCC] + COMMON + EXTRA.get(src, []) + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
             objs.append(obj)
         with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 4)) as ex:
             outs = list(ex.map(_run, cmds))

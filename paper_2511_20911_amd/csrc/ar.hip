@@ -425,6 +425,43 @@ __device__ __forceinline__ bf16x4 hidden_out4(bool first, f32x4 acc, f32x4 bias,
     return h;
 }
 
+// the same element arithmetic with the residual input already widened to fp32
+__device__ __forceinline__ bf16x4 hidden_out4f(bool first, f32x4 acc, f32x4 bias, f32x4 resid) {
+    bf16x4 h;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const float z = acc[v] + bias[v];
+        const float rz = z > 0.f ? z : 0.f;
+        h[v] = f2bf(first ? rz : resid[v] + rz);
+    }
+    return h;
+}
+
+// four bf16 values widened to fp32 exactly (a bf16 is the top half of its fp32)
+__device__ __forceinline__ f32x4 widen4(bf16x4 h) {
+    const uint2 b = __builtin_bit_cast(uint2, h);
+    return f32x4{__uint_as_float(b.x << 16), __uint_as_float(b.x & 0xffff0000u), __uint_as_float(b.y << 16),
+                 __uint_as_float(b.y & 0xffff0000u)};
+}
+
+// D layout -> B fragment inside a wavefront.  Lane (j, g) (j = lane % 16,
+// g = lane / 16) holds channels 4g..4g+3 (h0) and 16+4g..16+4g+3 (h1) of
+// column j; the B operand wants channels 8g..8g+7 of the same column, i.e.
+// half g / 2 of the lanes in rows 2 (g % 2) and 2 (g % 2) + 1.  Per packed
+// dword, a 32-lane swap (rows 2,3 of h0 <-> rows 0,1 of h1) followed by a
+// 16-lane swap (odd rows of the first <-> even rows of the second) leaves
+// the first four channels in the first register and the last four in the
+// second.
+__device__ __forceinline__ bf16x8 regroup(bf16x4 h0, bf16x4 h1) {
+    const uint2 a = __builtin_bit_cast(uint2, h0), b = __builtin_bit_cast(uint2, h1);
+    const auto s0 = __builtin_amdgcn_permlane32_swap(a.x, b.x, false, false);
+    const auto t0 = __builtin_amdgcn_permlane16_swap(s0[0], s0[1], false, false);
+    const auto s1 = __builtin_amdgcn_permlane32_swap(a.y, b.y, false, false);
+    const auto t1 = __builtin_amdgcn_permlane16_swap(s1[0], s1[1], false, false);
+    const uint4 o = {t0[0], t1[0], t0[1], t1[1]};
+    return __builtin_bit_cast(bf16x8, o);
+}
+
 __device__ __forceinline__ bf16x4 zero4() {
     bf16x4 z;
 #pragma unroll
@@ -578,137 +615,175 @@ __global__ void __launch_bounds__(256) score_fused_kernel(int64_t n, int L, cons
     }
 }
 
-constexpr int kSeqChains = 32;
-constexpr int kSeqLdsBytes = (NL * NT * C * C + NL * kSeqChains * C + 2 * kSeqChains * C + C) * 2 + NL * C * 4;
+// Ancestral sampler.  Each wavefront draws 16 configurations site by site in
+// raster order and computes every layer and all 32 channels of its own
+// chains, so the wavefronts of a workgroup (1, 2 or 4 of them, sharing the
+// packed weights in LDS) never wait for each other inside the site loop.  Per
+// layer the weights are the A operand (rows = output channels, two halves of
+// 16) and the activations the B operand (columns = chains): a lane ends the
+// layer with four consecutive channels of each half for its chain, and two
+// lane swaps per register regroup them into the next layer's B fragment.
+// The operand of the (0,-1) tap is the fragment each lane used at the
+// previous site; the taps of the row above come from a one-row ring in global
+// memory, each element read once into a window that slides along the row.
+// The weights of the next layer are loaded while a layer finishes.  Spin i is
+// +1 iff u < sigmoid(logit), u the top 24 bits of Philox (ctr = (site, step,
+// chain, id << 3 | 6)), drawn by the lane that holds the logit at the end of
+// the last layer; the logits go to logit_out for the log q sum.
+constexpr int kSeqMaxWaves = 4;
+constexpr int kSeqPad = 16 * kSeqMaxWaves;  // the ring's chain count is a multiple of this
+constexpr int kSeqLdsBytes = NL * NT * C * C * 2 + NL * C * 4;
 
-// Ancestral sampler: a workgroup of four wavefronts draws 32 configurations
-// site by site in raster order.  Wavefront w computes chains 16 (w & 1) ..+15
-// times output channels 16 (w >> 1) ..+15 of every layer at the current
-// site; the layers are separated by workgroup barriers.  LDS holds all
-// weights (120 KB), the activations of every layer at the previous site
-// (the (0,-1) tap) and at the current site (the centre tap, double-buffered
-// by layer parity).  The three taps in the row above come from a two-row ring
-// in global memory, prefetched three layers ahead.  The weights are the A
-// operand and the activations the B operand, so each lane ends a layer with
-// four consecutive channels of one chain (8-byte LDS and global stores).
-// Spin i is +1 iff u < sigmoid(logit) with u the top 24 bits of Philox
-// (ctr = (site, step, chain, id << 3 | 6)), drawn by the lanes that hold the
-// logit at the end of the last layer; the logits go to logit_out for the log q
-// sum.
-__global__ void __launch_bounds__(256) seq16_kernel(int64_t n, int64_t npad, int L, const __bf16* __restrict__ wf,
-                                                    const float* __restrict__ bias, __bf16* __restrict__ ring,
-                                                    const __bf16* __restrict__ zpad, int8_t* __restrict__ spins,
-                                                    float* __restrict__ logit_out, uint64_t seed, uint32_t step,
-                                                    uint32_t id) {
+// keeps the compiler from moving this wavefront's memory accesses across it
+// (its memory operations complete in order, so no instruction is needed)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L, const __bf16* __restrict__ wf,
+                                                  const float* __restrict__ bias, __bf16* __restrict__ ring,
+                                                  const __bf16* __restrict__ zpad, int8_t* __restrict__ spins,
+                                                  float* __restrict__ logit_out, uint64_t seed, uint32_t step,
+                                                  uint32_t id) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __bf16* wl = reinterpret_cast<__bf16*>(smem);
-    __bf16* prev = wl + NL * NT * C * C;      // [NL][32 chains][C]: h_l at the previous site
-    __bf16* tile = prev + NL * kSeqChains * C;  // [2][32 chains][C]: h_l at the current site
-    __bf16* zrow = tile + 2 * kSeqChains * C;   // [C] zeros: operand of taps outside the lattice
-    float* bl = reinterpret_cast<float*>(zrow + C);  // [NL][C] biases
+    __bf16* wl = reinterpret_cast<__bf16*>(smem);                 // [NL][NT][C][C], rows swizzled
+    float* bl = reinterpret_cast<float*>(wl + NL * NT * C * C);   // [NL][C] biases
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int chh = w & 1, coh = w >> 1;
     const int r16 = lane & 15, kg = lane >> 4;
-    const int N = L * L;
-    const int64_t base = (int64_t)blockIdx.x * kSeqChains;
     for (int g = tid; g < NL * NT * C * 4; g += blockDim.x) {
         const int row = g >> 2, grp = g & 3;
         *reinterpret_cast<bf16x8*>(wl + swz(row, grp)) = load8(wf + (int64_t)row * C + grp * 8);
     }
-    for (int g = tid; g < NL * kSeqChains * 4; g += blockDim.x) *reinterpret_cast<bf16x8*>(prev + g * 8) = zero8();
-    if (tid < 4) *reinterpret_cast<bf16x8*>(zrow + tid * 8) = zero8();
     for (int g = tid; g < NL * C; g += blockDim.x) bl[g] = bias[g];
-    // Operand roles: the weights are the A operand (row = output channel of
-    // this wavefront's 16-channel half), the activations the B operand
-    // (column = chain); a lane's D values are the four consecutive output
-    // channels oc4 .. oc4 + 3 of its own chain ca.
-    const int oc = 16 * coh + r16;  // A row: output channel of this lane's weight fragment
-    const int ca = 16 * chh + r16;  // B / D column: chain within the workgroup
-    const int oc4 = 16 * coh + 4 * kg;
-    const int64_t gca = base + ca;  // the ring has npad >= n chains: padding rows have their own slots
-    // ring element (layer, chain, row, column): [NL][npad][2][L][C]
-    auto ridx = [&](int l, int64_t chain, int r, int c) -> int64_t {
-        return ((((int64_t)l * npad + chain) * 2 + (r & 1)) * L + c) * C;
+    __syncthreads();
+    // wavefront-uniform by construction; readfirstlane lets the compiler keep it (and the ring base) scalar
+    const int64_t wbase = (int64_t)blockIdx.x * (blockDim.x >> 2) + 16 * __builtin_amdgcn_readfirstlane(w);
+    if (wbase >= n) return;  // no further workgroup barrier below
+    // Operand roles: A row = output channel 16 h + r16 (h = half), B / D column
+    // = chain r16 of this wavefront; a lane's D values of half h are channels
+    // 16 h + 4 kg .. + 3 of its chain.
+    const int64_t gca = wbase + r16;  // the ring has npad >= grid size chains: padding rows have their own slots
+    const int N = L * L;
+    // Ring element (layer, chain, column, channel): [NL][npad][L][C], one row
+    // per chain and layer.  Site (r, c) writes column c after the row above's
+    // column c was last read (as the (-1,+1) tap of site (r, c - 1)), so the
+    // slots of a row hold row r at columns < c and row r - 1 from c on.
+    // Addresses are a wavefront-uniform part (this wavefront's first chain,
+    // layer, column) plus a per-lane 32-bit byte offset (chain within the
+    // wavefront, channel group) fixed for the whole kernel.
+    const int64_t chain_stride = (int64_t)L * C;
+    const int64_t ring_layer = npad * chain_stride;
+    const __bf16* ring_w = ring + wbase * chain_stride;
+    const uint32_t rd_off = (uint32_t)(r16 * chain_stride + kg * 8) * 2;  // bytes: B fragment of the lane
+    const uint32_t wr_off = (uint32_t)(r16 * chain_stride + 4 * kg) * 2;  // bytes: D values of the lane (half 0)
+    const uint32_t zr_off = (uint32_t)(kg * 8) * 2;
+    auto slot = [&](int l, int c) -> int64_t { return (int64_t)l * ring_layer + (int64_t)c * C; };  // uniform
+    auto fetch = [&](int l, bool inside, int c) -> bf16x8 {  // `inside` is wavefront-uniform
+        const char* src = inside ? reinterpret_cast<const char*>(ring_w + slot(l, c))
+                                 : reinterpret_cast<const char*>(zpad);
+        return *reinterpret_cast<const bf16x8*>(src + (inside ? rd_off : zr_off));
     };
-    // row-above fragments, prefetched three layers ahead: slot l % 3 holds layer l
-    constexpr int kAhead = 3;
-    bf16x8 pr[kAhead][3];
-    auto fetch = [&](bf16x8 (&dst)[3], int l, int r, int c) {
+    // A fragments of layer l for both halves (the centre tap is masked in the first layer, the last
+    // layer has one output channel)
+    bf16x8 bw0[NT], bw1[NT];
+    auto load_w = [&](int l) {
+        const __bf16* Wl = wl + l * NT * C * C;
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            const int cc = c - 1 + t;
-            const bool inside = r > 0 && cc >= 0 && cc < L;  // wavefront-uniform
-            const __bf16* src = inside ? ring + ridx(l, gca, r - 1, cc) : zpad;
-            dst[t] = load8(src + kg * 8);
+        for (int t = 0; t < NT; ++t) {
+            const bool used = t < 4 || l > 0;
+            bw0[t] = used ? load8(Wl + t * C * C + swz(r16, kg)) : zero8();
+            bw1[t] = (used && l < NL - 1) ? load8(Wl + t * C * C + swz(16 + r16, kg)) : zero8();
         }
     };
+    // B fragments per layer l: the row above at columns c - 1 and c (a
+    // window that slides by one column per site and is refilled at a row
+    // end), at column c + 1 (prefetched three layers ahead into slot l % 3),
+    // and h_l at the previous site (l = 0: its spin; zero at a row start).
+    constexpr int kAhead = 3;
+    bf16x8 up0[NL], up1[NL], left[NL], pr[kAhead];
 #pragma unroll
-    for (int l = 0; l < kAhead; ++l) fetch(pr[l], l, 0, 0);
-    bf16x4 pend[NL];
-    __syncthreads();
+    for (int l = 0; l < NL; ++l) up0[l] = up1[l] = zero8();
+#pragma unroll
+    for (int l = 0; l < kAhead; ++l) pr[l] = zero8();  // row 0 has no row above
+    f32x4 hp0 = {0.f, 0.f, 0.f, 0.f}, hp1 = hp0;  // h_l of this lane's outputs as floats: the residual inputs
+    bf16x8 hb = zero8();                           // h_l as this lane's B fragment: the centre tap's operand
+    load_w(0);
     for (int site = 0; site < N; ++site) {
         const int r = site / L, c = site - r * L;
         const int sn = site + 1, rn = sn / L, cn = sn - rn * L;
         const bool more = sn < N;
-        // ring offset of this lane's outputs at layer 0 (chain ca, channels oc4..)
-        const int64_t ring_lane = ridx(0, gca, r, c) + oc4;
-        const int64_t ring_layer = (int64_t)npad * 2 * L * C;
-        // the draw of this lane's chain at this site (the wavefronts holding the logit channel)
-        float u = 0.f;
-        if (coh == 0) {
-            const gk::P4 q = gk::philox((uint32_t)site, step, (uint32_t)gca, (id << 3) | 6u, (uint32_t)seed,
-                                        (uint32_t)(seed >> 32));
-            u = (float)(q.v[0] >> 8) * (1.0f / 16777216.0f);
+        if (c == 0) {
+#pragma unroll
+            for (int l = 0; l < NL; ++l) left[l] = zero8();
         }
+        const gk::P4 q = gk::philox((uint32_t)site, step, (uint32_t)gca, (id << 3) | 6u, (uint32_t)seed,
+                                    (uint32_t)(seed >> 32));
+        const float u = (float)(q.v[0] >> 8) * (1.0f / 16777216.0f);
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
-            const __bf16* tl = tile + (l & 1) * kSeqChains * C;
-            __bf16* tn = tile + ((l + 1) & 1) * kSeqChains * C;
-            if (l < NL - 1 || coh == 0) {
-                const __bf16* Wl = wl + l * NT * C * C;
-                // all LDS operands of the layer first, so their latencies overlap
-                bf16x8 bw[NT];
+            const bool last = l == NL - 1;
+            const bf16x8 op[4] = {up0[l], up1[l], pr[l % kAhead], left[l]};
+            f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int t = 0; t < NT; ++t) bw[t] = (t < 4 || l > 0) ? load8(Wl + t * C * C + swz(oc, kg)) : zero8();
-                const bf16x8 a3 = load8((c > 0) ? prev + l * kSeqChains * C + swz(ca, kg) : zrow + kg * 8);
-                const bf16x8 a4 = (l > 0) ? load8(tl + swz(ca, kg)) : zero8();
-                const f32x4 bj = *reinterpret_cast<const f32x4*>(bl + l * C + oc4);
-                const bf16x4 res = (l > 0 && l < NL - 1) ? *reinterpret_cast<const bf16x4*>(tl + swz_el(ca, oc4))
-                                                         : zero4();  // residual inputs of the four outputs
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int t = 0; t < 3; ++t) acc = mfma16(bw[t], pr[l % kAhead][t], acc);
-                acc = mfma16(bw[3], a3, acc);
-                if (l > 0) acc = mfma16(bw[4], a4, acc);
-                if (l < NL - 1) {
-                    const bf16x4 hn = hidden_out4(l == 0, acc, bj, res);
-                    *reinterpret_cast<bf16x4*>(tn + swz_el(ca, oc4)) = hn;
-                    pend[l + 1] = hn;
-                    *reinterpret_cast<bf16x4*>(ring + ring_lane + (l + 1) * ring_layer) = hn;
-                } else if (kg == 0) {
-                    // the logit (output channel 0 of this lane's chain) and the spin it draws
-                    const float x = acc[0] + bj[0];
-                    const float p = 1.f / (1.f + expf(-x));
-                    const float sg = (u < p) ? 1.f : -1.f;
-                    prev[swz_el(ca, 0)] = f2bf(sg);  // first layer's input at this site (channel 0; the rest stay 0)
-                    ring[ridx(0, gca, r, c)] = f2bf(sg);
+            for (int t = 0; t < 4; ++t) {
+                acc0 = mfma16(bw0[t], op[t], acc0);
+                if (!last) acc1 = mfma16(bw1[t], op[t], acc1);
+            }
+            if (l > 0) {
+                acc0 = mfma16(bw0[4], hb, acc0);
+                if (!last) acc1 = mfma16(bw1[4], hb, acc1);
+                left[l] = hb;
+            }
+            // the next layer's weights (of this site or the next) load while this one finishes
+            if (l + 1 < NL)
+                load_w(l + 1);
+            else if (more)
+                load_w(0);
+            // slide the window; at a row end refill it with columns -1 (outside) and 0 of this row
+            if (c + 1 < L) {
+                up0[l] = up1[l];
+                up1[l] = pr[l % kAhead];
+            } else if (r + 1 < L) {
+                up0[l] = zero8();
+                up1[l] = fetch(l, true, 0);
+            }
+            if (!last) {
+                const f32x4 bj0 = *reinterpret_cast<const f32x4*>(bl + l * C + 4 * kg);
+                const f32x4 bj1 = *reinterpret_cast<const f32x4*>(bl + l * C + 16 + 4 * kg);
+                const bf16x4 h0 = hidden_out4f(l == 0, acc0, bj0, hp0);
+                const bf16x4 h1 = hidden_out4f(l == 0, acc1, bj1, hp1);
+                char* dst = reinterpret_cast<char*>(ring + (ring_w - ring) + slot(l + 1, c)) + wr_off;
+                *reinterpret_cast<bf16x4*>(dst) = h0;
+                *reinterpret_cast<bf16x4*>(dst + 32) = h1;
+                hb = regroup(h0, h1);
+                hp0 = widen4(h0);
+                hp1 = widen4(h1);
+            } else {
+                // the logit is output channel 0: element 0 of the lanes with kg == 0
+                const float x = acc0[0] + bl[l * C];
+                const float p = 1.f / (1.f + expf(-x));
+                const __bf16 sg = f2bf((u < p) ? 1.f : -1.f);
+                bf16x8 s8 = zero8();
+                if (kg == 0) {
+                    s8[0] = sg;  // the first layer's input fragment: channel 0 is the spin, the rest 0
+                    *reinterpret_cast<__bf16*>(reinterpret_cast<char*>(ring + (ring_w - ring) + slot(0, c)) +
+                                               wr_off) = sg;
                     if (gca < n) {
-                        spins[gca * N + site] = (int8_t)sg;
+                        spins[gca * N + site] = (int8_t)bf2f(sg);
                         logit_out[gca * N + site] = x;
                     }
                 }
+                left[0] = s8;
             }
-            // every wavefront has read prev[l - 1] (before the last barrier): store this site's h_{l-1};
-            // h_11 of the previous site goes in at the first layer of the next one
-            if (l >= 2) *reinterpret_cast<bf16x4*>(prev + (l - 1) * kSeqChains * C + swz_el(ca, oc4)) = pend[l - 1];
-            if (l == 0 && site > 0)
-                *reinterpret_cast<bf16x4*>(prev + (NL - 1) * kSeqChains * C + swz_el(ca, oc4)) = pend[NL - 1];
-            // refill this slot with the layer three ahead (of this site or the next)
+            wave_sync();  // this layer's ring stores precede every later ring load
+            // refill this prefetch slot: column c + 1 of the row above for layer l + 3 of this site, or of
+            // the next site
             if (l + kAhead < NL)
-                fetch(pr[l % kAhead], l + kAhead, r, c);
+                pr[l % kAhead] = fetch(l + kAhead, r > 0 && c + 1 < L, c + 1);
             else if (more)
-                fetch(pr[l % kAhead], l + kAhead - NL, rn, cn);
-            __syncthreads();
+                pr[l % kAhead] = fetch(l + kAhead - NL, rn > 0 && cn + 1 < L, cn + 1);
         }
     }
 }
@@ -946,8 +1021,8 @@ int ensure_seq(crbm_ar_t* a, int64_t n) {
     if (a->slogit) (void)hipFree(a->slogit);
     a->ring = nullptr;
     a->slogit = nullptr;
-    const int64_t npad = (n + kSeqChains - 1) / kSeqChains * kSeqChains;
-    if (alloc(&a->ring, (int64_t)NL * npad * 2 * a->L * C) || alloc(&a->slogit, n * a->L * a->L)) {
+    const int64_t npad = (n + kSeqPad - 1) / kSeqPad * kSeqPad;
+    if (alloc(&a->ring, (int64_t)NL * npad * a->L * C) || alloc(&a->slogit, n * a->L * a->L)) {
         a->scap = 0;
         return fail_ar(CRBM_ENOMEM, "sampler buffers");
     }
@@ -1034,14 +1109,17 @@ int run_seq(crbm_ar_t* a, int64_t n, int8_t* spins, double* logq, uint64_t seed,
     if (rc != CRBM_OK) return rc;
     const int L = a->L;
     hipStream_t st = a->stream;
-    // layer-1 input ring: channels 1..31 stay zero, channel 0 receives the spins
-    const int64_t npad = (n + kSeqChains - 1) / kSeqChains * kSeqChains;
-    AR_TRY(hipMemsetAsync(a->ring, 0, sizeof(__bf16) * (size_t)npad * 2 * L * C, st), "clear sampler input");
-    AR_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&seq16_kernel),
+    // the first layer's ring rows: channels 1..31 stay zero, channel 0 receives the spins
+    const int64_t npad = (n + kSeqPad - 1) / kSeqPad * kSeqPad;
+    AR_TRY(hipMemsetAsync(a->ring, 0, sizeof(__bf16) * (size_t)npad * L * C, st), "clear sampler input");
+    // one wavefront per 16 chains; as many per workgroup as keep one workgroup per compute unit busy
+    const int waves = n <= 16 * 256 ? 1 : n <= 32 * 256 ? 2 : kSeqMaxWaves;
+    const int per_wg = 16 * waves;
+    AR_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&seq_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, kSeqLdsBytes),
            "sampler LDS size");
-    hipLaunchKernelGGL(seq16_kernel, dim3((unsigned)((n + kSeqChains - 1) / kSeqChains)), dim3(256), kSeqLdsBytes,
-                       st, n, npad, L, a->wf, a->bias, a->ring, a->zpad, spins, a->slogit, seed, step, id);
+    hipLaunchKernelGGL(seq_kernel, dim3((unsigned)((n + per_wg - 1) / per_wg)), dim3(64 * waves), kSeqLdsBytes, st, n, npad, L, a->wf, a->bias, a->ring, a->zpad, spins, a->slogit, seed,
+                       step, id);
     hipLaunchKernelGGL(logq_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->slogit, spins, n, L * L,
                        logq);
     AR_TRY(hipGetLastError(), "sampler kernels");

@@ -87,6 +87,36 @@ def test_sampler_logq_equals_scorer_and_follows_logits(L, n):
     assert np.all(agree | near)
 
 
+@pytest.mark.parametrize("L", [6, 18])
+def test_sampler_chains_independent_of_batch_size(L):
+    """A chain's configuration and log q depend only on (network, seed, step,
+    id, chain index): batches that launch one, two or four wavefronts per
+    workgroup, with ragged last workgroups, agree chain by chain, and sampled
+    chains at the batch edges match the oracle's log q and uniforms."""
+    params = ar.init_params(seed=37, scale=INIT_SCALE)
+    net = crbm.ARNet(L)
+    net.set_params(flatten(params))
+    runs = {n: net.sample(n, seed=5, step=1, id=4) for n in (16, 40, 4100, 8200)}
+    s_ref, lq_ref = runs[16]
+    for n, (s, lq) in runs.items():
+        assert torch.equal(s[:16], s_ref), n
+        assert torch.equal(lq[:16], lq_ref), n
+        assert torch.equal(lq, net.logq(s)), n
+    s40, lq40 = runs[40]
+    assert torch.equal(runs[8200][0][:40], s40) and torch.equal(runs[8200][1][:40], lq40)
+    s, lq = runs[8200]
+    pick = [4095, 4099, 8191, 8199]
+    sn = s.cpu().numpy()[pick]
+    ref, c = ar.forward(unflatten(flatten(params), params), sn)
+    assert np.all(np.abs(lq.cpu().numpy()[pick] - ref) < LOGQ_TOL_PER_SITE * L * L)
+    p = 1 / (1 + np.exp(-c["logit"].reshape(len(pick), L * L)))
+    for k, ch in enumerate(pick):
+        u = np.array([(int(oracle.philox([i, 1, ch, (4 << 3) | 6], [5, 0])[0]) >> 8) / 16777216.0
+                      for i in range(L * L)])
+        agree = (sn[k].reshape(-1) == 1) == (u < p[k])
+        assert np.all(agree | (np.abs(u - p[k]) < 1e-3)), ch
+
+
 def test_training_reduces_loss():
     L = 6
     net = crbm.ARNet(L)
