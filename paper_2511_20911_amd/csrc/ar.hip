@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "crbm.h"
@@ -397,8 +398,8 @@ __global__ void pack_kernel(const float* th, __bf16* wf, __bf16* wb, float* bias
 // Sampling and scoring share one per-element arithmetic: for every output
 // (configuration, site, channel) the five taps are accumulated in order
 // (-1,-1), (-1,0), (-1,1), (0,-1), (0,0) by one 16x16x32 bf16 matrix-core
-// instruction each (all 32 input channels at once), starting from zero; then
-// bias, ReLU and the residual add in fp32 and one rounding to bf16.  The
+// instruction each (all 32 input channels at once), starting from the bias;
+// then ReLU and the residual add in fp32 and one rounding to bf16.  The
 // logits of both paths are therefore bit-identical, and so is log q, which
 // logq_kernel sums from them.
 
@@ -408,30 +409,33 @@ __device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// hidden activation of one element: relu(z) for layer 1, h + relu(z) after
-__device__ __forceinline__ __bf16 hidden_out(bool first, float acc, float bias, __bf16 resid) {
-    const float z = acc + bias;
-    const float rz = z > 0.f ? z : 0.f;
+// max(z, +0) as an integer max of the bit pattern: equal to (z > 0 ? z : +0)
+// for every non-NaN z (negative values and -0 give +0), in one instruction
+__device__ __forceinline__ float relu(float z) { return __int_as_float(max(__float_as_int(z), 0)); }
+
+// hidden activation of one element from its pre-activation z (bias
+// included): relu(z) for layer 1, h + relu(z) after
+__device__ __forceinline__ __bf16 hidden_out(bool first, float z, __bf16 resid) {
+    const float rz = relu(z);
     return f2bf(first ? rz : bf2f(resid) + rz);
 }
 
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 
 // four consecutive output channels of one pixel / chain (the D layout below)
-__device__ __forceinline__ bf16x4 hidden_out4(bool first, f32x4 acc, f32x4 bias, bf16x4 resid) {
+__device__ __forceinline__ bf16x4 hidden_out4(bool first, f32x4 z, bf16x4 resid) {
     bf16x4 h;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) h[v] = hidden_out(first, acc[v], bias[v], resid[v]);
+    for (int v = 0; v < 4; ++v) h[v] = hidden_out(first, z[v], resid[v]);
     return h;
 }
 
 // the same element arithmetic with the residual input already widened to fp32
-__device__ __forceinline__ bf16x4 hidden_out4f(bool first, f32x4 acc, f32x4 bias, f32x4 resid) {
+__device__ __forceinline__ bf16x4 hidden_out4f(bool first, f32x4 z, f32x4 resid) {
     bf16x4 h;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const float z = acc[v] + bias[v];
-        const float rz = z > 0.f ? z : 0.f;
+        const float rz = relu(z[v]);
         h[v] = f2bf(first ? rz : resid[v] + rz);
     }
     return h;
@@ -460,6 +464,17 @@ __device__ __forceinline__ bf16x8 regroup(bf16x4 h0, bf16x4 h1) {
     const auto t1 = __builtin_amdgcn_permlane16_swap(s1[0], s1[1], false, false);
     const uint4 o = {t0[0], t1[0], t0[1], t1[1]};
     return __builtin_bit_cast(bf16x8, o);
+}
+
+// B fragment -> D layout: the inverse of regroup (each swap is its own inverse)
+__device__ __forceinline__ void ungroup(bf16x8 x, bf16x4& h0, bf16x4& h1) {
+    const uint4 o = __builtin_bit_cast(uint4, x);
+    const auto s0 = __builtin_amdgcn_permlane16_swap(o.x, o.z, false, false);
+    const auto t0 = __builtin_amdgcn_permlane32_swap(s0[0], s0[1], false, false);
+    const auto s1 = __builtin_amdgcn_permlane16_swap(o.y, o.w, false, false);
+    const auto t1 = __builtin_amdgcn_permlane32_swap(s1[0], s1[1], false, false);
+    h0 = __builtin_bit_cast(bf16x4, uint2{t0[0], t1[0]});
+    h1 = __builtin_bit_cast(bf16x4, uint2{t0[1], t1[1]});
 }
 
 __device__ __forceinline__ bf16x4 zero4() {
@@ -495,7 +510,7 @@ __global__ void __launch_bounds__(256) conv16_kernel(const __bf16* __restrict__ 
     const int64_t ntiles = (P + 15) / 16;
     for (int64_t tile = w0; tile < ntiles; tile += nw) {
         const int64_t p = tile * 16 + r16;
-        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        f32x4 acc0 = bj0, acc1 = bj1;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             if (t >= taps.n) break;
@@ -506,20 +521,24 @@ __global__ void __launch_bounds__(256) conv16_kernel(const __bf16* __restrict__ 
         }
         if (p >= P) continue;
         if (last) {
-            if (kg == 0) logit[p] = acc0[0] + bj0[0];
+            if (kg == 0) logit[p] = acc0[0];
         } else {
             const int64_t o0 = p * C + 4 * kg, o1 = o0 + 16;
             const bf16x4 r0 = first ? zero4() : *reinterpret_cast<const bf16x4*>(in + o0);
             const bf16x4 r1 = first ? zero4() : *reinterpret_cast<const bf16x4*>(in + o1);
-            *reinterpret_cast<bf16x4*>(out + o0) = hidden_out4(first, acc0, bj0, r0);
-            *reinterpret_cast<bf16x4*>(out + o1) = hidden_out4(first, acc1, bj1, r1);
+            *reinterpret_cast<bf16x4*>(out + o0) = hidden_out4(first, acc0, r0);
+            *reinterpret_cast<bf16x4*>(out + o1) = hidden_out4(first, acc1, r1);
         }
     }
 }
 
-// LDS rows of 32 bf16 channels with their four 16-byte groups XOR-swizzled
-// by the row index (spreads the 16-byte reads of a wavefront over the banks).
-__device__ __forceinline__ int swz(int row, int grp) { return row * C + ((grp ^ (row & 3)) << 3); }
+// LDS rows of 32 bf16 channels (64 bytes) with their four 16-byte groups
+// XOR-swizzled by bits 1-2 of the row index.  A 16-byte read is served eight
+// lanes at a time over 32 four-byte banks; eight consecutive rows at one
+// group then land on eight distinct bank quads (row parity picks the half,
+// the swizzle the quad within it), so the reads of consecutive rows or
+// output channels are free of bank conflicts.
+__device__ __forceinline__ int swz(int row, int grp) { return row * C + ((grp ^ ((row >> 1) & 3)) << 3); }
 __device__ __forceinline__ int swz_el(int row, int ch) { return swz(row, ch >> 3) + (ch & 7); }
 
 // Fused scorer: one workgroup of four wavefronts per configuration, all 12
@@ -533,7 +552,9 @@ __device__ __forceinline__ int swz_el(int row, int ch) { return swz(row, ch >> 3
 // same epilogue as conv16_kernel and the sampler.  Used for L <= kFuseMaxL.
 constexpr int kFuseMaxL = 32;
 
-__host__ __device__ constexpr int fused_pixels(int L) { return (L + 1) * (L + 2); }
+// padded pixels per buffer, a multiple of 8 so that both buffers start on a
+// 512-byte boundary (the address arithmetic below relies on it)
+__host__ __device__ constexpr int fused_pixels(int L) { return ((L + 1) * (L + 2) + 7) / 8 * 8; }
 
 __global__ void __launch_bounds__(256) score_fused_kernel(int64_t n, int L, const int8_t* __restrict__ spins,
                                                           const __bf16* __restrict__ wf,
@@ -541,8 +562,7 @@ __global__ void __launch_bounds__(256) score_fused_kernel(int64_t n, int L, cons
                                                           float* __restrict__ logit) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = L * L, W2 = L + 2, PP = fused_pixels(L);
-    __bf16* buf0 = reinterpret_cast<__bf16*>(smem);
-    __bf16* buf1 = buf0 + PP * C;
+    __bf16* buf0 = reinterpret_cast<__bf16*>(smem);  // two buffers of PP pixels: layer input and output
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int r16 = lane & 15, kg = lane >> 4;
     const int64_t b = blockIdx.x;
@@ -556,50 +576,69 @@ __global__ void __launch_bounds__(256) score_fused_kernel(int64_t n, int L, cons
         buf0[swz_el((r + 1) * W2 + c + 1, 0)] = f2bf((float)sp[p]);
     }
     const int ntiles = (N + 15) / 16;
-    // this lane's A-row pixel in its wavefront's first tile, and the step to
+    // this lane's B-column pixel in its wavefront's first tile, and the step to
     // the next tile (64 pixels on) in rows and columns
     const int p0 = w * 16 + r16, r0 = p0 / L, c0 = p0 - r0 * L;
     const int dr64 = 64 / L, dc64 = 64 - dr64 * L;
     const int plast = (L + 1) * W2 - 2;  // padded index of pixel N - 1 (row L-1, column L-1)
+    const int toff[NT] = {-W2 - 1, -W2, -W2 + 1, -1, 0};
+    // Byte address of (row, group kg) in a buffer at byte offset `base` (a
+    // multiple of 512): with u = base / 8 + 8 row it is swz(row, kg) * 2 + base
+    // = 8 u | ((u ^ 16 kg) & 0x30), because bits 4-5 of u are bits 1-2 of row.
+    const uint32_t kg16 = 16u * kg;
+    auto lds_at = [&](uint32_t u) -> uint32_t { return (u << 3) | ((u ^ kg16) & 0x30u); };
     __syncthreads();
-    __bf16* in = buf0;
-    __bf16* out = buf1;
-    for (int l = 0; l < NL; ++l) {
-        const bool first = l == 0, last = l == NL - 1;
-        const int nt = first ? 4 : 5;
+    uint32_t in_u = 0, out_u = (uint32_t)PP * C * 2 / 8;  // buffer base / 8
+    // A fragments and biases of a layer; the next layer's are loaded before
+    // the barrier that ends the current one
+    bf16x8 Wa[NT][2], Wn[NT][2];
+    f32x4 bj0, bj1, bn0, bn1;
+    auto load_w = [&](int l, bf16x8 (&W)[NT][2], f32x4& b0, f32x4& b1) {
         const __bf16* Wl = wf + (int64_t)l * NT * C * C;
-        bf16x8 Wa[NT][2];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb) Wa[t][cb] = load8(Wl + ((int64_t)t * C + 16 * cb + r16) * C + kg * 8);
-        const f32x4 bj0 = *reinterpret_cast<const f32x4*>(bias + l * C + 4 * kg);
-        const f32x4 bj1 = *reinterpret_cast<const f32x4*>(bias + l * C + 16 + 4 * kg);
-        const int toff[NT] = {-W2 - 1, -W2, -W2 + 1, -1, 0};
+            for (int cb = 0; cb < 2; ++cb) W[t][cb] = load8(Wl + ((int64_t)t * C + 16 * cb + r16) * C + kg * 8);
+        b0 = *reinterpret_cast<const f32x4*>(bias + l * C + 4 * kg);
+        b1 = *reinterpret_cast<const f32x4*>(bias + l * C + 16 + 4 * kg);
+    };
+    load_w(0, Wa, bj0, bj1);
+    // one layer over this wavefront's tiles; K = 0 first layer (four taps, no
+    // residual), 1 hidden layer, 2 last layer (the logit only)
+    auto pass = [&](auto kind) {
+        constexpr int K = decltype(kind)::value;
+        constexpr bool first = K == 0, last = K == 2;
+        constexpr int nt = first ? 4 : 5;
         int r = r0, c = c0;
 #pragma unroll 1
         for (int tile = w; tile < ntiles; tile += 4) {
             // the ragged tail reads a valid pixel; its outputs are dropped
-            const int pid = (tile * 16 + r16 < N) ? (r + 1) * W2 + c + 1 : plast;
-            f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+            const bool live = tile * 16 + r16 < N;
+            const int pid = live ? (r + 1) * W2 + c + 1 : plast;
+            bf16x8 a[NT];
+            const uint32_t u = in_u + 8u * (uint32_t)pid;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                if (t >= nt) break;
-                const bf16x8 a = *reinterpret_cast<const bf16x8*>(in + swz(pid + toff[t], kg));
-                acc0 = mfma16(Wa[t][0], a, acc0);
-                if (!last) acc1 = mfma16(Wa[t][1], a, acc1);
+            for (int t = 0; t < nt; ++t)
+                a[t] = *reinterpret_cast<const bf16x8*>(smem + lds_at(u + 8 * toff[t]));
+            f32x4 acc0 = bj0, acc1 = bj1;
+#pragma unroll
+            for (int t = 0; t < nt; ++t) {
+                acc0 = mfma16(Wa[t][0], a[t], acc0);
+                if (!last) acc1 = mfma16(Wa[t][1], a[t], acc1);
             }
-            const int pi = tile * 16 + r16;  // this lane's pixel (its D column)
-            if (pi < N) {
-                if (last) {
-                    if (kg == 0) logit[b * N + pi] = acc0[0] + bj0[0];
-                } else {
-                    const int o0 = swz_el(pid, 4 * kg), o1 = swz_el(pid, 16 + 4 * kg);
-                    const bf16x4 r0 = first ? zero4() : *reinterpret_cast<const bf16x4*>(in + o0);
-                    const bf16x4 r1 = first ? zero4() : *reinterpret_cast<const bf16x4*>(in + o1);
-                    *reinterpret_cast<bf16x4*>(out + o0) = hidden_out4(first, acc0, bj0, r0);
-                    *reinterpret_cast<bf16x4*>(out + o1) = hidden_out4(first, acc1, bj1, r1);
+            if (last) {
+                if (live && kg == 0) logit[b * N + tile * 16 + r16] = acc0[0];
+            } else {
+                // the residual inputs are the centre tap's operand in the D layout
+                f32x4 rf0 = {0.f, 0.f, 0.f, 0.f}, rf1 = rf0;
+                if (!first) {
+                    bf16x4 h0, h1;
+                    ungroup(a[4], h0, h1);
+                    rf0 = widen4(h0);
+                    rf1 = widen4(h1);
                 }
+                const bf16x8 o = regroup(hidden_out4f(first, acc0, rf0), hidden_out4f(first, acc1, rf1));
+                if (live) *reinterpret_cast<bf16x8*>(smem + lds_at(out_u + 8u * (uint32_t)pid)) = o;
             }
             r += dr64;
             c += dc64;
@@ -608,10 +647,26 @@ __global__ void __launch_bounds__(256) score_fused_kernel(int64_t n, int L, cons
                 ++r;
             }
         }
+    };
+    for (int l = 0; l < NL; ++l) {
+        if (l == 0)
+            pass(std::integral_constant<int, 0>{});
+        else if (l < NL - 1)
+            pass(std::integral_constant<int, 1>{});
+        else
+            pass(std::integral_constant<int, 2>{});
+        if (l + 1 < NL) load_w(l + 1, Wn, bn0, bn1);
         __syncthreads();
-        __bf16* t_ = in;
-        in = out;
-        out = t_;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            Wa[t][0] = Wn[t][0];
+            Wa[t][1] = Wn[t][1];
+        }
+        bj0 = bn0;
+        bj1 = bn1;
+        const uint32_t t_ = in_u;
+        in_u = out_u;
+        out_u = t_;
     }
 }
 
@@ -688,8 +743,11 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
     // A fragments of layer l for both halves (the centre tap is masked in the first layer, the last
     // layer has one output channel)
     bf16x8 bw0[NT], bw1[NT];
+    f32x4 bj0, bj1;  // biases of the lane's output channels: the accumulators' initial values
     auto load_w = [&](int l) {
         const __bf16* Wl = wl + l * NT * C * C;
+        bj0 = *reinterpret_cast<const f32x4*>(bl + l * C + 4 * kg);
+        bj1 = *reinterpret_cast<const f32x4*>(bl + l * C + 16 + 4 * kg);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const bool used = t < 4 || l > 0;
@@ -725,7 +783,7 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
         for (int l = 0; l < NL; ++l) {
             const bool last = l == NL - 1;
             const bf16x8 op[4] = {up0[l], up1[l], pr[l % kAhead], left[l]};
-            f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+            f32x4 acc0 = bj0, acc1 = bj1;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 acc0 = mfma16(bw0[t], op[t], acc0);
@@ -750,10 +808,8 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
                 up1[l] = fetch(l, true, 0);
             }
             if (!last) {
-                const f32x4 bj0 = *reinterpret_cast<const f32x4*>(bl + l * C + 4 * kg);
-                const f32x4 bj1 = *reinterpret_cast<const f32x4*>(bl + l * C + 16 + 4 * kg);
-                const bf16x4 h0 = hidden_out4f(l == 0, acc0, bj0, hp0);
-                const bf16x4 h1 = hidden_out4f(l == 0, acc1, bj1, hp1);
+                const bf16x4 h0 = hidden_out4f(l == 0, acc0, hp0);
+                const bf16x4 h1 = hidden_out4f(l == 0, acc1, hp1);
                 char* dst = reinterpret_cast<char*>(ring + (ring_w - ring) + slot(l + 1, c)) + wr_off;
                 *reinterpret_cast<bf16x4*>(dst) = h0;
                 *reinterpret_cast<bf16x4*>(dst + 32) = h1;
@@ -762,7 +818,7 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
                 hp1 = widen4(h1);
             } else {
                 // the logit is output channel 0: element 0 of the lanes with kg == 0
-                const float x = acc0[0] + bl[l * C];
+                const float x = acc0[0];
                 const float p = 1.f / (1.f + expf(-x));
                 const __bf16 sg = f2bf((u < p) ? 1.f : -1.f);
                 bf16x8 s8 = zero8();
