@@ -145,17 +145,23 @@ __device__ __forceinline__ SweepK load_sweep(const uint32_t* tb, int lane) {
     return K;
 }
 
+// a[k] and a[k] = v for a runtime k, as bit masks over constant indices: a
+// select between array elements would be folded into an indexed load, which
+// keeps the whole array in memory (scratch or LDS) instead of registers
 template <int N>
 __device__ __forceinline__ uint32_t pick(const uint32_t (&a)[N], int k) {
-    uint32_t v = a[0];
+    uint32_t v = 0u;
 #pragma unroll
-    for (int x = 1; x < N; ++x) v = (k == x) ? a[x] : v;
+    for (int x = 0; x < N; ++x) v |= a[x] & (0u - (uint32_t)(k == x));
     return v;
 }
 template <int N>
 __device__ __forceinline__ void put(uint32_t (&a)[N], int k, uint32_t v) {
 #pragma unroll
-    for (int x = 0; x < N; ++x) a[x] = (k == x) ? v : a[x];
+    for (int x = 0; x < N; ++x) {
+        const uint32_t msk = 0u - (uint32_t)(k == x);
+        a[x] = (a[x] & ~msk) | (v & msk);
+    }
 }
 
 struct Rng {
