@@ -17,6 +17,12 @@ Mask A taps (dr, dc): (-1,-1) (-1,0) (-1,1) (0,-1) (sites strictly before the
 current one in raster order); mask B adds the centre (0,0).  The logit at a
 site therefore depends only on earlier sites.
 
+Conditional network: a point x (a few scalar features of the Hamiltonian,
+e.g. J2/J1, h/J1 and ln T) shifts every layer's biases by g(x) = W2^T tanh(W1^T x
++ b1), one vector of C values per layer (only channel 0 matters in the logit
+layer); a fresh conditional network has W2 = 0 and equals its unconditional
+part.
+
 Target of the Gibbs chain (the CRBM marginal with the fixed-point weights):
   log pi(v) = a' M + sum_t c_t n_t(v) + const,  c_t = log cosh(2 w'_t),
 n_t = number of type-t bonds with s_a = sig_t s_b, w' = wq / 2^16,
@@ -31,6 +37,8 @@ import numpy as np
 TAPS_A = [(-1, -1), (-1, 0), (-1, 1), (0, -1)]
 TAPS_B = TAPS_A + [(0, 0)]
 N_LAYERS = 12
+COND_FEATURES = 3
+COND_HIDDEN = 32
 
 
 def bf16(x):
@@ -95,8 +103,38 @@ def _conv_w(x, g, taps):
     return dW
 
 
-def forward(params, spins, emulate_bf16=True):
-    """spins [B, L, L] of +-1 -> (log q [B], cache for backward)."""
+def init_cond(C=32, seed=0, H=COND_HIDDEN):
+    """Seeded conditioning MLP: W1 [3, H] ~ N(0, 1/3), b1 = 0, W2 = 0 [H, 12, C]."""
+    rng = np.random.default_rng(seed)
+    return {"W1": rng.standard_normal((COND_FEATURES, H)) / math.sqrt(COND_FEATURES),
+            "b1": np.zeros(H), "W2": np.zeros((H, N_LAYERS, C))}
+
+
+def cond_bias(cond, feats):
+    """Bias offsets of points feats [P, 3] -> [P, 12, C]."""
+    h = np.tanh(np.asarray(feats, np.float64) @ cond["W1"] + cond["b1"])
+    return np.einsum("ph,hlc->plc", h, cond["W2"])
+
+
+def cond_grad(cond, feats, point_idx, gbias):
+    """Gradient of a loss with respect to the MLP, given the loss gradient
+    gbias [B, 12, C] with respect to each sample's bias offsets and the
+    sample -> point map point_idx [B]."""
+    feats = np.asarray(feats, np.float64)
+    P = feats.shape[0]
+    gp = np.zeros((P,) + gbias.shape[1:])
+    np.add.at(gp, np.asarray(point_idx), gbias)  # per point: offsets are shared by its samples
+    pre = feats @ cond["W1"] + cond["b1"]
+    h = np.tanh(pre)
+    dW2 = np.einsum("ph,plc->hlc", h, gp)
+    dh = np.einsum("hlc,plc->ph", cond["W2"], gp)
+    dpre = dh * (1.0 - h * h)
+    return {"W1": feats.T @ dpre, "b1": dpre.sum(axis=0), "W2": dW2}
+
+
+def forward(params, spins, emulate_bf16=True, bias_add=None):
+    """spins [B, L, L] of +-1 -> (log q [B], cache for backward).  bias_add
+    [B, 12, C] (optional): per-sample bias offsets of a conditional network."""
     rb = bf16 if emulate_bf16 else (lambda v: np.asarray(v, np.float64))
     s = np.asarray(spins, np.float64)
     h = s[..., None]
@@ -105,6 +143,8 @@ def forward(params, spins, emulate_bf16=True):
         W, b = params[l]
         taps = TAPS_A if l == 0 else TAPS_B
         z = _conv(h, rb(W), taps) + b
+        if bias_add is not None:
+            z = z + np.asarray(bias_add, np.float64)[:, None, None, l, :z.shape[3]]
         zs.append(z)
         if l == N_LAYERS - 1:
             logit = z[..., 0]
@@ -119,16 +159,20 @@ def forward(params, spins, emulate_bf16=True):
     return logq, {"hs": hs, "zs": zs, "logit": logit, "spins": s, "rb": rb}
 
 
-def loss_and_grad(params, spins, emulate_bf16=True):
+def loss_and_grad(params, spins, emulate_bf16=True, bias_add=None, per_sample_bias=False):
     """Mean negative log-likelihood over the batch and its gradient
-    (hand-derived backward, straight through the bf16 roundings)."""
-    logq, c = forward(params, spins, emulate_bf16)
+    (hand-derived backward, straight through the bf16 roundings).  With
+    per_sample_bias, also the gradient with respect to each sample's bias
+    offsets [B, 12, C] (zero beyond the logit layer's one channel)."""
+    logq, c = forward(params, spins, emulate_bf16, bias_add)
     rb = c["rb"]
     B = spins.shape[0]
     s, logit = c["spins"], c["logit"]
     # d(-log sigmoid(s l))/dl = -s (1 - sigmoid(s l))
     g = -s * (1.0 / (1.0 + np.exp(s * logit))) / B
     grads = [None] * N_LAYERS
+    C = params[0][0].shape[2]
+    gbias = np.zeros((B, N_LAYERS, C))
     dz = g[..., None]
     for l in range(N_LAYERS - 1, -1, -1):
         W, b = params[l]
@@ -136,6 +180,7 @@ def loss_and_grad(params, spins, emulate_bf16=True):
         hin = c["hs"][l]
         dzb = rb(dz)
         grads[l] = (_conv_w(hin, dzb, taps), dz.sum(axis=(0, 1, 2)))
+        gbias[:, l, :dz.shape[3]] = dz.sum(axis=(1, 2))
         if l == 0:
             break
         dh_in = _conv_t(dzb, rb(W), taps)
@@ -144,19 +189,21 @@ def loss_and_grad(params, spins, emulate_bf16=True):
         dh = dh_in
         zprev = c["zs"][l - 1]
         dz = dh * (zprev > 0)
+    if per_sample_bias:
+        return -logq.mean(), grads, gbias
     return -logq.mean(), grads
 
 
-def sample(params, n, L, uniforms, emulate_bf16=True):
+def sample(params, n, L, uniforms, emulate_bf16=True, bias_add=None):
     """Ancestral sampling in raster order; uniforms [n, L*L] in [0, 1):
     sigma_i = +1 iff u_i < sigmoid(logit_i).  Returns spins and log q."""
     s = np.zeros((n, L, L))
     for i in range(L * L):
         r, c = divmod(i, L)
-        logq, cache = forward(params, s, emulate_bf16)
+        logq, cache = forward(params, s, emulate_bf16, bias_add)
         p = 1.0 / (1.0 + np.exp(-cache["logit"][:, r, c]))
         s[:, r, c] = np.where(uniforms[:, i] < p, 1.0, -1.0)
-    logq, _ = forward(params, s, emulate_bf16)
+    logq, _ = forward(params, s, emulate_bf16, bias_add)
     return s.astype(np.int8), logq
 
 

@@ -88,3 +88,84 @@ def test_mh_with_exact_proposal_accepts_everything():
     lp_cur, lp_prop = rng.normal(size=100), rng.normal(size=100)
     acc = ar.mh_accept(lp_cur, lp_cur, lp_prop, lp_prop, rng.random(100))
     assert acc.all()
+
+
+# ---------------------------------------------------------------- conditional network
+
+def _cond_nonzero(seed, scale=0.3):
+    """A conditioning MLP with random (not zero) output weights."""
+    c = ar.init_cond(seed=seed)
+    c["b1"] = np.random.default_rng(seed + 1).standard_normal(c["b1"].shape) * 0.2
+    c["W2"] = np.random.default_rng(seed + 2).standard_normal(c["W2"].shape) * scale
+    return c
+
+
+FEATS = np.array([[1.0, 0.0, math.log(0.4)], [0.5, 1.2, math.log(0.2)], [2.0, -0.5, 0.0]])
+
+
+def test_fresh_conditional_network_is_the_unconditional_one():
+    """W2 = 0 at initialisation: every point's offsets vanish."""
+    params = ar.init_params(seed=11, scale=0.7)
+    c = ar.init_cond(seed=12)
+    s = (2 * np.random.default_rng(2).integers(0, 2, (4, 6, 6)) - 1).astype(np.int8)
+    off = ar.cond_bias(c, FEATS)[[0, 1, 2, 1]]
+    assert np.all(off == 0.0)
+    lq0, _ = ar.forward(params, s)
+    lq1, _ = ar.forward(params, s, bias_add=off)
+    assert np.array_equal(lq0, lq1)
+
+
+@pytest.mark.parametrize("point", [1])
+def test_conditional_normalised_per_point_4x4(point):
+    """For every point, q(. | x) sums to 1 over all 2^16 states."""
+    params = ar.init_params(seed=13, scale=1.0)
+    c = _cond_nonzero(14)
+    states = P.all_states(4)
+    off = np.repeat(ar.cond_bias(c, FEATS)[point][None], states.shape[0], axis=0)
+    assert np.abs(off).max() > 0.1  # the offsets are not trivial
+    lq, _ = ar.forward(params, states, bias_add=off)
+    assert abs(np.logaddexp.reduce(lq)) < 1e-9
+
+
+def test_constant_offset_is_a_base_bias_shift():
+    """The same offsets for every sample equal adding them to the base biases
+    (the logit layer uses channel 0 only)."""
+    params = ar.init_params(seed=15, scale=0.8)
+    rng = np.random.default_rng(3)
+    off = rng.standard_normal((ar.N_LAYERS, 32)) * 0.3
+    shifted = [(W, b + off[l, :b.size]) for l, (W, b) in enumerate(params)]
+    s = (2 * rng.integers(0, 2, (3, 6, 6)) - 1).astype(np.int8)
+    lq0, _ = ar.forward(params, s, bias_add=np.repeat(off[None], 3, axis=0))
+    lq1, _ = ar.forward(shifted, s)
+    assert np.allclose(lq0, lq1, rtol=0, atol=1e-12)
+
+
+def test_conditional_gradient_matches_finite_differences():
+    """d loss / d (W1, b1, W2) from the per-sample bias gradients and the MLP
+    backward against central differences of the loss (no bf16 rounding, so
+    the loss is smooth)."""
+    params = ar.init_params(seed=16, scale=1.0)
+    params = [(W, b + 0.05) for W, b in params]  # keep pre-activations off the ReLU kink
+    c = _cond_nonzero(17, scale=0.2)
+    rng = np.random.default_rng(4)
+    s = (2 * rng.integers(0, 2, (5, 4, 4)) - 1).astype(np.int8)
+    idx = np.array([0, 2, 1, 2, 0])
+
+    def loss_of(cc):
+        off = ar.cond_bias(cc, FEATS)[idx]
+        return ar.loss_and_grad(params, s, emulate_bf16=False, bias_add=off)[0]
+
+    _, _, gb = ar.loss_and_grad(params, s, emulate_bf16=False, bias_add=ar.cond_bias(c, FEATS)[idx],
+                                per_sample_bias=True)
+    g = ar.cond_grad(c, FEATS, idx, gb)
+    h = 1e-6
+    for name, picks in (("W1", [(0, 3), (2, 17)]), ("b1", [(5,), (30,)]), ("W2", [(1, 0, 4), (7, 11, 0), (9, 5, 31)])):
+        for ix in picks:
+            cp = {k: v.copy() for k, v in c.items()}
+            cm = {k: v.copy() for k, v in c.items()}
+            cp[name][ix] += h
+            cm[name][ix] -= h
+            fd = (loss_of(cp) - loss_of(cm)) / (2 * h)
+            assert abs(fd - g[name][ix]) < 1e-6 + 1e-5 * abs(fd), (name, ix, fd, g[name][ix])
+    # the logit layer's channels 1..31 carry no gradient
+    assert np.all(g["W2"][:, ar.N_LAYERS - 1, 1:] == 0.0)
