@@ -210,7 +210,23 @@ typedef struct {
     int32_t layers;     /* must be 12 */
     uint64_t seed;      /* random stream of the sequential scorer (unused by training) */
     void* stream;       /* hipStream_t */
+    int32_t cond_points;/* 0: unconditional; 1..128: conditional network for up to this many points */
 } crbm_ar_config;
+
+/* Conditional network (an addition for the multi-point workloads): each point
+ * p has a feature vector x_p of 3 doubles chosen by the caller (for example
+ * J2/J1, h/J1 and ln T of a Hamiltonian point); every layer's biases are
+ * shifted by g(x_p) = W2^T tanh(W1^T x_p + b1) (32 hidden units), so one
+ * network serves all points.  The MLP parameters follow the network's in the
+ * parameter layout: W1 [3][32], b1 [32], W2 [32][12][32] (layer, channel; only
+ * channel 0 of the logit layer is used).  crbm_ar_init_params draws W1 from
+ * N(0, 1/3) and zeroes b1 and W2.  A conditional network needs its points
+ * (crbm_ar_set_points) before it trains, scores or samples (else
+ * CRBM_ESTATE).  The *_cond calls take a device int32 array `points_dev` with
+ * one point index per configuration (values are clamped to [0, n_points));
+ * NULL means point 0 for every configuration.  On an unconditional network
+ * points_dev is ignored and the plain calls below are the *_cond calls with
+ * NULL. */
 
 int crbm_ar_create(const crbm_ar_config* c, crbm_ar_t** out);   /* parameters start at zero */
 int64_t crbm_ar_num_params(const crbm_ar_t* a);
@@ -221,6 +237,17 @@ int crbm_ar_get_params(crbm_ar_t* a, float* host, int64_t n);
  * layer, drawn by SplitMix64 + Box-Muller from `seed`; biases zero.  Resets
  * the Adam state.  Synchronises.  CRBM_EINVAL for scale < 0. */
 int crbm_ar_init_params(crbm_ar_t* a, uint64_t seed, double scale);
+/* Set the feature vectors of the points (host, [n_points][3]; copied).
+ * CRBM_EINVAL if the network is unconditional, n_points is not in
+ * 1..cond_points or a feature is not finite.  Synchronises. */
+int crbm_ar_set_points(crbm_ar_t* a, int32_t n_points, const double* feats_host);
+int crbm_ar_grad_cond(crbm_ar_t* a, const int8_t* samples_dev, const int32_t* points_dev, int64_t batch,
+                      float* grad_host, double* loss_out);
+int crbm_ar_train_step_cond(crbm_ar_t* a, const int8_t* samples_dev, const int32_t* points_dev, int64_t batch,
+                            float lr, double* loss_out);
+int crbm_ar_logq_cond(crbm_ar_t* a, const int8_t* spins_dev, const int32_t* points_dev, int64_t n, double* logq_dev);
+int crbm_ar_sample_cond(crbm_ar_t* a, int64_t n, uint64_t seed, int64_t step, uint32_t id, const int32_t* points_dev,
+                        int8_t* spins_dev, double* logq_dev);
 /* Gradient of the mean negative log-likelihood over a batch of samples
  * (device int8 +-1 [batch][L][L]); grad_host (may be NULL) receives it in the
  * parameter layout, loss_out (may be NULL) the loss.  Synchronises. */
@@ -238,10 +265,14 @@ int crbm_ar_logq(crbm_ar_t* a, const int8_t* spins_dev, int64_t n, double* logq_
 int crbm_ar_sample(crbm_ar_t* a, int64_t n, uint64_t seed, int64_t step, uint32_t id, int8_t* spins_dev,
                    double* logq_dev);
 /* n_cycles of: gibbs_per_mh Gibbs sweeps of h (crbm_sample), then one
- * independent MH step per chain with a's proposals; h must hold one instance
- * with a constant temperature and the same L, on the same stream.  Cycle k of
- * the network's life draws its proposals with step = k and its MH uniform from
- * Philox (ctr = (0, k, chain, id << 3 | 5)).  counts_trace
+ * independent MH step per chain with a's proposals; every instance of h must
+ * have the network's L and a constant temperature, and h and a must use the
+ * same stream.  Each chain's acceptance uses its own instance's target.  A
+ * conditional network draws the proposals of instance i's chains at point i
+ * (CRBM_EINVAL if fewer points are set than h has instances).  Cycle k of the
+ * network's life draws its proposals with step = k and its MH uniforms from
+ * Philox (ctr = (0, k, chain, id << 3 | 5)); chain is the index over all
+ * instances' chains and id the first instance's id.  counts_trace
  * (device, may be NULL): int32 (M, B1, B2) after each cycle, [n_cycles][chains][3].
  * order_trace (device, may be NULL): the plateau structure factor record of
  * crbm_sample_thinned after each cycle, same layout.

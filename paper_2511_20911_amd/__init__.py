@@ -67,7 +67,7 @@ class _Obs(ct.Structure):
 
 class _ARConfig(ct.Structure):
     _fields_ = [("L", ct.c_int32), ("channels", ct.c_int32), ("layers", ct.c_int32), ("seed", ct.c_uint64),
-                ("stream", ct.c_void_p)]
+                ("stream", ct.c_void_p), ("cond_points", ct.c_int32)]
 
 
 _lib = None
@@ -113,6 +113,14 @@ def lib() -> ct.CDLL:
                                      ct.c_void_p]
         L.crbm_sample_mh.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p, ct.c_void_p,
                                      p(ct.c_int64)]
+        L.crbm_ar_set_points.argtypes = [ct.c_void_p, ct.c_int32, p(ct.c_double)]
+        L.crbm_ar_grad_cond.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, p(ct.c_float),
+                                        p(ct.c_double)]
+        L.crbm_ar_train_step_cond.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_float,
+                                              p(ct.c_double)]
+        L.crbm_ar_logq_cond.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p]
+        L.crbm_ar_sample_cond.argtypes = [ct.c_void_p, ct.c_int64, ct.c_uint64, ct.c_int64, ct.c_uint32,
+                                          ct.c_void_p, ct.c_void_p, ct.c_void_p]
         L.crbm_ar_destroy.argtypes = [ct.c_void_p]
         L.crbm_ar_destroy.restype = None
         L.crbm_tau_int.argtypes = [ct.c_void_p, ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int64,
@@ -308,15 +316,28 @@ class Sampler:
         return out
 
 
-class ARNet:
-    """Handle on the learned autoregressive proposal (crbm_ar_*)."""
+def _points_ptr(points, n):
+    """Device pointer of an int32 CUDA tensor of n point indices, or None."""
+    if points is None:
+        return None
+    import torch
+    assert points.is_cuda and points.dtype == torch.int32 and points.numel() == n and points.is_contiguous()
+    return ct.c_void_p(points.data_ptr())
 
-    def __init__(self, L: int, seed: int = 0, stream=None):
+
+class ARNet:
+    """Handle on the learned autoregressive proposal (crbm_ar_*).  With
+    cond_points > 0 the network is conditional: set_points() gives each point
+    a feature vector of 3 numbers, and the calls take `points`, an int32
+    CUDA tensor with one point index per configuration (None = point 0)."""
+
+    def __init__(self, L: int, seed: int = 0, stream=None, cond_points: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the network runs only on the HIP device")
         self.L = L
-        cfg = _ARConfig(L, 32, 12, seed, _stream_handle(stream))
+        self.cond_points = cond_points
+        cfg = _ARConfig(L, 32, 12, seed, _stream_handle(stream), cond_points)
         h = ct.c_void_p()
         _check(lib().crbm_ar_create(ct.byref(cfg), ct.byref(h)))
         self._h = h
@@ -342,33 +363,40 @@ class ARNet:
         _check(lib().crbm_ar_get_params(self._h, a.ctypes.data_as(ct.POINTER(ct.c_float)), a.size))
         return a
 
-    def grad(self, samples):
+    def set_points(self, feats):
+        """Feature vectors of the points, [n_points, 3] (conditional network)."""
+        f = np.ascontiguousarray(feats, np.float64)
+        assert f.ndim == 2 and f.shape[1] == 3
+        _check(lib().crbm_ar_set_points(self._h, f.shape[0], f.ctypes.data_as(ct.POINTER(ct.c_double))))
+
+    def grad(self, samples, points=None):
         assert samples.is_cuda and samples.dtype.itemsize == 1
         g = np.zeros(self.num_params, np.float32)
         loss = ct.c_double()
-        _check(lib().crbm_ar_grad(self._h, ct.c_void_p(samples.data_ptr()), samples.shape[0],
-                                  g.ctypes.data_as(ct.POINTER(ct.c_float)), ct.byref(loss)))
+        _check(lib().crbm_ar_grad_cond(self._h, ct.c_void_p(samples.data_ptr()), _points_ptr(points, samples.shape[0]),
+                                       samples.shape[0], g.ctypes.data_as(ct.POINTER(ct.c_float)), ct.byref(loss)))
         return g, float(loss.value)
 
-    def train_step(self, samples, lr: float) -> float:
+    def train_step(self, samples, lr: float, points=None) -> float:
         loss = ct.c_double()
-        _check(lib().crbm_ar_train_step(self._h, ct.c_void_p(samples.data_ptr()), samples.shape[0], lr,
-                                        ct.byref(loss)))
+        _check(lib().crbm_ar_train_step_cond(self._h, ct.c_void_p(samples.data_ptr()),
+                                             _points_ptr(points, samples.shape[0]), samples.shape[0], lr,
+                                             ct.byref(loss)))
         return float(loss.value)
 
-    def logq(self, spins):
+    def logq(self, spins, points=None):
         import torch
         out = torch.empty(spins.shape[0], dtype=torch.float64, device="cuda")
-        _check(lib().crbm_ar_logq(self._h, ct.c_void_p(spins.data_ptr()), spins.shape[0],
-                                  ct.c_void_p(out.data_ptr())))
+        _check(lib().crbm_ar_logq_cond(self._h, ct.c_void_p(spins.data_ptr()), _points_ptr(points, spins.shape[0]),
+                                       spins.shape[0], ct.c_void_p(out.data_ptr())))
         return out
 
-    def sample(self, n: int, seed: int, step: int = 0, id: int = 0):
+    def sample(self, n: int, seed: int, step: int = 0, id: int = 0, points=None):
         import torch
         spins = torch.empty((n, self.L, self.L), dtype=torch.int8, device="cuda")
         lq = torch.empty(n, dtype=torch.float64, device="cuda")
-        _check(lib().crbm_ar_sample(self._h, n, seed, step, id, ct.c_void_p(spins.data_ptr()),
-                                    ct.c_void_p(lq.data_ptr())))
+        _check(lib().crbm_ar_sample_cond(self._h, n, seed, step, id, _points_ptr(points, n),
+                                         ct.c_void_p(spins.data_ptr()), ct.c_void_p(lq.data_ptr())))
         return spins, lq
 
 

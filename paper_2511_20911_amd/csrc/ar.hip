@@ -34,6 +34,9 @@ namespace ar {
 constexpr int C = 32;
 constexpr int NL = 12;
 constexpr int NT = 5;  // taps per layer (mask A uses the first 4)
+// conditioning MLP: features -> hidden (tanh) -> one bias offset per layer and channel
+constexpr int kCondF = 3, kCondH = 32, kCondOut = NL * C;
+constexpr int kCondMaxPoints = 128;
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
@@ -95,9 +98,13 @@ enum { EP_RELU = 0, EP_RESID = 1, EP_LOGIT = 2, EP_DGRAD = 3, EP_DGRAD_RESID = 4
 //   acc[p][j] = sum_t sum_k in[p + tap_t][k] * Wop[t][j][k]
 // with the matrix-core layout: A row i = pixel, B column j = out channel,
 // k = 16-element chunks of the 32 input channels of each tap.
+// bias: layer biases [C] (pt == nullptr), or layer row of a per-point table
+// with rows kCondOut apart, the row of pixel p being that of its sample's
+// point pt[p / L^2] (clamped to [0, npts))
 __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ Wop,
-                                                     const float* __restrict__ bias, Taps taps, int L, int64_t P,
-                                                     int mode, const __bf16* __restrict__ resid_bf,
+                                                     const float* __restrict__ bias, const int32_t* __restrict__ pt,
+                                                     int npts, Taps taps, int L, int64_t P, int mode,
+                                                     const __bf16* __restrict__ resid_bf,
                                                      const float* __restrict__ resid_f, __bf16* out_bf,
                                                      uint8_t* out_mask, float* out_f) {
     const int lane = threadIdx.x & 63;
@@ -111,7 +118,9 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
 #pragma unroll
         for (int kh = 0; kh < 2; ++kh)
             Bf[t][kh] = (t < taps.n) ? load8(Wop + ((int64_t)t * C + li) * C + kh * 16 + half * 8) : zero8();
-    const float bj = (mode == EP_DGRAD || mode == EP_DGRAD_RESID) ? 0.f : bias[li];
+    const bool dgrad = mode == EP_DGRAD || mode == EP_DGRAD_RESID;
+    const float bj = dgrad ? 0.f : bias[li];
+    const int64_t LL = (int64_t)L * L;
     const int64_t ntiles = (P + 31) / 32;
     for (int64_t tile = w0; tile < ntiles; tile += nw) {
         const int64_t p = tile * 32 + li;
@@ -134,7 +143,12 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
             const int i = 8 * (v >> 2) + 4 * half + (v & 3);
             const int64_t pi = tile * 32 + i;
             if (pi >= P) continue;
-            const float z = acc[v] + bj;
+            float bv = bj;
+            if (pt && !dgrad) {
+                const int q = pt[pi / LL];
+                bv = bias[(int64_t)(q < 0 ? 0 : (q >= npts ? npts - 1 : q)) * kCondOut + li];
+            }
+            const float z = acc[v] + bv;
             const int64_t o = pi * C + li;
             switch (mode) {
                 case EP_RELU:
@@ -357,6 +371,126 @@ __global__ void __launch_bounds__(256) colsum0_kernel(const float* g32, int64_t 
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// ------------------------------------------------------------------------
+// Conditioning.  A point's features x (kCondF values) shift the biases of
+// every layer by g(x) = W2^T tanh(W1^T x + b1); MLP parameters (fp32) are
+// W1 [kCondF][kCondH], b1 [kCondH], W2 [kCondH][NL][C].  The inference and
+// training kernels read the per-point table cb[p][l][c] = bias[l][c] + g(x_p).
+
+__device__ __forceinline__ int clamp_point(int q, int npts) { return q < 0 ? 0 : (q >= npts ? npts - 1 : q); }
+
+// one workgroup (kCondOut threads) per point
+__global__ void __launch_bounds__(kCondOut) cond_bias_kernel(const float* __restrict__ mlp,
+                                                             const float* __restrict__ feats,
+                                                             const float* __restrict__ bias, float* __restrict__ cb) {
+    __shared__ float hsh[kCondH];
+    const int p = blockIdx.x, j = threadIdx.x;
+    const float* W1 = mlp;
+    const float* b1 = W1 + kCondF * kCondH;
+    const float* W2 = b1 + kCondH;
+    if (j < kCondH) {
+        float z = b1[j];
+#pragma unroll
+        for (int f = 0; f < kCondF; ++f) z += feats[p * kCondF + f] * W1[f * kCondH + j];
+        hsh[j] = tanhf(z);
+    }
+    __syncthreads();
+    float g = 0.f;
+#pragma unroll 8
+    for (int k = 0; k < kCondH; ++k) g += hsh[k] * W2[k * kCondOut + j];
+    cb[(int64_t)p * kCondOut + j] = bias[j] + g;
+}
+
+// gradient of the loss with respect to each sample's biases of layer l: the
+// sum over the sample's pixels of the pre-activation gradient (masked dh, or
+// the logit gradient g32 in the logit layer), in a fixed order; one
+// workgroup per sample, 8 pixel slices x 32 channels
+__global__ void __launch_bounds__(256) sample_bias_grad_kernel(const float* __restrict__ dh,
+                                                               const uint8_t* __restrict__ mask,
+                                                               const float* __restrict__ g32, int N, int l,
+                                                               float* __restrict__ gs) {
+    const int64_t b = blockIdx.x;
+    const int c = threadIdx.x & 31, slot = threadIdx.x >> 5;
+    float s = 0.f;
+    if (g32) {
+        if (c == 0)
+            for (int i = slot; i < N; i += 8) s += g32[b * N + i];
+    } else {
+        for (int i = slot; i < N; i += 8) {
+            const int64_t o = (b * N + i) * C + c;
+            s += mask[o] ? dh[o] : 0.f;
+        }
+    }
+    __shared__ float red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (slot == 0) {
+        float t = 0.f;
+        for (int k = 0; k < 8; ++k) t += red[k * 32 + c];
+        gs[(b * NL + l) * C + c] = t;
+    }
+}
+
+// per point: the sum of its samples' bias gradients, samples in index order
+__global__ void point_grad_kernel(const float* __restrict__ gs, const int32_t* __restrict__ pt, int64_t B, int npts,
+                                  float* __restrict__ gp) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= (int64_t)npts * kCondOut) return;
+    const int p = (int)(x / kCondOut), j = (int)(x % kCondOut);
+    double s = 0.0;
+    for (int64_t b = 0; b < B; ++b)
+        if ((pt ? clamp_point(pt[b], npts) : 0) == p) s += gs[b * kCondOut + j];
+    gp[x] = (float)s;
+}
+
+// MLP backward from the per-point bias gradients gp [npts][kCondOut] into
+// gmlp (the MLP part of the gradient vector); one workgroup
+__global__ void __launch_bounds__(kCondOut) cond_backward_kernel(const float* __restrict__ mlp,
+                                                                 const float* __restrict__ feats, int npts,
+                                                                 const float* __restrict__ gp,
+                                                                 float* __restrict__ gmlp) {
+    __shared__ float hsh[kCondMaxPoints * kCondH];
+    __shared__ float dpre[kCondMaxPoints * kCondH];
+    const int j = threadIdx.x;
+    const float* W1 = mlp;
+    const float* b1 = W1 + kCondF * kCondH;
+    const float* W2 = b1 + kCondH;
+    for (int x = j; x < npts * kCondH; x += blockDim.x) {
+        const int p = x / kCondH, k = x % kCondH;
+        float z = b1[k];
+#pragma unroll
+        for (int f = 0; f < kCondF; ++f) z += feats[p * kCondF + f] * W1[f * kCondH + k];
+        hsh[x] = tanhf(z);
+    }
+    __syncthreads();
+    // dW2[k][j] = sum_p h[p][k] gp[p][j]
+    for (int k = 0; k < kCondH; ++k) {
+        float s = 0.f;
+        for (int p = 0; p < npts; ++p) s += hsh[p * kCondH + k] * gp[(int64_t)p * kCondOut + j];
+        gmlp[kCondF * kCondH + kCondH + k * kCondOut + j] = s;
+    }
+    // dpre[p][k] = (1 - h^2) sum_j W2[k][j] gp[p][j]
+    for (int x = j; x < npts * kCondH; x += blockDim.x) {
+        const int p = x / kCondH, k = x % kCondH;
+        float s = 0.f;
+        for (int jj = 0; jj < kCondOut; ++jj) s += W2[k * kCondOut + jj] * gp[(int64_t)p * kCondOut + jj];
+        const float hv = hsh[x];
+        dpre[x] = s * (1.f - hv * hv);
+    }
+    __syncthreads();
+    if (j < kCondF * kCondH) {  // dW1[f][k] = sum_p x[p][f] dpre[p][k]
+        const int f = j / kCondH, k = j % kCondH;
+        float s = 0.f;
+        for (int p = 0; p < npts; ++p) s += feats[p * kCondF + f] * dpre[p * kCondH + k];
+        gmlp[j] = s;
+    } else if (j < kCondF * kCondH + kCondH) {  // db1[k] = sum_p dpre[p][k]
+        const int k = j - kCondF * kCondH;
+        float s = 0.f;
+        for (int p = 0; p < npts; ++p) s += dpre[p * kCondH + k];
+        gmlp[j] = s;
+    }
+}
+
 // Adam on the fp32 master parameters (Kingma & Ba, 2015)
 __global__ void adam_kernel(float* th, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                             float eps, float c1, float c2) {
@@ -490,8 +624,12 @@ __device__ __forceinline__ bf16x4 zero4() {
 // weights are the A operand (rows = output channels of a 16-block) and the
 // activations the B operand (columns = pixels), so a lane's D values are four
 // consecutive output channels of its own pixel.
+// bias: this layer's row of the bias table (rows kCondOut apart; the row of
+// pixel p is that of its configuration's point pt[p / L^2], or row 0 if pt is
+// nullptr)
 __global__ void __launch_bounds__(256) conv16_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ Wl,
-                                                     const float* __restrict__ bias, int layer, int L, int64_t P,
+                                                     const float* __restrict__ bias, const int32_t* __restrict__ pt,
+                                                     int npts, int layer, int L, int64_t P,
                                                      __bf16* __restrict__ out, float* __restrict__ logit) {
     const int lane = threadIdx.x & 63;
     const int r16 = lane & 15, kg = lane >> 4;
@@ -505,11 +643,12 @@ __global__ void __launch_bounds__(256) conv16_kernel(const __bf16* __restrict__ 
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
             Wa[t][cb] = (t < taps.n) ? load8(Wl + ((int64_t)t * C + 16 * cb + r16) * C + kg * 8) : zero8();
-    const f32x4 bj0 = *reinterpret_cast<const f32x4*>(bias + 4 * kg);
-    const f32x4 bj1 = *reinterpret_cast<const f32x4*>(bias + 16 + 4 * kg);
-    const int64_t ntiles = (P + 15) / 16;
+    const int64_t ntiles = (P + 15) / 16, LL = (int64_t)L * L;
     for (int64_t tile = w0; tile < ntiles; tile += nw) {
         const int64_t p = tile * 16 + r16;
+        const float* brow = bias + (pt ? (int64_t)clamp_point(pt[(p < P ? p : P - 1) / LL], npts) * kCondOut : 0);
+        const f32x4 bj0 = *reinterpret_cast<const f32x4*>(brow + 4 * kg);
+        const f32x4 bj1 = *reinterpret_cast<const f32x4*>(brow + 16 + 4 * kg);
         f32x4 acc0 = bj0, acc1 = bj1;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
@@ -558,7 +697,8 @@ __host__ __device__ constexpr int fused_pixels(int L) { return ((L + 1) * (L + 2
 
 __global__ void __launch_bounds__(256) score_fused_kernel(int64_t n, int L, const int8_t* __restrict__ spins,
                                                           const __bf16* __restrict__ wf,
-                                                          const float* __restrict__ bias,
+                                                          const float* __restrict__ bias_tab,
+                                                          const int32_t* __restrict__ pt, int npts,
                                                           float* __restrict__ logit) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = L * L, W2 = L + 2, PP = fused_pixels(L);
@@ -568,6 +708,7 @@ __global__ void __launch_bounds__(256) score_fused_kernel(int64_t n, int L, cons
     const int64_t b = blockIdx.x;
     if (b >= n) return;  // uniform per workgroup
     const int8_t* sp = spins + b * N;
+    const float* bias = bias_tab + (pt ? (int64_t)clamp_point(pt[b], npts) * kCondOut : 0);  // [NL][C]
     // both buffers: zeros everywhere (the border stays zero), then the spins
     for (int g = tid; g < 2 * PP * 4; g += blockDim.x) *reinterpret_cast<bf16x8*>(buf0 + g * 8) = zero8();
     __syncthreads();
@@ -687,7 +828,7 @@ __global__ void __launch_bounds__(256) score_fused_kernel(int64_t n, int L, cons
 // the last layer; the logits go to logit_out for the log q sum.
 constexpr int kSeqMaxWaves = 4;
 constexpr int kSeqPad = 16 * kSeqMaxWaves;  // the ring's chain count is a multiple of this
-constexpr int kSeqLdsBytes = NL * NT * C * C * 2 + NL * C * 4;
+constexpr int kSeqLdsBytes = NL * NT * C * C * 2;
 
 // keeps the compiler from moving this wavefront's memory accesses across it
 // (its memory operations complete in order, so no instruction is needed)
@@ -697,21 +838,22 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// bias_tab: the bias table (rows kCondOut apart); chain i reads row
+// pt[i] (clamped to [0, npts)), or row 0 if pt is nullptr
 __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L, const __bf16* __restrict__ wf,
-                                                  const float* __restrict__ bias, __bf16* __restrict__ ring,
+                                                  const float* __restrict__ bias_tab, const int32_t* __restrict__ pt,
+                                                  int npts, __bf16* __restrict__ ring,
                                                   const __bf16* __restrict__ zpad, int8_t* __restrict__ spins,
                                                   float* __restrict__ logit_out, uint64_t seed, uint32_t step,
                                                   uint32_t id) {
     extern __shared__ __align__(16) unsigned char smem[];
     __bf16* wl = reinterpret_cast<__bf16*>(smem);                 // [NL][NT][C][C], rows swizzled
-    float* bl = reinterpret_cast<float*>(wl + NL * NT * C * C);   // [NL][C] biases
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int r16 = lane & 15, kg = lane >> 4;
     for (int g = tid; g < NL * NT * C * 4; g += blockDim.x) {
         const int row = g >> 2, grp = g & 3;
         *reinterpret_cast<bf16x8*>(wl + swz(row, grp)) = load8(wf + (int64_t)row * C + grp * 8);
     }
-    for (int g = tid; g < NL * C; g += blockDim.x) bl[g] = bias[g];
     __syncthreads();
     // wavefront-uniform by construction; readfirstlane lets the compiler keep it (and the ring base) scalar
     const int64_t wbase = (int64_t)blockIdx.x * (blockDim.x >> 2) + 16 * __builtin_amdgcn_readfirstlane(w);
@@ -721,6 +863,8 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
     // 16 h + 4 kg .. + 3 of its chain.
     const int64_t gca = wbase + r16;  // the ring has npad >= grid size chains: padding rows have their own slots
     const int N = L * L;
+    // this lane's chain's bias rows (padding chains read the last chain's)
+    const float* bl = bias_tab + (pt ? (int64_t)clamp_point(pt[gca < n ? gca : n - 1], npts) * kCondOut : 0);
     // Ring element (layer, chain, column, channel): [NL][npad][L][C], one row
     // per chain and layer.  Site (r, c) writes column c after the row above's
     // column c was last read (as the (-1,+1) tap of site (r, c - 1)), so the
@@ -772,6 +916,10 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
         const int r = site / L, c = site - r * L;
         const int sn = site + 1, rn = sn / L, cn = sn - rn * L;
         const bool more = sn < N;
+        // an empty statement that marks the bias row pointer as modified: the
+        // bias loads stay in the loop (vector-memory reads that hit the cache)
+        // instead of being hoisted into registers that every layer must copy
+        asm volatile("" : "+v"(bl));
         if (c == 0) {
 #pragma unroll
             for (int l = 0; l < NL; ++l) left[l] = zero8();
@@ -909,18 +1057,25 @@ __global__ void __launch_bounds__(256) counts_int8_kernel(const int8_t* s, int64
 // Independent MH (one thread per chain): log alpha = [log pi' - log pi] +
 // [log q - log q'], log pi from the exact integer counts; accept iff
 // log u < log alpha with u from Philox stream 5.
+// the MH target of one instance: log pi = a M + c1 n1 + c2 n2 (+ const)
+struct MhTarget {
+    double a, c1, c2;
+    int32_t sg1, sg2;
+};
+
+// chain ch belongs to instance ci[ch] with target tg[ci[ch]]
 __global__ void mh_kernel(int64_t n, int L, int8_t* cur, const int8_t* prop, int32_t* cnt_cur,
-                          const int32_t* cnt_prop, double* lq_cur, const double* lq_prop, double a, double c1,
-                          double c2, int sg1, int sg2, uint64_t seed, uint32_t step, uint32_t id,
-                          unsigned long long* n_acc) {
+                          const int32_t* cnt_prop, double* lq_cur, const double* lq_prop, const MhTarget* tg,
+                          const int32_t* ci, uint64_t seed, uint32_t step, uint32_t id, unsigned long long* n_acc) {
     const int64_t ch = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (ch >= n) return;
     const int64_t N = (int64_t)L * L;
+    const MhTarget t = tg[ci[ch]];
     auto logpi = [&](const int32_t* k) {
         const int64_t M = k[0], B1 = k[1], B2 = k[2];
-        const int64_t n1 = sg1 < 0 ? (2 * N - B1) / 2 : (2 * N + B1) / 2;
-        const int64_t n2 = sg2 < 0 ? (N / 2 - B2) / 2 : (N / 2 + B2) / 2;
-        return a * (double)M + c1 * (double)n1 + c2 * (double)n2;
+        const int64_t n1 = t.sg1 < 0 ? (2 * N - B1) / 2 : (2 * N + B1) / 2;
+        const int64_t n2 = t.sg2 < 0 ? (N / 2 - B2) / 2 : (N / 2 + B2) / 2;
+        return t.a * (double)M + t.c1 * (double)n1 + t.c2 * (double)n2;
     };
     const double la = (logpi(cnt_prop + ch * 3) - logpi(cnt_cur + ch * 3)) + (lq_cur[ch] - lq_prop[ch]);
     const gk::P4 r = gk::philox(0u, step, (uint32_t)ch, (id << 3) | 5u, (uint32_t)seed, (uint32_t)(seed >> 32));
@@ -989,7 +1144,13 @@ struct crbm_ar_s {
     int L = 0;
     uint64_t seed = 0;
     hipStream_t stream = nullptr;
-    int64_t np = 0;
+    int64_t np = 0;        // parameters: the network's, then (conditional) the MLP's
+    int64_t np_base = 0;   // the network's
+    int cond = 0;          // conditional: capacity in points (0 = unconditional)
+    int npts = 0;          // points set by crbm_ar_set_points
+    float* feats = nullptr;  // [cond][kCondF]
+    float* cb = nullptr;     // [cond][NL][C]: per-point bias table
+    float *gs = nullptr, *gp = nullptr;  // training: per-sample [B][NL][C] and per-point [cond][NL][C] bias gradients
     int64_t t_adam = 0;
     uint64_t mh_step = 0;  // MH cycles run so far: the counter word of their random streams
     float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr, *bias = nullptr;
@@ -1018,6 +1179,9 @@ struct crbm_ar_s {
     float* ilogit = nullptr;                // [n N]
     // MH buffers
     int64_t mcap = 0;
+    int32_t* mh_ci = nullptr;   // [chains]: instance (= point) of each chain
+    MhTarget* mh_tg = nullptr;  // [kCondMaxPoints or instances]: per-instance targets
+    int mh_tgcap = 0;
     int8_t *cur = nullptr, *prop = nullptr;
     int32_t *ccur = nullptr, *cprop = nullptr;
     double *lqc = nullptr, *lqp = nullptr;
@@ -1025,7 +1189,8 @@ struct crbm_ar_s {
     ~crbm_ar_s() {
         void* ps[] = {theta, grad, m, v, bias, wf, wb, hs, mask, logit, g32, dh0, dh1, dz, g, logq, part, dW, bpart,
                       part2, xt, dzt,
-                      spins_copy, ring, slogit, zpad, ih0, ih1, ilogit, cur, prop, ccur, cprop, lqc, lqp, nacc};
+                      spins_copy, ring, slogit, zpad, ih0, ih1, ilogit, cur, prop, ccur, cprop, lqc, lqp, nacc,
+                      feats, cb, gs, gp, mh_ci, mh_tg};
         for (void* p : ps)
             if (p) (void)hipFree(p);
     }
@@ -1051,11 +1216,12 @@ int64_t padded_pixels(int64_t P) { return (P + kTP - 1) / kTP * kTP; }
 int ensure_train(crbm_ar_t* a, int64_t B) {
     if (B <= a->tcap) return CRBM_OK;
     void* ps[] = {a->hs, a->mask, a->logit, a->g32, a->dh0, a->dh1, a->dz, a->g, a->logq, a->part, a->bpart,
-                  a->spins_copy, a->part2, a->xt, a->dzt};
+                  a->spins_copy, a->part2, a->xt, a->dzt, a->gs};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     a->part2 = nullptr;
     a->xt = a->dzt = nullptr;
+    a->gs = nullptr;
     const int64_t P = B * a->L * a->L, Ppad = padded_pixels(P);
     const int64_t nch = (Ppad + kWChunk - 1) / kWChunk;
     if (alloc(&a->hs, (int64_t)NL * P * C) || alloc(&a->mask, (int64_t)(NL - 1) * P * C) || alloc(&a->logit, P) ||
@@ -1063,7 +1229,7 @@ int ensure_train(crbm_ar_t* a, int64_t B) {
         alloc(&a->g, P * C) || alloc(&a->logq, B) || alloc(&a->part, nch * NT * C * C) ||
         alloc(&a->bpart, (int64_t)4096 * C) || alloc(&a->spins_copy, P) ||
         alloc(&a->part2, (int64_t)kRedSlices * NT * C * C) || alloc(&a->xt, (int64_t)NT * C * Ppad) ||
-        alloc(&a->dzt, (int64_t)C * Ppad)) {
+        alloc(&a->dzt, (int64_t)C * Ppad) || (a->cond > 0 && alloc(&a->gs, B * kCondOut))) {
         a->tcap = 0;
         return fail_ar(CRBM_ENOMEM, "training buffers");
     }
@@ -1089,8 +1255,23 @@ int ensure_seq(crbm_ar_t* a, int64_t n) {
 int pack(crbm_ar_t* a) {
     hipLaunchKernelGGL(pack_kernel, dim3((NL * NT * C * C + 255) / 256), dim3(256), 0, a->stream, a->theta, a->wf, a->wb,
                        a->bias);
+    if (a->cond > 0 && a->npts > 0)
+        hipLaunchKernelGGL(cond_bias_kernel, dim3((unsigned)a->npts), dim3(kCondOut), 0, a->stream,
+                           a->theta + a->np_base, a->feats, a->bias, a->cb);
     AR_TRY(hipGetLastError(), "pack");
     return CRBM_OK;
+}
+
+// the bias table the kernels read, the point map they use, and its size:
+// the per-point table of a conditional network, else the layer biases
+struct BiasSel {
+    const float* tab;
+    const int32_t* pt;
+    int npts;
+};
+BiasSel bias_sel(const crbm_ar_t* a, const int32_t* pt) {
+    if (a->cond > 0) return {a->cb, pt, a->npts};
+    return {a->bias, nullptr, 1};
 }
 
 int conv_blocks(int64_t P) {
@@ -1099,8 +1280,10 @@ int conv_blocks(int64_t P) {
     return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
 }
 
-// forward + loss + backward into a->grad; per-sample log q into a->logq
-int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B) {
+// forward + loss + backward into a->grad; per-sample log q into a->logq.
+// pt: point of each sample (conditional network), or nullptr (point 0)
+int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
+    const BiasSel bs = bias_sel(a, pt);
     const int L = a->L;
     const int64_t P = B * L * L;
     const size_t LSZ = (size_t)P * C;
@@ -1113,8 +1296,8 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B) {
         __bf16* out = (l < NL - 1) ? a->hs + (size_t)(l + 1) * LSZ : nullptr;
         uint8_t* mk = (l < NL - 1) ? a->mask + (size_t)l * LSZ : nullptr;
         hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P)), dim3(256), 0, st, a->hs + (size_t)l * LSZ, W,
-                           a->bias + l * C, tp, L, P, mode, a->hs + (size_t)l * LSZ, (const float*)nullptr, out, mk,
-                           a->logit);
+                           bs.tab + l * C, bs.pt, bs.npts, tp, L, P, mode, a->hs + (size_t)l * LSZ,
+                           (const float*)nullptr, out, mk, a->logit);
     }
     hipLaunchKernelGGL(loss_kernel, dim3((unsigned)B), dim3(256), 0, st, a->logit, spins, L, 1.0f / (float)B, a->logq,
                        a->g, a->g32);
@@ -1137,6 +1320,10 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B) {
             dzl = a->dz;
         }
         hipLaunchKernelGGL(scatter_bias_kernel, dim3(1), dim3(256), 0, st, a->bpart, nbp, l, a->grad);
+        if (a->cond > 0)  // each sample's share, for the conditioning MLP
+            hipLaunchKernelGGL(sample_bias_grad_kernel, dim3((unsigned)B), dim3(256), 0, st, dh,
+                               a->mask + (size_t)(l < NL - 1 ? l : 0) * LSZ, l == NL - 1 ? a->g32 : nullptr, L * L,
+                               l, a->gs);
         hipLaunchKernelGGL(transpose_taps_kernel, dim3((unsigned)(Ppad / kTP)), dim3(256), 0, st,
                            a->hs + (size_t)l * LSZ, dzl, tp, L, P, Ppad, a->xt, a->dzt);
         hipLaunchKernelGGL(wgrad_kernel, dim3((unsigned)((nch + 3) / 4)), dim3(256), 0, st, a->xt, a->dzt, tp.n, Ppad,
@@ -1150,17 +1337,26 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B) {
         if (l > 0) {
             const __bf16* Wb = a->wb + (size_t)l * NT * C * C;
             const int mode = (l == NL - 1) ? EP_DGRAD : EP_DGRAD_RESID;
-            hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P)), dim3(256), 0, st, dzl, Wb, a->bias, tm, L, P, mode,
-                               (const __bf16*)nullptr, (const float*)dh, (__bf16*)nullptr, (uint8_t*)nullptr, dh_alt);
+            hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P)), dim3(256), 0, st, dzl, Wb, a->bias,
+                               (const int32_t*)nullptr, 1, tm, L, P, mode, (const __bf16*)nullptr, (const float*)dh,
+                               (__bf16*)nullptr, (uint8_t*)nullptr, dh_alt);
             std::swap(dh, dh_alt);
         }
+    }
+    if (a->cond > 0) {
+        hipLaunchKernelGGL(point_grad_kernel, dim3((unsigned)((a->npts * kCondOut + 255) / 256)), dim3(256), 0, st,
+                           a->gs, pt, B, a->npts, a->gp);
+        hipLaunchKernelGGL(cond_backward_kernel, dim3(1), dim3(kCondOut), 0, st, a->theta + a->np_base, a->feats,
+                           a->npts, a->gp, a->grad + a->np_base);
     }
     AR_TRY(hipGetLastError(), "training kernels");
     return CRBM_OK;
 }
 
 // ancestral sampling of n configurations (spins and their log q)
-int run_seq(crbm_ar_t* a, int64_t n, int8_t* spins, double* logq, uint64_t seed, uint32_t step, uint32_t id) {
+int run_seq(crbm_ar_t* a, int64_t n, int8_t* spins, double* logq, uint64_t seed, uint32_t step, uint32_t id,
+            const int32_t* pt) {
+    const BiasSel bs = bias_sel(a, pt);
     int rc = ensure_seq(a, n);
     if (rc != CRBM_OK) return rc;
     const int L = a->L;
@@ -1174,8 +1370,8 @@ int run_seq(crbm_ar_t* a, int64_t n, int8_t* spins, double* logq, uint64_t seed,
     AR_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&seq_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, kSeqLdsBytes),
            "sampler LDS size");
-    hipLaunchKernelGGL(seq_kernel, dim3((unsigned)((n + per_wg - 1) / per_wg)), dim3(64 * waves), kSeqLdsBytes, st, n, npad, L, a->wf, a->bias, a->ring, a->zpad, spins, a->slogit, seed,
-                       step, id);
+    hipLaunchKernelGGL(seq_kernel, dim3((unsigned)((n + per_wg - 1) / per_wg)), dim3(64 * waves), kSeqLdsBytes, st,
+                       n, npad, L, a->wf, bs.tab, bs.pt, bs.npts, a->ring, a->zpad, spins, a->slogit, seed, step, id);
     hipLaunchKernelGGL(logq_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->slogit, spins, n, L * L,
                        logq);
     AR_TRY(hipGetLastError(), "sampler kernels");
@@ -1200,7 +1396,8 @@ int ensure_infer(crbm_ar_t* a, int64_t n) {
 }
 
 // log q of n given configurations by one full forward pass over all sites
-int run_score(crbm_ar_t* a, int64_t n, const int8_t* spins, double* logq) {
+int run_score(crbm_ar_t* a, int64_t n, const int8_t* spins, double* logq, const int32_t* pt) {
+    const BiasSel bs = bias_sel(a, pt);
     int rc = ensure_infer(a, n);
     if (rc != CRBM_OK) return rc;
     const int L = a->L;
@@ -1211,8 +1408,8 @@ int run_score(crbm_ar_t* a, int64_t n, const int8_t* spins, double* logq) {
         AR_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&score_fused_kernel),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds),
                "scorer LDS size");
-        hipLaunchKernelGGL(score_fused_kernel, dim3((unsigned)n), dim3(256), lds, st, n, L, spins, a->wf, a->bias,
-                           a->ilogit);
+        hipLaunchKernelGGL(score_fused_kernel, dim3((unsigned)n), dim3(256), lds, st, n, L, spins, a->wf, bs.tab,
+                           bs.pt, bs.npts, a->ilogit);
         hipLaunchKernelGGL(logq_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->ilogit, spins, n,
                            L * L, logq);
         AR_TRY(hipGetLastError(), "scoring kernels");
@@ -1225,7 +1422,7 @@ int run_score(crbm_ar_t* a, int64_t n, const int8_t* spins, double* logq) {
     const int blocks = (int)std::min<int64_t>(4096, (tiles + 3) / 4);
     for (int l = 0; l < NL; ++l) {
         hipLaunchKernelGGL(conv16_kernel, dim3(blocks), dim3(256), 0, st, in, a->wf + (size_t)l * NT * C * C,
-                           a->bias + l * C, l, L, P, out, a->ilogit);
+                           bs.tab + l * C, bs.pt, bs.npts, l, L, P, out, a->ilogit);
         std::swap(in, out);
     }
     hipLaunchKernelGGL(logq_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->ilogit, spins, n, L * L,
@@ -1245,15 +1442,20 @@ int crbm_ar_create(const crbm_ar_config* c, crbm_ar_t** out) {
     *out = nullptr;
     if (c->L < 4 || c->L > CRBM_MAX_L || (c->L & 1)) return fail_ar(CRBM_EINVAL, "bad L");
     if (c->channels != C || c->layers != NL) return fail_ar(CRBM_EUNSUPPORTED, "kernels are built for 32 channels, 12 layers");
+    if (c->cond_points < 0 || c->cond_points > kCondMaxPoints) return fail_ar(CRBM_EINVAL, "cond_points must be 0..128");
     crbm_ar_s* a = new (std::nothrow) crbm_ar_s();
     if (!a) return fail_ar(CRBM_ENOMEM, "host allocation");
     a->L = c->L;
     a->seed = c->seed;
     a->stream = (hipStream_t)c->stream;
-    a->np = n_params();
+    a->cond = c->cond_points;
+    a->np_base = n_params();
+    a->np = a->np_base + (a->cond > 0 ? (int64_t)kCondF * kCondH + kCondH + (int64_t)kCondH * kCondOut : 0);
     if (alloc(&a->theta, a->np) || alloc(&a->grad, a->np) || alloc(&a->m, a->np) || alloc(&a->v, a->np) ||
         alloc(&a->bias, NL * C) || alloc(&a->wf, (int64_t)NL * NT * C * C) || alloc(&a->wb, (int64_t)NL * NT * C * C) ||
-        alloc(&a->dW, NT * C * C) || alloc(&a->zpad, C)) {
+        alloc(&a->dW, NT * C * C) || alloc(&a->zpad, C) ||
+        (a->cond > 0 && (alloc(&a->feats, (int64_t)a->cond * kCondF) || alloc(&a->cb, (int64_t)a->cond * kCondOut) ||
+                         alloc(&a->gp, (int64_t)a->cond * kCondOut)))) {
         delete a;
         return fail_ar(CRBM_ENOMEM, "parameter buffers");
     }
@@ -1272,6 +1474,23 @@ int crbm_ar_create(const crbm_ar_config* c, crbm_ar_t** out) {
     return CRBM_OK;
 }
 
+int crbm_ar_set_points(crbm_ar_t* a, int32_t n_points, const double* feats_host) {
+    if (!a || !feats_host) return fail_ar(CRBM_EINVAL, "NULL argument");
+    if (a->cond == 0) return fail_ar(CRBM_EINVAL, "the network is not conditional");
+    if (n_points < 1 || n_points > a->cond) return fail_ar(CRBM_EINVAL, "n_points must be 1..cond_points");
+    std::vector<float> f((size_t)n_points * kCondF);
+    for (size_t i = 0; i < f.size(); ++i) {
+        if (!std::isfinite(feats_host[i])) return fail_ar(CRBM_EINVAL, "features must be finite");
+        f[i] = (float)feats_host[i];
+    }
+    AR_TRY(hipMemcpyAsync(a->feats, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice, a->stream), "copy features");
+    a->npts = n_points;
+    int rc = pack(a);
+    if (rc != CRBM_OK) return rc;
+    AR_TRY(hipStreamSynchronize(a->stream), "synchronize");
+    return CRBM_OK;
+}
+
 int crbm_ar_set_params(crbm_ar_t* a, const float* host, int64_t n) {
     if (!a || !host || n != a->np) return fail_ar(CRBM_EINVAL, "parameter count mismatch");
     AR_TRY(hipMemcpyAsync(a->theta, host, sizeof(float) * n, hipMemcpyHostToDevice, a->stream), "copy params");
@@ -1287,7 +1506,9 @@ int crbm_ar_set_params(crbm_ar_t* a, const float* host, int64_t n) {
 int crbm_ar_init_params(crbm_ar_t* a, uint64_t seed, double scale) {
     if (!a || !(scale >= 0.0)) return fail_ar(CRBM_EINVAL, "bad arguments");
     // N(0, std^2) by SplitMix64 + Box-Muller; std = scale sqrt(2 / fan-in),
-    // times 0.1 for the logit layer; biases zero
+    // times 0.1 for the logit layer; biases zero.  Conditioning MLP: W1 with
+    // std sqrt(1 / features), b1 and W2 zero (a fresh conditional network is
+    // its unconditional part)
     std::vector<float> th((size_t)a->np, 0.f);
     uint64_t x = seed;
     auto next = [&]() {
@@ -1309,6 +1530,8 @@ int crbm_ar_init_params(crbm_ar_t* a, uint64_t seed, double scale) {
         for (int k = 0; k < T * ci * co; ++k) th[off + k] = (float)(sd * normal());
         off += (size_t)T * ci * co + co;
     }
+    if (a->cond > 0)
+        for (int k = 0; k < kCondF * kCondH; ++k) th[off + k] = (float)(std::sqrt(1.0 / kCondF) * normal());
     return crbm_ar_set_params(a, th.data(), a->np);
 }
 
@@ -1319,31 +1542,52 @@ int crbm_ar_get_params(crbm_ar_t* a, float* host, int64_t n) {
     return CRBM_OK;
 }
 
-int crbm_ar_grad(crbm_ar_t* a, const int8_t* samples_dev, int64_t batch, float* grad_host, double* loss_out) {
+static int need_points(const crbm_ar_t* a) {
+    if (a->cond > 0 && a->npts == 0) return fail_ar(CRBM_ESTATE, "conditional network: call crbm_ar_set_points first");
+    return CRBM_OK;
+}
+
+static int mean_loss(crbm_ar_t* a, int64_t batch, double* loss_out) {
+    std::vector<double> lq(batch);
+    AR_TRY(hipMemcpyAsync(lq.data(), a->logq, sizeof(double) * batch, hipMemcpyDeviceToHost, a->stream), "copy logq");
+    AR_TRY(hipStreamSynchronize(a->stream), "synchronize");
+    double s = 0.0;
+    for (double x : lq) s += x;
+    *loss_out = -s / (double)batch;
+    return CRBM_OK;
+}
+
+int crbm_ar_grad_cond(crbm_ar_t* a, const int8_t* samples_dev, const int32_t* points_dev, int64_t batch,
+                      float* grad_host, double* loss_out) {
     if (!a || !samples_dev || batch < 1) return fail_ar(CRBM_EINVAL, "bad arguments");
-    int rc = ensure_train(a, batch);
+    int rc = need_points(a);
     if (rc != CRBM_OK) return rc;
-    rc = grad_pass(a, samples_dev, batch);
+    rc = ensure_train(a, batch);
+    if (rc != CRBM_OK) return rc;
+    rc = grad_pass(a, samples_dev, batch, points_dev);
     if (rc != CRBM_OK) return rc;
     if (grad_host)
         AR_TRY(hipMemcpyAsync(grad_host, a->grad, sizeof(float) * a->np, hipMemcpyDeviceToHost, a->stream), "copy grad");
     if (loss_out) {
-        std::vector<double> lq(batch);
-        AR_TRY(hipMemcpyAsync(lq.data(), a->logq, sizeof(double) * batch, hipMemcpyDeviceToHost, a->stream), "copy logq");
-        AR_TRY(hipStreamSynchronize(a->stream), "synchronize");
-        double s = 0.0;
-        for (double x : lq) s += x;
-        *loss_out = -s / (double)batch;
+        rc = mean_loss(a, batch, loss_out);
+        if (rc != CRBM_OK) return rc;
     }
     AR_TRY(hipStreamSynchronize(a->stream), "synchronize");
     return CRBM_OK;
 }
 
-int crbm_ar_train_step(crbm_ar_t* a, const int8_t* samples_dev, int64_t batch, float lr, double* loss_out) {
+int crbm_ar_grad(crbm_ar_t* a, const int8_t* samples_dev, int64_t batch, float* grad_host, double* loss_out) {
+    return crbm_ar_grad_cond(a, samples_dev, nullptr, batch, grad_host, loss_out);
+}
+
+int crbm_ar_train_step_cond(crbm_ar_t* a, const int8_t* samples_dev, const int32_t* points_dev, int64_t batch,
+                            float lr, double* loss_out) {
     if (!a || !samples_dev || batch < 1 || !(lr > 0.f)) return fail_ar(CRBM_EINVAL, "bad arguments");
-    int rc = ensure_train(a, batch);
+    int rc = need_points(a);
     if (rc != CRBM_OK) return rc;
-    rc = grad_pass(a, samples_dev, batch);
+    rc = ensure_train(a, batch);
+    if (rc != CRBM_OK) return rc;
+    rc = grad_pass(a, samples_dev, batch, points_dev);
     if (rc != CRBM_OK) return rc;
     a->t_adam += 1;
     const float b1 = 0.9f, b2 = 0.999f;
@@ -1352,26 +1596,36 @@ int crbm_ar_train_step(crbm_ar_t* a, const int8_t* samples_dev, int64_t batch, f
                        a->m, a->v, a->np, lr, b1, b2, 1e-8f, c1, c2);
     rc = pack(a);
     if (rc != CRBM_OK) return rc;
-    if (loss_out) {
-        std::vector<double> lq(batch);
-        AR_TRY(hipMemcpyAsync(lq.data(), a->logq, sizeof(double) * batch, hipMemcpyDeviceToHost, a->stream), "copy logq");
-        AR_TRY(hipStreamSynchronize(a->stream), "synchronize");
-        double s = 0.0;
-        for (double x : lq) s += x;
-        *loss_out = -s / (double)batch;
-    }
+    if (loss_out) return mean_loss(a, batch, loss_out);
     return CRBM_OK;
 }
 
-int crbm_ar_logq(crbm_ar_t* a, const int8_t* spins_dev, int64_t n, double* logq_dev) {
+int crbm_ar_train_step(crbm_ar_t* a, const int8_t* samples_dev, int64_t batch, float lr, double* loss_out) {
+    return crbm_ar_train_step_cond(a, samples_dev, nullptr, batch, lr, loss_out);
+}
+
+int crbm_ar_logq_cond(crbm_ar_t* a, const int8_t* spins_dev, const int32_t* points_dev, int64_t n, double* logq_dev) {
     if (!a || !spins_dev || !logq_dev || n < 1) return fail_ar(CRBM_EINVAL, "bad arguments");
-    return run_score(a, n, spins_dev, logq_dev);
+    const int rc = need_points(a);
+    if (rc != CRBM_OK) return rc;
+    return run_score(a, n, spins_dev, logq_dev, points_dev);
+}
+
+int crbm_ar_logq(crbm_ar_t* a, const int8_t* spins_dev, int64_t n, double* logq_dev) {
+    return crbm_ar_logq_cond(a, spins_dev, nullptr, n, logq_dev);
+}
+
+int crbm_ar_sample_cond(crbm_ar_t* a, int64_t n, uint64_t seed, int64_t step, uint32_t id, const int32_t* points_dev,
+                        int8_t* spins_dev, double* logq_dev) {
+    if (!a || !spins_dev || !logq_dev || n < 1) return fail_ar(CRBM_EINVAL, "bad arguments");
+    const int rc = need_points(a);
+    if (rc != CRBM_OK) return rc;
+    return run_seq(a, n, spins_dev, logq_dev, seed, (uint32_t)step, id, points_dev);
 }
 
 int crbm_ar_sample(crbm_ar_t* a, int64_t n, uint64_t seed, int64_t step, uint32_t id, int8_t* spins_dev,
                    double* logq_dev) {
-    if (!a || !spins_dev || !logq_dev || n < 1) return fail_ar(CRBM_EINVAL, "bad arguments");
-    return run_seq(a, n, spins_dev, logq_dev, seed, (uint32_t)step, id);
+    return crbm_ar_sample_cond(a, n, seed, step, id, nullptr, spins_dev, logq_dev);
 }
 
 void crbm_ar_destroy(crbm_ar_t* a) {
@@ -1384,24 +1638,62 @@ int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_
                    int32_t* order_trace, int64_t* n_accepted) {
     if (!h || !a || n_cycles < 0 || gibbs_per_mh < 0) return fail_ar(CRBM_EINVAL, "bad arguments");
     HandleView v{};
-    if (handle_view(h, &v) != CRBM_OK) return fail_ar(CRBM_EINVAL, "bad handle");
-    if (v.n_inst != 1 || v.sched_kind != CRBM_SCHED_CONST)
-        return fail_ar(CRBM_EUNSUPPORTED, "MH needs a handle with one instance at a constant temperature");
+    if (handle_view(h, &v, 0) != CRBM_OK) return fail_ar(CRBM_EINVAL, "bad handle");
     if (v.L != a->L) return fail_ar(CRBM_EINVAL, "lattice size of the network and the handle differ");
     if (v.stream != a->stream) return fail_ar(CRBM_EINVAL, "handle and network must use the same stream");
-    const int64_t n = v.n_chains, N = (int64_t)v.L * v.L;
+    const int n_inst = v.n_inst;
+    if (a->cond > 0 && n_inst > a->npts)
+        return fail_ar(CRBM_EINVAL, "conditional network: instance i uses point i, set at least one point per instance");
+    // every instance: same L, constant temperature, its chains right after the previous instance's
+    const int64_t N = (int64_t)v.L * v.L, words = (int64_t)v.L * ((v.L + 31) / 32);
+    std::vector<MhTarget> tg((size_t)n_inst);
+    int64_t n = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        HandleView vi{};
+        if (handle_view(h, &vi, i) != CRBM_OK) return fail_ar(CRBM_EINVAL, "bad handle");
+        if (vi.L != v.L || vi.sched_kind != CRBM_SCHED_CONST)
+            return fail_ar(CRBM_EUNSUPPORTED, "MH needs instances of one lattice size, each at a constant temperature");
+        if (vi.state != v.state + n * words) return fail_ar(CRBM_EUNSUPPORTED, "instances are not contiguous");
+        tg[(size_t)i] = MhTarget{vi.a, vi.c1, vi.c2, vi.sg1, vi.sg2};
+        n += vi.n_chains;
+    }
     hipStream_t st = a->stream;
     if (n > a->mcap) {
-        void* ps[] = {a->cur, a->prop, a->ccur, a->cprop, a->lqc, a->lqp, a->nacc};
+        void* ps[] = {a->cur, a->prop, a->ccur, a->cprop, a->lqc, a->lqp, a->nacc, a->mh_ci};
         for (void* p : ps)
             if (p) (void)hipFree(p);
+        a->mh_ci = nullptr;
         if (alloc(&a->cur, n * N) || alloc(&a->prop, n * N) || alloc(&a->ccur, n * 3) || alloc(&a->cprop, n * 3) ||
-            alloc(&a->lqc, n) || alloc(&a->lqp, n) || alloc(&a->nacc, 1)) {
+            alloc(&a->lqc, n) || alloc(&a->lqp, n) || alloc(&a->nacc, 1) || alloc(&a->mh_ci, n)) {
             a->mcap = 0;
             return fail_ar(CRBM_ENOMEM, "MH buffers");
         }
         a->mcap = n;
     }
+    if (n_inst > a->mh_tgcap) {
+        if (a->mh_tg) (void)hipFree(a->mh_tg);
+        a->mh_tg = nullptr;
+        if (alloc(&a->mh_tg, n_inst)) {
+            a->mh_tgcap = 0;
+            return fail_ar(CRBM_ENOMEM, "MH targets");
+        }
+        a->mh_tgcap = n_inst;
+    }
+    {
+        std::vector<int32_t> ci((size_t)n);
+        int64_t c0 = 0;
+        for (int i = 0; i < n_inst; ++i) {
+            HandleView vi{};
+            (void)handle_view(h, &vi, i);
+            for (int64_t k = 0; k < vi.n_chains; ++k) ci[(size_t)(c0 + k)] = i;
+            c0 += vi.n_chains;
+        }
+        AR_TRY(hipMemcpyAsync(a->mh_ci, ci.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st), "copy chain map");
+        AR_TRY(hipMemcpyAsync(a->mh_tg, tg.data(), sizeof(MhTarget) * n_inst, hipMemcpyHostToDevice, st),
+               "copy targets");
+        AR_TRY(hipStreamSynchronize(st), "synchronize");  // the host vectors go out of scope
+    }
+    const int32_t* pts = a->cond > 0 ? a->mh_ci : nullptr;  // chain i of instance k is conditioned on point k
     AR_TRY(hipMemsetAsync(a->nacc, 0, sizeof(unsigned long long), st), "zero counter");
     const unsigned nb = (unsigned)((n + 255) / 256);
     for (int64_t cyc = 0; cyc < n_cycles; ++cyc) {
@@ -1413,20 +1705,19 @@ int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_
         // the current state changes only by MH itself when no Gibbs sweeps
         // are interleaved; then its counts and log q carry over
         if (cyc == 0 || gibbs_per_mh > 0) {
-            if (handle_view(h, &v) != CRBM_OK) return fail_ar(CRBM_EINVAL, "bad handle");
             AR_TRY(launch_unpack(v.state, a->cur, n, v.L, st), "unpack state");
             hipLaunchKernelGGL(counts_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->cur, n, v.L, a->ccur,
                                (int32_t*)nullptr);
-            rc = run_score(a, n, a->cur, a->lqc);
+            rc = run_score(a, n, a->cur, a->lqc, pts);
             if (rc != CRBM_OK) return rc;
         }
         const uint32_t step = (uint32_t)(a->mh_step++);
-        rc = run_seq(a, n, a->prop, a->lqp, v.seed, step, v.id);
+        rc = run_seq(a, n, a->prop, a->lqp, v.seed, step, v.id, pts);
         if (rc != CRBM_OK) return rc;
         hipLaunchKernelGGL(counts_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->prop, n, v.L, a->cprop,
                            (int32_t*)nullptr);
         hipLaunchKernelGGL(mh_kernel, dim3(nb), dim3(256), 0, st, n, v.L, a->cur, a->prop, a->ccur, a->cprop, a->lqc,
-                           a->lqp, v.a, v.c1, v.c2, v.sg1, v.sg2, v.seed, step, v.id, a->nacc);
+                           a->lqp, a->mh_tg, a->mh_ci, v.seed, step, v.id, a->nacc);
         AR_TRY(launch_pack(v.state, a->cur, n, v.L, st), "pack state");
         if (order_trace)  // recounts the current states (same counts) with the structure factor
             hipLaunchKernelGGL(counts_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->cur, n, v.L,

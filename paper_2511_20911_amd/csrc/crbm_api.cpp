@@ -239,10 +239,10 @@ int build_graph(crbm_s* h) {
 
 }  // namespace
 
-int crbmlib::handle_view(crbm_t* h, HandleView* v) {
-    if (!h || !v) return CRBM_EINVAL;
-    const crbm_instance& I = h->inst[0];
-    v->state = h->d_state + h->state_off[0];
+int crbmlib::handle_view(crbm_t* h, HandleView* v, int i) {
+    if (!h || !v || i < 0 || i >= (int)h->inst.size()) return CRBM_EINVAL;
+    const crbm_instance& I = h->inst[(size_t)i];
+    v->state = h->d_state + h->state_off[(size_t)i];
     v->L = I.L;
     v->n_chains = I.n_chains;
     v->id = I.id;
@@ -254,9 +254,9 @@ int crbmlib::handle_view(crbm_t* h, HandleView* v) {
     v->S = h->S;
     v->stream = h->stream;
     int64_t wq1, wq2;
-    hidden_weight(h->Jq[0][0], I.T0, &wq1, &v->sg1);
-    hidden_weight(h->Jq[1][0], I.T0, &wq2, &v->sg2);
-    v->a = (double)llround((double)h->Jq[2][0] / I.T0) / 65536.0;
+    hidden_weight(h->Jq[0][(size_t)i], I.T0, &wq1, &v->sg1);
+    hidden_weight(h->Jq[1][(size_t)i], I.T0, &wq2, &v->sg2);
+    v->a = (double)llround((double)h->Jq[2][(size_t)i] / I.T0) / 65536.0;
     v->c1 = log(cosh(2.0 * (double)wq1 / 65536.0));
     v->c2 = log(cosh(2.0 * (double)wq2 / 65536.0));
     return CRBM_OK;

@@ -53,7 +53,7 @@ struct GibbsArgs {
 
 // What the learned-proposal code needs from a Gibbs handle.
 struct HandleView {
-    uint32_t* state;   // bit rows of the handle's first instance
+    uint32_t* state;   // bit rows of the instance
     int L;
     int64_t n_chains;
     uint32_t id;
@@ -67,7 +67,8 @@ struct HandleView {
     double a, c1, c2;
     int sg1, sg2;
 };
-int handle_view(crbm_t* h, HandleView* v);
+// the view of instance i (0 <= i < number of instances)
+int handle_view(crbm_t* h, HandleView* v, int i);
 
 // Records the message returned by crbm_last_error() on this thread; returns code.
 int set_error(int code, const char* msg);
