@@ -218,6 +218,45 @@ def learned_mh(crbm, torch, temps=(0.4, 0.2, 0.1), steps=800, cycles=500):
     return out
 
 
+def learned_points(crbm, torch, L=48, steps=400, cycles=60, chains=512):
+    """Conditional learned MH vs plain Gibbs over the 64 scale points at LxL
+    (points near the T = 0 phase boundaries, 512 chains each, all in one
+    handle): one 12-layer 32-channel network conditioned on (J2/J1, h/4, ln T)
+    through per-layer bias offsets, trained on Gibbs samples of all points,
+    then 1 MH : 10 Gibbs sweeps against plain Gibbs for the same wall time."""
+    import numpy as np
+    from paper_2511_20911_amd import learned, workloads
+    pts = [(p.J2, p.h, p.T0) for p in workloads.scale_points(L)]
+    t0 = time.perf_counter()
+    data, pidx = learned.training_set_points(pts, L, chains, anneal_sweeps=2000, snapshots=16, spacing=50)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = crbm.ARNet(L, seed=5, cond_points=len(pts))
+    net.set_points(np.array([learned.features(*p) for p in pts]))
+    net.init_params(seed=5, scale=0.5)
+    t0 = time.perf_counter()
+    loss = learned.train_points(net, data, pidx, steps=steps, batch=256)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    n_train = int(data.shape[0])
+    del data, pidx
+    torch.cuda.empty_cache()
+    r = learned.compare_points(net, pts, L, chains, cycles=cycles, gibbs_per_mh=10, trace_every=10)
+    del net
+    torch.cuda.empty_cache()
+    r.update({"workload": f"SS Ising {L}x{L}, the 64 scale points (4 phase-boundary lines, T ~ logU[0.1, 1]), "
+                          f"{chains} chains each in one handle; conditional proposal: 12 masked 3x3 conv layers, "
+                          "32 channels, bias offsets from a 3-32-384 tanh MLP of (J2/J1, h/4, ln T); trained on "
+                          f"{n_train} Gibbs samples (anneal 5->T over 2000 sweeps, 16 snapshots 50 sweeps apart, "
+                          "translation and transpose augmentation), "
+                          f"{steps} Adam steps of batch 256; 1 MH : 10 Gibbs vs plain Gibbs at equal wall time, "
+                          "seeded +-1 start, first 20% discarded",
+              "ess": "sum over points of chains x kept samples / max(tau_E, tau_m)",
+              "data_s": t_data, "train_s": t_train, "train_steps": steps, "final_loss_per_site": loss,
+              "ess_min_ratio": r["learned"]["ess_min_per_s"] / r["gibbs"]["ess_min_per_s"]})
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +272,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch graph measurement")
     ap.add_argument("--no-mh", action="store_true", help="skip the learned-MH vs Gibbs ESS comparison")
     ap.add_argument("--no-scale", action="store_true", help="skip the 48x48 / 96x96 Gibbs measurement")
+    ap.add_argument("--no-c5-mh", action="store_true", help="skip the conditional learned-MH comparison at 48x48")
+    ap.add_argument("--c5-mh-96", action="store_true", help="also run the conditional learned-MH comparison at 96x96")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the sampler's chains are independent and this build runs on a "
@@ -338,6 +379,10 @@ def main():
         result["scale"] = scale_gibbs(crbm, torch)
     if not args.no_mh:
         result["learned_mh"] = learned_mh(crbm, torch)
+    if not args.no_c5_mh:
+        result["learned_mh_points"] = {"48": learned_points(crbm, torch, 48)}
+        if args.c5_mh_96:
+            result["learned_mh_points"]["96"] = learned_points(crbm, torch, 96, steps=200, cycles=20)
     if not args.no_cpu_baseline and n_sweeps == S:
         base, finals = cpu_baseline()
         result["cpu_baseline"] = base

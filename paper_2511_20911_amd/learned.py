@@ -20,6 +20,12 @@ and moves data between device tensors:
   O_1/3 = max |S(q*)|^2 / N^2 (q* = (pi, 2pi/3), (2pi/3, pi); Sec. III.B) from
   the library's estimator.
 
+Many points at once (the phase-boundary workloads): one conditional network
+(bias offsets from an MLP of each point's features) serves every point of a
+multi-instance handle: training_set_points, train_points and compare_points
+mirror the single-point functions, with per-point energies, tau_int of E and
+m, ESS and the 3-SE agreement of the two samplers.
+
 The paper samples its CRBM by Gibbs only (Sec. II.B); the learned proposal is
 an addition that leaves the stationary law unchanged (exact MH acceptance on
 integer bond counts).
@@ -162,4 +168,125 @@ def compare(net: ARNet, L, J1, J2, h, T, n_chains=8192, cycles=500, gibbs_per_mh
         "gibbs": {"sweeps": sweeps, "trace_every": trace_every, "us_per_sweep": 1e6 * per_sweep,
                   **gibbs.__dict__, "ess_per_s": gibbs.ess / t_g, "ess_min_per_s": gibbs.ess_min / t_g,
                   "tau_unit": f"{trace_every} sweeps"},
+    }
+
+
+# ---------------------------------------------------------------- many points, one conditional network
+
+def features(J2, h, T):
+    """Conditioning features of a point (J1 = 1): (J2/J1, h/(4 J1), ln T)."""
+    return (float(J2), float(h) / 4.0, math.log(float(T)))
+
+
+def training_set_points(points, L, chains, anneal_sweeps=4000, snapshots=32, spacing=50, seed=91, T_start=5.0,
+                        id0=200):
+    """Gibbs samples at every point (J2, h, T): one handle anneals all points
+    geometrically from T_start to their own T, then `snapshots` states of
+    every chain spaced by `spacing` sweeps at that T.  Returns (spins int8
+    CUDA [snapshots * len(points) * chains, L, L], point index int32 CUDA
+    [same])."""
+    import torch
+    N = L * L
+    ann = Sampler([Instance(L=L, J1=1.0, J2=J2, h=h, n_chains=chains, sched="geometric", T0=T_start, T1=T,
+                            id=id0 + k) for k, (J2, h, T) in enumerate(points)], seed=seed, n_sweeps=anneal_sweeps)
+    ann.sample(anneal_sweeps)
+    st, _ = ann.get_state()
+    fixed = Sampler([Instance(L=L, J1=1.0, J2=J2, h=h, n_chains=chains, sched="const", T0=T, id=id0 + k)
+                     for k, (J2, h, T) in enumerate(points)], seed=seed + 1, n_sweeps=snapshots * spacing)
+    fixed.set_state(st, 0)
+    total = len(points) * chains
+    out = torch.empty((snapshots, total * N), dtype=torch.int8, device="cuda")
+    for k in range(snapshots):
+        fixed.sample(spacing, spins_out=out[k])
+    pts = torch.arange(len(points), dtype=torch.int32, device="cuda").repeat_interleave(chains).repeat(snapshots)
+    return out.view(-1, L, L), pts
+
+
+def train_points(net: ARNet, data, pts, steps=600, batch=512, lr=1e-3, lr_late=3e-4, late_from=0.625, seed=1):
+    """Maximum-likelihood training of a conditional network on random
+    augmented mini-batches that mix the points.  Returns the last per-site loss."""
+    import torch
+    gen = torch.Generator()
+    gen.manual_seed(seed)
+    gidx = torch.Generator(device="cuda")
+    gidx.manual_seed(seed + 1)
+    N = data.shape[1] * data.shape[2]
+    loss = float("nan")
+    for it in range(steps):
+        idx = torch.randint(0, data.shape[0], (batch,), device="cuda", generator=gidx)
+        loss = net.train_step(augment(data[idx], gen), lr if it < late_from * steps else lr_late,
+                              points=pts[idx].contiguous())
+    return loss / N
+
+
+def _point_stats(trace, c0, c1, weights, N, discard, max_lag):
+    """<E>/N, its SE over chains, tau_int of E and of m, for chains [c0, c1)."""
+    t = trace[discard:, c0:c1].double()
+    E = (weights[0] * t[..., 0] + weights[1] * t[..., 1] + weights[2] * t[..., 2]) / 65536.0 / N
+    cm = E.mean(0)
+    tau_e = tau_int(trace, weights, c0=c0, c1=c1, discard=discard, max_lag=max_lag)[0]
+    tau_m = tau_int(trace, (1, 0, 0), c0=c0, c1=c1, discard=discard, max_lag=max_lag)[0]
+    return float(cm.mean()), float(cm.std() / math.sqrt(cm.numel())), tau_e, tau_m
+
+
+def compare_points(net: ARNet, points, L, chains, cycles=100, gibbs_per_mh=10, trace_every=10, seed=321, id0=400):
+    """Learned MH (cycles of gibbs_per_mh Gibbs sweeps + one MH step, each
+    point's chains proposing at that point) against plain Gibbs run for the
+    same wall time, both from the same seeded start over all points in one
+    handle; the first fifth of each run is discarded.  Per point: <E>/N with
+    SE, tau_int of E and m, ESS = chains x kept / max(tau_E, tau_m); totals
+    over points; and whether the two samplers agree within 3 combined SE."""
+    import torch
+    N = L * L
+    insts = [Instance(L=L, J1=1.0, J2=J2, h=h, n_chains=chains, sched="const", T0=T, id=id0 + k)
+             for k, (J2, h, T) in enumerate(points)]
+    n = chains * len(points)
+    mh = Sampler(insts, seed=seed, n_sweeps=max(1, cycles * gibbs_per_mh))
+    tr = torch.empty((cycles, n, 3), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    acc = sample_mh(mh, net, cycles, gibbs_per_mh, trace=tr)
+    torch.cuda.synchronize()
+    t_mh = time.perf_counter() - t0
+    del mh
+    probe = Sampler(insts, seed=seed, n_sweeps=60)
+    probe.sample(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    probe.sample(50)
+    torch.cuda.synchronize()
+    per_sweep = (time.perf_counter() - t0) / 50
+    del probe
+    n_s = max(10, int(t_mh / per_sweep) // trace_every)
+    sweeps = n_s * trace_every
+    gb = Sampler(insts, seed=seed, n_sweeps=sweeps)
+    trg = torch.empty((n_s, n, 3), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gb.sample(sweeps, trace=trg, trace_every=trace_every)
+    torch.cuda.synchronize()
+    t_g = time.perf_counter() - t0
+    rows, ess_l, ess_g, agree = [], 0.0, 0.0, 0
+    for k, (J2, h, T) in enumerate(points):
+        w = energy_weights(1.0, J2, h)
+        c0, c1 = k * chains, (k + 1) * chains
+        El, sel, tel, tml = _point_stats(tr, c0, c1, w, N, cycles // 5, cycles // 2)
+        Eg, seg, teg, tmg = _point_stats(trg, c0, c1, w, N, n_s // 5, n_s // 2)
+        el = chains * (cycles - cycles // 5) / max(tel, tml)
+        eg = chains * (n_s - n_s // 5) / max(teg, tmg)
+        ess_l += el
+        ess_g += eg
+        ok = abs(El - Eg) <= 3.0 * math.sqrt(sel * sel + seg * seg) + 1e-12
+        agree += ok
+        rows.append({"J2": J2, "h": h, "T": T, "E_learned": El, "se_learned": sel, "tau_E_learned": tel,
+                     "tau_m_learned": tml, "E_gibbs": Eg, "se_gibbs": seg, "tau_E_gibbs": teg, "tau_m_gibbs": tmg,
+                     "agree_3se": bool(ok)})
+    return {
+        "learned": {"cycles": cycles, "gibbs_per_mh": gibbs_per_mh, "acceptance": acc / (cycles * n),
+                    "ms_per_cycle": 1e3 * t_mh / cycles, "seconds": t_mh, "ess_min_per_s": ess_l / t_mh,
+                    "tau_unit": "MH cycles"},
+        "gibbs": {"sweeps": sweeps, "trace_every": trace_every, "us_per_sweep": 1e6 * per_sweep, "seconds": t_g,
+                  "ess_min_per_s": ess_g / t_g, "tau_unit": f"{trace_every} sweeps"},
+        "points_agreeing_within_3se": agree,
+        "points": rows,
     }
