@@ -276,8 +276,8 @@ def main():
     ap.add_argument("--c5-mh-96", action="store_true", help="also run the conditional learned-MH comparison at 96x96")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the sampler's chains are independent and this build runs on a "
-              "single MI355X; multi-GPU runs are not part of it.", file=sys.stderr)
+        print("bench.py measures one GPU only (--gpus 1): chains are independent, and sharding them over "
+              "several GPUs is a design, not an implemented path.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -75,3 +75,14 @@ def test_table_errors():
     with pytest.raises(crbm.CrbmError) as e:
         crbm.table_for(1.0, 0.5, 0.0, 1e-6)  # weights beyond int32 in 16.16
     assert e.value.code == crbm.CRBM_ERANGE
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N > 1 exits with a message instead of measuring."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
