@@ -407,9 +407,6 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
         for (int w = 0; w < W; ++w) Q[NR][w] = 0u;
     }
     const uint32_t c3h = (it.id << 3) | 1u, c3v = (it.id << 3) | 3u;
-    int64_t acc[11];
-#pragma unroll
-    for (int x = 0; x < 11; ++x) acc[x] = 0;
 
     for (int64_t s = a.s0; s < a.s1; ++s) {
         const uint32_t* tb = a.tables + it.tab_off + (uint64_t)it.tab_stride * (uint64_t)s;
@@ -558,12 +555,13 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
                     od[2] = (int32_t)sb;
                 }
             }
-            if (meas) {
-                acc[0] += 1;
-                acc[1] += M; acc[2] += B1; acc[3] += B2;
-                acc[4] += M * M; acc[5] += B1 * B1; acc[6] += B2 * B2;
-                acc[7] += M * B1; acc[8] += M * B2; acc[9] += B1 * B2;
-                acc[10] += M < 0 ? -M : M;
+            if (meas && g == 0 && active) {  // the chain's accumulators live in memory: no registers held
+                int64_t* ac = a.acc + gch * 11;
+                ac[0] += 1;
+                ac[1] += M; ac[2] += B1; ac[3] += B2;
+                ac[4] += M * M; ac[5] += B1 * B1; ac[6] += B2 * B2;
+                ac[7] += M * B1; ac[8] += M * B2; ac[9] += B1 * B2;
+                ac[10] += M < 0 ? -M : M;
             }
         }
     }
@@ -574,11 +572,6 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
         for (int x = 0; x < NR; ++x)
 #pragma unroll
             for (int w = 0; w < W; ++w) st[x * W + w] = Q[x][w];
-    }
-    if (g == 0 && a.measure_every > 0) {
-        int64_t* ac = a.acc + gch * 11;
-#pragma unroll
-        for (int x = 0; x < 11; ++x) ac[x] += acc[x];
     }
     if (a.spins_out) {
         int8_t* out = a.spins_out + it.spin_off + ((uint64_t)cl * L + (uint64_t)g * NR) * L;
@@ -591,8 +584,12 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
 // (a.queue != nullptr): each wavefront pops items from a device counter until
 // the list is exhausted, so a grid sized to the machine drains any number of
 // items and concurrent kernels share the CUs as their queues empty.
+// Rows of three words (L > 64) would otherwise take more than 256 registers
+// per lane and one wavefront per SIMD; asking for two trades a few spilled
+// values for the latency hiding of a second wavefront (measured: 96x96 runs
+// 1.6x faster, 72x72 1.5x).
 template <int L, int R>
-__global__ void __launch_bounds__(256) gibbs_kernel(GibbsArgs a) {
+__global__ void __launch_bounds__(256, (Geo<L>::W >= 3 ? 2 : 1)) gibbs_kernel(GibbsArgs a) {
     const int lane = threadIdx.x & 63;
     if (a.queue == nullptr) {
         const int wv = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
