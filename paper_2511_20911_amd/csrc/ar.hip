@@ -828,7 +828,7 @@ __global__ void __launch_bounds__(256) score_fused_kernel(int64_t n, int L, cons
 // the last layer; the logits go to logit_out for the log q sum.
 constexpr int kSeqMaxWaves = 4;
 constexpr int kSeqPad = 16 * kSeqMaxWaves;  // the ring's chain count is a multiple of this
-constexpr int kSeqLdsBytes = NL * NT * C * C * 2;
+constexpr int kSeqLdsBytes = NL * NT * C * C * 2 + NL * C * 4;  // weights, then the shared biases
 
 // keeps the compiler from moving this wavefront's memory accesses across it
 // (its memory operations complete in order, so no instruction is needed)
@@ -838,8 +838,11 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// bias_tab: the bias table (rows kCondOut apart); chain i reads row
-// pt[i] (clamped to [0, npts)), or row 0 if pt is nullptr
+// bias_tab: the bias table (rows kCondOut apart).  PER_CHAIN: chain i reads
+// row pt[i] (clamped to [0, npts)) from global memory; else every chain reads
+// row 0, staged in LDS with the weights (a global read in each layer's
+// dependency chain would add its latency to every layer step).
+template <bool PER_CHAIN>
 __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L, const __bf16* __restrict__ wf,
                                                   const float* __restrict__ bias_tab, const int32_t* __restrict__ pt,
                                                   int npts, __bf16* __restrict__ ring,
@@ -850,10 +853,13 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
     __bf16* wl = reinterpret_cast<__bf16*>(smem);                 // [NL][NT][C][C], rows swizzled
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int r16 = lane & 15, kg = lane >> 4;
+    float* bsh = reinterpret_cast<float*>(wl + NL * NT * C * C);  // [NL][C] shared biases (not PER_CHAIN)
     for (int g = tid; g < NL * NT * C * 4; g += blockDim.x) {
         const int row = g >> 2, grp = g & 3;
         *reinterpret_cast<bf16x8*>(wl + swz(row, grp)) = load8(wf + (int64_t)row * C + grp * 8);
     }
+    if (!PER_CHAIN)
+        for (int g = tid; g < NL * C; g += blockDim.x) bsh[g] = bias_tab[g];
     __syncthreads();
     // wavefront-uniform by construction; readfirstlane lets the compiler keep it (and the ring base) scalar
     const int64_t wbase = (int64_t)blockIdx.x * (blockDim.x >> 2) + 16 * __builtin_amdgcn_readfirstlane(w);
@@ -864,7 +870,8 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
     const int64_t gca = wbase + r16;  // the ring has npad >= grid size chains: padding rows have their own slots
     const int N = L * L;
     // this lane's chain's bias rows (padding chains read the last chain's)
-    const float* bl = bias_tab + (pt ? (int64_t)clamp_point(pt[gca < n ? gca : n - 1], npts) * kCondOut : 0);
+    const float* bl =
+        PER_CHAIN ? bias_tab + (int64_t)clamp_point(pt[gca < n ? gca : n - 1], npts) * kCondOut : bsh;
     // Ring element (layer, chain, column, channel): [NL][npad][L][C], one row
     // per chain and layer.  Site (r, c) writes column c after the row above's
     // column c was last read (as the (-1,+1) tap of site (r, c - 1)), so the
@@ -916,10 +923,11 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
         const int r = site / L, c = site - r * L;
         const int sn = site + 1, rn = sn / L, cn = sn - rn * L;
         const bool more = sn < N;
-        // an empty statement that marks the bias row pointer as modified: the
-        // bias loads stay in the loop (vector-memory reads that hit the cache)
-        // instead of being hoisted into registers that every layer must copy
-        asm volatile("" : "+v"(bl));
+        // PER_CHAIN: an empty statement that marks the bias row pointer as
+        // modified, so the bias loads stay in the loop (vector-memory reads
+        // that hit the cache) instead of being hoisted into registers that
+        // every layer must copy
+        if (PER_CHAIN) asm volatile("" : "+v"(bl));
         if (c == 0) {
 #pragma unroll
             for (int l = 0; l < NL; ++l) left[l] = zero8();
@@ -1102,26 +1110,29 @@ __global__ void scatter_grad_kernel(const float* dW, int l, float* grad) {
     grad[off + x] = dW[((int64_t)t * C + i) * C + o];
 }
 
-// bias gradient of layer l: sum of nparts partial sums per output channel;
-// 256 threads = 8 slices x 32 channels, slices reduced in LDS
+// bias gradient of layer l: the sum of nparts partial sums, one workgroup
+// per output channel; 256 threads each add a strided share of the partials,
+// then a fixed-order tree in LDS (fp64)
 __global__ void __launch_bounds__(256) scatter_bias_kernel(const float* part, int nparts, int l, float* grad) {
-    const int j = threadIdx.x & 31, slice = threadIdx.x >> 5;
+    const int j = blockIdx.x;
     const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
     const int stride = (co == 1) ? 1 : C;
     double s = 0.0;
-    if (j < co)
-        for (int p = slice; p < nparts; p += 8) s += part[(int64_t)p * stride + j];
+    for (int p = threadIdx.x; p < nparts; p += blockDim.x) s += part[(int64_t)p * stride + j];
     __shared__ double red[256];
     red[threadIdx.x] = s;
     __syncthreads();
-    if (slice == 0 && j < co) {
-        for (int k = 1; k < 8; ++k) s += red[k * 32 + j];
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
         int64_t off = 0;
         for (int k = 0; k < l; ++k) {
             const int Tk = (k == 0) ? 4 : 5, cik = (k == 0) ? 1 : C, cok = (k == NL - 1) ? 1 : C;
             off += (int64_t)Tk * cik * cok + cok;
         }
-        grad[off + (int64_t)T * ci * co + j] = (float)s;
+        grad[off + (int64_t)T * ci * co + j] = (float)red[0];
     }
 }
 
@@ -1319,7 +1330,8 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
                                a->bpart);
             dzl = a->dz;
         }
-        hipLaunchKernelGGL(scatter_bias_kernel, dim3(1), dim3(256), 0, st, a->bpart, nbp, l, a->grad);
+        hipLaunchKernelGGL(scatter_bias_kernel, dim3(l == NL - 1 ? 1 : C), dim3(256), 0, st, a->bpart, nbp, l,
+                           a->grad);
         if (a->cond > 0)  // each sample's share, for the conditioning MLP
             hipLaunchKernelGGL(sample_bias_grad_kernel, dim3((unsigned)B), dim3(256), 0, st, dh,
                                a->mask + (size_t)(l < NL - 1 ? l : 0) * LSZ, l == NL - 1 ? a->g32 : nullptr, L * L,
@@ -1367,11 +1379,20 @@ int run_seq(crbm_ar_t* a, int64_t n, int8_t* spins, double* logq, uint64_t seed,
     // one wavefront per 16 chains; as many per workgroup as keep one workgroup per compute unit busy
     const int waves = n <= 16 * 256 ? 1 : n <= 32 * 256 ? 2 : kSeqMaxWaves;
     const int per_wg = 16 * waves;
-    AR_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&seq_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, kSeqLdsBytes),
-           "sampler LDS size");
-    hipLaunchKernelGGL(seq_kernel, dim3((unsigned)((n + per_wg - 1) / per_wg)), dim3(64 * waves), kSeqLdsBytes, st,
-                       n, npad, L, a->wf, bs.tab, bs.pt, bs.npts, a->ring, a->zpad, spins, a->slogit, seed, step, id);
+    const dim3 grid((unsigned)((n + per_wg - 1) / per_wg)), block(64 * waves);
+    if (bs.pt) {
+        AR_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&seq_kernel<true>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, kSeqLdsBytes),
+               "sampler LDS size");
+        hipLaunchKernelGGL(seq_kernel<true>, grid, block, kSeqLdsBytes, st, n, npad, L, a->wf, bs.tab, bs.pt,
+                           bs.npts, a->ring, a->zpad, spins, a->slogit, seed, step, id);
+    } else {
+        AR_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&seq_kernel<false>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, kSeqLdsBytes),
+               "sampler LDS size");
+        hipLaunchKernelGGL(seq_kernel<false>, grid, block, kSeqLdsBytes, st, n, npad, L, a->wf, bs.tab, bs.pt,
+                           bs.npts, a->ring, a->zpad, spins, a->slogit, seed, step, id);
+    }
     hipLaunchKernelGGL(logq_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->slogit, spins, n, L * L,
                        logq);
     AR_TRY(hipGetLastError(), "sampler kernels");
