@@ -218,3 +218,52 @@ def test_unconditional_mh_on_two_instances():
         assert abs(vals.mean() - ex["E"]) < 4 * se, (k, vals.mean(), ex["E"], se)
     # the two laws are far apart on this scale: a shared target would fail one of them
     assert abs(exs[0] - exs[1]) > 8 * max(ses), (exs, ses)
+
+
+# ---------------------------------------------------------------- error paths (host-side checks, no kernel fault)
+
+def _code(fn):
+    try:
+        fn()
+    except crbm.CrbmError as e:
+        return e.code
+    return crbm.CRBM_OK
+
+
+def test_conditional_errors():
+    assert _code(lambda: crbm.ARNet(6, cond_points=129)) == crbm.CRBM_EINVAL
+    assert _code(lambda: crbm.ARNet(6, cond_points=-1)) == crbm.CRBM_EINVAL
+    net = crbm.ARNet(6, cond_points=2)
+    s = torch.from_numpy(_spins(4, 6, 1)).cuda()
+    # no points yet: every conditional computation refuses
+    assert _code(lambda: net.logq(s)) == crbm.CRBM_ESTATE
+    assert _code(lambda: net.sample(4, seed=1)) == crbm.CRBM_ESTATE
+    assert _code(lambda: net.train_step(s, 1e-3)) == crbm.CRBM_ESTATE
+    assert _code(lambda: net.set_points(np.zeros((3, 3)))) == crbm.CRBM_EINVAL       # more than cond_points
+    assert _code(lambda: net.set_points(np.array([[0.0, np.nan, 1.0]]))) == crbm.CRBM_EINVAL
+    plain = crbm.ARNet(6)
+    assert _code(lambda: plain.set_points(np.zeros((1, 3)))) == crbm.CRBM_EINVAL     # not conditional
+    net.set_points(FEATS[:2])
+    assert _code(lambda: net.logq(s)) == crbm.CRBM_OK
+    # out-of-range point indices are clamped, not read out of bounds
+    a = net.logq(s, points=_pts([5, -3, 1, 0]))
+    b = net.logq(s, points=_pts([1, 0, 1, 0]))
+    assert torch.equal(a, b)
+
+
+def test_mh_handle_checks():
+    L = 4
+    net = crbm.ARNet(L, cond_points=2)
+    net.set_points(FEATS[:1])  # one point, two instances below
+    two = crbm.Sampler([crbm.Instance(L=L, J2=1.0, h=3.0, n_chains=8, T0=1.0, id=k) for k in range(2)], seed=1,
+                       n_sweeps=10)
+    assert _code(lambda: crbm.sample_mh(two, net, 1, 0)) == crbm.CRBM_EINVAL
+    plain = crbm.ARNet(L)
+    mixed = crbm.Sampler([crbm.Instance(L=L, n_chains=8, T0=1.0, id=0), crbm.Instance(L=6, n_chains=8, T0=1.0, id=1)],
+                         seed=1, n_sweeps=10)
+    assert _code(lambda: crbm.sample_mh(mixed, plain, 1, 0)) == crbm.CRBM_EUNSUPPORTED
+    anneal = crbm.Sampler([crbm.Instance(L=L, n_chains=8, sched="linear", T0=2.0, T1=1.0, id=0)], seed=1, n_sweeps=10)
+    assert _code(lambda: crbm.sample_mh(anneal, plain, 1, 0)) == crbm.CRBM_EUNSUPPORTED
+    other_L = crbm.ARNet(6)
+    single = crbm.Sampler([crbm.Instance(L=L, n_chains=8, T0=1.0, id=0)], seed=1, n_sweeps=10)
+    assert _code(lambda: crbm.sample_mh(single, other_L, 1, 0)) == crbm.CRBM_EINVAL
