@@ -31,7 +31,7 @@ SEED = 0x5EED000000000002
 J2S = (0.5, 1.0, 1.5, 2.0)
 HS = tuple(3.0 * j / 15 for j in range(16))
 
-# Algorithmic integer work per visible spin and sweep (documented in the design doc):
+# Algorithmic integer work per visible spin and sweep:
 # 3.5 stochastic units (1 spin + 2.5 hidden), each needing a 16-bit Philox
 # slot (1/8 of a Philox4x32-10 block = 10 rounds x (2 mul-hi/lo + 2 xor3) = 40
 # ops) and one integer compare.

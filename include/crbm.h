@@ -45,7 +45,7 @@ enum {
     CRBM_ERANGE = -2,      /* a fixed-point weight or bias does not fit in int32 */
     CRBM_ENOMEM = -3,      /* device or host allocation failed */
     CRBM_EHIP = -4,        /* a HIP runtime call failed */
-    CRBM_EUNSUPPORTED = -5,/* valid request this build does not implement (open boundaries, an L without a compiled kernel) */
+    CRBM_EUNSUPPORTED = -5,/* valid request this library does not implement (open boundaries, an L without a compiled kernel) */
     CRBM_ESTATE = -6       /* misuse of a handle (e.g. sampling past the end of the schedule) */
 };
 
@@ -56,7 +56,7 @@ enum {
     CRBM_SCHED_EXPLICIT = 3   /* T_s = T_explicit[s] */
 };
 
-#define CRBM_MAX_L 96      /* largest lattice side supported by this build */
+#define CRBM_MAX_L 96      /* largest lattice side supported by this library */
 #define CRBM_N_ACC 11      /* per-chain accumulator words, see crbm_obs */
 
 /* One Hamiltonian point (one "instance").  Host memory, copied at create. */
