@@ -55,7 +55,9 @@ __device__ __forceinline__ P4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
     uint64_t p0 = (uint64_t)kM0 * c0;
     uint64_t p1 = (uint64_t)kM1 * c2;
     uint32_t x0 = (uint32_t)(p1 >> 32) ^ (c1 ^ k0);
-    uint32_t x2 = (uint32_t)(p0 >> 32) ^ (c3 ^ k1);
+    // one VALU op with the uniform c3 ^ k1 as its scalar operand (an ordinary
+    // xor chain is reassociated into two vector xors)
+    uint32_t x2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3 ^ k1, 0u, 0xF0 ^ 0xCC);
     uint32_t x1 = (uint32_t)p1, x3 = (uint32_t)p0;
 #pragma unroll
     for (int r = 1; r < 10; ++r) {
@@ -173,34 +175,50 @@ __host__ __device__ constexpr uint32_t bits_between(int lo, int hi) {
     return (hi <= lo) ? 0u : ((hi - lo == 32) ? 0xffffffffu : (((1u << (hi - lo)) - 1u) << lo));
 }
 
+// Truth tables of the three-input bit operation, written as functions of the
+// operand patterns a = 0xF0, b = 0xCC, c = 0xAA.
+constexpr int kLutAndNotAnd = 0xF0 & ~0xCC & 0xAA;      // a & ~b & c
+constexpr int kLutKeepEqual = 0xF0 & ~(0xCC ^ 0xAA) & 0xFF;  // a & ~(b ^ c)
+
+// All ones where bit (31 - b) of the wavefront-uniform word x is set.
+__device__ __forceinline__ uint32_t plane_mask(uint32_t x, int b) {
+    return (uint32_t)((int32_t)(x << b) >> 31);
+}
+
+// One plane of the bit-sliced compare: t holds the thresholds' bit of this
+// plane for every unit (wavefront-uniform), p the random bits.  Units still
+// tied (eq) with random bit 0 against threshold bit 1 fall below it (lt).
+__device__ __forceinline__ void compare_plane(uint32_t& lt, uint32_t& eq, uint32_t p, uint32_t t) {
+    lt |= __builtin_amdgcn_bitop3_b32(eq, p, t, kLutAndNotAnd);
+    eq = __builtin_amdgcn_bitop3_b32(eq, p, t, kLutKeepEqual);
+}
+
 // Bit-sliced comparison U < T over 32 packed hidden units.  val: units that
 // exist; ag: agreeing units (threshold T1 or T2 by type); j2: units of dimer
 // type.  Returns the units with U >= threshold ("flip against the field").
+// The threshold plane is uniform over the wavefront: a scalar operand of the
+// two bit operations per plane.
 __device__ __forceinline__ uint32_t hidden_compare(uint32_t val, uint32_t ag, uint32_t j2, const SweepK& K,
                                                    uint32_t cb, uint32_t c3, const Rng& rg) {
-    const uint32_t j1 = val & ~j2;
+    // only bits of units that exist matter (eq is confined to them)
+    const bool only1 = j2 == 0u, only2 = (j2 & val) == val;
+    auto tplane = [&](int b) -> uint32_t {
+        const uint32_t m0 = plane_mask(K.T[0], b), m1 = plane_mask(K.T[1], b);
+        return only1 ? m0 : (only2 ? m1 : (m0 & ~j2) | (m1 & j2));
+    };
     P4 p = philox(cb, rg.sweep, rg.chain, c3, rg.k0, rg.k1);
     // plane 0: every threshold has its top bit set (T >= 2^31); disagreeing
     // units (threshold exactly 2^31) are decided here
     uint32_t lt = val & ~p.v[0];
     uint32_t eq = ag & p.v[0];
 #pragma unroll
-    for (int b = 1; b < 4; ++b) {
-        const uint32_t t = (((K.T[0] >> (31 - b)) & 1u) ? j1 : 0u) | (((K.T[1] >> (31 - b)) & 1u) ? j2 : 0u);
-        lt |= eq & ~p.v[b] & t;
-        eq &= ~(p.v[b] ^ t);
-    }
+    for (int b = 1; b < 4; ++b) compare_plane(lt, eq, p.v[b], tplane(b));
 #pragma unroll 1
     for (int c = 1; c < 8; ++c) {
         if (!__any(eq != 0u)) break;
         p = philox(cb | (uint32_t)c, rg.sweep, rg.chain, c3, rg.k0, rg.k1);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int b = 4 * c + s;
-            const uint32_t t = (((K.T[0] >> (31 - b)) & 1u) ? j1 : 0u) | (((K.T[1] >> (31 - b)) & 1u) ? j2 : 0u);
-            lt |= eq & ~p.v[s] & t;
-            eq &= ~(p.v[s] ^ t);
-        }
+        for (int s = 0; s < 4; ++s) compare_plane(lt, eq, p.v[s], tplane(4 * c + s));
     }
     return val & ~lt;
 }
@@ -318,6 +336,19 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
             Sg[c] = ((dd & count_ge(b0, b1, b2, K.kge[1])) | (~dd & count_ge(b0, b1, b2, K.kge[0]))) & E;
             D[c] = 0u;
         }
+        // Byte offsets of the table lookups: byte k of By[4c + j] is 4 idx, with
+        // idx = dd + 2 b0 + 4 b1 + 8 b2, of the class-c spin at even column
+        // 2 (j + 4k), so that each lookup address is one byte of a register.
+        uint32_t By[16];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t xe = (Pa[c] & 0x33333333u) | ((Pb[c] & 0x33333333u) << 2);  // columns 4u
+            const uint32_t xo = ((Pa[c] >> 2) & 0x33333333u) | (Pb[c] & 0xccccccccu);  // columns 4u + 2
+            By[4 * c + 0] = (xe & 0x0f0f0f0fu) << 2;
+            By[4 * c + 1] = (xo & 0x0f0f0f0fu) << 2;
+            By[4 * c + 2] = (xe >> 2) & 0x3c3c3c3cu;
+            By[4 * c + 3] = (xo >> 2) & 0x3c3c3c3cu;
+        }
         const int NQ = 2 * m;
         const int NB = (NQ + 7) / 8;
         const uint32_t cbase = (uint32_t)(i * G::W + w) << 5;
@@ -343,8 +374,9 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
                     const int row = q / m, col = q % m, cls = 2 * row + (col & 1), pos = col & ~1;
                     if (!(row == 0 ? do_top : do_mid)) continue;
                     const uint32_t p16 = slot16(p, s);
-                    const uint32_t idx = ((Pa[cls] >> pos) & 3u) | (((Pb[cls] >> pos) & 3u) << 2);
-                    const uint32_t e = __shfl(K.tabv, (int)idx);
+                    const int si = col >> 1;
+                    const int addr = (int)((By[4 * cls + (si & 3)] >> (8 * (si >> 2))) & 0xffu);
+                    const uint32_t e = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)K.tabv);
                     D[cls] |= (uint32_t)(p16 >= (e & 0xffffu)) << pos;
                     tie |= __ballot(p16 == (e >> 16));
                 }
@@ -365,8 +397,9 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
                     const int row = q / m, col = q % m, cls = 2 * row + (col & 1), pos = col & ~1;
                     if (!(row == 0 ? do_top : do_mid)) continue;
                     const uint32_t U = (slot16(p, s) << 16) | slot16(r, s);
-                    const uint32_t idx = ((pick(Pa, cls) >> pos) & 3u) | (((pick(Pb, cls) >> pos) & 3u) << 2);
-                    const uint32_t t = __shfl(K.tfull, (int)idx);
+                    const int si = col >> 1;
+                    const int addr = (int)((pick(By, 4 * cls + (si & 3)) >> (8 * (si >> 2))) & 0xffu);
+                    const uint32_t t = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)K.tfull);
                     const uint32_t d = U >= t;
                     put(D, cls, (pick(D, cls) & ~(1u << pos)) | (d << pos));
                 }
