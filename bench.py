@@ -257,6 +257,52 @@ def learned_points(crbm, torch, L=48, steps=400, cycles=60, chains=512):
     return r
 
 
+# Sec. III.C / Fig. 5 phase points and the paper's TTS_99 on its 30 MHz FPGA
+# (one sample per 33.3 ns), context only
+TTS_POINTS = (("fm", 1.0, 7.0, "33 ns"), ("dimer", 2.5, 0.0, "~5 us"), ("neel", 1.0, 0.0, "200 us"),
+              ("one_third", 0.5, 4.0, "120 ms"))
+
+
+def tts_leg(crbm, torch, sizes=(6, 12, 18), temps=(0.2, 0.3, 0.5, 0.7, 1.0), chains=8192, sweeps=20000,
+            long_sweeps=100000, long_temps=(0.2, 0.3)):
+    """Time-to-solution (Eq. (14)) at the four phase points: constant-T runs
+    from the seeded random start, per-chain minimum energy and first hit on
+    the device, p_gnd against the exact ordered ground state, best T of a
+    small grid (the paper tunes beta per problem).  The 1/3 plateau at L >= 12
+    is rarely solved within the grid's runs; it gets longer runs at the two
+    lowest temperatures as well."""
+    import numpy as np
+    from paper_2511_20911_amd import tts as T
+
+    fin = lambda x: None if x is None or not np.isfinite(x) else float(x)
+    out = []
+    for k, (phase, J2, h, paper) in enumerate(TTS_POINTS):
+        for j, L in enumerate(sizes):
+            base_id = 1000 + 100 * k + 10 * j
+            r = T.phase_tts(L, J2, h, temps, chains, sweeps, seed=SEED + 5, id=base_id)
+            assert r["phase"] == phase
+            cands = [(x, sweeps) for x in r["by_T"]]
+            if phase == "one_third" and L >= 12:
+                r2 = T.phase_tts(L, J2, h, long_temps, chains, long_sweeps, seed=SEED + 6, id=base_id + 5)
+                cands += [(x, long_sweeps) for x in r2["by_T"]]
+            b, run_len = min(cands, key=lambda c: c[0]["tts_sweeps"])
+            out.append({"phase": phase, "J2": J2, "h": h, "L": L, "best_T": b["T"], "run_sweeps": run_len,
+                        "p_gnd": b["p_gnd"], "T_hit_sweeps": b["T_sweeps"], "tts99_sweeps": fin(b["tts_sweeps"]),
+                        "tts99_latency_s": fin(b["tts_latency_s"]), "tts99_amortised_s": fin(b["tts_amortised_s"]),
+                        "sweep_latency_us": b["sweep_latency_s"] * 1e6, "paper_fpga_tts99": paper,
+                        "p_gnd_by_T": {f"{x['T']}@{n}": x["p_gnd"] for x, n in cands}})
+    return {"protocol": f"{chains} independent constant-T runs per (phase, L, T), {sweeps} sweeps (1/3 plateau at "
+                        f"L >= 12 also {long_sweeps} sweeps at T in {list(long_temps)}), from the seeded +-1 start; "
+                        "p_gnd = share of runs whose lowest energy equals the exact ordered ground state; "
+                        "T = mean first-hit sweep of those runs; TTS99 = T log(0.01)/log(1-p_gnd) (TTS100 = T); "
+                        "best T of " + str(list(temps)),
+            "times": "latency: one run sharing the GPU with the batch (device time per batch sweep); "
+                     "amortised: device time per run-sweep",
+            "context": "the paper's FPGA: one sample per 33.3 ns, so its TTS99 in sweeps is 1 (FM), ~150 (dimer), "
+                       "~6e3 (Neel), ~3.6e6 (1/3) at its largest sizes",
+            "points": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,6 +320,7 @@ def main():
     ap.add_argument("--no-scale", action="store_true", help="skip the 48x48 / 96x96 Gibbs measurement")
     ap.add_argument("--no-c5-mh", action="store_true", help="skip the conditional learned-MH comparison at 48x48")
     ap.add_argument("--c5-mh-96", action="store_true", help="also run the conditional learned-MH comparison at 96x96")
+    ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution runs at the four phase points")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (--gpus 1): chains are independent, and sharding them over "
@@ -377,6 +424,8 @@ def main():
         result["batched_uneven"] = batched_uneven(crbm, torch)
     if not args.no_scale:
         result["scale"] = scale_gibbs(crbm, torch)
+    if not args.no_tts:
+        result["tts"] = tts_leg(crbm, torch)
     if not args.no_mh:
         result["learned_mh"] = learned_mh(crbm, torch)
     if not args.no_c5_mh:

@@ -185,6 +185,26 @@ int crbm_tau_int(const int32_t* trace_dev, int64_t n_samples, int64_t trace_chai
                  int64_t discard, const double w[3], int32_t max_lag, double c_window, void* stream,
                  double* tau_out, double* ess_out, int32_t* window_out, double* rho_out);
 
+/* Ground-state search behind the time-to-solution of Sec. III.C Eq. (14)
+ * (the host picks the lowest-energy states it has sampled, App. A I/O
+ * Programming Logic): fold a counts trace written by crbm_sample /
+ * crbm_sample_thinned (trace_dev: device, int32 [n_samples][trace_chains][3])
+ * into per-chain running minima of E = w[0] M + w[1] B1 + w[2] B2, exact in
+ * int64 (with w = (-hq, J1q, J2q), E is H in 2^-16 units).  For chain c0 + i,
+ * i < c1 - c0: emin_dev[i] (device int64) is the lowest E seen and
+ * first_dev[i] (device int64) the number of completed sweeps of the chain when
+ * that value was first reached, sample t of the trace counting as sweep0 +
+ * (t + 1) * trace_every (sweep0 = the handle's sweep index before the
+ * crbm_sample call that wrote the trace).  Only a strictly lower energy
+ * replaces a minimum, so folding consecutive traces of one run gives the
+ * first hit over the whole run.  reset != 0 starts from emin = INT64_MAX,
+ * first = -1 instead of the arrays' contents.  n_samples = 0 with reset = 0 is
+ * a no-op.  Asynchronous on `stream`.  CRBM_EINVAL for NULL outputs, an empty
+ * or out-of-range chain range, trace_every < 1, sweep0 < 0 or |w[k]| >= 2^31. */
+int crbm_min_energy(const int32_t* trace_dev, int64_t n_samples, int64_t trace_chains, int64_t c0, int64_t c1,
+                    const int64_t w[3], int64_t sweep0, int32_t trace_every, int32_t reset, int64_t* emin_dev,
+                    int64_t* first_dev, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Learned proposal (an addition to the paper's Gibbs sampler): a masked-
  * convolution autoregressive network q(s) over the spins in raster order

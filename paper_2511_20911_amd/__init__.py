@@ -100,6 +100,8 @@ def lib() -> ct.CDLL:
         L.crbm_autotune.argtypes = [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p, p(ct.c_int32), p(ct.c_int32),
                                     p(ct.c_double)]
         L.crbm_set_tiling.argtypes = [ct.c_int32, ct.c_int32, ct.c_int32]
+        L.crbm_min_energy.argtypes = [ct.c_void_p, ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int64, p(ct.c_int64),
+                                      ct.c_int64, ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p]
         L.crbm_ar_create.argtypes = [p(_ARConfig), p(ct.c_void_p)]
         L.crbm_ar_num_params.argtypes = [ct.c_void_p]
         L.crbm_ar_num_params.restype = ct.c_int64
@@ -189,6 +191,31 @@ def tau_int(trace, weights, c0: int = 0, c1: Optional[int] = None, discard: int 
                               _stream_handle(stream), ct.byref(tau), ct.byref(ess), ct.byref(win),
                               rho.ctypes.data_as(ct.POINTER(ct.c_double))))
     return float(tau.value), float(ess.value), int(win.value), rho
+
+
+def min_energy(trace, weights, sweep0: int = 0, trace_every: int = 1, c0: int = 0, c1: Optional[int] = None,
+               emin=None, first=None, stream=None):
+    """Per-chain running minimum of E = w0 M + w1 B1 + w2 B2 over a device
+    counts trace [n_samples, chains, 3] (int32) and the number of completed
+    sweeps at its first hit (crbm_min_energy).  emin/first: int64 device
+    tensors of c1 - c0 entries carrying the minima of earlier traces of the
+    same run, or None to start afresh.  Returns (emin, first)."""
+    import torch
+    assert trace.is_cuda and trace.dim() == 3 and trace.shape[2] == 3 and trace.dtype == torch.int32
+    trace = trace.contiguous()
+    n, nch = int(trace.shape[0]), int(trace.shape[1])
+    c1 = nch if c1 is None else c1
+    reset = emin is None
+    if reset:
+        emin = torch.empty(c1 - c0, dtype=torch.int64, device=trace.device)
+        first = torch.empty(c1 - c0, dtype=torch.int64, device=trace.device)
+    assert emin.dtype == torch.int64 and first.dtype == torch.int64
+    assert emin.numel() >= c1 - c0 and first.numel() >= c1 - c0 and emin.is_contiguous() and first.is_contiguous()
+    w = (ct.c_int64 * 3)(*[int(x) for x in weights])
+    _check(lib().crbm_min_energy(ct.c_void_p(trace.data_ptr()), n, nch, c0, c1, w, sweep0, trace_every,
+                                 1 if reset else 0, ct.c_void_p(emin.data_ptr()), ct.c_void_p(first.data_ptr()),
+                                 _stream_handle(stream)))
+    return emin, first
 
 
 def set_tiling(L: int, rows: int, waves_per_block: int = 4):

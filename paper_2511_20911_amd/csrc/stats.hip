@@ -1,6 +1,7 @@
 // stats.hip -- integrated autocorrelation time and effective sample size of
 // an observable of the per-sweep counts trace, for the ESS/s comparison of
-// samplers (the paper itself reports time-to-solution, Sec. III.C Eq. (14)).
+// samplers; and the per-chain minimum energy and first-hit sweep behind the
+// time-to-solution of Sec. III.C Eq. (14).
 //
 // O[t][c] = wM M + wB1 B1 + wB2 B2 from the trace record (M, B1, B2) of chain
 // c at sample t.  The grand mean over chains and kept samples is removed, so
@@ -77,10 +78,53 @@ __global__ void __launch_bounds__(256) autocov_kernel(const double* x, int64_t m
     (void)max_lag;
 }
 
+// one thread per chain of [c0, c0 + nc): fold samples [0, n) of the counts
+// trace into the chain's running minimum of E = w0 M + w1 B1 + w2 B2 (exact
+// int64) and the number of completed sweeps at which that minimum was first
+// reached; sample t of the trace was recorded after sweep0 + (t + 1) every
+// sweeps.  A later sample only replaces the minimum if it is strictly lower.
+__global__ void min_energy_kernel(const int32_t* trace, int64_t n, int64_t stride_chains, int64_t c0, int64_t nc,
+                                  int64_t w0, int64_t w1, int64_t w2, int64_t sweep0, int64_t every, int reset,
+                                  int64_t* emin, int64_t* first) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    int64_t best = reset ? INT64_MAX : emin[c];
+    int64_t at = reset ? -1 : first[c];
+    for (int64_t t = 0; t < n; ++t) {
+        const int32_t* r = trace + (t * stride_chains + c0 + c) * 3;
+        const int64_t E = w0 * (int64_t)r[0] + w1 * (int64_t)r[1] + w2 * (int64_t)r[2];
+        if (E < best) {
+            best = E;
+            at = sweep0 + (t + 1) * every;
+        }
+    }
+    emin[c] = best;
+    first[c] = at;
+}
+
 }  // namespace
 }  // namespace crbmlib
 
 using namespace crbmlib;
+
+extern "C" int crbm_min_energy(const int32_t* trace_dev, int64_t n_samples, int64_t trace_chains, int64_t c0,
+                               int64_t c1, const int64_t w[3], int64_t sweep0, int32_t trace_every, int32_t reset,
+                               int64_t* emin_dev, int64_t* first_dev, void* stream) {
+    if (!w || !emin_dev || !first_dev || n_samples < 0 || (n_samples > 0 && !trace_dev) || trace_chains < 1 ||
+        c0 < 0 || c1 > trace_chains || c1 <= c0 || sweep0 < 0 || trace_every < 1)
+        return set_error(CRBM_EINVAL, "crbm_min_energy: bad arguments");
+    const int64_t lim = (int64_t)1 << 31;
+    for (int k = 0; k < 3; ++k)
+        if (w[k] <= -lim || w[k] >= lim) return set_error(CRBM_EINVAL, "crbm_min_energy: |w| must be < 2^31");
+    const int64_t nc = c1 - c0;
+    hipLaunchKernelGGL(min_energy_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       trace_dev, n_samples, trace_chains, c0, nc, w[0], w[1], w[2], sweep0, (int64_t)trace_every,
+                       reset ? 1 : 0, emin_dev, first_dev);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(CRBM_EHIP, hipGetErrorString(e));
+    set_error(CRBM_OK, "");
+    return CRBM_OK;
+}
 
 extern "C" int crbm_tau_int(const int32_t* trace_dev, int64_t n_samples, int64_t trace_chains, int64_t c0,
                             int64_t c1, int64_t discard, const double w[3], int32_t max_lag, double c_window,
