@@ -80,7 +80,22 @@ typedef struct {
     int32_t tile_rows;         /* cell rows per lane: 0 = tuned/default choice, else must divide L/2 */
     int32_t launch_mode;       /* CRBM_LAUNCH_DIRECT or CRBM_LAUNCH_GRAPH */
     int32_t waves_per_block;   /* 1..4 wavefronts per workgroup; 0 = tuned/default choice */
+    int32_t precision;         /* CRBM_PRECISION_* (0 = the default 16.16 / 32-bit path) */
 } crbm_config;
+
+/* Arithmetic of the per-sweep weights, fields and sigmoid thresholds.
+ * CRBM_PRECISION_Q16: 16.16 weights and bias, 32-bit thresholds and uniforms.
+ * CRBM_PRECISION_FPGA: the paper's hardware precision (App. A Dimension and
+ *   Precision; Sigmoid and LFSR-Forward), for studying its effect on sampling:
+ *   weights w and visible bias a = h/T rounded to signed Q5.4 (steps of 1/16,
+ *   |.| <= 511/16, saturating); the hidden convolution output (0 or +-2w) in
+ *   the same 10 bits and the visible accumulator (bias plus the 5 incident
+ *   +-w) in 12 bits (|.| <= 2047/16), both saturating; the sigmoid as the
+ *   closest 16-bit value, min(65535, round(65536 sigmoid(2|x|))), compared
+ *   with a 16-bit uniform (the top half of the unit's 32-bit Philox uniform).
+ *   Handles in this mode are refused by crbm_sample_mh: their stationary law
+ *   is not the exact CRBM marginal the acceptance uses. */
+enum { CRBM_PRECISION_Q16 = 0, CRBM_PRECISION_FPGA = 1 };
 
 enum {
     CRBM_LAUNCH_DIRECT = 0, /* one grid launch per lattice size, one wavefront per work item */
@@ -320,6 +335,13 @@ int crbm_sweep_table(const crbm_t* h, int32_t i, int64_t s, uint32_t out[16]);
  * temperature T, exactly as crbm_create builds it.  Returns CRBM_EINVAL for
  * T <= 0 or non-finite input, CRBM_ERANGE on fixed-point overflow. */
 int crbm_table_for(double J1, double J2, double h, double T, uint32_t out[16]);
+
+/* The 16-word device table of one sweep for (J1, J2, h) at temperature T in
+ * the given precision (CRBM_PRECISION_*), built on the host exactly as
+ * crbm_create builds it (layout: the library's internal table; for tests).
+ * CRBM_ERANGE if a 16.16 value overflows int32, CRBM_EINVAL for a bad T,
+ * precision or NULL out. */
+int crbm_table_for_precision(double J1, double J2, double h, double T, int32_t precision, uint32_t* out);
 
 #ifdef __cplusplus
 }

@@ -43,6 +43,7 @@ class _Instance(ct.Structure):
         ("T1", ct.c_double),
         ("T_explicit", ct.POINTER(ct.c_double)),
         ("id", ct.c_uint32),
+        ("precision", ct.c_int32),
     ]
 
 
@@ -71,6 +72,11 @@ def lib():
         L.oracle_visible_bias.restype = i64
         L.oracle_threshold.argtypes = [i64]
         L.oracle_threshold.restype = u32
+        L.oracle_q54.argtypes = [dbl]
+        L.oracle_q54.restype = i64
+        L.oracle_sigmoid16.argtypes = [i64]
+        L.oracle_sigmoid16.restype = u32
+        L.oracle_bond_weight_q54.argtypes = [i64, dbl, p(i64), p(ct.c_int)]
         L.oracle_bond_sites.argtypes = [ct.c_int] * 4 + [p(ct.c_int)] * 5
         L.oracle_counts.argtypes = [ct.c_int, p(ct.c_int8), p(i64), p(i64), p(i64)]
         L.oracle_corr.argtypes = [ct.c_int, p(ct.c_int8), p(i64)]
@@ -93,17 +99,19 @@ class Instance:
     """One Hamiltonian point: lattice side L, couplings, schedule, RNG id."""
 
     def __init__(self, L, J1=1.0, J2=0.5, h=0.0, sched="const", T0=1.0, T1=None,
-                 T_explicit=None, id=0):
+                 T_explicit=None, id=0, precision=0):
         self.L, self.J1, self.J2, self.h = int(L), float(J1), float(J2), float(h)
         self.sched = sched
         self.T0 = float(T0)
         self.T1 = float(T0 if T1 is None else T1)
         self.T_explicit = None if T_explicit is None else np.ascontiguousarray(T_explicit, np.float64)
         self.id = int(id)
+        self.precision = int(precision)  # 0: 16.16 / 32-bit; 1: the hardware's Q5.4 / 16-bit
 
     def c(self) -> _Instance:
         te = None if self.T_explicit is None else _ptr(self.T_explicit, ct.c_double)
-        return _Instance(self.L, self.J1, self.J2, self.h, SCHED[self.sched], self.T0, self.T1, te, self.id)
+        return _Instance(self.L, self.J1, self.J2, self.h, SCHED[self.sched], self.T0, self.T1, te, self.id,
+                         self.precision)
 
 
 # ------------------------------------------------------------------ primitives
@@ -146,6 +154,23 @@ def visible_bias(hq: int, T: float) -> int:
 
 def threshold(y: int) -> int:
     return int(lib().oracle_threshold(int(y)))
+
+
+def q54(v: float) -> int:
+    """Hardware fixed point (App. A Dimension and Precision) in 2^-16 units."""
+    return int(lib().oracle_q54(float(v)))
+
+
+def sigmoid16(y: int) -> int:
+    """Closest 16-bit value of sigmoid(2 y 2^-16) (App. A Sigmoid module)."""
+    return int(lib().oracle_sigmoid16(int(y)))
+
+
+def bond_weight_q54(Jq: int, T: float):
+    wq = ct.c_int64()
+    sg = ct.c_int()
+    lib().oracle_bond_weight_q54(int(Jq), float(T), ct.byref(wq), ct.byref(sg))
+    return int(wq.value), int(sg.value)
 
 
 def bond_sites(L, k, i, j):

@@ -224,6 +224,45 @@ uint32_t oracle_threshold(int64_t y)
     return (uint32_t)t;
 }
 
+/* ---------------------------------------------- hardware precision mode */
+
+/* App. A Dimension and Precision: the convolution uses 10-bit signed fixed
+ * point with 4 fraction bits (steps of 1/16, magnitude at most 511/16, read
+ * here as saturating), the accumulator 2 more integer bits (2047/16); App. A
+ * Sigmoid and LFSR-Forward: the sigmoid is the closest 16-bit value and is
+ * compared with a 16-bit uniform.  Values in 2^-16 units. */
+#define Q54_STEP 4096
+#define Q54_MAX (511 * Q54_STEP)
+#define ACC_MAX (2047 * Q54_STEP)
+
+int64_t oracle_q54(double v)
+{
+    long m = lround(fabs(v) * 16.0);
+    if (m > 511) m = 511;
+    return (int64_t)(v < 0.0 ? -m : m) * Q54_STEP;
+}
+
+static int64_t clamp_abs(int64_t x, int64_t lim)
+{
+    return x > lim ? lim : (x < -lim ? -lim : x);
+}
+
+/* closest 16-bit value of sigmoid(2 y 2^-16), capped at 65535 */
+uint32_t oracle_sigmoid16(int64_t y)
+{
+    double p = 1.0 / (1.0 + exp(-2.0 * ldexp((double)y, -16)));
+    double t = floor(p * 65536.0 + 0.5);
+    return t > 65535.0 ? 65535u : (uint32_t)t;
+}
+
+void oracle_bond_weight_q54(int64_t Jq, double T, int64_t* wq, int* sig)
+{
+    double K = -((double)Jq / 65536.0) / T;
+    double a = fabs(K);
+    *wq = oracle_q54(a + 0.5 * log1p(sqrt(-expm1(-4.0 * a))));
+    *sig = (K < 0.0) ? -1 : +1;
+}
+
 /* ------------------------------------------------------------------- bonds */
 
 /* Window offsets (dr_a, dc_a, dr_b, dc_b) and coupling type (1 = J1, 2 = J2)
@@ -306,6 +345,12 @@ static int sweep_params(const oracle_instance* in, int64_t S, int64_t s,
     double T = oracle_schedule_T(in->sched_kind, in->T0, in->T1, in->T_explicit, S, s);
     if (!(T > 0.0) || !isfinite(T)) return -1;
     int64_t J1q = oracle_quantise(in->J1), J2q = oracle_quantise(in->J2), hq = oracle_quantise(in->h);
+    if (in->precision == 1) {
+        oracle_bond_weight_q54(J1q, T, wq1, sg1);
+        oracle_bond_weight_q54(J2q, T, wq2, sg2);
+        *aq = oracle_q54(((double)hq / 65536.0) / T);
+        return 0;
+    }
     oracle_bond_weight(J1q, T, wq1, sg1);
     oracle_bond_weight(J2q, T, wq2, sg2);
     *aq = oracle_visible_bias(hq, T);
@@ -333,6 +378,16 @@ static int8_t gibbs_unit(int64_t x, uint32_t U)
     int8_t sgn = (x >= 0) ? +1 : -1;
     int64_t y = (x >= 0) ? x : -x;
     return (U < oracle_threshold(y)) ? sgn : (int8_t)(-sgn);
+}
+
+/* hardware precision: field saturated to lim, 16-bit sigmoid against the top
+ * 16 bits of the unit's uniform */
+static int8_t gibbs_unit16(int64_t x, int64_t lim, uint32_t U)
+{
+    x = clamp_abs(x, lim);
+    int8_t sgn = (x >= 0) ? +1 : -1;
+    int64_t y = (x >= 0) ? x : -x;
+    return ((U >> 16) < oracle_sigmoid16(y)) ? sgn : (int8_t)(-sgn);
 }
 
 int oracle_run_chain(const oracle_instance* in, int64_t S, uint64_t seed, uint32_t chain,
@@ -363,7 +418,7 @@ int oracle_run_chain(const oracle_instance* in, int64_t S, uint64_t seed, uint32
                     int sg = (type == 1) ? sg1 : sg2;
                     int64_t x = wq * (int64_t)(s[ra * L + ca] + sg * s[rb * L + cb]);
                     uint32_t U = oracle_uniform_hidden(seed, in->id, chain, sweep, L, k, i, j);
-                    hid[(k * C + i) * C + j] = gibbs_unit(x, U);
+                    hid[(k * C + i) * C + j] = in->precision == 1 ? gibbs_unit16(x, Q54_MAX, U) : gibbs_unit(x, U);
                 }
         /* visible half-step, Eq. (12) plus the visible bias: every spin from
          * the hidden units just drawn.  Accumulate fields bond by bond. */
@@ -382,7 +437,8 @@ int oracle_run_chain(const oracle_instance* in, int64_t S, uint64_t seed, uint32
         for (int r = 0; r < L; ++r)
             for (int c = 0; c < L; ++c) {
                 uint32_t U = oracle_uniform_visible(seed, in->id, chain, sweep, L, r, c);
-                s[r * L + c] = gibbs_unit(field[r * L + c], U);
+                s[r * L + c] = in->precision == 1 ? gibbs_unit16(field[r * L + c], ACC_MAX, U)
+                                                  : gibbs_unit(field[r * L + c], U);
             }
         if (trace || acc) {
             int64_t M, B1, B2;

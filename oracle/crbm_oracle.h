@@ -14,6 +14,7 @@ typedef struct {
     double T0, T1;
     const double* T_explicit;
     uint32_t id;           /* instance id in the random-number counter */
+    int32_t precision;     /* 0: 16.16 weights, 32-bit sigmoid; 1: the hardware's Q5.4 / 16-bit precision */
 } oracle_instance;
 
 void     oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -22,6 +23,9 @@ uint32_t oracle_uniform_hidden(uint64_t seed, uint32_t id, uint32_t chain, uint3
 uint32_t oracle_uniform_visible(uint64_t seed, uint32_t id, uint32_t chain, uint32_t sweep,
                                 int L, int r, int c);
 int64_t  oracle_quantise(double J);
+int64_t  oracle_q54(double v);
+uint32_t oracle_sigmoid16(int64_t y);
+void     oracle_bond_weight_q54(int64_t Jq, double T, int64_t* wq, int* sig);
 double   oracle_schedule_T(int kind, double T0, double T1, const double* T_explicit,
                            int64_t S, int64_t s);
 void     oracle_bond_weight(int64_t Jq, double T, int64_t* wq, int* sig);

@@ -46,11 +46,12 @@ class _Config(ct.Structure):
     _fields_ = [
         ("seed", ct.c_uint64), ("n_sweeps", ct.c_int64), ("measure_every", ct.c_int32),
         ("burn_in", ct.c_int64), ("stream", ct.c_void_p), ("tile_rows", ct.c_int32),
-        ("launch_mode", ct.c_int32), ("waves_per_block", ct.c_int32),
+        ("launch_mode", ct.c_int32), ("waves_per_block", ct.c_int32), ("precision", ct.c_int32),
     ]
 
 
 LAUNCH = {"direct": 0, "graph": 1}
+PRECISION = {"q16": 0, "fpga": 1}
 
 
 class _Obs(ct.Structure):
@@ -97,6 +98,8 @@ def lib() -> ct.CDLL:
         L.crbm_threshold.restype = ct.c_uint32
         L.crbm_sweep_table.argtypes = [ct.c_void_p, ct.c_int32, ct.c_int64, p(ct.c_uint32)]
         L.crbm_table_for.argtypes = [ct.c_double, ct.c_double, ct.c_double, ct.c_double, p(ct.c_uint32)]
+        L.crbm_table_for_precision.argtypes = [ct.c_double, ct.c_double, ct.c_double, ct.c_double, ct.c_int32,
+                                               p(ct.c_uint32)]
         L.crbm_autotune.argtypes = [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p, p(ct.c_int32), p(ct.c_int32),
                                     p(ct.c_double)]
         L.crbm_set_tiling.argtypes = [ct.c_int32, ct.c_int32, ct.c_int32]
@@ -159,10 +162,11 @@ def threshold(y: int) -> int:
     return int(lib().crbm_threshold(int(y)))
 
 
-def table_for(J1: float, J2: float, h: float, T: float) -> np.ndarray:
+def table_for(J1: float, J2: float, h: float, T: float, precision: str = "q16") -> np.ndarray:
     """The library's 16-word device table for one sweep (host computation)."""
     out = np.zeros(16, np.uint32)
-    _check(lib().crbm_table_for(J1, J2, h, T, out.ctypes.data_as(ct.POINTER(ct.c_uint32))))
+    _check(lib().crbm_table_for_precision(J1, J2, h, T, PRECISION[precision],
+                                          out.ctypes.data_as(ct.POINTER(ct.c_uint32))))
     return out
 
 
@@ -240,7 +244,7 @@ class Sampler:
 
     def __init__(self, instances: Sequence[Instance], seed: int, n_sweeps: int, measure_every: int = 0,
                  burn_in: int = 0, stream=None, tile_rows: int = 0, launch: str = "direct",
-                 waves_per_block: int = 0):
+                 waves_per_block: int = 0, precision: str = "q16"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the CRBM sampler runs only on the HIP device")
@@ -257,7 +261,7 @@ class Sampler:
                                I.T0 if I.T1 is None else I.T1, te, I.id)
         self.stream = stream
         cfg = _Config(seed, n_sweeps, measure_every, burn_in, _stream_handle(stream), tile_rows, LAUNCH[launch],
-                      waves_per_block)
+                      waves_per_block, PRECISION[precision])
         h = ct.c_void_p()
         _check(lib().crbm_create(arr, len(self.instances), ct.byref(cfg), ct.byref(h)))
         self._h = h

@@ -1662,6 +1662,8 @@ int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_
     if (handle_view(h, &v, 0) != CRBM_OK) return fail_ar(CRBM_EINVAL, "bad handle");
     if (v.L != a->L) return fail_ar(CRBM_EINVAL, "lattice size of the network and the handle differ");
     if (v.stream != a->stream) return fail_ar(CRBM_EINVAL, "handle and network must use the same stream");
+    if (v.precision != CRBM_PRECISION_Q16)
+        return fail_ar(CRBM_EUNSUPPORTED, "MH needs the default precision (the acceptance uses the exact CRBM marginal)");
     const int n_inst = v.n_inst;
     if (a->cond > 0 && n_inst > a->npts)
         return fail_ar(CRBM_EINVAL, "conditional network: instance i uses point i, set at least one point per instance");

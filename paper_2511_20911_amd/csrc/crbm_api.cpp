@@ -74,23 +74,57 @@ uint32_t threshold(int64_t y) {
     return (uint32_t)t;
 }
 
+// The paper's hardware precision (App. A Dimension and Precision; Sigmoid and
+// LFSR-Forward), in 16.16 units: signed Q5.4 values are multiples of 2^12
+// with magnitude at most 511 steps (saturating); the visible accumulator has
+// two more integer bits (2047 steps); the sigmoid is the closest 16-bit value,
+// so the 32-bit threshold is that value shifted up by 16 bits and the compare
+// with a 32-bit uniform decides on its top 16 bits alone.
+constexpr int64_t kQ54Step = 4096, kQ54Max = 511 * kQ54Step, kAccMax = 2047 * kQ54Step;
+
+int64_t q54(double v) {
+    double m = floor(fabs(v) * 16.0 + 0.5);
+    if (m > 511.0) m = 511.0;
+    return (v < 0.0 ? -(int64_t)m : (int64_t)m) * kQ54Step;
+}
+
+int64_t saturate(int64_t x, int64_t lim) { return x > lim ? lim : (x < -lim ? -lim : x); }
+
+uint32_t threshold16(int64_t y) {
+    const double p = 1.0 / (1.0 + exp(-(2.0 * ldexp((double)y, -16))));
+    double t = floor(p * 65536.0 + 0.5);
+    if (t > 65535.0) t = 65535.0;
+    return (uint32_t)t << 16;
+}
+
 // One sweep's 16-word device table (layout in crbm_internal.h).
-int build_table(int64_t J1q, int64_t J2q, int64_t hq, double T, uint32_t* out) {
+int build_table(int64_t J1q, int64_t J2q, int64_t hq, double T, int precision, uint32_t* out) {
     int64_t wq1, wq2;
     int s1, s2;
     hidden_weight(J1q, T, &wq1, &s1);
     hidden_weight(J2q, T, &wq2, &s2);
-    const int64_t aq = llround((double)hq / T);
+    int64_t aq = llround((double)hq / T);
+    const bool fpga = precision == CRBM_PRECISION_FPGA;
+    if (fpga) {
+        // re-round the exact weights and bias to Q5.4 (the 16.16 values above
+        // are only used for the range check of the default path)
+        const double K1 = fabs(((double)J1q / 65536.0) / T), K2 = fabs(((double)J2q / 65536.0) / T);
+        wq1 = q54(K1 + 0.5 * log1p(sqrt(-expm1(-4.0 * K1))));
+        wq2 = q54(K2 + 0.5 * log1p(sqrt(-expm1(-4.0 * K2))));
+        aq = q54(((double)hq / 65536.0) / T);
+    }
     const int64_t lim = (int64_t)1 << 31;
     if (wq1 >= lim || wq2 >= lim || aq >= lim || aq <= -lim) return CRBM_ERANGE;
+    auto thr = [&](int64_t y) { return fpga ? threshold16(y) : threshold(y); };
     std::memset(out, 0, sizeof(uint32_t) * kTabWords);
-    out[0] = threshold(2 * wq1);
-    out[1] = threshold(2 * wq2);
+    out[0] = thr(fpga ? saturate(2 * wq1, kQ54Max) : 2 * wq1);
+    out[1] = thr(fpga ? saturate(2 * wq2, kQ54Max) : 2 * wq2);
     uint32_t kge[2] = {5u, 5u};
     for (int d = 0; d < 2; ++d)
         for (int n = 4; n >= 0; --n) {
-            const int64_t x = aq + wq1 * (2 * n - 4) + wq2 * (2 * d - 1);
-            out[3 + 2 * n + d] = threshold(x < 0 ? -x : x);
+            int64_t x = aq + wq1 * (2 * n - 4) + wq2 * (2 * d - 1);
+            if (fpga) x = saturate(x, kAccMax);
+            out[3 + 2 * n + d] = thr(x < 0 ? -x : x);
             if (x >= 0) kge[d] = (uint32_t)n;
         }
     out[2] = (s1 < 0 ? 1u : 0u) | (s2 < 0 ? 2u : 0u) | (wq1 != 0 ? 4u : 0u) | (wq2 != 0 ? 8u : 0u) |
@@ -253,6 +287,7 @@ int crbmlib::handle_view(crbm_t* h, HandleView* v, int i) {
     v->cur = h->cur;
     v->S = h->S;
     v->stream = h->stream;
+    v->precision = h->cfg.precision;
     int64_t wq1, wq2;
     hidden_weight(h->Jq[0][(size_t)i], I.T0, &wq1, &v->sg1);
     hidden_weight(h->Jq[1][(size_t)i], I.T0, &wq2, &v->sg2);
@@ -281,6 +316,8 @@ int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cf
     if (cfg->launch_mode != CRBM_LAUNCH_DIRECT && cfg->launch_mode != CRBM_LAUNCH_GRAPH)
         return fail(CRBM_EINVAL, "unknown launch_mode");
     if (cfg->waves_per_block < 0 || cfg->waves_per_block > 4) return fail(CRBM_EINVAL, "waves_per_block must be 0..4");
+    if (cfg->precision != CRBM_PRECISION_Q16 && cfg->precision != CRBM_PRECISION_FPGA)
+        return fail(CRBM_EINVAL, "unknown precision");
     const double lim = 2147483647.0 / 65536.0;
     for (int i = 0; i < n_inst; ++i) {
         const crbm_instance& I = inst[i];
@@ -342,7 +379,7 @@ int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cf
         h->h_tables.resize(h->h_tables.size() + (size_t)ntab * kTabWords);
         for (int64_t s = 0; s < ntab; ++s) {
             const double T = schedule_T(I.sched_kind, I.T0, I.T1, I.T_explicit, h->S, s);
-            const int rc = build_table(h->Jq[0][i], h->Jq[1][i], h->Jq[2][i], T,
+            const int rc = build_table(h->Jq[0][i], h->Jq[1][i], h->Jq[2][i], T, cfg->precision,
                                        h->h_tables.data() + h->tab_off[i] + (size_t)s * kTabWords);
             if (rc != CRBM_OK) {
                 delete h;
@@ -684,7 +721,19 @@ int crbm_table_for(double J1, double J2, double h, double T, uint32_t out[16]) {
     if (!out || !(T > 0.0) || !std::isfinite(T) || !std::isfinite(J1) || !std::isfinite(J2) || !std::isfinite(h))
         return fail(CRBM_EINVAL, "bad arguments");
     if (fabs(J1) >= lim || fabs(J2) >= lim || fabs(h) >= lim) return fail(CRBM_ERANGE, "|J| * 2^16 must fit in int32");
-    const int rc = build_table(q16(J1), q16(J2), q16(h), T, out);
+    const int rc = build_table(q16(J1), q16(J2), q16(h), T, CRBM_PRECISION_Q16, out);
+    if (rc != CRBM_OK) return fail(rc, "fixed-point weight or bias overflows int32");
+    return CRBM_OK;
+}
+
+int crbm_table_for_precision(double J1, double J2, double h, double T, int32_t precision, uint32_t* out) {
+    g_err.clear();
+    const double lim = 2147483647.0 / 65536.0;
+    if (!out || !(T > 0.0) || !std::isfinite(T) || !std::isfinite(J1) || !std::isfinite(J2) || !std::isfinite(h) ||
+        (precision != CRBM_PRECISION_Q16 && precision != CRBM_PRECISION_FPGA))
+        return fail(CRBM_EINVAL, "bad arguments");
+    if (fabs(J1) >= lim || fabs(J2) >= lim || fabs(h) >= lim) return fail(CRBM_ERANGE, "|J| * 2^16 must fit in int32");
+    const int rc = build_table(q16(J1), q16(J2), q16(h), T, precision, out);
     if (rc != CRBM_OK) return fail(rc, "fixed-point weight or bias overflows int32");
     return CRBM_OK;
 }

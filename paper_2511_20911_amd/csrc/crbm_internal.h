@@ -66,6 +66,7 @@ struct HandleView {
     // MH target: log pi = a M + c1 n1 + c2 n2 (+ const) at the constant temperature
     double a, c1, c2;
     int sg1, sg2;
+    int precision;     // CRBM_PRECISION_* of the handle's tables
 };
 // the view of instance i (0 <= i < number of instances)
 int handle_view(crbm_t* h, HandleView* v, int i);
