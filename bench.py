@@ -303,6 +303,50 @@ def tts_leg(crbm, torch, sizes=(6, 12, 18), temps=(0.2, 0.3, 0.5, 0.7, 1.0), cha
             "points": out}
 
 
+def _crossing(hs, m, level):
+    """First h where m(h) rises through `level` (linear interpolation), or None."""
+    for k in range(len(hs) - 1):
+        if m[k] < level <= m[k + 1]:
+            return hs[k] + (level - m[k]) * (hs[k + 1] - hs[k]) / (m[k + 1] - m[k])
+    return None
+
+
+def precision_leg(crbm, torch, temps=(0.1, 0.25, 0.5), n_h=65, h_max=8.0, chains=256, anneal=2000, measure=1000):
+    """Magnetisation curve m(h) along J2/J1 = 1 at 18x18 (Fig. 3b) in the
+    default 16.16 / 32-bit precision and in the hardware's Q5.4 / 16-bit one
+    (App. A Dimension and Precision), at equal temperatures: geometric anneal
+    5 -> T, then `measure` sweeps at T with exact accumulators.  For the two
+    transitions (Neel -> 1/3 at h = 2, 1/3 -> FM at h = 5) it reports where m
+    crosses the middle of its step and the 10-90 % width of the step."""
+    import numpy as np
+
+    hs = [h_max * k / (n_h - 1) for k in range(n_h)]
+    steps = (("neel_to_third", 0.0, 1.0 / 3.0, 2.0), ("third_to_fm", 1.0 / 3.0, 1.0, 5.0))
+    out = {"workload": f"SS Ising 18x18, J1 = J2 = 1, h in [0, {h_max}] ({n_h} points), {chains} chains each, "
+                       f"geometric anneal 5 -> T over {anneal} sweeps then {measure} measured sweeps at T",
+           "h": hs, "by_T": []}
+    for T in temps:
+        sched = np.concatenate([5.0 * (T / 5.0) ** (np.arange(anneal) / (anneal - 1)), np.full(measure, T)])
+        row = {"T": T}
+        for prec in ("q16", "fpga"):
+            insts = [crbm.Instance(L=18, J1=1.0, J2=1.0, h=h, n_chains=chains, sched="explicit", T_explicit=sched,
+                                   id=3000 + k) for k, h in enumerate(hs)]
+            smp = crbm.Sampler(insts, seed=SEED + 7, n_sweeps=anneal + measure, measure_every=1, burn_in=anneal,
+                               precision=prec)
+            smp.sample(anneal + measure)
+            obs = smp.observables()
+            m = [float(o["m"]) for o in obs]
+            smp.close()
+            trans = {}
+            for name, lo, hi, h_exact in steps:
+                mid = _crossing(hs, m, lo + 0.5 * (hi - lo))
+                a, b = _crossing(hs, m, lo + 0.1 * (hi - lo)), _crossing(hs, m, lo + 0.9 * (hi - lo))
+                trans[name] = {"h_exact": h_exact, "h_mid": mid, "width_10_90": None if a is None or b is None else b - a}
+            row[prec] = {"m": [round(x, 5) for x in m], "transitions": trans}
+        out["by_T"].append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -321,6 +365,8 @@ def main():
     ap.add_argument("--no-c5-mh", action="store_true", help="skip the conditional learned-MH comparison at 48x48")
     ap.add_argument("--c5-mh-96", action="store_true", help="also run the conditional learned-MH comparison at 96x96")
     ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution runs at the four phase points")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the m(h) comparison of the default and the hardware precision")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (--gpus 1): chains are independent, and sharding them over "
@@ -426,6 +472,8 @@ def main():
         result["scale"] = scale_gibbs(crbm, torch)
     if not args.no_tts:
         result["tts"] = tts_leg(crbm, torch)
+    if not args.no_precision:
+        result["precision"] = precision_leg(crbm, torch)
     if not args.no_mh:
         result["learned_mh"] = learned_mh(crbm, torch)
     if not args.no_c5_mh:
