@@ -299,6 +299,16 @@ int crbm_ar_logq(crbm_ar_t* a, const int8_t* spins_dev, int64_t n, double* logq_
  * into spins_dev (int8 [n][L][L]) with their log q into logq_dev (fp64 [n]). */
 int crbm_ar_sample(crbm_ar_t* a, int64_t n, uint64_t seed, int64_t step, uint32_t id, int8_t* spins_dev,
                    double* logq_dev);
+/* n_steps batches of n proposals in one launch (for an independent-MH
+ * proposal stream, whose draws do not depend on the chains): batch k, written
+ * at spins_dev + k n L^2 and logq_dev + k n (device int8 [n_steps][n][L][L],
+ * fp64 [n_steps][n]), equals crbm_ar_sample_cond(a, n, seed, step0 + k, id,
+ * points_dev, ...) bit for bit; points_dev (device int32 [n], or NULL for an
+ * unconditional network) is shared by all batches.  One launch of n n_steps
+ * chains keeps more SIMDs busy than n_steps launches of n.  CRBM_EINVAL for
+ * n < 1, n_steps < 1, n n_steps > 2^31 or NULL outputs. */
+int crbm_ar_sample_steps(crbm_ar_t* a, int64_t n, int32_t n_steps, uint64_t seed, int64_t step0, uint32_t id,
+                         const int32_t* points_dev, int8_t* spins_dev, double* logq_dev);
 /* n_cycles of: gibbs_per_mh Gibbs sweeps of h (crbm_sample), then one
  * independent MH step per chain with a's proposals; every instance of h must
  * have the network's L and a constant temperature, and h and a must use the
@@ -311,7 +321,11 @@ int crbm_ar_sample(crbm_ar_t* a, int64_t n, uint64_t seed, int64_t step, uint32_
  * (device, may be NULL): int32 (M, B1, B2) after each cycle, [n_cycles][chains][3].
  * order_trace (device, may be NULL): the plateau structure factor record of
  * crbm_sample_thinned after each cycle, same layout.
- * n_accepted (host, may be NULL): accepted moves (synchronises). */
+ * n_accepted (host, may be NULL): accepted moves (synchronises).
+ * The proposals of up to 8 cycles (at most 16384 proposals) are drawn in one
+ * sampler launch, as by crbm_ar_sample_steps; results do not depend on how
+ * cycles are grouped, or on how they are split over calls.
+ * CRBM_EUNSUPPORTED for a handle created with CRBM_PRECISION_FPGA. */
 int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_mh, int32_t* counts_trace,
                    int32_t* order_trace, int64_t* n_accepted);
 void crbm_ar_destroy(crbm_ar_t* a);

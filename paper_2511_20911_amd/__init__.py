@@ -126,6 +126,8 @@ def lib() -> ct.CDLL:
         L.crbm_ar_logq_cond.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p]
         L.crbm_ar_sample_cond.argtypes = [ct.c_void_p, ct.c_int64, ct.c_uint64, ct.c_int64, ct.c_uint32,
                                           ct.c_void_p, ct.c_void_p, ct.c_void_p]
+        L.crbm_ar_sample_steps.argtypes = [ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_uint64, ct.c_int64, ct.c_uint32,
+                                           ct.c_void_p, ct.c_void_p, ct.c_void_p]
         L.crbm_ar_destroy.argtypes = [ct.c_void_p]
         L.crbm_ar_destroy.restype = None
         L.crbm_tau_int.argtypes = [ct.c_void_p, ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int64,
@@ -428,6 +430,17 @@ class ARNet:
         lq = torch.empty(n, dtype=torch.float64, device="cuda")
         _check(lib().crbm_ar_sample_cond(self._h, n, seed, step, id, _points_ptr(points, n),
                                          ct.c_void_p(spins.data_ptr()), ct.c_void_p(lq.data_ptr())))
+        return spins, lq
+
+    def sample_steps(self, n: int, n_steps: int, seed: int, step0: int = 0, id: int = 0, points=None):
+        """n_steps batches of n proposals in one launch; batch k equals
+        sample(n, seed, step0 + k, id, points).  Returns spins [n_steps, n, L, L]
+        and log q [n_steps, n]."""
+        import torch
+        spins = torch.empty((n_steps, n, self.L, self.L), dtype=torch.int8, device="cuda")
+        lq = torch.empty((n_steps, n), dtype=torch.float64, device="cuda")
+        _check(lib().crbm_ar_sample_steps(self._h, n, n_steps, seed, step0, id, _points_ptr(points, n),
+                                          ct.c_void_p(spins.data_ptr()), ct.c_void_p(lq.data_ptr())))
         return spins, lq
 
 

@@ -827,6 +827,9 @@ __global__ void __launch_bounds__(256) score_fused_kernel(int64_t n, int L, cons
 // chain, id << 3 | 6)), drawn by the lane that holds the logit at the end of
 // the last layer; the logits go to logit_out for the log q sum.
 constexpr int kSeqMaxWaves = 4;
+// MH: proposals of several cycles per sampler launch, up to this many chains
+// (1024 wavefronts of 16 chains: one per SIMD) and this many cycles
+constexpr int64_t kMhBatchChains = 16384, kMhMaxBatch = 8;
 constexpr int kSeqPad = 16 * kSeqMaxWaves;  // the ring's chain count is a multiple of this
 constexpr int kSeqLdsBytes = NL * NT * C * C * 2 + NL * C * 4;  // weights, then the shared biases
 
@@ -848,7 +851,7 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
                                                   int npts, __bf16* __restrict__ ring,
                                                   const __bf16* __restrict__ zpad, int8_t* __restrict__ spins,
                                                   float* __restrict__ logit_out, uint64_t seed, uint32_t step,
-                                                  uint32_t id) {
+                                                  uint32_t id, int64_t n_step) {
     extern __shared__ __align__(16) unsigned char smem[];
     __bf16* wl = reinterpret_cast<__bf16*>(smem);                 // [NL][NT][C][C], rows swizzled
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -868,10 +871,14 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
     // = chain r16 of this wavefront; a lane's D values of half h are channels
     // 16 h + 4 kg .. + 3 of its chain.
     const int64_t gca = wbase + r16;  // the ring has npad >= grid size chains: padding rows have their own slots
+    // proposal gca of the launch is chain gca % n_step of batch gca / n_step:
+    // its random stream, and its point, are those of a launch of that batch alone
+    const int64_t gcr = gca % n_step;
+    const uint32_t stepr = step + (uint32_t)(gca / n_step);
     const int N = L * L;
     // this lane's chain's bias rows (padding chains read the last chain's)
     const float* bl =
-        PER_CHAIN ? bias_tab + (int64_t)clamp_point(pt[gca < n ? gca : n - 1], npts) * kCondOut : bsh;
+        PER_CHAIN ? bias_tab + (int64_t)clamp_point(pt[gca < n ? gcr : (n - 1) % n_step], npts) * kCondOut : bsh;
     // Ring element (layer, chain, column, channel): [NL][npad][L][C], one row
     // per chain and layer.  Site (r, c) writes column c after the row above's
     // column c was last read (as the (-1,+1) tap of site (r, c - 1)), so the
@@ -932,7 +939,7 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
 #pragma unroll
             for (int l = 0; l < NL; ++l) left[l] = zero8();
         }
-        const gk::P4 q = gk::philox((uint32_t)site, step, (uint32_t)gca, (id << 3) | 6u, (uint32_t)seed,
+        const gk::P4 q = gk::philox((uint32_t)site, stepr, (uint32_t)gcr, (id << 3) | 6u, (uint32_t)seed,
                                     (uint32_t)(seed >> 32));
         const float u = (float)(q.v[0] >> 8) * (1.0f / 16777216.0f);
 #pragma unroll
@@ -1193,15 +1200,19 @@ struct crbm_ar_s {
     int32_t* mh_ci = nullptr;   // [chains]: instance (= point) of each chain
     MhTarget* mh_tg = nullptr;  // [kCondMaxPoints or instances]: per-instance targets
     int mh_tgcap = 0;
-    int8_t *cur = nullptr, *prop = nullptr;
+    int8_t* cur = nullptr;
     int32_t *ccur = nullptr, *cprop = nullptr;
-    double *lqc = nullptr, *lqp = nullptr;
+    double* lqc = nullptr;
     unsigned long long* nacc = nullptr;
+    // proposals of up to mh_kcap cycles of mh_kn chains: [cycle][chain][N] and [cycle][chain]
+    int64_t mh_kcap = 0, mh_kn = 0;
+    int8_t* mh_prop = nullptr;
+    double* mh_lqp = nullptr;
     ~crbm_ar_s() {
         void* ps[] = {theta, grad, m, v, bias, wf, wb, hs, mask, logit, g32, dh0, dh1, dz, g, logq, part, dW, bpart,
                       part2, xt, dzt,
-                      spins_copy, ring, slogit, zpad, ih0, ih1, ilogit, cur, prop, ccur, cprop, lqc, lqp, nacc,
-                      feats, cb, gs, gp, mh_ci, mh_tg};
+                      spins_copy, ring, slogit, zpad, ih0, ih1, ilogit, cur, ccur, cprop, lqc, nacc,
+                      feats, cb, gs, gp, mh_ci, mh_tg, mh_prop, mh_lqp};
         for (void* p : ps)
             if (p) (void)hipFree(p);
     }
@@ -1366,8 +1377,10 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
 }
 
 // ancestral sampling of n configurations (spins and their log q)
+// n proposals in batches of n_step (n a multiple of n_step): batch k is keyed
+// as step + k and is conditioned on pt[0 .. n_step)
 int run_seq(crbm_ar_t* a, int64_t n, int8_t* spins, double* logq, uint64_t seed, uint32_t step, uint32_t id,
-            const int32_t* pt) {
+            const int32_t* pt, int64_t n_step) {
     const BiasSel bs = bias_sel(a, pt);
     int rc = ensure_seq(a, n);
     if (rc != CRBM_OK) return rc;
@@ -1385,13 +1398,13 @@ int run_seq(crbm_ar_t* a, int64_t n, int8_t* spins, double* logq, uint64_t seed,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, kSeqLdsBytes),
                "sampler LDS size");
         hipLaunchKernelGGL(seq_kernel<true>, grid, block, kSeqLdsBytes, st, n, npad, L, a->wf, bs.tab, bs.pt,
-                           bs.npts, a->ring, a->zpad, spins, a->slogit, seed, step, id);
+                           bs.npts, a->ring, a->zpad, spins, a->slogit, seed, step, id, n_step);
     } else {
         AR_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&seq_kernel<false>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, kSeqLdsBytes),
                "sampler LDS size");
         hipLaunchKernelGGL(seq_kernel<false>, grid, block, kSeqLdsBytes, st, n, npad, L, a->wf, bs.tab, bs.pt,
-                           bs.npts, a->ring, a->zpad, spins, a->slogit, seed, step, id);
+                           bs.npts, a->ring, a->zpad, spins, a->slogit, seed, step, id, n_step);
     }
     hipLaunchKernelGGL(logq_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->slogit, spins, n, L * L,
                        logq);
@@ -1641,12 +1654,21 @@ int crbm_ar_sample_cond(crbm_ar_t* a, int64_t n, uint64_t seed, int64_t step, ui
     if (!a || !spins_dev || !logq_dev || n < 1) return fail_ar(CRBM_EINVAL, "bad arguments");
     const int rc = need_points(a);
     if (rc != CRBM_OK) return rc;
-    return run_seq(a, n, spins_dev, logq_dev, seed, (uint32_t)step, id, points_dev);
+    return run_seq(a, n, spins_dev, logq_dev, seed, (uint32_t)step, id, points_dev, n);
 }
 
 int crbm_ar_sample(crbm_ar_t* a, int64_t n, uint64_t seed, int64_t step, uint32_t id, int8_t* spins_dev,
                    double* logq_dev) {
     return crbm_ar_sample_cond(a, n, seed, step, id, nullptr, spins_dev, logq_dev);
+}
+
+int crbm_ar_sample_steps(crbm_ar_t* a, int64_t n, int32_t n_steps, uint64_t seed, int64_t step0, uint32_t id,
+                         const int32_t* points_dev, int8_t* spins_dev, double* logq_dev) {
+    if (!a || !spins_dev || !logq_dev || n < 1 || n_steps < 1 || n > ((int64_t)1 << 31) / n_steps)
+        return fail_ar(CRBM_EINVAL, "bad arguments");
+    const int rc = need_points(a);
+    if (rc != CRBM_OK) return rc;
+    return run_seq(a, n * n_steps, spins_dev, logq_dev, seed, (uint32_t)step0, id, points_dev, n);
 }
 
 void crbm_ar_destroy(crbm_ar_t* a) {
@@ -1682,12 +1704,12 @@ int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_
     }
     hipStream_t st = a->stream;
     if (n > a->mcap) {
-        void* ps[] = {a->cur, a->prop, a->ccur, a->cprop, a->lqc, a->lqp, a->nacc, a->mh_ci};
+        void* ps[] = {a->cur, a->ccur, a->cprop, a->lqc, a->nacc, a->mh_ci};
         for (void* p : ps)
             if (p) (void)hipFree(p);
         a->mh_ci = nullptr;
-        if (alloc(&a->cur, n * N) || alloc(&a->prop, n * N) || alloc(&a->ccur, n * 3) || alloc(&a->cprop, n * 3) ||
-            alloc(&a->lqc, n) || alloc(&a->lqp, n) || alloc(&a->nacc, 1) || alloc(&a->mh_ci, n)) {
+        if (alloc(&a->cur, n * N) || alloc(&a->ccur, n * 3) || alloc(&a->cprop, n * 3) || alloc(&a->lqc, n) ||
+            alloc(&a->nacc, 1) || alloc(&a->mh_ci, n)) {
             a->mcap = 0;
             return fail_ar(CRBM_ENOMEM, "MH buffers");
         }
@@ -1719,6 +1741,25 @@ int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_
     const int32_t* pts = a->cond > 0 ? a->mh_ci : nullptr;  // chain i of instance k is conditioned on point k
     AR_TRY(hipMemsetAsync(a->nacc, 0, sizeof(unsigned long long), st), "zero counter");
     const unsigned nb = (unsigned)((n + 255) / 256);
+    // Proposals do not depend on the chains, so the sampler draws those of
+    // up to kb cycles in one launch: enough wavefronts (16 chains each) for
+    // one per SIMD, where one cycle's alone would leave SIMDs idle.  Each
+    // cycle's proposals keep their own step in the random stream, so the
+    // results do not depend on kb.
+    const int64_t kb = std::max<int64_t>(1, std::min<int64_t>(kMhBatchChains / n, kMhMaxBatch));
+    if (kb > a->mh_kcap || n > a->mh_kn) {
+        if (a->mh_prop) (void)hipFree(a->mh_prop);
+        if (a->mh_lqp) (void)hipFree(a->mh_lqp);
+        a->mh_prop = nullptr;
+        a->mh_lqp = nullptr;
+        if (alloc(&a->mh_prop, kb * n * N) || alloc(&a->mh_lqp, kb * n)) {
+            a->mh_kcap = a->mh_kn = 0;
+            return fail_ar(CRBM_ENOMEM, "MH proposal buffers");
+        }
+        a->mh_kcap = kb;
+        a->mh_kn = n;
+    }
+    int64_t batch_first = 0, batch_len = 0;  // cycles whose proposals are in the buffers
     for (int64_t cyc = 0; cyc < n_cycles; ++cyc) {
         if (gibbs_per_mh > 0) {
             const int rc = crbm_sample(h, gibbs_per_mh, nullptr, nullptr);
@@ -1734,13 +1775,19 @@ int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_
             rc = run_score(a, n, a->cur, a->lqc, pts);
             if (rc != CRBM_OK) return rc;
         }
+        if (cyc >= batch_first + batch_len) {
+            batch_first = cyc;
+            batch_len = std::min<int64_t>(kb, n_cycles - cyc);
+            rc = run_seq(a, batch_len * n, a->mh_prop, a->mh_lqp, v.seed, (uint32_t)a->mh_step, v.id, pts, n);
+            if (rc != CRBM_OK) return rc;
+        }
         const uint32_t step = (uint32_t)(a->mh_step++);
-        rc = run_seq(a, n, a->prop, a->lqp, v.seed, step, v.id, pts);
-        if (rc != CRBM_OK) return rc;
-        hipLaunchKernelGGL(counts_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->prop, n, v.L, a->cprop,
+        int8_t* prop = a->mh_prop + (cyc - batch_first) * n * N;
+        double* lqp = a->mh_lqp + (cyc - batch_first) * n;
+        hipLaunchKernelGGL(counts_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, prop, n, v.L, a->cprop,
                            (int32_t*)nullptr);
-        hipLaunchKernelGGL(mh_kernel, dim3(nb), dim3(256), 0, st, n, v.L, a->cur, a->prop, a->ccur, a->cprop, a->lqc,
-                           a->lqp, a->mh_tg, a->mh_ci, v.seed, step, v.id, a->nacc);
+        hipLaunchKernelGGL(mh_kernel, dim3(nb), dim3(256), 0, st, n, v.L, a->cur, prop, a->ccur, a->cprop, a->lqc,
+                           lqp, a->mh_tg, a->mh_ci, v.seed, step, v.id, a->nacc);
         AR_TRY(launch_pack(v.state, a->cur, n, v.L, st), "pack state");
         if (order_trace)  // recounts the current states (same counts) with the structure factor
             hipLaunchKernelGGL(counts_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->cur, n, v.L,

@@ -237,3 +237,40 @@ def test_full_size_proposals_18x18():
         u = np.array([(int(oracle.philox([i, 5, ch, 6], [99, 0])[0]) >> 8) / 16777216.0 for i in range(L * L)])
         agree = (sn[k].reshape(-1) == 1) == (u < p[k])
         assert np.all(agree | (np.abs(u - p[k]) < 1e-3)), ch
+
+
+@pytest.mark.parametrize("L,n,steps", [(6, 40, 3), (18, 17, 2), (6, 8192, 2)])
+def test_sample_steps_equal_separate_calls(L, n, steps):
+    """crbm_ar_sample_steps: batch k of one launch equals a launch of that batch
+    alone with step step0 + k, bit for bit (spins and log q), for ragged
+    batches and for the 16384-proposal launch of two 8192-chain MH cycles."""
+    print(f"case L={L} n={n} steps={steps}", flush=True)
+    net = crbm.ARNet(L)
+    net.set_params(flatten(ar.init_params(seed=17, scale=INIT_SCALE)))
+    s, lq = net.sample_steps(n, steps, seed=0x51, step0=9, id=3)
+    for k in range(steps):
+        s1, lq1 = net.sample(n, seed=0x51, step=9 + k, id=3)
+        assert torch.equal(s[k], s1) and torch.equal(lq[k], lq1), k
+
+
+def test_mh_cycles_do_not_depend_on_batching():
+    """One call of 5 MH cycles (proposals drawn together) equals 5 calls of one
+    cycle each: same accepted count, same traces, same final states."""
+    L, n = 4, 64
+
+    def run(split):
+        net = _trained_net(L, 1.0, 3.0, 0.5, steps=40)
+        inst = crbm.Instance(L=L, J1=1.0, J2=1.0, h=3.0, n_chains=n, sched="const", T0=0.5, id=3)
+        smp = crbm.Sampler([inst], seed=12, n_sweeps=100)
+        tr = torch.empty((5, n, 3), dtype=torch.int32, device="cuda")
+        if split:
+            acc = sum(crbm.sample_mh(smp, net, 1, 2, trace=tr[k:k + 1]) for k in range(5))
+        else:
+            acc = crbm.sample_mh(smp, net, 5, 2, trace=tr)
+        st, _ = smp.get_state()
+        return acc, tr.cpu().numpy(), st.cpu().numpy()
+
+    a1, t1, s1 = run(False)
+    a2, t2, s2 = run(True)
+    assert a1 == a2 and np.array_equal(t1, t2) and np.array_equal(s1, s2)
+    assert a1 > 0

@@ -267,3 +267,16 @@ def test_mh_handle_checks():
     other_L = crbm.ARNet(6)
     single = crbm.Sampler([crbm.Instance(L=L, n_chains=8, T0=1.0, id=0)], seed=1, n_sweeps=10)
     assert _code(lambda: crbm.sample_mh(single, other_L, 1, 0)) == crbm.CRBM_EINVAL
+
+
+def test_cond_sample_steps_equal_separate_calls():
+    """Batched proposals of a conditional network (every batch on the same
+    per-chain points) equal separate launches bit for bit."""
+    base, c = _cond_params(77)
+    net = _net(6, base, c)
+    n = 40
+    idx = _pts((np.arange(n) * 5) % 3)
+    s, lq = net.sample_steps(n, 3, seed=8, step0=4, id=1, points=idx)
+    for k in range(3):
+        s1, lq1 = net.sample(n, seed=8, step=4 + k, id=1, points=idx)
+        assert torch.equal(s[k], s1) and torch.equal(lq[k], lq1), k
