@@ -173,85 +173,74 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
     }
 }
 
-// Weight-gradient operands in channel-major form.  For each tap t of the
-// layer, the layer input shifted by the tap (zero outside the lattice), and
-// the output gradient, each as [channel][Ppad] bf16 (Ppad = P rounded up to
-// kTP, padding zero), transposed through an LDS tile of kTP pixels.  The
-// contraction over pixels then reads 16-byte runs of consecutive pixels.
-constexpr int kTP = 64;
-constexpr int kTRow = kTP + 8;  // LDS row stride (16-byte aligned rows)
-
-__global__ void __launch_bounds__(256) transpose_taps_kernel(const __bf16* __restrict__ in,
-                                                             const __bf16* __restrict__ dz, Taps taps, int L,
-                                                             int64_t P, int64_t Ppad, __bf16* __restrict__ xt,
-                                                             __bf16* __restrict__ dzt) {
-    __shared__ __align__(16) __bf16 tl[(NT + 1) * C * kTRow];  // slots 0..NT-1 taps, slot NT the gradient
-    const int tid = threadIdx.x;
-    const int64_t p0 = (int64_t)blockIdx.x * kTP;
-    const int px = tid >> 2, grp = tid & 3;
-    const int64_t p = p0 + px;
-    {
-        const bf16x8 v = (p < P) ? load8(dz + p * C + grp * 8) : zero8();
-#pragma unroll
-        for (int e = 0; e < 8; ++e) tl[(NT * C + grp * 8 + e) * kTRow + px] = v[e];
-    }
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        if (t >= taps.n) break;
-        const int64_t q = (p < P) ? shift_pixel(p, taps.dr[t], taps.dc[t], L) : -1;
-        const bf16x8 v = (q >= 0) ? load8(in + q * C + grp * 8) : zero8();
-#pragma unroll
-        for (int e = 0; e < 8; ++e) tl[(t * C + grp * 8 + e) * kTRow + px] = v[e];
-    }
-    __syncthreads();
-    constexpr int kSeg = kTP / 8;
-    const int nrows = (taps.n + 1) * C;
-    for (int k = tid; k < nrows * kSeg; k += blockDim.x) {
-        const int row = k / kSeg, seg = k - (k / kSeg) * kSeg;
-        const int slot = row / C, ch = row - slot * C;
-        const bool grad = slot == taps.n;
-        const bf16x8 v = *reinterpret_cast<const bf16x8*>(tl + ((grad ? NT : slot) * C + ch) * kTRow + seg * 8);
-        __bf16* dst = grad ? dzt + (int64_t)ch * Ppad : xt + ((int64_t)slot * C + ch) * Ppad;
-        *reinterpret_cast<bf16x8*>(dst + p0 + seg * 8) = v;
-    }
-}
-
-// Partial weight gradients from the channel-major operands, one wavefront per
-// chunk of kWChunk pixels, all taps at once (they share the gradient operand):
-//   part[chunk][t][i][j] = sum_{p in chunk} xt[t][i][p] dzt[j][p]
+// Partial weight gradients, one chunk of kWChunk pixels each, all taps at once
+// (they share the gradient operand):
+//   part[chunk][t][i][j] = sum_{p in chunk} in[p + tap_t][i] dz[p][j]
 // (A row i = input channel, k = pixel; B column j = output channel).
 constexpr int kWChunk = 512;
 
-__global__ void __launch_bounds__(256) wgrad_kernel(const __bf16* __restrict__ xt, const __bf16* __restrict__ dzt,
-                                                    int ntaps, int64_t Ppad, int nchunks, float* __restrict__ part) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (wid >= (int64_t)nchunks) return;
+// One single-wavefront workgroup per chunk stages 32-pixel tiles of the
+// pixel-major layer input, shifted by each tap (zero outside the lattice), and
+// of the gradient through LDS in channel-major form (the matrix-core operands
+// need consecutive pixels per channel) and contracts them on the matrix cores.
+// No channel-major copy goes through HBM.
+constexpr int kFT = 32;           // pixels per staged tile (two 16-pixel k-steps)
+constexpr int kFRow = kFT + 8;    // LDS row stride in elements (80 bytes: 16-byte aligned rows)
+
+__global__ void __launch_bounds__(64) wgrad_fused_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ dz,
+                                                         Taps taps, int L, int64_t P, float* __restrict__ part) {
+    __shared__ __align__(16) __bf16 tl[(NT + 1) * C * kFRow];  // slots 0..NT-1 taps, slot NT the gradient
+    const int lane = threadIdx.x;
     const int li = lane & 31, half = lane >> 5;
-    const int64_t k_begin = wid * kWChunk;
-    const int64_t k_end = (k_begin + kWChunk < Ppad) ? k_begin + kWChunk : Ppad;
+    const int px = lane >> 1, hc = lane & 1;  // staging: pixel of the tile, channel half
+    const int64_t chunk = blockIdx.x;
+    const int64_t k_begin = chunk * kWChunk;
+    const int64_t k_end = (k_begin + kWChunk < P) ? k_begin + kWChunk : P;
     f32x16 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[t][v] = 0.f;
-    const __bf16* brow = dzt + (int64_t)li * Ppad + half * 8;
-    for (int64_t k0 = k_begin; k0 < k_end; k0 += 16) {
-        const bf16x8 b = load8(brow + k0);
+    for (int64_t p0 = k_begin; p0 < k_end; p0 += kFT) {
+        const int64_t p = p0 + px;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            const bf16x8 v = (p < P) ? load8(dz + p * C + hc * 16 + hh * 8) : zero8();
+#pragma unroll
+            for (int e = 0; e < 8; ++e) tl[(NT * C + hc * 16 + hh * 8 + e) * kFRow + px] = v[e];
+        }
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            if (t >= ntaps) break;
-            const bf16x8 a = load8(xt + ((int64_t)t * C + li) * Ppad + half * 8 + k0);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+            if (t >= taps.n) break;
+            const int64_t q = (p < P) ? shift_pixel(p, taps.dr[t], taps.dc[t], L) : -1;
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const bf16x8 v = (q >= 0) ? load8(in + q * C + hc * 16 + hh * 8) : zero8();
+#pragma unroll
+                for (int e = 0; e < 8; ++e) tl[(t * C + hc * 16 + hh * 8 + e) * kFRow + px] = v[e];
+            }
         }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kFT / 16; ++ks) {
+            const int col = ks * 16 + half * 8;
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(tl + (NT * C + li) * kFRow + col);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                if (t >= taps.n) break;
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(tl + (t * C + li) * kFRow + col);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+            }
+        }
+        __syncthreads();
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        if (t >= ntaps) break;
+        if (t >= taps.n) break;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int i = 8 * (v >> 2) + 4 * half + (v & 3);
-            part[(((int64_t)wid * NT + t) * C + i) * C + li] = acc[t][v];
+            part[((chunk * NT + t) * C + i) * C + li] = acc[t][v];
         }
     }
 }
@@ -1184,7 +1173,6 @@ struct crbm_ar_s {
     double* logq = nullptr;     // [B]
     float *part = nullptr, *dW = nullptr, *bpart = nullptr;
     double* part2 = nullptr;                // [kRedSlices][NT][C][C]
-    __bf16 *xt = nullptr, *dzt = nullptr;   // [NT][C][Ppad], [C][Ppad]: channel-major weight-gradient operands
     int8_t* spins_copy = nullptr;
     // sequential sampler buffers (capacity in chains)
     int64_t scap = 0;
@@ -1210,7 +1198,7 @@ struct crbm_ar_s {
     double* mh_lqp = nullptr;
     ~crbm_ar_s() {
         void* ps[] = {theta, grad, m, v, bias, wf, wb, hs, mask, logit, g32, dh0, dh1, dz, g, logq, part, dW, bpart,
-                      part2, xt, dzt,
+                      part2,
                       spins_copy, ring, slogit, zpad, ih0, ih1, ilogit, cur, ccur, cprop, lqc, nacc,
                       feats, cb, gs, gp, mh_ci, mh_tg, mh_prop, mh_lqp};
         for (void* p : ps)
@@ -1233,25 +1221,24 @@ hipError_t alloc(T** p, int64_t n) {
     return hipMalloc((void**)p, sizeof(T) * (size_t)(n > 0 ? n : 1));
 }
 
-int64_t padded_pixels(int64_t P) { return (P + kTP - 1) / kTP * kTP; }
+// weight-gradient chunks of a batch of P pixels
+int64_t wgrad_chunks(int64_t P) { return (P + kWChunk - 1) / kWChunk; }
 
 int ensure_train(crbm_ar_t* a, int64_t B) {
     if (B <= a->tcap) return CRBM_OK;
     void* ps[] = {a->hs, a->mask, a->logit, a->g32, a->dh0, a->dh1, a->dz, a->g, a->logq, a->part, a->bpart,
-                  a->spins_copy, a->part2, a->xt, a->dzt, a->gs};
+                  a->spins_copy, a->part2, a->gs};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     a->part2 = nullptr;
-    a->xt = a->dzt = nullptr;
     a->gs = nullptr;
-    const int64_t P = B * a->L * a->L, Ppad = padded_pixels(P);
-    const int64_t nch = (Ppad + kWChunk - 1) / kWChunk;
+    const int64_t P = B * a->L * a->L;
+    const int64_t nch = wgrad_chunks(P);
     if (alloc(&a->hs, (int64_t)NL * P * C) || alloc(&a->mask, (int64_t)(NL - 1) * P * C) || alloc(&a->logit, P) ||
         alloc(&a->g32, P) || alloc(&a->dh0, P * C) || alloc(&a->dh1, P * C) || alloc(&a->dz, P * C) ||
         alloc(&a->g, P * C) || alloc(&a->logq, B) || alloc(&a->part, nch * NT * C * C) ||
         alloc(&a->bpart, (int64_t)4096 * C) || alloc(&a->spins_copy, P) ||
-        alloc(&a->part2, (int64_t)kRedSlices * NT * C * C) || alloc(&a->xt, (int64_t)NT * C * Ppad) ||
-        alloc(&a->dzt, (int64_t)C * Ppad) || (a->cond > 0 && alloc(&a->gs, B * kCondOut))) {
+        alloc(&a->part2, (int64_t)kRedSlices * NT * C * C) || (a->cond > 0 && alloc(&a->gs, B * kCondOut))) {
         a->tcap = 0;
         return fail_ar(CRBM_ENOMEM, "training buffers");
     }
@@ -1323,8 +1310,7 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
     }
     hipLaunchKernelGGL(loss_kernel, dim3((unsigned)B), dim3(256), 0, st, a->logit, spins, L, 1.0f / (float)B, a->logq,
                        a->g, a->g32);
-    const int64_t Ppad = padded_pixels(P);
-    const int nch = (int)((Ppad + kWChunk - 1) / kWChunk);
+    const int nch = (int)wgrad_chunks(P);
     float* dh = a->dh0;
     float* dh_alt = a->dh1;
     for (int l = NL - 1; l >= 0; --l) {
@@ -1347,10 +1333,8 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
             hipLaunchKernelGGL(sample_bias_grad_kernel, dim3((unsigned)B), dim3(256), 0, st, dh,
                                a->mask + (size_t)(l < NL - 1 ? l : 0) * LSZ, l == NL - 1 ? a->g32 : nullptr, L * L,
                                l, a->gs);
-        hipLaunchKernelGGL(transpose_taps_kernel, dim3((unsigned)(Ppad / kTP)), dim3(256), 0, st,
-                           a->hs + (size_t)l * LSZ, dzl, tp, L, P, Ppad, a->xt, a->dzt);
-        hipLaunchKernelGGL(wgrad_kernel, dim3((unsigned)((nch + 3) / 4)), dim3(256), 0, st, a->xt, a->dzt, tp.n, Ppad,
-                           nch, a->part);
+        hipLaunchKernelGGL(wgrad_fused_kernel, dim3((unsigned)nch), dim3(64), 0, st, a->hs + (size_t)l * LSZ, dzl, tp,
+                           L, P, a->part);
         hipLaunchKernelGGL(reduce_slices_kernel, dim3((NT * C * C + 255) / 256, kRedSlices), dim3(256), 0, st,
                            a->part, nch, NT * C * C, a->part2);
         hipLaunchKernelGGL(reduce_final_kernel, dim3((NT * C * C + 255) / 256), dim3(256), 0, st, a->part2,
