@@ -275,10 +275,13 @@ __device__ __forceinline__ void hidden_row(const uint32_t (&top)[Geo<L>::W], con
             const int off = 2 * n * p;
             uint32_t pair = DP[off >> 5] >> (off & 31);
             if ((off & 31) + 2 * n > 32) pair |= DP[(off >> 5) + 1] << (32 - (off & 31));
-            const uint32_t d0 = pair & E, d1 = (pair >> 1) & E;
-            // sign of the field: s_a for agreeing bonds, +1 for a zero field
-            H[2 * p][w] = (((ea[2 * p] & A[2 * p]) | ~A[2 * p]) & E) ^ d0;
-            H[2 * p + 1][w] = (((ea[2 * p + 1] & A[2 * p + 1]) | ~A[2 * p + 1]) & E) ^ d1;
+            // sign of the field (s_a for agreeing bonds, +1 for a zero field),
+            // flipped where the unit went against it.  Only the cells' even
+            // columns are meaningful: the other bits are left as they fall,
+            // because every consumer of H masks with the even-column mask and
+            // column shifts move bits by even amounts.
+            H[2 * p][w] = (ea[2 * p] | ~A[2 * p]) ^ pair;
+            H[2 * p + 1][w] = (ea[2 * p + 1] | ~A[2 * p + 1]) ^ (pair >> 1);
         }
     }
 }
