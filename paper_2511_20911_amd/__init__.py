@@ -437,6 +437,8 @@ class ARNet:
         sample(n, seed, step0 + k, id, points).  Returns spins [n_steps, n, L, L]
         and log q [n_steps, n]."""
         import torch
+        if n < 1 or n_steps < 1:  # the library's own argument error
+            _check(lib().crbm_ar_sample_steps(self._h, n, n_steps, seed, step0, id, None, None, None))
         spins = torch.empty((n_steps, n, self.L, self.L), dtype=torch.int8, device="cuda")
         lq = torch.empty((n_steps, n), dtype=torch.float64, device="cuda")
         _check(lib().crbm_ar_sample_steps(self._h, n, n_steps, seed, step0, id, _points_ptr(points, n),

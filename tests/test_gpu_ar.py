@@ -279,3 +279,25 @@ def test_mh_cycles_do_not_depend_on_batching():
     a2, t2, s2 = run(True)
     assert a1 == a2 and np.array_equal(t1, t2) and np.array_equal(s1, s2)
     assert a1 > 0
+
+
+def test_batched_sampler_and_mh_edge_cases():
+    """crbm_ar_sample_steps rejects empty requests; zero MH cycles accept
+    nothing and leave the state as it was; a one-chain handle runs."""
+    net = crbm.ARNet(6)
+    net.set_params(flatten(ar.init_params(seed=3, scale=INIT_SCALE)))
+    for n, k in ((0, 2), (4, 0), (-1, 1)):
+        with pytest.raises(crbm.CrbmError) as e:
+            net.sample_steps(n, k, seed=1)
+        assert e.value.code == crbm.CRBM_EINVAL, (n, k)
+    inst = crbm.Instance(L=6, J1=1.0, J2=1.0, h=3.0, n_chains=1, sched="const", T0=0.5, id=4)
+    smp = crbm.Sampler([inst], seed=2, n_sweeps=50)
+    smp.sample(5)
+    before, _ = smp.get_state()
+    assert crbm.sample_mh(smp, net, 0, 3) == 0
+    after, _ = smp.get_state()
+    assert torch.equal(before, after)
+    tr = torch.empty((3, 1, 3), dtype=torch.int32, device="cuda")
+    crbm.sample_mh(smp, net, 3, 1, trace=tr)
+    st, _ = smp.get_state()
+    assert tuple(tr[-1, 0].cpu().numpy().astype(int)) == oracle.counts(6, st.cpu().numpy().reshape(6, 6))
