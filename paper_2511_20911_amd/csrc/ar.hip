@@ -91,6 +91,21 @@ __device__ __forceinline__ int64_t shift_pixel(int64_t p, int dr, int dc, int L)
     return b * LL + (int64_t)r * L + c;
 }
 
+// A point index clamped to the points that exist.
+__device__ __forceinline__ int clamp_point(int q, int npts) { return q < 0 ? 0 : (q >= npts ? npts - 1 : q); }
+
+// Orders this wavefront's LDS writes before its later LDS reads of other
+// lanes' data: a wavefront's LDS accesses execute in issue order, so only the
+// compiler has to be kept from moving them (no workgroup barrier: the
+// wavefronts of a workgroup loop over different numbers of tiles).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kOutRow = 33;  // LDS row stride (floats) of a staged output tile: the two lane halves hit different banks
+
 // Epilogue modes of the generic conv kernel.
 enum { EP_RELU = 0, EP_RESID = 1, EP_LOGIT = 2, EP_DGRAD = 3, EP_DGRAD_RESID = 4 };
 
@@ -111,6 +126,8 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int li = lane & 31, half = lane >> 5;
+    __shared__ float tile_out[4][32 * kOutRow];  // one output tile per wavefront (4 per workgroup)
+    float* T = tile_out[threadIdx.x >> 6];
     // B fragments stay in registers for the whole launch
     bf16x8 Bf[NT][2];
 #pragma unroll
@@ -137,39 +154,67 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, Bf[t][kh], acc, 0, 0, 0);
             }
         }
-        // D[i][j]: j = lane & 31, i = 8 (v / 4) + 4 half + (v % 4)
+        if (mode == EP_LOGIT) {
+            // D[i][j]: j = lane & 31, i = 8 (v / 4) + 4 half + (v % 4); only channel 0 is the logit
+            if (li == 0)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int i = 8 * (v >> 2) + 4 * half + (v & 3);
-            const int64_t pi = tile * 32 + i;
-            if (pi >= P) continue;
-            float bv = bj;
-            if (pt && !dgrad) {
-                const int q = pt[pi / LL];
-                bv = bias[(int64_t)(q < 0 ? 0 : (q >= npts ? npts - 1 : q)) * kCondOut + li];
-            }
-            const float z = acc[v] + bv;
-            const int64_t o = pi * C + li;
-            switch (mode) {
-                case EP_RELU:
-                    out_bf[o] = f2bf(z > 0.f ? z : 0.f);
-                    if (out_mask) out_mask[o] = z > 0.f;
-                    break;
-                case EP_RESID:
-                    out_bf[o] = f2bf(bf2f(resid_bf[o]) + (z > 0.f ? z : 0.f));
-                    if (out_mask) out_mask[o] = z > 0.f;
-                    break;
-                case EP_LOGIT:
-                    if (li == 0) out_f[pi] = z;
-                    break;
-                case EP_DGRAD:
-                    out_f[o] = z;
-                    break;
-                default:  // EP_DGRAD_RESID
-                    out_f[o] = z + resid_f[o];
-                    break;
+                for (int v = 0; v < 16; ++v) {
+                    const int i = 8 * (v >> 2) + 4 * half + (v & 3);
+                    const int64_t pi = tile * 32 + i;
+                    if (pi >= P) continue;
+                    float bv = bj;
+                    if (pt) bv = bias[(int64_t)clamp_point(pt[pi / LL], npts) * kCondOut];
+                    out_f[pi] = acc[v] + bv;
+                }
+            continue;
+        }
+        // The tile's 32 pixels x 32 channels are one contiguous block of the
+        // pixel-major output: pass the accumulators through this wavefront's
+        // LDS rows so that each lane then owns 16 consecutive elements (one
+        // pixel, half its channels) and moves them with 16-byte accesses.
+#pragma unroll
+        for (int v = 0; v < 16; ++v) T[(8 * (v >> 2) + 4 * half + (v & 3)) * kOutRow + li] = acc[v];
+        wave_sync();
+        const int64_t pi = tile * 32 + (lane >> 1);
+        const int c0 = (lane & 1) * 16;
+        if (pi < P) {
+            const float* br = dgrad ? nullptr : (pt ? bias + (int64_t)clamp_point(pt[pi / LL], npts) * kCondOut : bias);
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {  // two runs of 8 channels keep fewer values live
+                const int cb = c0 + 8 * hh;
+                float z[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) z[e] = T[(lane >> 1) * kOutRow + cb + e] + (dgrad ? 0.f : br[cb + e]);
+                const int64_t o = pi * C + cb;
+                if (mode == EP_RELU || mode == EP_RESID) {
+                    const bf16x8 r = mode == EP_RESID ? load8(resid_bf + o) : zero8();
+                    bf16x8 ob;
+                    uint32_t mk[2] = {0u, 0u};
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const float y = z[e] > 0.f ? z[e] : 0.f;
+                        ob[e] = f2bf(mode == EP_RESID ? bf2f(r[e]) + y : y);
+                        mk[e >> 2] |= (uint32_t)(z[e] > 0.f) << (8 * (e & 3));
+                    }
+                    *reinterpret_cast<bf16x8*>(out_bf + o) = ob;
+                    if (out_mask) *reinterpret_cast<uint2*>(out_mask + o) = make_uint2(mk[0], mk[1]);
+                } else {  // EP_DGRAD, EP_DGRAD_RESID
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        float4 d = make_float4(z[4 * q], z[4 * q + 1], z[4 * q + 2], z[4 * q + 3]);
+                        if (mode == EP_DGRAD_RESID) {
+                            const float4 r = *reinterpret_cast<const float4*>(resid_f + o + 4 * q);
+                            d.x += r.x;
+                            d.y += r.y;
+                            d.z += r.z;
+                            d.w += r.w;
+                        }
+                        *reinterpret_cast<float4*>(out_f + o + 4 * q) = d;
+                    }
+                }
             }
         }
+        wave_sync();  // the rows are rewritten by the next tile
     }
 }
 
@@ -366,7 +411,6 @@ __global__ void __launch_bounds__(256) colsum0_kernel(const float* g32, int64_t 
 // W1 [kCondF][kCondH], b1 [kCondH], W2 [kCondH][NL][C].  The inference and
 // training kernels read the per-point table cb[p][l][c] = bias[l][c] + g(x_p).
 
-__device__ __forceinline__ int clamp_point(int q, int npts) { return q < 0 ? 0 : (q >= npts ? npts - 1 : q); }
 
 // one workgroup (kCondOut threads) per point
 __global__ void __launch_bounds__(kCondOut) cond_bias_kernel(const float* __restrict__ mlp,
@@ -821,14 +865,6 @@ constexpr int kSeqMaxWaves = 4;
 constexpr int64_t kMhBatchChains = 16384, kMhMaxBatch = 8;
 constexpr int kSeqPad = 16 * kSeqMaxWaves;  // the ring's chain count is a multiple of this
 constexpr int kSeqLdsBytes = NL * NT * C * C * 2 + NL * C * 4;  // weights, then the shared biases
-
-// keeps the compiler from moving this wavefront's memory accesses across it
-// (its memory operations complete in order, so no instruction is needed)
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // bias_tab: the bias table (rows kCondOut apart).  PER_CHAIN: chain i reads
 // row pt[i] (clamped to [0, npts)) from global memory; else every chain reads
