@@ -368,25 +368,39 @@ __global__ void __launch_bounds__(256) logq_kernel(const float* __restrict__ log
     if (lane == 0) logq[ch] = s;
 }
 
-// dz = bf16(dh * mask), plus per-block partial bias gradients sum dh * mask
-__global__ void __launch_bounds__(256) mask_kernel(const float* dh, const uint8_t* mask, int64_t P, __bf16* dz,
-                                                   float* bias_part) {
-    // block handles 256 / 32 = 8 pixels per step, thread = (pixel slot, channel)
-    const int c = threadIdx.x & 31, slot = threadIdx.x >> 5;
-    float s = 0.f;
-    for (int64_t p = (int64_t)blockIdx.x * 8 + slot; p < P; p += (int64_t)gridDim.x * 8) {
-        const int64_t o = p * C + c;
-        const float v = mask[o] ? dh[o] : 0.f;
-        dz[o] = f2bf(v);
-        s += v;
+// dz = bf16(dh * mask), plus per-block partial bias gradients sum dh * mask.
+// A thread takes 8 consecutive channels of a pixel (16-byte loads and stores);
+// a block covers 64 pixels per step.
+constexpr int kMaskPix = 64;
+
+__global__ void __launch_bounds__(256) mask_kernel(const float* __restrict__ dh, const uint8_t* __restrict__ mask,
+                                                   int64_t P, __bf16* __restrict__ dz, float* __restrict__ bias_part) {
+    const int c0 = (threadIdx.x & 3) * 8, slot = threadIdx.x >> 2;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int64_t p = (int64_t)blockIdx.x * kMaskPix + slot; p < P; p += (int64_t)gridDim.x * kMaskPix) {
+        const int64_t o = p * C + c0;
+        const float4 a = *reinterpret_cast<const float4*>(dh + o);
+        const float4 b = *reinterpret_cast<const float4*>(dh + o + 4);
+        const uint2 m = *reinterpret_cast<const uint2*>(mask + o);
+        const float x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        bf16x8 out;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t mw = e < 4 ? m.x : m.y;
+            const float v = ((mw >> (8 * (e & 3))) & 0xffu) ? x[e] : 0.f;
+            out[e] = f2bf(v);
+            s[e] += v;
+        }
+        *reinterpret_cast<bf16x8*>(dz + o) = out;
     }
-    __shared__ float red[256];
-    red[threadIdx.x] = s;
+    __shared__ float red[kMaskPix][C + 1];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[slot][c0 + e] = s[e];
     __syncthreads();
-    if (slot == 0) {
+    if (threadIdx.x < C) {
         float t = 0.f;
-        for (int k = 0; k < 8; ++k) t += red[k * 32 + c];
-        bias_part[(int64_t)blockIdx.x * C + c] = t;
+        for (int k = 0; k < kMaskPix; ++k) t += red[k][threadIdx.x];
+        bias_part[(int64_t)blockIdx.x * C + threadIdx.x] = t;
     }
 }
 
@@ -1358,7 +1372,7 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
             nbp = 256;
             hipLaunchKernelGGL(colsum0_kernel, dim3(nbp), dim3(256), 0, st, a->g32, P, a->bpart);
         } else {
-            nbp = (int)std::min<int64_t>(1024, (P + 7) / 8);
+            nbp = (int)std::min<int64_t>(1024, (P + kMaskPix - 1) / kMaskPix);
             hipLaunchKernelGGL(mask_kernel, dim3(nbp), dim3(256), 0, st, dh, a->mask + (size_t)l * LSZ, P, a->dz,
                                a->bpart);
             dzl = a->dz;
