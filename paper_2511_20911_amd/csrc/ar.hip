@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
 // (they share the gradient operand):
 //   part[chunk][t][i][j] = sum_{p in chunk} in[p + tap_t][i] dz[p][j]
 // (A row i = input channel, k = pixel; B column j = output channel).
-constexpr int kWChunk = 512;
+constexpr int kWChunk = 256;
 
 // One single-wavefront workgroup per chunk stages 32-pixel tiles of the
 // pixel-major layer input, shifted by each tap (zero outside the lattice), and
