@@ -304,14 +304,6 @@ __global__ void __launch_bounds__(256) reduce_slices_kernel(const float* __restr
     part2[(int64_t)sl * n + x] = s;
 }
 
-__global__ void reduce_final_kernel(const double* __restrict__ part2, int n, float* __restrict__ out) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n) return;
-    double s = 0.0;
-#pragma unroll 4
-    for (int k = 0; k < kRedSlices; ++k) s += part2[(int64_t)k * n + x];
-    out[x] = (float)s;
-}
 
 // spins int8 [P] -> bf16 [P][32] with the spin in channel 0
 __global__ void embed_kernel(const int8_t* spins, int64_t P, __bf16* h0) {
@@ -1142,8 +1134,11 @@ __global__ void mh_kernel(int64_t n, int L, int8_t* cur, const int8_t* prop, int
     }
 }
 
-__global__ void scatter_grad_kernel(const float* dW, int l, float* grad) {
-    // dW [T][32][32] padded -> grad layout of layer l
+// Stage 2 of the weight-gradient sum, written into the gradient layout of
+// layer l: entry (t, i, o) of the layer is the fp64 sum of the kRedSlices
+// slices of part2 [slice][NT][C][C] (taps, input and output channels beyond
+// the layer's own are padding and skipped).
+__global__ void reduce_scatter_grad_kernel(const double* __restrict__ part2, int l, float* __restrict__ grad) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
     if (x >= T * ci * co) return;
@@ -1153,7 +1148,11 @@ __global__ void scatter_grad_kernel(const float* dW, int l, float* grad) {
         off += (int64_t)Tk * cik * cok + cok;
     }
     const int o = x % co, i = (x / co) % ci, t = x / (co * ci);
-    grad[off + x] = dW[((int64_t)t * C + i) * C + o];
+    const int64_t n = (int64_t)NT * C * C, src = ((int64_t)t * C + i) * C + o;
+    double sum = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < kRedSlices; ++k) sum += part2[k * n + src];
+    grad[off + x] = (float)sum;
 }
 
 // bias gradient of layer l: the sum of nparts partial sums, one workgroup
@@ -1221,7 +1220,7 @@ struct crbm_ar_s {
     float *dh0 = nullptr, *dh1 = nullptr;  // [P][C]
     __bf16 *dz = nullptr, *g = nullptr;    // [P][C]
     double* logq = nullptr;     // [B]
-    float *part = nullptr, *dW = nullptr, *bpart = nullptr;
+    float *part = nullptr, *bpart = nullptr;
     double* part2 = nullptr;                // [kRedSlices][NT][C][C]
     int8_t* spins_copy = nullptr;
     // sequential sampler buffers (capacity in chains)
@@ -1247,7 +1246,7 @@ struct crbm_ar_s {
     int8_t* mh_prop = nullptr;
     double* mh_lqp = nullptr;
     ~crbm_ar_s() {
-        void* ps[] = {theta, grad, m, v, bias, wf, wb, hs, mask, logit, g32, dh0, dh1, dz, g, logq, part, dW, bpart,
+        void* ps[] = {theta, grad, m, v, bias, wf, wb, hs, mask, logit, g32, dh0, dh1, dz, g, logq, part, bpart,
                       part2,
                       spins_copy, ring, slogit, zpad, ih0, ih1, ilogit, cur, ccur, cprop, lqc, nacc,
                       feats, cb, gs, gp, mh_ci, mh_tg, mh_prop, mh_lqp};
@@ -1387,10 +1386,9 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
                            L, P, a->part);
         hipLaunchKernelGGL(reduce_slices_kernel, dim3((NT * C * C + 255) / 256, kRedSlices), dim3(256), 0, st,
                            a->part, nch, NT * C * C, a->part2);
-        hipLaunchKernelGGL(reduce_final_kernel, dim3((NT * C * C + 255) / 256), dim3(256), 0, st, a->part2,
-                           NT * C * C, a->dW);
         const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
-        hipLaunchKernelGGL(scatter_grad_kernel, dim3((T * ci * co + 255) / 256), dim3(256), 0, st, a->dW, l, a->grad);
+        hipLaunchKernelGGL(reduce_scatter_grad_kernel, dim3((T * ci * co + 255) / 256), dim3(256), 0, st, a->part2, l,
+                           a->grad);
         if (l > 0) {
             const __bf16* Wb = a->wb + (size_t)l * NT * C * C;
             const int mode = (l == NL - 1) ? EP_DGRAD : EP_DGRAD_RESID;
@@ -1521,7 +1519,7 @@ int crbm_ar_create(const crbm_ar_config* c, crbm_ar_t** out) {
     a->np = a->np_base + (a->cond > 0 ? (int64_t)kCondF * kCondH + kCondH + (int64_t)kCondH * kCondOut : 0);
     if (alloc(&a->theta, a->np) || alloc(&a->grad, a->np) || alloc(&a->m, a->np) || alloc(&a->v, a->np) ||
         alloc(&a->bias, NL * C) || alloc(&a->wf, (int64_t)NL * NT * C * C) || alloc(&a->wb, (int64_t)NL * NT * C * C) ||
-        alloc(&a->dW, NT * C * C) || alloc(&a->zpad, C) ||
+        alloc(&a->zpad, C) ||
         (a->cond > 0 && (alloc(&a->feats, (int64_t)a->cond * kCondF) || alloc(&a->cb, (int64_t)a->cond * kCondOut) ||
                          alloc(&a->gp, (int64_t)a->cond * kCondOut)))) {
         delete a;
