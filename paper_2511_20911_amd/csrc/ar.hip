@@ -81,7 +81,11 @@ __device__ __forceinline__ bf16x8 zero8() {
     return z;
 }
 
-// Neighbour pixel of p shifted by (dr, dc) inside the same lattice, or -1.
+// Neighbour pixel of p shifted by (dr, dc) inside the same lattice, or -1,
+// recomputed per tap.  The forward and data-gradient convolution keeps this
+// form: with the cheaper per-pixel flags below its loads are scheduled earlier
+// and it needs 128-144 VGPRs instead of 118, which costs more than the
+// divisions save.
 __device__ __forceinline__ int64_t shift_pixel(int64_t p, int dr, int dc, int L) {
     const int64_t LL = (int64_t)L * L;
     const int64_t b = p / LL;
@@ -89,6 +93,24 @@ __device__ __forceinline__ int64_t shift_pixel(int64_t p, int dr, int dc, int L)
     const int r = rc / L + dr, c = rc % L + dc;
     if (r < 0 || r >= L || c < 0 || c >= L) return -1;
     return b * LL + (int64_t)r * L + c;
+}
+
+// Which neighbours pixel p (p < 2^31, checked on the host) of a batch of
+// L x L lattices has inside its own lattice: bit 0 the row above, bit 1 the
+// row below, bit 2 the column to the left, bit 3 the column to the right.
+// Two 32-bit divisions, once per pixel; only this one word stays live.
+__device__ __forceinline__ uint32_t edge_flags(int64_t p, int L) {
+    const uint32_t pu = (uint32_t)p, LL = (uint32_t)(L * L);
+    const uint32_t rc = pu - (pu / LL) * LL, r = rc / (uint32_t)L, c = rc - r * (uint32_t)L;
+    const uint32_t last = (uint32_t)L - 1u;
+    return (uint32_t)(r > 0u) | ((uint32_t)(r < last) << 1) | ((uint32_t)(c > 0u) << 2) | ((uint32_t)(c < last) << 3);
+}
+
+// Neighbour of pixel p shifted by (dr, dc), |dr|, |dc| <= 1 (3 x 3 taps),
+// inside the same lattice, or -1; f = edge_flags(p, L).
+__device__ __forceinline__ int64_t shift_pix(int64_t p, uint32_t f, int dr, int dc, int L) {
+    const uint32_t need = (dr < 0 ? 1u : 0u) | (dr > 0 ? 2u : 0u) | (dc < 0 ? 4u : 0u) | (dc > 0 ? 8u : 0u);
+    return (f & need) == need ? p + (int64_t)(dr * L + dc) : -1;
 }
 
 // A point index clamped to the points that exist.
@@ -254,10 +276,11 @@ __global__ void __launch_bounds__(64) wgrad_fused_kernel(const __bf16* __restric
 #pragma unroll
             for (int e = 0; e < 8; ++e) tl[(NT * C + hc * 16 + hh * 8 + e) * kFRow + px] = v[e];
         }
+        const uint32_t ef = edge_flags(p < P ? p : 0, L);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             if (t >= taps.n) break;
-            const int64_t q = (p < P) ? shift_pixel(p, taps.dr[t], taps.dc[t], L) : -1;
+            const int64_t q = (p < P) ? shift_pix(p, ef, taps.dr[t], taps.dc[t], L) : -1;
 #pragma unroll
             for (int hh = 0; hh < 2; ++hh) {
                 const bf16x8 v = (q >= 0) ? load8(in + q * C + hc * 16 + hh * 8) : zero8();
@@ -300,6 +323,7 @@ __global__ void __launch_bounds__(256) reduce_slices_kernel(const float* __restr
     const int sl = blockIdx.y;
     if (x >= n) return;
     double s = 0.0;
+#pragma unroll 8  // loads in flight; the sum keeps its order
     for (int c = sl; c < nchunks; c += kRedSlices) s += part[(int64_t)c * n + x];
     part2[(int64_t)sl * n + x] = s;
 }
@@ -682,17 +706,19 @@ __global__ void __launch_bounds__(256) conv16_kernel(const __bf16* __restrict__ 
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
             Wa[t][cb] = (t < taps.n) ? load8(Wl + ((int64_t)t * C + 16 * cb + r16) * C + kg * 8) : zero8();
-    const int64_t ntiles = (P + 15) / 16, LL = (int64_t)L * L;
+    const int64_t ntiles = (P + 15) / 16;
+    const uint32_t LL = (uint32_t)(L * L);  // pixel indices fit 32 bits
     for (int64_t tile = w0; tile < ntiles; tile += nw) {
         const int64_t p = tile * 16 + r16;
-        const float* brow = bias + (pt ? (int64_t)clamp_point(pt[(p < P ? p : P - 1) / LL], npts) * kCondOut : 0);
+        const float* brow = bias + (pt ? (int64_t)clamp_point(pt[(uint32_t)(p < P ? p : P - 1) / LL], npts) * kCondOut : 0);
         const f32x4 bj0 = *reinterpret_cast<const f32x4*>(brow + 4 * kg);
         const f32x4 bj1 = *reinterpret_cast<const f32x4*>(brow + 16 + 4 * kg);
         f32x4 acc0 = bj0, acc1 = bj1;
+        const uint32_t ef = edge_flags(p < P ? p : 0, L);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             if (t >= taps.n) break;
-            const int64_t q = (p < P) ? shift_pixel(p, taps.dr[t], taps.dc[t], L) : -1;
+            const int64_t q = (p < P) ? shift_pix(p, ef, taps.dr[t], taps.dc[t], L) : -1;
             const bf16x8 a = (q >= 0) ? load8(in + q * C + kg * 8) : zero8();
             acc0 = mfma16(Wa[t][0], a, acc0);
             if (!last) acc1 = mfma16(Wa[t][1], a, acc1);
@@ -1273,8 +1299,12 @@ hipError_t alloc(T** p, int64_t n) {
 // weight-gradient chunks of a batch of P pixels
 int64_t wgrad_chunks(int64_t P) { return (P + kWChunk - 1) / kWChunk; }
 
+// The weight-gradient and layer-wise scoring kernels index pixels in 32 bits.
+constexpr int64_t kMaxPixels = (int64_t)1 << 31;
+
 int ensure_train(crbm_ar_t* a, int64_t B) {
     if (B <= a->tcap) return CRBM_OK;
+    if (B > (kMaxPixels - 1) / ((int64_t)a->L * a->L)) return fail_ar(CRBM_EINVAL, "batch too large (samples x L^2 must be below 2^31)");
     void* ps[] = {a->hs, a->mask, a->logit, a->g32, a->dh0, a->dh1, a->dz, a->g, a->logq, a->part, a->bpart,
                   a->spins_copy, a->part2, a->gs};
     for (void* p : ps)
@@ -1446,6 +1476,7 @@ int run_seq(crbm_ar_t* a, int64_t n, int8_t* spins, double* logq, uint64_t seed,
 
 int ensure_infer(crbm_ar_t* a, int64_t n) {
     if (n <= a->icap) return CRBM_OK;
+    if (n > (kMaxPixels - 1) / ((int64_t)a->L * a->L)) return fail_ar(CRBM_EINVAL, "batch too large (samples x L^2 must be below 2^31)");
     void* ps[] = {a->ih0, a->ih1, a->ilogit};
     for (void* p : ps)
         if (p) (void)hipFree(p);

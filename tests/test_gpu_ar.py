@@ -1,6 +1,7 @@
 """GPU tests of the learned proposal: the bf16 matrix-core kernels against the
 oracle (which rounds to bf16 at the same points), sampler self-consistency,
 MH reproducing exact 4x4 averages, and what training gains."""
+import ctypes as ct
 import math
 
 import numpy as np
@@ -279,6 +280,25 @@ def test_mh_cycles_do_not_depend_on_batching():
     a2, t2, s2 = run(True)
     assert a1 == a2 and np.array_equal(t1, t2) and np.array_equal(s1, s2)
     assert a1 > 0
+
+
+def test_batches_beyond_32_bit_pixel_indices_are_refused():
+    """Training and scoring batches of 2^31 pixels or more are refused before
+    any buffer is sized or any kernel runs (the pointer is never read)."""
+    L = 18
+    net = crbm.ARNet(L)
+    x = torch.ones((1, L, L), dtype=torch.int8, device="cuda")
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    big = (2**31 - 1) // (L * L) + 1
+    lib = crbm.lib()
+    loss = ct.c_double()
+    assert lib.crbm_ar_train_step_cond(net._h, ct.c_void_p(x.data_ptr()), None, big, 1e-3,
+                                       ct.byref(loss)) == crbm.CRBM_EINVAL
+    assert "2^31" in lib.crbm_last_error().decode()
+    assert lib.crbm_ar_grad_cond(net._h, ct.c_void_p(x.data_ptr()), None, big, None, None) == crbm.CRBM_EINVAL
+    assert lib.crbm_ar_logq_cond(net._h, ct.c_void_p(x.data_ptr()), None, big,
+                                 ct.c_void_p(out.data_ptr())) == crbm.CRBM_EINVAL
+    assert torch.isfinite(net.logq(x)).all()  # the handle still works
 
 
 def test_batched_sampler_and_mh_edge_cases():
