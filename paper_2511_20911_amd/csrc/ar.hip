@@ -138,12 +138,14 @@ enum { EP_RELU = 0, EP_RESID = 1, EP_LOGIT = 2, EP_DGRAD = 3, EP_DGRAD_RESID = 4
 // bias: layer biases [C] (pt == nullptr), or layer row of a per-point table
 // with rows kCondOut apart, the row of pixel p being that of its sample's
 // point pt[p / L^2] (clamped to [0, npts))
+// out_mask (ReLU modes, may be NULL): one word per pixel, bit j set where
+// channel j's pre-activation is positive
 __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ Wop,
                                                      const float* __restrict__ bias, const int32_t* __restrict__ pt,
                                                      int npts, Taps taps, int L, int64_t P, int mode,
                                                      const __bf16* __restrict__ resid_bf,
                                                      const float* __restrict__ resid_f, __bf16* out_bf,
-                                                     uint8_t* out_mask, float* out_f) {
+                                                     uint32_t* out_mask, float* out_f) {
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -201,6 +203,7 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
         const int c0 = (lane & 1) * 16;
         if (pi < P) {
             const float* br = dgrad ? nullptr : (pt ? bias + (int64_t)clamp_point(pt[pi / LL], npts) * kCondOut : bias);
+            uint32_t mbits = 0u;  // ReLU mask of this lane's 16 channels
 #pragma unroll
             for (int hh = 0; hh < 2; ++hh) {  // two runs of 8 channels keep fewer values live
                 const int cb = c0 + 8 * hh;
@@ -211,15 +214,13 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
                 if (mode == EP_RELU || mode == EP_RESID) {
                     const bf16x8 r = mode == EP_RESID ? load8(resid_bf + o) : zero8();
                     bf16x8 ob;
-                    uint32_t mk[2] = {0u, 0u};
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
                         const float y = z[e] > 0.f ? z[e] : 0.f;
                         ob[e] = f2bf(mode == EP_RESID ? bf2f(r[e]) + y : y);
-                        mk[e >> 2] |= (uint32_t)(z[e] > 0.f) << (8 * (e & 3));
+                        mbits |= (uint32_t)(z[e] > 0.f) << (8 * hh + e);
                     }
                     *reinterpret_cast<bf16x8*>(out_bf + o) = ob;
-                    if (out_mask) *reinterpret_cast<uint2*>(out_mask + o) = make_uint2(mk[0], mk[1]);
                 } else {  // EP_DGRAD, EP_DGRAD_RESID
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
@@ -235,6 +236,8 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
                     }
                 }
             }
+            // one 32-bit word per pixel, bit j = channel j; each lane stores its half
+            if (out_mask) reinterpret_cast<uint16_t*>(out_mask)[2 * pi + (lane & 1)] = (uint16_t)mbits;
         }
         wave_sync();  // the rows are rewritten by the next tile
     }
@@ -389,7 +392,7 @@ __global__ void __launch_bounds__(256) logq_kernel(const float* __restrict__ log
 // a block covers 64 pixels per step.
 constexpr int kMaskPix = 64;
 
-__global__ void __launch_bounds__(256) mask_kernel(const float* __restrict__ dh, const uint8_t* __restrict__ mask,
+__global__ void __launch_bounds__(256) mask_kernel(const float* __restrict__ dh, const uint32_t* __restrict__ mask,
                                                    int64_t P, __bf16* __restrict__ dz, float* __restrict__ bias_part) {
     const int c0 = (threadIdx.x & 3) * 8, slot = threadIdx.x >> 2;
     float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -397,13 +400,12 @@ __global__ void __launch_bounds__(256) mask_kernel(const float* __restrict__ dh,
         const int64_t o = p * C + c0;
         const float4 a = *reinterpret_cast<const float4*>(dh + o);
         const float4 b = *reinterpret_cast<const float4*>(dh + o + 4);
-        const uint2 m = *reinterpret_cast<const uint2*>(mask + o);
+        const uint32_t m = mask[p] >> c0;
         const float x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
         bf16x8 out;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const uint32_t mw = e < 4 ? m.x : m.y;
-            const float v = ((mw >> (8 * (e & 3))) & 0xffu) ? x[e] : 0.f;
+            const float v = ((m >> e) & 1u) ? x[e] : 0.f;
             out[e] = f2bf(v);
             s[e] += v;
         }
@@ -469,7 +471,7 @@ __global__ void __launch_bounds__(kCondOut) cond_bias_kernel(const float* __rest
 // the logit gradient g32 in the logit layer), in a fixed order; one
 // workgroup per sample, 8 pixel slices x 32 channels
 __global__ void __launch_bounds__(256) sample_bias_grad_kernel(const float* __restrict__ dh,
-                                                               const uint8_t* __restrict__ mask,
+                                                               const uint32_t* __restrict__ mask,
                                                                const float* __restrict__ g32, int N, int l,
                                                                float* __restrict__ gs) {
     const int64_t b = blockIdx.x;
@@ -480,8 +482,8 @@ __global__ void __launch_bounds__(256) sample_bias_grad_kernel(const float* __re
             for (int i = slot; i < N; i += 8) s += g32[b * N + i];
     } else {
         for (int i = slot; i < N; i += 8) {
-            const int64_t o = (b * N + i) * C + c;
-            s += mask[o] ? dh[o] : 0.f;
+            const int64_t px = b * N + i;
+            s += ((mask[px] >> c) & 1u) ? dh[px * C + c] : 0.f;
         }
     }
     __shared__ float red[256];
@@ -1240,7 +1242,7 @@ struct crbm_ar_s {
     // training buffers (capacity in samples)
     int64_t tcap = 0;
     __bf16* hs = nullptr;       // [NL][P][C]
-    uint8_t* mask = nullptr;    // [NL-1][P][C]
+    uint32_t* mask = nullptr;   // [NL-1][P]: bit j of a pixel's word = channel j of its ReLU is open
     float* logit = nullptr;     // [P]
     float* g32 = nullptr;       // [P]
     float *dh0 = nullptr, *dh1 = nullptr;  // [P][C]
@@ -1313,7 +1315,7 @@ int ensure_train(crbm_ar_t* a, int64_t B) {
     a->gs = nullptr;
     const int64_t P = B * a->L * a->L;
     const int64_t nch = wgrad_chunks(P);
-    if (alloc(&a->hs, (int64_t)NL * P * C) || alloc(&a->mask, (int64_t)(NL - 1) * P * C) || alloc(&a->logit, P) ||
+    if (alloc(&a->hs, (int64_t)NL * P * C) || alloc(&a->mask, (int64_t)(NL - 1) * P) || alloc(&a->logit, P) ||
         alloc(&a->g32, P) || alloc(&a->dh0, P * C) || alloc(&a->dh1, P * C) || alloc(&a->dz, P * C) ||
         alloc(&a->g, P * C) || alloc(&a->logq, B) || alloc(&a->part, nch * NT * C * C) ||
         alloc(&a->bpart, (int64_t)4096 * C) || alloc(&a->spins_copy, P) ||
@@ -1382,7 +1384,7 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
         const __bf16* W = a->wf + (size_t)l * NT * C * C;
         const int mode = (l == NL - 1) ? EP_LOGIT : (l == 0 ? EP_RELU : EP_RESID);
         __bf16* out = (l < NL - 1) ? a->hs + (size_t)(l + 1) * LSZ : nullptr;
-        uint8_t* mk = (l < NL - 1) ? a->mask + (size_t)l * LSZ : nullptr;
+        uint32_t* mk = (l < NL - 1) ? a->mask + (size_t)l * P : nullptr;
         hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P)), dim3(256), 0, st, a->hs + (size_t)l * LSZ, W,
                            bs.tab + l * C, bs.pt, bs.npts, tp, L, P, mode, a->hs + (size_t)l * LSZ,
                            (const float*)nullptr, out, mk, a->logit);
@@ -1402,7 +1404,7 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
             hipLaunchKernelGGL(colsum0_kernel, dim3(nbp), dim3(256), 0, st, a->g32, P, a->bpart);
         } else {
             nbp = (int)std::min<int64_t>(1024, (P + kMaskPix - 1) / kMaskPix);
-            hipLaunchKernelGGL(mask_kernel, dim3(nbp), dim3(256), 0, st, dh, a->mask + (size_t)l * LSZ, P, a->dz,
+            hipLaunchKernelGGL(mask_kernel, dim3(nbp), dim3(256), 0, st, dh, a->mask + (size_t)l * P, P, a->dz,
                                a->bpart);
             dzl = a->dz;
         }
@@ -1410,7 +1412,7 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
                            a->grad);
         if (a->cond > 0)  // each sample's share, for the conditioning MLP
             hipLaunchKernelGGL(sample_bias_grad_kernel, dim3((unsigned)B), dim3(256), 0, st, dh,
-                               a->mask + (size_t)(l < NL - 1 ? l : 0) * LSZ, l == NL - 1 ? a->g32 : nullptr, L * L,
+                               a->mask + (size_t)(l < NL - 1 ? l : 0) * P, l == NL - 1 ? a->g32 : nullptr, L * L,
                                l, a->gs);
         hipLaunchKernelGGL(wgrad_fused_kernel, dim3((unsigned)nch), dim3(64), 0, st, a->hs + (size_t)l * LSZ, dzl, tp,
                            L, P, a->part);
@@ -1424,7 +1426,7 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
             const int mode = (l == NL - 1) ? EP_DGRAD : EP_DGRAD_RESID;
             hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P)), dim3(256), 0, st, dzl, Wb, a->bias,
                                (const int32_t*)nullptr, 1, tm, L, P, mode, (const __bf16*)nullptr, (const float*)dh,
-                               (__bf16*)nullptr, (uint8_t*)nullptr, dh_alt);
+                               (__bf16*)nullptr, (uint32_t*)nullptr, dh_alt);
             std::swap(dh, dh_alt);
         }
     }
