@@ -1226,6 +1226,7 @@ using namespace crbmlib::ar;
 
 struct crbm_ar_s {
     int L = 0;
+    int cus = 256;         // compute units of the device the handle was made on
     uint64_t seed = 0;
     hipStream_t stream = nullptr;
     int64_t np = 0;        // parameters: the network's, then (conditional) the MLP's
@@ -1364,10 +1365,17 @@ BiasSel bias_sel(const crbm_ar_t* a, const int32_t* pt) {
     return {a->bias, nullptr, 1};
 }
 
-int conv_blocks(int64_t P) {
+// Workgroups of the forward / data-gradient convolution: one 32-pixel tile per
+// wavefront, at most one resident wavefront per SIMD slot (4 workgroups of 4
+// wavefronts per compute unit at its 4 wavefronts per SIMD), the rest taken
+// in turn.  Filling the chip once and looping loads each wavefront's weight
+// fragments once: at 1024-sample batches on 256 compute units this is 4%
+// faster per training step than one tile per wavefront, and 1.25x or 2x the
+// slots is slower.
+int conv_blocks(int64_t P, int cus) {
     const int64_t tiles = (P + 31) / 32;
-    const int64_t b = (tiles + 3) / 4;
-    return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+    const int64_t b = (tiles + 3) / 4, cap = 4 * (int64_t)cus;
+    return (int)(b < cap ? (b > 0 ? b : 1) : cap);
 }
 
 // forward + loss + backward into a->grad; per-sample log q into a->logq.
@@ -1385,7 +1393,7 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
         const int mode = (l == NL - 1) ? EP_LOGIT : (l == 0 ? EP_RELU : EP_RESID);
         __bf16* out = (l < NL - 1) ? a->hs + (size_t)(l + 1) * LSZ : nullptr;
         uint32_t* mk = (l < NL - 1) ? a->mask + (size_t)l * P : nullptr;
-        hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P)), dim3(256), 0, st, a->hs + (size_t)l * LSZ, W,
+        hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P, a->cus)), dim3(256), 0, st, a->hs + (size_t)l * LSZ, W,
                            bs.tab + l * C, bs.pt, bs.npts, tp, L, P, mode, a->hs + (size_t)l * LSZ,
                            (const float*)nullptr, out, mk, a->logit);
     }
@@ -1424,7 +1432,7 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
         if (l > 0) {
             const __bf16* Wb = a->wb + (size_t)l * NT * C * C;
             const int mode = (l == NL - 1) ? EP_DGRAD : EP_DGRAD_RESID;
-            hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P)), dim3(256), 0, st, dzl, Wb, a->bias,
+            hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P, a->cus)), dim3(256), 0, st, dzl, Wb, a->bias,
                                (const int32_t*)nullptr, 1, tm, L, P, mode, (const __bf16*)nullptr, (const float*)dh,
                                (__bf16*)nullptr, (uint32_t*)nullptr, dh_alt);
             std::swap(dh, dh_alt);
@@ -1546,6 +1554,12 @@ int crbm_ar_create(const crbm_ar_config* c, crbm_ar_t** out) {
     if (!a) return fail_ar(CRBM_ENOMEM, "host allocation");
     a->L = c->L;
     a->seed = c->seed;
+    {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            a->cus = n;
+    }
     a->stream = (hipStream_t)c->stream;
     a->cond = c->cond_points;
     a->np_base = n_params();
