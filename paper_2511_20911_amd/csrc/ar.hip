@@ -271,27 +271,37 @@ __global__ void __launch_bounds__(64) wgrad_fused_kernel(const __bf16* __restric
     for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[t][v] = 0.f;
-    for (int64_t p0 = k_begin; p0 < k_end; p0 += kFT) {
+    // Global loads of the next tile are issued before the current tile's
+    // matrix-core work and land in registers; they are written to LDS after it.
+    bf16x8 G[2], X[NT][2];
+    auto fetch = [&](int64_t p0) {
         const int64_t p = p0 + px;
 #pragma unroll
-        for (int hh = 0; hh < 2; ++hh) {
-            const bf16x8 v = (p < P) ? load8(dz + p * C + hc * 16 + hh * 8) : zero8();
-#pragma unroll
-            for (int e = 0; e < 8; ++e) tl[(NT * C + hc * 16 + hh * 8 + e) * kFRow + px] = v[e];
-        }
+        for (int hh = 0; hh < 2; ++hh) G[hh] = (p < P) ? load8(dz + p * C + hc * 16 + hh * 8) : zero8();
         const uint32_t ef = edge_flags(p < P ? p : 0, L);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
+            const int64_t q = (t < taps.n && p < P) ? shift_pix(p, ef, taps.dr[t], taps.dc[t], L) : -1;
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) X[t][hh] = (q >= 0) ? load8(in + q * C + hc * 16 + hh * 8) : zero8();
+        }
+    };
+    if (k_begin < k_end) fetch(k_begin);
+    for (int64_t p0 = k_begin; p0 < k_end; p0 += kFT) {
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) tl[(NT * C + hc * 16 + hh * 8 + e) * kFRow + px] = G[hh][e];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
             if (t >= taps.n) break;
-            const int64_t q = (p < P) ? shift_pix(p, ef, taps.dr[t], taps.dc[t], L) : -1;
 #pragma unroll
-            for (int hh = 0; hh < 2; ++hh) {
-                const bf16x8 v = (q >= 0) ? load8(in + q * C + hc * 16 + hh * 8) : zero8();
+            for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
-                for (int e = 0; e < 8; ++e) tl[(t * C + hc * 16 + hh * 8 + e) * kFRow + px] = v[e];
-            }
+                for (int e = 0; e < 8; ++e) tl[(t * C + hc * 16 + hh * 8 + e) * kFRow + px] = X[t][hh][e];
         }
         __syncthreads();
+        if (p0 + kFT < k_end) fetch(p0 + kFT);
 #pragma unroll
         for (int ks = 0; ks < kFT / 16; ++ks) {
             const int col = ks * 16 + half * 8;
