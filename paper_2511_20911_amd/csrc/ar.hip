@@ -163,21 +163,43 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
     const float bj = dgrad ? 0.f : bias[li];
     const int64_t LL = (int64_t)L * L;
     const int64_t ntiles = (P + 31) / 32;
+    // A tile's operands are loaded while the previous tile's epilogue runs.
+    bf16x8 A[NT][2];
+    auto gather = [&](int64_t tl) {
+        const int64_t pp = tl * 32 + li;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int64_t q = (t < taps.n && pp < P) ? shift_pixel(pp, taps.dr[t], taps.dc[t], L) : -1;
+#pragma unroll
+            for (int kh = 0; kh < 2; ++kh) A[t][kh] = (q >= 0) ? load8(in + q * C + kh * 16 + half * 8) : zero8();
+        }
+    };
+    if (w0 < ntiles) gather(w0);
     for (int64_t tile = w0; tile < ntiles; tile += nw) {
-        const int64_t p = tile * 32 + li;
         f32x16 acc;
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[v] = 0.f;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             if (t >= taps.n) break;
-            const int64_t q = (p < P) ? shift_pixel(p, taps.dr[t], taps.dc[t], L) : -1;
 #pragma unroll
-            for (int kh = 0; kh < 2; ++kh) {
-                const bf16x8 a = (q >= 0) ? load8(in + q * C + kh * 16 + half * 8) : zero8();
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, Bf[t][kh], acc, 0, 0, 0);
-            }
+            for (int kh = 0; kh < 2; ++kh) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[t][kh], Bf[t][kh], acc, 0, 0, 0);
         }
+        // the epilogue's residual is loaded before the next tile's operands, so
+        // that waiting for it does not wait for them
+        const int64_t pi = tile * 32 + (lane >> 1);
+        const int c0 = (lane & 1) * 16;
+        bf16x8 rb[2];
+        float4 rf[4];
+        if (mode == EP_RESID && pi < P) {
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) rb[hh] = load8(resid_bf + pi * C + c0 + 8 * hh);
+        }
+        if (mode == EP_DGRAD_RESID && pi < P) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) rf[k] = *reinterpret_cast<const float4*>(resid_f + pi * C + c0 + 4 * k);
+        }
+        if (tile + nw < ntiles) gather(tile + nw);
         if (mode == EP_LOGIT) {
             // D[i][j]: j = lane & 31, i = 8 (v / 4) + 4 half + (v % 4); only channel 0 is the logit
             if (li == 0)
@@ -199,8 +221,6 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
 #pragma unroll
         for (int v = 0; v < 16; ++v) T[(8 * (v >> 2) + 4 * half + (v & 3)) * kOutRow + li] = acc[v];
         wave_sync();
-        const int64_t pi = tile * 32 + (lane >> 1);
-        const int c0 = (lane & 1) * 16;
         if (pi < P) {
             const float* br = dgrad ? nullptr : (pt ? bias + (int64_t)clamp_point(pt[pi / LL], npts) * kCondOut : bias);
             uint32_t mbits = 0u;  // ReLU mask of this lane's 16 channels
@@ -212,7 +232,7 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
                 for (int e = 0; e < 8; ++e) z[e] = T[(lane >> 1) * kOutRow + cb + e] + (dgrad ? 0.f : br[cb + e]);
                 const int64_t o = pi * C + cb;
                 if (mode == EP_RELU || mode == EP_RESID) {
-                    const bf16x8 r = mode == EP_RESID ? load8(resid_bf + o) : zero8();
+                    const bf16x8 r = mode == EP_RESID ? rb[hh] : zero8();
                     bf16x8 ob;
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
@@ -226,7 +246,7 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
                     for (int q = 0; q < 2; ++q) {
                         float4 d = make_float4(z[4 * q], z[4 * q + 1], z[4 * q + 2], z[4 * q + 3]);
                         if (mode == EP_DGRAD_RESID) {
-                            const float4 r = *reinterpret_cast<const float4*>(resid_f + o + 4 * q);
+                            const float4 r = rf[2 * hh + q];
                             d.x += r.x;
                             d.y += r.y;
                             d.z += r.z;
@@ -1236,7 +1256,7 @@ using namespace crbmlib::ar;
 
 struct crbm_ar_s {
     int L = 0;
-    int cus = 256;         // compute units of the device the handle was made on
+    int conv_wg = 512;     // convolution workgroups that are resident at once on the device
     uint64_t seed = 0;
     hipStream_t stream = nullptr;
     int64_t np = 0;        // parameters: the network's, then (conditional) the MLP's
@@ -1375,16 +1395,15 @@ BiasSel bias_sel(const crbm_ar_t* a, const int32_t* pt) {
     return {a->bias, nullptr, 1};
 }
 
-// Workgroups of the forward / data-gradient convolution: one 32-pixel tile per
-// wavefront, at most one resident wavefront per SIMD slot (4 workgroups of 4
-// wavefronts per compute unit at its 4 wavefronts per SIMD), the rest taken
-// in turn.  Filling the chip once and looping loads each wavefront's weight
-// fragments once: at 1024-sample batches on 256 compute units this is 4%
-// faster per training step than one tile per wavefront, and 1.25x or 2x the
-// slots is slower.
-int conv_blocks(int64_t P, int cus) {
+// Workgroups of the forward / data-gradient convolution: as many as are
+// resident at once (cap: compute units x the kernel's occupancy in
+// workgroups), each wavefront looping over 32-pixel tiles with its weight
+// fragments loaded once and the next tile's operands loading during the
+// current tile's epilogue.  At 1024-sample batches this beats one tile per
+// wavefront, and also half or 1.5x the resident count.
+int conv_blocks(int64_t P, int cap) {
     const int64_t tiles = (P + 31) / 32;
-    const int64_t b = (tiles + 3) / 4, cap = 4 * (int64_t)cus;
+    const int64_t b = (tiles + 3) / 4;
     return (int)(b < cap ? (b > 0 ? b : 1) : cap);
 }
 
@@ -1403,7 +1422,7 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
         const int mode = (l == NL - 1) ? EP_LOGIT : (l == 0 ? EP_RELU : EP_RESID);
         __bf16* out = (l < NL - 1) ? a->hs + (size_t)(l + 1) * LSZ : nullptr;
         uint32_t* mk = (l < NL - 1) ? a->mask + (size_t)l * P : nullptr;
-        hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P, a->cus)), dim3(256), 0, st, a->hs + (size_t)l * LSZ, W,
+        hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P, a->conv_wg)), dim3(256), 0, st, a->hs + (size_t)l * LSZ, W,
                            bs.tab + l * C, bs.pt, bs.npts, tp, L, P, mode, a->hs + (size_t)l * LSZ,
                            (const float*)nullptr, out, mk, a->logit);
     }
@@ -1442,7 +1461,7 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
         if (l > 0) {
             const __bf16* Wb = a->wb + (size_t)l * NT * C * C;
             const int mode = (l == NL - 1) ? EP_DGRAD : EP_DGRAD_RESID;
-            hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P, a->cus)), dim3(256), 0, st, dzl, Wb, a->bias,
+            hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P, a->conv_wg)), dim3(256), 0, st, dzl, Wb, a->bias,
                                (const int32_t*)nullptr, 1, tm, L, P, mode, (const __bf16*)nullptr, (const float*)dh,
                                (__bf16*)nullptr, (uint32_t*)nullptr, dh_alt);
             std::swap(dh, dh_alt);
@@ -1565,10 +1584,11 @@ int crbm_ar_create(const crbm_ar_config* c, crbm_ar_t** out) {
     a->L = c->L;
     a->seed = c->seed;
     {
-        int dev = 0, n = 0;
+        int dev = 0, n = 0, per_cu = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
-            a->cus = n;
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0 &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, conv32_kernel, 256, 0) == hipSuccess && per_cu > 0)
+            a->conv_wg = n * per_cu;
     }
     a->stream = (hipStream_t)c->stream;
     a->cond = c->cond_points;
