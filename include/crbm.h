@@ -287,8 +287,7 @@ int crbm_ar_sample_cond(crbm_ar_t* a, int64_t n, uint64_t seed, int64_t step, ui
  * (device int8 +-1 [batch][L][L]); grad_host (may be NULL) receives it in the
  * parameter layout, loss_out (may be NULL) the loss.  Synchronises.
  * Training and scoring batches hold fewer than 2^31 pixels (batch x L^2: the
- * weight-gradient and layer-wise scoring kernels index pixels in 32 bits);
- * larger ones get CRBM_EINVAL. */
+ * convolution kernels index pixels in 32 bits); larger ones get CRBM_EINVAL. */
 int crbm_ar_grad(crbm_ar_t* a, const int8_t* samples_dev, int64_t batch, float* grad_host, double* loss_out);
 /* One Adam step (beta = 0.9, 0.999, eps = 1e-8) at learning rate lr on a batch. */
 int crbm_ar_train_step(crbm_ar_t* a, const int8_t* samples_dev, int64_t batch, float lr, double* loss_out);

@@ -81,20 +81,6 @@ __device__ __forceinline__ bf16x8 zero8() {
     return z;
 }
 
-// Neighbour pixel of p shifted by (dr, dc) inside the same lattice, or -1,
-// recomputed per tap.  The forward and data-gradient convolution keeps this
-// form: with the cheaper per-pixel flags below its loads are scheduled earlier
-// and it needs 128-144 VGPRs instead of 118, which costs more than the
-// divisions save.
-__device__ __forceinline__ int64_t shift_pixel(int64_t p, int dr, int dc, int L) {
-    const int64_t LL = (int64_t)L * L;
-    const int64_t b = p / LL;
-    const int rc = (int)(p - b * LL);
-    const int r = rc / L + dr, c = rc % L + dc;
-    if (r < 0 || r >= L || c < 0 || c >= L) return -1;
-    return b * LL + (int64_t)r * L + c;
-}
-
 // Which neighbours pixel p (p < 2^31, checked on the host) of a batch of
 // L x L lattices has inside its own lattice: bit 0 the row above, bit 1 the
 // row below, bit 2 the column to the left, bit 3 the column to the right.
@@ -167,9 +153,10 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
     bf16x8 A[NT][2];
     auto gather = [&](int64_t tl) {
         const int64_t pp = tl * 32 + li;
+        const uint32_t ef = edge_flags(pp < P ? pp : 0, L);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int64_t q = (t < taps.n && pp < P) ? shift_pixel(pp, taps.dr[t], taps.dc[t], L) : -1;
+            const int64_t q = (t < taps.n && pp < P) ? shift_pix(pp, ef, taps.dr[t], taps.dc[t], L) : -1;
 #pragma unroll
             for (int kh = 0; kh < 2; ++kh) A[t][kh] = (q >= 0) ? load8(in + q * C + kh * 16 + half * 8) : zero8();
         }
@@ -1332,7 +1319,7 @@ hipError_t alloc(T** p, int64_t n) {
 // weight-gradient chunks of a batch of P pixels
 int64_t wgrad_chunks(int64_t P) { return (P + kWChunk - 1) / kWChunk; }
 
-// The weight-gradient and layer-wise scoring kernels index pixels in 32 bits.
+// The convolution kernels index pixels in 32 bits.
 constexpr int64_t kMaxPixels = (int64_t)1 << 31;
 
 int ensure_train(crbm_ar_t* a, int64_t B) {
