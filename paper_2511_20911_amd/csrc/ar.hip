@@ -349,12 +349,14 @@ __global__ void __launch_bounds__(256) reduce_slices_kernel(const float* __restr
 }
 
 
-// spins int8 [P] -> bf16 [P][32] with the spin in channel 0
+// spins int8 [P] -> bf16 [P][32] with the spin in channel 0; a thread writes
+// 8 channels (16 bytes) of one pixel
 __global__ void embed_kernel(const int8_t* spins, int64_t P, __bf16* h0) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P * C) return;
-    const int64_t p = i / C;
-    h0[i] = ((i % C) == 0) ? f2bf((float)spins[p]) : (__bf16)0.0f;
+    if (i >= P * (C / 8)) return;
+    bf16x8 v = zero8();
+    if ((i & 3) == 0) v[0] = f2bf((float)spins[i >> 2]);
+    *reinterpret_cast<bf16x8*>(h0 + i * 8) = v;
 }
 
 // loss: per sample log q (fp64) and the logit gradient of -mean log q
@@ -1179,36 +1181,45 @@ __global__ void mh_kernel(int64_t n, int L, int8_t* cur, const int8_t* prop, int
     }
 }
 
-// Stage 2 of the weight-gradient sum, written into the gradient layout of
-// layer l: entry (t, i, o) of the layer is the fp64 sum of the kRedSlices
-// slices of part2 [slice][NT][C][C] (taps, input and output channels beyond
-// the layer's own are padding and skipped).
-__global__ void reduce_scatter_grad_kernel(const double* __restrict__ part2, int l, float* __restrict__ grad) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
-    if (x >= T * ci * co) return;
+// Offset of layer l's weights in the parameter layout (each layer: its
+// [T][ci][co] weights, then its co biases).
+__device__ __forceinline__ int64_t layer_offset(int l) {
     int64_t off = 0;
     for (int k = 0; k < l; ++k) {
         const int Tk = (k == 0) ? 4 : 5, cik = (k == 0) ? 1 : C, cok = (k == NL - 1) ? 1 : C;
         off += (int64_t)Tk * cik * cok + cok;
     }
-    const int o = x % co, i = (x / co) % ci, t = x / (co * ci);
-    const int64_t n = (int64_t)NT * C * C, src = ((int64_t)t * C + i) * C + o;
-    double sum = 0.0;
-#pragma unroll 4
-    for (int k = 0; k < kRedSlices; ++k) sum += part2[k * n + src];
-    grad[off + x] = (float)sum;
+    return off;
 }
 
-// bias gradient of layer l: the sum of nparts partial sums, one workgroup
-// per output channel; 256 threads each add a strided share of the partials,
-// then a fixed-order tree in LDS (fp64)
-__global__ void __launch_bounds__(256) scatter_bias_kernel(const float* part, int nparts, int l, float* grad) {
-    const int j = blockIdx.x;
+// Layer l's gradient in the parameter layout, one launch:
+// - the first wblocks workgroups: weight entry (t, i, o) is the fp64 sum of
+//   the kRedSlices slices of part2 [slice][NT][C][C] (taps, input and output
+//   channels beyond the layer's own are padding and skipped);
+// - then one workgroup per output channel j: bias j is the sum of the nparts
+//   partial sums bpart[p][j] (the last layer: bpart[p]), 256 threads each
+//   adding a strided share, then a fixed-order tree in LDS (fp64).
+__global__ void __launch_bounds__(256) finish_layer_grad_kernel(const double* __restrict__ part2, int wblocks,
+                                                                const float* __restrict__ bpart, int nparts, int l,
+                                                                float* __restrict__ grad) {
     const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
+    const int64_t off = layer_offset(l);
+    if ((int)blockIdx.x < wblocks) {
+        const int x = blockIdx.x * blockDim.x + threadIdx.x;
+        if (x >= T * ci * co) return;
+        const int o = x % co, i = (x / co) % ci, t = x / (co * ci);
+        const int64_t n = (int64_t)NT * C * C, src = ((int64_t)t * C + i) * C + o;
+        double sum = 0.0;
+#pragma unroll 4
+        for (int k = 0; k < kRedSlices; ++k) sum += part2[k * n + src];
+        grad[off + x] = (float)sum;
+        return;
+    }
+    // the whole workgroup takes this branch (blockIdx is uniform)
+    const int j = (int)blockIdx.x - wblocks;
     const int stride = (co == 1) ? 1 : C;
     double s = 0.0;
-    for (int p = threadIdx.x; p < nparts; p += blockDim.x) s += part[(int64_t)p * stride + j];
+    for (int p = threadIdx.x; p < nparts; p += blockDim.x) s += bpart[(int64_t)p * stride + j];
     __shared__ double red[256];
     red[threadIdx.x] = s;
     __syncthreads();
@@ -1216,14 +1227,7 @@ __global__ void __launch_bounds__(256) scatter_bias_kernel(const float* part, in
         if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        int64_t off = 0;
-        for (int k = 0; k < l; ++k) {
-            const int Tk = (k == 0) ? 4 : 5, cik = (k == 0) ? 1 : C, cok = (k == NL - 1) ? 1 : C;
-            off += (int64_t)Tk * cik * cok + cok;
-        }
-        grad[off + (int64_t)T * ci * co + j] = (float)red[0];
-    }
+    if (threadIdx.x == 0) grad[off + (int64_t)T * ci * co + j] = (float)red[0];
 }
 
 int64_t n_params() {
@@ -1402,7 +1406,7 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
     const int64_t P = B * L * L;
     const size_t LSZ = (size_t)P * C;
     hipStream_t st = a->stream;
-    hipLaunchKernelGGL(embed_kernel, dim3((unsigned)((P * C + 255) / 256)), dim3(256), 0, st, spins, P, a->hs);
+    hipLaunchKernelGGL(embed_kernel, dim3((unsigned)((P * (C / 8) + 255) / 256)), dim3(256), 0, st, spins, P, a->hs);
     for (int l = 0; l < NL; ++l) {
         const Taps tp = taps_for(l, false);
         const __bf16* W = a->wf + (size_t)l * NT * C * C;
@@ -1432,8 +1436,6 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
                                a->bpart);
             dzl = a->dz;
         }
-        hipLaunchKernelGGL(scatter_bias_kernel, dim3(l == NL - 1 ? 1 : C), dim3(256), 0, st, a->bpart, nbp, l,
-                           a->grad);
         if (a->cond > 0)  // each sample's share, for the conditioning MLP
             hipLaunchKernelGGL(sample_bias_grad_kernel, dim3((unsigned)B), dim3(256), 0, st, dh,
                                a->mask + (size_t)(l < NL - 1 ? l : 0) * P, l == NL - 1 ? a->g32 : nullptr, L * L,
@@ -1443,8 +1445,9 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
         hipLaunchKernelGGL(reduce_slices_kernel, dim3((NT * C * C + 255) / 256, kRedSlices), dim3(256), 0, st,
                            a->part, nch, NT * C * C, a->part2);
         const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
-        hipLaunchKernelGGL(reduce_scatter_grad_kernel, dim3((T * ci * co + 255) / 256), dim3(256), 0, st, a->part2, l,
-                           a->grad);
+        const int wblocks = (T * ci * co + 255) / 256;
+        hipLaunchKernelGGL(finish_layer_grad_kernel, dim3(wblocks + co), dim3(256), 0, st, a->part2, wblocks, a->bpart,
+                           nbp, l, a->grad);
         if (l > 0) {
             const __bf16* Wb = a->wb + (size_t)l * NT * C * C;
             const int mode = (l == NL - 1) ? EP_DGRAD : EP_DGRAD_RESID;
@@ -1538,7 +1541,7 @@ int run_score(crbm_ar_t* a, int64_t n, const int8_t* spins, double* logq, const 
         AR_TRY(hipGetLastError(), "scoring kernels");
         return CRBM_OK;
     }
-    hipLaunchKernelGGL(embed_kernel, dim3((unsigned)((P * C + 255) / 256)), dim3(256), 0, st, spins, P, a->ih0);
+    hipLaunchKernelGGL(embed_kernel, dim3((unsigned)((P * (C / 8) + 255) / 256)), dim3(256), 0, st, spins, P, a->ih0);
     __bf16* in = a->ih0;
     __bf16* out = a->ih1;
     const int64_t tiles = (P + 15) / 16;
