@@ -126,12 +126,17 @@ enum { EP_RELU = 0, EP_RESID = 1, EP_LOGIT = 2, EP_DGRAD = 3, EP_DGRAD_RESID = 4
 // point pt[p / L^2] (clamped to [0, npts))
 // out_mask (ReLU modes, may be NULL): one word per pixel, bit j set where
 // channel j's pre-activation is positive
+// gate (data-gradient modes, may be NULL): the ReLU mask of the layer below;
+// then gz also receives the gated gradient in bf16 (out_f where the mask bit
+// is set, else 0), and gbias[wave][C] each wavefront's fp32 sum of it over its
+// pixels (fixed order: its tiles in turn, then a butterfly over its lanes)
 __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ Wop,
                                                      const float* __restrict__ bias, const int32_t* __restrict__ pt,
                                                      int npts, Taps taps, int L, int64_t P, int mode,
                                                      const __bf16* __restrict__ resid_bf,
                                                      const float* __restrict__ resid_f, __bf16* out_bf,
-                                                     uint32_t* out_mask, float* out_f) {
+                                                     uint32_t* out_mask, float* out_f, const uint32_t* __restrict__ gate,
+                                                     __bf16* __restrict__ gz, float* __restrict__ gbias) {
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -161,6 +166,9 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
             for (int kh = 0; kh < 2; ++kh) A[t][kh] = (q >= 0) ? load8(in + q * C + kh * 16 + half * 8) : zero8();
         }
     };
+    float gsum[16];  // gated-gradient sums of this lane's 16 channels (gate only)
+#pragma unroll
+    for (int k = 0; k < 16; ++k) gsum[k] = 0.f;
     if (w0 < ntiles) gather(w0);
     for (int64_t tile = w0; tile < ntiles; tile += nw) {
         f32x16 acc;
@@ -186,6 +194,7 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
 #pragma unroll
             for (int k = 0; k < 4; ++k) rf[k] = *reinterpret_cast<const float4*>(resid_f + pi * C + c0 + 4 * k);
         }
+        const uint32_t gm = (gate && pi < P) ? gate[pi] >> c0 : 0u;
         if (tile + nw < ntiles) gather(tile + nw);
         if (mode == EP_LOGIT) {
             // D[i][j]: j = lane & 31, i = 8 (v / 4) + 4 half + (v % 4); only channel 0 is the logit
@@ -229,6 +238,7 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
                     }
                     *reinterpret_cast<bf16x8*>(out_bf + o) = ob;
                 } else {  // EP_DGRAD, EP_DGRAD_RESID
+                    float dv[8];
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
                         float4 d = make_float4(z[4 * q], z[4 * q + 1], z[4 * q + 2], z[4 * q + 3]);
@@ -240,6 +250,20 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
                             d.w += r.w;
                         }
                         *reinterpret_cast<float4*>(out_f + o + 4 * q) = d;
+                        dv[4 * q] = d.x;
+                        dv[4 * q + 1] = d.y;
+                        dv[4 * q + 2] = d.z;
+                        dv[4 * q + 3] = d.w;
+                    }
+                    if (gate) {
+                        bf16x8 zb;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const float v = ((gm >> (8 * hh + e)) & 1u) ? dv[e] : 0.f;
+                            zb[e] = f2bf(v);
+                            gsum[8 * hh + e] += v;
+                        }
+                        *reinterpret_cast<bf16x8*>(gz + o) = zb;
                     }
                 }
             }
@@ -247,6 +271,19 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
             if (out_mask) reinterpret_cast<uint16_t*>(out_mask)[2 * pi + (lane & 1)] = (uint16_t)mbits;
         }
         wave_sync();  // the rows are rewritten by the next tile
+    }
+    if (gate) {
+        // lanes of equal parity hold the same 16 channels (pixel = lane / 2)
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            float v = gsum[k];
+#pragma unroll
+            for (int m = 2; m < 64; m <<= 1) v += __shfl_xor(v, m);
+            gsum[k] = v;
+        }
+        if (lane < 2)
+#pragma unroll
+            for (int k = 0; k < 16; ++k) gbias[w0 * C + (lane & 1) * 16 + k] = gsum[k];
     }
 }
 
@@ -404,41 +441,6 @@ __global__ void __launch_bounds__(256) logq_kernel(const float* __restrict__ log
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d);
     if (lane == 0) logq[ch] = s;
-}
-
-// dz = bf16(dh * mask), plus per-block partial bias gradients sum dh * mask.
-// A thread takes 8 consecutive channels of a pixel (16-byte loads and stores);
-// a block covers 64 pixels per step.
-constexpr int kMaskPix = 64;
-
-__global__ void __launch_bounds__(256) mask_kernel(const float* __restrict__ dh, const uint32_t* __restrict__ mask,
-                                                   int64_t P, __bf16* __restrict__ dz, float* __restrict__ bias_part) {
-    const int c0 = (threadIdx.x & 3) * 8, slot = threadIdx.x >> 2;
-    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int64_t p = (int64_t)blockIdx.x * kMaskPix + slot; p < P; p += (int64_t)gridDim.x * kMaskPix) {
-        const int64_t o = p * C + c0;
-        const float4 a = *reinterpret_cast<const float4*>(dh + o);
-        const float4 b = *reinterpret_cast<const float4*>(dh + o + 4);
-        const uint32_t m = mask[p] >> c0;
-        const float x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-        bf16x8 out;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float v = ((m >> e) & 1u) ? x[e] : 0.f;
-            out[e] = f2bf(v);
-            s[e] += v;
-        }
-        *reinterpret_cast<bf16x8*>(dz + o) = out;
-    }
-    __shared__ float red[kMaskPix][C + 1];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) red[slot][c0 + e] = s[e];
-    __syncthreads();
-    if (threadIdx.x < C) {
-        float t = 0.f;
-        for (int k = 0; k < kMaskPix; ++k) t += red[k][threadIdx.x];
-        bias_part[(int64_t)blockIdx.x * C + threadIdx.x] = t;
-    }
 }
 
 // bias gradient of the logit layer: sum over pixels of the fp32 logit gradient
@@ -1340,7 +1342,7 @@ int ensure_train(crbm_ar_t* a, int64_t B) {
     if (alloc(&a->hs, (int64_t)NL * P * C) || alloc(&a->mask, (int64_t)(NL - 1) * P) || alloc(&a->logit, P) ||
         alloc(&a->g32, P) || alloc(&a->dh0, P * C) || alloc(&a->dh1, P * C) || alloc(&a->dz, P * C) ||
         alloc(&a->g, P * C) || alloc(&a->logq, B) || alloc(&a->part, nch * NT * C * C) ||
-        alloc(&a->bpart, (int64_t)4096 * C) || alloc(&a->spins_copy, P) ||
+        alloc(&a->bpart, (int64_t)std::max<int64_t>(4096, 4 * (int64_t)a->conv_wg) * C) || alloc(&a->spins_copy, P) ||
         alloc(&a->part2, (int64_t)kRedSlices * NT * C * C) || (a->cond > 0 && alloc(&a->gs, B * kCondOut))) {
         a->tcap = 0;
         return fail_ar(CRBM_ENOMEM, "training buffers");
@@ -1415,13 +1417,20 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
         uint32_t* mk = (l < NL - 1) ? a->mask + (size_t)l * P : nullptr;
         hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P, a->conv_wg)), dim3(256), 0, st, a->hs + (size_t)l * LSZ, W,
                            bs.tab + l * C, bs.pt, bs.npts, tp, L, P, mode, a->hs + (size_t)l * LSZ,
-                           (const float*)nullptr, out, mk, a->logit);
+                           (const float*)nullptr, out, mk, a->logit, (const uint32_t*)nullptr, (__bf16*)nullptr,
+                           (float*)nullptr);
     }
     hipLaunchKernelGGL(loss_kernel, dim3((unsigned)B), dim3(256), 0, st, a->logit, spins, L, 1.0f / (float)B, a->logq,
                        a->g, a->g32);
     const int nch = (int)wgrad_chunks(P);
     float* dh = a->dh0;
     float* dh_alt = a->dh1;
+    // The data-gradient convolution of layer l also applies the ReLU mask of
+    // layer l - 1 and sums the result per channel, so layer l - 1 starts with
+    // its gated gradient (bf16, alternating between dz and the logit-gradient
+    // buffer, which is free after the top layer) and its bias partial sums.
+    __bf16* dz_next = nullptr;
+    int nbp_next = 0;
     for (int l = NL - 1; l >= 0; --l) {
         const Taps tp = taps_for(l, false), tm = taps_for(l, true);
         const __bf16* dzl;
@@ -1431,10 +1440,8 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
             nbp = 256;
             hipLaunchKernelGGL(colsum0_kernel, dim3(nbp), dim3(256), 0, st, a->g32, P, a->bpart);
         } else {
-            nbp = (int)std::min<int64_t>(1024, (P + kMaskPix - 1) / kMaskPix);
-            hipLaunchKernelGGL(mask_kernel, dim3(nbp), dim3(256), 0, st, dh, a->mask + (size_t)l * P, P, a->dz,
-                               a->bpart);
-            dzl = a->dz;
+            dzl = dz_next;
+            nbp = nbp_next;
         }
         if (a->cond > 0)  // each sample's share, for the conditioning MLP
             hipLaunchKernelGGL(sample_bias_grad_kernel, dim3((unsigned)B), dim3(256), 0, st, dh,
@@ -1451,9 +1458,13 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
         if (l > 0) {
             const __bf16* Wb = a->wb + (size_t)l * NT * C * C;
             const int mode = (l == NL - 1) ? EP_DGRAD : EP_DGRAD_RESID;
-            hipLaunchKernelGGL(conv32_kernel, dim3(conv_blocks(P, a->conv_wg)), dim3(256), 0, st, dzl, Wb, a->bias,
-                               (const int32_t*)nullptr, 1, tm, L, P, mode, (const __bf16*)nullptr, (const float*)dh,
-                               (__bf16*)nullptr, (uint32_t*)nullptr, dh_alt);
+            const int nb = conv_blocks(P, a->conv_wg);
+            dz_next = (dzl == a->dz) ? a->g : a->dz;
+            nbp_next = 4 * nb;
+            hipLaunchKernelGGL(conv32_kernel, dim3(nb), dim3(256), 0, st, dzl, Wb, a->bias, (const int32_t*)nullptr, 1,
+                               tm, L, P, mode, (const __bf16*)nullptr, (const float*)dh, (__bf16*)nullptr,
+                               (uint32_t*)nullptr, dh_alt, (const uint32_t*)(a->mask + (size_t)(l - 1) * P), dz_next,
+                               a->bpart);
             std::swap(dh, dh_alt);
         }
     }
