@@ -62,6 +62,32 @@ def test_gradient_matches_oracle(L):
     assert cos > 0.9995, cos
 
 
+def test_gradient_of_a_large_batch_is_the_mean_of_its_parts():
+    """At 1024 samples of 18 x 18 the convolution launches give each wavefront
+    several 32-pixel tiles (operands loaded a tile ahead, ReLU gate and bias
+    sums carried across tiles); at 64 samples each wavefront has at most one
+    tile.  The mean-loss gradient is linear in the samples, so the big batch's
+    gradient must equal the mean of its 16 parts' gradients up to fp32
+    summation order."""
+    L, n, parts = 18, 1024, 16
+    params = ar.init_params(seed=77, scale=INIT_SCALE)
+    net = crbm.ARNet(L)
+    net.set_params(flatten(params))
+    s = torch.from_numpy(_rand_spins(n, L, 78)).cuda()
+    g, loss = net.grad(s)
+    ref = np.zeros_like(g, dtype=np.float64)
+    ref_loss = 0.0
+    m = n // parts
+    for k in range(parts):
+        gk, lk = net.grad(s[k * m:(k + 1) * m].contiguous())
+        ref += gk.astype(np.float64) / parts
+        ref_loss += lk / parts
+    assert abs(loss - ref_loss) < 1e-6 * abs(ref_loss), (loss, ref_loss)
+    rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    assert rel < 1e-4, rel
+    assert np.abs(g - ref).max() < 1e-3 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("L,n", [(6, 96), (18, 40), (36, 24)])
 def test_sampler_logq_equals_scorer_and_follows_logits(L, n):
     """Ancestral sampler vs scorer: identical log q (the fused one-workgroup
