@@ -291,25 +291,31 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
 // (they share the gradient operand):
 //   part[chunk][t][i][j] = sum_{p in chunk} in[p + tap_t][i] dz[p][j]
 // (A row i = input channel, k = pixel; B column j = output channel).
-constexpr int kWChunk = 256;
+constexpr int kWChunk = 512;
+constexpr int kWWaves = 2;  // wavefronts per chunk, kWChunk / kWWaves pixels each
 
-// One single-wavefront workgroup per chunk stages 32-pixel tiles of the
+// Each wavefront of a chunk's workgroup stages 32-pixel tiles of the
 // pixel-major layer input, shifted by each tap (zero outside the lattice), and
 // of the gradient through LDS in channel-major form (the matrix-core operands
 // need consecutive pixels per channel) and contracts them on the matrix cores.
-// No channel-major copy goes through HBM.
+// No channel-major copy goes through HBM.  The wavefronts' sums are added in
+// LDS (wavefront 0's plus wavefront 1's), so a chunk writes one partial.
 constexpr int kFT = 32;           // pixels per staged tile (two 16-pixel k-steps)
 constexpr int kFRow = kFT + 8;    // LDS row stride in elements (80 bytes: 16-byte aligned rows)
 
-__global__ void __launch_bounds__(64) wgrad_fused_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ dz,
-                                                         Taps taps, int L, int64_t P, float* __restrict__ part) {
-    __shared__ __align__(16) __bf16 tl[(NT + 1) * C * kFRow];  // slots 0..NT-1 taps, slot NT the gradient
-    const int lane = threadIdx.x;
+__global__ void __launch_bounds__(64 * kWWaves) wgrad_fused_kernel(const __bf16* __restrict__ in,
+                                                                   const __bf16* __restrict__ dz, Taps taps, int L,
+                                                                   int64_t P, float* __restrict__ part) {
+    constexpr int kSlot = (NT + 1) * C * kFRow;  // one wavefront's tiles: slots 0..NT-1 taps, slot NT the gradient
+    __shared__ __align__(16) __bf16 tls[kWWaves * kSlot];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __bf16* tl = tls + wv * kSlot;
     const int li = lane & 31, half = lane >> 5;
     const int px = lane >> 1, hc = lane & 1;  // staging: pixel of the tile, channel half
     const int64_t chunk = blockIdx.x;
-    const int64_t k_begin = chunk * kWChunk;
-    const int64_t k_end = (k_begin + kWChunk < P) ? k_begin + kWChunk : P;
+    const int64_t c_begin = chunk * kWChunk;
+    const int64_t k_begin = c_begin + wv * (kWChunk / kWWaves);
+    const int64_t k_end = (k_begin + kWChunk / kWWaves < P) ? k_begin + kWChunk / kWWaves : P;
     f32x16 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
@@ -344,7 +350,7 @@ __global__ void __launch_bounds__(64) wgrad_fused_kernel(const __bf16* __restric
 #pragma unroll
                 for (int e = 0; e < 8; ++e) tl[(t * C + hc * 16 + hh * 8 + e) * kFRow + px] = X[t][hh][e];
         }
-        __syncthreads();
+        wave_sync();  // this wavefront's own tiles: no workgroup barrier
         if (p0 + kFT < k_end) fetch(p0 + kFT);
 #pragma unroll
         for (int ks = 0; ks < kFT / 16; ++ks) {
@@ -357,17 +363,28 @@ __global__ void __launch_bounds__(64) wgrad_fused_kernel(const __bf16* __restric
                 acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
             }
         }
-        __syncthreads();
+        wave_sync();  // this wavefront's own tiles: no workgroup barrier
     }
+    // every wavefront reaches this point (no barrier inside the loops above)
+    float* red = reinterpret_cast<float*>(tls);  // NT * 16 * 64 floats fit in the tiles' space
+    static_assert(kWWaves == 2 && NT * 16 * 64 * sizeof(float) <= kWWaves * kSlot * sizeof(__bf16), "reduction buffer");
+    __syncthreads();
+    if (wv == 1)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        if (t >= taps.n) break;
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int i = 8 * (v >> 2) + 4 * half + (v & 3);
-            part[((chunk * NT + t) * C + i) * C + li] = acc[t][v];
+            for (int v = 0; v < 16; ++v) red[(t * 16 + v) * 64 + lane] = acc[t][v];
+    __syncthreads();
+    if (wv == 0)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            if (t >= taps.n) break;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int i = 8 * (v >> 2) + 4 * half + (v & 3);
+                part[((chunk * NT + t) * C + i) * C + li] = acc[t][v] + red[(t * 16 + v) * 64 + lane];
+            }
         }
-    }
 }
 
 // Two-stage deterministic sum over chunks: stage 1 (block = 256 entries x one
@@ -1447,7 +1464,7 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
             hipLaunchKernelGGL(sample_bias_grad_kernel, dim3((unsigned)B), dim3(256), 0, st, dh,
                                a->mask + (size_t)(l < NL - 1 ? l : 0) * P, l == NL - 1 ? a->g32 : nullptr, L * L,
                                l, a->gs);
-        hipLaunchKernelGGL(wgrad_fused_kernel, dim3((unsigned)nch), dim3(64), 0, st, a->hs + (size_t)l * LSZ, dzl, tp,
+        hipLaunchKernelGGL(wgrad_fused_kernel, dim3((unsigned)nch), dim3(64 * kWWaves), 0, st, a->hs + (size_t)l * LSZ, dzl, tp,
                            L, P, a->part);
         hipLaunchKernelGGL(reduce_slices_kernel, dim3((NT * C * C + 255) / 256, kRedSlices), dim3(256), 0, st,
                            a->part, nch, NT * C * C, a->part2);
