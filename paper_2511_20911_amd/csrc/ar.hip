@@ -389,7 +389,7 @@ __global__ void __launch_bounds__(64 * kWWaves) wgrad_fused_kernel(const __bf16*
 
 // Two-stage deterministic sum over chunks: stage 1 (block = 256 entries x one
 // of S slices) sums chunks s, s + S, ... in fp64; stage 2 sums the S slices.
-constexpr int kRedSlices = 32;
+constexpr int kRedSlices = 16;
 
 __global__ void __launch_bounds__(256) reduce_slices_kernel(const float* __restrict__ part, int nchunks, int n,
                                                             double* __restrict__ part2) {
