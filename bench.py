@@ -9,8 +9,12 @@ T 5.0 -> 0.05 over 10^4 sweeps, 16.16 fixed-point couplings, then the exact
 final-state energy and magnetisation of every point.  Inputs (tables, initial
 spins) are resident in HBM before the timed region.
 
-Prints one JSON line (metric, value = visible spin-updates/s, roofline of the
-Gibbs kernel, CPU-oracle baseline).
+The other legs (uneven batch, 48x48 / 96x96 scale, time-to-solution,
+hardware precision, learned MH at 18x18 and at the scale points) follow the
+headline.  Progress lines start with '#'; the last line is one compact JSON
+object (metric, value = visible spin-updates/s, roofline of the Gibbs kernel,
+a few numbers per leg, CPU-oracle baseline); the full per-leg tables go to
+the --detail-out file.
 """
 from __future__ import annotations
 
@@ -31,13 +35,27 @@ SEED = 0x5EED000000000002
 J2S = (0.5, 1.0, 1.5, 2.0)
 HS = tuple(3.0 * j / 15 for j in range(16))
 
-# Algorithmic integer work per visible spin and sweep:
-# 3.5 stochastic units (1 spin + 2.5 hidden), each needing a 16-bit Philox
-# slot (1/8 of a Philox4x32-10 block = 10 rounds x (2 mul-hi/lo + 2 xor3) = 40
-# ops) and one integer compare.
-OPS_PER_SPIN_SWEEP = 3.5 * (40.0 / 8.0 + 1.0)
+# Algorithmic integer work per visible spin and sweep, three models (the
+# headline fraction uses the first; the others are reported beside it):
+#
+# lazy_exact: what an exact Gibbs decision needs.  3.5 stochastic units (1
+#   spin + 2.5 hidden units); comparing a uniform U with a threshold t bit by
+#   bit from the top ends at the first bit where they differ, after 2 bits on
+#   average, so 7 random bits = 7/128 of a Philox4x32-10 block (10 rounds x
+#   (2 multiplies + 2 three-input xors) = 40 ops); one compare per unit; the
+#   hidden unit's 2-spin pattern (1 op) and the spin's 5-term pattern (4 ops)
+#   plus its table lookup (1 op).
+PHILOX_BLOCK_OPS = 40.0
+OPS_LAZY = 7.0 / 128.0 * PHILOX_BLOCK_OPS + 3.5 + 2.5 * 1.0 + 1.0 * (4.0 + 1.0)
+# slot16: a 16-bit uniform slot (1/8 block) and one compare per unit
+OPS_SLOT16 = 3.5 * (PHILOX_BLOCK_OPS / 8.0 + 1.0)
+# uniform32: a full 32-bit uniform (1/4 block) and one compare per unit; the
+#   kernel draws fewer random bits than this, so its fraction exceeds 1
+OPS_U32 = 3.5 * (PHILOX_BLOCK_OPS / 4.0 + 1.0)
 # MI355X integer VALU peak: 256 CUs x 64 lanes x 2.4 GHz (one 32-bit op per lane per clock)
 ALU_PEAK_OPS = 256 * 64 * 2.4e9
+# MI355X LDS peak: 256 CUs x 128 bytes per clock x 2.4 GHz
+LDS_PEAK_BPS = 256 * 128 * 2.4e9
 
 
 def instances(crbm, chains=CHAINS):
@@ -51,46 +69,90 @@ def instances(crbm, chains=CHAINS):
     return out
 
 
-def measured_traffic():
-    """HBM bytes per launch of the 18x18 Gibbs kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None once the kernel sources
-    differ from the ones that were profiled."""
+PROFILE = os.path.join(ROOT, "profiles", "gibbs_kernel_18x18_anneal_64pts.md")
+PROFILE_KEYS = ("traffic_bytes_per_launch", "valu_lane_insts_per_spin_sweep", "lds_bytes_per_spin_sweep",
+                "kernel_sources_sha256_12")
+
+
+def profile_fields():
+    """Counter figures of the 18x18 Gibbs kernel from its committed rocprofv3
+    summary ("key: value" lines), or {} once the kernel sources differ from
+    the ones that were profiled (the summary records their hash)."""
     import hashlib
-    prof = os.path.join(ROOT, "profiles", "gibbs_kernel_18x18_anneal_64pts.md")
     h = hashlib.sha256()
     for f in ("gibbs_kernel.h", "crbm_internal.h"):
         with open(os.path.join(ROOT, "paper_2511_20911_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     try:
-        fields = dict(line.split(": ", 1) for line in open(prof).read().splitlines()
-                      if line.startswith(("traffic_bytes_per_launch: ", "kernel_sources_sha256_12: ")))
+        with open(PROFILE) as fh:
+            fields = dict(line.split(": ", 1) for line in fh.read().splitlines()
+                          if line.split(": ", 1)[0] in PROFILE_KEYS)
     except OSError:
-        return None
+        return {}
     if fields.get("kernel_sources_sha256_12", "").strip() != h.hexdigest()[:12]:
-        return None
-    return int(fields["traffic_bytes_per_launch"])
+        return {}
+    return {k: float(v) for k, v in fields.items() if k != "kernel_sources_sha256_12"}
 
 
-def cpu_baseline(sample_points=3, chains_per_point=3):
-    """The CPU oracle (single-threaded C) on a bounded sample of the same
-    workload: the first chains of a few points, full schedule."""
-    import numpy as np
+def _oracle_worker(job):
+    """One host process of the CPU baseline: full-schedule oracle chains of
+    the 18x18 workload (a list of (point index, chain)).  Returns the final
+    states and the process's own elapsed time."""
     import oracle
-    pts = [(J2S[0], HS[0]), (J2S[1], HS[15]), (J2S[2], HS[7]), (J2S[3], HS[3])][:sample_points]
-    ids = {(J2, h): 16 * J2S.index(J2) + HS.index(h) for J2, h in pts}
-    finals = {}
     t0 = time.perf_counter()
-    for (J2, h) in pts:
-        oi = oracle.Instance(L, 1.0, J2, h, "geometric", 5.0, 0.05, id=ids[(J2, h)])
-        for ch in range(chains_per_point):
-            s, _, _ = oracle.run_chain(oi, S, SEED, ch, 0, S)
-            finals[(ids[(J2, h)], ch)] = s
-    dt = time.perf_counter() - t0
-    n = len(pts) * chains_per_point
-    rate = n * S * L * L / dt
-    return {"value": rate, "unit": "spin-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} chains ({sample_points} points x {chains_per_point}) x {S} sweeps at 18x18, "
-                      f"{dt:.1f} s single-threaded"}, finals
+    finals = {}
+    for k, ch in job:
+        J2, h = J2S[k // 16], HS[k % 16]
+        oi = oracle.Instance(L, 1.0, J2, h, "geometric", 5.0, 0.05, id=k)
+        s, _, _ = oracle.run_chain(oi, S, SEED, ch, 0, S)
+        finals[(k, ch)] = s
+    return finals, time.perf_counter() - t0
+
+
+def host_cpu():
+    """CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
+def cpu_baseline(chains_per_proc=4, max_procs=16):
+    """The CPU oracle (plain single-threaded C) on a bounded sample of the
+    same workload: one oracle process per host core (at most max_procs), each
+    running chains_per_proc full-schedule chains of its own; chain p of point
+    (4p + j) mod 64 for process p, so the processes' chains are disjoint and
+    spread over the points.  Runs before the GPU is touched (forked workers)."""
+    import multiprocessing as mp
+    model, avail = host_cpu()
+    procs = max(1, min(max_procs, avail))
+    jobs = [[((4 * p + j) % 64, p) for j in range(chains_per_proc)] for p in range(procs)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(procs) as pool:
+        res = pool.map(_oracle_worker, jobs)
+    wall = time.perf_counter() - t0
+    finals = {}
+    for f, _ in res:
+        finals.update(f)
+    per_chain = S * L * L
+    per_proc = [chains_per_proc * per_chain / dt for _, dt in res]
+    rate = len(finals) * per_chain / wall
+    return {"value": rate, "unit": "spin-updates/s", "cores": procs, "kind": "oracle",
+            "per_core": float(sum(per_proc) / len(per_proc)),
+            "cpu_model": model, "cpus_available": avail,
+            "sample": f"{len(finals)} chains of the 18x18 workload ({chains_per_proc} per process, "
+                      f"{procs} single-threaded oracle processes on disjoint chains), full {S}-sweep "
+                      f"schedule each, {wall:.1f} s wall"}, finals
 
 
 def batched_uneven(crbm, torch):
@@ -244,7 +306,7 @@ def learned_points(crbm, torch, L=48, steps=400, cycles=60, chains=512):
     r = learned.compare_points(net, pts, L, chains, cycles=cycles, gibbs_per_mh=10, trace_every=10)
     del net
     torch.cuda.empty_cache()
-    r.update({"workload": f"SS Ising {L}x{L}, the 64 scale points (4 phase-boundary lines, T ~ logU[0.1, 1]), "
+    r.update({"channels": 32, "workload": f"SS Ising {L}x{L}, the 64 scale points (4 phase-boundary lines, T ~ logU[0.1, 1]), "
                           f"{chains} chains each in one handle; conditional proposal: 12 masked 3x3 conv layers, "
                           "32 channels, bias offsets from a 3-32-384 tanh MLP of (J2/J1, h/4, ln T); trained on "
                           f"{n_train} Gibbs samples (anneal 5->T over 2000 sweeps, 16 snapshots 50 sweeps apart, "
@@ -347,12 +409,58 @@ def precision_leg(crbm, torch, temps=(0.1, 0.25, 0.5), n_h=65, h_max=8.0, chains
     return out
 
 
+def _r(x, n=4):
+    """Round to n significant digits for the compact result line."""
+    if x is None:
+        return None
+    x = float(x)
+    return float(f"{x:.{n}g}") if x == x and abs(x) != float("inf") else None
+
+
+def summarise(legs):
+    """A few numbers per leg for the final result line (the full tables go to
+    the detail file)."""
+    out = {}
+    b = legs.get("batched_uneven")
+    if b:
+        out["batched_uneven"] = {"spin_updates_per_s": _r(b["spin_updates_per_s"]), "ms": _r(b["ms"]),
+                                 "load_balance_efficiency": _r(b["load_balance_efficiency"], 3)}
+    s = legs.get("scale")
+    if s:
+        out["scale"] = {str(x["L"]): _r(x["spin_updates_per_s"]) for x in s["sizes"]}
+    m = legs.get("learned_mh")
+    if m:
+        out["learned_mh"] = [{"T": p["T"], "acceptance": _r(p["learned"]["acceptance"], 3),
+                              "ess_per_s_learned": _r(p["learned"]["ess_per_s"], 3),
+                              "ess_per_s_gibbs": _r(p["gibbs"]["ess_per_s"], 3),
+                              "ess_ratio": _r(p["ess_ratio"], 3), "ess_min_ratio": _r(p["ess_min_ratio"], 3),
+                              "bias_se_learned": _r(p["learned"]["bias_se"], 2),
+                              "bias_se_gibbs": _r(p["gibbs"]["bias_se"], 2), "train_s": _r(p["train_s"], 3)}
+                             for p in m["points"]]
+    c = legs.get("learned_mh_points")
+    if c:
+        out["learned_mh_points"] = {k: {"channels": v.get("channels"), "acceptance": _r(v["learned"]["acceptance"], 3),
+                                        "ess_min_ratio": _r(v["ess_min_ratio"], 3),
+                                        "agree_3se": v["points_agreeing_within_3se"], "points": len(v["points"])}
+                                    for k, v in c.items()}
+    t = legs.get("tts")
+    if t:
+        out["tts_sweeps"] = {f'{p["phase"]}@{p["L"]}': _r(p["tts99_sweeps"], 3) for p in t["points"]}
+    p = legs.get("precision")
+    if p:
+        out["precision_third_to_fm_h_mid"] = {
+            str(r["T"]): [_r(r[q]["transitions"]["third_to_fm"]["h_mid"], 3) for q in ("q16", "fpga")]
+            for r in p["by_T"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-chains", type=int, default=4, help="oracle chains per host process in the CPU baseline")
     ap.add_argument("--sweeps", type=int, default=S, help="sweeps per step (default: the full schedule)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
@@ -367,11 +475,23 @@ def main():
     ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution runs at the four phase points")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the m(h) comparison of the default and the hardware precision")
+    ap.add_argument("--headline-only", action="store_true", help="skip every leg but the headline")
+    ap.add_argument("--detail-out", type=str, default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file for the full per-leg tables ('' = none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (--gpus 1): chains are independent, and sharding them over "
               "several GPUs is a design, not an implemented path.", file=sys.stderr)
         sys.exit(2)
+    if args.headline_only:
+        args.no_batched = args.no_mh = args.no_scale = args.no_c5_mh = args.no_tts = args.no_precision = True
+    n_sweeps = min(args.sweeps, S)
+
+    # the CPU baseline runs first, in forked host processes, before the GPU is touched
+    base, finals = (None, {})
+    if not args.no_cpu_baseline and n_sweeps == S:
+        base, finals = cpu_baseline(chains_per_proc=args.cpu_chains)
+        print(f"# cpu baseline: {base['sample']}", flush=True)
 
     import numpy as np
     import torch
@@ -398,7 +518,6 @@ def main():
     torch.cuda.synchronize()
     create_ms = (time.perf_counter() - t0) * 1e3
     init_spins, _ = smp.get_state()
-    n_sweeps = min(args.sweeps, S)
     stream = torch.cuda.current_stream()
 
     step_ms, kern_ms = [], []
@@ -419,12 +538,42 @@ def main():
         if it >= args.warmup:
             step_ms.append((t_end - t_start) * 1e3)
             kern_ms.append(k0.elapsed_time(k1))
+        print(f"# step {it}: {(t_end - t_start) * 1e3:.1f} ms", flush=True)
 
     chains = smp.total_chains
-    ms = float(np.mean(step_ms))
-    value = chains * n_sweeps * L * L / (ms / 1e3)
+    ms = float(np.median(step_ms))
+    spin_sweeps = chains * n_sweeps * L * L
+    value = spin_sweeps / (ms / 1e3)
     kms = float(np.mean(kern_ms))
-    achieved = chains * n_sweeps * L * L * OPS_PER_SPIN_SWEEP / (kms / 1e3)
+    kernel_rate = spin_sweeps / (kms / 1e3)
+    achieved = kernel_rate * OPS_LAZY
+    prof = profile_fields() if n_sweeps == S else {}
+    roofline = {
+        "bound": "alu",
+        "achieved": achieved / 1e12,
+        "peak": ALU_PEAK_OPS / 1e12,
+        "unit": "TOP/s",
+        "frac": achieved / ALU_PEAK_OPS,
+        "traffic": prof.get("traffic_bytes_per_launch"),
+        "kernel": f"gibbs_kernel<{L},{rows}>",
+        "kernel_ms": kms,
+        "work_model": "lazy_exact",
+        "ops_per_spin_sweep": {"lazy_exact": OPS_LAZY, "slot16": OPS_SLOT16, "uniform32": OPS_U32},
+        "frac_by_model": {"lazy_exact": _r(achieved / ALU_PEAK_OPS, 3),
+                          "slot16": _r(kernel_rate * OPS_SLOT16 / ALU_PEAK_OPS, 3),
+                          "uniform32": _r(kernel_rate * OPS_U32 / ALU_PEAK_OPS, 3)},
+    }
+    if prof:
+        # issued VALU lane instructions per spin-sweep and the LDS (ds_bpermute)
+        # bytes, from the SQ counters of the same kernel, at this run's speed
+        if "valu_lane_insts_per_spin_sweep" in prof:
+            v = prof["valu_lane_insts_per_spin_sweep"]
+            roofline["valu_lane_insts_per_spin_sweep"] = v
+            roofline["valu_issue_frac"] = _r(kernel_rate * v / ALU_PEAK_OPS, 3)
+        if "lds_bytes_per_spin_sweep" in prof:
+            lb = prof["lds_bytes_per_spin_sweep"]
+            roofline["lds"] = {"achieved": _r(kernel_rate * lb / 1e12, 3), "peak": LDS_PEAK_BPS / 1e12,
+                               "unit": "TB/s", "frac": _r(kernel_rate * lb / LDS_PEAK_BPS, 3)}
     result = {
         "metric": METRIC,
         "value": value,
@@ -444,51 +593,63 @@ def main():
                         "16.16 fixed point, seeded +-1 start",
             "L": L, "points": len(insts), "chains": chains, "sweeps": n_sweeps,
             "node_updates_per_s": value * 3.5,
+            "step_ms_min_max": [min(step_ms), max(step_ms)],
             "create_and_tables_ms": create_ms,
             "tiling": {"rows_per_lane": rows, "lanes_per_chain": (L // 2) // rows, "waves_per_block": wpb,
                        "autotuned": tuning is not None},
         },
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": ALU_PEAK_OPS / 1e12,
-            "unit": "TOP/s",
-            "frac": achieved / ALU_PEAK_OPS,
-            "traffic": measured_traffic() if n_sweeps == S else None,
-            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
-            "kernel": f"gibbs_kernel<{L},{rows}>",
-            "kernel_ms": kms,
-            "ops_per_spin_sweep": OPS_PER_SPIN_SWEEP,
-        },
+        "roofline": roofline,
     }
+    detail = {"headline": dict(result)}
     if obs is not None:
         E = np.array([o["E_per_spin"] for o in obs]).reshape(4, 16)
         m = np.array([o["m"] for o in obs]).reshape(4, 16)
-        result["final_state"] = {"J2": list(J2S), "E_per_spin_mean": E.round(5).tolist(),
+        detail["final_state"] = {"J2": list(J2S), "E_per_spin_mean": E.round(5).tolist(),
                                  "m_mean": m.round(5).tolist()}
-    if not args.no_batched:
-        result["batched_uneven"] = batched_uneven(crbm, torch)
-    if not args.no_scale:
-        result["scale"] = scale_gibbs(crbm, torch)
-    if not args.no_tts:
-        result["tts"] = tts_leg(crbm, torch)
-    if not args.no_precision:
-        result["precision"] = precision_leg(crbm, torch)
-    if not args.no_mh:
-        result["learned_mh"] = learned_mh(crbm, torch)
-    if not args.no_c5_mh:
-        result["learned_mh_points"] = {"48": learned_points(crbm, torch, 48)}
-        if args.c5_mh_96:
-            result["learned_mh_points"]["96"] = learned_points(crbm, torch, 96, steps=200, cycles=20)
-    if not args.no_cpu_baseline and n_sweeps == S:
-        base, finals = cpu_baseline()
-        result["cpu_baseline"] = base
-        # the sampled oracle chains double as a parity check of this very run
+    parity = None
+    if finals:
         spins, _ = smp.get_state()
         parts = smp.split_spins(spins.cpu())
-        result["cpu_baseline"]["parity_sampled_chains"] = all(
-            np.array_equal(parts[i][ch].numpy(), s) for (i, ch), s in finals.items())
-    print(json.dumps(result))
+        parity = all(np.array_equal(parts[i][ch].numpy(), s) for (i, ch), s in finals.items())
+    del smp
+    torch.cuda.empty_cache()
+
+    legs = {}
+    def leg(name, fn):
+        t = time.perf_counter()
+        legs[name] = fn()
+        print(f"# leg {name}: {time.perf_counter() - t:.1f} s", flush=True)
+    if not args.no_batched:
+        leg("batched_uneven", lambda: batched_uneven(crbm, torch))
+    if not args.no_scale:
+        leg("scale", lambda: scale_gibbs(crbm, torch))
+    if not args.no_tts:
+        leg("tts", lambda: tts_leg(crbm, torch))
+    if not args.no_precision:
+        leg("precision", lambda: precision_leg(crbm, torch))
+    if not args.no_mh:
+        leg("learned_mh", lambda: learned_mh(crbm, torch))
+    if not args.no_c5_mh:
+        def c5():
+            r = {"48": learned_points(crbm, torch, 48)}
+            if args.c5_mh_96:
+                r["96"] = learned_points(crbm, torch, 96, steps=200, cycles=20)
+            return r
+        leg("learned_mh_points", c5)
+    detail.update(legs)
+    result["legs"] = summarise(legs)
+    if base is not None:
+        base["parity_sampled_chains"] = parity
+        result["cpu_baseline"] = base
+        detail["cpu_baseline"] = base
+    if args.detail_out:
+        d = os.path.dirname(args.detail_out)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        with open(args.detail_out, "w") as f:
+            json.dump(detail, f, indent=1)
+        result["detail_file"] = args.detail_out
+    print(json.dumps(result, separators=(",", ":")), flush=True)
 
 
 if __name__ == "__main__":

@@ -292,13 +292,20 @@ int crbm_ar_grad(crbm_ar_t* a, const int8_t* samples_dev, int64_t batch, float* 
 /* One Adam step (beta = 0.9, 0.999, eps = 1e-8) at learning rate lr on a batch. */
 int crbm_ar_train_step(crbm_ar_t* a, const int8_t* samples_dev, int64_t batch, float lr, double* loss_out);
 /* log q of n configurations (device int8 [n][L][L]) into logq_dev (device fp64 [n])
- * by one forward pass over all sites.  The per-site arithmetic, and the fp64 sum
+ * by one forward pass over all sites, under the proposal law of
+ * crbm_ar_sample (per site log(t / 2^32) or log(1 - t / 2^32)).  The per-site arithmetic, and the fp64 sum
  * over sites in raster order, are those of crbm_ar_sample, so a proposal scored
  * here gets the log q its sampler returned, bit for bit.  Asynchronous. */
 int crbm_ar_logq(crbm_ar_t* a, const int8_t* spins_dev, int64_t n, double* logq_dev);
-/* n independent proposals (ancestral sampling: spin i = +1 iff u < sigmoid(logit_i),
- * u = 24-bit uniform from Philox (ctr = (site, step, chain, id << 3 | 6), key = seed))
- * into spins_dev (int8 [n][L][L]) with their log q into logq_dev (fp64 [n]). */
+/* n independent proposals by ancestral sampling in raster order into
+ * spins_dev (int8 [n][L][L]) with their log q into logq_dev (fp64 [n]).
+ * With t(x) = clamp(rint(2^32 sigmoid(-|x|)), 1, 2^31) (fp32 sigmoid) for
+ * the logit x of site i, the spin is +1 iff u < 2^32 - t (x >= 0) or u < t
+ * (x < 0), with u word 0 of Philox (ctr = (site, step, chain, id << 3 | 6),
+ * key = seed): the value against the sign of x has probability exactly
+ * t / 2^32, and log q sums log(t / 2^32) or log(1 - t / 2^32) over the sites,
+ * the exact probability of the drawn proposal (for the Metropolis-Hastings
+ * ratio), at any logit. */
 int crbm_ar_sample(crbm_ar_t* a, int64_t n, uint64_t seed, int64_t step, uint32_t id, int8_t* spins_dev,
                    double* logq_dev);
 /* n_steps batches of n proposals in one launch (for an independent-MH

@@ -12,7 +12,16 @@ Network (channels C, 12 layers, 3x3 masked kernels, zero padding):
   z1 = convA(h0) + b1,           h1 = bf16(relu(z1))
   zl = convB(h_{l-1}) + bl,      hl = bf16(h_{l-1} + relu(zl))     l = 2..11
   logit = convB(h11) + b12
-  log q(sigma) = sum_i log sigmoid(sigma_i logit_i)
+  training loss: -sum_i log sigmoid(sigma_i logit_i)
+The proposal draws site i by an integer compare with an exactly known
+probability: with t_i = clamp(rint(2^32 sigmoid(-|logit_i|)), 1, 2^31) (the
+sigmoid in fp32, as the kernels take the decision) the probability of the
+value against the sign of the logit, sigma_i = +1 iff a 32-bit uniform u_i is
+below 2^32 - t_i (logit >= 0) or t_i (logit < 0); the proposal's log q sums
+log(t_i / 2^32) (minority) or log(1 - t_i / 2^32) over the sites.  It
+differs from the sigmoid law by at most half a unit in 2^-32 per site, and it
+is the probability with which the proposal was really drawn, which the
+Metropolis-Hastings ratio needs.
 Mask A taps (dr, dc): (-1,-1) (-1,0) (-1,1) (0,-1) (sites strictly before the
 current one in raster order); mask B adds the centre (0,0).  The logit at a
 site therefore depends only on earlier sites.
@@ -133,7 +142,8 @@ def cond_grad(cond, feats, point_idx, gbias):
 
 
 def forward(params, spins, emulate_bf16=True, bias_add=None):
-    """spins [B, L, L] of +-1 -> (log q [B], cache for backward).  bias_add
+    """spins [B, L, L] of +-1 -> (sum of log sigmoid(s_i logit_i) [B], the
+    training law, and the cache for backward).  bias_add
     [B, 12, C] (optional): per-sample bias offsets of a conditional network."""
     rb = bf16 if emulate_bf16 else (lambda v: np.asarray(v, np.float64))
     s = np.asarray(spins, np.float64)
@@ -194,17 +204,52 @@ def loss_and_grad(params, spins, emulate_bf16=True, bias_add=None, per_sample_bi
     return -logq.mean(), grads
 
 
+def minority_threshold(logit):
+    """t = clamp(rint(2^32 sigmoid(-|x|)), 1, 2^31) with the sigmoid in fp32
+    (the precision in which the kernels take the decision); uint64 array."""
+    x = np.abs(np.asarray(logit, np.float32))
+    e = np.exp(-x).astype(np.float32)
+    p = (e / (np.float32(1.0) + e)).astype(np.float32)
+    t = np.rint(p.astype(np.float64) * 2.0 ** 32)  # p 2^32 is exact: a power-of-two scale
+    return np.clip(np.nan_to_num(t, nan=1.0), 1.0, 2.0 ** 31).astype(np.uint64)
+
+
+def proposal_site_logq(logit, spins):
+    """log of the probability with which the proposal draws each site's spin:
+    log(t / 2^32) for the minority value, log(1 - t / 2^32) for the sign of the
+    logit."""
+    x = np.asarray(logit, np.float32)
+    t = minority_threshold(x).astype(np.float64) * 2.0 ** -32
+    majority = (x >= 0) == (np.asarray(spins) > 0)
+    return np.where(majority, np.log1p(-t), np.log(t))
+
+
+def proposal_logq(logit, spins):
+    """log q of configurations [B, L, L] under the proposal's integer rule."""
+    return proposal_site_logq(logit, spins).sum(axis=(1, 2))
+
+
+def up_threshold(logit):
+    """sigma = +1 iff u < this: 2^32 - t for logit >= 0, t for logit < 0."""
+    x = np.asarray(logit, np.float32)
+    t = minority_threshold(x).astype(np.int64)
+    return np.where(x >= 0, (1 << 32) - t, t).astype(np.uint64)
+
+
 def sample(params, n, L, uniforms, emulate_bf16=True, bias_add=None):
-    """Ancestral sampling in raster order; uniforms [n, L*L] in [0, 1):
-    sigma_i = +1 iff u_i < sigmoid(logit_i).  Returns spins and log q."""
+    """Ancestral sampling in raster order; uniforms [n, L*L] of 32-bit
+    integers: sigma_i = +1 iff u_i < up_threshold(logit_i).  Returns spins
+    and their proposal log q."""
     s = np.zeros((n, L, L))
+    u = np.asarray(uniforms, np.uint64)
     for i in range(L * L):
         r, c = divmod(i, L)
-        logq, cache = forward(params, s, emulate_bf16, bias_add)
-        p = 1.0 / (1.0 + np.exp(-cache["logit"][:, r, c]))
-        s[:, r, c] = np.where(uniforms[:, i] < p, 1.0, -1.0)
-    logq, _ = forward(params, s, emulate_bf16, bias_add)
-    return s.astype(np.int8), logq
+        _, cache = forward(params, s, emulate_bf16, bias_add)
+        x = cache["logit"][:, r, c]
+        up = u[:, i] < up_threshold(x)
+        s[:, r, c] = np.where(up, 1.0, -1.0)
+    _, cache = forward(params, s, emulate_bf16, bias_add)
+    return s.astype(np.int8), proposal_logq(cache["logit"], s)
 
 
 def log_target(counts, wq1, sg1, wq2, sg2, aq, L):

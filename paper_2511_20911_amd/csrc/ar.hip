@@ -9,7 +9,14 @@
 // padding.  Layer 1 uses mask A (the 4 sites before the centre in raster
 // order), layers 2-12 mask B (plus the centre).  Layers 2-11 are residual,
 // h_l = bf16(h_{l-1} + relu(z_l)); layer 12 gives one logit per site.
-// log q(s) = sum_i log sigmoid(s_i logit_i).
+// Training fits log sigmoid(s_i logit_i) per site.  The proposal draws each
+// spin by an integer compare whose probability is exactly representable: with
+// t(x) = clamp(rint(2^32 sigmoid(-|x|)), 1, 2^31) the probability of the
+// value against the sign of the logit x (the minority value; +1 counts as the
+// sign of 0), the spin is +1 iff a 32-bit uniform u < t_up(x), t_up = 2^32 - t
+// for x >= 0 and t for x < 0 (monotone in x), so P(minority) = t / 2^32
+// exactly, and log q(s) sums the logs of exactly these probabilities.  The Metropolis-Hastings ratio then uses the probability of
+// the proposal that was really drawn, at every logit, however confident.
 //
 // Layouts: activations [pixel][32] bf16 (pixel = (b L + r) L + c), channel
 // dimension padded to 32 for the 1-channel input and output; weights per layer
@@ -97,6 +104,33 @@ __device__ __forceinline__ uint32_t edge_flags(int64_t p, int L) {
 __device__ __forceinline__ int64_t shift_pix(int64_t p, uint32_t f, int dr, int dc, int L) {
     const uint32_t need = (dr < 0 ? 1u : 0u) | (dr > 0 ? 2u : 0u) | (dc < 0 ? 4u : 0u) | (dc > 0 ? 8u : 0u);
     return (f & need) == need ? p + (int64_t)(dr * L + dc) : -1;
+}
+
+// Minority threshold of a site with logit x (fp32 arithmetic): the value
+// against the sign of x has probability t / 2^32, t = clamp(rint(2^32
+// sigmoid(-|x|)), 1, 2^31).  p 2^32 is exact (a power-of-two scale), so the
+// rounding is the only one after the sigmoid.  NaN gives t = 1.
+__device__ __forceinline__ uint32_t minority_threshold(float x) {
+    const float e = expf(-fabsf(x));
+    const float p = e / (1.0f + e);
+    const float t = fminf(fmaxf(rintf(p * 4294967296.0f), 1.0f), 2147483648.0f);
+    return (uint32_t)t;
+}
+
+// The spin is +1 iff its 32-bit uniform is below this: 2^32 - t for x >= 0,
+// t for x < 0 (monotone in x, 2^31 at x = 0 from both sides).
+__device__ __forceinline__ uint32_t up_threshold(float x) {
+    const uint32_t t = minority_threshold(x);
+    return x >= 0.0f ? 0u - t : t;
+}
+
+// log of the probability with which the proposal drew spin s (+-1) at a site
+// with logit x: log(t / 2^32) for the minority value, log(1 - t / 2^32) for
+// the sign of x, in fp64.
+__device__ __forceinline__ double site_logq(float x, float s) {
+    const double t = (double)minority_threshold(x) * 0x1p-32;
+    const bool majority = (x >= 0.0f) == (s > 0.0f);
+    return majority ? log1p(-t) : log(t);
 }
 
 // A point index clamped to the points that exist.
@@ -440,8 +474,9 @@ __global__ void __launch_bounds__(256) loss_kernel(const float* logit, const int
     if (threadIdx.x == 0) logq[b] = red[0];
 }
 
-// log q per chain from per-site logits: log q = sum_i -log1p(exp(-s_i l_i))
-// in fp64.  One wavefront per chain: lane k sums the sites k, k + 64, ... in
+// log q per chain from per-site logits: the sum over sites of site_logq, the
+// log-probability with which the sampler's integer rule draws that spin, in
+// fp64.  One wavefront per chain: lane k sums the sites k, k + 64, ... in
 // order, then a fixed butterfly over the 64 lane sums.  The sampler and the
 // scorer both reduce their logits with this kernel, so equal logits give
 // bit-identical log q.
@@ -452,8 +487,7 @@ __global__ void __launch_bounds__(256) logq_kernel(const float* __restrict__ log
     if (ch >= n) return;  // uniform per wavefront
     double s = 0.0;
     for (int i = lane; i < N; i += 64) {
-        const float sg = (float)spins[ch * N + i];
-        s += -log1p(exp(-(double)(sg * logit[ch * N + i])));
+        s += site_logq(logit[ch * N + i], (float)spins[ch * N + i]);
     }
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d);
@@ -928,8 +962,8 @@ __global__ void __launch_bounds__(256) score_fused_kernel(int64_t n, int L, cons
 // previous site; the taps of the row above come from a one-row ring in global
 // memory, each element read once into a window that slides along the row.
 // The weights of the next layer are loaded while a layer finishes.  Spin i is
-// +1 iff u < sigmoid(logit), u the top 24 bits of Philox (ctr = (site, step,
-// chain, id << 3 | 6)), drawn by the lane that holds the logit at the end of
+// +1 iff u < up_threshold(logit), u = word 0 of Philox (ctr = (site, step,
+// chain, id << 3 | 6)), decided by the lane that holds the logit at the end of
 // the last layer; the logits go to logit_out for the log q sum.
 constexpr int kSeqMaxWaves = 4;
 // MH: proposals of several cycles per sampler launch, up to this many chains
@@ -1038,7 +1072,7 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
         }
         const gk::P4 q = gk::philox((uint32_t)site, stepr, (uint32_t)gcr, (id << 3) | 6u, (uint32_t)seed,
                                     (uint32_t)(seed >> 32));
-        const float u = (float)(q.v[0] >> 8) * (1.0f / 16777216.0f);
+        const uint32_t u = q.v[0];
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
             const bool last = l == NL - 1;
@@ -1079,8 +1113,8 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
             } else {
                 // the logit is output channel 0: element 0 of the lanes with kg == 0
                 const float x = acc0[0];
-                const float p = 1.f / (1.f + expf(-x));
-                const __bf16 sg = f2bf((u < p) ? 1.f : -1.f);
+                const bool up = u < up_threshold(x);
+                const __bf16 sg = f2bf(up ? 1.f : -1.f);
                 bf16x8 s8 = zero8();
                 if (kg == 0) {
                     s8[0] = sg;  // the first layer's input fragment: channel 0 is the spin, the rest 0

@@ -107,7 +107,7 @@ def test_crbm_marginal_is_boltzmann(L, J2, h, T):
     slack is the 16.16 rounding of the weights and bias."""
     inst = oracle.Instance(L, 1.0, J2, h, "const", T)
     if L == 4:
-        states = P.all_states(4)[::7]
+        states = P.all_states(4)
     else:
         rng = np.random.default_rng(3)
         states = (2 * rng.integers(0, 2, (400, L, L)) - 1).astype(np.int8)
