@@ -200,6 +200,26 @@ int crbm_tau_int(const int32_t* trace_dev, int64_t n_samples, int64_t trace_chai
                  int64_t discard, const double w[3], int32_t max_lag, double c_window, void* stream,
                  double* tau_out, double* ess_out, int32_t* window_out, double* rho_out);
 
+/* crbm_tau_int without device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, arithmetic and results as
+ * crbm_tau_int (bit for bit).  Its scratch (chain means, the centred series,
+ * per-block and per-lag sums) is one file-scope device array of
+ * CRBM_TAU_NOALLOC_MAX_DOUBLES doubles (64 MiB) per device, held until the
+ * process ends; a request needs (c1 - c0) (n_samples - discard + 1) + 1 +
+ * (K + 1) (ceil((c1 - c0) / 256) + 1) doubles with K = min(max_lag,
+ * n_samples - discard - 1), and K <= CRBM_TAU_NOALLOC_MAX_LAG; larger
+ * requests return CRBM_ERANGE before any work is enqueued.  Every scratch
+ * word the call reads it has written first, so nothing needs clearing.  All
+ * calls on one device share that device's array: calls that overlap in time
+ * on one device (several streams or host threads) race and must be
+ * serialised by the caller.  Synchronises `stream`. */
+#define CRBM_TAU_NOALLOC_MAX_DOUBLES (8 * 1024 * 1024)
+#define CRBM_TAU_NOALLOC_MAX_LAG 4096
+int crbm_tau_int_noalloc(const int32_t* trace_dev, int64_t n_samples, int64_t trace_chains, int64_t c0, int64_t c1,
+                         int64_t discard, const double w[3], int32_t max_lag, double c_window, void* stream,
+                         double* tau_out, double* ess_out, int32_t* window_out, double* rho_out);
+
 /* Ground-state search behind the time-to-solution of Sec. III.C Eq. (14)
  * (the host picks the lowest-energy states it has sampled, App. A I/O
  * Programming Logic): fold a counts trace written by crbm_sample /

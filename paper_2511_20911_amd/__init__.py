@@ -133,6 +133,7 @@ def lib() -> ct.CDLL:
         L.crbm_tau_int.argtypes = [ct.c_void_p, ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int64,
                                    p(ct.c_double), ct.c_int32, ct.c_double, ct.c_void_p, p(ct.c_double),
                                    p(ct.c_double), p(ct.c_int32), p(ct.c_double)]
+        L.crbm_tau_int_noalloc.argtypes = L.crbm_tau_int.argtypes
         L.crbm_get_tiling.argtypes = [ct.c_int32, p(ct.c_int32), p(ct.c_int32)]
         _lib = L
     return _lib
@@ -182,9 +183,10 @@ def autotune(L: int, n_chains: int = 4096, n_sweeps: int = 50, stream=None):
 
 
 def tau_int(trace, weights, c0: int = 0, c1: Optional[int] = None, discard: int = 0, max_lag: int = 2000,
-            c_window: float = 6.0, stream=None):
+            c_window: float = 6.0, stream=None, noalloc: bool = False):
     """tau_int, ESS, window and rho(k) of O = w0 M + w1 B1 + w2 B2 over a
-    device counts trace [n_samples, chains, 3] (int32)."""
+    device counts trace [n_samples, chains, 3] (int32).  noalloc: through
+    crbm_tau_int_noalloc (no device allocation; bounded request size)."""
     assert trace.is_cuda and trace.dim() == 3 and trace.shape[2] == 3 and trace.element_size() == 4
     trace = trace.contiguous()
     n, nch = int(trace.shape[0]), int(trace.shape[1])
@@ -193,9 +195,10 @@ def tau_int(trace, weights, c0: int = 0, c1: Optional[int] = None, discard: int 
     K = min(max_lag, n - discard - 1)
     rho = np.zeros(K + 1, np.float64)
     tau, ess, win = ct.c_double(), ct.c_double(), ct.c_int32()
-    _check(lib().crbm_tau_int(ct.c_void_p(trace.data_ptr()), n, nch, c0, c1, discard, w, max_lag, c_window,
-                              _stream_handle(stream), ct.byref(tau), ct.byref(ess), ct.byref(win),
-                              rho.ctypes.data_as(ct.POINTER(ct.c_double))))
+    fn = lib().crbm_tau_int_noalloc if noalloc else lib().crbm_tau_int
+    _check(fn(ct.c_void_p(trace.data_ptr()), n, nch, c0, c1, discard, w, max_lag, c_window,
+              _stream_handle(stream), ct.byref(tau), ct.byref(ess), ct.byref(win),
+              rho.ctypes.data_as(ct.POINTER(ct.c_double))))
     return float(tau.value), float(ess.value), int(win.value), rho
 
 

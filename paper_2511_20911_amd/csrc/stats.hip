@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "crbm.h"
@@ -102,6 +103,49 @@ __global__ void min_energy_kernel(const int32_t* trace, int64_t n, int64_t strid
     first[c] = at;
 }
 
+// one thread per lag k: the autocovariance sum at lag k over the chain
+// blocks' partial sums, added in block order (the order in which the host
+// adds them in crbm_tau_int, so both entry points give the same sums)
+__global__ void lag_sum_kernel(const double* part, int K, int nblk, double* sums) {
+    const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k > K) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(int64_t)k * nblk + b];
+    sums[k] = s;
+}
+
+// Scratch of crbm_tau_int_noalloc: chain means and grand mean, the centred
+// series and the per-block partial sums, all in one file-scope device array
+// (each device holds its own copy).  Host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
+constexpr int64_t kTauScratchDoubles = CRBM_TAU_NOALLOC_MAX_DOUBLES;
+__device__ __align__(256) double scratch[kTauScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// Device address of the current device's scratch array, looked up once per
+// device.  Returns nullptr (with the error set) if the lookup fails.
+double* scratch_ptr() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        set_error(CRBM_EHIP, "crbm_tau_int_noalloc: no current device");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(CRBM_EHIP, "crbm_tau_int_noalloc: hipGetSymbolAddress failed");
+            return nullptr;
+        }
+        g_scratch[dev] = static_cast<double*>(p);
+    }
+    return g_scratch[dev];
+}
+
 }  // namespace
 }  // namespace crbmlib
 
@@ -181,6 +225,67 @@ extern "C" int crbm_tau_int(const int32_t* trace_dev, int64_t n_samples, int64_t
     }
     if (rho_out)
         for (int k = 0; k <= K; ++k) rho_out[k] = gam[0] > 0.0 ? gam[k] / gam[0] : (k == 0 ? 1.0 : 0.0);
+    *tau_out = tau;
+    if (ess_out) *ess_out = (double)nc * (double)m / tau;
+    if (window_out) *window_out = W;
+    set_error(CRBM_OK, "");
+    return CRBM_OK;
+}
+
+extern "C" int crbm_tau_int_noalloc(const int32_t* trace_dev, int64_t n_samples, int64_t trace_chains, int64_t c0,
+                                    int64_t c1, int64_t discard, const double w[3], int32_t max_lag,
+                                    double c_window, void* stream, double* tau_out, double* ess_out,
+                                    int32_t* window_out, double* rho_out) {
+    if (!trace_dev || !w || !tau_out || n_samples < 2 || trace_chains < 1 || c0 < 0 || c1 > trace_chains ||
+        c1 <= c0 || discard < 0 || n_samples - discard < 2 || max_lag < 1 || !(c_window > 0.0))
+        return set_error(CRBM_EINVAL, "crbm_tau_int_noalloc: bad arguments");
+    const int64_t nc = c1 - c0, m = n_samples - discard;
+    const int K = (int)std::min<int64_t>(max_lag, m - 1);
+    const int nblk = (int)((nc + 255) / 256);
+    if (K > CRBM_TAU_NOALLOC_MAX_LAG)
+        return set_error(CRBM_ERANGE, "crbm_tau_int_noalloc: max_lag (capped at n_samples - discard - 1) exceeds "
+                                      "CRBM_TAU_NOALLOC_MAX_LAG");
+    // scratch layout: [nc + 1] means | [m nc] centred series | [(K + 1) nblk] partials | [K + 1] lag sums
+    const int64_t need = (nc + 1) + m * nc + (int64_t)(K + 1) * nblk + (K + 1);
+    if (nc > kTauScratchDoubles || m > kTauScratchDoubles || need > kTauScratchDoubles)
+        return set_error(CRBM_ERANGE, "crbm_tau_int_noalloc: the request needs more than "
+                                      "CRBM_TAU_NOALLOC_MAX_DOUBLES doubles of scratch");
+    double* base = scratch_ptr();
+    if (!base) return CRBM_EHIP;
+    hipStream_t st = (hipStream_t)stream;
+    double* d_mean = base;
+    double* d_x = d_mean + (nc + 1);
+    double* d_part = d_x + m * nc;
+    double* d_sums = d_part + (int64_t)(K + 1) * nblk;
+    // every scratch word that is read is written first in this call: no clearing needed
+    hipLaunchKernelGGL(chain_mean_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, trace_dev,
+                       n_samples, trace_chains, c0, nc, discard, w[0], w[1], w[2], d_mean);
+    hipLaunchKernelGGL(grand_mean_kernel, dim3(1), dim3(256), 0, st, d_mean, nc, d_mean + nc);
+    hipLaunchKernelGGL(centre_kernel, dim3((unsigned)((m * nc + 255) / 256)), dim3(256), 0, st, trace_dev,
+                       n_samples, trace_chains, c0, nc, discard, w[0], w[1], w[2], d_mean + nc, d_x);
+    hipLaunchKernelGGL(autocov_kernel, dim3((unsigned)(K + 1), (unsigned)nblk), dim3(256), 0, st, d_x, m, nc, K,
+                       d_part, nblk);
+    hipLaunchKernelGGL(lag_sum_kernel, dim3((unsigned)((K + 1 + 255) / 256)), dim3(256), 0, st, d_part, K, nblk,
+                       d_sums);
+    hipError_t e = hipGetLastError();
+    double sums[CRBM_TAU_NOALLOC_MAX_LAG + 1];
+    if (e == hipSuccess) e = hipMemcpyAsync(sums, d_sums, sizeof(double) * (size_t)(K + 1), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return set_error(CRBM_EHIP, hipGetErrorString(e));
+    for (int k = 0; k <= K; ++k) sums[k] = sums[k] / (double)(m - k) / (double)nc;
+    double tau = 1.0;
+    int W = K;
+    if (sums[0] > 0.0) {
+        for (int k = 1; k <= K; ++k) {
+            tau += 2.0 * sums[k] / sums[0];
+            if ((double)k >= c_window * tau) {
+                W = k;
+                break;
+            }
+        }
+    }
+    if (rho_out)
+        for (int k = 0; k <= K; ++k) rho_out[k] = sums[0] > 0.0 ? sums[k] / sums[0] : (k == 0 ? 1.0 : 0.0);
     *tau_out = tau;
     if (ess_out) *ess_out = (double)nc * (double)m / tau;
     if (window_out) *window_out = W;
