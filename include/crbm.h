@@ -57,7 +57,7 @@ enum {
 };
 
 #define CRBM_MAX_L 96      /* largest lattice side supported by this library */
-#define CRBM_N_ACC 11      /* per-chain accumulator words, see crbm_obs */
+#define CRBM_N_ACC 14      /* per-chain accumulator words, see crbm_obs */
 
 /* One Hamiltonian point (one "instance").  Host memory, copied at create. */
 typedef struct {
@@ -81,7 +81,17 @@ typedef struct {
     int32_t launch_mode;       /* CRBM_LAUNCH_DIRECT or CRBM_LAUNCH_GRAPH */
     int32_t waves_per_block;   /* 1..4 wavefronts per workgroup; 0 = tuned/default choice */
     int32_t precision;         /* CRBM_PRECISION_* (0 = the default 16.16 / 32-bit path) */
+    uint32_t flags;            /* CRBM_F_* */
 } crbm_config;
+
+/* crbm_config.flags.  CRBM_F_CORR: accumulate the spin-spin correlation
+ * C(dr, dc) = sum_{r,c} s(r,c) s(r+dr, c+dc) of every chain after every
+ * measured sweep (the sweeps crbm_obs accumulates), exactly in int64, for the
+ * static structure factor S(q) of Sec. III.B Eq. (13); crbm_observables
+ * returns the sums.  A measured sweep then ends a kernel launch, so sampling
+ * runs one launch per measured sweep (direct launches, also for
+ * CRBM_LAUNCH_GRAPH handles). */
+#define CRBM_F_CORR 1u
 
 /* Arithmetic of the per-sweep weights, fields and sigmoid thresholds.
  * CRBM_PRECISION_Q16: 16.16 weights and bias, 32-bit thresholds and uniforms.
@@ -112,11 +122,13 @@ typedef struct {
     int64_t sum_M, sum_B1, sum_B2;
     int64_t sum_MM, sum_B1B1, sum_B2B2, sum_MB1, sum_MB2, sum_B1B2;
     int64_t sum_absM;
+    int64_t sum_Ms, sum_MsMs, sum_absMs;      /* staggered magnetisation Ms = sum (-1)^(r+c) s(r,c) */
     double E_per_spin;                        /* <E>/N from the exact sums */
     double m;                                 /* <M>/N */
     double abs_m;                             /* <|M|>/N */
     double dimer;                             /* -<B2>/(N/2): +1 for antiparallel dimers */
     double E_var_per_spin;                    /* (<E^2> - <E>^2)/N from the exact second moments */
+    double abs_stag_m;                        /* <|Ms|>/N: 1 in a Neel state (Sec. III.A AFM phase) */
 } crbm_obs;
 
 typedef struct crbm_s crbm_t;
@@ -154,9 +166,13 @@ int crbm_sample_thinned(crbm_t* h, int64_t n_sweeps, int8_t* spins_out, int32_t*
 
 /* Synchronise the stream and fill out[n_inst] from the exact int64
  * accumulators.  corr_out: host pointer or NULL; if given, receives for each
- * instance the sum over its chains of C(dr,dc) = sum_{r,c} s(r,c) s(r+dr,c+dc)
- * of the CURRENT state, int64 [L][L] per instance, instances concatenated
- * (S(q) of Eq. (13) is its 2-D Fourier transform). */
+ * instance, int64 [L][L] per instance, instances concatenated, the sum of
+ * C(dr,dc) = sum_{r,c} s(r,c) s(r+dr,c+dc):
+ *   - handles created with CRBM_F_CORR: over its chains and all measured
+ *     sweeps since creation or the last crbm_reset_observables (the same
+ *     samples as out[i].n_samples, so C/n_samples is the sample average);
+ *   - other handles: over its chains in the current state only.
+ * S(q) of Eq. (13) is the 2-D Fourier transform of the average. */
 int crbm_observables(crbm_t* h, crbm_obs* out, int64_t* corr_out);
 
 /* Checkpoint / resume.  spins: device pointer, int8 +-1, same layout as

@@ -83,7 +83,9 @@ def lib():
         L.oracle_order.argtypes = [ct.c_int, p(ct.c_int8), p(i64)]
         L.oracle_init_spins.argtypes = [p(_Instance), ct.c_uint64, u32, p(ct.c_int8)]
         L.oracle_run_chain.argtypes = [p(_Instance), i64, ct.c_uint64, u32, i64, i64,
-                                       p(ct.c_int8), p(i32), i32, i64, p(i64)]
+                                       p(ct.c_int8), p(i32), i32, i64, p(i64), p(i64)]
+        L.oracle_staggered.argtypes = [ct.c_int, p(ct.c_int8)]
+        L.oracle_staggered.restype = i64
         L.oracle_run_chain.restype = ct.c_int
         L.oracle_log_marginal.argtypes = [p(_Instance), i64, i64, p(ct.c_int8)]
         L.oracle_log_marginal.restype = dbl
@@ -215,15 +217,23 @@ def log_marginal(inst: Instance, S: int, sweep: int, spins) -> float:
     return float(lib().oracle_log_marginal(ct.byref(ci), S, sweep, _ptr(s, ct.c_int8)))
 
 
-N_ACC = 11  # n, M, B1, B2, MM, B1B1, B2B2, MB1, MB2, B1B2, |M|
+N_ACC = 14  # n, M, B1, B2, MM, B1B1, B2B2, MB1, MB2, B1B2, |M|, Ms, MsMs, |Ms|
+
+
+def staggered(L, spins) -> int:
+    """Staggered magnetisation sum (-1)^(r+c) s(r,c) of one configuration."""
+    s = np.ascontiguousarray(spins, np.int8).reshape(L * L)
+    return int(lib().oracle_staggered(L, _ptr(s, ct.c_int8)))
 
 
 def run_chain(inst: Instance, S: int, seed: int, chain: int, sweep_begin: int, sweep_end: int,
-              spins=None, trace=False, measure_every=0, burn_in=0, acc=None):
+              spins=None, trace=False, measure_every=0, burn_in=0, acc=None, corr=None):
     """Run sweeps [sweep_begin, sweep_end) of one chain.
 
     spins: None -> initialise from the init stream; else an (L, L) int8 array
-    of +-1 (copied).  Returns (spins, trace or None, acc)."""
+    of +-1 (copied).  corr: None, or an int64 array of L*L entries to which
+    C(dr, dc) of the state after every measured sweep is added.
+    Returns (spins, trace or None, acc)."""
     L = inst.L
     if spins is None:
         s = init_spins(inst, seed, chain).reshape(L * L).copy()
@@ -235,7 +245,8 @@ def run_chain(inst: Instance, S: int, seed: int, chain: int, sweep_begin: int, s
     ci = inst.c()
     rc = lib().oracle_run_chain(
         ct.byref(ci), S, seed, chain, sweep_begin, sweep_end, _ptr(s, ct.c_int8),
-        _ptr(tr, ct.c_int32) if trace else None, measure_every, burn_in, _ptr(a, ct.c_int64))
+        _ptr(tr, ct.c_int32) if trace else None, measure_every, burn_in, _ptr(a, ct.c_int64),
+        None if corr is None else _ptr(corr, ct.c_int64))
     if rc != 0:
         raise RuntimeError(f"oracle_run_chain failed: {rc}")
     return s.reshape(L, L), tr, a

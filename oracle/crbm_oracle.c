@@ -301,6 +301,17 @@ void oracle_counts(int L, const int8_t* s, int64_t* M, int64_t* B1, int64_t* B2)
     *M = m; *B1 = b1; *B2 = b2;
 }
 
+/* Staggered (Neel) magnetisation sum_{r,c} (-1)^(r+c) s(r,c): +-N in the two
+ * Neel states of the square-lattice bonds (the antiferromagnetic phase of
+ * Sec. III.A, whose S(q) peaks at (pi, pi) in Sec. III.B). */
+int64_t oracle_staggered(int L, const int8_t* s)
+{
+    int64_t ms = 0;
+    for (int r = 0; r < L; ++r)
+        for (int c = 0; c < L; ++c) ms += ((r + c) % 2 == 0) ? s[r * L + c] : -s[r * L + c];
+    return ms;
+}
+
 void oracle_corr(int L, const int8_t* s, int64_t* corr)
 {
     /* corr[dr * L + dc] += sum_{r,c} s(r,c) s(r+dr, c+dc) */
@@ -392,7 +403,8 @@ static int8_t gibbs_unit16(int64_t x, int64_t lim, uint32_t U)
 
 int oracle_run_chain(const oracle_instance* in, int64_t S, uint64_t seed, uint32_t chain,
                      int64_t sweep_begin, int64_t sweep_end, int8_t* s,
-                     int32_t* trace, int32_t measure_every, int64_t burn_in, int64_t* acc)
+                     int32_t* trace, int32_t measure_every, int64_t burn_in, int64_t* acc,
+                     int64_t* corr_acc)
 {
     int L = in->L;
     int C = L / 2;
@@ -440,6 +452,7 @@ int oracle_run_chain(const oracle_instance* in, int64_t S, uint64_t seed, uint32
                 s[r * L + c] = in->precision == 1 ? gibbs_unit16(field[r * L + c], ACC_MAX, U)
                                                   : gibbs_unit(field[r * L + c], U);
             }
+        const int measured = measure_every > 0 && sw >= burn_in && (sw - burn_in) % measure_every == 0;
         if (trace || acc) {
             int64_t M, B1, B2;
             oracle_counts(L, s, &M, &B1, &B2);
@@ -447,14 +460,17 @@ int oracle_run_chain(const oracle_instance* in, int64_t S, uint64_t seed, uint32
                 int32_t* t = trace + 3 * (sw - sweep_begin);
                 t[0] = (int32_t)M; t[1] = (int32_t)B1; t[2] = (int32_t)B2;
             }
-            if (acc && measure_every > 0 && sw >= burn_in && (sw - burn_in) % measure_every == 0) {
+            if (acc && measured) {
+                int64_t ms = oracle_staggered(L, s);
                 acc[0] += 1;
                 acc[1] += M; acc[2] += B1; acc[3] += B2;
                 acc[4] += M * M; acc[5] += B1 * B1; acc[6] += B2 * B2;
                 acc[7] += M * B1; acc[8] += M * B2; acc[9] += B1 * B2;
                 acc[10] += (M < 0) ? -M : M;
+                acc[11] += ms; acc[12] += ms * ms; acc[13] += (ms < 0) ? -ms : ms;
             }
         }
+        if (corr_acc && measured) oracle_corr(L, s, corr_acc);  /* Sec. III.B Eq. (13): summed C(dr, dc) */
     }
     free(hid);
     free(field);

@@ -34,11 +34,13 @@ uint32_t oracle_threshold(int64_t y);
 void     oracle_bond_sites(int L, int k, int i, int j, int* ra, int* ca, int* rb, int* cb, int* type);
 void     oracle_counts(int L, const int8_t* s, int64_t* M, int64_t* B1, int64_t* B2);
 void     oracle_corr(int L, const int8_t* s, int64_t* corr);
+int64_t  oracle_staggered(int L, const int8_t* s);
 void     oracle_order(int L, const int8_t* s, int64_t out[3]);
 void     oracle_init_spins(const oracle_instance* in, uint64_t seed, uint32_t chain, int8_t* s);
 int      oracle_run_chain(const oracle_instance* in, int64_t S, uint64_t seed, uint32_t chain,
                           int64_t sweep_begin, int64_t sweep_end, int8_t* s,
-                          int32_t* trace, int32_t measure_every, int64_t burn_in, int64_t* acc);
+                          int32_t* trace, int32_t measure_every, int64_t burn_in, int64_t* acc,
+                          int64_t* corr_acc);
 double   oracle_log_marginal(const oracle_instance* in, int64_t S, int64_t sweep, const int8_t* s);
 
 #endif

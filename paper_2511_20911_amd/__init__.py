@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libcrbm.so")
 
 CRBM_OK, CRBM_EINVAL, CRBM_ERANGE, CRBM_ENOMEM, CRBM_EHIP, CRBM_EUNSUPPORTED, CRBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
 SCHED = {"const": 0, "linear": 1, "geometric": 2, "explicit": 3}
-N_ACC = 11
+N_ACC = 14
 MAX_L = 96
 SUPPORTED_L = tuple(range(4, 33, 2)) + (36, 40, 48, 64, 72, 96)
 
@@ -47,7 +47,11 @@ class _Config(ct.Structure):
         ("seed", ct.c_uint64), ("n_sweeps", ct.c_int64), ("measure_every", ct.c_int32),
         ("burn_in", ct.c_int64), ("stream", ct.c_void_p), ("tile_rows", ct.c_int32),
         ("launch_mode", ct.c_int32), ("waves_per_block", ct.c_int32), ("precision", ct.c_int32),
+        ("flags", ct.c_uint32),
     ]
+
+
+CRBM_F_CORR = 1
 
 
 LAUNCH = {"direct": 0, "graph": 1}
@@ -61,8 +65,9 @@ class _Obs(ct.Structure):
         ("sum_MM", ct.c_int64), ("sum_B1B1", ct.c_int64), ("sum_B2B2", ct.c_int64),
         ("sum_MB1", ct.c_int64), ("sum_MB2", ct.c_int64), ("sum_B1B2", ct.c_int64),
         ("sum_absM", ct.c_int64),
+        ("sum_Ms", ct.c_int64), ("sum_MsMs", ct.c_int64), ("sum_absMs", ct.c_int64),
         ("E_per_spin", ct.c_double), ("m", ct.c_double), ("abs_m", ct.c_double),
-        ("dimer", ct.c_double), ("E_var_per_spin", ct.c_double),
+        ("dimer", ct.c_double), ("E_var_per_spin", ct.c_double), ("abs_stag_m", ct.c_double),
     ]
 
 
@@ -249,7 +254,7 @@ class Sampler:
 
     def __init__(self, instances: Sequence[Instance], seed: int, n_sweeps: int, measure_every: int = 0,
                  burn_in: int = 0, stream=None, tile_rows: int = 0, launch: str = "direct",
-                 waves_per_block: int = 0, precision: str = "q16"):
+                 waves_per_block: int = 0, precision: str = "q16", corr: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the CRBM sampler runs only on the HIP device")
@@ -266,7 +271,7 @@ class Sampler:
                                I.T0 if I.T1 is None else I.T1, te, I.id)
         self.stream = stream
         cfg = _Config(seed, n_sweeps, measure_every, burn_in, _stream_handle(stream), tile_rows, LAUNCH[launch],
-                      waves_per_block, PRECISION[precision])
+                      waves_per_block, PRECISION[precision], CRBM_F_CORR if corr else 0)
         h = ct.c_void_p()
         _check(lib().crbm_create(arr, len(self.instances), ct.byref(cfg), ct.byref(h)))
         self._h = h
@@ -307,6 +312,10 @@ class Sampler:
                                          int(trace_every)))
 
     def observables(self, corr: bool = False):
+        """Per-instance observables (dicts of the crbm_obs fields); with
+        corr, also the per-instance [L, L] int64 sums of C(dr, dc): over the
+        measured sweeps for a sampler created with corr=True, else over the
+        current state's chains."""
         obs = (_Obs * len(self.instances))()
         cbuf = None
         if corr:

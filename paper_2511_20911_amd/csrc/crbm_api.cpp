@@ -194,6 +194,8 @@ struct crbm_s {
     uint32_t* d_tables = nullptr;
     int64_t* d_acc = nullptr;
     uint32_t* d_queue = nullptr;  // one work counter per group (graph mode)
+    unsigned long long* d_corr = nullptr;  // CRBM_F_CORR: summed C(dr, dc), [sum over instances of L^2]
+    std::vector<int64_t> corr_off;         // offset of each instance's C block
     std::vector<Group> groups;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -204,6 +206,7 @@ struct crbm_s {
         if (d_tables) (void)hipFree(d_tables);
         if (d_acc) (void)hipFree(d_acc);
         if (d_queue) (void)hipFree(d_queue);
+        if (d_corr) (void)hipFree(d_corr);
         for (auto& g : groups)
             if (g.d_items) (void)hipFree(g.d_items);
     }
@@ -212,8 +215,10 @@ struct crbm_s {
 namespace {
 
 GibbsArgs make_args(const crbm_s* h, const Group& g, size_t gi, int64_t s0, int64_t s1, int8_t* spins_out,
-                    int32_t* trace, int32_t trace_every = 1, int32_t* order = nullptr) {
+                    int32_t* trace, int32_t trace_every = 1, int32_t* order = nullptr, int64_t trace_s0 = -1,
+                    bool direct = false) {
     GibbsArgs a{};
+    a.trace_s0 = trace_s0 < 0 ? s0 : trace_s0;
     a.state = h->d_state;
     a.tables = h->d_tables;
     a.items = g.d_items;
@@ -229,7 +234,7 @@ GibbsArgs make_args(const crbm_s* h, const Group& g, size_t gi, int64_t s0, int6
     a.order = order;
     a.total_chains = h->total_chains;
     a.spins_out = spins_out;
-    a.queue = (h->cfg.launch_mode == CRBM_LAUNCH_GRAPH) ? h->d_queue + gi : nullptr;
+    a.queue = (h->cfg.launch_mode == CRBM_LAUNCH_GRAPH && !direct) ? h->d_queue + gi : nullptr;
     a.waves_per_block = g.wpb;
     a.grid_blocks = g.grid_blocks;
     return a;
@@ -318,6 +323,7 @@ int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cf
     if (cfg->waves_per_block < 0 || cfg->waves_per_block > 4) return fail(CRBM_EINVAL, "waves_per_block must be 0..4");
     if (cfg->precision != CRBM_PRECISION_Q16 && cfg->precision != CRBM_PRECISION_FPGA)
         return fail(CRBM_EINVAL, "unknown precision");
+    if (cfg->flags & ~CRBM_F_CORR) return fail(CRBM_EINVAL, "unknown flags");
     const double lim = 2147483647.0 / 65536.0;
     for (int i = 0; i < n_inst; ++i) {
         const crbm_instance& I = inst[i];
@@ -442,6 +448,17 @@ int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cf
             return fail(CRBM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
         }
     }
+    if (cfg->flags & CRBM_F_CORR) {
+        int64_t tot = 0;
+        for (int i = 0; i < n_inst; ++i) {
+            h->corr_off.push_back(tot);
+            tot += (int64_t)h->inst[i].L * h->inst[i].L;
+        }
+        if ((e = hipMalloc(&h->d_corr, sizeof(unsigned long long) * (size_t)tot)) != hipSuccess) {
+            delete h;
+            return fail(CRBM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+    }
     if (cfg->launch_mode == CRBM_LAUNCH_GRAPH) {
         if ((e = hipMalloc(&h->d_queue, sizeof(uint32_t) * h->groups.size())) != hipSuccess) {
             delete h;
@@ -465,6 +482,11 @@ int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cf
     chk(hipMemcpyAsync(h->d_tables, h->h_tables.data(), sizeof(uint32_t) * h->h_tables.size(), hipMemcpyHostToDevice,
                        h->stream), "copy tables");
     chk(hipMemsetAsync(h->d_acc, 0, sizeof(int64_t) * CRBM_N_ACC * (size_t)h->total_chains, h->stream), "zero acc");
+    if (h->d_corr)
+        chk(hipMemsetAsync(h->d_corr, 0, sizeof(unsigned long long) * (size_t)(h->corr_off.back() +
+                                                                               (int64_t)h->inst.back().L * h->inst.back().L),
+                           h->stream),
+            "zero corr");
     for (auto& g : h->groups) {
         chk(hipMemcpyAsync(g.d_items, g.items.data(), sizeof(Item) * g.items.size(), hipMemcpyHostToDevice, h->stream),
             "copy items");
@@ -494,6 +516,29 @@ int crbm_sample_thinned(crbm_t* h, int64_t n_sweeps, int8_t* spins_out, int32_t*
         return fail(CRBM_EINVAL, "trace_every must be >= 1 and divide n_sweeps");
     if (order_trace && !counts_trace) return fail(CRBM_EINVAL, "order_trace needs counts_trace");
     if (h->cur + n_sweeps > h->S) return fail(CRBM_ESTATE, "sampling past the end of the schedule");
+    if (h->d_corr && h->cfg.measure_every > 0) {
+        // one direct launch per measured sweep, then that sweep's C(dr, dc) added to the sums
+        const int64_t call0 = h->cur, end = h->cur + n_sweeps, me = h->cfg.measure_every, b = h->cfg.burn_in;
+        int64_t s = h->cur;
+        while (s < end) {
+            int64_t m = s < b ? b : s;  // next measured sweep >= s
+            if ((m - b) % me) m += me - (m - b) % me;
+            const int64_t stop = m < end ? m + 1 : end;
+            for (size_t gi = 0; gi < h->groups.size(); ++gi) {
+                const GibbsArgs a = make_args(h, h->groups[gi], gi, s, stop, stop == end ? spins_out : nullptr,
+                                              counts_trace, trace_every, order_trace, call0, true);
+                HIP_TRY(launch_gibbs(h->groups[gi].L, h->groups[gi].R, a, h->stream), "gibbs kernel");
+            }
+            if (m < end)
+                for (size_t i = 0; i < h->inst.size(); ++i)
+                    HIP_TRY(launch_corr(h->d_state + h->state_off[i], h->inst[i].n_chains, h->inst[i].L,
+                                        h->d_corr + h->corr_off[i], h->stream),
+                            "correlation kernel");
+            s = stop;
+        }
+        h->cur = end;
+        return CRBM_OK;
+    }
     if (h->cfg.launch_mode == CRBM_LAUNCH_GRAPH) {
         for (size_t gi = 0; gi < h->groups.size(); ++gi) {
             Group& g = h->groups[gi];
@@ -635,6 +680,7 @@ int crbm_observables(crbm_t* h, crbm_obs* out, int64_t* corr_out) {
         o.sum_MM = s[4]; o.sum_B1B1 = s[5]; o.sum_B2B2 = s[6];
         o.sum_MB1 = s[7]; o.sum_MB2 = s[8]; o.sum_B1B2 = s[9];
         o.sum_absM = s[10];
+        o.sum_Ms = s[11]; o.sum_MsMs = s[12]; o.sum_absMs = s[13];
         if (s[0] > 0) {
             const double N = (double)I.L * I.L, ns = (double)s[0];
             const double a = (double)h->Jq[0][i] / 65536.0, b = (double)h->Jq[1][i] / 65536.0,
@@ -647,9 +693,15 @@ int crbm_observables(crbm_t* h, crbm_obs* out, int64_t* corr_out) {
             o.abs_m = (double)s[10] / ns / N;
             o.dimer = -((double)s[3] / ns) / (N / 2.0);
             o.E_var_per_spin = (mE2 - mE * mE) / N;
+            o.abs_stag_m = (double)s[13] / ns / N;
         }
     }
-    if (corr_out) {
+    if (corr_out && h->d_corr) {
+        const int64_t tot = h->corr_off.back() + (int64_t)h->inst.back().L * h->inst.back().L;
+        HIP_TRY(hipMemcpyAsync(corr_out, h->d_corr, sizeof(int64_t) * (size_t)tot, hipMemcpyDeviceToHost, h->stream),
+                "copy correlation sums");
+        HIP_TRY(hipStreamSynchronize(h->stream), "synchronize");
+    } else if (corr_out) {
         int64_t tot = 0;
         for (int i = 0; i < n; ++i) tot += (int64_t)h->inst[i].L * h->inst[i].L;
         unsigned long long* d = nullptr;
@@ -676,6 +728,12 @@ int crbm_reset_observables(crbm_t* h) {
     if (!h) return fail(CRBM_EINVAL, "handle is NULL");
     HIP_TRY(hipMemsetAsync(h->d_acc, 0, sizeof(int64_t) * CRBM_N_ACC * (size_t)h->total_chains, h->stream),
             "zero accumulators");
+    if (h->d_corr)
+        HIP_TRY(hipMemsetAsync(h->d_corr, 0,
+                               sizeof(unsigned long long) *
+                                   (size_t)(h->corr_off.back() + (int64_t)h->inst.back().L * h->inst.back().L),
+                               h->stream),
+                "zero correlation sums");
     return CRBM_OK;
 }
 

@@ -40,9 +40,10 @@ struct GibbsArgs {
     int64_t s0, s1;           // sweeps [s0, s1) of the schedule
     int64_t burn_in;
     uint64_t seed;
-    int64_t* acc;             // [global chain][11] int64 accumulators
-    int32_t* trace;           // [(s1 - s0) / trace_every][total_chains][3] or nullptr
+    int64_t* acc;             // [global chain][CRBM_N_ACC] int64 accumulators
+    int32_t* trace;           // [(s1 - trace_s0) / trace_every][total_chains][3] or nullptr
     int32_t trace_every;      // record after every trace_every-th sweep of the call
+    int64_t trace_s0;         // first sweep of the crbm_sample call (a call may take several launches)
     int32_t* order;           // plateau structure factor trace, same layout as trace, or nullptr
     int64_t total_chains;
     int8_t* spins_out;        // int8 spins at Item::spin_off, or nullptr

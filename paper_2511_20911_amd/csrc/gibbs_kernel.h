@@ -502,7 +502,7 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
             for (int w = 0; w < W; ++w) Q[x][w] = Q[x + 1][w];
 
         const bool meas = a.measure_every > 0 && s >= a.burn_in && ((s - a.burn_in) % a.measure_every) == 0;
-        const bool rec = a.trace != nullptr && ((s - a.s0 + 1) % a.trace_every) == 0;
+        const bool rec = a.trace != nullptr && ((s - a.trace_s0 + 1) % a.trace_every) == 0;
         if (meas || rec) {
             uint32_t nb[W];
 #pragma unroll
@@ -525,6 +525,21 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
                 for (int w = 0; w < W; ++w)
                     dis2 += __popc((tp[w] ^ rsh<L, 1>(md, w)) & Gm::even(w)) +
                             __popc((rsh<L, 2>(md, w) ^ rsh<L, 1>(bt, w)) & Gm::even(w));
+            }
+            // staggered magnetisation sum (-1)^(r+c) s = sum over rows of (-1)^r 2 (up at even
+            // columns - up at odd columns) (L even: as many even as odd columns)
+            int stag = 0;
+            if (meas) {
+#pragma unroll
+                for (int x = 0; x < NR; ++x) {
+                    int pe = 0, po = 0;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        pe += __popc(Q[x][w] & Gm::even(w));
+                        po += __popc(Q[x][w] & ~Gm::even(w) & Gm::full(w));
+                    }
+                    stag += (x & 1) ? 2 * (po - pe) : 2 * (pe - po);  // band rows start at an even row
+                }
             }
             // plateau structure factor sums: A_k = sum (-1)^r s over columns = k (mod 3),
             // B_k = sum (-1)^c s over rows = k (mod 3)
@@ -551,7 +566,7 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
                     ob[2] += (rm == 2) ? e : 0;
                 }
             }
-            int tp = pop, t1 = dis1, t2 = dis2;
+            int tp = pop, t1 = dis1, t2 = dis2, ts = stag;
             int sa3[3] = {oa[0], oa[1], oa[2]}, sb3[3] = {ob[0], ob[1], ob[2]};  // chain totals
             if (want_order) {
 #pragma unroll
@@ -570,10 +585,11 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
                 tp += __shfl(pop, src);
                 t1 += __shfl(dis1, src);
                 t2 += __shfl(dis2, src);
+                if (meas) ts += __shfl(stag, src);
             }
             const int64_t M = 2 * tp - N, B1 = 2 * N - 2 * t1, B2 = N / 2 - 2 * t2;
             if (rec && g == 0 && active) {
-                const uint64_t rix = ((uint64_t)((s - a.s0) / a.trace_every) * (uint64_t)a.total_chains + gch) * 3;
+                const uint64_t rix = ((uint64_t)((s - a.trace_s0) / a.trace_every) * (uint64_t)a.total_chains + gch) * 3;
                 int32_t* tr = a.trace + rix;
                 tr[0] = (int32_t)M;
                 tr[1] = (int32_t)B1;
@@ -592,12 +608,14 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
                 }
             }
             if (meas && g == 0 && active) {  // the chain's accumulators live in memory: no registers held
-                int64_t* ac = a.acc + gch * 11;
+                int64_t* ac = a.acc + gch * CRBM_N_ACC;
+                const int64_t Ms = ts;
                 ac[0] += 1;
                 ac[1] += M; ac[2] += B1; ac[3] += B2;
                 ac[4] += M * M; ac[5] += B1 * B1; ac[6] += B2 * B2;
                 ac[7] += M * B1; ac[8] += M * B2; ac[9] += B1 * B2;
                 ac[10] += M < 0 ? -M : M;
+                ac[11] += Ms; ac[12] += Ms * Ms; ac[13] += Ms < 0 ? -Ms : Ms;
             }
         }
     }

@@ -38,5 +38,5 @@ def test_c_caller_matches_oracle(tmp_path):
     for ch in range(64):
         _, _, a = oracle.run_chain(oi, 300, seed, ch, 0, 300, measure_every=1, burn_in=200)
         acc += a
-    assert got[:11] == acc.tolist()
+    assert got[:11] == acc[:11].tolist()  # the demo prints the first 11 sums
     assert got[11] == -6  # CRBM_ESTATE past the end of the schedule

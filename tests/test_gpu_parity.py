@@ -199,13 +199,60 @@ def test_accumulators_and_structure_factor_match_oracle():
         s, _, a = oracle.run_chain(oi, S, seed, ch, 0, S, measure_every=3, burn_in=100)
         acc += a
         csum += oracle.corr(12, s)
-    keys = ["n_samples", "sum_M", "sum_B1", "sum_B2", "sum_MM", "sum_B1B1", "sum_B2B2", "sum_MB1", "sum_MB2",
-            "sum_B1B2", "sum_absM"]
-    assert [obs[0][k] for k in keys] == acc.tolist()
+    assert [obs[0][k] for k in ACC_KEYS] == acc.tolist()
     assert np.array_equal(corr[0], csum)
     n = acc[0]
     E = (acc[2] + acc[3] - 3 * acc[1]) / n / 144
     assert abs(obs[0]["E_per_spin"] - E) < 1e-12
+    assert abs(obs[0]["abs_stag_m"] - acc[13] / n / 144) < 1e-12
+
+
+ACC_KEYS = ["n_samples", "sum_M", "sum_B1", "sum_B2", "sum_MM", "sum_B1B1", "sum_B2B2", "sum_MB1", "sum_MB2",
+            "sum_B1B2", "sum_absM", "sum_Ms", "sum_MsMs", "sum_absMs"]
+
+
+@pytest.mark.parametrize("launch", ["direct", "graph"])
+def test_accumulated_structure_factor_matches_oracle(launch):
+    """Sampler created with CRBM_F_CORR: C(dr, dc) summed over the chains and
+    every measured sweep (Sec. III.B Eq. (13) averages it over the sampled
+    states), for two lattice sizes in one handle (a one-word and a two-word
+    row); every accumulator, the thinned counts trace written across the
+    per-measured-sweep launches and the final states equal the oracle's; a
+    reset zeroes the sums, which then restart."""
+    seed, S, me, burn, te = 44, 90, 4, 13, 5
+    insts = [crbm.Instance(L=12, J1=1.0, J2=1.0, h=2.0, n_chains=10, sched="geometric", T0=3.0, T1=0.5, id=3),
+             crbm.Instance(L=36, J1=1.0, J2=1.5, h=1.0, n_chains=3, sched="const", T0=0.9, id=4)]
+    smp = crbm.Sampler(insts, seed=seed, n_sweeps=S, measure_every=me, burn_in=burn, corr=True, launch=launch)
+    n_tot = smp.total_chains
+    tr = torch.zeros((60 // te, n_tot, 3), dtype=torch.int32, device="cuda")
+    smp.sample(60, trace=tr, trace_every=te)
+    obs, corr = smp.observables(corr=True)
+    trn = tr.cpu().numpy()
+    states = {}
+    for k, I in enumerate(insts):
+        acc = np.zeros(oracle.N_ACC, np.int64)
+        csum = np.zeros(I.L * I.L, np.int64)
+        for ch in range(I.n_chains):
+            s, t, a = oracle.run_chain(_oi(I), S, seed, ch, 0, 60, trace=True, measure_every=me, burn_in=burn,
+                                       corr=csum)
+            acc += a
+            states[(k, ch)] = s
+            assert np.array_equal(trn[:, int(smp.chain_offsets[k]) + ch], t[te - 1::te]), (k, ch)
+        assert [obs[k][key] for key in ACC_KEYS] == acc.tolist(), k
+        assert np.array_equal(corr[k].reshape(-1), csum), k
+        assert corr[k][0, 0] == I.L * I.L * acc[0]  # C(0, 0) = N per sample
+    # the rest of the schedule after a reset: sums restart from zero
+    smp.reset_observables()
+    smp.sample(S - 60)
+    obs2, corr2 = smp.observables(corr=True)
+    for k, I in enumerate(insts):
+        acc = np.zeros(oracle.N_ACC, np.int64)
+        csum = np.zeros(I.L * I.L, np.int64)
+        for ch in range(I.n_chains):
+            oracle.run_chain(_oi(I), S, seed, ch, 60, S, spins=states[(k, ch)], measure_every=me, burn_in=burn,
+                             acc=acc, corr=csum)
+        assert [obs2[k][key] for key in ACC_KEYS] == acc.tolist(), k
+        assert np.array_equal(corr2[k].reshape(-1), csum), k
 
 
 def test_degenerate_couplings_bit_exact():
@@ -309,7 +356,7 @@ def test_multiword_observables_and_corr():
         s, _, a = oracle.run_chain(_oi(I), S, seed, ch, 0, S, measure_every=2, burn_in=5)
         acc += a
         csum += oracle.corr(48, s)
-    assert obs[0]["n_samples"] == acc[0] and obs[0]["sum_B1"] == acc[2] and obs[0]["sum_MM"] == acc[4]
+    assert [obs[0][k] for k in ACC_KEYS] == acc.tolist()
     assert np.array_equal(corr[0], csum)
 
 

@@ -404,3 +404,49 @@ def test_philox_matches_rocrand_engine():
         lib.rocrand_philox_block(c.ctypes.data_as(ct.c_void_p), k.ctypes.data_as(ct.c_void_p),
                                  o.ctypes.data_as(ct.c_void_p))
         assert np.array_equal(o, oracle.philox(c, k)), (c, k)
+
+
+# ------------------------------------------------------------ staggered magnetisation and accumulated C
+
+def test_staggered_magnetisation_of_perfect_states():
+    """Ms = sum (-1)^(r+c) s: +-N for the two Neel states (the AFM phase of
+    Sec. III.A), 0 for the ferromagnet, for row stripes and for the UUD
+    plateau state."""
+    L = 6
+    r, c = np.meshgrid(np.arange(L), np.arange(L), indexing="ij")
+    neel = np.where((r + c) % 2 == 0, 1, -1).astype(np.int8)
+    assert oracle.staggered(L, neel) == L * L and oracle.staggered(L, -neel) == -L * L
+    assert oracle.staggered(L, np.ones((L, L), np.int8)) == 0
+    assert oracle.staggered(L, np.where(r % 2 == 0, 1, -1).astype(np.int8)) == 0
+    uud = np.where((c % 3 == 2) & (r % 2 == 0), -1, np.where((c % 3 == 0) & (r % 2 == 1), -1, 1)).astype(np.int8)
+    assert oracle.staggered(L, uud) == 0
+
+
+def test_accumulated_correlation_invariants():
+    """C(dr, dc) summed over measured sweeps: C(0, 0) = N per sample,
+    sum over all offsets = sum of M^2 over the samples (the accumulator's
+    second moment), C(-d) = C(d), |C(d)| <= C(0); and the staggered sums equal
+    those of the states at the measured sweeps (the chain rerun sweep by
+    sweep); the annealed 6x6 workload ends in Neel states, |Ms| = N."""
+    L, S, me, burn = 6, 120, 3, 30
+    inst = oracle.Instance(L, 1.0, 0.5, 0.0, "linear", 3.0, 0.1, id=5)
+    acc = np.zeros(oracle.N_ACC, np.int64)
+    corr = np.zeros(L * L, np.int64)
+    s_end, _, _ = oracle.run_chain(inst, S, 17, 2, 0, S, measure_every=me, burn_in=burn, acc=acc, corr=corr)
+    C = corr.reshape(L, L)
+    n = acc[0]
+    assert n == len(range(burn, S, me))
+    assert C[0, 0] == L * L * n
+    assert C.sum() == acc[4]
+    assert np.array_equal(C, np.roll(np.roll(C[::-1, ::-1], 1, axis=0), 1, axis=1))
+    assert np.abs(C).max() == C[0, 0]
+    ms = []
+    s = None
+    for sw in range(S):
+        s, _, _ = oracle.run_chain(inst, S, 17, 2, sw, sw + 1, spins=s)
+        if sw >= burn and (sw - burn) % me == 0:
+            ms.append(oracle.staggered(L, s))
+    ms = np.array(ms, np.int64)
+    assert acc[11] == ms.sum() and acc[12] == (ms * ms).sum() and acc[13] == np.abs(ms).sum()
+    assert np.array_equal(s, s_end)
+    assert abs(oracle.staggered(L, s_end)) == L * L
