@@ -327,6 +327,43 @@ int crbm_ar_sample_cond(crbm_ar_t* a, int64_t n, uint64_t seed, int64_t step, ui
 int crbm_ar_grad(crbm_ar_t* a, const int8_t* samples_dev, int64_t batch, float* grad_host, double* loss_out);
 /* One Adam step (beta = 0.9, 0.999, eps = 1e-8) at learning rate lr on a batch. */
 int crbm_ar_train_step(crbm_ar_t* a, const int8_t* samples_dev, int64_t batch, float lr, double* loss_out);
+/* A whole training run in the library (Sec. II.B's sampler supplies the
+ * data; the training itself is an addition): `steps` Adam steps, each on a
+ * minibatch drawn on the device from `n` training configurations
+ * (samples_dev, device int8 [n][L][L]; points_dev, device int32 [n] point
+ * indices of a conditional network, or NULL) as crbm_ar_batch draws it
+ * with step = step0 + k for the k-th step; learning rate lr for the steps
+ * k < late_from * steps, lr_late after.  loss_out (host, may be NULL): the
+ * mean negative log-likelihood per configuration of the last step's batch.
+ * Equals `steps` calls of crbm_ar_train_step_cond on those batches, bit for
+ * bit.  CRBM_EINVAL for bad options (steps < 0, batch < 1, lr <= 0,
+ * step0 + steps > 2^32 - 1), CRBM_ESTATE for a conditional network without
+ * points.  Synchronises only to return the loss. */
+typedef struct {
+    int64_t steps;       /* Adam steps */
+    int64_t batch;       /* configurations per step */
+    float lr, lr_late;   /* learning rates */
+    double late_from;    /* fraction of the steps after which lr_late applies */
+    uint64_t seed;       /* key of the minibatch stream */
+    int64_t step0;       /* counter of the first step's minibatch */
+    int32_t augment;     /* nonzero: random lattice symmetries (see crbm_ar_batch) */
+} crbm_train_opts;
+int crbm_ar_train(crbm_ar_t* a, const int8_t* samples_dev, const int32_t* points_dev, int64_t n,
+                  const crbm_train_opts* opts, double* loss_out);
+/* The minibatch of training step `step` (no network needed; asynchronous on
+ * `stream`): configuration b of out_dev (device int8 [batch][L][L]) is
+ * training configuration idx_b = floor(u n / 2^64), u = out[0] 2^32 + out[1]
+ * of Philox (ctr = (b, step, 0, 7), key = seed); with augment, rolled by
+ * (2 (out[2] mod L/2), 2 ((out[3] >> 1) mod L/2)) sites along (rows,
+ * columns), out[r][c] = in[(r - dr) mod L][(c - dc) mod L], then transposed
+ * if out[3] is odd: symmetries of the periodic Shastry-Sutherland lattice
+ * (the dimer layout of Sec. I Fig. 1 maps onto itself), so every
+ * configuration keeps its energy.  points_out_dev (may be NULL): the point
+ * of each drawn configuration (points_dev[idx_b], 0 if points_dev is NULL);
+ * index_out_dev (may be NULL): idx_b. */
+int crbm_ar_batch(const int8_t* samples_dev, const int32_t* points_dev, int64_t n, int32_t L, int64_t batch,
+                  uint64_t seed, int64_t step, int32_t augment, int8_t* out_dev, int32_t* points_out_dev,
+                  int64_t* index_out_dev, void* stream);
 /* log q of n configurations (device int8 [n][L][L]) into logq_dev (device fp64 [n])
  * by one forward pass over all sites, under the proposal law of
  * crbm_ar_sample (per site log(t / 2^32) or log(1 - t / 2^32)).  The per-site arithmetic, and the fp64 sum

@@ -76,6 +76,11 @@ class _ARConfig(ct.Structure):
                 ("stream", ct.c_void_p), ("cond_points", ct.c_int32)]
 
 
+class _TrainOpts(ct.Structure):
+    _fields_ = [("steps", ct.c_int64), ("batch", ct.c_int64), ("lr", ct.c_float), ("lr_late", ct.c_float),
+                ("late_from", ct.c_double), ("seed", ct.c_uint64), ("step0", ct.c_int64), ("augment", ct.c_int32)]
+
+
 _lib = None
 
 
@@ -133,6 +138,10 @@ def lib() -> ct.CDLL:
                                           ct.c_void_p, ct.c_void_p, ct.c_void_p]
         L.crbm_ar_sample_steps.argtypes = [ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_uint64, ct.c_int64, ct.c_uint32,
                                            ct.c_void_p, ct.c_void_p, ct.c_void_p]
+        L.crbm_ar_train.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, p(_TrainOpts),
+                                    p(ct.c_double)]
+        L.crbm_ar_batch.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int64, ct.c_uint64,
+                                    ct.c_int64, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]
         L.crbm_ar_destroy.argtypes = [ct.c_void_p]
         L.crbm_ar_destroy.restype = None
         L.crbm_tau_int.argtypes = [ct.c_void_p, ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int64,
@@ -429,6 +438,21 @@ class ARNet:
                                              ct.byref(loss)))
         return float(loss.value)
 
+    def train(self, data, steps: int, batch: int = 1024, lr: float = 1e-3, lr_late: float = 3e-4,
+              late_from: float = 0.625, seed: int = 1, step0: int = 0, augment: bool = True, points=None) -> float:
+        """A training run in the library (crbm_ar_train): `steps` Adam steps on
+        minibatches drawn on the device from data (int8 CUDA [n, L, L]; points:
+        int32 CUDA [n] for a conditional network), with random lattice
+        symmetries.  Returns the last step's mean loss per configuration."""
+        assert data.is_cuda and data.dtype.itemsize == 1 and data.is_contiguous()
+        n = int(data.shape[0])
+        o = _TrainOpts(int(steps), int(batch), float(lr), float(lr_late), float(late_from), int(seed), int(step0),
+                       1 if augment else 0)
+        loss = ct.c_double()
+        _check(lib().crbm_ar_train(self._h, ct.c_void_p(data.data_ptr()), _points_ptr(points, n), n, ct.byref(o),
+                                   ct.byref(loss)))
+        return float(loss.value)
+
     def logq(self, spins, points=None):
         import torch
         out = torch.empty(spins.shape[0], dtype=torch.float64, device="cuda")
@@ -456,6 +480,22 @@ class ARNet:
         _check(lib().crbm_ar_sample_steps(self._h, n, n_steps, seed, step0, id, _points_ptr(points, n),
                                           ct.c_void_p(spins.data_ptr()), ct.c_void_p(lq.data_ptr())))
         return spins, lq
+
+
+def train_batch(data, batch: int, seed: int, step: int, augment: bool = True, points=None, stream=None):
+    """The minibatch crbm_ar_train draws at `step` (crbm_ar_batch): returns
+    (configurations int8 [batch, L, L], their points int32 [batch], the
+    indices of the drawn training configurations int64 [batch])."""
+    import torch
+    assert data.is_cuda and data.dtype.itemsize == 1 and data.is_contiguous() and data.dim() == 3
+    n, L = int(data.shape[0]), int(data.shape[1])
+    out = torch.empty((batch, L, L), dtype=torch.int8, device="cuda")
+    pts = torch.empty(batch, dtype=torch.int32, device="cuda")
+    idx = torch.empty(batch, dtype=torch.int64, device="cuda")
+    _check(lib().crbm_ar_batch(ct.c_void_p(data.data_ptr()), _points_ptr(points, n), n, L, batch, seed, step,
+                               1 if augment else 0, ct.c_void_p(out.data_ptr()), ct.c_void_p(pts.data_ptr()),
+                               ct.c_void_p(idx.data_ptr()), _stream_handle(stream)))
+    return out, pts, idx
 
 
 def sample_mh(sampler: Sampler, net: ARNet, n_cycles: int, gibbs_per_mh: int, trace=None, order=None) -> int:

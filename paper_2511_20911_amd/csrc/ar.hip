@@ -1138,6 +1138,48 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
     }
 }
 
+// Minibatch of a training run: sample b of step `step` is training sample
+// idx = floor(u64 n / 2^64) with u64 = (out[0] << 32 | out[1]) of Philox
+// (ctr = (b, step, 0, 7), key = seed), moved by a lattice symmetry of the
+// periodic Shastry-Sutherland lattice: rolled by (dr, dc) = (2 (out[2] mod
+// L/2), 2 ((out[3] >> 1) mod L/2)) sites (even translations map the dimer
+// pattern onto itself), then transposed if out[3] is odd (the transpose maps
+// both dimer orientations onto themselves).  out[r][c] = in[(r - dr) mod L]
+// [(c - dc) mod L] before the transpose.  One workgroup per sample.
+__global__ void __launch_bounds__(256) gather_batch_kernel(const int8_t* __restrict__ samples,
+                                                           const int32_t* __restrict__ pts_in, int64_t n, int L,
+                                                           uint64_t seed, uint32_t step, int augment,
+                                                           int8_t* __restrict__ out, int32_t* __restrict__ pts_out,
+                                                           int64_t* __restrict__ idx_out) {
+    const int64_t b = blockIdx.x;
+    const gk::P4 q = gk::philox((uint32_t)b, step, 0u, 7u, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint64_t u = ((uint64_t)q.v[0] << 32) | q.v[1];
+    const int64_t idx = (int64_t)__umul64hi(u, (uint64_t)n);
+    const int half = L / 2;
+    const int dr = augment ? 2 * (int)(q.v[2] % (uint32_t)half) : 0;
+    const int dc = augment ? 2 * (int)((q.v[3] >> 1) % (uint32_t)half) : 0;
+    const bool tr = augment && (q.v[3] & 1u);
+    const int N = L * L;
+    const int8_t* src = samples + idx * N;
+    int8_t* dst = out + b * N;
+    for (int p = threadIdx.x; p < N; p += blockDim.x) {
+        int r = p / L, c = p - (p / L) * L;
+        if (tr) {
+            const int t = r;
+            r = c;
+            c = t;
+        }
+        int rs = r - dr, cs = c - dc;
+        rs += rs < 0 ? L : 0;
+        cs += cs < 0 ? L : 0;
+        dst[p] = src[rs * L + cs];
+    }
+    if (threadIdx.x == 0) {
+        if (pts_out) pts_out[b] = pts_in ? pts_in[idx] : 0;
+        if (idx_out) idx_out[b] = idx;
+    }
+}
+
 }  // namespace ar
 }  // namespace crbmlib
 
@@ -1348,11 +1390,15 @@ struct crbm_ar_s {
     int64_t mh_kcap = 0, mh_kn = 0;
     int8_t* mh_prop = nullptr;
     double* mh_lqp = nullptr;
+    // crbm_ar_train: the current minibatch and its points (capacity in samples)
+    int64_t bcap = 0;
+    int8_t* bspins = nullptr;
+    int32_t* bpts = nullptr;
     ~crbm_ar_s() {
         void* ps[] = {theta, grad, m, v, bias, wf, wb, hs, mask, logit, g32, dh0, dh1, dz, g, logq, part, bpart,
                       part2,
                       spins_copy, ring, slogit, zpad, ih0, ih1, ilogit, cur, ccur, cprop, lqc, nacc,
-                      feats, cb, gs, gp, mh_ci, mh_tg, mh_prop, mh_lqp};
+                      feats, cb, gs, gp, mh_ci, mh_tg, mh_prop, mh_lqp, bspins, bpts};
         for (void* p : ps)
             if (p) (void)hipFree(p);
     }
@@ -1654,12 +1700,14 @@ int crbm_ar_create(const crbm_ar_config* c, crbm_ar_t** out) {
         delete a;
         return fail_ar(CRBM_ENOMEM, "parameter buffers");
     }
-    (void)hipMemsetAsync(a->zpad, 0, sizeof(__bf16) * C, a->stream);
-    (void)hipMemsetAsync(a->theta, 0, sizeof(float) * a->np, a->stream);
-    (void)hipMemsetAsync(a->m, 0, sizeof(float) * a->np, a->stream);
-    (void)hipMemsetAsync(a->v, 0, sizeof(float) * a->np, a->stream);
-    (void)hipMemsetAsync(a->grad, 0, sizeof(float) * a->np, a->stream);
-    int rc = pack(a);
+    int rc = CRBM_OK;
+    if (hipMemsetAsync(a->zpad, 0, sizeof(__bf16) * C, a->stream) != hipSuccess ||
+        hipMemsetAsync(a->theta, 0, sizeof(float) * a->np, a->stream) != hipSuccess ||
+        hipMemsetAsync(a->m, 0, sizeof(float) * a->np, a->stream) != hipSuccess ||
+        hipMemsetAsync(a->v, 0, sizeof(float) * a->np, a->stream) != hipSuccess ||
+        hipMemsetAsync(a->grad, 0, sizeof(float) * a->np, a->stream) != hipSuccess)
+        rc = fail_ar(CRBM_EHIP, "zeroing the parameter buffers");
+    if (rc == CRBM_OK) rc = pack(a);
     if (rc == CRBM_OK && hipStreamSynchronize(a->stream) != hipSuccess) rc = fail_ar(CRBM_EHIP, "synchronize");
     if (rc != CRBM_OK) {
         delete a;
@@ -1797,6 +1845,50 @@ int crbm_ar_train_step_cond(crbm_ar_t* a, const int8_t* samples_dev, const int32
 
 int crbm_ar_train_step(crbm_ar_t* a, const int8_t* samples_dev, int64_t batch, float lr, double* loss_out) {
     return crbm_ar_train_step_cond(a, samples_dev, nullptr, batch, lr, loss_out);
+}
+
+int crbm_ar_batch(const int8_t* samples_dev, const int32_t* points_dev, int64_t n, int32_t L, int64_t batch,
+                  uint64_t seed, int64_t step, int32_t augment, int8_t* out_dev, int32_t* points_out_dev,
+                  int64_t* index_out_dev, void* stream) {
+    if (!samples_dev || !out_dev || n < 1 || batch < 1 || L < 4 || L > CRBM_MAX_L || (L & 1) || step < 0 ||
+        step > 0xffffffffLL || batch > 0x7fffffffLL)
+        return fail_ar(CRBM_EINVAL, "crbm_ar_batch: bad arguments");
+    hipLaunchKernelGGL(gather_batch_kernel, dim3((unsigned)batch), dim3(256), 0, (hipStream_t)stream, samples_dev,
+                       points_dev, n, L, seed, (uint32_t)step, augment ? 1 : 0, out_dev, points_out_dev,
+                       index_out_dev);
+    AR_TRY(hipGetLastError(), "crbm_ar_batch");
+    return CRBM_OK;
+}
+
+int crbm_ar_train(crbm_ar_t* a, const int8_t* samples_dev, const int32_t* points_dev, int64_t n,
+                  const crbm_train_opts* o, double* loss_out) {
+    if (!a || !samples_dev || !o || n < 1 || o->steps < 0 || o->batch < 1 || !(o->lr > 0.f) ||
+        !(o->lr_late > 0.f) || !(o->late_from >= 0.0) || o->step0 < 0 || o->step0 + o->steps > 0xffffffffLL)
+        return fail_ar(CRBM_EINVAL, "crbm_ar_train: bad arguments");
+    int rc = need_points(a);
+    if (rc != CRBM_OK) return rc;
+    if (o->batch > a->bcap) {
+        if (a->bspins) (void)hipFree(a->bspins);
+        if (a->bpts) (void)hipFree(a->bpts);
+        a->bspins = nullptr;
+        a->bpts = nullptr;
+        a->bcap = 0;
+        if (alloc(&a->bspins, o->batch * a->L * a->L) || alloc(&a->bpts, o->batch))
+            return fail_ar(CRBM_ENOMEM, "crbm_ar_train: batch buffers");
+        a->bcap = o->batch;
+    }
+    const bool cond = a->cond > 0 && points_dev != nullptr;
+    for (int64_t k = 0; k < o->steps; ++k) {
+        rc = crbm_ar_batch(samples_dev, cond ? points_dev : nullptr, n, a->L, o->batch, o->seed, o->step0 + k,
+                           o->augment, a->bspins, cond ? a->bpts : nullptr, nullptr, a->stream);
+        if (rc != CRBM_OK) return rc;
+        const float lr = (double)k < o->late_from * (double)o->steps ? o->lr : o->lr_late;
+        rc = crbm_ar_train_step_cond(a, a->bspins, cond ? a->bpts : nullptr, o->batch, lr,
+                                     (loss_out && k + 1 == o->steps) ? loss_out : nullptr);
+        if (rc != CRBM_OK) return rc;
+    }
+    if (loss_out && o->steps == 0) *loss_out = 0.0;
+    return CRBM_OK;
 }
 
 int crbm_ar_logq_cond(crbm_ar_t* a, const int8_t* spins_dev, const int32_t* points_dev, int64_t n, double* logq_dev) {

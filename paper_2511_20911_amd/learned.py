@@ -7,13 +7,11 @@ and moves data between device tensors:
 
 * training_set: configurations drawn by the library's own Gibbs sampler
   (geometric anneal to the target temperature, then spaced snapshots at it);
-* augment: symmetries of the periodic Shastry-Sutherland lattice with the
-  dimer layout of Fig. 1a -- translations by two sites in either direction
-  and the transpose (r, c) -> (c, r), which maps the '\\' dimers of the
-  plaquettes (2i, 2j) and the '/' dimers of the plaquettes (2i+1, 2j+1) onto
-  themselves;
-* train: Adam steps of the library's fused forward / backward kernels on
-  random augmented mini-batches;
+* train: a training run in the library (crbm_ar_train): Adam steps of its
+  fused forward / backward kernels on minibatches it draws on the device,
+  each moved by a symmetry of the periodic Shastry-Sutherland lattice with
+  the dimer layout of Fig. 1a (translations by two sites in either direction,
+  the transpose (r, c) -> (c, r));
 * compare: learned MH (1 MH step per `gibbs_per_mh` Gibbs sweeps) against
   plain Gibbs given the same wall-clock time, both from the same seeded start,
   with tau_int / ESS of the energy and of the plateau order parameter
@@ -65,33 +63,13 @@ def training_set(L, J1, J2, h, T, n_chains=4096, anneal_sweeps=20000, snapshots=
     return out.view(-1, L, L)
 
 
-def augment(batch, gen):
-    """A random lattice symmetry (translation by an even vector, optional
-    transpose) applied to a whole batch [B, L, L]."""
-    import torch
-    L = batch.shape[1]
-    a = 2 * int(torch.randint(0, L // 2, (1,), generator=gen))
-    c = 2 * int(torch.randint(0, L // 2, (1,), generator=gen))
-    b = torch.roll(batch, shifts=(a, c), dims=(1, 2))
-    if int(torch.randint(0, 2, (1,), generator=gen)):
-        b = b.transpose(1, 2)
-    return b.contiguous()
-
-
 def train(net: ARNet, data, steps=800, batch=1024, lr=1e-3, lr_late=3e-4, late_from=0.625, seed=1):
-    """Maximum-likelihood training on random augmented mini-batches of `data`.
-    Returns the per-site loss of the last step."""
-    import torch
-    gen = torch.Generator()
-    gen.manual_seed(seed)
-    gidx = torch.Generator(device="cuda")
-    gidx.manual_seed(seed + 1)
+    """Maximum-likelihood training in the library (crbm_ar_train): minibatches
+    drawn on the device with random lattice symmetries (even translations,
+    transpose).  Returns the per-site loss of the last step."""
     N = data.shape[1] * data.shape[2]
-    loss = float("nan")
-    for it in range(steps):
-        idx = torch.randint(0, data.shape[0], (batch,), device="cuda", generator=gidx)
-        loss = net.train_step(augment(data[idx], gen), lr if it < late_from * steps else lr_late)
-    return loss / N
+    return net.train(data.contiguous(), steps, batch=batch, lr=lr, lr_late=lr_late, late_from=late_from,
+                     seed=seed) / N
 
 
 @dataclass
@@ -203,20 +181,11 @@ def training_set_points(points, L, chains, anneal_sweeps=4000, snapshots=32, spa
 
 
 def train_points(net: ARNet, data, pts, steps=600, batch=512, lr=1e-3, lr_late=3e-4, late_from=0.625, seed=1):
-    """Maximum-likelihood training of a conditional network on random
-    augmented mini-batches that mix the points.  Returns the last per-site loss."""
-    import torch
-    gen = torch.Generator()
-    gen.manual_seed(seed)
-    gidx = torch.Generator(device="cuda")
-    gidx.manual_seed(seed + 1)
+    """Maximum-likelihood training of a conditional network in the library on
+    minibatches that mix the points.  Returns the last per-site loss."""
     N = data.shape[1] * data.shape[2]
-    loss = float("nan")
-    for it in range(steps):
-        idx = torch.randint(0, data.shape[0], (batch,), device="cuda", generator=gidx)
-        loss = net.train_step(augment(data[idx], gen), lr if it < late_from * steps else lr_late,
-                              points=pts[idx].contiguous())
-    return loss / N
+    return net.train(data.contiguous(), steps, batch=batch, lr=lr, lr_late=lr_late, late_from=late_from, seed=seed,
+                     points=pts.contiguous()) / N
 
 
 def _point_stats(trace, c0, c1, weights, N, discard, max_lag):

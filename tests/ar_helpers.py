@@ -64,3 +64,30 @@ def assert_grad_blocks(g, ref_grads, like):
                                        err_msg=f"layer {l} {kind}")
             rel = np.linalg.norm(a - b) / np.linalg.norm(b)
             assert rel < GRAD_REL_L2, (l, kind, rel)
+
+
+def documented_batch(oracle, data, batch, seed, step, augment=True, points=None):
+    """The minibatch of training step `step` as crbm_ar_batch documents it,
+    written out on the host: configuration b is data[idx_b], idx_b =
+    floor(u n / 2^64) with u = out[0] 2^32 + out[1] of Philox (ctr = (b, step,
+    0, 7), key = seed); with augment, rolled by (2 (out[2] mod L/2),
+    2 ((out[3] >> 1) mod L/2)) along (rows, columns), then transposed if out[3]
+    is odd.  Returns (configurations, points, indices)."""
+    n, L = data.shape[0], data.shape[1]
+    key = [seed & 0xffffffff, seed >> 32]
+    out = np.empty((batch, L, L), np.int8)
+    pts = np.zeros(batch, np.int32)
+    idx = np.zeros(batch, np.int64)
+    for b in range(batch):
+        w = [int(x) for x in oracle.philox([b, step, 0, 7], key)]
+        u = (w[0] << 32) | w[1]
+        i = (u * n) >> 64
+        x = data[i]
+        if augment:
+            x = np.roll(x, (2 * (w[2] % (L // 2)), 2 * ((w[3] >> 1) % (L // 2))), axis=(0, 1))
+            if w[3] & 1:
+                x = x.T
+        out[b] = x
+        idx[b] = i
+        pts[b] = 0 if points is None else points[i]
+    return out, pts, idx

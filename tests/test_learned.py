@@ -1,7 +1,8 @@
-"""The learned-proposal pipeline of paper_2511_20911_amd.learned: the data
-augmentation is a symmetry of the lattice (CPU), the library's parameter
-initialiser has the stated statistics, and on a 6x6 plateau lattice the
-trained proposal samples the exact law with high acceptance (GPU)."""
+"""The learned-proposal pipeline: the training run's lattice symmetries keep
+every bond count (CPU); the library's minibatches are the documented ones and
+a training run equals its steps one by one (GPU); the parameter initialiser
+has the stated statistics, and on a 6x6 plateau lattice the trained proposal
+samples the exact law with high acceptance (GPU)."""
 import math
 
 import numpy as np
@@ -15,24 +16,25 @@ from paper_2511_20911_amd import learned  # noqa: E402
 
 
 @pytest.mark.parametrize("L", [6, 12, 18])
-def test_augmentation_preserves_every_bond_count(L):
-    """Translations by even vectors and the transpose map the SS lattice onto
-    itself: (M, B1, B2) of every configuration is unchanged."""
+def test_training_symmetries_preserve_every_bond_count(L):
+    """The symmetries crbm_ar_batch applies (translations by even vectors,
+    the transpose) map the SS lattice onto itself: (M, B1, B2) of every drawn
+    configuration equals that of the training configuration it came from,
+    and both transposed and untransposed draws occur."""
+    import oracle
+    from ar_helpers import documented_batch
     rng = np.random.default_rng(L)
-    s = (2 * rng.integers(0, 2, (64, L, L)) - 1).astype(np.int8)
-    gen = torch.Generator()
-    gen.manual_seed(3)
-    before = P.bond_counts(s)
-    seen_transpose = False
-    for _ in range(12):
-        a = learned.augment(torch.from_numpy(s), gen).numpy()
-        after = P.bond_counts(a)
-        for x, y in zip(before, after):
-            assert np.array_equal(x, y)
-        seen_transpose |= not np.array_equal(a, np.roll(s, (0, 0), (1, 2))) and any(
-            np.array_equal(a, np.roll(s, (i, j), (1, 2)).transpose(0, 2, 1)) for i in range(0, L, 2)
-            for j in range(0, L, 2))
-    assert seen_transpose
+    s = (2 * rng.integers(0, 2, (40, L, L)) - 1).astype(np.int8)
+    out, _, idx = documented_batch(oracle, s, 64, seed=0x1234 + L, step=3)
+    before = P.bond_counts(s[idx])
+    after = P.bond_counts(out)
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    transposed = [any(np.array_equal(o, np.roll(s[i], (a, c), (0, 1)).T) for a in range(0, L, 2) for c in range(0, L, 2))
+                  and not any(np.array_equal(o, np.roll(s[i], (a, c), (0, 1))) for a in range(0, L, 2)
+                              for c in range(0, L, 2)) for o, i in zip(out, idx)]
+    assert 0 < sum(transposed) < len(transposed)
+    assert len(set(idx.tolist())) > 20  # the draws spread over the training set
 
 
 def test_odd_translation_is_not_a_symmetry():
@@ -78,3 +80,49 @@ def test_trained_proposal_samples_plateau_6x6():
     assert lm["acceptance"] > 0.3, lm
     assert abs(lm["E_per_spin"] - ref) < 4 * lm["se"] + 1e-12, (lm, ref)
     assert r["gibbs"]["ess_per_s"] > 0 and lm["ess_per_s"] > 0
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("L,augment", [(6, True), (18, True), (12, False)])
+def test_library_minibatches_are_the_documented_ones(L, augment):
+    import oracle
+    from ar_helpers import documented_batch
+    rng = np.random.default_rng(5 + L)
+    s = (2 * rng.integers(0, 2, (300, L, L)) - 1).astype(np.int8)
+    pts = rng.integers(0, 7, 300).astype(np.int32)
+    got, gp, gi = crbm.train_batch(torch.from_numpy(s).cuda(), 96, seed=0xABCDEF0123, step=41, augment=augment,
+                                   points=torch.from_numpy(pts).cuda())
+    ref, rp, ri = documented_batch(oracle, s, 96, seed=0xABCDEF0123, step=41, augment=augment, points=pts)
+    assert np.array_equal(gi.cpu().numpy(), ri)
+    assert np.array_equal(gp.cpu().numpy(), rp)
+    assert np.array_equal(got.cpu().numpy(), ref)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("cond", [False, True])
+def test_training_run_equals_its_steps(cond):
+    """crbm_ar_train over 7 steps (learning rate switching after 3.5 steps)
+    leaves the same parameters, bit for bit, as 7 calls of
+    crbm_ar_train_step_cond on the minibatches crbm_ar_batch draws."""
+    L, n, B = 6, 500, 64
+    rng = np.random.default_rng(9)
+    data = torch.from_numpy((2 * rng.integers(0, 2, (n, L, L)) - 1).astype(np.int8)).cuda()
+    pts = torch.from_numpy(rng.integers(0, 3, n).astype(np.int32)).cuda() if cond else None
+    feats = np.array([[1.0, 0.5, -1.0], [0.5, 0.2, 0.0], [2.0, 0.9, 0.3]])
+
+    def fresh():
+        net = crbm.ARNet(L, cond_points=3 if cond else 0)
+        if cond:
+            net.set_points(feats)
+        net.init_params(seed=4, scale=0.5)
+        return net
+
+    a = fresh()
+    loss_a = a.train(data, 7, batch=B, lr=2e-3, lr_late=5e-4, late_from=0.5, seed=77, step0=3, points=pts)
+    b = fresh()
+    for k in range(7):
+        x, p, _ = crbm.train_batch(data, B, seed=77, step=3 + k, points=pts)
+        loss_b = b.train_step(x, 2e-3 if k < 4 else 5e-4, points=p if cond else None)
+    assert np.array_equal(a.get_params(), b.get_params())
+    assert loss_a == loss_b
+    assert not np.array_equal(a.get_params(), fresh().get_params())
