@@ -250,3 +250,132 @@ def run_chain(inst: Instance, S: int, seed: int, chain: int, sweep_begin: int, s
     if rc != 0:
         raise RuntimeError(f"oracle_run_chain failed: {rc}")
     return s.reshape(L, L), tr, a
+
+
+# ------------------------------------------------------------- general lattices
+
+class _Lattice(ct.Structure):
+    _fields_ = [
+        ("Lr", ct.c_int32), ("Lc", ct.c_int32),
+        ("open_r", ct.c_int32), ("open_c", ct.c_int32),
+        ("J", ct.c_double * 10),
+        ("h_even", ct.c_double), ("h_odd", ct.c_double),
+        ("sched_kind", ct.c_int32),
+        ("T0", ct.c_double), ("T1", ct.c_double),
+        ("T_explicit", ct.POINTER(ct.c_double)),
+        ("id", ct.c_uint32),
+    ]
+
+
+LATTICE_N_ACC = 18  # n, M_e, M_o, B_0..B_9, sum M^2, sum |M|, sum Ms, sum Ms^2, sum |Ms|
+
+
+def ss_filters(J1, J2):
+    """Per-filter couplings of the Shastry-Sutherland lattice: k0-k7 square edges, k8-k9 dimers."""
+    return [float(J1)] * 8 + [float(J2)] * 2
+
+
+class Lattice:
+    """A general lattice: Lr x Lc, open or periodic per axis, one coupling per
+    filter (App. A Convoluter-Reverse), a field per column parity (App. A
+    Accumulator), a temperature schedule and an RNG id."""
+
+    def __init__(self, Lr, Lc, J, h_even=0.0, h_odd=None, open_r=False, open_c=False, sched="const", T0=1.0,
+                 T1=None, T_explicit=None, id=0):
+        self.Lr, self.Lc = int(Lr), int(Lc)
+        self.open_r, self.open_c = bool(open_r), bool(open_c)
+        self.J = [float(x) for x in J]
+        assert len(self.J) == 10
+        self.h_even = float(h_even)
+        self.h_odd = float(h_even if h_odd is None else h_odd)
+        self.sched = sched
+        self.T0 = float(T0)
+        self.T1 = float(T0 if T1 is None else T1)
+        self.T_explicit = None if T_explicit is None else np.ascontiguousarray(T_explicit, np.float64)
+        self.id = int(id)
+
+    def c(self) -> _Lattice:
+        te = None if self.T_explicit is None else _ptr(self.T_explicit, ct.c_double)
+        return _Lattice(self.Lr, self.Lc, int(self.open_r), int(self.open_c), (ct.c_double * 10)(*self.J),
+                        self.h_even, self.h_odd, SCHED[self.sched], self.T0, self.T1, te, self.id)
+
+
+def _lattice_lib():
+    L = lib()
+    if not getattr(L, "_lattice_ready", False):
+        i64, i32, u32 = ct.c_int64, ct.c_int32, ct.c_uint32
+        p = ct.POINTER
+        L.oracle_lattice_bond.argtypes = [p(_Lattice), ct.c_int, ct.c_int, ct.c_int] + [p(ct.c_int)] * 4
+        L.oracle_lattice_bond.restype = ct.c_int
+        L.oracle_lattice_counts.argtypes = [p(_Lattice), p(ct.c_int8), p(i64)]
+        L.oracle_lattice_corr.argtypes = [ct.c_int, ct.c_int, p(ct.c_int8), p(i64)]
+        L.oracle_lattice_init_spins.argtypes = [p(_Lattice), ct.c_uint64, u32, p(ct.c_int8)]
+        L.oracle_lattice_run_chain.argtypes = [p(_Lattice), i64, ct.c_uint64, u32, i64, i64, p(ct.c_int8), p(i32),
+                                               i32, i64, p(i64), p(i64)]
+        L.oracle_lattice_run_chain.restype = ct.c_int
+        L.oracle_lattice_log_marginal.argtypes = [p(_Lattice), i64, i64, p(ct.c_int8)]
+        L.oracle_lattice_log_marginal.restype = ct.c_double
+        L._lattice_ready = True
+    return L
+
+
+def lattice_bond(lat: Lattice, k, i, j):
+    """((ra, ca), (rb, cb)) of bond k of cell (i, j), or None if it is absent."""
+    v = [ct.c_int() for _ in range(4)]
+    ci = lat.c()
+    if not _lattice_lib().oracle_lattice_bond(ct.byref(ci), k, i, j, *[ct.byref(x) for x in v]):
+        return None
+    ra, ca, rb, cb = (x.value for x in v)
+    return (ra, ca), (rb, cb)
+
+
+def lattice_counts(lat: Lattice, spins) -> np.ndarray:
+    """(M_even, M_odd, B_0, ..., B_9) of one configuration."""
+    s = np.ascontiguousarray(spins, np.int8).reshape(lat.Lr * lat.Lc)
+    out = np.zeros(12, np.int64)
+    ci = lat.c()
+    _lattice_lib().oracle_lattice_counts(ct.byref(ci), _ptr(s, ct.c_int8), _ptr(out, ct.c_int64))
+    return out
+
+
+def lattice_corr(Lr, Lc, spins) -> np.ndarray:
+    """Cn[dr, dc + Lc - 1] = sum of s(r,c) s(r+dr, c+dc) over pairs inside the lattice (no wrap)."""
+    s = np.ascontiguousarray(spins, np.int8).reshape(Lr * Lc)
+    out = np.zeros(Lr * (2 * Lc - 1), np.int64)
+    _lattice_lib().oracle_lattice_corr(Lr, Lc, _ptr(s, ct.c_int8), _ptr(out, ct.c_int64))
+    return out.reshape(Lr, 2 * Lc - 1)
+
+
+def lattice_init_spins(lat: Lattice, seed: int, chain: int) -> np.ndarray:
+    s = np.zeros(lat.Lr * lat.Lc, np.int8)
+    ci = lat.c()
+    _lattice_lib().oracle_lattice_init_spins(ct.byref(ci), seed, chain, _ptr(s, ct.c_int8))
+    return s.reshape(lat.Lr, lat.Lc)
+
+
+def lattice_log_marginal(lat: Lattice, S: int, sweep: int, spins) -> float:
+    s = np.ascontiguousarray(spins, np.int8).reshape(lat.Lr * lat.Lc)
+    ci = lat.c()
+    return float(_lattice_lib().oracle_lattice_log_marginal(ct.byref(ci), S, sweep, _ptr(s, ct.c_int8)))
+
+
+def run_lattice_chain(lat: Lattice, S: int, seed: int, chain: int, sweep_begin: int, sweep_end: int,
+                      spins=None, trace=False, measure_every=0, burn_in=0, acc=None, corr=None):
+    """Sweeps [sweep_begin, sweep_end) of one chain of a general lattice.
+    Returns (spins [Lr, Lc], trace [n, 12] of (M_e, M_o, B_0..B_9) or None, acc)."""
+    n_sites = lat.Lr * lat.Lc
+    if spins is None:
+        s = lattice_init_spins(lat, seed, chain).reshape(n_sites).copy()
+    else:
+        s = np.ascontiguousarray(spins, np.int8).reshape(n_sites).copy()
+    n = sweep_end - sweep_begin
+    tr = np.zeros((n, 12), np.int32) if trace else None
+    a = np.zeros(LATTICE_N_ACC, np.int64) if acc is None else acc
+    ci = lat.c()
+    rc = _lattice_lib().oracle_lattice_run_chain(
+        ct.byref(ci), S, seed, chain, sweep_begin, sweep_end, _ptr(s, ct.c_int8),
+        _ptr(tr, ct.c_int32) if trace else None, measure_every, burn_in, _ptr(a, ct.c_int64),
+        None if corr is None else _ptr(corr, ct.c_int64))
+    if rc != 0:
+        raise RuntimeError(f"oracle_lattice_run_chain failed: {rc}")
+    return s.reshape(lat.Lr, lat.Lc), tr, a

@@ -504,3 +504,218 @@ double oracle_log_marginal(const oracle_instance* in, int64_t S, int64_t sweep, 
             }
     return acc;
 }
+
+/* ==================================================================== */
+/* General lattices: open or periodic axes, rectangular Lr x Lc, one      */
+/* coupling per filter, a field per column parity.                        */
+/* ==================================================================== */
+/*
+ * What it follows:
+ *   - App. A Wrapper Module: per axis, the lattice either wraps (the first
+ *     columns / rows are copied past the last ones) or is padded with zeros.
+ *     Reading: on an open axis a bond whose endpoint falls past the last row
+ *     (column) does not exist: no hidden unit is drawn for it and no field
+ *     reaches its remaining spin.  (A hidden unit coupled to a padded zero
+ *     would see one spin only; summed out it gives the constant 2 cosh(w),
+ *     so the marginal law of the spins is the same either way; leaving the
+ *     bond out also leaves no stray noise in the dynamics.)
+ *   - App. A Hidden Node Registers: floor((L+1)/2) cells per axis; for the
+ *     even sizes taken here that is L/2.
+ *   - App. A Convoluter-Reverse: every filter has its own weights (raw
+ *     filters), so each of the 10 filters k carries its own coupling J_k
+ *     (the SS lattice is J_k = J1 for k < 8, J2 for k = 8, 9).
+ *   - App. A Accumulator: separate visible biases for even and odd columns.
+ *
+ * Conventions (beyond those at the top of this file, which they reduce to
+ * for a periodic square lattice with J_k = (J1 x 8, J2 x 2), h_even = h_odd):
+ *   spins      s(r,c), 0 <= r < Lr, 0 <= c < Lc, Lr and Lc even.
+ *   cells      (i,j), 0 <= i < Lr/2, 0 <= j < Lc/2; bond k of cell (i,j) joins
+ *              (2i + dr_a, 2j + dc_a) and (2i + dr_b, 2j + dc_b) (the table
+ *              above); a coordinate equal to Lr (Lc) wraps to 0 on a periodic
+ *              axis and makes the bond absent on an open one.
+ *   weights    per sweep and filter k: K_k = -(Jq_k / 2^16) / T_s, sig_k, wq_k
+ *              as above; visible bias aq_p = llround(hq_p / T_s) for column
+ *              parity p = c mod 2.
+ *   uniforms   the hidden and spin uniforms of the square lattice with the
+ *              column layout of Lc (W = ceil(Lc/32) words per row, i the cell
+ *              row); init: site index r Lc + c.
+ *   counts     M_e, M_o = spin sums over even / odd columns; B_k = sum over the
+ *              present bonds of filter k of s_a s_b; energy
+ *              E_q = sum_k Jq_k B_k - hq_e M_e - hq_o M_o (exact, 2^16 units).
+ *   corr       Cn(dr, dc) = sum over sites with (r + dr, c + dc) inside the
+ *              lattice of s(r,c) s(r+dr, c+dc), 0 <= dr < Lr, -Lc < dc < Lc,
+ *              no wrapping, stored [dr][dc + Lc - 1]: for every wave vector q,
+ *              |sum_r s_r e^{i q.r}|^2 = sum over all displacements of
+ *              Cn(d) e^{i q.d} (Eq. (13)), with Cn(-d) = Cn(d).
+ */
+
+
+/* Sites of bond k of cell (i,j); returns 1 if the bond exists. */
+int oracle_lattice_bond(const oracle_lattice* in, int k, int i, int j, int* ra, int* ca, int* rb, int* cb)
+{
+    int r0 = 2 * i + BOND[k][0], c0 = 2 * j + BOND[k][1];
+    int r1 = 2 * i + BOND[k][2], c1 = 2 * j + BOND[k][3];
+    if (r0 >= in->Lr || r1 >= in->Lr) {
+        if (in->open_r) return 0;
+        r0 %= in->Lr;
+        r1 %= in->Lr;
+    }
+    if (c0 >= in->Lc || c1 >= in->Lc) {
+        if (in->open_c) return 0;
+        c0 %= in->Lc;
+        c1 %= in->Lc;
+    }
+    *ra = r0; *ca = c0; *rb = r1; *cb = c1;
+    return 1;
+}
+
+void oracle_lattice_counts(const oracle_lattice* in, const int8_t* s, int64_t out[12])
+{
+    int Lr = in->Lr, Lc = in->Lc;
+    for (int q = 0; q < 12; ++q) out[q] = 0;
+    for (int r = 0; r < Lr; ++r)
+        for (int c = 0; c < Lc; ++c) out[c % 2] += s[r * Lc + c];
+    for (int k = 0; k < 10; ++k)
+        for (int i = 0; i < Lr / 2; ++i)
+            for (int j = 0; j < Lc / 2; ++j) {
+                int ra, ca, rb, cb;
+                if (oracle_lattice_bond(in, k, i, j, &ra, &ca, &rb, &cb))
+                    out[2 + k] += s[ra * Lc + ca] * s[rb * Lc + cb];
+            }
+}
+
+void oracle_lattice_corr(int Lr, int Lc, const int8_t* s, int64_t* corr)
+{
+    /* corr[dr][dc + Lc - 1] += sum of s(r,c) s(r+dr, c+dc) over pairs inside the lattice */
+    for (int dr = 0; dr < Lr; ++dr)
+        for (int dc = -(Lc - 1); dc < Lc; ++dc) {
+            int64_t acc = 0;
+            for (int r = 0; r + dr < Lr; ++r)
+                for (int c = 0; c < Lc; ++c) {
+                    int c2 = c + dc;
+                    if (c2 < 0 || c2 >= Lc) continue;
+                    acc += s[r * Lc + c] * s[(r + dr) * Lc + c2];
+                }
+            corr[dr * (2 * Lc - 1) + dc + Lc - 1] += acc;
+        }
+}
+
+void oracle_lattice_init_spins(const oracle_lattice* in, uint64_t seed, uint32_t chain, int8_t* s)
+{
+    uint32_t key[2] = { (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32) };
+    for (int r = 0; r < in->Lr; ++r)
+        for (int c = 0; c < in->Lc; ++c) {
+            uint32_t site = (uint32_t)(r * in->Lc + c);
+            uint32_t ctr[4] = { site >> 7, 0u, chain, (in->id << 3) | 0u };
+            uint32_t out[4];
+            oracle_philox4x32_10(ctr, key, out);
+            uint32_t b = site & 127u;
+            s[r * in->Lc + c] = ((out[b >> 5] >> (b & 31u)) & 1u) ? +1 : -1;
+        }
+}
+
+/* Per-sweep weights of a general lattice: wq[k], sig[k] per filter, aq[p] per column parity. */
+static int lattice_params(const oracle_lattice* in, int64_t S, int64_t s, int64_t wq[10], int sig[10],
+                          int64_t aq[2])
+{
+    double T = oracle_schedule_T(in->sched_kind, in->T0, in->T1, in->T_explicit, S, s);
+    if (!(T > 0.0) || !isfinite(T)) return -1;
+    for (int k = 0; k < 10; ++k) oracle_bond_weight(oracle_quantise(in->J[k]), T, &wq[k], &sig[k]);
+    aq[0] = oracle_visible_bias(oracle_quantise(in->h_even), T);
+    aq[1] = oracle_visible_bias(oracle_quantise(in->h_odd), T);
+    return 0;
+}
+
+int oracle_lattice_run_chain(const oracle_lattice* in, int64_t S, uint64_t seed, uint32_t chain,
+                             int64_t sweep_begin, int64_t sweep_end, int8_t* s, int32_t* trace,
+                             int32_t measure_every, int64_t burn_in, int64_t* acc, int64_t* corr_acc)
+{
+    int Lr = in->Lr, Lc = in->Lc, Cr = Lr / 2, Cc = Lc / 2;
+    int8_t* hid = (int8_t*)malloc((size_t)10 * Cr * Cc);
+    int64_t* field = (int64_t*)malloc(sizeof(int64_t) * (size_t)Lr * Lc);
+    if (!hid || !field) { free(hid); free(field); return -3; }
+    for (int64_t sw = sweep_begin; sw < sweep_end; ++sw) {
+        int64_t wq[10], aq[2];
+        int sig[10];
+        if (lattice_params(in, S, sw, wq, sig, aq) != 0) {
+            free(hid);
+            free(field);
+            return -1;
+        }
+        uint32_t sweep = (uint32_t)sw;
+        /* hidden half-step, Eq. (11): every present bond's unit from the old spins */
+        for (int k = 0; k < 10; ++k)
+            for (int i = 0; i < Cr; ++i)
+                for (int j = 0; j < Cc; ++j) {
+                    int ra, ca, rb, cb;
+                    int8_t* h = &hid[(k * Cr + i) * Cc + j];
+                    if (!oracle_lattice_bond(in, k, i, j, &ra, &ca, &rb, &cb)) {
+                        *h = 0;
+                        continue;
+                    }
+                    int64_t x = wq[k] * (int64_t)(s[ra * Lc + ca] + sig[k] * s[rb * Lc + cb]);
+                    *h = gibbs_unit(x, oracle_uniform_hidden(seed, in->id, chain, sweep, Lc, k, i, j));
+                }
+        /* visible half-step, Eq. (12), with the column-parity bias of App. A Accumulator */
+        for (int r = 0; r < Lr; ++r)
+            for (int c = 0; c < Lc; ++c) field[r * Lc + c] = aq[c % 2];
+        for (int k = 0; k < 10; ++k)
+            for (int i = 0; i < Cr; ++i)
+                for (int j = 0; j < Cc; ++j) {
+                    int ra, ca, rb, cb;
+                    if (!oracle_lattice_bond(in, k, i, j, &ra, &ca, &rb, &cb)) continue;
+                    int64_t hv = hid[(k * Cr + i) * Cc + j];
+                    field[ra * Lc + ca] += wq[k] * hv;
+                    field[rb * Lc + cb] += wq[k] * sig[k] * hv;
+                }
+        for (int r = 0; r < Lr; ++r)
+            for (int c = 0; c < Lc; ++c)
+                s[r * Lc + c] = gibbs_unit(field[r * Lc + c],
+                                           oracle_uniform_visible(seed, in->id, chain, sweep, Lc, r, c));
+        const int measured = measure_every > 0 && sw >= burn_in && (sw - burn_in) % measure_every == 0;
+        if (trace || (acc && measured)) {
+            int64_t cnt[12];
+            oracle_lattice_counts(in, s, cnt);
+            if (trace)
+                for (int q = 0; q < 12; ++q) trace[12 * (sw - sweep_begin) + q] = (int32_t)cnt[q];
+            if (acc && measured) {
+                int64_t M = cnt[0] + cnt[1], ms = 0;
+                for (int r = 0; r < Lr; ++r)
+                    for (int c = 0; c < Lc; ++c) ms += ((r + c) % 2 == 0) ? s[r * Lc + c] : -s[r * Lc + c];
+                acc[0] += 1;
+                for (int q = 0; q < 12; ++q) acc[1 + q] += cnt[q];
+                acc[13] += M * M;
+                acc[14] += M < 0 ? -M : M;
+                acc[15] += ms;
+                acc[16] += ms * ms;
+                acc[17] += ms < 0 ? -ms : ms;
+            }
+        }
+        if (corr_acc && measured) oracle_lattice_corr(Lr, Lc, s, corr_acc);
+    }
+    free(hid);
+    free(field);
+    return 0;
+}
+
+/* log of the sum over the hidden units of exp(sum_b w_b h_b (s_a + sig_b s_b) + sum_c a_{c%2} s),
+ * real-valued weights of sweep s (Eq. (4) on a general lattice: present bonds only). */
+double oracle_lattice_log_marginal(const oracle_lattice* in, int64_t S, int64_t sweep, const int8_t* s)
+{
+    int64_t wq[10], aq[2];
+    int sig[10];
+    if (lattice_params(in, S, sweep, wq, sig, aq) != 0) return NAN;
+    int Lr = in->Lr, Lc = in->Lc;
+    double acc = 0.0;
+    for (int r = 0; r < Lr; ++r)
+        for (int c = 0; c < Lc; ++c) acc += ldexp((double)aq[c % 2], -16) * (double)s[r * Lc + c];
+    for (int k = 0; k < 10; ++k)
+        for (int i = 0; i < Lr / 2; ++i)
+            for (int j = 0; j < Lc / 2; ++j) {
+                int ra, ca, rb, cb;
+                if (!oracle_lattice_bond(in, k, i, j, &ra, &ca, &rb, &cb)) continue;
+                double x = ldexp((double)wq[k], -16) * (double)(s[ra * Lc + ca] + sig[k] * s[rb * Lc + cb]);
+                acc += log(2.0 * cosh(x));
+            }
+    return acc;
+}

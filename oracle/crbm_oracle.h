@@ -43,4 +43,28 @@ int      oracle_run_chain(const oracle_instance* in, int64_t S, uint64_t seed, u
                           int64_t* corr_acc);
 double   oracle_log_marginal(const oracle_instance* in, int64_t S, int64_t sweep, const int8_t* s);
 
+/* General lattices (open or periodic axes, one coupling per filter, a field
+ * per column parity); conventions in crbm_oracle.c. */
+typedef struct {
+    int32_t Lr, Lc;        /* rows, columns: even */
+    int32_t open_r, open_c;/* 1: that axis is open (bonds past the edge absent), 0: periodic */
+    double J[10];          /* coupling of filter k */
+    double h_even, h_odd;  /* field on even / odd columns */
+    int32_t sched_kind;
+    double T0, T1;
+    const double* T_explicit;
+    uint32_t id;
+} oracle_lattice;
+
+#define ORACLE_LATTICE_N_ACC 18  /* n, M_e, M_o, B_0..B_9, sum M^2, sum |M|, sum Ms, sum Ms^2, sum |Ms| */
+
+int      oracle_lattice_bond(const oracle_lattice* in, int k, int i, int j, int* ra, int* ca, int* rb, int* cb);
+void     oracle_lattice_counts(const oracle_lattice* in, const int8_t* s, int64_t out[12]);
+void     oracle_lattice_corr(int Lr, int Lc, const int8_t* s, int64_t* corr);
+void     oracle_lattice_init_spins(const oracle_lattice* in, uint64_t seed, uint32_t chain, int8_t* s);
+int      oracle_lattice_run_chain(const oracle_lattice* in, int64_t S, uint64_t seed, uint32_t chain,
+                                  int64_t sweep_begin, int64_t sweep_end, int8_t* s, int32_t* trace,
+                                  int32_t measure_every, int64_t burn_in, int64_t* acc, int64_t* corr_acc);
+double   oracle_lattice_log_marginal(const oracle_lattice* in, int64_t S, int64_t sweep, const int8_t* s);
+
 #endif

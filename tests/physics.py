@@ -84,3 +84,59 @@ def structure_factor(corr_sum, n_samples, L):
     F = np.fft.fft2(C).real  # sum_d C(d) e^{-i q d}; C is inversion symmetric
     N = L * L
     return F / N / N
+
+
+# ------------------------------------------------------- general lattices
+
+def lattice_bonds(Lr, Lc, open_r=False, open_c=False):
+    """Bonds of an Lr x Lc Shastry-Sutherland lattice as (filter, site a, site b),
+    written from the square-lattice edges and the dimer plaquettes of Fig. 1a,
+    labelled by the parity of their first site: horizontal edge (r,c)-(r,c+1) is
+    filter 0/1 on even rows (even/odd c) and 2/3 on odd rows; vertical edge
+    (r,c)-(r+1,c) is 4/5 in even columns (even/odd r) and 6/7 in odd columns;
+    the '\\' dimer (2i,2j)-(2i+1,2j+1) is 8 and the '/' dimer
+    (2i+1,2j+2)-(2i+2,2j+1) is 9.  On an open axis the edges and dimers that
+    would wrap around are left out."""
+    out = []
+    for r in range(Lr):
+        for c in range(Lc):
+            if c + 1 < Lc or not open_c:
+                out.append((2 * (r % 2) + (c % 2), (r, c), (r, (c + 1) % Lc)))
+            if r + 1 < Lr or not open_r:
+                out.append((4 + 2 * (c % 2) + (r % 2), (r, c), ((r + 1) % Lr, c)))
+    for i in range(Lr // 2):
+        for j in range(Lc // 2):
+            out.append((8, (2 * i, 2 * j), (2 * i + 1, 2 * j + 1)))
+            if (2 * j + 2 < Lc or not open_c) and (2 * i + 2 < Lr or not open_r):
+                out.append((9, (2 * i + 1, (2 * j + 2) % Lc), ((2 * i + 2) % Lr, 2 * j + 1)))
+    return out
+
+
+def lattice_counts(spins, Lr, Lc, open_r=False, open_c=False):
+    """spins [..., Lr, Lc] -> int64 [..., 12] = (M_even, M_odd, B_0..B_9)."""
+    s = np.asarray(spins, np.int64)
+    out = np.zeros(s.shape[:-2] + (12,), np.int64)
+    out[..., 0] = s[..., :, 0::2].sum(axis=(-1, -2))
+    out[..., 1] = s[..., :, 1::2].sum(axis=(-1, -2))
+    for k, a, b in lattice_bonds(Lr, Lc, open_r, open_c):
+        out[..., 2 + k] += s[..., a[0], a[1]] * s[..., b[0], b[1]]
+    return out
+
+
+def lattice_energy(counts, J, h_even, h_odd):
+    """H = sum_k J_k B_k - h_even M_even - h_odd M_odd from lattice_counts."""
+    c = np.asarray(counts, np.float64)
+    return c[..., 2:] @ np.asarray(J, np.float64) - h_even * c[..., 0] - h_odd * c[..., 1]
+
+
+def lattice_exact(Lr, Lc, J, h_even, h_odd, T, open_r=False, open_c=False):
+    """Exact <E>/N and <m> by enumeration of all 2^(Lr Lc) states (Lr Lc <= 16)."""
+    n = Lr * Lc
+    idx = np.arange(1 << n, dtype=np.int64)
+    st = (2 * ((idx[:, None] >> np.arange(n)[None, :]) & 1) - 1).reshape(-1, Lr, Lc)
+    cnt = lattice_counts(st, Lr, Lc, open_r, open_c)
+    E = lattice_energy(cnt, J, h_even, h_odd)
+    M = cnt[:, 0] + cnt[:, 1]
+    w = np.exp(-(E - E.min()) / T)
+    Z = w.sum()
+    return {"E": float((w * E).sum() / Z / n), "m": float((w * M).sum() / Z / n), "E_min": float(E.min() / n)}
