@@ -67,7 +67,7 @@ def test_init_params_statistics():
 def test_trained_proposal_samples_plateau_6x6():
     """6x6 at (J2, h, T) = (1, 3, 0.4): trained on Gibbs samples, learned MH
     (1 MH : 10 Gibbs) reproduces the exact <E>/N of the transfer matrix within
-    4 SE with acceptance above 0.3."""
+    3 SE with acceptance above 0.3."""
     from oracle import exact
     L, T = 6, 0.4
     data = learned.training_set(L, 1.0, 1.0, 3.0, T, n_chains=1024, anneal_sweeps=2000, snapshots=64)
@@ -78,7 +78,7 @@ def test_trained_proposal_samples_plateau_6x6():
     ref = exact.tm_averages(L, 1.0, 1.0, 3.0, T)["E"]
     lm = r["learned"]
     assert lm["acceptance"] > 0.3, lm
-    assert abs(lm["E_per_spin"] - ref) < 4 * lm["se"] + 1e-12, (lm, ref)
+    assert abs(lm["E_per_spin"] - ref) < 3 * lm["se"] + 1e-12, (lm, ref)
     assert r["gibbs"]["ess_per_s"] > 0 and lm["ess_per_s"] > 0
 
 
@@ -126,3 +126,32 @@ def test_training_run_equals_its_steps(cond):
     assert np.array_equal(a.get_params(), b.get_params())
     assert loss_a == loss_b
     assert not np.array_equal(a.get_params(), fresh().get_params())
+
+
+@pytest.mark.gpu
+def test_learned_mh_beats_gibbs_on_the_plateau_18x18():
+    """The learned part's claim at 18x18 on the 1/3 plateau (Sec. III.A point
+    J2/J1 = 1, h/J1 = 3), T = 0.2: a proposal trained on 2^20 Gibbs samples,
+    run as 1 MH : 10 Gibbs sweeps on 8192 chains, gives more energy and
+    order-parameter effective samples per second than plain Gibbs run for the
+    same wall time from the same seeded start; its <E>/N lies within 3 SE of
+    the exact transfer-matrix value, and it is at least as close to that value
+    as plain Gibbs (whose chains freeze into domains of different plateau
+    translations at this temperature)."""
+    import json
+    import os
+    L, T = 18, 0.2
+    ref_path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "plateau_reference.json")
+    with open(ref_path) as f:
+        ref = [v["E_per_spin"] for v in json.load(f)["values"] if v["L"] == 12 and v["T"] == T][0]
+    data = learned.training_set(L, 1.0, 1.0, 3.0, T)
+    net = crbm.ARNet(L, seed=5)
+    net.init_params(seed=5, scale=0.5)
+    learned.train(net, data, steps=800)
+    del data
+    r = learned.compare(net, L, 1.0, 1.0, 3.0, T, cycles=500)
+    lm, gb = r["learned"], r["gibbs"]
+    assert lm["acceptance"] > 0.3, lm
+    assert lm["ess_per_s"] > gb["ess_per_s"] and lm["ess_min_per_s"] > gb["ess_min_per_s"], (lm, gb)
+    assert abs(lm["E_per_spin"] - ref) <= 3 * lm["se"] + 1e-12, (lm["E_per_spin"], ref, lm["se"])
+    assert abs(lm["E_per_spin"] - ref) <= abs(gb["E_per_spin"] - ref) + 1e-12, (lm["E_per_spin"], gb["E_per_spin"], ref)
