@@ -62,7 +62,7 @@ enum {
 /* One Hamiltonian point (one "instance").  Host memory, copied at create. */
 typedef struct {
     int32_t L;                 /* lattice side: even, 4 <= L <= 32, or 36, 40, 48, 64, 72, 96 */
-    int32_t periodic;          /* must be 1 (periodic in both directions) */
+    int32_t periodic;          /* must be 1 (periodic in both directions); open axes: crbm_lattice_create */
     double J1, J2, h;          /* couplings and field; |J| * 2^16 < 2^31 */
     int32_t n_chains;          /* independent chains, >= 1 */
     int32_t sched_kind;        /* CRBM_SCHED_* */
@@ -438,6 +438,108 @@ int crbm_table_for(double J1, double J2, double h, double T, uint32_t out[16]);
  * CRBM_ERANGE if a 16.16 value overflows int32, CRBM_EINVAL for a bad T,
  * precision or NULL out. */
 int crbm_table_for_precision(double J1, double J2, double h, double T, int32_t precision, uint32_t* out);
+
+/* ------------------------------------------------------------------------
+ * General lattices: open or periodic axes, one coupling per filter, a field
+ * per column parity.
+ *
+ * App. A Wrapper Module: each axis of the lattice either wraps around or is
+ * padded with zeros (open boundary; Sec. III.A uses it for the laterally
+ * confined lattices of width 12).  Here a bond whose endpoint falls past the
+ * last row (column) of an open axis does not exist: no hidden unit is drawn
+ * for it and no field reaches its other spin.  App. A Hidden Node Registers:
+ * (rows/2) x (cols/2) cells of 10 filters.  App. A Convoluter-Reverse: the
+ * host writes every filter, so each filter k carries its own coupling J_k
+ * (k0-k3: horizontal square edges (0,0)-(0,1), (0,1)-(0,2), (1,0)-(1,1),
+ * (1,1)-(1,2) of the cell window; k4-k7: vertical edges (0,0)-(1,0),
+ * (1,0)-(2,0), (0,1)-(1,1), (1,1)-(2,1); k8: the dimer (0,0)-(1,1); k9: the
+ * dimer (1,2)-(2,1)); the Shastry-Sutherland lattice is J_k = J1 for k < 8
+ * and J2 for k = 8, 9.  App. A Accumulator: separate visible biases for even
+ * and odd columns.  H = sum_k J_k sum_{bonds of k} s_a s_b - h_even sum_{even c} s
+ * - h_odd sum_{odd c} s.
+ *
+ * Arithmetic and random numbers follow the square-lattice sampler (16.16
+ * couplings, 32-bit thresholds, the same Philox counters with the column
+ * layout of `cols`), so a periodic square lattice with the SS couplings gives
+ * the trajectories of crbm_create / crbm_sample bit for bit.
+ *
+ * Counts of one state (int32, exact): c[0] = M_even, c[1] = M_odd (spin sums
+ * over even / odd columns), c[2 + k] = B_k = sum over the bonds of filter k of
+ * s_a s_b; E = sum_k Jq_k B_k - hq_even M_even - hq_odd M_odd in 2^-16 units
+ * (Jq = llround(J 2^16)).
+ * ------------------------------------------------------------------------ */
+#define CRBM_LAT_MAX_SIDE 64
+#define CRBM_LAT_N_COUNTS 12
+/* accumulator words per instance: n, sums of the 12 counts, sum M^2, sum |M|,
+ * sum Ms, sum Ms^2, sum |Ms| (M = M_even + M_odd, Ms = sum (-1)^(r+c) s) */
+#define CRBM_LAT_N_ACC 18
+
+typedef struct {
+    int32_t rows, cols;            /* even, 4 <= rows, cols <= CRBM_LAT_MAX_SIDE */
+    int32_t open_rows, open_cols;  /* 1: that axis is open, 0: periodic */
+    double J[10];                  /* coupling of filter k; |J| 2^16 < 2^31 */
+    double h_even, h_odd;          /* field on even / odd columns */
+    int32_t n_chains;              /* >= 1 */
+    int32_t sched_kind;            /* CRBM_SCHED_* */
+    double T0, T1;
+    const double* T_explicit;      /* host array of n_sweeps temperatures (EXPLICIT only), copied */
+    uint32_t id;                   /* instance id in the random-number counter, < 2^29 */
+} crbm_lattice;
+
+typedef struct crbm_lat_s crbm_lat_t;
+
+/* Create a sampler for n_inst general lattices sharing cfg (seed, n_sweeps,
+ * measure_every, burn_in, stream, flags; CRBM_F_CORR accumulates the
+ * displacement correlation below).  tile_rows, launch_mode and
+ * waves_per_block are ignored; precision must be CRBM_PRECISION_Q16.
+ * Builds the per-sweep tables on the host, allocates the device state and
+ * initialises every chain from the seed (stream 0, site index r cols + c);
+ * returns after the set-up has finished on cfg->stream.  Errors:
+ * CRBM_EINVAL (odd or out-of-range sides, non-finite couplings or fields,
+ * T <= 0, n_chains < 1, NULL pointers), CRBM_ERANGE (a field leaves int32 at
+ * some sweep), CRBM_EUNSUPPORTED (another precision), CRBM_EHIP. */
+int crbm_lattice_create(const crbm_lattice* inst, int32_t n_inst, const crbm_config* cfg, crbm_lat_t** out);
+
+/* Enqueue the next n_sweeps sweeps on cfg->stream (asynchronous).
+ * spins_out: device int8 [sum of chains x rows x cols] (+-1, instances
+ *   concatenated, chains row-major) or NULL.
+ * counts_trace: device int32 [n_sweeps / trace_every][total chains][12], the
+ *   counts after every trace_every-th sweep of this call, or NULL.
+ * Errors: CRBM_EINVAL (trace_every < 1 or not dividing n_sweeps),
+ * CRBM_ESTATE (past the end of the schedule), CRBM_EHIP. */
+int crbm_lattice_sample(crbm_lat_t* h, int64_t n_sweeps, int8_t* spins_out, int32_t* counts_trace,
+                        int32_t trace_every);
+
+/* Synchronise the stream and return, per instance, the CRBM_LAT_N_ACC
+ * accumulator sums over chains and measured sweeps (host int64
+ * [n_inst][CRBM_LAT_N_ACC]).  corr_out (host int64, or NULL; needs
+ * CRBM_F_CORR): per instance [rows][2 cols - 1] sums over chains and measured
+ * sweeps of Cn(dr, dc) = sum of s(r,c) s(r+dr, c+dc) over the pairs inside the
+ * lattice (no wrapping), 0 <= dr < rows, -cols < dc < cols at index
+ * [dr][dc + cols - 1]: the static structure factor of Sec. III.B Eq. (13) at
+ * any wave vector q is sum over all displacements d of Cn(d) e^{i q.d}
+ * (Cn(-d) = Cn(d)), on open and periodic lattices alike. */
+int crbm_lattice_observables(crbm_lat_t* h, int64_t* acc_out, int64_t* corr_out);
+
+/* Zero the accumulators and correlation sums (asynchronous). */
+int crbm_lattice_reset_observables(crbm_lat_t* h);
+
+/* Checkpoint / resume: int8 spins (device, layout of spins_out) and the
+ * sweep index.  get_state synchronises; set_state is asynchronous.
+ * CRBM_EINVAL for a sweep index outside [0, n_sweeps]. */
+int crbm_lattice_get_state(crbm_lat_t* h, int8_t* spins_dev, int64_t* sweep_index);
+int crbm_lattice_set_state(crbm_lat_t* h, const int8_t* spins_dev, int64_t sweep_index);
+
+int64_t crbm_lattice_total_chains(const crbm_lat_t* h);
+
+/* Free everything the handle owns (after its stream has finished).  NULL is allowed. */
+void crbm_lattice_destroy(crbm_lat_t* h);
+
+/* Host only: the device table of one sweep at temperature T for a lattice
+ * (1056 words: per-filter hidden thresholds and flags, then 512 visible
+ * entries by sublattice, edge type and incident-unit pattern; layout in the
+ * kernel source).  For tests.  CRBM_EINVAL, CRBM_ERANGE as crbm_lattice_create. */
+int crbm_lattice_table(const crbm_lattice* inst, double T, uint32_t* out);
 
 #ifdef __cplusplus
 }

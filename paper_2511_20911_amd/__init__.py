@@ -81,6 +81,17 @@ class _TrainOpts(ct.Structure):
                 ("late_from", ct.c_double), ("seed", ct.c_uint64), ("step0", ct.c_int64), ("augment", ct.c_int32)]
 
 
+class _Lattice(ct.Structure):
+    _fields_ = [("rows", ct.c_int32), ("cols", ct.c_int32), ("open_rows", ct.c_int32), ("open_cols", ct.c_int32),
+                ("J", ct.c_double * 10), ("h_even", ct.c_double), ("h_odd", ct.c_double),
+                ("n_chains", ct.c_int32), ("sched_kind", ct.c_int32), ("T0", ct.c_double), ("T1", ct.c_double),
+                ("T_explicit", ct.POINTER(ct.c_double)), ("id", ct.c_uint32)]
+
+
+LAT_N_ACC = 18
+LAT_TAB_WORDS = 1056
+
+
 _lib = None
 
 
@@ -149,6 +160,17 @@ def lib() -> ct.CDLL:
                                    p(ct.c_double), p(ct.c_int32), p(ct.c_double)]
         L.crbm_tau_int_noalloc.argtypes = L.crbm_tau_int.argtypes
         L.crbm_get_tiling.argtypes = [ct.c_int32, p(ct.c_int32), p(ct.c_int32)]
+        L.crbm_lattice_create.argtypes = [p(_Lattice), ct.c_int32, p(_Config), p(ct.c_void_p)]
+        L.crbm_lattice_sample.argtypes = [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_int32]
+        L.crbm_lattice_observables.argtypes = [ct.c_void_p, p(ct.c_int64), ct.c_void_p]
+        L.crbm_lattice_reset_observables.argtypes = [ct.c_void_p]
+        L.crbm_lattice_get_state.argtypes = [ct.c_void_p, ct.c_void_p, p(ct.c_int64)]
+        L.crbm_lattice_set_state.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int64]
+        L.crbm_lattice_total_chains.argtypes = [ct.c_void_p]
+        L.crbm_lattice_total_chains.restype = ct.c_int64
+        L.crbm_lattice_destroy.argtypes = [ct.c_void_p]
+        L.crbm_lattice_destroy.restype = None
+        L.crbm_lattice_table.argtypes = [p(_Lattice), ct.c_double, p(ct.c_uint32)]
         _lib = L
     return _lib
 
@@ -508,3 +530,145 @@ def sample_mh(sampler: Sampler, net: ARNet, n_cycles: int, gibbs_per_mh: int, tr
                                 ct.c_void_p(trace.data_ptr()) if trace is not None else None,
                                 ct.c_void_p(order.data_ptr()) if order is not None else None, ct.byref(acc)))
     return int(acc.value)
+
+
+# ------------------------------------------------------------- general lattices
+
+def ss_filters(J1: float, J2: float):
+    """Per-filter couplings of the Shastry-Sutherland lattice: filters k0-k7
+    are square edges (J1), k8 and k9 the dimers (J2)."""
+    return [float(J1)] * 8 + [float(J2)] * 2
+
+
+@dataclass
+class Lattice:
+    """One general lattice for crbm_lattice_create: rows x cols, each axis open
+    or periodic, one coupling per filter, fields on even / odd columns."""
+    rows: int
+    cols: int
+    J: Sequence[float]
+    h_even: float = 0.0
+    h_odd: Optional[float] = None
+    open_rows: bool = False
+    open_cols: bool = False
+    n_chains: int = 64
+    sched: str = "const"
+    T0: float = 1.0
+    T1: Optional[float] = None
+    T_explicit: Optional[np.ndarray] = None
+    id: int = 0
+
+    def c(self, keep):
+        te = None
+        if self.sched == "explicit":
+            t = np.ascontiguousarray(self.T_explicit, np.float64)
+            keep.append(t)
+            te = t.ctypes.data_as(ct.POINTER(ct.c_double))
+        J = [float(x) for x in self.J]
+        assert len(J) == 10
+        return _Lattice(self.rows, self.cols, int(self.open_rows), int(self.open_cols), (ct.c_double * 10)(*J),
+                        float(self.h_even), float(self.h_even if self.h_odd is None else self.h_odd), self.n_chains,
+                        SCHED[self.sched], self.T0, self.T0 if self.T1 is None else self.T1, te, self.id)
+
+
+def lattice_table(lat: Lattice, T: float) -> np.ndarray:
+    """The device table of one sweep at temperature T (host only)."""
+    out = np.zeros(LAT_TAB_WORDS, np.uint32)
+    keep = []
+    c = lat.c(keep)
+    _check(lib().crbm_lattice_table(ct.byref(c), float(T), out.ctypes.data_as(ct.POINTER(ct.c_uint32))))
+    return out
+
+
+class LatticeSampler:
+    """Handle on crbm_lattice_create / crbm_lattice_sample / crbm_lattice_observables."""
+
+    def __init__(self, lattices: Sequence[Lattice], seed: int, n_sweeps: int, measure_every: int = 0,
+                 burn_in: int = 0, stream=None, corr: bool = False):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the CRBM sampler runs only on the HIP device")
+        self.lattices = list(lattices)
+        self._keep = []
+        arr = (_Lattice * len(self.lattices))()
+        for k, I in enumerate(self.lattices):
+            arr[k] = I.c(self._keep)
+        cfg = _Config(seed, n_sweeps, measure_every, burn_in, _stream_handle(stream), 0, 0, 0, 0,
+                      CRBM_F_CORR if corr else 0)
+        h = ct.c_void_p()
+        _check(lib().crbm_lattice_create(arr, len(self.lattices), ct.byref(cfg), ct.byref(h)))
+        self._h = h
+        self.corr = corr
+        self.n_sweeps = n_sweeps
+        self.total_chains = int(lib().crbm_lattice_total_chains(h))
+        self.spin_offsets = np.cumsum([0] + [I.n_chains * I.rows * I.cols for I in self.lattices])
+        self.chain_offsets = np.cumsum([0] + [I.n_chains for I in self.lattices])
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.crbm_lattice_destroy(h)
+            self._h = None
+
+    def close(self):
+        self.__del__()
+
+    @property
+    def total_spins(self) -> int:
+        return int(self.spin_offsets[-1])
+
+    def sample(self, n_sweeps: int, spins_out=None, trace=None, trace_every: int = 1):
+        """Enqueue n_sweeps sweeps.  spins_out: int8 CUDA tensor of total_spins
+        elements; trace: int32 CUDA tensor [n_sweeps // trace_every, total_chains, 12]
+        of (M_even, M_odd, B_0..B_9) after every trace_every-th sweep."""
+        if spins_out is not None:
+            assert spins_out.is_cuda and spins_out.dtype.itemsize == 1 and spins_out.numel() == self.total_spins
+        if trace is not None:
+            assert trace.is_cuda and trace.element_size() == 4
+            assert trace.numel() == (n_sweeps // trace_every) * self.total_chains * 12
+        _check(lib().crbm_lattice_sample(self._h, n_sweeps,
+                                         ct.c_void_p(spins_out.data_ptr()) if spins_out is not None else None,
+                                         ct.c_void_p(trace.data_ptr()) if trace is not None else None,
+                                         int(trace_every)))
+
+    def observables(self):
+        """Per-lattice int64 accumulator sums [n, 18] and, for a sampler created
+        with corr=True, the per-lattice [rows, 2 cols - 1] displacement
+        correlation sums (else None)."""
+        acc = np.zeros((len(self.lattices), LAT_N_ACC), np.int64)
+        cbuf = None
+        if self.corr:
+            cbuf = np.zeros(sum(I.rows * (2 * I.cols - 1) for I in self.lattices), np.int64)
+        _check(lib().crbm_lattice_observables(self._h, acc.ctypes.data_as(ct.POINTER(ct.c_int64)),
+                                              cbuf.ctypes.data_as(ct.c_void_p) if cbuf is not None else None))
+        if cbuf is None:
+            return acc, None
+        parts, off = [], 0
+        for I in self.lattices:
+            n = I.rows * (2 * I.cols - 1)
+            parts.append(cbuf[off:off + n].reshape(I.rows, 2 * I.cols - 1))
+            off += n
+        return acc, parts
+
+    def reset_observables(self):
+        _check(lib().crbm_lattice_reset_observables(self._h))
+
+    def get_state(self):
+        import torch
+        spins = torch.empty(self.total_spins, dtype=torch.int8, device="cuda")
+        idx = ct.c_int64()
+        _check(lib().crbm_lattice_get_state(self._h, ct.c_void_p(spins.data_ptr()), ct.byref(idx)))
+        return spins, int(idx.value)
+
+    def set_state(self, spins, sweep_index: int):
+        assert spins is None or (spins.is_cuda and spins.numel() == self.total_spins)
+        _check(lib().crbm_lattice_set_state(self._h, ct.c_void_p(spins.data_ptr()) if spins is not None else None,
+                                            int(sweep_index)))
+
+    def split_spins(self, flat):
+        """Split a flat [total_spins] tensor into per-lattice [n_chains, rows, cols] views."""
+        out = []
+        for k, I in enumerate(self.lattices):
+            a, b = int(self.spin_offsets[k]), int(self.spin_offsets[k + 1])
+            out.append(flat[a:b].view(I.n_chains, I.rows, I.cols))
+        return out

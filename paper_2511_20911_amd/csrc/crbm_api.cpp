@@ -132,6 +132,16 @@ int build_table(int64_t J1q, int64_t J2q, int64_t hq, double T, int precision, u
     return CRBM_OK;
 }
 
+}  // namespace
+
+double crbmlib::map_schedule_T(int kind, double T0, double T1, const double* Te, int64_t S, int64_t s) {
+    return schedule_T(kind, T0, T1, Te, S, s);
+}
+void crbmlib::map_hidden_weight(int64_t Jq, double T, int64_t* wq, int* sig) { hidden_weight(Jq, T, wq, sig); }
+uint32_t crbmlib::map_threshold(int64_t y) { return threshold(y); }
+
+namespace {
+
 // Default cell rows per lane: the compiled tiling that keeps the most lanes of
 // a wavefront busy (G lanes per chain, floor(64/G) chains), preferring R = 3.
 int default_rows(int L) {

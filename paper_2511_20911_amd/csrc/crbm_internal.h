@@ -72,6 +72,14 @@ struct HandleView {
 // the view of instance i (0 <= i < number of instances)
 int handle_view(crbm_t* h, HandleView* v, int i);
 
+// The host mapping of the conventions (crbm_api.cpp), shared with the
+// general-lattice sampler: schedule temperature of sweep s, hidden weight and
+// coupling sign of a quantised coupling at T, and the 32-bit sigmoid threshold
+// of a field magnitude y (2^-16 units).
+double map_schedule_T(int kind, double T0, double T1, const double* Te, int64_t S, int64_t s);
+void map_hidden_weight(int64_t Jq, double T, int64_t* wq, int* sig);
+uint32_t map_threshold(int64_t y);
+
 // Records the message returned by crbm_last_error() on this thread; returns code.
 int set_error(int code, const char* msg);
 

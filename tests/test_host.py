@@ -86,3 +86,56 @@ def test_bench_refuses_more_than_one_gpu():
                        timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+@pytest.mark.parametrize("Lr,Lc,orr,oc,seed", [(6, 8, True, True, 1), (8, 6, False, True, 2), (6, 6, True, False, 3),
+                                               (4, 4, False, False, 4)])
+def test_lattice_tables_equal_oracle_fields(Lr, Lc, orr, oc, seed):
+    """The general-lattice table (crbm_lattice_table, host only): the hidden
+    threshold of every filter is t(2 wq_k) from the oracle's weights, and for
+    every site the 32 visible entries of its (sublattice, edge) type are the
+    thresholds and signs of aq + sum of +-wq over the site's present bonds in
+    the oracle's geometry, every sign combination once per value of the bits
+    of absent bonds."""
+    rng = np.random.default_rng(seed)
+    J = list(rng.uniform(-2.0, 2.0, 10))
+    J[6] = 0.0
+    he, ho, T = 1.7, -0.9, 0.8
+    lat = crbm.Lattice(rows=Lr, cols=Lc, J=J, h_even=he, h_odd=ho, open_rows=orr, open_cols=oc)
+    tab = crbm.lattice_table(lat, T).astype(np.int64)
+    wq, sg = zip(*[oracle.bond_weight(oracle.quantise(x), T) for x in J])
+    aq = [oracle.visible_bias(oracle.quantise(he), T), oracle.visible_bias(oracle.quantise(ho), T)]
+    for k in range(10):
+        assert tab[k] == (oracle.threshold(2 * wq[k]) if wq[k] else 1 << 31)
+        assert ((int(tab[10]) >> k) & 1) == (sg[k] < 0) and ((int(tab[11]) >> k) & 1) == (wq[k] != 0)
+    ol = oracle.Lattice(Lr, Lc, J, he, ho, open_r=orr, open_c=oc, T0=T)
+    inc = {}
+    for k in range(10):
+        for i in range(Lr // 2):
+            for j in range(Lc // 2):
+                b = oracle.lattice_bond(ol, k, i, j)
+                if b is not None:
+                    inc.setdefault(b[0], []).append(wq[k])
+                    inc.setdefault(b[1], []).append(wq[k])
+    import itertools
+    for r in range(Lr):
+        for c in range(Lc):
+            ws = inc[(r, c)]
+            assert len(ws) <= 5
+            cls = 2 * (r % 2) + (c % 2)
+            redge = orr and (r == 0 if r % 2 == 0 else r == Lr - 1)
+            cedge = oc and (c == 0 if c % 2 == 0 else c == Lc - 1)
+            typ = (cls * 2 + int(redge)) * 2 + int(cedge)
+            want = []
+            for signs in itertools.product((-1, 1), repeat=len(ws)):
+                x = aq[c % 2] + sum(s * w for s, w in zip(signs, ws))
+                want += [(oracle.threshold(abs(x)), int(x >= 0))] * (1 << (5 - len(ws)))
+            got = []
+            for pat in range(32):
+                e = typ * 32 + pat
+                t = int(tab[16 + 512 + e])
+                hi = t >> 16
+                tc = min(0xffff, hi + (1 if t & 0xffff else 0))
+                assert int(tab[16 + e]) == (tc | (hi << 16))
+                got.append((t, (int(tab[16 + 1024 + e // 32]) >> (e % 32)) & 1))
+            assert sorted(got) == sorted(want), (r, c)
