@@ -409,6 +409,100 @@ def precision_leg(crbm, torch, temps=(0.1, 0.25, 0.5), n_h=65, h_max=8.0, chains
     return out
 
 
+def phase_map_leg(crbm, torch, L=18, chains=32, T=0.25, anneal=2000, measure=1000):
+    """Magnetisation map m(J2/J1, h) of Fig. 3a at 18x18 (J2/J1 in [0, 3] by
+    0.1, h/J1 in [-8, 8] by 0.25: 2015 points, 32 chains each, all in one
+    handle; geometric anneal 3 -> T over `anneal` sweeps, then `measure`
+    measured sweeps at T), and its transition lines: the fields where dm/dh
+    peaks (Fig. 3b: the peaks of the first derivative sit at the critical
+    points), each matched to the nearest T = 0 boundary of the four ordered
+    phases (Neel | 1/3 at h = 4 - 2 J2, dimer | 1/3 at h = J2 - 2, 1/3 | FM at
+    h = 4 + J2).  At T > 0 the lower line moves to smaller fields: the
+    plateau's entropy favours it (Clausius-Clapeyron)."""
+    import numpy as np
+    from paper_2511_20911_amd import phase
+    J2s = [round(0.1 * k, 2) for k in range(31)]
+    hs = [-8.0 + 0.25 * k for k in range(65)]
+    m, E, dt, work = phase.phase_map(J2s, hs, L=L, chains=chains, T=T, anneal=anneal, measure=measure)
+    lines = []
+    dev = {"neel_third": [], "dimer_third": [], "third_fm": []}
+    for a, J2 in enumerate(J2s):
+        found = [h for h in phase.transition_fields(hs, m[a]) if h > 0]
+        exact = phase.boundaries_T0(J2)
+        for x in exact:
+            if not found:
+                continue
+            f = min(found, key=lambda v: abs(v - x))
+            kind = "third_fm" if abs(x - (4 + J2)) < 1e-6 else ("neel_third" if J2 < 2 else "dimer_third")
+            dev[kind].append(f - x)
+        lines.append({"J2": J2, "h_transitions": [round(f, 3) for f in found],
+                      "h_exact_T0": [round(x, 3) for x in exact]})
+    summary = {k: {"mean_shift": float(np.mean(v)) if v else None, "max_abs_shift": float(np.max(np.abs(v))) if v else None,
+                   "lines": len(v)} for k, v in dev.items()}
+    return {"workload": f"SS Ising {L}x{L} periodic, J2/J1 in [0, 3] (31), h/J1 in [-8, 8] (65), {chains} chains per "
+                        f"point in one handle, geometric anneal 3 -> {T} over {anneal} sweeps + {measure} measured "
+                        "sweeps",
+            "seconds": dt, "spin_updates_per_s": work / dt, "shift_from_T0_boundaries": summary, "lines": lines,
+            "m": np.round(m, 4).tolist(), "J2": J2s, "h": hs}
+
+
+def confined_leg(crbm, torch):
+    """Laterally confined SS lattice of width 12 (12 columns open, 18 rows
+    periodic; Sec. III.A-B, Fig. 3f, Fig. 4b,d) at J2/J1 = 1.5 across the
+    confined transition at h = 3.5, against the periodic 18x18 lattice at the
+    same points: <E>/N, <m> and the structure factor S(q)/N^2 (maximum,
+    where, at (2pi/3, pi), (pi, 2pi/3) and Gamma, and two cuts)."""
+    from paper_2511_20911_amd import phase
+    hs = [2.5, 3.0, 3.5, 4.0, 4.5, 5.0]
+    strip = phase.confined_scan(hs, width=12, length=18, J2=1.5, T=0.2)
+    per = phase.confined_scan(hs, width=18, length=18, J2=1.5, T=0.2, open_cols=False, id0=6100)
+    return {"workload": "SS Ising, J2/J1 = 1.5, h in {2.5 .. 5.0}; 12 x 18 strip (12 columns open, 18 rows periodic) "
+                        "and 18 x 18 periodic; 512 chains per point, geometric anneal 5 -> 0.2 over 4000 sweeps, "
+                        "2000 sweeps at 0.2, counts and displacement correlation every 4th sweep",
+            "strip": strip, "periodic": per}
+
+
+def raw_filter_leg(crbm, torch, sweeps=500, n_inst=64):
+    """The general-lattice kernel (one coupling per filter, App. A
+    Convoluter-Reverse; open axes) at 18x18: 64 instances x 4096 chains with
+    ten random couplings each, periodic; the same with both axes open; the
+    12 x 18 confined strip; and the square-lattice kernel on the SS couplings
+    of the same size, all timed with HIP events over `sweeps` sweeps."""
+    import numpy as np
+    rng = np.random.default_rng(41)
+    out = {}
+
+    def timed(smp, work):
+        smp.sample(20)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        smp.sample(sweeps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        return {"ms": ms, "spin_updates_per_s": work / (ms / 1e3)}
+
+    for name, orr, oc, rows, cols in (("raw18_periodic", False, False, 18, 18), ("raw18_open", True, True, 18, 18),
+                                      ("strip12x18", False, True, 18, 12)):
+        lats = [crbm.Lattice(rows=rows, cols=cols, J=list(rng.uniform(-1.5, 1.5, 10)), h_even=float(rng.uniform(0, 3)),
+                             h_odd=float(rng.uniform(0, 3)), open_rows=orr, open_cols=oc, n_chains=4096,
+                             sched="const", T0=float(rng.uniform(0.3, 2.0)), id=7000 + k) for k in range(n_inst)]
+        smp = crbm.LatticeSampler(lats, seed=SEED + 9, n_sweeps=sweeps + 20)
+        out[name] = timed(smp, n_inst * 4096 * rows * cols * sweeps)
+        del smp
+    insts = [crbm.Instance(L=18, J1=1.0, J2=float(rng.uniform(0.5, 2)), h=float(rng.uniform(0, 3)), n_chains=4096,
+                           sched="const", T0=float(rng.uniform(0.3, 2.0)), id=7100 + k) for k in range(n_inst)]
+    smp = crbm.Sampler(insts, seed=SEED + 9, n_sweeps=sweeps + 20)
+    out["square18_ss"] = timed(smp, n_inst * 4096 * 324 * sweeps)
+    del smp
+    out["workload"] = (f"{n_inst} instances x 4096 chains, constant T, {sweeps} sweeps: general-lattice kernel with ten "
+                       "random filter couplings and random even/odd fields (18x18 periodic, 18x18 open, 12-wide strip), "
+                       "and the square-lattice kernel on SS couplings (18x18)")
+    return out
+
+
 def _r(x, n=4):
     """Round to n significant digits for the compact result line."""
     if x is None:
@@ -446,6 +540,18 @@ def summarise(legs):
     t = legs.get("tts")
     if t:
         out["tts_sweeps"] = {f'{p["phase"]}@{p["L"]}': _r(p["tts99_sweeps"], 3) for p in t["points"]}
+    pm = legs.get("phase_map")
+    if pm:
+        out["phase_map"] = {"spin_updates_per_s": _r(pm["spin_updates_per_s"], 3),
+                            "mean_shift_from_T0": {k: _r(v["mean_shift"], 3)
+                                                   for k, v in pm["shift_from_T0_boundaries"].items()}}
+    cf = legs.get("confined")
+    if cf:
+        out["confined_S_peak_off_gamma"] = {k: [_r(p["S_max_off_gamma"], 3) for p in cf[k]["points"]]
+                                            for k in ("strip", "periodic")}
+    rf = legs.get("raw_filters")
+    if rf:
+        out["lattice_kernel"] = {k: _r(v["spin_updates_per_s"], 3) for k, v in rf.items() if isinstance(v, dict)}
     p = legs.get("precision")
     if p:
         out["precision_third_to_fm_h_mid"] = {
@@ -475,7 +581,12 @@ def main():
     ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution runs at the four phase points")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the m(h) comparison of the default and the hardware precision")
+    ap.add_argument("--no-lattice", action="store_true",
+                    help="skip the phase map, the confined-lattice S(q) scan and the general-lattice kernel timing")
     ap.add_argument("--headline-only", action="store_true", help="skip every leg but the headline")
+    ap.add_argument("--legs", type=str, default="",
+                    help="comma-separated legs to run after the headline (batched_uneven, scale, tts, precision, "
+                         "phase_map, confined, raw_filters, learned_mh, learned_mh_points); default: all")
     ap.add_argument("--detail-out", type=str, default=os.path.join("gpurun_out", "bench_detail.json"),
                     help="file for the full per-leg tables ('' = none)")
     args = ap.parse_args()
@@ -485,6 +596,7 @@ def main():
         sys.exit(2)
     if args.headline_only:
         args.no_batched = args.no_mh = args.no_scale = args.no_c5_mh = args.no_tts = args.no_precision = True
+        args.no_lattice = True
     n_sweeps = min(args.sweeps, S)
 
     # the CPU baseline runs first, in forked host processes, before the GPU is touched
@@ -619,17 +731,25 @@ def main():
         t = time.perf_counter()
         legs[name] = fn()
         print(f"# leg {name}: {time.perf_counter() - t:.1f} s", flush=True)
-    if not args.no_batched:
+    only = set(x for x in args.legs.split(",") if x)
+    want = lambda name, off: (name in only) if only else not off  # noqa: E731
+    if want("batched_uneven", args.no_batched):
         leg("batched_uneven", lambda: batched_uneven(crbm, torch))
-    if not args.no_scale:
+    if want("scale", args.no_scale):
         leg("scale", lambda: scale_gibbs(crbm, torch))
-    if not args.no_tts:
+    if want("tts", args.no_tts):
         leg("tts", lambda: tts_leg(crbm, torch))
-    if not args.no_precision:
+    if want("precision", args.no_precision):
         leg("precision", lambda: precision_leg(crbm, torch))
-    if not args.no_mh:
+    if want("phase_map", args.no_lattice):
+        leg("phase_map", lambda: phase_map_leg(crbm, torch))
+    if want("confined", args.no_lattice):
+        leg("confined", lambda: confined_leg(crbm, torch))
+    if want("raw_filters", args.no_lattice):
+        leg("raw_filters", lambda: raw_filter_leg(crbm, torch))
+    if want("learned_mh", args.no_mh):
         leg("learned_mh", lambda: learned_mh(crbm, torch))
-    if not args.no_c5_mh:
+    if want("learned_mh_points", args.no_c5_mh):
         def c5():
             r = {"48": learned_points(crbm, torch, 48)}
             if args.c5_mh_96:
