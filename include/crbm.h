@@ -418,6 +418,14 @@ void crbm_destroy(crbm_t* h);
 /* Message of the last error on this thread ("" if none). */
 const char* crbm_last_error(void);
 
+/* Failure injection for tests of the error paths (process-wide, not
+ * thread-safe against concurrent creates): with n >= 0, the library's n-th
+ * device allocation from now on (0 = the next) fails as if the device were out
+ * of memory, once; n < 0 disarms it.  Every entry point that allocates must
+ * then return CRBM_ENOMEM with a message, free what it had taken, and work
+ * normally on the next call.  Returns CRBM_OK. */
+int crbm_debug_fail_alloc(int32_t n);
+
 /* Host-side helpers that expose the library's own tables (used by tests to
  * check them against the oracle).
  * crbm_threshold: the 32-bit sigmoid threshold t(y) for an integer field

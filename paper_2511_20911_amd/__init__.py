@@ -160,6 +160,7 @@ def lib() -> ct.CDLL:
                                    p(ct.c_double), p(ct.c_int32), p(ct.c_double)]
         L.crbm_tau_int_noalloc.argtypes = L.crbm_tau_int.argtypes
         L.crbm_get_tiling.argtypes = [ct.c_int32, p(ct.c_int32), p(ct.c_int32)]
+        L.crbm_debug_fail_alloc.argtypes = [ct.c_int32]
         L.crbm_lattice_create.argtypes = [p(_Lattice), ct.c_int32, p(_Config), p(ct.c_void_p)]
         L.crbm_lattice_sample.argtypes = [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_int32]
         L.crbm_lattice_observables.argtypes = [ct.c_void_p, p(ct.c_int64), ct.c_void_p]
@@ -533,6 +534,12 @@ def sample_mh(sampler: Sampler, net: ARNet, n_cycles: int, gibbs_per_mh: int, tr
 
 
 # ------------------------------------------------------------- general lattices
+
+def debug_fail_alloc(n: int):
+    """Make the library's n-th device allocation from now on fail (n < 0: disarm);
+    for tests of the error paths."""
+    _check(lib().crbm_debug_fail_alloc(int(n)))
+
 
 def ss_filters(J1: float, J2: float):
     """Per-filter couplings of the Shastry-Sutherland lattice: filters k0-k7

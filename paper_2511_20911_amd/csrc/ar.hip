@@ -1416,7 +1416,7 @@ int fail_ar(int code, const char* msg) { return set_error(code, msg); }
 
 template <class T>
 hipError_t alloc(T** p, int64_t n) {
-    return hipMalloc((void**)p, sizeof(T) * (size_t)(n > 0 ? n : 1));
+    return dev_alloc(p, sizeof(T) * (size_t)(n > 0 ? n : 1));
 }
 
 // weight-gradient chunks of a batch of P pixels
@@ -1432,8 +1432,19 @@ int ensure_train(crbm_ar_t* a, int64_t B) {
                   a->spins_copy, a->part2, a->gs};
     for (void* p : ps)
         if (p) (void)hipFree(p);
+    // every pointer is cleared: an allocation that fails part-way leaves the
+    // rest null, so neither a later call nor the destructor frees them twice
+    a->hs = nullptr;
+    a->mask = nullptr;
+    a->logit = a->g32 = nullptr;
+    a->dh0 = a->dh1 = nullptr;
+    a->dz = a->g = nullptr;
+    a->logq = nullptr;
+    a->part = a->bpart = nullptr;
+    a->spins_copy = nullptr;
     a->part2 = nullptr;
     a->gs = nullptr;
+    a->tcap = 0;
     const int64_t P = B * a->L * a->L;
     const int64_t nch = wgrad_chunks(P);
     if (alloc(&a->hs, (int64_t)NL * P * C) || alloc(&a->mask, (int64_t)(NL - 1) * P) || alloc(&a->logit, P) ||
@@ -1737,8 +1748,8 @@ int crbm_ar_set_points(crbm_ar_t* a, int32_t n_points, const double* feats_host)
 int crbm_ar_set_params(crbm_ar_t* a, const float* host, int64_t n) {
     if (!a || !host || n != a->np) return fail_ar(CRBM_EINVAL, "parameter count mismatch");
     AR_TRY(hipMemcpyAsync(a->theta, host, sizeof(float) * n, hipMemcpyHostToDevice, a->stream), "copy params");
-    (void)hipMemsetAsync(a->m, 0, sizeof(float) * a->np, a->stream);
-    (void)hipMemsetAsync(a->v, 0, sizeof(float) * a->np, a->stream);
+    AR_TRY(hipMemsetAsync(a->m, 0, sizeof(float) * a->np, a->stream), "clear Adam moments");
+    AR_TRY(hipMemsetAsync(a->v, 0, sizeof(float) * a->np, a->stream), "clear Adam moments");
     a->t_adam = 0;
     int rc = pack(a);
     if (rc != CRBM_OK) return rc;
@@ -1960,7 +1971,12 @@ int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_
         void* ps[] = {a->cur, a->ccur, a->cprop, a->lqc, a->nacc, a->mh_ci};
         for (void* p : ps)
             if (p) (void)hipFree(p);
+        a->cur = nullptr;
+        a->ccur = a->cprop = nullptr;
+        a->lqc = nullptr;
+        a->nacc = nullptr;
         a->mh_ci = nullptr;
+        a->mcap = 0;
         if (alloc(&a->cur, n * N) || alloc(&a->ccur, n * 3) || alloc(&a->cprop, n * 3) || alloc(&a->lqc, n) ||
             alloc(&a->nacc, 1) || alloc(&a->mh_ci, n)) {
             a->mcap = 0;

@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -22,6 +23,30 @@ using namespace crbmlib;
 
 namespace {
 thread_local std::string g_err;
+}
+
+namespace {
+// allocations to let through before the armed failure; -1 = not armed
+std::atomic<int64_t> g_alloc_countdown{-1};
+}
+
+hipError_t crbmlib::dev_alloc_bytes(void** p, size_t bytes) {
+    int64_t c = g_alloc_countdown.load();
+    while (c >= 0) {
+        if (g_alloc_countdown.compare_exchange_weak(c, c - 1)) {
+            if (c == 0) {
+                *p = nullptr;
+                return hipErrorOutOfMemory;
+            }
+            break;
+        }
+    }
+    return hipMalloc(p, bytes);
+}
+
+extern "C" int crbm_debug_fail_alloc(int32_t n) {
+    g_alloc_countdown.store(n < 0 ? -1 : (int64_t)n);
+    return CRBM_OK;
 }
 
 int crbmlib::set_error(int code, const char* msg) {
@@ -446,14 +471,14 @@ int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cf
 
     // device state
     hipError_t e;
-    if ((e = hipMalloc(&h->d_state, sizeof(uint32_t) * (size_t)h->total_words)) != hipSuccess ||
-        (e = hipMalloc(&h->d_tables, sizeof(uint32_t) * h->h_tables.size())) != hipSuccess ||
-        (e = hipMalloc(&h->d_acc, sizeof(int64_t) * CRBM_N_ACC * (size_t)h->total_chains)) != hipSuccess) {
+    if ((e = dev_alloc(&h->d_state, sizeof(uint32_t) * (size_t)h->total_words)) != hipSuccess ||
+        (e = dev_alloc(&h->d_tables, sizeof(uint32_t) * h->h_tables.size())) != hipSuccess ||
+        (e = dev_alloc(&h->d_acc, sizeof(int64_t) * CRBM_N_ACC * (size_t)h->total_chains)) != hipSuccess) {
         delete h;
         return fail(e == hipErrorOutOfMemory ? CRBM_ENOMEM : CRBM_EHIP, std::string("hipMalloc: ") + hipGetErrorString(e));
     }
     for (auto& g : h->groups) {
-        if ((e = hipMalloc(&g.d_items, sizeof(Item) * g.items.size())) != hipSuccess) {
+        if ((e = dev_alloc(&g.d_items, sizeof(Item) * g.items.size())) != hipSuccess) {
             delete h;
             return fail(CRBM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
         }
@@ -464,19 +489,22 @@ int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cf
             h->corr_off.push_back(tot);
             tot += (int64_t)h->inst[i].L * h->inst[i].L;
         }
-        if ((e = hipMalloc(&h->d_corr, sizeof(unsigned long long) * (size_t)tot)) != hipSuccess) {
+        if ((e = dev_alloc(&h->d_corr, sizeof(unsigned long long) * (size_t)tot)) != hipSuccess) {
             delete h;
             return fail(CRBM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
         }
     }
     if (cfg->launch_mode == CRBM_LAUNCH_GRAPH) {
-        if ((e = hipMalloc(&h->d_queue, sizeof(uint32_t) * h->groups.size())) != hipSuccess) {
+        if ((e = dev_alloc(&h->d_queue, sizeof(uint32_t) * h->groups.size())) != hipSuccess) {
             delete h;
             return fail(CRBM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
         }
         int dev = 0, cus = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if ((e = hipGetDevice(&dev)) != hipSuccess ||
+            (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) {
+            delete h;
+            return fail(CRBM_EHIP, std::string("device query: ") + hipGetErrorString(e));
+        }
         for (auto& g : h->groups) {
             int per_cu = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gibbs_kernel_fn(g.L, g.R), 64 * g.wpb, 0) !=
@@ -635,12 +663,12 @@ int crbm_autotune(int32_t L, int32_t n_chains, int32_t n_sweeps, void* stream, i
                 return rc;
             }
             rc = crbm_sample(t, 2, nullptr, nullptr);  // warm-up
-            (void)hipEventRecord(e0, st);
+            if (rc == CRBM_OK && hipEventRecord(e0, st) != hipSuccess) rc = fail(CRBM_EHIP, "autotune: event record");
             if (rc == CRBM_OK) rc = crbm_sample(t, n_sweeps, nullptr, nullptr);
-            (void)hipEventRecord(e1, st);
-            (void)hipEventSynchronize(e1);
             float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rc == CRBM_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = fail(CRBM_EHIP, "autotune: event timing");
             crbm_destroy(t);
             if (rc != CRBM_OK) {
                 (void)hipEventDestroy(e0);
@@ -715,7 +743,8 @@ int crbm_observables(crbm_t* h, crbm_obs* out, int64_t* corr_out) {
         int64_t tot = 0;
         for (int i = 0; i < n; ++i) tot += (int64_t)h->inst[i].L * h->inst[i].L;
         unsigned long long* d = nullptr;
-        HIP_TRY(hipMalloc(&d, sizeof(unsigned long long) * (size_t)tot), "hipMalloc corr");
+        if (dev_alloc(&d, sizeof(unsigned long long) * (size_t)tot) != hipSuccess)
+            return fail(CRBM_ENOMEM, "hipMalloc corr");
         int rc = CRBM_OK;
         int64_t off = 0;
         hipError_t e = hipMemsetAsync(d, 0, sizeof(unsigned long long) * (size_t)tot, h->stream);

@@ -80,6 +80,15 @@ double map_schedule_T(int kind, double T0, double T1, const double* Te, int64_t 
 void map_hidden_weight(int64_t Jq, double T, int64_t* wq, int* sig);
 uint32_t map_threshold(int64_t y);
 
+// Every device allocation of the library goes through dev_alloc, which fails
+// with hipErrorOutOfMemory when crbm_debug_fail_alloc has armed it (tests of
+// the error paths), and otherwise calls hipMalloc.
+hipError_t dev_alloc_bytes(void** p, size_t bytes);
+template <class T>
+inline hipError_t dev_alloc(T** p, size_t bytes) {
+    return dev_alloc_bytes(reinterpret_cast<void**>(p), bytes);
+}
+
 // Records the message returned by crbm_last_error() on this thread; returns code.
 int set_error(int code, const char* msg);
 

@@ -672,6 +672,14 @@ int lfail(int code, const std::string& msg) { return set_error(code, msg.c_str()
         if (e_ != hipSuccess) return lfail(CRBM_EHIP, std::string(what) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+#define LAT_ALLOC(expr, what)                                                                 \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return lfail(e_ == hipErrorOutOfMemory ? CRBM_ENOMEM : CRBM_EHIP,                 \
+                         std::string(what) + ": " + hipGetErrorString(e_));                   \
+    } while (0)
+
 LatArgs lat_args(const crbm_lat_s* h, int x, int64_t s0, int64_t s1, int8_t* spins_out, int32_t* trace,
                  int32_t trace_every) {
     LatArgs a{};
@@ -785,19 +793,19 @@ int crbm_lattice_create(const crbm_lattice* insts, int32_t n_inst, const crbm_co
         h->Texp.push_back(std::move(te));
     }
     h->total_chains = chains;
-    LAT_HIP(hipMalloc(&h->d_state, sizeof(uint32_t) * (size_t)words), "hipMalloc state");
-    LAT_HIP(hipMalloc(&h->d_tables, sizeof(uint32_t) * tables.size()), "hipMalloc tables");
-    LAT_HIP(hipMalloc(&h->d_acc, sizeof(int64_t) * (size_t)chains * CRBM_LAT_N_ACC), "hipMalloc accumulators");
+    LAT_ALLOC(dev_alloc(&h->d_state, sizeof(uint32_t) * (size_t)words), "hipMalloc state");
+    LAT_ALLOC(dev_alloc(&h->d_tables, sizeof(uint32_t) * tables.size()), "hipMalloc tables");
+    LAT_ALLOC(dev_alloc(&h->d_acc, sizeof(int64_t) * (size_t)chains * CRBM_LAT_N_ACC), "hipMalloc accumulators");
     LAT_HIP(hipMemcpyAsync(h->d_tables, tables.data(), sizeof(uint32_t) * tables.size(), hipMemcpyHostToDevice,
                            h->stream), "copy tables");
     LAT_HIP(hipMemsetAsync(h->d_acc, 0, sizeof(int64_t) * (size_t)chains * CRBM_LAT_N_ACC, h->stream), "clear accumulators");
     if (h->corr_words > 0) {
-        LAT_HIP(hipMalloc(&h->d_corr, sizeof(unsigned long long) * (size_t)h->corr_words), "hipMalloc corr");
+        LAT_ALLOC(dev_alloc(&h->d_corr, sizeof(unsigned long long) * (size_t)h->corr_words), "hipMalloc corr");
         LAT_HIP(hipMemsetAsync(h->d_corr, 0, sizeof(unsigned long long) * (size_t)h->corr_words, h->stream), "clear corr");
     }
     for (int x = 0; x < 2; ++x) {
         if (h->items[x].empty()) continue;
-        LAT_HIP(hipMalloc(&h->d_items[x], sizeof(LatItem) * h->items[x].size()), "hipMalloc items");
+        LAT_ALLOC(dev_alloc(&h->d_items[x], sizeof(LatItem) * h->items[x].size()), "hipMalloc items");
         LAT_HIP(hipMemcpyAsync(h->d_items[x], h->items[x].data(), sizeof(LatItem) * h->items[x].size(),
                                hipMemcpyHostToDevice, h->stream), "copy items");
         hipLaunchKernelGGL(lat_init_kernel, dim3((unsigned)h->items[x].size()), dim3(256), 0, h->stream, h->d_state,

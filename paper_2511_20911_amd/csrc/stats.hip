@@ -182,12 +182,12 @@ extern "C" int crbm_tau_int(const int32_t* trace_dev, int64_t n_samples, int64_t
     const int K = (int)std::min<int64_t>(max_lag, m - 1);
     double *d_mean = nullptr, *d_x = nullptr, *d_part = nullptr;
     const int nblk = (int)((nc + 255) / 256);
-    if (hipMalloc(&d_mean, sizeof(double) * (nc + 1)) != hipSuccess) return set_error(CRBM_ENOMEM, "hipMalloc");
-    if (hipMalloc(&d_x, sizeof(double) * m * nc) != hipSuccess) {
+    if (dev_alloc(&d_mean, sizeof(double) * (nc + 1)) != hipSuccess) return set_error(CRBM_ENOMEM, "hipMalloc");
+    if (dev_alloc(&d_x, sizeof(double) * m * nc) != hipSuccess) {
         (void)hipFree(d_mean);
         return set_error(CRBM_ENOMEM, "hipMalloc");
     }
-    if (hipMalloc(&d_part, sizeof(double) * (int64_t)(K + 1) * nblk) != hipSuccess) {
+    if (dev_alloc(&d_part, sizeof(double) * (int64_t)(K + 1) * nblk) != hipSuccess) {
         (void)hipFree(d_mean);
         (void)hipFree(d_x);
         return set_error(CRBM_ENOMEM, "hipMalloc");
