@@ -321,6 +321,144 @@ __global__ void __launch_bounds__(256) conv32_kernel(const __bf16* __restrict__ 
     }
 }
 
+// Fused training forward for L <= kFwdMaxL: one workgroup of four wavefronts
+// per configuration runs all 12 layers with the layer input and output in
+// LDS, and writes what the backward reads (every layer's input h_l in the
+// pixel-major layout [NL][P][C], the ReLU masks, the logits).  Per 32-pixel
+// tile it runs exactly the arithmetic of conv32_kernel: the same
+// 32x32x16 instructions with the same operands in the same order, the
+// accumulators from zero, the bias added in the same epilogue, so its
+// activations, masks and logits equal the layered path's bit for bit; only
+// the operands come from LDS instead of the caches.  The LDS grid carries a
+// zero border (one row above, one column on each side) so that every tap
+// reads a valid address and out-of-lattice taps read zeros, as the layered
+// path's edge tests give; a pixel's four 16-byte channel chunks are XOR
+// swizzled by (pixel / 4) mod 4, so eight lanes reading one chunk of eight
+// consecutive pixels hit distinct banks.
+constexpr int kFwdMaxL = 30;
+__host__ __device__ constexpr int fwd_pixels(int L) { return (L + 1) * (L + 2); }
+__host__ __device__ constexpr int fwd_lds_bytes(int L) {
+    return 2 * fwd_pixels(L) * C * 2 + 4 * 32 * kOutRow * 4;
+}
+
+__device__ __forceinline__ int fwd_off(int pix, int chunk) {  // bf16 offset of a 16-byte chunk
+    return pix * C + ((chunk ^ ((pix >> 2) & 3)) << 3);
+}
+
+__global__ void __launch_bounds__(256) train_fwd_kernel(int64_t B, int L, const int8_t* __restrict__ spins,
+                                                        const __bf16* __restrict__ wf,
+                                                        const float* __restrict__ bias_tab,
+                                                        const int32_t* __restrict__ pt, int npts,
+                                                        __bf16* __restrict__ hs, uint32_t* __restrict__ mask,
+                                                        float* __restrict__ logit) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = L * L, W2 = L + 2, PP = fwd_pixels(L);
+    __bf16* bufs = reinterpret_cast<__bf16*>(smem);                       // [2][PP][C]
+    float* T = reinterpret_cast<float*>(smem + (size_t)2 * PP * C * 2) + (threadIdx.x >> 6) * 32 * kOutRow;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int li = lane & 31, half = lane >> 5;
+    const int64_t b = blockIdx.x;
+    if (b >= B) return;  // uniform per workgroup
+    const int64_t P = B * N, LSZ = P * C;
+    const int8_t* sp = spins + b * N;
+    const float* brow = bias_tab + (pt ? (int64_t)clamp_point(pt[b], npts) * kCondOut : 0);  // [NL][C]
+    for (int g = tid; g < 2 * PP * (C / 8); g += blockDim.x)
+        *reinterpret_cast<bf16x8*>(bufs + (int64_t)g * 8) = zero8();
+    __syncthreads();
+    // h_0: the spin in channel 0 (the embedding of the layered path), in LDS and in HBM
+    for (int g = tid; g < N * (C / 8); g += blockDim.x) {
+        const int p = g >> 2, ch = g & 3;
+        bf16x8 v = zero8();
+        if (ch == 0) v[0] = f2bf((float)sp[p]);
+        *reinterpret_cast<bf16x8*>(hs + (b * N + p) * C + ch * 8) = v;
+        const int r = p / L, c = p - r * L;
+        if (ch == 0) *reinterpret_cast<bf16x8*>(bufs + fwd_off((r + 1) * W2 + c + 1, 0)) = v;
+    }
+    __syncthreads();
+    const int ntiles = (N + 31) / 32;
+    int in_b = 0;
+    for (int l = 0; l < NL; ++l) {
+        const int nt = (l == 0) ? 4 : 5;
+        const int mode = (l == NL - 1) ? EP_LOGIT : (l == 0 ? EP_RELU : EP_RESID);
+        const __bf16* Wop = wf + (int64_t)l * NT * C * C;
+        bf16x8 Bf[NT][2];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int kh = 0; kh < 2; ++kh)
+                Bf[t][kh] = (t < nt) ? load8(Wop + ((int64_t)t * C + li) * C + kh * 16 + half * 8) : zero8();
+        const float* br = brow + l * C;
+        const __bf16* bin = bufs + (size_t)in_b * PP * C;
+        __bf16* bout = bufs + (size_t)(1 - in_b) * PP * C;
+        const int toff[NT] = {-W2 - 1, -W2, -W2 + 1, -1, 0};
+        for (int tile = w; tile < ntiles; tile += 4) {
+            const int pp = tile * 32 + li;
+            bf16x8 A[NT][2];
+            if (pp < N) {
+                const int r = pp / L, c = pp - r * L, pidx = (r + 1) * W2 + c + 1;
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int kh = 0; kh < 2; ++kh)
+                        A[t][kh] = (t < nt) ? *reinterpret_cast<const bf16x8*>(bin + fwd_off(pidx + toff[t], 2 * kh + half))
+                                            : zero8();
+            } else {
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int kh = 0; kh < 2; ++kh) A[t][kh] = zero8();
+            }
+            f32x16 acc;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                if (t >= nt) break;
+#pragma unroll
+                for (int kh = 0; kh < 2; ++kh) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[t][kh], Bf[t][kh], acc, 0, 0, 0);
+            }
+            if (mode == EP_LOGIT) {
+                if (li == 0)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const int i = 8 * (v >> 2) + 4 * half + (v & 3);
+                        const int p = tile * 32 + i;
+                        if (p < N) logit[b * N + p] = acc[v] + br[0];
+                    }
+                continue;
+            }
+#pragma unroll
+            for (int v = 0; v < 16; ++v) T[(8 * (v >> 2) + 4 * half + (v & 3)) * kOutRow + li] = acc[v];
+            wave_sync();
+            const int pi = tile * 32 + (lane >> 1), c0 = (lane & 1) * 16;
+            if (pi < N) {
+                const int r = pi / L, c = pi - r * L, pidx = (r + 1) * W2 + c + 1;
+                uint32_t mbits = 0u;
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh) {
+                    const int cb = c0 + 8 * hh;
+                    const bf16x8 rr = mode == EP_RESID ? *reinterpret_cast<const bf16x8*>(bin + fwd_off(pidx, cb >> 3))
+                                                       : zero8();
+                    bf16x8 ob;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const float z = T[(lane >> 1) * kOutRow + cb + e] + br[cb + e];
+                        const float y = z > 0.f ? z : 0.f;
+                        ob[e] = f2bf(mode == EP_RESID ? bf2f(rr[e]) + y : y);
+                        mbits |= (uint32_t)(z > 0.f) << (8 * hh + e);
+                    }
+                    *reinterpret_cast<bf16x8*>(bout + fwd_off(pidx, cb >> 3)) = ob;
+                    *reinterpret_cast<bf16x8*>(hs + (int64_t)(l + 1) * LSZ + (b * N + pi) * C + cb) = ob;
+                }
+                reinterpret_cast<uint16_t*>(mask + (int64_t)l * P)[2 * (b * N + pi) + (lane & 1)] = (uint16_t)mbits;
+            }
+            wave_sync();  // the rows are rewritten by the next tile
+        }
+        __syncthreads();  // the layer's output is complete before it is read as input
+        in_b = 1 - in_b;
+    }
+}
+
 // Partial weight gradients, one chunk of kWChunk pixels each, all taps at once
 // (they share the gradient operand):
 //   part[chunk][t][i][j] = sum_{p in chunk} in[p + tap_t][i] dz[p][j]
@@ -1252,25 +1390,40 @@ struct MhTarget {
 };
 
 // chain ch belongs to instance ci[ch] with target tg[ci[ch]]
-__global__ void mh_kernel(int64_t n, int L, int8_t* cur, const int8_t* prop, int32_t* cnt_cur,
-                          const int32_t* cnt_prop, double* lq_cur, const double* lq_prop, const MhTarget* tg,
-                          const int32_t* ci, uint64_t seed, uint32_t step, uint32_t id, unsigned long long* n_acc) {
-    const int64_t ch = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per chain: lane 0 takes the accept decision on the exact
+// integer log pi_q (R16) and the two log q; on acceptance the wavefront copies
+// the proposal (L^2 bytes, a multiple of 4) as 32-bit words, strided over its
+// lanes, with the counts and log q.
+__global__ void __launch_bounds__(256) mh_kernel(int64_t n, int L, int8_t* cur, const int8_t* prop,
+                                                 int32_t* cnt_cur, const int32_t* cnt_prop, double* lq_cur,
+                                                 const double* lq_prop, const MhTarget* tg, const int32_t* ci,
+                                                 uint64_t seed, uint32_t step, uint32_t id,
+                                                 unsigned long long* n_acc) {
+    const int64_t ch = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (ch >= n) return;
     const int64_t N = (int64_t)L * L;
-    const MhTarget t = tg[ci[ch]];
-    auto logpi = [&](const int32_t* k) {
-        const int64_t M = k[0], B1 = k[1], B2 = k[2];
-        const int64_t n1 = t.sg1 < 0 ? (2 * N - B1) / 2 : (2 * N + B1) / 2;
-        const int64_t n2 = t.sg2 < 0 ? (N / 2 - B2) / 2 : (N / 2 + B2) / 2;
-        return t.a * (double)M + t.c1 * (double)n1 + t.c2 * (double)n2;
-    };
-    const double la = (logpi(cnt_prop + ch * 3) - logpi(cnt_cur + ch * 3)) + (lq_cur[ch] - lq_prop[ch]);
-    const gk::P4 r = gk::philox(0u, step, (uint32_t)ch, (id << 3) | 5u, (uint32_t)seed, (uint32_t)(seed >> 32));
-    const double u = ((double)(((uint64_t)r.v[0] << 21) ^ (r.v[1] >> 11)) + 0.5) * (1.0 / 9007199254740992.0);
-    if (log(u) < la) {
-        for (int64_t i = 0; i < N; ++i) cur[ch * N + i] = prop[ch * N + i];
-        for (int k = 0; k < 3; ++k) cnt_cur[ch * 3 + k] = cnt_prop[ch * 3 + k];
+    int acc = 0;
+    if (lane == 0) {
+        const MhTarget t = tg[ci[ch]];
+        auto logpi = [&](const int32_t* k) {
+            const int64_t M = k[0], B1 = k[1], B2 = k[2];
+            const int64_t n1 = t.sg1 < 0 ? (2 * N - B1) / 2 : (2 * N + B1) / 2;
+            const int64_t n2 = t.sg2 < 0 ? (N / 2 - B2) / 2 : (N / 2 + B2) / 2;
+            return t.a * (double)M + t.c1 * (double)n1 + t.c2 * (double)n2;
+        };
+        const double la = (logpi(cnt_prop + ch * 3) - logpi(cnt_cur + ch * 3)) + (lq_cur[ch] - lq_prop[ch]);
+        const gk::P4 r = gk::philox(0u, step, (uint32_t)ch, (id << 3) | 5u, (uint32_t)seed, (uint32_t)(seed >> 32));
+        const double u = ((double)(((uint64_t)r.v[0] << 21) ^ (r.v[1] >> 11)) + 0.5) * (1.0 / 9007199254740992.0);
+        acc = log(u) < la ? 1 : 0;
+    }
+    acc = __shfl(acc, 0);
+    if (!acc) return;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(prop + ch * N);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(cur + ch * N);
+    for (int64_t w = lane; w < N / 4; w += 64) dst[w] = src[w];
+    if (lane < 3) cnt_cur[ch * 3 + lane] = cnt_prop[ch * 3 + lane];
+    if (lane == 0) {
         lq_cur[ch] = lq_prop[ch];
         atomicAdd(n_acc, 1ull);
     }
@@ -1516,6 +1669,15 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
     const int64_t P = B * L * L;
     const size_t LSZ = (size_t)P * C;
     hipStream_t st = a->stream;
+    if (L <= kFwdMaxL) {
+        // the whole forward per configuration in LDS, bit for bit the layered path's
+        const int lds = fwd_lds_bytes(L);
+        AR_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&train_fwd_kernel),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds),
+               "training forward LDS size");
+        hipLaunchKernelGGL(train_fwd_kernel, dim3((unsigned)B), dim3(256), lds, st, B, L, spins, a->wf, bs.tab, bs.pt,
+                           bs.npts, a->hs, a->mask, a->logit);
+    } else {
     hipLaunchKernelGGL(embed_kernel, dim3((unsigned)((P * (C / 8) + 255) / 256)), dim3(256), 0, st, spins, P, a->hs);
     for (int l = 0; l < NL; ++l) {
         const Taps tp = taps_for(l, false);
@@ -1527,6 +1689,7 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
                            bs.tab + l * C, bs.pt, bs.npts, tp, L, P, mode, a->hs + (size_t)l * LSZ,
                            (const float*)nullptr, out, mk, a->logit, (const uint32_t*)nullptr, (__bf16*)nullptr,
                            (float*)nullptr);
+    }
     }
     hipLaunchKernelGGL(loss_kernel, dim3((unsigned)B), dim3(256), 0, st, a->logit, spins, L, 1.0f / (float)B, a->logq,
                        a->g, a->g32);
@@ -2009,7 +2172,6 @@ int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_
     }
     const int32_t* pts = a->cond > 0 ? a->mh_ci : nullptr;  // chain i of instance k is conditioned on point k
     AR_TRY(hipMemsetAsync(a->nacc, 0, sizeof(unsigned long long), st), "zero counter");
-    const unsigned nb = (unsigned)((n + 255) / 256);
     // Proposals do not depend on the chains, so the sampler draws those of
     // up to kb cycles in one launch: enough wavefronts (16 chains each) for
     // one per SIMD, where one cycle's alone would leave SIMDs idle.  Each
@@ -2055,8 +2217,8 @@ int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_
         double* lqp = a->mh_lqp + (cyc - batch_first) * n;
         hipLaunchKernelGGL(counts_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, prop, n, v.L, a->cprop,
                            (int32_t*)nullptr);
-        hipLaunchKernelGGL(mh_kernel, dim3(nb), dim3(256), 0, st, n, v.L, a->cur, prop, a->ccur, a->cprop, a->lqc,
-                           lqp, a->mh_tg, a->mh_ci, v.seed, step, v.id, a->nacc);
+        hipLaunchKernelGGL(mh_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, n, v.L, a->cur, prop, a->ccur,
+                           a->cprop, a->lqc, lqp, a->mh_tg, a->mh_ci, v.seed, step, v.id, a->nacc);
         AR_TRY(launch_pack(v.state, a->cur, n, v.L, st), "pack state");
         if (order_trace)  // recounts the current states (same counts) with the structure factor
             hipLaunchKernelGGL(counts_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->cur, n, v.L,
