@@ -459,6 +459,161 @@ __global__ void __launch_bounds__(256) train_fwd_kernel(int64_t B, int L, const 
     }
 }
 
+// Fused data-gradient chain for L <= kBwdMaxL: one workgroup of four
+// wavefronts per configuration runs the transposed convolutions of layers
+// 11 .. 1 with the gated gradient dz in LDS (double-buffered, zero border
+// below and on both sides for the mirrored taps) and the fp32 gradient of the
+// residual stream dh in registers (each wavefront keeps its tiles, at most
+// MAXT of 32 pixels, for the whole chain).  Per tile it runs conv32_kernel's
+// data-gradient arithmetic exactly (same instructions, operands and order;
+// dh_{l-1} = conv^T(dz_l) + dh_l; dz_{l-1} = bf16 of dh_{l-1} where layer
+// l-1's ReLU was open, else 0), so every dz equals the layered path's bit for
+// bit.  Outputs: dz_l of layers 10 .. 0 (pixel-major, the weight gradient's
+// operand), and per configuration and layer the sum of dz over its pixels in
+// fp32 (the bias-gradient partials, bpl[NL][B][C]; layer 11's is the sum of
+// the logit gradient, [B]); with gs != nullptr the same sums are the
+// per-sample bias gradients of a conditional network.
+constexpr int kBwdMaxL = 24;
+__host__ __device__ constexpr int bwd_lds_bytes(int L) {
+    return 2 * (L + 1) * (L + 2) * C * 2 + 4 * 32 * kOutRow * 4 + 4 * 32 * 4;
+}
+
+template <int MAXT>
+__global__ void __launch_bounds__(256) train_bwd_kernel(int64_t B, int L, const __bf16* __restrict__ g,
+                                                        const float* __restrict__ g32,
+                                                        const __bf16* __restrict__ wb,
+                                                        const uint32_t* __restrict__ mask, __bf16* __restrict__ dzs,
+                                                        float* __restrict__ bpl, float* __restrict__ gs) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = L * L, W2 = L + 2, PP = (L + 1) * (L + 2);
+    __bf16* bufs = reinterpret_cast<__bf16*>(smem);  // [2][PP][C]
+    float* Tall = reinterpret_cast<float*>(smem + (size_t)2 * PP * C * 2);
+    float* red = Tall + 4 * 32 * kOutRow;           // [4 wavefronts][C]
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    float* T = Tall + w * 32 * kOutRow;
+    const int li = lane & 31, half = lane >> 5;
+    const int64_t b = blockIdx.x;
+    if (b >= B) return;  // uniform per workgroup
+    const int64_t P = B * N, LSZ = P * C;
+    for (int q = tid; q < 2 * PP * (C / 8); q += blockDim.x)
+        *reinterpret_cast<bf16x8*>(bufs + (int64_t)q * 8) = zero8();
+    __syncthreads();
+    // dz of the logit layer: the loss gradient (channel 0), and its sum over the pixels
+    float gsum0 = 0.f;
+    for (int q = tid; q < N * (C / 8); q += blockDim.x) {
+        const int p = q >> 2, ch = q & 3;
+        const int r = p / L, c = p - r * L;
+        *reinterpret_cast<bf16x8*>(bufs + fwd_off(r * W2 + c + 1, ch)) =
+            *reinterpret_cast<const bf16x8*>(g + (b * N + p) * C + ch * 8);
+    }
+    for (int p = tid; p < N; p += blockDim.x) gsum0 += g32[b * N + p];
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) gsum0 += __shfl_xor(gsum0, m);
+    if (lane == 0) red[w * C] = gsum0;
+    __syncthreads();
+    if (tid == 0) {
+        const float t0 = ((red[0] + red[C]) + red[2 * C]) + red[3 * C];
+        bpl[(int64_t)(NL - 1) * B * C + b] = t0;
+        if (gs) {
+            gs[(b * NL + (NL - 1)) * C] = t0;
+            for (int c = 1; c < C; ++c) gs[(b * NL + (NL - 1)) * C + c] = 0.f;
+        }
+    }
+    const int ntiles = (N + 31) / 32;
+    const int mtoff[NT] = {W2 + 1, W2, W2 - 1, 1, 0};  // the mirrored taps (1,1) (1,0) (1,-1) (0,1) (0,0)
+    float dh[MAXT][16];
+#pragma unroll
+    for (int k = 0; k < MAXT; ++k)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) dh[k][e] = 0.f;
+    int in_b = 0;
+    for (int l = NL - 1; l >= 1; --l) {
+        const __bf16* Wop = wb + (int64_t)l * NT * C * C;
+        bf16x8 Bf[NT][2];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int kh = 0; kh < 2; ++kh) Bf[t][kh] = load8(Wop + ((int64_t)t * C + li) * C + kh * 16 + half * 8);
+        const __bf16* bin = bufs + (size_t)in_b * PP * C;
+        __bf16* bout = bufs + (size_t)(1 - in_b) * PP * C;
+        const uint32_t* gate = mask + (int64_t)(l - 1) * P;
+        __bf16* dzo = dzs + (int64_t)(l - 1) * LSZ;
+        float gsum[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) gsum[e] = 0.f;
+#pragma unroll
+        for (int k = 0; k < MAXT; ++k) {
+            const int tile = w + 4 * k;
+            if (tile >= ntiles) break;
+            const int pp = tile * 32 + li;
+            bf16x8 A[NT][2];
+            if (pp < N) {
+                const int r = pp / L, c = pp - r * L, pidx = r * W2 + c + 1;
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int kh = 0; kh < 2; ++kh)
+                        A[t][kh] = *reinterpret_cast<const bf16x8*>(bin + fwd_off(pidx + mtoff[t], 2 * kh + half));
+            } else {
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int kh = 0; kh < 2; ++kh) A[t][kh] = zero8();
+            }
+            f32x16 acc;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int kh = 0; kh < 2; ++kh) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[t][kh], Bf[t][kh], acc, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) T[(8 * (v >> 2) + 4 * half + (v & 3)) * kOutRow + li] = acc[v];
+            wave_sync();
+            const int pi = tile * 32 + (lane >> 1), c0 = (lane & 1) * 16;
+            if (pi < N) {
+                const int r = pi / L, c = pi - r * L, pidx = r * W2 + c + 1;
+                const uint32_t gm = gate[b * N + pi] >> c0;
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh) {
+                    bf16x8 zb;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const float z = T[(lane >> 1) * kOutRow + c0 + 8 * hh + e];
+                        const float d = (l == NL - 1) ? z : z + dh[k][8 * hh + e];
+                        dh[k][8 * hh + e] = d;
+                        const float v = ((gm >> (8 * hh + e)) & 1u) ? d : 0.f;
+                        zb[e] = f2bf(v);
+                        gsum[8 * hh + e] += v;
+                    }
+                    *reinterpret_cast<bf16x8*>(bout + fwd_off(pidx, (c0 >> 3) + hh)) = zb;
+                    *reinterpret_cast<bf16x8*>(dzo + (b * N + pi) * C + c0 + 8 * hh) = zb;
+                }
+            }
+            wave_sync();  // the rows are rewritten by the next tile
+        }
+        // per-configuration sums of dz_{l-1}: lanes of equal parity hold the same 16 channels
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            float v = gsum[e];
+#pragma unroll
+            for (int m = 2; m < 64; m <<= 1) v += __shfl_xor(v, m);
+            gsum[e] = v;
+        }
+        if (lane < 2)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) red[w * C + lane * 16 + e] = gsum[e];
+        __syncthreads();  // dz_{l-1} and the sums are complete
+        if (tid < C) {
+            const float t0 = ((red[tid] + red[C + tid]) + red[2 * C + tid]) + red[3 * C + tid];
+            bpl[((int64_t)(l - 1) * B + b) * C + tid] = t0;
+            if (gs) gs[(b * NL + (l - 1)) * C + tid] = t0;
+        }
+        __syncthreads();  // red is rewritten by the next layer
+        in_b = 1 - in_b;
+    }
+}
+
 // Partial weight gradients, one chunk of kWChunk pixels each, all taps at once
 // (they share the gradient operand):
 //   part[chunk][t][i][j] = sum_{p in chunk} in[p + tap_t][i] dz[p][j]
@@ -1521,6 +1676,8 @@ struct crbm_ar_s {
     float *part = nullptr, *bpart = nullptr;
     double* part2 = nullptr;                // [kRedSlices][NT][C][C]
     int8_t* spins_copy = nullptr;
+    __bf16* dzs = nullptr;      // fused backward: dz of layers 0 .. NL-2, [NL-1][P][C]
+    float* bpl = nullptr;       // fused backward: per-configuration bias partials, [NL][B][C]
     // sequential sampler buffers (capacity in chains)
     int64_t scap = 0;
     __bf16* ring = nullptr;     // [NL][n][2][L][C]: activations of the last two rows
@@ -1549,7 +1706,7 @@ struct crbm_ar_s {
     int32_t* bpts = nullptr;
     ~crbm_ar_s() {
         void* ps[] = {theta, grad, m, v, bias, wf, wb, hs, mask, logit, g32, dh0, dh1, dz, g, logq, part, bpart,
-                      part2,
+                      part2, dzs, bpl,
                       spins_copy, ring, slogit, zpad, ih0, ih1, ilogit, cur, ccur, cprop, lqc, nacc,
                       feats, cb, gs, gp, mh_ci, mh_tg, mh_prop, mh_lqp, bspins, bpts};
         for (void* p : ps)
@@ -1582,7 +1739,7 @@ int ensure_train(crbm_ar_t* a, int64_t B) {
     if (B <= a->tcap) return CRBM_OK;
     if (B > (kMaxPixels - 1) / ((int64_t)a->L * a->L)) return fail_ar(CRBM_EINVAL, "batch too large (samples x L^2 must be below 2^31)");
     void* ps[] = {a->hs, a->mask, a->logit, a->g32, a->dh0, a->dh1, a->dz, a->g, a->logq, a->part, a->bpart,
-                  a->spins_copy, a->part2, a->gs};
+                  a->spins_copy, a->part2, a->gs, a->dzs, a->bpl};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     // every pointer is cleared: an allocation that fails part-way leaves the
@@ -1597,6 +1754,8 @@ int ensure_train(crbm_ar_t* a, int64_t B) {
     a->spins_copy = nullptr;
     a->part2 = nullptr;
     a->gs = nullptr;
+    a->dzs = nullptr;
+    a->bpl = nullptr;
     a->tcap = 0;
     const int64_t P = B * a->L * a->L;
     const int64_t nch = wgrad_chunks(P);
@@ -1604,7 +1763,8 @@ int ensure_train(crbm_ar_t* a, int64_t B) {
         alloc(&a->g32, P) || alloc(&a->dh0, P * C) || alloc(&a->dh1, P * C) || alloc(&a->dz, P * C) ||
         alloc(&a->g, P * C) || alloc(&a->logq, B) || alloc(&a->part, nch * NT * C * C) ||
         alloc(&a->bpart, (int64_t)std::max<int64_t>(4096, 4 * (int64_t)a->conv_wg) * C) || alloc(&a->spins_copy, P) ||
-        alloc(&a->part2, (int64_t)kRedSlices * NT * C * C) || (a->cond > 0 && alloc(&a->gs, B * kCondOut))) {
+        alloc(&a->part2, (int64_t)kRedSlices * NT * C * C) || (a->cond > 0 && alloc(&a->gs, B * kCondOut)) ||
+        (a->L <= kBwdMaxL && (alloc(&a->dzs, (int64_t)(NL - 1) * P * C) || alloc(&a->bpl, (int64_t)NL * B * C)))) {
         a->tcap = 0;
         return fail_ar(CRBM_ENOMEM, "training buffers");
     }
@@ -1694,6 +1854,36 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
     hipLaunchKernelGGL(loss_kernel, dim3((unsigned)B), dim3(256), 0, st, a->logit, spins, L, 1.0f / (float)B, a->logq,
                        a->g, a->g32);
     const int nch = (int)wgrad_chunks(P);
+    if (L <= kBwdMaxL) {
+        // the whole data-gradient chain per configuration, then the weight
+        // gradients of all layers from the stored dz (bit for bit the layered
+        // path's; the bias sums come per configuration instead of per
+        // wavefront of the layered launch, so their fp32 grouping differs)
+        const int lds = bwd_lds_bytes(L);
+        const bool small = (L * L + 31) / 32 <= 12;
+        const void* fn = small ? reinterpret_cast<const void*>(&train_bwd_kernel<3>)
+                               : reinterpret_cast<const void*>(&train_bwd_kernel<5>);
+        AR_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds), "training backward LDS size");
+        float* gs = a->cond > 0 ? a->gs : nullptr;
+        if (small)
+            hipLaunchKernelGGL(train_bwd_kernel<3>, dim3((unsigned)B), dim3(256), lds, st, B, L, a->g, a->g32, a->wb,
+                               a->mask, a->dzs, a->bpl, gs);
+        else
+            hipLaunchKernelGGL(train_bwd_kernel<5>, dim3((unsigned)B), dim3(256), lds, st, B, L, a->g, a->g32, a->wb,
+                               a->mask, a->dzs, a->bpl, gs);
+        for (int l = NL - 1; l >= 0; --l) {
+            const Taps tp = taps_for(l, false);
+            const __bf16* dzl = (l == NL - 1) ? a->g : a->dzs + (size_t)l * LSZ;
+            hipLaunchKernelGGL(wgrad_fused_kernel, dim3((unsigned)nch), dim3(64 * kWWaves), 0, st,
+                               a->hs + (size_t)l * LSZ, dzl, tp, L, P, a->part);
+            hipLaunchKernelGGL(reduce_slices_kernel, dim3((NT * C * C + 255) / 256, kRedSlices), dim3(256), 0, st,
+                               a->part, nch, NT * C * C, a->part2);
+            const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
+            const int wblocks = (T * ci * co + 255) / 256;
+            hipLaunchKernelGGL(finish_layer_grad_kernel, dim3(wblocks + co), dim3(256), 0, st, a->part2, wblocks,
+                               a->bpl + (size_t)l * B * C, (int)B, l, a->grad);
+        }
+    } else {
     float* dh = a->dh0;
     float* dh_alt = a->dh1;
     // The data-gradient convolution of layer l also applies the ReLU mask of
@@ -1738,6 +1928,7 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
                                a->bpart);
             std::swap(dh, dh_alt);
         }
+    }
     }
     if (a->cond > 0) {
         hipLaunchKernelGGL(point_grad_kernel, dim3((unsigned)((a->npts * kCondOut + 255) / 256)), dim3(256), 0, st,
