@@ -630,9 +630,21 @@ constexpr int kWWaves = 2;  // wavefronts per chunk, kWChunk / kWWaves pixels ea
 constexpr int kFT = 32;           // pixels per staged tile (two 16-pixel k-steps)
 constexpr int kFRow = kFT + 8;    // LDS row stride in elements (80 bytes: 16-byte aligned rows)
 
-__global__ void __launch_bounds__(64 * kWWaves) wgrad_fused_kernel(const __bf16* __restrict__ in,
-                                                                   const __bf16* __restrict__ dz, Taps taps, int L,
-                                                                   int64_t P, float* __restrict__ part) {
+// Weight-gradient jobs of one launch (blockIdx.y picks the job): the layer's
+// input, its gated gradient, its partial-sum buffer and its layer index.
+struct WgradJobs {
+    const __bf16* in[NL];
+    const __bf16* dz[NL];
+    float* part[NL];
+    int layer[NL];
+};
+
+__global__ void __launch_bounds__(64 * kWWaves) wgrad_fused_kernel(WgradJobs jobs, int L, int64_t P) {
+    const int job = blockIdx.y;
+    const __bf16* __restrict__ in = jobs.in[job];
+    const __bf16* __restrict__ dz = jobs.dz[job];
+    float* __restrict__ part = jobs.part[job];
+    const Taps taps = taps_for_dev(jobs.layer[job]);
     constexpr int kSlot = (NT + 1) * C * kFRow;  // one wavefront's tiles: slots 0..NT-1 taps, slot NT the gradient
     __shared__ __align__(16) __bf16 tls[kWWaves * kSlot];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -718,10 +730,14 @@ __global__ void __launch_bounds__(64 * kWWaves) wgrad_fused_kernel(const __bf16*
 // of S slices) sums chunks s, s + S, ... in fp64; stage 2 sums the S slices.
 constexpr int kRedSlices = 16;
 
+// blockIdx.z picks one of several partial-sum sets, part_stride / part2_stride apart
 __global__ void __launch_bounds__(256) reduce_slices_kernel(const float* __restrict__ part, int nchunks, int n,
-                                                            double* __restrict__ part2) {
+                                                            double* __restrict__ part2, int64_t part_stride,
+                                                            int64_t part2_stride) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int sl = blockIdx.y;
+    part += (int64_t)blockIdx.z * part_stride;
+    part2 += (int64_t)blockIdx.z * part2_stride;
     if (x >= n) return;
     double s = 0.0;
 #pragma unroll 8  // loads in flight; the sum keeps its order
@@ -1602,10 +1618,20 @@ __device__ __forceinline__ int64_t layer_offset(int l) {
 // - then one workgroup per output channel j: bias j is the sum of the nparts
 //   partial sums bpart[p][j] (the last layer: bpart[p]), 256 threads each
 //   adding a strided share, then a fixed-order tree in LDS (fp64).
-__global__ void __launch_bounds__(256) finish_layer_grad_kernel(const double* __restrict__ part2, int wblocks,
-                                                                const float* __restrict__ bpart, int nparts, int l,
+// layer l = l0 + blockIdx.y; its slices at part2 + blockIdx.y part2_stride,
+// its bias partials at bpart + blockIdx.y bpart_stride; blocks beyond the
+// layer's weight blocks and bias channels return
+__global__ void __launch_bounds__(256) finish_layer_grad_kernel(const double* __restrict__ part2,
+                                                                int64_t part2_stride,
+                                                                const float* __restrict__ bpart,
+                                                                int64_t bpart_stride, int nparts, int l0,
                                                                 float* __restrict__ grad) {
+    const int l = l0 + (int)blockIdx.y;
+    part2 += (int64_t)blockIdx.y * part2_stride;
+    bpart += (int64_t)blockIdx.y * bpart_stride;
     const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
+    const int wblocks = (T * ci * co + 255) / 256;
+    if ((int)blockIdx.x >= wblocks + co) return;
     const int64_t off = layer_offset(l);
     if ((int)blockIdx.x < wblocks) {
         const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1761,9 +1787,10 @@ int ensure_train(crbm_ar_t* a, int64_t B) {
     const int64_t nch = wgrad_chunks(P);
     if (alloc(&a->hs, (int64_t)NL * P * C) || alloc(&a->mask, (int64_t)(NL - 1) * P) || alloc(&a->logit, P) ||
         alloc(&a->g32, P) || alloc(&a->dh0, P * C) || alloc(&a->dh1, P * C) || alloc(&a->dz, P * C) ||
-        alloc(&a->g, P * C) || alloc(&a->logq, B) || alloc(&a->part, nch * NT * C * C) ||
+        alloc(&a->g, P * C) || alloc(&a->logq, B) ||
+        alloc(&a->part, (a->L <= kBwdMaxL ? NL : 1) * nch * NT * C * C) ||
         alloc(&a->bpart, (int64_t)std::max<int64_t>(4096, 4 * (int64_t)a->conv_wg) * C) || alloc(&a->spins_copy, P) ||
-        alloc(&a->part2, (int64_t)kRedSlices * NT * C * C) || (a->cond > 0 && alloc(&a->gs, B * kCondOut)) ||
+        alloc(&a->part2, (int64_t)(a->L <= kBwdMaxL ? NL : 1) * kRedSlices * NT * C * C) || (a->cond > 0 && alloc(&a->gs, B * kCondOut)) ||
         (a->L <= kBwdMaxL && (alloc(&a->dzs, (int64_t)(NL - 1) * P * C) || alloc(&a->bpl, (int64_t)NL * B * C)))) {
         a->tcap = 0;
         return fail_ar(CRBM_ENOMEM, "training buffers");
@@ -1871,18 +1898,21 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
         else
             hipLaunchKernelGGL(train_bwd_kernel<5>, dim3((unsigned)B), dim3(256), lds, st, B, L, a->g, a->g32, a->wb,
                                a->mask, a->dzs, a->bpl, gs);
-        for (int l = NL - 1; l >= 0; --l) {
-            const Taps tp = taps_for(l, false);
-            const __bf16* dzl = (l == NL - 1) ? a->g : a->dzs + (size_t)l * LSZ;
-            hipLaunchKernelGGL(wgrad_fused_kernel, dim3((unsigned)nch), dim3(64 * kWWaves), 0, st,
-                               a->hs + (size_t)l * LSZ, dzl, tp, L, P, a->part);
-            hipLaunchKernelGGL(reduce_slices_kernel, dim3((NT * C * C + 255) / 256, kRedSlices), dim3(256), 0, st,
-                               a->part, nch, NT * C * C, a->part2);
-            const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
-            const int wblocks = (T * ci * co + 255) / 256;
-            hipLaunchKernelGGL(finish_layer_grad_kernel, dim3(wblocks + co), dim3(256), 0, st, a->part2, wblocks,
-                               a->bpl + (size_t)l * B * C, (int)B, l, a->grad);
+        // the weight gradients of all layers in one launch each of the
+        // partial sums, their slice fold and the finish
+        WgradJobs jobs{};
+        const int64_t pst = (int64_t)nch * NT * C * C, p2st = (int64_t)kRedSlices * NT * C * C;
+        for (int l = 0; l < NL; ++l) {
+            jobs.in[l] = a->hs + (size_t)l * LSZ;
+            jobs.dz[l] = (l == NL - 1) ? a->g : a->dzs + (size_t)l * LSZ;
+            jobs.part[l] = a->part + l * pst;
+            jobs.layer[l] = l;
         }
+        hipLaunchKernelGGL(wgrad_fused_kernel, dim3((unsigned)nch, NL), dim3(64 * kWWaves), 0, st, jobs, L, P);
+        hipLaunchKernelGGL(reduce_slices_kernel, dim3((NT * C * C + 255) / 256, kRedSlices, NL), dim3(256), 0, st,
+                           a->part, nch, NT * C * C, a->part2, pst, p2st);
+        hipLaunchKernelGGL(finish_layer_grad_kernel, dim3((NT * C * C + 255) / 256 + C, NL), dim3(256), 0, st, a->part2,
+                           p2st, a->bpl, (int64_t)B * C, (int)B, 0, a->grad);
     } else {
     float* dh = a->dh0;
     float* dh_alt = a->dh1;
@@ -1893,7 +1923,7 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
     __bf16* dz_next = nullptr;
     int nbp_next = 0;
     for (int l = NL - 1; l >= 0; --l) {
-        const Taps tp = taps_for(l, false), tm = taps_for(l, true);
+        const Taps tm = taps_for(l, true);
         const __bf16* dzl;
         int nbp;
         if (l == NL - 1) {
@@ -1908,14 +1938,18 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
             hipLaunchKernelGGL(sample_bias_grad_kernel, dim3((unsigned)B), dim3(256), 0, st, dh,
                                a->mask + (size_t)(l < NL - 1 ? l : 0) * P, l == NL - 1 ? a->g32 : nullptr, L * L,
                                l, a->gs);
-        hipLaunchKernelGGL(wgrad_fused_kernel, dim3((unsigned)nch), dim3(64 * kWWaves), 0, st, a->hs + (size_t)l * LSZ, dzl, tp,
-                           L, P, a->part);
-        hipLaunchKernelGGL(reduce_slices_kernel, dim3((NT * C * C + 255) / 256, kRedSlices), dim3(256), 0, st,
-                           a->part, nch, NT * C * C, a->part2);
+        WgradJobs job1{};
+        job1.in[0] = a->hs + (size_t)l * LSZ;
+        job1.dz[0] = dzl;
+        job1.part[0] = a->part;
+        job1.layer[0] = l;
+        hipLaunchKernelGGL(wgrad_fused_kernel, dim3((unsigned)nch, 1), dim3(64 * kWWaves), 0, st, job1, L, P);
+        hipLaunchKernelGGL(reduce_slices_kernel, dim3((NT * C * C + 255) / 256, kRedSlices, 1), dim3(256), 0, st,
+                           a->part, nch, NT * C * C, a->part2, (int64_t)0, (int64_t)0);
         const int T = (l == 0) ? 4 : 5, ci = (l == 0) ? 1 : C, co = (l == NL - 1) ? 1 : C;
         const int wblocks = (T * ci * co + 255) / 256;
-        hipLaunchKernelGGL(finish_layer_grad_kernel, dim3(wblocks + co), dim3(256), 0, st, a->part2, wblocks, a->bpart,
-                           nbp, l, a->grad);
+        hipLaunchKernelGGL(finish_layer_grad_kernel, dim3(wblocks + co, 1), dim3(256), 0, st, a->part2, (int64_t)0,
+                           a->bpart, (int64_t)0, nbp, l, a->grad);
         if (l > 0) {
             const __bf16* Wb = a->wb + (size_t)l * NT * C * C;
             const int mode = (l == NL - 1) ? EP_DGRAD : EP_DGRAD_RESID;
