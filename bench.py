@@ -54,6 +54,11 @@ OPS_SLOT16 = 3.5 * (PHILOX_BLOCK_OPS / 8.0 + 1.0)
 OPS_U32 = 3.5 * (PHILOX_BLOCK_OPS / 4.0 + 1.0)
 # MI355X integer VALU peak: 256 CUs x 64 lanes x 2.4 GHz (one 32-bit op per lane per clock)
 ALU_PEAK_OPS = 256 * 64 * 2.4e9
+# MI355X dense bf16 matrix-core peak, FLOP/s
+BF16_PEAK_FLOPS = 2.5e15
+# masked-tap work of one 18x18 forward pass of the 12-layer 32-channel proposal:
+# layer 1 4 taps x 1 -> 32, layers 2-11 5 taps x 32 -> 32, layer 12 5 taps x 32 -> 1
+AR_FLOP_PER_SAMPLE = 2 * 324 * (4 * 1 * 32 + 10 * 5 * 32 * 32 + 5 * 32 * 1)
 # MI355X LDS peak: 256 CUs x 128 bytes per clock x 2.4 GHz
 LDS_PEAK_BPS = 256 * 128 * 2.4e9
 
@@ -270,7 +275,13 @@ def learned_mh(crbm, torch, temps=(0.4, 0.2, 0.1), steps=800, cycles=500):
             d = r[k]["E_per_spin"] - ref[T]
             # se = 0: every kept sample has the same energy; then report the bias only if it is not rounding
             r[k]["bias_se"] = d / r[k]["se"] if r[k]["se"] > 0 else (0.0 if abs(d) < 1e-12 else None)
+        # algorithmic training work: forward, data gradient and weight gradient over
+        # the masked taps, 3 x 33.4 MFLOP per 18x18 sample, 1024 samples per step
+        step_flop = 3 * AR_FLOP_PER_SAMPLE * 1024
         r.update({"T": T, "E_ref": ref[T], "data_s": t_data, "train_s": t_train, "train_steps": steps,
+                  "train_step_ms": 1e3 * t_train / steps,
+                  "train_tflops": step_flop / (t_train / steps) / 1e12,
+                  "train_frac_bf16": step_flop / (t_train / steps) / BF16_PEAK_FLOPS,
                   "final_loss_per_site": loss,
                   "ess_ratio": r["learned"]["ess_per_s"] / r["gibbs"]["ess_per_s"],
                   "ess_min_ratio": r["learned"]["ess_min_per_s"] / r["gibbs"]["ess_min_per_s"]})
@@ -529,7 +540,8 @@ def summarise(legs):
                               "ess_per_s_gibbs": _r(p["gibbs"]["ess_per_s"], 3),
                               "ess_ratio": _r(p["ess_ratio"], 3), "ess_min_ratio": _r(p["ess_min_ratio"], 3),
                               "bias_se_learned": _r(p["learned"]["bias_se"], 2),
-                              "bias_se_gibbs": _r(p["gibbs"]["bias_se"], 2), "train_s": _r(p["train_s"], 3)}
+                              "bias_se_gibbs": _r(p["gibbs"]["bias_se"], 2), "train_s": _r(p["train_s"], 3),
+                              "train_step_ms": _r(p["train_step_ms"], 3), "train_frac_bf16": _r(p["train_frac_bf16"], 3)}
                              for p in m["points"]]
     c = legs.get("learned_mh_points")
     if c:
