@@ -29,6 +29,9 @@
 // row, the threshold is looked up per spin by (n, d) from a 10-entry table held
 // one entry per lane.  U = (P << 16) | Q with P, Q 16-bit Philox slots; Q is
 // drawn only when P equals the threshold's top half (probability 2^-16).
+// With tc = ceil(t / 2^16), P >= tc decides U >= t except where P = tc - 1,
+// which holds every such tie (and, when 2^16 divides t, P = t/2^16 - 1,
+// which the exact path then decides as well).
 #pragma once
 #include "crbm_internal.h"
 
@@ -125,8 +128,8 @@ struct SweepK {
     uint32_t neg[2];   // all ones if sig_t < 0
     uint32_t en[2];    // all ones if wq_t != 0
     uint32_t kge[2];   // spin field >= 0 iff n >= kge[d]
-    uint32_t tabv;     // lane l < 10: min(tceil, 0xffff) | thi << 16 of visible entry l
-    uint32_t tfull;    // lane l < 10: full visible threshold of entry l
+    uint32_t tabv;     // lane l < 10: ceil(t / 2^16) of visible entry l (0 .. 2^16)
+    uint32_t tfull;    // lane l < 10: full visible threshold t of entry l
 };
 
 __device__ __forceinline__ SweepK load_sweep(const uint32_t* tb, int lane) {
@@ -140,10 +143,8 @@ __device__ __forceinline__ SweepK load_sweep(const uint32_t* tb, int lane) {
         K.kge[t] = (fl >> (8 + 4 * t)) & 15u;
     }
     const uint32_t tv = tb[3 + (lane < 10 ? lane : 9)];
-    uint32_t tc = (tv >> 16) + ((tv & 0xffffu) != 0u);
-    tc = tc > 0xffffu ? 0xffffu : tc;
     K.tfull = tv;
-    K.tabv = tc | (tv & 0xffff0000u);
+    K.tabv = (tv >> 16) + ((tv & 0xffffu) != 0u);
     return K;
 }
 
@@ -179,6 +180,7 @@ __host__ __device__ constexpr uint32_t bits_between(int lo, int hi) {
 // operand patterns a = 0xF0, b = 0xCC, c = 0xAA.
 constexpr int kLutAndNotAnd = 0xF0 & ~0xCC & 0xAA;      // a & ~b & c
 constexpr int kLutKeepEqual = 0xF0 & ~(0xCC ^ 0xAA) & 0xFF;  // a & ~(b ^ c)
+constexpr int kLutSelectC = ((0xF0 & ~0xAA) | (0xCC & 0xAA)) & 0xFF;  // c ? b : a
 
 // All ones where bit (31 - b) of the wavefront-uniform word x is set.
 __device__ __forceinline__ uint32_t plane_mask(uint32_t x, int b) {
@@ -193,13 +195,20 @@ __device__ __forceinline__ void compare_plane(uint32_t& lt, uint32_t& eq, uint32
     eq = __builtin_amdgcn_bitop3_b32(eq, p, t, kLutKeepEqual);
 }
 
-// Bit-sliced comparison U < T over 32 packed hidden units.  val: units that
-// exist; ag: agreeing units (threshold T1 or T2 by type); j2: units of dimer
-// type.  Returns the units with U >= threshold ("flip against the field").
-// The threshold plane is uniform over the wavefront: a scalar operand of the
-// two bit operations per plane.
-__device__ __forceinline__ uint32_t hidden_compare(uint32_t val, uint32_t ag, uint32_t j2, const SweepK& K,
-                                                   uint32_t cb, uint32_t c3, const Rng& rg) {
+// Threshold plane b for 32 units whose dimer-type units are the bits of j2.
+__device__ __forceinline__ uint32_t threshold_plane(const SweepK& K, int b, uint32_t j2) {
+    return __builtin_amdgcn_bitop3_b32(plane_mask(K.T[0], b), plane_mask(K.T[1], b), j2, kLutSelectC);
+}
+
+// First two Philox blocks (planes 0-7) of the bit-sliced comparison U < T
+// over 32 packed hidden units.  val: units that exist; ag: agreeing units
+// (threshold T1 or T2 by type); j2: units of dimer type.  Leaves in lt the
+// units already known to fall below their threshold and in eq those still
+// tied.  The threshold plane is uniform over the wavefront: a scalar operand
+// of the two bit operations per plane.
+__device__ __forceinline__ void hidden_compare_head(uint32_t val, uint32_t ag, uint32_t j2, const SweepK& K,
+                                                    uint32_t cb, uint32_t c3, const Rng& rg, uint32_t& lt,
+                                                    uint32_t& eq) {
     // only bits of units that exist matter (eq is confined to them)
     const bool only1 = j2 == 0u, only2 = (j2 & val) == val;
     auto tplane = [&](int b) -> uint32_t {
@@ -209,18 +218,88 @@ __device__ __forceinline__ uint32_t hidden_compare(uint32_t val, uint32_t ag, ui
     P4 p = philox(cb, rg.sweep, rg.chain, c3, rg.k0, rg.k1);
     // plane 0: every threshold has its top bit set (T >= 2^31); disagreeing
     // units (threshold exactly 2^31) are decided here
-    uint32_t lt = val & ~p.v[0];
-    uint32_t eq = ag & p.v[0];
+    lt = val & ~p.v[0];
+    eq = ag & p.v[0];
 #pragma unroll
     for (int b = 1; b < 4; ++b) compare_plane(lt, eq, p.v[b], tplane(b));
-#pragma unroll 1
-    for (int c = 1; c < 8; ++c) {
-        if (!__any(eq != 0u)) break;
-        p = philox(cb | (uint32_t)c, rg.sweep, rg.chain, c3, rg.k0, rg.k1);
+    if (!__any(eq != 0u)) return;
+    p = philox(cb | 1u, rg.sweep, rg.chain, c3, rg.k0, rg.k1);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) compare_plane(lt, eq, p.v[s], tplane(4 * c + s));
+    for (int s = 0; s < 4; ++s) compare_plane(lt, eq, p.v[s], tplane(4 + s));
+}
+
+// The rest of the comparison (planes 8-31) for the NPW words of one row word
+// whose units are still tied.  A unit is tied after 8 planes with probability
+// 2^-8, so only about one word in ten has such a unit; continuing every word
+// in place would run each further block on all 64 lanes while any lane of the
+// wavefront is tied.  Instead the tied words of the wavefront are ranked
+// (ballot and prefix count) and moved through this wavefront's 5 x 64 word
+// LDS buffer onto consecutive lanes, up to 64 at a time, which draw their
+// remaining blocks together and hand each word's result back.  Every unit
+// still consumes exactly its own planes, in order, so the decisions are those
+// of the full 32-bit comparison.  A unit equal to its threshold in all 32
+// planes is not below it.
+__device__ __forceinline__ void hidden_compare_tail(int NPW, uint32_t (&lt)[5], uint32_t (&eq)[5],
+                                                    const uint32_t (&j2)[5], uint32_t cbw, const SweepK& K, uint32_t c3, const Rng& rg,
+                                                    uint32_t* buf, int lane) {
+    uint32_t* const b_eq = buf;
+    uint32_t* const b_lt = buf + 64;
+    uint32_t* const b_cb = buf + 128;
+    uint32_t* const b_ch = buf + 192;
+    uint32_t* const b_j2 = buf + 256;
+    for (;;) {
+        int slot[5] = {-1, -1, -1, -1, -1};
+        uint32_t n = 0u;  // tied words ranked so far (wavefront-uniform)
+#pragma unroll
+        for (int pw = 0; pw < 5; ++pw) {
+            if (pw >= NPW) continue;
+            const bool tied = eq[pw] != 0u;
+            const uint64_t bal = __ballot(tied);
+            const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bal, n));
+            slot[pw] = (tied && r < 64u) ? (int)r : -1;
+            if (slot[pw] >= 0) {
+                b_eq[r] = eq[pw];
+                b_lt[r] = lt[pw];
+                b_cb[r] = cbw | ((uint32_t)pw << 3);
+                b_ch[r] = rg.chain;
+                b_j2[r] = j2[pw];
+            }
+            n += (uint32_t)__popcll(bal);
+        }
+        if (n == 0u) return;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const bool mine = (uint32_t)lane < n;
+        uint32_t e = 0u, l = 0u, cb = 0u, ch = 0u, jm = 0u;
+        if (mine) {
+            e = b_eq[lane];
+            l = b_lt[lane];
+            cb = b_cb[lane];
+            ch = b_ch[lane];
+            jm = b_j2[lane];
+        }
+#pragma unroll 1
+        for (int c = 2; c < 8; ++c) {
+            if (!__any(e != 0u)) break;
+            const P4 p = philox(cb | (uint32_t)c, rg.sweep, ch, c3, rg.k0, rg.k1);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) compare_plane(l, e, p.v[s], threshold_plane(K, 4 * c + s, jm));
+        }
+        if (mine) b_lt[lane] = l;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int pw = 0; pw < 5; ++pw) {
+            if (pw < NPW && slot[pw] >= 0) {
+                lt[pw] = b_lt[slot[pw]];
+                eq[pw] = 0u;
+            }
+        }
+        if (n <= 64u) return;
     }
-    return val & ~lt;
 }
 
 // Hidden half-step of one cell row i: 10 hidden planes (bits at the cells' even
@@ -228,7 +307,8 @@ __device__ __forceinline__ uint32_t hidden_compare(uint32_t val, uint32_t ag, ui
 template <int L>
 __device__ __forceinline__ void hidden_row(const uint32_t (&top)[Geo<L>::W], const uint32_t (&mid)[Geo<L>::W],
                                            const uint32_t (&bot)[Geo<L>::W], const SweepK& K, uint32_t i,
-                                           uint32_t c3, const Rng& rg, uint32_t (&H)[10][Geo<L>::W]) {
+                                           uint32_t c3, const Rng& rg, uint32_t* tailbuf, int lane,
+                                           uint32_t (&H)[10][Geo<L>::W]) {
     using G = Geo<L>;
 #pragma unroll
     for (int w = 0; w < G::W; ++w) {
@@ -258,18 +338,23 @@ __device__ __forceinline__ void hidden_row(const uint32_t (&top)[Geo<L>::W], con
         }
         const int NQ = 10 * n;
         const int NPW = (NQ + 31) / 32;
-        uint32_t DP[NPWMAX] = {0u, 0u, 0u, 0u, 0u};
+        uint32_t LT[NPWMAX] = {0u, 0u, 0u, 0u, 0u}, EQ[NPWMAX] = {0u, 0u, 0u, 0u, 0u};
+        uint32_t J2[NPWMAX] = {0u, 0u, 0u, 0u, 0u}, VAL[NPWMAX] = {0u, 0u, 0u, 0u, 0u};
         const uint32_t cbw = (uint32_t)(i * G::W + w) << 8;
 #pragma unroll
         for (int pw = 0; pw < NPWMAX; ++pw) {
             if (pw < NPW) {
                 const int lo = 32 * pw;
-                const uint32_t val = bits_between(0, (NQ - lo) < 32 ? (NQ - lo) : 32);
+                VAL[pw] = bits_between(0, (NQ - lo) < 32 ? (NQ - lo) : 32);
                 const int j2lo = 8 * n - lo;
-                const uint32_t j2 = bits_between(j2lo < 0 ? 0 : (j2lo > 32 ? 32 : j2lo), (NQ - lo) < 32 ? (NQ - lo) : 32);
-                DP[pw] = hidden_compare(val, PA[pw], j2, K, cbw | ((uint32_t)pw << 3), c3, rg);
+                J2[pw] = bits_between(j2lo < 0 ? 0 : (j2lo > 32 ? 32 : j2lo), (NQ - lo) < 32 ? (NQ - lo) : 32);
+                hidden_compare_head(VAL[pw], PA[pw], J2[pw], K, cbw | ((uint32_t)pw << 3), c3, rg, LT[pw], EQ[pw]);
             }
         }
+        hidden_compare_tail(NPW, LT, EQ, J2, cbw, K, c3, rg, tailbuf, lane);
+        uint32_t DP[NPWMAX] = {0u, 0u, 0u, 0u, 0u};  // units at or above their threshold
+#pragma unroll
+        for (int pw = 0; pw < NPWMAX; ++pw) DP[pw] = VAL[pw] & ~LT[pw];
 #pragma unroll
         for (int p = 0; p < 5; ++p) {
             const int off = 2 * n * p;
@@ -326,7 +411,7 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
             {H[2][w], H[4][w] ^ n1, H[5][w], h3l ^ n1, h9l},              // (1,0): k2a k4b k5a k3b(j-1) | k9a(j-1)
             {H[2][w] ^ n1, H[3][w], H[6][w] ^ n1, H[7][w], H[8][w] ^ n2}, // (1,1): k2b k3a k6b k7a | k8b
         };
-        uint32_t Pa[4], Pb[4], Sg[4], D[4];
+        uint32_t Pa[4], Pb[4], Sg[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const uint32_t s1 = term[c][0] ^ term[c][1], c1 = term[c][0] & term[c][1];
@@ -337,11 +422,12 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
             Pa[c] = dd | (b0 << 1);
             Pb[c] = b1 | (b2 << 1);
             Sg[c] = ((dd & count_ge(b0, b1, b2, K.kge[1])) | (~dd & count_ge(b0, b1, b2, K.kge[0]))) & E;
-            D[c] = 0u;
         }
         // Byte offsets of the table lookups: byte k of By[4c + j] is 4 idx, with
         // idx = dd + 2 b0 + 4 b1 + 8 b2, of the class-c spin at even column
         // 2 (j + 4k), so that each lookup address is one byte of a register.
+        // ds_bpermute reads its source lane from address bits 2-7 only (lane
+        // index modulo 64), so By >> 8k is the address of byte k as it stands.
         uint32_t By[16];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -355,9 +441,14 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
         const int NQ = 2 * m;
         const int NB = (NQ + 7) / 8;
         const uint32_t cbase = (uint32_t)(i * G::W + w) << 5;
+        // ND[row]: bit c = 1 where U < t (the spin at column c follows its
+        // field), shifted in from the highest column down: slots are taken
+        // from the last block and the last slot backwards, so each row's
+        // spins arrive in descending column order
+        uint32_t ND[2] = {0u, 0u};
         uint32_t tieblk = 0u;
 #pragma unroll
-        for (int blk = 0; blk < 8; ++blk) {
+        for (int blk = 7; blk >= 0; --blk) {
             if (blk >= NB) continue;
             const bool has_top = blk * 8 < m, has_mid = blk * 8 + 7 >= m;
             if (!((do_top && has_top) || (do_mid && has_mid))) continue;
@@ -371,23 +462,23 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
             }
             uint64_t tie = 0;
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
+            for (int s = 7; s >= 0; --s) {
                 const int q = blk * 8 + s;
                 if (q < NQ) {
-                    const int row = q / m, col = q % m, cls = 2 * row + (col & 1), pos = col & ~1;
+                    const int row = q / m, col = q % m, cls = 2 * row + (col & 1);
                     if (!(row == 0 ? do_top : do_mid)) continue;
-                    const uint32_t p16 = slot16(p, s);
                     const int si = col >> 1;
-                    const int addr = (int)((By[4 * cls + (si & 3)] >> (8 * (si >> 2))) & 0xffu);
-                    const uint32_t e = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)K.tabv);
-                    D[cls] |= (uint32_t)(p16 >= (e & 0xffffu)) << pos;
-                    tie |= __ballot(p16 == (e >> 16));
+                    const uint32_t addr = By[4 * cls + (si & 3)] >> (8 * (si >> 2));
+                    const uint32_t tc = (uint32_t)__builtin_amdgcn_ds_bpermute((int)addr, (int)K.tabv);
+                    const uint32_t r = slot16(p, s) - tc;  // negative iff P < tc
+                    ND[row] = __builtin_amdgcn_alignbit(ND[row], r, 31);
+                    tie |= __ballot(r == 0xffffffffu);
                 }
             }
             if (tie) tieblk |= 1u << blk;
         }
-        // Rare path: a primary slot equal to the threshold's top half; redo the
-        // affected blocks with the refinement stream and exact 32-bit compares.
+        // Rare path: a primary slot P = tc - 1; redo the affected blocks with
+        // the refinement stream and exact 32-bit compares.
         while (tieblk) {
             const int blk = __builtin_ctz(tieblk);
             tieblk &= tieblk - 1u;
@@ -397,25 +488,29 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
             for (int s = 0; s < 8; ++s) {
                 const int q = blk * 8 + s;
                 if (q < NQ) {
-                    const int row = q / m, col = q % m, cls = 2 * row + (col & 1), pos = col & ~1;
+                    const int row = q / m, col = q % m, cls = 2 * row + (col & 1);
                     if (!(row == 0 ? do_top : do_mid)) continue;
                     const uint32_t U = (slot16(p, s) << 16) | slot16(r, s);
                     const int si = col >> 1;
-                    const int addr = (int)((pick(By, 4 * cls + (si & 3)) >> (8 * (si >> 2))) & 0xffu);
+                    const int addr = (int)(pick(By, 4 * cls + (si & 3)) >> (8 * (si >> 2)));
                     const uint32_t t = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)K.tfull);
-                    const uint32_t d = U >= t;
-                    put(D, cls, (pick(D, cls) & ~(1u << pos)) | (d << pos));
+                    const uint32_t bit = 1u << col, f = (U < t) ? bit : 0u;
+                    if (row == 0)
+                        ND[0] = (ND[0] & ~bit) | f;
+                    else
+                        ND[1] = (ND[1] & ~bit) | f;
                 }
             }
         }
-        ntop[w] = (Sg[0] ^ D[0]) | ((Sg[1] ^ D[1]) << 1);
-        nmid[w] = (Sg[2] ^ D[2]) | ((Sg[3] ^ D[3]) << 1);
+        // new spin = field sign, flipped where U >= t
+        ntop[w] = ~((Sg[0] | (Sg[1] << 1)) ^ ND[0]) & G::full(w);
+        nmid[w] = ~((Sg[2] | (Sg[3] << 1)) ^ ND[1]) & G::full(w);
     }
 }
 
 // One work item: up to 64/G chains of one instance, all sweeps [s0, s1).
 template <int L, int R>
-__device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, int lane) {
+__device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, int lane, uint32_t* tailbuf) {
     using Gm = Geo<L>;
     constexpr int W = Gm::W;
     constexpr int C = L / 2;
@@ -461,7 +556,7 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
         for (int m = 0; m < R; ++m) {
             const uint32_t i = (uint32_t)(g * R + m);
             uint32_t H[10][W];
-            hidden_row<L>(Q[0], Q[1], Q[2], K, i, c3h, rg, H);
+            hidden_row<L>(Q[0], Q[1], Q[2], K, i, c3h, rg, tailbuf, lane, H);
             uint32_t nt[W], nm[W];
             visible_row<L>(H, Hp5, Hp7, Hp9, K, m > 0, true, i, c3v, rg, nt, nm, straddle);
 #pragma unroll
@@ -645,10 +740,13 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
 template <int L, int R>
 __global__ void __launch_bounds__(256, (Geo<L>::W >= 3 ? 2 : 1)) gibbs_kernel(GibbsArgs a) {
     const int lane = threadIdx.x & 63;
+    // per wavefront: the tied hidden words of the comparison's tail (5 x 64 words)
+    __shared__ uint32_t tail_lds[4][5 * 64];
+    uint32_t* const tailbuf = tail_lds[threadIdx.x >> 6];
     if (a.queue == nullptr) {
         const int wv = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
         if (wv >= a.n_items) return;
-        gibbs_item<L, R>(a, a.items[wv], lane);
+        gibbs_item<L, R>(a, a.items[wv], lane, tailbuf);
         return;
     }
     for (;;) {
@@ -656,7 +754,7 @@ __global__ void __launch_bounds__(256, (Geo<L>::W >= 3 ? 2 : 1)) gibbs_kernel(Gi
         if (lane == 0) next = atomicAdd(a.queue, 1u);
         next = __builtin_amdgcn_readfirstlane(next);
         if (next >= (uint32_t)a.n_items) return;
-        gibbs_item<L, R>(a, a.items[next], lane);
+        gibbs_item<L, R>(a, a.items[next], lane, tailbuf);
     }
 }
 
