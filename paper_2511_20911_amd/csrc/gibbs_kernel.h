@@ -31,7 +31,10 @@
 // drawn only when P equals the threshold's top half (probability 2^-16).
 // With tc = ceil(t / 2^16), P >= tc decides U >= t except where P = tc - 1,
 // which holds every such tie (and, when 2^16 divides t, P = t/2^16 - 1,
-// which the exact path then decides as well).
+// which the exact path then decides as well).  The table entry carries the
+// field's sign as 2^31 added to tc where the field is negative, so the sign
+// bit of P - entry is the new spin itself (1 = up): P < tc for a field >= 0,
+// P >= tc for a negative one; a tie leaves 0xffff in the low half either way.
 #pragma once
 #include "crbm_internal.h"
 
@@ -128,7 +131,8 @@ struct SweepK {
     uint32_t neg[2];   // all ones if sig_t < 0
     uint32_t en[2];    // all ones if wq_t != 0
     uint32_t kge[2];   // spin field >= 0 iff n >= kge[d]
-    uint32_t tabv;     // lane l < 10: ceil(t / 2^16) of visible entry l (0 .. 2^16)
+    uint32_t tabv;     // lane l < 10: ceil(t / 2^16) of visible entry l (0 .. 2^16), plus 2^31
+                       // where the entry's field is negative
     uint32_t tfull;    // lane l < 10: full visible threshold t of entry l
 };
 
@@ -142,9 +146,11 @@ __device__ __forceinline__ SweepK load_sweep(const uint32_t* tb, int lane) {
         K.en[t] = (fl & (4u << t)) ? 0xffffffffu : 0u;
         K.kge[t] = (fl >> (8 + 4 * t)) & 15u;
     }
-    const uint32_t tv = tb[3 + (lane < 10 ? lane : 9)];
+    const int l = lane < 10 ? lane : 9;  // entry l: dimer term d = l & 1, J1 count n = l >> 1
+    const uint32_t tv = tb[3 + l];
     K.tfull = tv;
-    K.tabv = (tv >> 16) + ((tv & 0xffffu) != 0u);
+    const uint32_t kge = (l & 1) ? K.kge[1] : K.kge[0];  // a select: no runtime index into K
+    K.tabv = (tv >> 16) + ((tv & 0xffffu) != 0u) + (((uint32_t)(l >> 1) >= kge) ? 0u : 0x80000000u);
     return K;
 }
 
@@ -371,18 +377,6 @@ __device__ __forceinline__ void hidden_row(const uint32_t (&top)[Geo<L>::W], con
     }
 }
 
-// n >= k for a bit-sliced count n = n0 + 2 n1 + 4 n2 in 0..4 and uniform k.
-__device__ __forceinline__ uint32_t count_ge(uint32_t n0, uint32_t n1, uint32_t n2, uint32_t k) {
-    switch (k) {
-        case 0: return 0xffffffffu;
-        case 1: return n0 | n1 | n2;
-        case 2: return n1 | n2;
-        case 3: return n2 | (n1 & n0);
-        case 4: return n2;
-        default: return 0u;
-    }
-}
-
 // Visible half-step of the two rows of cell row i (Eq. (12)).  H: hidden
 // planes of this cell row; Hp5/Hp7/Hp9: planes 5, 7, 9 of the cell row above.
 // Classes: 0 top even, 1 top odd, 2 mid even, 3 mid odd columns.
@@ -411,7 +405,7 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
             {H[2][w], H[4][w] ^ n1, H[5][w], h3l ^ n1, h9l},              // (1,0): k2a k4b k5a k3b(j-1) | k9a(j-1)
             {H[2][w] ^ n1, H[3][w], H[6][w] ^ n1, H[7][w], H[8][w] ^ n2}, // (1,1): k2b k3a k6b k7a | k8b
         };
-        uint32_t Pa[4], Pb[4], Sg[4];
+        uint32_t Pa[4], Pb[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const uint32_t s1 = term[c][0] ^ term[c][1], c1 = term[c][0] & term[c][1];
@@ -421,7 +415,6 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
             const uint32_t dd = term[c][4] & E;
             Pa[c] = dd | (b0 << 1);
             Pb[c] = b1 | (b2 << 1);
-            Sg[c] = ((dd & count_ge(b0, b1, b2, K.kge[1])) | (~dd & count_ge(b0, b1, b2, K.kge[0]))) & E;
         }
         // Byte offsets of the table lookups: byte k of By[4c + j] is 4 idx, with
         // idx = dd + 2 b0 + 4 b1 + 8 b2, of the class-c spin at even column
@@ -441,11 +434,11 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
         const int NQ = 2 * m;
         const int NB = (NQ + 7) / 8;
         const uint32_t cbase = (uint32_t)(i * G::W + w) << 5;
-        // ND[row]: bit c = 1 where U < t (the spin at column c follows its
-        // field), shifted in from the highest column down: slots are taken
-        // from the last block and the last slot backwards, so each row's
-        // spins arrive in descending column order
-        uint32_t ND[2] = {0u, 0u};
+        // NS[row]: bit c = the new spin at column c (1 = up), shifted in from
+        // the highest column down: slots are taken from the last block and the
+        // last slot backwards, so each row's spins arrive in descending column
+        // order
+        uint32_t NS[2] = {0u, 0u};
         uint32_t tieblk = 0u;
 #pragma unroll
         for (int blk = 7; blk >= 0; --blk) {
@@ -469,16 +462,17 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
                     if (!(row == 0 ? do_top : do_mid)) continue;
                     const int si = col >> 1;
                     const uint32_t addr = By[4 * cls + (si & 3)] >> (8 * (si >> 2));
-                    const uint32_t tc = (uint32_t)__builtin_amdgcn_ds_bpermute((int)addr, (int)K.tabv);
-                    const uint32_t r = slot16(p, s) - tc;  // negative iff P < tc
-                    ND[row] = __builtin_amdgcn_alignbit(ND[row], r, 31);
-                    tie |= __ballot(r == 0xffffffffu);
+                    const uint32_t v = (uint32_t)__builtin_amdgcn_ds_bpermute((int)addr, (int)K.tabv);
+                    const uint32_t r = slot16(p, s) - v;  // sign bit: the new spin
+                    NS[row] = __builtin_amdgcn_alignbit(NS[row], r, 31);
+                    tie |= __ballot((uint16_t)r == 0xffffu);
                 }
             }
             if (tie) tieblk |= 1u << blk;
         }
         // Rare path: a primary slot P = tc - 1; redo the affected blocks with
-        // the refinement stream and exact 32-bit compares.
+        // the refinement stream and exact 32-bit compares (the new spin is
+        // U < t for a field >= 0, U >= t for a negative one).
         while (tieblk) {
             const int blk = __builtin_ctz(tieblk);
             tieblk &= tieblk - 1u;
@@ -494,17 +488,17 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
                     const int si = col >> 1;
                     const int addr = (int)(pick(By, 4 * cls + (si & 3)) >> (8 * (si >> 2)));
                     const uint32_t t = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)K.tfull);
-                    const uint32_t bit = 1u << col, f = (U < t) ? bit : 0u;
+                    const uint32_t neg = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)K.tabv) >> 31;
+                    const uint32_t bit = 1u << col, f = ((U < t) ^ neg) ? bit : 0u;
                     if (row == 0)
-                        ND[0] = (ND[0] & ~bit) | f;
+                        NS[0] = (NS[0] & ~bit) | f;
                     else
-                        ND[1] = (ND[1] & ~bit) | f;
+                        NS[1] = (NS[1] & ~bit) | f;
                 }
             }
         }
-        // new spin = field sign, flipped where U >= t
-        ntop[w] = ~((Sg[0] | (Sg[1] << 1)) ^ ND[0]) & G::full(w);
-        nmid[w] = ~((Sg[2] | (Sg[3] << 1)) ^ ND[1]) & G::full(w);
+        ntop[w] = NS[0] & G::full(w);
+        nmid[w] = NS[1] & G::full(w);
     }
 }
 
