@@ -15,7 +15,9 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcrbm.so")
 
 SOURCES = ["gibbs_aux.hip", "gibbs_tiles_a.hip", "gibbs_tiles_b.hip", "gibbs_tiles_c.hip",
-           "gibbs_tiles_d.hip", "gibbs_tiles_e.hip", "gibbs_tiles_f.hip", "stats.hip", "ar.hip", "lattice.hip", "crbm_api.cpp"]
+           "gibbs_tiles_d.hip", "gibbs_tiles_e.hip", "gibbs_tiles_f.hip", "stats.hip", "ar.hip", "lattice.hip",
+           "lattice_widths_a.hip", "lattice_widths_b.hip", "lattice_widths_c.hip", "lattice_widths_d.hip",
+           "crbm_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

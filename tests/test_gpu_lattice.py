@@ -66,6 +66,24 @@ def test_open_and_mixed_boundaries_bit_exact():
     _check(lats, smp, parts, tr, 0x5EED0000000000F1, S, S, _picks)
 
 
+def test_every_compiled_width_bit_exact():
+    """The sampler is compiled once per even column count 4 .. 64: one handle
+    holds a lattice of every width (4 or 6 rows, the four boundary kinds in
+    turn, random couplings and even/odd fields, 3 chains each), and every
+    instance's first and last chains equal the oracle, spins and counts of
+    every sweep."""
+    rng = np.random.default_rng(17)
+    S, seed = 40, 0x5EED0000000000F6
+    lats = []
+    for k, cols in enumerate(range(4, 66, 2)):
+        lats.append(crbm.Lattice(rows=4 + 2 * (k % 2), cols=cols, J=list(rng.uniform(-1.5, 1.5, 10)),
+                                 h_even=float(rng.uniform(-1, 1)), h_odd=float(rng.uniform(-1, 1)),
+                                 open_rows=bool(k & 1), open_cols=bool(k & 2), n_chains=3,
+                                 sched="linear", T0=2.0, T1=0.4, id=40 + k))
+    smp, parts, tr = _run(lats, seed, S)
+    _check(lats, smp, parts, tr, seed, S, S, lambda I: (0, I.n_chains - 1))
+
+
 @pytest.mark.parametrize("L", [6, 18, 36])
 def test_periodic_square_equals_square_sampler(L):
     """Both axes periodic, J_k = (J1 x 8, J2 x 2), one field: the same
