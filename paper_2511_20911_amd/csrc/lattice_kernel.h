@@ -110,14 +110,18 @@ __host__ __device__ constexpr uint32_t col_edge_terms(int cls) {
     return cls == 0 ? 0x04u : cls == 1 ? 0x12u : cls == 2 ? 0x18u : 0x02u;
 }
 
-// LDS of a workgroup (words):
-//   [kVis, +512)    visible entry of kernel index x = ((cls * 2 + column edge) * 2 + row edge) * 32 + pattern:
-//                   ceil(t / 2^16), plus 2^31 where the entry's field is negative
-//   [kFull, +512)   full threshold t of kernel index x
-//   [kTail, +320)   tied hidden words of the comparison's tail (5 x 64)
-//   [kSpins, ...)   bit rows [Lr][W][64]
-constexpr int kVis = 0, kFull = 512, kTail = 1024, kSpins = 1344;
-__host__ __device__ constexpr int lat_lds_bytes(int Lr, int W) { return (kSpins + Lr * W * 64) * 4; }
+// LDS of a workgroup (words; small enough that 16 workgroups of an 18 x 18
+// lattice fit a compute unit, as many as its registers allow):
+//   [kVis, +512)       visible entry of kernel index x = ((cls * 2 + column edge) * 2 + row edge) * 32
+//                      + pattern: ceil(t / 2^16), plus 2^31 where the entry's field is negative
+//   [kTail, +256)      tied hidden words of the comparison's tail (4 x 64)
+//   [kPlanes, +160 W)  threshold planes of the hidden words, [w][pw][b] (5 words pw of 32 planes b
+//                      per row word w), from the sweep's filter thresholds
+//   [spins(W), ...)    bit rows [Lr][W][64]
+// The full thresholds, needed only by the rare exact path, stay in the global table.
+constexpr int kVis = 0, kTail = 512, kPlanes = 768;
+__host__ __device__ constexpr int lat_spins_word(int W) { return kPlanes + 160 * W; }
+__host__ __device__ constexpr int lat_lds_bytes(int Lr, int W) { return (lat_spins_word(W) + Lr * W * 64) * 4; }
 
 template <int LC>
 struct LGeo {
@@ -152,22 +156,21 @@ __device__ __forceinline__ uint32_t lsh2(const uint32_t (&x)[LGeo<LC>::W], int w
 }
 
 struct LSweep {
-    uint32_t T[10];    // agree thresholds
     uint32_t neg[10];  // all ones if sig_k < 0
     uint32_t en[10];   // all ones if wq_k != 0
 };
 
 // Threshold plane b of hidden word pw of a row word with n cells: units
 // 32 pw .. 32 pw + 31; unit u belongs to filter 2 (u div 2n) + (u mod 2).
-// Wavefront-uniform (scalar registers).
-__device__ __forceinline__ uint32_t filter_plane(const LSweep& K, int n, int pw, int b) {
+// T: the ten filter thresholds.  Built once per table into LDS (kPlanes).
+__device__ __forceinline__ uint32_t filter_plane(const uint32_t* T, int n, int pw, int b) {
     uint32_t t = 0u;
 #pragma unroll
     for (int p = 0; p < 5; ++p) {
         const int lo = 2 * n * p - 32 * pw, hi = 2 * n * (p + 1) - 32 * pw;
         if (hi <= 0 || lo >= 32) continue;
         const uint32_t run = gk::bits_between(lo < 0 ? 0 : lo, hi > 32 ? 32 : hi);
-        t |= run & ((gk::plane_mask(K.T[2 * p], b) & 0x55555555u) | (gk::plane_mask(K.T[2 * p + 1], b) & 0xAAAAAAAAu));
+        t |= run & ((gk::plane_mask(T[2 * p], b) & 0x55555555u) | (gk::plane_mask(T[2 * p + 1], b) & 0xAAAAAAAAu));
     }
     return t;
 }
@@ -176,31 +179,37 @@ __device__ __forceinline__ uint32_t filter_plane(const LSweep& K, int n, int pw,
 // units of hidden word pw: val, units that exist; ag, agreeing units.  Every
 // threshold has its top bit set (t >= 2^31), so plane 0 decides the units of
 // threshold exactly 2^31 (disagreeing bonds, zero fields).
-__device__ __forceinline__ void hidden_head(uint32_t val, uint32_t ag, int n, int pw, const LSweep& K, uint32_t cb,
-                                            uint32_t c3, uint32_t sweep, uint32_t chain, uint32_t k0, uint32_t k1,
-                                            uint32_t& lt, uint32_t& eq) {
+// pl: the word's 32 threshold planes in LDS (the same for every lane).
+__device__ __forceinline__ void hidden_head(uint32_t val, uint32_t ag, const uint32_t* pl, uint32_t cb, uint32_t c3,
+                                            uint32_t sweep, uint32_t chain, uint32_t k0, uint32_t k1, uint32_t& lt,
+                                            uint32_t& eq) {
     P4 p = philox(cb, sweep, chain, c3, k0, k1);
     lt = val & ~p.v[0];
     eq = ag & p.v[0];
-#pragma unroll
-    for (int b = 1; b < 4; ++b) gk::compare_plane(lt, eq, p.v[b], filter_plane(K, n, pw, b));
+    const uint4 t0 = *reinterpret_cast<const uint4*>(pl);
+    gk::compare_plane(lt, eq, p.v[1], t0.y);
+    gk::compare_plane(lt, eq, p.v[2], t0.z);
+    gk::compare_plane(lt, eq, p.v[3], t0.w);
     if (!__any(eq != 0u)) return;
     p = philox(cb | 1u, sweep, chain, c3, k0, k1);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) gk::compare_plane(lt, eq, p.v[s], filter_plane(K, n, pw, 4 + s));
+    const uint4 t1 = *reinterpret_cast<const uint4*>(pl + 4);
+    gk::compare_plane(lt, eq, p.v[0], t1.x);
+    gk::compare_plane(lt, eq, p.v[1], t1.y);
+    gk::compare_plane(lt, eq, p.v[2], t1.z);
+    gk::compare_plane(lt, eq, p.v[3], t1.w);
 }
 
 // The rest of the comparison (planes 8-31) for the NPW hidden words of one
 // row word whose units are still tied: the tied words of the wavefront are
-// ranked (ballot and prefix count) and moved through this wavefront's 5 x 64
+// ranked (ballot and prefix count) and moved through this wavefront's 4 x 64
 // word LDS buffer onto consecutive lanes, up to 64 at a time, which draw their
 // remaining blocks together and hand each word's result back.  Each unit
 // consumes exactly its own planes, in order, so the decisions are those of
 // the full 32-bit comparison; a unit equal to its threshold in all 32 planes
-// is not below it.  A compacted lane takes the threshold planes of its word's
-// pw by selection among the wavefront-uniform ones.
-__device__ __forceinline__ void hidden_tail(int n, int NPW, uint32_t (&lt)[5], uint32_t (&eq)[5], uint32_t cbw,
-                                            const LSweep& K, uint32_t c3, uint32_t sweep, uint32_t chain,
+// is not below it.  A compacted lane reads the threshold planes of its own
+// word from LDS (planes: the row word's [pw][32] planes).
+__device__ __forceinline__ void hidden_tail(int NPW, uint32_t (&lt)[5], uint32_t (&eq)[5], uint32_t cbw,
+                                            const uint32_t* planes, uint32_t c3, uint32_t sweep, uint32_t chain,
                                             uint32_t k0, uint32_t k1, uint32_t* buf, int lane) {
     uint32_t* const b_eq = buf;
     uint32_t* const b_lt = buf + 64;
@@ -237,19 +246,16 @@ __device__ __forceinline__ void hidden_tail(int n, int NPW, uint32_t (&lt)[5], u
             cb = b_cb[lane];
             ch = b_ch[lane];
         }
-        const uint32_t wpw = (cb >> 3) & 7u;
+        const uint32_t* const wpl = planes + 32 * ((cb >> 3) & 7u);
 #pragma unroll 1
         for (int c = 2; c < 8; ++c) {
             if (!__any(e != 0u)) break;
             const P4 p = philox(cb | (uint32_t)c, sweep, ch, c3, k0, k1);
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                uint32_t t = filter_plane(K, n, 0, 4 * c + s);
-#pragma unroll
-                for (int q = 1; q < 5; ++q)
-                    if (q < NPW) t = (wpw == (uint32_t)q) ? filter_plane(K, n, q, 4 * c + s) : t;
-                gk::compare_plane(l, e, p.v[s], t);
-            }
+            const uint4 t = *reinterpret_cast<const uint4*>(wpl + 4 * c);
+            gk::compare_plane(l, e, p.v[0], t.x);
+            gk::compare_plane(l, e, p.v[1], t.y);
+            gk::compare_plane(l, e, p.v[2], t.z);
+            gk::compare_plane(l, e, p.v[3], t.w);
         }
         if (mine) b_lt[lane] = l;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -272,9 +278,9 @@ __device__ __forceinline__ void hidden_tail(int n, int NPW, uint32_t (&lt)[5], u
 template <int LC>
 __device__ __forceinline__ void hidden_row(const uint32_t (&top)[LGeo<LC>::W], const uint32_t (&mid)[LGeo<LC>::W],
                                            const uint32_t (&bot)[LGeo<LC>::W], bool open_c, bool last_row_open,
-                                           const LSweep& K, int i, uint32_t c3, uint32_t sweep, uint32_t chain,
-                                           uint32_t k0, uint32_t k1, uint32_t* tailbuf, int lane,
-                                           uint32_t (&H)[10][LGeo<LC>::W]) {
+                                           const LSweep& K, const uint32_t* planes, int i, uint32_t c3,
+                                           uint32_t sweep, uint32_t chain, uint32_t k0, uint32_t k1,
+                                           uint32_t* tailbuf, int lane, uint32_t (&H)[10][LGeo<LC>::W]) {
     using G = LGeo<LC>;
 #pragma unroll
     for (int w = 0; w < G::W; ++w) {
@@ -315,12 +321,13 @@ __device__ __forceinline__ void hidden_row(const uint32_t (&top)[LGeo<LC>::W], c
         const int NPW = (10 * n + 31) / 32;
         const uint32_t cbw = (uint32_t)(i * G::W + w) << 8;
         uint32_t LT[5] = {0u, 0u, 0u, 0u, 0u}, EQ[5] = {0u, 0u, 0u, 0u, 0u};
+        const uint32_t* const wpl = planes + 160 * w;
 #pragma unroll
         for (int pw = 0; pw < 5; ++pw)
             if (pw < NPW)
-                hidden_head(PP[pw], PA[pw], n, pw, K, cbw | ((uint32_t)pw << 3), c3, sweep, chain, k0, k1, LT[pw],
-                            EQ[pw]);
-        hidden_tail(n, NPW, LT, EQ, cbw, K, c3, sweep, chain, k0, k1, tailbuf, lane);
+                hidden_head(PP[pw], PA[pw], wpl + 32 * pw, cbw | ((uint32_t)pw << 3), c3, sweep, chain, k0, k1,
+                            LT[pw], EQ[pw]);
+        hidden_tail(NPW, LT, EQ, cbw, wpl, c3, sweep, chain, k0, k1, tailbuf, lane);
 #pragma unroll
         for (int p = 0; p < 5; ++p) {
             const int off = 2 * n * p;
@@ -367,7 +374,8 @@ template <int LC, bool DO_MID>
 __device__ __forceinline__ void visible_rows(const uint32_t (&H)[10][LGeo<LC>::W], const uint32_t (&Hp5)[LGeo<LC>::W],
                                              const uint32_t (&Hp7)[LGeo<LC>::W], const uint32_t (&Hp9)[LGeo<LC>::W],
                                              bool open_c, bool redge_top, bool redge_mid, const LSweep& K,
-                                             const uint32_t* lds, int i, bool do_top, bool save, uint32_t c3,
+                                             const uint32_t* lds, const uint32_t* __restrict__ gtab, int i,
+                                             bool do_top, bool save, uint32_t c3,
                                              uint32_t sweep, uint32_t chain, uint32_t k0, uint32_t k1,
                                              uint32_t (&nt)[LGeo<LC>::W], uint32_t (&nm)[LGeo<LC>::W],
                                              P4 (&straddle)[LGeo<LC>::W]) {
@@ -482,7 +490,9 @@ __device__ __forceinline__ void visible_rows(const uint32_t (&H)[10][LGeo<LC>::W
                 if (edge) addr += cedge_off;
                 const uint32_t off = 512u * (uint32_t)cls + addr;
                 const uint32_t v = *reinterpret_cast<const uint32_t*>(tb + 4 * kVis + off);
-                const uint32_t t = *reinterpret_cast<const uint32_t*>(tb + 4 * kFull + off);
+                // the host's entry index ((cls * 2 + row edge) * 2 + column edge) * 32 + pattern
+                const uint32_t x = off >> 2, pat = x & 31u, redge = (x >> 5) & 1u, cedge = (x >> 6) & 1u;
+                const uint32_t t = gtab[kHead + kEntries + ((((uint32_t)cls * 2u + redge) * 2u + cedge) << 5) + pat];
                 const uint32_t U = (gk::slot16(p, s) << 16) | gk::slot16(r, s);
                 const uint32_t bit = 1u << col, f = ((U < t) ^ (v >> 31)) ? bit : 0u;
                 if (row == 0)
@@ -511,7 +521,7 @@ __global__ void __launch_bounds__(64) lattice_kernel(LatArgs a) {
     const int lane = threadIdx.x;
     const int Lr = it.Lr, Cr = it.Lr / 2;
     const bool open_r = it.open_r != 0, open_c = it.open_c != 0;
-    uint32_t* const S = lds + kSpins;  // [Lr][W][64]
+    uint32_t* const S = lds + lat_spins_word(W);  // [Lr][W][64]
     uint32_t* const tailbuf = lds + kTail;
     const bool active = lane < (int)it.nchains;
     const uint32_t chain = it.chain0 + (active ? (uint32_t)lane : 0u);
@@ -535,7 +545,14 @@ __global__ void __launch_bounds__(64) lattice_kernel(LatArgs a) {
                 const bool nonneg = ((tb[kHead + 2 * kEntries + (x >> 5)] >> (x & 31)) & 1u) != 0u;
                 const int kx = ((cls * 2 + cedge) * 2 + redge) * 32 + pat;
                 lds[kVis + kx] = (t >> 16) + ((t & 0xffffu) != 0u) + (nonneg ? 0u : 0x80000000u);
-                lds[kFull + kx] = t;
+            }
+            // the hidden words' threshold planes
+            uint32_t T[10];
+#pragma unroll
+            for (int k = 0; k < 10; ++k) T[k] = tb[k];
+            for (int x = lane; x < W * 160; x += 64) {
+                const int w = x / 160, pw = (x / 32) % 5, b = x % 32;
+                lds[kPlanes + x] = filter_plane(T, w == W - 1 ? G::ML / 2 : 16, pw, b);
             }
             __syncthreads();
             tab_loaded = ts;
@@ -544,7 +561,6 @@ __global__ void __launch_bounds__(64) lattice_kernel(LatArgs a) {
         const uint32_t fneg = tb[10], fen = tb[11];
 #pragma unroll
         for (int k = 0; k < 10; ++k) {
-            K.T[k] = tb[k];
             K.neg[k] = ((fneg >> k) & 1u) ? 0xffffffffu : 0u;
             K.en[k] = ((fen >> k) & 1u) ? 0xffffffffu : 0u;
         }
@@ -566,11 +582,11 @@ __global__ void __launch_bounds__(64) lattice_kernel(LatArgs a) {
                 bot[w] = S[(rb * W + w) * 64 + lane];
             }
             uint32_t H[10][W];
-            hidden_row<LC>(top, mid, bot, open_c, open_r && i == Cr - 1, K, i, c3h, sweep, chain, k0, k1, tailbuf,
-                           lane, H);
+            hidden_row<LC>(top, mid, bot, open_c, open_r && i == Cr - 1, K, lds + kPlanes, i, c3h, sweep, chain, k0,
+                           k1, tailbuf, lane, H);
             uint32_t nt[W], nm[W];
-            visible_rows<LC, true>(H, Hp5, Hp7, Hp9, open_c, false, open_r && i == Cr - 1, K, lds, i, i > 0, i == 0,
-                                   c3v, sweep, chain, k0, k1, nt, nm, straddle);
+            visible_rows<LC, true>(H, Hp5, Hp7, Hp9, open_c, false, open_r && i == Cr - 1, K, lds, tb, i, i > 0,
+                                   i == 0, c3v, sweep, chain, k0, k1, nt, nm, straddle);
 #pragma unroll
             for (int w = 0; w < W; ++w) {
                 if (i > 0) S[((2 * i) * W + w) * 64 + lane] = nt[w];
@@ -588,8 +604,8 @@ __global__ void __launch_bounds__(64) lattice_kernel(LatArgs a) {
                 Hd[0][w] = Hf0[w]; Hd[1][w] = Hf1[w]; Hd[4][w] = Hf4[w]; Hd[6][w] = Hf6[w]; Hd[8][w] = Hf8[w];
                 Hd[2][w] = Hd[3][w] = Hd[5][w] = Hd[7][w] = Hd[9][w] = 0u;
             }
-            visible_rows<LC, false>(Hd, Hp5, Hp7, Hp9, open_c, open_r, false, K, lds, 0, true, false, c3v, sweep,
-                                    chain, k0, k1, nt, nm, straddle);
+            visible_rows<LC, false>(Hd, Hp5, Hp7, Hp9, open_c, open_r, false, K, lds, tb, 0, true, false, c3v,
+                                    sweep, chain, k0, k1, nt, nm, straddle);
 #pragma unroll
             for (int w = 0; w < W; ++w) S[w * 64 + lane] = nt[w];
         }
