@@ -1001,6 +1001,7 @@ __device__ __forceinline__ __bf16 hidden_out(bool first, float z, __bf16 resid) 
 }
 
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));  // a buffer store's 64-bit data
 
 // four consecutive output channels of one pixel / chain (the D layout below)
 __device__ __forceinline__ bf16x4 hidden_out4(bool first, f32x4 z, bf16x4 resid) {
@@ -1270,10 +1271,19 @@ __global__ void __launch_bounds__(256) score_fused_kernel(int64_t n, int L, cons
 // The operand of the (0,-1) tap is the fragment each lane used at the
 // previous site; the taps of the row above come from a one-row ring in global
 // memory, each element read once into a window that slides along the row.
+// Ring accesses are buffer loads and stores: a wavefront-uniform descriptor
+// (this wavefront's slot of a layer and column, or a zero block of the same
+// shape outside the lattice) plus the lane's fixed byte offset, so no address
+// arithmetic runs per access.  Each lane reads the weights from LDS at two
+// base addresses (layers 0-5 and 6-11) plus immediate offsets.
 // The weights of the next layer are loaded while a layer finishes.  Spin i is
 // +1 iff u < up_threshold(logit), u = word 0 of Philox (ctr = (site, step,
 // chain, id << 3 | 6)), decided by the lane that holds the logit at the end of
 // the last layer; the logits go to logit_out for the log q sum.
+// Up to 4 wavefronts per workgroup: one per SIMD.  (The kernel needs about
+// 290 registers per lane; capped at 256 so that two wavefronts share a SIMD
+// it spills inside the layer loop and runs slower: 32768 proposals at 18x18
+// took 7.5 ms against 4.7 ms in two rounds of one wavefront per SIMD.)
 constexpr int kSeqMaxWaves = 4;
 // MH: proposals of several cycles per sampler launch, up to this many chains
 // (1024 wavefronts of 16 chains: one per SIMD) and this many cycles
@@ -1331,26 +1341,42 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
     const __bf16* ring_w = ring + wbase * chain_stride;
     const uint32_t rd_off = (uint32_t)(r16 * chain_stride + kg * 8) * 2;  // bytes: B fragment of the lane
     const uint32_t wr_off = (uint32_t)(r16 * chain_stride + 4 * kg) * 2;  // bytes: D values of the lane (half 0)
-    const uint32_t zr_off = (uint32_t)(kg * 8) * 2;
     auto slot = [&](int l, int c) -> int64_t { return (int64_t)l * ring_layer + (int64_t)c * C; };  // uniform
+    // buffer descriptor of a wavefront-uniform base covering 16 chains' rows (nrec bytes)
+    const int nrec = (int)(16 * chain_stride * 2);
+    auto rsrc = [&](const __bf16* base) {
+        // readfirstlane returns a signed int: widen each half through uint32_t,
+        // or a low half with bit 31 set would fill the high half with ones
+        const uint64_t v = reinterpret_cast<uint64_t>(base);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+        const uint64_t u = ((uint64_t)hi << 32) | (uint64_t)lo;
+        return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(u), (short)0, nrec, 0x00020000);
+    };
     auto fetch = [&](int l, bool inside, int c) -> bf16x8 {  // `inside` is wavefront-uniform
-        const char* src = inside ? reinterpret_cast<const char*>(ring_w + slot(l, c))
-                                 : reinterpret_cast<const char*>(zpad);
-        return *reinterpret_cast<const bf16x8*>(src + (inside ? rd_off : zr_off));
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc(inside ? ring_w + slot(l, c) : zpad), rd_off, 0, 0);
+        return __builtin_bit_cast(bf16x8, v);
     };
     // A fragments of layer l for both halves (the centre tap is masked in the first layer, the last
     // layer has one output channel)
     bf16x8 bw0[NT], bw1[NT];
     f32x4 bj0, bj1;  // biases of the lane's output channels: the accumulators' initial values
+    // this lane's A fragments at two bases, so that every load is a base plus an
+    // immediate offset below 64 KiB (row 16 + r16 is 16 rows after row r16: the
+    // swizzle depends on the row's low bits only)
+    const char* const wb_lo = reinterpret_cast<const char*>(wl + swz(r16, kg));
+    uint32_t hi_off = 2u * 6u * NT * C * C;
+    asm volatile("" : "+v"(hi_off));  // keeps the second base a register of its own
+    const char* const wb_hi = wb_lo + hi_off;
     auto load_w = [&](int l) {
-        const __bf16* Wl = wl + l * NT * C * C;
+        const char* Wl = l < 6 ? wb_lo + 2 * l * NT * C * C : wb_hi + 2 * (l - 6) * NT * C * C;
         bj0 = *reinterpret_cast<const f32x4*>(bl + l * C + 4 * kg);
         bj1 = *reinterpret_cast<const f32x4*>(bl + l * C + 16 + 4 * kg);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const bool used = t < 4 || l > 0;
-            bw0[t] = used ? load8(Wl + t * C * C + swz(r16, kg)) : zero8();
-            bw1[t] = (used && l < NL - 1) ? load8(Wl + t * C * C + swz(16 + r16, kg)) : zero8();
+            bw0[t] = used ? *reinterpret_cast<const bf16x8*>(Wl + 2 * t * C * C) : zero8();
+            bw1[t] = (used && l < NL - 1) ? *reinterpret_cast<const bf16x8*>(Wl + 2 * (t * C * C + 16 * C)) : zero8();
         }
     };
     // B fragments per layer l: the row above at columns c - 1 and c (a
@@ -1375,9 +1401,16 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
         // that hit the cache) instead of being hoisted into registers that
         // every layer must copy
         if (PER_CHAIN) asm volatile("" : "+v"(bl));
-        if (c == 0) {
+        if (c == 0) {  // a row start: no left neighbour; the row above at columns -1 (outside) and 0
 #pragma unroll
             for (int l = 0; l < NL; ++l) left[l] = zero8();
+            if (r > 0) {
+#pragma unroll
+                for (int l = 0; l < NL; ++l) {
+                    up0[l] = zero8();
+                    up1[l] = fetch(l, true, 0);
+                }
+            }
         }
         const gk::P4 q = gk::philox((uint32_t)site, stepr, (uint32_t)gcr, (id << 3) | 6u, (uint32_t)seed,
                                     (uint32_t)(seed >> 32));
@@ -1402,20 +1435,15 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
                 load_w(l + 1);
             else if (more)
                 load_w(0);
-            // slide the window; at a row end refill it with columns -1 (outside) and 0 of this row
-            if (c + 1 < L) {
-                up0[l] = up1[l];
-                up1[l] = pr[l % kAhead];
-            } else if (r + 1 < L) {
-                up0[l] = zero8();
-                up1[l] = fetch(l, true, 0);
-            }
+            // slide the window (a row start refills it)
+            up0[l] = up1[l];
+            up1[l] = pr[l % kAhead];
             if (!last) {
                 const bf16x4 h0 = hidden_out4f(l == 0, acc0, hp0);
                 const bf16x4 h1 = hidden_out4f(l == 0, acc1, hp1);
-                char* dst = reinterpret_cast<char*>(ring + (ring_w - ring) + slot(l + 1, c)) + wr_off;
-                *reinterpret_cast<bf16x4*>(dst) = h0;
-                *reinterpret_cast<bf16x4*>(dst + 32) = h1;
+                const auto rw = rsrc(ring_w + slot(l + 1, c));
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, h0), rw, wr_off, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, h1), rw, wr_off + 32u, 0, 0);
                 hb = regroup(h0, h1);
                 hp0 = widen4(h0);
                 hp1 = widen4(h1);
@@ -1427,8 +1455,8 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
                 bf16x8 s8 = zero8();
                 if (kg == 0) {
                     s8[0] = sg;  // the first layer's input fragment: channel 0 is the spin, the rest 0
-                    *reinterpret_cast<__bf16*>(reinterpret_cast<char*>(ring + (ring_w - ring) + slot(0, c)) +
-                                               wr_off) = sg;
+                    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, sg), rsrc(ring_w + slot(0, c)),
+                                                          wr_off, 0, 0);
                     if (gca < n) {
                         spins[gca * N + site] = (int8_t)bf2f(sg);
                         logit_out[gca * N + site] = x;
@@ -1708,7 +1736,7 @@ struct crbm_ar_s {
     int64_t scap = 0;
     __bf16* ring = nullptr;     // [NL][n][2][L][C]: activations of the last two rows
     float* slogit = nullptr;    // [n][N]
-    __bf16* zpad = nullptr;     // [C] zeros: row-above operand outside the lattice
+    __bf16* zpad = nullptr;     // [16][L][C] zeros: the sampler's row-above operand outside the lattice
     // scoring buffers (capacity in chains): ping-pong activations and logits
     int64_t icap = 0;
     __bf16 *ih0 = nullptr, *ih1 = nullptr;  // [n N][C]
@@ -1991,19 +2019,16 @@ int run_seq(crbm_ar_t* a, int64_t n, int8_t* spins, double* logq, uint64_t seed,
     const int waves = n <= 16 * 256 ? 1 : n <= 32 * 256 ? 2 : kSeqMaxWaves;
     const int per_wg = 16 * waves;
     const dim3 grid((unsigned)((n + per_wg - 1) / per_wg)), block(64 * waves);
-    if (bs.pt) {
-        AR_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&seq_kernel<true>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, kSeqLdsBytes),
+    auto launch = [&](auto kernel) -> int {
+        AR_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   kSeqLdsBytes),
                "sampler LDS size");
-        hipLaunchKernelGGL(seq_kernel<true>, grid, block, kSeqLdsBytes, st, n, npad, L, a->wf, bs.tab, bs.pt,
-                           bs.npts, a->ring, a->zpad, spins, a->slogit, seed, step, id, n_step);
-    } else {
-        AR_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&seq_kernel<false>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, kSeqLdsBytes),
-               "sampler LDS size");
-        hipLaunchKernelGGL(seq_kernel<false>, grid, block, kSeqLdsBytes, st, n, npad, L, a->wf, bs.tab, bs.pt,
-                           bs.npts, a->ring, a->zpad, spins, a->slogit, seed, step, id, n_step);
-    }
+        hipLaunchKernelGGL(kernel, grid, block, kSeqLdsBytes, st, n, npad, L, a->wf, bs.tab, bs.pt, bs.npts, a->ring,
+                           a->zpad, spins, a->slogit, seed, step, id, n_step);
+        return CRBM_OK;
+    };
+    rc = bs.pt ? launch(seq_kernel<true>) : launch(seq_kernel<false>);
+    if (rc != CRBM_OK) return rc;
     hipLaunchKernelGGL(logq_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a->slogit, spins, n, L * L,
                        logq);
     AR_TRY(hipGetLastError(), "sampler kernels");
@@ -2093,14 +2118,14 @@ int crbm_ar_create(const crbm_ar_config* c, crbm_ar_t** out) {
     a->np = a->np_base + (a->cond > 0 ? (int64_t)kCondF * kCondH + kCondH + (int64_t)kCondH * kCondOut : 0);
     if (alloc(&a->theta, a->np) || alloc(&a->grad, a->np) || alloc(&a->m, a->np) || alloc(&a->v, a->np) ||
         alloc(&a->bias, NL * C) || alloc(&a->wf, (int64_t)NL * NT * C * C) || alloc(&a->wb, (int64_t)NL * NT * C * C) ||
-        alloc(&a->zpad, C) ||
+        alloc(&a->zpad, (int64_t)16 * c->L * C) ||
         (a->cond > 0 && (alloc(&a->feats, (int64_t)a->cond * kCondF) || alloc(&a->cb, (int64_t)a->cond * kCondOut) ||
                          alloc(&a->gp, (int64_t)a->cond * kCondOut)))) {
         delete a;
         return fail_ar(CRBM_ENOMEM, "parameter buffers");
     }
     int rc = CRBM_OK;
-    if (hipMemsetAsync(a->zpad, 0, sizeof(__bf16) * C, a->stream) != hipSuccess ||
+    if (hipMemsetAsync(a->zpad, 0, sizeof(__bf16) * 16 * c->L * C, a->stream) != hipSuccess ||
         hipMemsetAsync(a->theta, 0, sizeof(float) * a->np, a->stream) != hipSuccess ||
         hipMemsetAsync(a->m, 0, sizeof(float) * a->np, a->stream) != hipSuccess ||
         hipMemsetAsync(a->v, 0, sizeof(float) * a->np, a->stream) != hipSuccess ||

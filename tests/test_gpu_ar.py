@@ -312,11 +312,12 @@ def test_full_size_proposals_18x18():
         assert ok, ch
 
 
-@pytest.mark.parametrize("L,n,steps", [(6, 40, 3), (18, 17, 2), (6, 8192, 2)])
+@pytest.mark.parametrize("L,n,steps", [(6, 40, 3), (18, 17, 2), (6, 8192, 2), (6, 8192, 4), (18, 8192, 4)])
 def test_sample_steps_equal_separate_calls(L, n, steps):
     """crbm_ar_sample_steps: batch k of one launch equals a launch of that batch
     alone with step step0 + k, bit for bit (spins and log q), for ragged
-    batches and for the 16384-proposal launch of two 8192-chain MH cycles."""
+    batches and for the launches of two and four 8192-chain MH cycles (16384
+    and 32768 proposals: one and two rounds of one wavefront per SIMD)."""
     print(f"case L={L} n={n} steps={steps}", flush=True)
     net = crbm.ARNet(L)
     net.set_params(flatten(ar.init_params(seed=17, scale=INIT_SCALE)))
