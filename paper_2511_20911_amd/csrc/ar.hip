@@ -1001,7 +1001,7 @@ __device__ __forceinline__ __bf16 hidden_out(bool first, float z, __bf16 resid) 
 }
 
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));  // a buffer store's 64-bit data
+typedef unsigned int uint4v __attribute__((ext_vector_type(4)));  // a buffer store's 128-bit data
 
 // four consecutive output channels of one pixel / chain (the D layout below)
 __device__ __forceinline__ bf16x4 hidden_out4(bool first, f32x4 z, bf16x4 resid) {
@@ -1441,10 +1441,11 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
             if (!last) {
                 const bf16x4 h0 = hidden_out4f(l == 0, acc0, hp0);
                 const bf16x4 h1 = hidden_out4f(l == 0, acc1, hp1);
-                const auto rw = rsrc(ring_w + slot(l + 1, c));
-                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, h0), rw, wr_off, 0, 0);
-                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, h1), rw, wr_off + 32u, 0, 0);
                 hb = regroup(h0, h1);
+                // stored as the B fragment: 16 bytes per lane, so one instruction writes each
+                // chain's 64-byte channel row whole (two 8-byte halves each left partial lines)
+                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4v, hb), rsrc(ring_w + slot(l + 1, c)),
+                                                       rd_off, 0, 0);
                 hp0 = widen4(h0);
                 hp1 = widen4(h1);
             } else {
