@@ -1340,7 +1340,6 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
     const int64_t ring_layer = npad * chain_stride;
     const __bf16* ring_w = ring + wbase * chain_stride;
     const uint32_t rd_off = (uint32_t)(r16 * chain_stride + kg * 8) * 2;  // bytes: B fragment of the lane
-    const uint32_t wr_off = (uint32_t)(r16 * chain_stride + 4 * kg) * 2;  // bytes: D values of the lane (half 0)
     auto slot = [&](int l, int c) -> int64_t { return (int64_t)l * ring_layer + (int64_t)c * C; };  // uniform
     // buffer descriptor of a wavefront-uniform base covering 16 chains' rows (nrec bytes)
     const int nrec = (int)(16 * chain_stride * 2);
@@ -1384,7 +1383,17 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
     // end), at column c + 1 (prefetched three layers ahead into slot l % 3),
     // and h_l at the previous site (l = 0: its spin; zero at a row start).
     constexpr int kAhead = 3;
-    bf16x8 up0[NL], up1[NL], left[NL], pr[kAhead];
+    bf16x8 up0[NL], up1[NL], left[NL], pr[kAhead], sv[NL];
+    // ring fragment of layer m at column c: an even column's waits in sv for the odd one
+    auto store_pair = [&](int m, int c, const bf16x8& f, auto par) {
+        if (decltype(par)::value == 0) {
+            sv[m] = f;
+        } else {
+            const auto rw = rsrc(ring_w + slot(m, c - 1));
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4v, sv[m]), rw, rd_off, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4v, f), rw, rd_off + 2u * C, 0, 0);
+        }
+    };
 #pragma unroll
     for (int l = 0; l < NL; ++l) up0[l] = up1[l] = zero8();
 #pragma unroll
@@ -1392,7 +1401,13 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
     f32x4 hp0 = {0.f, 0.f, 0.f, 0.f}, hp1 = hp0;  // h_l of this lane's outputs as floats: the residual inputs
     bf16x8 hb = zero8();                           // h_l as this lane's B fragment: the centre tap's operand
     load_w(0);
-    for (int site = 0; site < N; ++site) {
+    // One site; PAR = its column's parity.  L is even, so the sites of a row
+    // pair up: an even site keeps its layers' ring fragments (sv) and the odd
+    // site after it stores both columns together, each chain's 128-byte line
+    // whole (a column alone left half-written lines, which cost memory-side
+    // reads).  A column is first read a row later, so the delay is safe.
+    auto do_site = [&](int site, auto par) {
+        constexpr int PAR = decltype(par)::value;
         const int r = site / L, c = site - r * L;
         const int sn = site + 1, rn = sn / L, cn = sn - rn * L;
         const bool more = sn < N;
@@ -1442,10 +1457,8 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
                 const bf16x4 h0 = hidden_out4f(l == 0, acc0, hp0);
                 const bf16x4 h1 = hidden_out4f(l == 0, acc1, hp1);
                 hb = regroup(h0, h1);
-                // stored as the B fragment: 16 bytes per lane, so one instruction writes each
-                // chain's 64-byte channel row whole (two 8-byte halves each left partial lines)
-                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4v, hb), rsrc(ring_w + slot(l + 1, c)),
-                                                       rd_off, 0, 0);
+                // the ring keeps the B fragment: 16 bytes per lane, 64 per chain and column
+                store_pair(l + 1, c, hb, par);
                 hp0 = widen4(h0);
                 hp1 = widen4(h1);
             } else {
@@ -1456,13 +1469,12 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
                 bf16x8 s8 = zero8();
                 if (kg == 0) {
                     s8[0] = sg;  // the first layer's input fragment: channel 0 is the spin, the rest 0
-                    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, sg), rsrc(ring_w + slot(0, c)),
-                                                          wr_off, 0, 0);
                     if (gca < n) {
                         spins[gca * N + site] = (int8_t)bf2f(sg);
                         logit_out[gca * N + site] = x;
                     }
                 }
+                store_pair(0, c, s8, par);
                 left[0] = s8;
             }
             wave_sync();  // this layer's ring stores precede every later ring load
@@ -1473,6 +1485,10 @@ __global__ void __launch_bounds__(256) seq_kernel(int64_t n, int64_t npad, int L
             else if (more)
                 pr[l % kAhead] = fetch(l + kAhead - NL, rn > 0 && cn + 1 < L, cn + 1);
         }
+    };
+    for (int site = 0; site < N; site += 2) {
+        do_site(site, std::integral_constant<int, 0>{});
+        do_site(site + 1, std::integral_constant<int, 1>{});
     }
 }
 
