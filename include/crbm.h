@@ -426,6 +426,14 @@ const char* crbm_last_error(void);
  * normally on the next call.  Returns CRBM_OK. */
 int crbm_debug_fail_alloc(int32_t n);
 
+/* Test hook (process-wide): the hidden comparison of the Gibbs samplers
+ * (crbm_sample, crbm_lattice_sample) finishes the words still tied after two
+ * random blocks on at most `cap` lanes per round, 64 by default; a smaller cap
+ * makes every launch from now on take several rounds, a path that 64 lanes
+ * almost never need.  Trajectories do not depend on it.  CRBM_EINVAL unless
+ * 1 <= cap <= 64. */
+int crbm_debug_tail_cap(int32_t cap);
+
 /* Host-side helpers that expose the library's own tables (used by tests to
  * check them against the oracle).
  * crbm_threshold: the 32-bit sigmoid threshold t(y) for an integer field

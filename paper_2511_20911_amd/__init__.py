@@ -161,6 +161,7 @@ def lib() -> ct.CDLL:
         L.crbm_tau_int_noalloc.argtypes = L.crbm_tau_int.argtypes
         L.crbm_get_tiling.argtypes = [ct.c_int32, p(ct.c_int32), p(ct.c_int32)]
         L.crbm_debug_fail_alloc.argtypes = [ct.c_int32]
+        L.crbm_debug_tail_cap.argtypes = [ct.c_int32]
         L.crbm_lattice_create.argtypes = [p(_Lattice), ct.c_int32, p(_Config), p(ct.c_void_p)]
         L.crbm_lattice_sample.argtypes = [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_int32]
         L.crbm_lattice_observables.argtypes = [ct.c_void_p, p(ct.c_int64), ct.c_void_p]
@@ -539,6 +540,12 @@ def debug_fail_alloc(n: int):
     """Make the library's n-th device allocation from now on fail (n < 0: disarm);
     for tests of the error paths."""
     _check(lib().crbm_debug_fail_alloc(int(n)))
+
+
+def debug_tail_cap(cap: int):
+    """Lanes per round of the Gibbs samplers' compacted hidden tail (64; a
+    smaller cap forces several rounds, for tests; trajectories do not change)."""
+    _check(lib().crbm_debug_tail_cap(int(cap)))
 
 
 def ss_filters(J1: float, J2: float):

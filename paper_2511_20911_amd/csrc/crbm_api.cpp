@@ -49,6 +49,18 @@ extern "C" int crbm_debug_fail_alloc(int32_t n) {
     return CRBM_OK;
 }
 
+namespace {
+std::atomic<uint32_t> g_tail_cap{64u};
+}
+
+uint32_t crbmlib::tail_cap() { return g_tail_cap.load(); }
+
+extern "C" int crbm_debug_tail_cap(int32_t cap) {
+    if (cap < 1 || cap > 64) return crbmlib::set_error(CRBM_EINVAL, "the tail cap must be 1 .. 64");
+    g_tail_cap.store((uint32_t)cap);
+    return CRBM_OK;
+}
+
 int crbmlib::set_error(int code, const char* msg) {
     g_err = msg ? msg : "";
     return code;
@@ -272,6 +284,7 @@ GibbsArgs make_args(const crbm_s* h, const Group& g, size_t gi, int64_t s0, int6
     a.queue = (h->cfg.launch_mode == CRBM_LAUNCH_GRAPH && !direct) ? h->d_queue + gi : nullptr;
     a.waves_per_block = g.wpb;
     a.grid_blocks = g.grid_blocks;
+    a.tail_cap = tail_cap();
     return a;
 }
 

@@ -50,6 +50,7 @@ struct GibbsArgs {
     uint32_t* queue;          // persistent mode: work counter (zeroed before launch); nullptr = direct
     int32_t waves_per_block;  // 1..4 (0 = 4)
     int32_t grid_blocks;      // persistent mode: blocks in the grid
+    uint32_t tail_cap;        // lanes per round of the hidden comparison's compacted tail (1..64)
 };
 
 // What the learned-proposal code needs from a Gibbs handle.
@@ -79,6 +80,10 @@ int handle_view(crbm_t* h, HandleView* v, int i);
 double map_schedule_T(int kind, double T0, double T1, const double* Te, int64_t S, int64_t s);
 void map_hidden_weight(int64_t Jq, double T, int64_t* wq, int* sig);
 uint32_t map_threshold(int64_t y);
+
+// Lanes per round of the compacted tail of the hidden comparison (64; fewer
+// only when crbm_debug_tail_cap has set them, to exercise the multi-round path).
+uint32_t tail_cap();
 
 // Every device allocation of the library goes through dev_alloc, which fails
 // with hipErrorOutOfMemory when crbm_debug_fail_alloc has armed it (tests of

@@ -240,14 +240,18 @@ __device__ __forceinline__ void hidden_compare_head(uint32_t val, uint32_t ag, u
 // in place would run each further block on all 64 lanes while any lane of the
 // wavefront is tied.  Instead the tied words of the wavefront are ranked
 // (ballot and prefix count) and moved through this wavefront's 5 x 64 word
-// LDS buffer onto consecutive lanes, up to 64 at a time, which draw their
-// remaining blocks together and hand each word's result back.  Every unit
-// still consumes exactly its own planes, in order, so the decisions are those
-// of the full 32-bit comparison.  A unit equal to its threshold in all 32
+// LDS buffer onto consecutive lanes, up to cap at a time, which draw their
+// remaining blocks together and hand each word's result back; words ranked
+// beyond cap wait for the next round.  cap is 64 in sampling (a test hook
+// lowers it to force several rounds); ranks start at 64 - cap, so that the
+// test against the buffer's end stays a constant.  Every unit still consumes
+// exactly its own planes, in order, so the decisions are those of the full
+// 32-bit comparison.  A unit equal to its threshold in all 32
 // planes is not below it.
 __device__ __forceinline__ void hidden_compare_tail(int NPW, uint32_t (&lt)[5], uint32_t (&eq)[5],
-                                                    const uint32_t (&j2)[5], uint32_t cbw, const SweepK& K, uint32_t c3, const Rng& rg,
+                                                    const uint32_t (&j2)[5], uint32_t cbw, uint32_t cap, const SweepK& K, uint32_t c3, const Rng& rg,
                                                     uint32_t* buf, int lane) {
+    const uint32_t first = 64u - cap;  // buffer entries below first stay unused
     uint32_t* const b_eq = buf;
     uint32_t* const b_lt = buf + 64;
     uint32_t* const b_cb = buf + 128;
@@ -255,7 +259,7 @@ __device__ __forceinline__ void hidden_compare_tail(int NPW, uint32_t (&lt)[5], 
     uint32_t* const b_j2 = buf + 256;
     for (;;) {
         int slot[5] = {-1, -1, -1, -1, -1};
-        uint32_t n = 0u;  // tied words ranked so far (wavefront-uniform)
+        uint32_t n = first;  // next buffer entry: first + tied words ranked so far (wavefront-uniform)
 #pragma unroll
         for (int pw = 0; pw < 5; ++pw) {
             if (pw >= NPW) continue;
@@ -273,11 +277,11 @@ __device__ __forceinline__ void hidden_compare_tail(int NPW, uint32_t (&lt)[5], 
             }
             n += (uint32_t)__popcll(bal);
         }
-        if (n == 0u) return;
+        if (n == first) return;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const bool mine = (uint32_t)lane < n;
+        const bool mine = (uint32_t)lane - first < n - first;  // first <= lane < n
         uint32_t e = 0u, l = 0u, cb = 0u, ch = 0u, jm = 0u;
         if (mine) {
             e = b_eq[lane];
@@ -313,8 +317,8 @@ __device__ __forceinline__ void hidden_compare_tail(int NPW, uint32_t (&lt)[5], 
 template <int L>
 __device__ __forceinline__ void hidden_row(const uint32_t (&top)[Geo<L>::W], const uint32_t (&mid)[Geo<L>::W],
                                            const uint32_t (&bot)[Geo<L>::W], const SweepK& K, uint32_t i,
-                                           uint32_t c3, const Rng& rg, uint32_t* tailbuf, int lane,
-                                           uint32_t (&H)[10][Geo<L>::W]) {
+                                           uint32_t c3, const Rng& rg, uint32_t* tailbuf, uint32_t tail_cap,
+                                           int lane, uint32_t (&H)[10][Geo<L>::W]) {
     using G = Geo<L>;
 #pragma unroll
     for (int w = 0; w < G::W; ++w) {
@@ -357,7 +361,7 @@ __device__ __forceinline__ void hidden_row(const uint32_t (&top)[Geo<L>::W], con
                 hidden_compare_head(VAL[pw], PA[pw], J2[pw], K, cbw | ((uint32_t)pw << 3), c3, rg, LT[pw], EQ[pw]);
             }
         }
-        hidden_compare_tail(NPW, LT, EQ, J2, cbw, K, c3, rg, tailbuf, lane);
+        hidden_compare_tail(NPW, LT, EQ, J2, cbw, tail_cap, K, c3, rg, tailbuf, lane);
         uint32_t DP[NPWMAX] = {0u, 0u, 0u, 0u, 0u};  // units at or above their threshold
 #pragma unroll
         for (int pw = 0; pw < NPWMAX; ++pw) DP[pw] = VAL[pw] & ~LT[pw];
@@ -503,7 +507,8 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
 }
 
 // One work item: up to 64/G chains of one instance, all sweeps [s0, s1).
-template <int L, int R>
+// CAP: the tail takes a.tail_cap words per round (else the constant 64).
+template <int L, int R, bool CAP>
 __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, int lane, uint32_t* tailbuf) {
     using Gm = Geo<L>;
     constexpr int W = Gm::W;
@@ -550,7 +555,7 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
         for (int m = 0; m < R; ++m) {
             const uint32_t i = (uint32_t)(g * R + m);
             uint32_t H[10][W];
-            hidden_row<L>(Q[0], Q[1], Q[2], K, i, c3h, rg, tailbuf, lane, H);
+            hidden_row<L>(Q[0], Q[1], Q[2], K, i, c3h, rg, tailbuf, CAP ? a.tail_cap : 64u, lane, H);
             uint32_t nt[W], nm[W];
             visible_row<L>(H, Hp5, Hp7, Hp9, K, m > 0, true, i, c3v, rg, nt, nm, straddle);
 #pragma unroll
@@ -731,7 +736,7 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
 // per lane and one wavefront per SIMD; asking for two trades a few spilled
 // values for the latency hiding of a second wavefront (measured: 96x96 runs
 // 1.6x faster, 72x72 1.5x).
-template <int L, int R>
+template <int L, int R, bool CAP>
 __global__ void __launch_bounds__(256, (Geo<L>::W >= 3 ? 2 : 1)) gibbs_kernel(GibbsArgs a) {
     const int lane = threadIdx.x & 63;
     // per wavefront: the tied hidden words of the comparison's tail (5 x 64 words)
@@ -740,7 +745,7 @@ __global__ void __launch_bounds__(256, (Geo<L>::W >= 3 ? 2 : 1)) gibbs_kernel(Gi
     if (a.queue == nullptr) {
         const int wv = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
         if (wv >= a.n_items) return;
-        gibbs_item<L, R>(a, a.items[wv], lane, tailbuf);
+        gibbs_item<L, R, CAP>(a, a.items[wv], lane, tailbuf);
         return;
     }
     for (;;) {
@@ -748,7 +753,7 @@ __global__ void __launch_bounds__(256, (Geo<L>::W >= 3 ? 2 : 1)) gibbs_kernel(Gi
         if (lane == 0) next = atomicAdd(a.queue, 1u);
         next = __builtin_amdgcn_readfirstlane(next);
         if (next >= (uint32_t)a.n_items) return;
-        gibbs_item<L, R>(a, a.items[next], lane, tailbuf);
+        gibbs_item<L, R, CAP>(a, a.items[next], lane, tailbuf);
     }
 }
 
@@ -758,14 +763,19 @@ hipError_t launch_tile(const GibbsArgs& a, hipStream_t st) {
     int blocks = (a.n_items + wpb - 1) / wpb;
     if (a.queue != nullptr && a.grid_blocks > 0 && a.grid_blocks < blocks) blocks = a.grid_blocks;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((gibbs_kernel<L, R>), dim3(blocks), dim3(64 * wpb), 0, st, a);
+    if (a.tail_cap < 64u)
+        hipLaunchKernelGGL((gibbs_kernel<L, R, true>), dim3(blocks), dim3(64 * wpb), 0, st, a);
+    else
+        hipLaunchKernelGGL((gibbs_kernel<L, R, false>), dim3(blocks), dim3(64 * wpb), 0, st, a);
     return hipGetLastError();
 }
 
-// Kernel function pointer and block size, for explicit graph nodes.
+// Kernel function pointer, for explicit graph nodes (the variant that the
+// current tail cap selects).
 template <int L, int R>
 const void* kernel_ptr() {
-    return reinterpret_cast<const void*>(&gibbs_kernel<L, R>);
+    if (tail_cap() < 64u) return reinterpret_cast<const void*>(&gibbs_kernel<L, R, true>);
+    return reinterpret_cast<const void*>(&gibbs_kernel<L, R, false>);
 }
 
 }  // namespace gk

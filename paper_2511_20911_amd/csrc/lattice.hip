@@ -188,6 +188,7 @@ LatArgs lat_args(const crbm_lat_s* h, int x, int64_t s0, int64_t s1, int8_t* spi
     a.total_chains = h->total_chains;
     a.spins_out = spins_out;
     a.corr = h->d_corr;
+    a.tail_cap = tail_cap();
     return a;
 }
 

@@ -82,6 +82,7 @@ struct LatArgs {
     int64_t total_chains;
     int8_t* spins_out;
     unsigned long long* corr;   // Cn sums of every instance, or nullptr
+    uint32_t tail_cap;          // lanes per round of the hidden comparison's compacted tail (1..64)
 };
 
 // Visible terms of each sublattice class (0: even row even col, 1: even row
@@ -202,22 +203,26 @@ __device__ __forceinline__ void hidden_head(uint32_t val, uint32_t ag, const uin
 // The rest of the comparison (planes 8-31) for the NPW hidden words of one
 // row word whose units are still tied: the tied words of the wavefront are
 // ranked (ballot and prefix count) and moved through this wavefront's 4 x 64
-// word LDS buffer onto consecutive lanes, up to 64 at a time, which draw their
-// remaining blocks together and hand each word's result back.  Each unit
+// word LDS buffer onto consecutive lanes, up to cap at a time, which draw
+// their remaining blocks together and hand each word's result back; words
+// ranked beyond cap wait for the next round.  cap is 64 in sampling (a test
+// hook lowers it to force several rounds); ranks start at 64 - cap, so that
+// the test against the buffer's end stays a constant.  Each unit
 // consumes exactly its own planes, in order, so the decisions are those of
 // the full 32-bit comparison; a unit equal to its threshold in all 32 planes
 // is not below it.  A compacted lane reads the threshold planes of its own
 // word from LDS (planes: the row word's [pw][32] planes).
 __device__ __forceinline__ void hidden_tail(int NPW, uint32_t (&lt)[5], uint32_t (&eq)[5], uint32_t cbw,
-                                            const uint32_t* planes, uint32_t c3, uint32_t sweep, uint32_t chain,
-                                            uint32_t k0, uint32_t k1, uint32_t* buf, int lane) {
+                                            uint32_t cap, const uint32_t* planes, uint32_t c3, uint32_t sweep,
+                                            uint32_t chain, uint32_t k0, uint32_t k1, uint32_t* buf, int lane) {
+    const uint32_t first = 64u - cap;  // buffer entries below first stay unused
     uint32_t* const b_eq = buf;
     uint32_t* const b_lt = buf + 64;
     uint32_t* const b_cb = buf + 128;
     uint32_t* const b_ch = buf + 192;
     for (;;) {
         int slot[5] = {-1, -1, -1, -1, -1};
-        uint32_t cnt = 0u;  // tied words ranked so far (wavefront-uniform)
+        uint32_t cnt = first;  // next buffer entry: first + tied words ranked so far (wavefront-uniform)
 #pragma unroll
         for (int pw = 0; pw < 5; ++pw) {
             if (pw >= NPW) continue;
@@ -234,11 +239,11 @@ __device__ __forceinline__ void hidden_tail(int NPW, uint32_t (&lt)[5], uint32_t
             }
             cnt += (uint32_t)__popcll(bal);
         }
-        if (cnt == 0u) return;
+        if (cnt == first) return;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const bool mine = (uint32_t)lane < cnt;
+        const bool mine = (uint32_t)lane - first < cnt - first;  // first <= lane < cnt
         uint32_t e = 0u, l = 0u, cb = 0u, ch = 0u;
         if (mine) {
             e = b_eq[lane];
@@ -280,7 +285,8 @@ __device__ __forceinline__ void hidden_row(const uint32_t (&top)[LGeo<LC>::W], c
                                            const uint32_t (&bot)[LGeo<LC>::W], bool open_c, bool last_row_open,
                                            const LSweep& K, const uint32_t* planes, int i, uint32_t c3,
                                            uint32_t sweep, uint32_t chain, uint32_t k0, uint32_t k1,
-                                           uint32_t* tailbuf, int lane, uint32_t (&H)[10][LGeo<LC>::W]) {
+                                           uint32_t* tailbuf, uint32_t tail_cap, int lane,
+                                           uint32_t (&H)[10][LGeo<LC>::W]) {
     using G = LGeo<LC>;
 #pragma unroll
     for (int w = 0; w < G::W; ++w) {
@@ -327,7 +333,7 @@ __device__ __forceinline__ void hidden_row(const uint32_t (&top)[LGeo<LC>::W], c
             if (pw < NPW)
                 hidden_head(PP[pw], PA[pw], wpl + 32 * pw, cbw | ((uint32_t)pw << 3), c3, sweep, chain, k0, k1,
                             LT[pw], EQ[pw]);
-        hidden_tail(NPW, LT, EQ, cbw, wpl, c3, sweep, chain, k0, k1, tailbuf, lane);
+        hidden_tail(NPW, LT, EQ, cbw, tail_cap, wpl, c3, sweep, chain, k0, k1, tailbuf, lane);
 #pragma unroll
         for (int p = 0; p < 5; ++p) {
             const int off = 2 * n * p;
@@ -512,7 +518,8 @@ __device__ __forceinline__ int wave_sum(int v) {
     return v;
 }
 
-template <int LC>
+// CAP: the hidden tail takes a.tail_cap words per round (else the constant 64).
+template <int LC, bool CAP>
 __global__ void __launch_bounds__(64) lattice_kernel(LatArgs a) {
     using G = LGeo<LC>;
     constexpr int W = G::W;
@@ -583,7 +590,7 @@ __global__ void __launch_bounds__(64) lattice_kernel(LatArgs a) {
             }
             uint32_t H[10][W];
             hidden_row<LC>(top, mid, bot, open_c, open_r && i == Cr - 1, K, lds + kPlanes, i, c3h, sweep, chain, k0,
-                           k1, tailbuf, lane, H);
+                           k1, tailbuf, CAP ? a.tail_cap : 64u, lane, H);
             uint32_t nt[W], nm[W];
             visible_rows<LC, true>(H, Hp5, Hp7, Hp9, open_c, false, open_r && i == Cr - 1, K, lds, tb, i, i > 0,
                                    i == 0, c3v, sweep, chain, k0, k1, nt, nm, straddle);
@@ -717,7 +724,10 @@ __global__ void __launch_bounds__(64) lattice_kernel(LatArgs a) {
 // wavefront with `lds` bytes of dynamic LDS.
 template <int LC>
 hipError_t launch_width(const LatArgs& a, int lds, hipStream_t st) {
-    hipLaunchKernelGGL(lattice_kernel<LC>, dim3((unsigned)a.n_items), dim3(64), lds, st, a);
+    if (a.tail_cap < 64u)
+        hipLaunchKernelGGL((lattice_kernel<LC, true>), dim3((unsigned)a.n_items), dim3(64), lds, st, a);
+    else
+        hipLaunchKernelGGL((lattice_kernel<LC, false>), dim3((unsigned)a.n_items), dim3(64), lds, st, a);
     return hipGetLastError();
 }
 

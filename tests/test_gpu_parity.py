@@ -417,3 +417,38 @@ def test_autotune_picks_a_valid_tiling():
     r, w, rate = crbm.autotune(18, n_chains=1024, n_sweeps=20)
     assert 9 % r == 0 and 1 <= w <= 4 and rate > 0
     assert crbm.get_tiling(18) == (r, w)
+
+
+@pytest.mark.parametrize("cap", [1, 5])
+def test_compacted_tail_in_several_rounds_is_bit_exact(cap):
+    """The hidden comparison finishes the words still tied after two random
+    blocks on at most `cap` lanes per round (crbm_debug_tail_cap); with 64
+    lanes a second round almost never happens, so here the cap forces several
+    per launch.  Square lattices of one, two and three words per row and a
+    general lattice with open edges still equal the oracle bit for bit."""
+    seed, S = 0x5EED0000000000C1, 60
+    insts = [crbm.Instance(L=18, J1=1.0, J2=1.0, h=3.0, n_chains=64, sched="geometric", T0=5.0, T1=0.2, id=1),
+             crbm.Instance(L=48, J1=1.0, J2=0.5, h=1.0, n_chains=20, sched="linear", T0=3.0, T1=0.3, id=2),
+             crbm.Instance(L=96, J1=1.0, J2=2.0, h=0.5, n_chains=5, sched="const", T0=0.8, id=3)]
+    lat = crbm.Lattice(rows=12, cols=18, J=[1.0, 0.8, -0.6, 1.2, 0.9, -1.1, 0.5, 1.4, 1.3, -0.7], h_even=0.4,
+                       h_odd=-0.2, open_cols=True, n_chains=70, sched="const", T0=0.9, id=4)
+    crbm.debug_tail_cap(cap)
+    try:
+        smp, parts, tr = _run_gpu(insts, seed, S)
+        lsmp = crbm.LatticeSampler([lat], seed=seed, n_sweeps=S)
+        lspins = torch.empty(lsmp.total_spins, dtype=torch.int8, device="cuda")
+        lsmp.sample(S, spins_out=lspins)
+        torch.cuda.synchronize()
+    finally:
+        crbm.debug_tail_cap(64)
+    for k, I in enumerate(insts):
+        _check_chains(I, parts[k], tr, int(smp.chain_offsets[k]), seed, S, (0, I.n_chains - 1))
+    got = lsmp.split_spins(lspins)[0].cpu().numpy()
+    ol = oracle.Lattice(12, 18, lat.J, 0.4, -0.2, open_c=True, T0=0.9, id=4)
+    for ch in (0, 69):
+        s, _, _ = oracle.run_lattice_chain(ol, S, seed, ch, 0, S)
+        assert np.array_equal(got[ch], s), ch
+    with pytest.raises(crbm.CrbmError):
+        crbm.debug_tail_cap(0)
+    with pytest.raises(crbm.CrbmError):
+        crbm.debug_tail_cap(65)
