@@ -99,6 +99,72 @@ def profile_fields():
     return {k: float(v) for k, v in fields.items() if k != "kernel_sources_sha256_12"}
 
 
+COPY_MIB = 1024  # the plain device copy that calibrates FETCH_SIZE and WRITE_SIZE
+
+
+def pmc_kib(db, counter, kernel_prefix):
+    """KiB that `counter` reads for the largest dispatch of the kernel whose
+    name contains kernel_prefix and for the largest __amd_rocclr_copyBuffer
+    dispatch (the calibration copy), from a rocprofv3 --pmc results database."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    per = {}
+    for name, ctr, disp, val in con.execute(
+            "select kernel_name, counter_name, dispatch_id, value from counters_collection"):
+        if ctr != counter:
+            continue
+        key = ("kernel" if kernel_prefix in name else "copy" if "__amd_rocclr_copyBuffer" in name else None)
+        if key is not None:
+            per[(key, disp)] = per.get((key, disp), 0.0) + float(val)
+    con.close()
+    kern = [v for (k, _), v in per.items() if k == "kernel"]
+    copy = [v for (k, _), v in per.items() if k == "copy"]
+    if not kern or not copy:
+        raise RuntimeError(f"{counter}: no {kernel_prefix!r} or copy dispatch in {db}")
+    return max(kern), max(copy)
+
+
+def measure_traffic(rows, wpb, timeout=240):
+    """HBM bytes of one launch of the 18x18 Gibbs kernel, measured now: two
+    child runs of this script under rocprofv3 --pmc (FETCH_SIZE, then
+    WRITE_SIZE), each holding one full launch of the same tiling and a plain
+    1 GiB device copy; each counter is scaled by the bytes the copy moves
+    over what it reads for the copy.  Returns (bytes, detail)."""
+    import glob
+    import shutil
+    import signal
+    import subprocess
+    exe = shutil.which("rocprofv3") or "/opt/rocm/bin/rocprofv3"
+    out_root = os.path.join(ROOT, "gpurun_out", "bench_pmc")
+    kname = f"gibbs_kernel<{L}, {rows}"
+    res = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        d = os.path.join(out_root, ctr)
+        shutil.rmtree(d, ignore_errors=True)
+        cmd = [exe, "--pmc", ctr, "-d", d, "-o", "pmc", "--", sys.executable, os.path.join(ROOT, "bench.py"),
+               "--headline-only", "--no-cpu-baseline", "--tiling", f"{rows},{wpb}", "--detail-out=",
+               "--steps", "1", "--warmup", "0", "--copy-mib", str(COPY_MIB), "--traffic", "off"]
+        proc = subprocess.Popen(cmd, cwd="/tmp", env=dict(os.environ, TMPDIR="/tmp"), start_new_session=True,
+                                stdout=subprocess.DEVNULL, stderr=subprocess.PIPE)
+        try:
+            _, err = proc.communicate(timeout=timeout)
+        except subprocess.TimeoutExpired:
+            os.killpg(proc.pid, signal.SIGKILL)
+            proc.wait()
+            raise RuntimeError(f"rocprofv3 --pmc {ctr}: no result within {timeout} s")
+        dbs = glob.glob(os.path.join(d, "**", "*results.db"), recursive=True)
+        if not dbs:
+            tail = err.decode(errors="replace").strip().splitlines()[-3:]
+            raise RuntimeError(f"rocprofv3 --pmc {ctr} (exit {proc.returncode}) wrote no database: {tail}")
+        res[ctr] = pmc_kib(dbs[0], ctr, kname)
+    (fk, fc), (wk, wc) = res["FETCH_SIZE"], res["WRITE_SIZE"]
+    copy_kib = COPY_MIB * 1024.0
+    f_scale, w_scale = copy_kib / fc, copy_kib / wc
+    traffic = (fk * f_scale + wk * w_scale) * 1024.0
+    return traffic, {"fetch_kib": _r(fk, 7), "write_kib": _r(wk, 7), "fetch_scale": _r(f_scale, 4),
+                     "write_scale": _r(w_scale, 4)}
+
+
 def _oracle_worker(job):
     """One host process of the CPU baseline: full-schedule oracle chains of
     the 18x18 workload (a list of (point index, chain)).  Returns the final
@@ -522,6 +588,79 @@ def _r(x, n=4):
     return float(f"{x:.{n}g}") if x == x and abs(x) != float("inf") else None
 
 
+def headline_result(step_ms, kern_ms, chains, n_sweeps, n_points, rows, wpb, tuning, create_ms, prof, steps,
+                    warmup):
+    """The result line's headline fields from the measured step and kernel
+    times (ms): value = median-step throughput, roofline of the Gibbs kernel
+    from its mean HIP-event time, counter figures (prof) scaled to that
+    speed."""
+    import statistics
+    ms = float(statistics.median(step_ms))
+    spin_sweeps = chains * n_sweeps * L * L
+    value = spin_sweeps / (ms / 1e3)
+    kms = float(sum(kern_ms) / len(kern_ms))
+    kernel_rate = spin_sweeps / (kms / 1e3)
+    achieved = kernel_rate * OPS_LAZY
+    roofline = {
+        "bound": "alu",
+        "achieved": achieved / 1e12,
+        "peak": ALU_PEAK_OPS / 1e12,
+        "unit": "TOP/s",
+        "frac": achieved / ALU_PEAK_OPS,
+        "traffic": None,
+        "kernel": f"gibbs_kernel<{L},{rows}>",
+        "kernel_ms": kms,
+        "work_model": "lazy_exact",
+        "ops_per_spin_sweep": {"lazy_exact": OPS_LAZY, "slot16": OPS_SLOT16, "uniform32": OPS_U32},
+        "frac_by_model": {"lazy_exact": _r(achieved / ALU_PEAK_OPS, 3),
+                          "slot16": _r(kernel_rate * OPS_SLOT16 / ALU_PEAK_OPS, 3),
+                          "uniform32": _r(kernel_rate * OPS_U32 / ALU_PEAK_OPS, 3)},
+    }
+    if prof:
+        # issued VALU lane instructions per spin-sweep and the LDS (ds_bpermute)
+        # bytes, from the SQ counters of the same kernel, at this run's speed
+        if "valu_lane_insts_per_spin_sweep" in prof:
+            v = prof["valu_lane_insts_per_spin_sweep"]
+            roofline["valu_lane_insts_per_spin_sweep"] = v
+            roofline["valu_issue_frac"] = _r(kernel_rate * v / ALU_PEAK_OPS, 3)
+        if "lds_bytes_per_spin_sweep" in prof:
+            lb = prof["lds_bytes_per_spin_sweep"]
+            roofline["lds"] = {"achieved": _r(kernel_rate * lb / 1e12, 3), "peak": LDS_PEAK_BPS / 1e12,
+                               "unit": "TB/s", "frac": _r(kernel_rate * lb / LDS_PEAK_BPS, 3)}
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "spin-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": "SS Ising 18x18 periodic, J1=1, J2/J1 in {0.5,1.0,1.5,2.0} x 16 h/J1 in [0,3], "
+                        "4096 chains per point (262144 chains), geometric anneal T 5.0->0.05 over 10^4 sweeps, "
+                        "16.16 fixed point, seeded +-1 start",
+            "L": L, "points": n_points, "chains": chains, "sweeps": n_sweeps,
+            "node_updates_per_s": value * 3.5,
+            "step_ms_min_max": [min(step_ms), max(step_ms)],
+            "create_and_tables_ms": create_ms,
+            "tiling": {"rows_per_lane": rows, "lanes_per_chain": (L // 2) // rows, "waves_per_block": wpb,
+                       "autotuned": tuning is not None},
+        },
+        "roofline": roofline,
+    }
+    return result
+
+
+def final_line(result):
+    """The one compact JSON line that ends the run."""
+    return json.dumps(result, separators=(",", ":"))
+
+
 def summarise(legs):
     """A few numbers per leg for the final result line (the full tables go to
     the detail file)."""
@@ -599,6 +738,10 @@ def main():
     ap.add_argument("--legs", type=str, default="",
                     help="comma-separated legs to run after the headline (batched_uneven, scale, tts, precision, "
                          "phase_map, confined, raw_filters, learned_mh, learned_mh_points); default: all")
+    ap.add_argument("--traffic", choices=("live", "profile", "off"), default="live",
+                    help="HBM traffic of the headline kernel: measured now by two rocprofv3 --pmc child runs "
+                         "(live), taken from the committed profile while its kernel sources match (profile), "
+                         "or not reported")
     ap.add_argument("--detail-out", type=str, default=os.path.join("gpurun_out", "bench_detail.json"),
                     help="file for the full per-leg tables ('' = none)")
     args = ap.parse_args()
@@ -664,66 +807,10 @@ def main():
             kern_ms.append(k0.elapsed_time(k1))
         print(f"# step {it}: {(t_end - t_start) * 1e3:.1f} ms", flush=True)
 
-    chains = smp.total_chains
-    ms = float(np.median(step_ms))
-    spin_sweeps = chains * n_sweeps * L * L
-    value = spin_sweeps / (ms / 1e3)
-    kms = float(np.mean(kern_ms))
-    kernel_rate = spin_sweeps / (kms / 1e3)
-    achieved = kernel_rate * OPS_LAZY
     prof = profile_fields() if n_sweeps == S else {}
-    roofline = {
-        "bound": "alu",
-        "achieved": achieved / 1e12,
-        "peak": ALU_PEAK_OPS / 1e12,
-        "unit": "TOP/s",
-        "frac": achieved / ALU_PEAK_OPS,
-        "traffic": prof.get("traffic_bytes_per_launch"),
-        "kernel": f"gibbs_kernel<{L},{rows}>",
-        "kernel_ms": kms,
-        "work_model": "lazy_exact",
-        "ops_per_spin_sweep": {"lazy_exact": OPS_LAZY, "slot16": OPS_SLOT16, "uniform32": OPS_U32},
-        "frac_by_model": {"lazy_exact": _r(achieved / ALU_PEAK_OPS, 3),
-                          "slot16": _r(kernel_rate * OPS_SLOT16 / ALU_PEAK_OPS, 3),
-                          "uniform32": _r(kernel_rate * OPS_U32 / ALU_PEAK_OPS, 3)},
-    }
-    if prof:
-        # issued VALU lane instructions per spin-sweep and the LDS (ds_bpermute)
-        # bytes, from the SQ counters of the same kernel, at this run's speed
-        if "valu_lane_insts_per_spin_sweep" in prof:
-            v = prof["valu_lane_insts_per_spin_sweep"]
-            roofline["valu_lane_insts_per_spin_sweep"] = v
-            roofline["valu_issue_frac"] = _r(kernel_rate * v / ALU_PEAK_OPS, 3)
-        if "lds_bytes_per_spin_sweep" in prof:
-            lb = prof["lds_bytes_per_spin_sweep"]
-            roofline["lds"] = {"achieved": _r(kernel_rate * lb / 1e12, 3), "peak": LDS_PEAK_BPS / 1e12,
-                               "unit": "TB/s", "frac": _r(kernel_rate * lb / LDS_PEAK_BPS, 3)}
-    result = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "spin-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {
-            "workload": "SS Ising 18x18 periodic, J1=1, J2/J1 in {0.5,1.0,1.5,2.0} x 16 h/J1 in [0,3], "
-                        "4096 chains per point (262144 chains), geometric anneal T 5.0->0.05 over 10^4 sweeps, "
-                        "16.16 fixed point, seeded +-1 start",
-            "L": L, "points": len(insts), "chains": chains, "sweeps": n_sweeps,
-            "node_updates_per_s": value * 3.5,
-            "step_ms_min_max": [min(step_ms), max(step_ms)],
-            "create_and_tables_ms": create_ms,
-            "tiling": {"rows_per_lane": rows, "lanes_per_chain": (L // 2) // rows, "waves_per_block": wpb,
-                       "autotuned": tuning is not None},
-        },
-        "roofline": roofline,
-    }
+    result = headline_result(step_ms, kern_ms, smp.total_chains, n_sweeps, len(insts), rows, wpb, tuning, create_ms,
+                             prof, args.steps, args.warmup)
+    roofline = result["roofline"]
     detail = {"headline": dict(result)}
     if obs is not None:
         E = np.array([o["E_per_spin"] for o in obs]).reshape(4, 16)
@@ -737,6 +824,23 @@ def main():
         parity = all(np.array_equal(parts[i][ch].numpy(), s) for (i, ch), s in finals.items())
     del smp
     torch.cuda.empty_cache()
+
+    # HBM traffic of the same launch: counters of two child runs while this
+    # process is idle (skipped when this run is itself under a profiler)
+    under_profiler = any(k.startswith("ROCPROF_") for k in os.environ)
+    if n_sweeps == S and args.traffic == "live" and not under_profiler:
+        t = time.perf_counter()
+        try:
+            tb, tinfo = measure_traffic(rows, wpb)
+            roofline["traffic"] = tb
+            roofline["traffic_source"] = dict(tinfo, how="rocprofv3 --pmc, this run")
+        except Exception as exc:  # reported, and the committed figure (if current) stands in
+            print(f"# traffic: live measurement failed: {exc}", flush=True)
+            roofline["traffic_error"] = str(exc)[:200]
+        print(f"# traffic: {time.perf_counter() - t:.1f} s", flush=True)
+    if roofline["traffic"] is None and args.traffic != "off" and "traffic_bytes_per_launch" in prof:
+        roofline["traffic"] = prof["traffic_bytes_per_launch"]
+        roofline["traffic_source"] = {"how": "committed rocprofv3 profile of the same kernel sources"}
 
     legs = {}
     def leg(name, fn):
@@ -781,7 +885,7 @@ def main():
         with open(args.detail_out, "w") as f:
             json.dump(detail, f, indent=1)
         result["detail_file"] = args.detail_out
-    print(json.dumps(result, separators=(",", ":")), flush=True)
+    print(final_line(result), flush=True)
 
 
 if __name__ == "__main__":
