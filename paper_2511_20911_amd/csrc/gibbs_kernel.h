@@ -150,7 +150,8 @@ __device__ __forceinline__ SweepK load_sweep(const uint32_t* tb, int lane) {
     const uint32_t tv = tb[3 + l];
     K.tfull = tv;
     const uint32_t kge = (l & 1) ? K.kge[1] : K.kge[0];  // a select: no runtime index into K
-    K.tabv = (tv >> 16) + ((tv & 0xffffu) != 0u) + (((uint32_t)(l >> 1) >= kge) ? 0u : 0x80000000u);
+    // tc - 1 with tc = ceil(t / 2^16) >= 2^15 (t >= 2^31: the threshold of |x|), so bit 31 is the sign alone
+    K.tabv = (tv >> 16) + ((tv & 0xffffu) != 0u) - 1u + (((uint32_t)(l >> 1) >= kge) ? 0u : 0x80000000u);
     return K;
 }
 
@@ -381,6 +382,16 @@ __device__ __forceinline__ void hidden_row(const uint32_t (&top)[Geo<L>::W], con
     }
 }
 
+// Minimum of the low 16 bits of three registers (v_min3_u16 reads the low
+// halves; only the low half of the result is meaningful).  Written out
+// because the compiler packs 16-bit minima into pairs with byte permutes,
+// which costs more than the two inputs per instruction this takes.
+__device__ __forceinline__ uint32_t min3_u16(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t d;
+    asm("v_min3_u16 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 // Visible half-step of the two rows of cell row i (Eq. (12)).  H: hidden
 // planes of this cell row; Hp5/Hp7/Hp9: planes 5, 7, 9 of the cell row above.
 // Classes: 0 top even, 1 top odd, 2 mid even, 3 mid odd columns.
@@ -457,7 +468,12 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
                 p = philox(cbase | (uint32_t)blk, rg.sweep, rg.chain, c3p, rg.k0, rg.k1);
                 if (shared && do_mid && !do_top) straddle[w] = p;
             }
-            uint64_t tie = 0;
+            // r of each slot (0xffff where a slot is absent or its row not
+            // updated): a tie is a zero low half, found by a 16-bit minimum
+            // over the block, two slots per instruction
+            uint32_t rv[8];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) rv[s] = 0xffffu;
 #pragma unroll
             for (int s = 7; s >= 0; --s) {
                 const int q = blk * 8 + s;
@@ -469,10 +485,14 @@ __device__ __forceinline__ void visible_row(const uint32_t (&H)[10][Geo<L>::W], 
                     const uint32_t v = (uint32_t)__builtin_amdgcn_ds_bpermute((int)addr, (int)K.tabv);
                     const uint32_t r = slot16(p, s) - v;  // sign bit: the new spin
                     NS[row] = __builtin_amdgcn_alignbit(NS[row], r, 31);
-                    tie |= __ballot((uint16_t)r == 0xffffu);
+                    rv[s] = r;
                 }
             }
-            if (tie) tieblk |= 1u << blk;
+            const int ns = NQ - blk * 8 < 8 ? NQ - blk * 8 : 8;  // slots of this block (compile time)
+            uint32_t low = ns > 1 ? min3_u16(rv[ns - 1], rv[ns - 1], rv[ns - 2]) : rv[0];
+#pragma unroll
+            for (int s = ns - 3; s >= 0; s -= 2) low = min3_u16(low, rv[s], rv[s > 0 ? s - 1 : 0]);
+            if (__ballot((uint16_t)low == 0u)) tieblk |= 1u << blk;
         }
         // Rare path: a primary slot P = tc - 1; redo the affected blocks with
         // the refinement stream and exact 32-bit compares (the new spin is
