@@ -431,8 +431,10 @@ __device__ __forceinline__ void visible_rows(const uint32_t (&H)[10][LGeo<LC>::W
         const uint32_t cbase = (uint32_t)(i * G::W + w) << 5;
         uint32_t NS[2] = {0u, 0u};
         uint32_t tieblk = 0u;
-        // one slot: the new spin is the sign bit of P - entry; P = tc - 1 flags the exact path
-        auto spin = [&](const P4& p, int s, int q, uint64_t& tie) {
+        // one slot: outside a tie the new spin is the sign bit of P - entry;
+        // a tie (P = tc - 1) leaves a zero low half, kept in rv[s] for the
+        // block's 16-bit minimum
+        auto spin = [&](const P4& p, int s, int q, uint32_t (&rv)[8]) {
             const int row = q / m, col = q % m, cls = 2 * row + (col & 1);
             const int si = col >> 1;
             const uint32_t by = (row == 0 ? ByT[4 * (cls & 1) + (si & 3)] : ByM[4 * (cls & 1) + (si & 3)]);
@@ -442,7 +444,7 @@ __device__ __forceinline__ void visible_rows(const uint32_t (&H)[10][LGeo<LC>::W
             const uint32_t v = *reinterpret_cast<const uint32_t*>(tb + 4 * kVis + 512 * cls + addr);
             const uint32_t r = gk::slot16(p, s) - v;
             NS[row] = __builtin_amdgcn_alignbit(NS[row], r, 31);
-            tie |= __ballot((uint16_t)r == 0xffffu);
+            rv[s] = r;
         };
 #pragma unroll
         for (int blk = 7; blk >= 0; --blk) {
@@ -457,22 +459,28 @@ __device__ __forceinline__ void visible_rows(const uint32_t (&H)[10][LGeo<LC>::W
                 p = philox(cbase | (uint32_t)blk, sweep, chain, c3, k0, k1);
                 if (shared && save) straddle[w] = p;
             }
-            uint64_t tie = 0;
+            uint32_t rv[8];  // 0xffff where a slot is absent or its row not updated
+#pragma unroll
+            for (int s = 0; s < 8; ++s) rv[s] = 0xffffu;
             if (DO_MID) {
 #pragma unroll
                 for (int s = 7; s >= 0; --s) {
                     const int q = blk * 8 + s;
-                    if (q < NQ && q >= m) spin(p, s, q, tie);
+                    if (q < NQ && q >= m) spin(p, s, q, rv);
                 }
             }
             if (has_top && do_top) {
 #pragma unroll
                 for (int s = 7; s >= 0; --s) {
                     const int q = blk * 8 + s;
-                    if (q < m) spin(p, s, q, tie);
+                    if (q < m) spin(p, s, q, rv);
                 }
             }
-            if (tie) tieblk |= 1u << blk;
+            const int ns = NQ - blk * 8 < 8 ? NQ - blk * 8 : 8;  // slots of this block (compile time)
+            uint32_t low = ns > 1 ? gk::min3_u16(rv[ns - 1], rv[ns - 1], rv[ns - 2]) : rv[0];
+#pragma unroll
+            for (int s = ns - 3; s >= 0; s -= 2) low = gk::min3_u16(low, rv[s], rv[s > 0 ? s - 1 : 0]);
+            if (__ballot((uint16_t)low == 0u)) tieblk |= 1u << blk;
         }
         // Rare path: a primary slot P = tc - 1; redo the affected blocks with
         // the refinement stream and exact 32-bit compares (the new spin is
@@ -551,7 +559,8 @@ __global__ void __launch_bounds__(64) lattice_kernel(LatArgs a) {
                 const uint32_t t = tb[kHead + kEntries + x];
                 const bool nonneg = ((tb[kHead + 2 * kEntries + (x >> 5)] >> (x & 31)) & 1u) != 0u;
                 const int kx = ((cls * 2 + cedge) * 2 + redge) * 32 + pat;
-                lds[kVis + kx] = (t >> 16) + ((t & 0xffffu) != 0u) + (nonneg ? 0u : 0x80000000u);
+                // tc - 1, tc = ceil(t / 2^16) >= 2^15 (t: the threshold of |x|), then the sign in bit 31
+                lds[kVis + kx] = (t >> 16) + ((t & 0xffffu) != 0u) - 1u + (nonneg ? 0u : 0x80000000u);
             }
             // the hidden words' threshold planes
             uint32_t T[10];
