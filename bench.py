@@ -323,6 +323,10 @@ def learned_mh(crbm, torch, temps=(0.4, 0.2, 0.1), steps=800, cycles=500):
                        "time, seeded +-1 start, first 20% discarded",
            "reference": "exact <E>/N by 12x12 row transfer matrix",
            "ess": "energy ESS (ess_per_s) and min over {energy, O_1/3 = max |S(q*)|^2/N^2} (ess_min_per_s)",
+           "sectors": "moves between the six degenerate plateau ground states (orientation and phase of the "
+                      "larger structure-factor amplitude), which E and O_1/3 do not see: 1024 chains from the "
+                      "same equilibrated states, 100 steps each, untimed; per chain and second at the timed "
+                      "comparison's cycle and sweep times (sector_moves_per_chain_s: [learned, gibbs])",
            "points": []}
     for T in temps:
         t0 = time.perf_counter()
@@ -351,6 +355,14 @@ def learned_mh(crbm, torch, temps=(0.4, 0.2, 0.1), steps=800, cycles=500):
                   "final_loss_per_site": loss,
                   "ess_ratio": r["learned"]["ess_per_s"] / r["gibbs"]["ess_per_s"],
                   "ess_min_ratio": r["learned"]["ess_min_per_s"] / r["gibbs"]["ess_min_per_s"]})
+        # tunnelling between the six degenerate plateau ground states (untimed,
+        # 1024 chains), as sector changes per chain and second of each sampler
+        sec = learned.sector_moves(net, L, 1.0, 1.0, 3.0, T)
+        sec["learned"]["per_chain_per_s"] = sec["learned"]["changes_per_chain_step"] / (
+            r["learned"]["ms_per_cycle"] / 1e3)
+        sec["gibbs"]["per_chain_per_s"] = sec["gibbs"]["changes_per_chain_step"] / (
+            r["gibbs"]["us_per_sweep"] * r["learned"]["gibbs_per_mh"] / 1e6)
+        r["sectors"] = sec
         out["points"].append(r)
         del net
         torch.cuda.empty_cache()
@@ -680,7 +692,9 @@ def summarise(legs):
                               "ess_ratio": _r(p["ess_ratio"], 3), "ess_min_ratio": _r(p["ess_min_ratio"], 3),
                               "bias_se_learned": _r(p["learned"]["bias_se"], 2),
                               "bias_se_gibbs": _r(p["gibbs"]["bias_se"], 2), "train_s": _r(p["train_s"], 3),
-                              "train_step_ms": _r(p["train_step_ms"], 3), "train_frac_bf16": _r(p["train_frac_bf16"], 3)}
+                              "train_step_ms": _r(p["train_step_ms"], 3), "train_frac_bf16": _r(p["train_frac_bf16"], 3),
+                              "sector_moves_per_chain_s": [_r(p["sectors"][k]["per_chain_per_s"], 3)
+                                                           for k in ("learned", "gibbs")] if "sectors" in p else None}
                              for p in m["points"]]
     c = legs.get("learned_mh_points")
     if c:
@@ -714,7 +728,7 @@ def summarise(legs):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5, help="timed steps (the value is their median)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-chains", type=int, default=4, help="oracle chains per host process in the CPU baseline")

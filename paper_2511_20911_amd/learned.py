@@ -16,7 +16,10 @@ and moves data between device tensors:
   plain Gibbs given the same wall-clock time, both from the same seeded start,
   with tau_int / ESS of the energy and of the plateau order parameter
   O_1/3 = max |S(q*)|^2 / N^2 (q* = (pi, 2pi/3), (2pi/3, pi); Sec. III.B) from
-  the library's estimator.
+  the library's estimator;
+* sector_moves: how often each sampler moves a chain between the plateau's
+  six degenerate ground states (plateau_sectors, from the phases of the two
+  structure-factor amplitudes), which E and O_1/3 cannot see.
 
 Many points at once (the phase-boundary workloads): one conditional network
 (bias offsets from an MLP of each point's features) serves every point of a
@@ -147,6 +150,94 @@ def compare(net: ARNet, L, J1, J2, h, T, n_chains=8192, cycles=500, gibbs_per_mh
                   **gibbs.__dict__, "ess_per_s": gibbs.ess / t_g, "ess_min_per_s": gibbs.ess_min / t_g,
                   "tau_unit": f"{trace_every} sweeps"},
     }
+
+
+def plateau_sectors(spins, threshold=0.05):
+    """Ordering sector of each configuration [n, L, L] (+-1; L a multiple of
+    6) on the 1/3 plateau, from the two structure-factor amplitudes of Sec.
+    III.B Eq. (13): S_A = sum s(r, c) e^{i(pi r + 2 pi c / 3)} and S_B = sum
+    s(r, c) e^{i(2 pi r / 3 + pi c)}.  Returns (orientation, phase, ordered):
+    0 where |S_A| >= |S_B| else 1, the argument of the larger amplitude, and
+    whether max |S|^2 / N^2 reaches `threshold` (an ordered state has about
+    1/3, a disordered one about 1/N).  The six plateau ground states (three
+    translations by two columns or rows, and the transpose) differ in
+    orientation or by 2 pi / 3 in phase."""
+    import numpy as np
+    s = np.asarray(spins, dtype=np.float64)
+    n, L = s.shape[0], s.shape[1]
+    r = np.arange(L)[:, None]
+    c = np.arange(L)[None, :]
+    pa = np.exp(1j * (np.pi * r + 2.0 * np.pi * c / 3.0))
+    pb = np.exp(1j * (2.0 * np.pi * r / 3.0 + np.pi * c))
+    flat = s.reshape(n, L * L)
+    sa = flat @ pa.reshape(-1)
+    sb = flat @ pb.reshape(-1)
+    orient = (np.abs(sb) > np.abs(sa)).astype(np.int8)
+    amp = np.where(orient == 0, sa, sb)
+    order = np.abs(amp) ** 2 / float(L * L) ** 2
+    return orient, np.angle(amp), order >= threshold
+
+
+def sector_changes(prev, cur):
+    """Per chain, whether the ordering sector changed between two
+    plateau_sectors results: both states ordered, and a different
+    orientation or a phase step of more than pi / 3 (sectors are 2 pi / 3
+    apart; thermal fluctuations of an ordered state move the phase far less)."""
+    import numpy as np
+    o0, p0, k0 = prev
+    o1, p1, k1 = cur
+    dp = np.angle(np.exp(1j * (p1 - p0)))
+    return k0 & k1 & ((o0 != o1) | (np.abs(dp) > np.pi / 3.0))
+
+
+def sector_moves(net: ARNet, L, J1, J2, h, T, n_chains=1024, warm_cycles=40, steps=100, gibbs_per_mh=10,
+                 seed=777, id=0):
+    """Tunnelling between the plateau's degenerate ground states, which the
+    energy and O_1/3 do not see (both are the same in all six).  Learned MH
+    runs warm_cycles cycles from a seeded start; plain Gibbs then starts from
+    the same states (its own seed), and both run `steps` steps: one cycle
+    (gibbs_per_mh sweeps + one MH step) or gibbs_per_mh sweeps.  After every
+    step each chain's sector is taken from its state on the host.  Returns,
+    per sampler, sector changes per chain and step, the fraction of chains
+    that changed sector at least once, and the mean fraction of ordered
+    states.  Untimed: the per-second rates follow from the timed comparison's
+    cycle and sweep times."""
+    import numpy as np
+    import torch
+    inst = Instance(L=L, J1=J1, J2=J2, h=h, n_chains=n_chains, sched="const", T0=T, id=id)
+    total = (warm_cycles + steps) * gibbs_per_mh
+    mh = Sampler([inst], seed=seed, n_sweeps=total)
+    sample_mh(mh, net, warm_cycles, gibbs_per_mh)
+    start, idx = mh.get_state()
+    gb = Sampler([inst], seed=seed + 1, n_sweeps=total)
+    gb.set_state(start, idx)
+
+    def host(sp):
+        return sp.view(n_chains, L, L).cpu().numpy()
+
+    out = {}
+    for name in ("learned", "gibbs"):
+        prev = plateau_sectors(host(start))
+        moved = np.zeros(n_chains, dtype=np.int64)
+        ordered = float(prev[2].mean())
+        for _ in range(steps):
+            if name == "learned":
+                sample_mh(mh, net, 1, gibbs_per_mh)
+                sp, _ = mh.get_state()
+            else:
+                gb.sample(gibbs_per_mh)
+                sp, _ = gb.get_state()
+            cur = plateau_sectors(host(sp))
+            moved += sector_changes(prev, cur)
+            ordered += float(cur[2].mean())
+            prev = cur
+        out[name] = {"changes_per_chain_step": float(moved.mean()) / steps,
+                     "chains_changed": float((moved > 0).mean()),
+                     "ordered_fraction": ordered / (steps + 1)}
+    torch.cuda.synchronize()
+    out.update({"steps": steps, "chains": n_chains, "warm_cycles": warm_cycles,
+                "step": f"learned: {gibbs_per_mh} Gibbs sweeps + 1 MH step; gibbs: {gibbs_per_mh} sweeps"})
+    return out
 
 
 # ---------------------------------------------------------------- many points, one conditional network
