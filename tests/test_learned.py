@@ -64,6 +64,26 @@ def test_init_params_statistics():
 
 
 @pytest.mark.gpu
+def test_learned_mh_moves_between_degenerate_plateau_states_12x12():
+    """12x12 on the 1/3 plateau at T = 0.2: from the same ordered states,
+    learned MH moves most chains between the six degenerate ground states
+    (sectors of learned.plateau_sectors) within 60 cycles, while 600 plain
+    Gibbs sweeps move at most a tenth as many: what the trained proposal
+    gains where E and O_1/3 cannot tell the states apart."""
+    L, T = 12, 0.2
+    data = learned.training_set(L, 1.0, 1.0, 3.0, T, n_chains=1024, anneal_sweeps=4000, snapshots=64)
+    net = crbm.ARNet(L, seed=4)
+    net.init_params(seed=4, scale=0.5)
+    learned.train(net, data, steps=400, batch=512)
+    del data
+    r = learned.sector_moves(net, L, 1.0, 1.0, 3.0, T, n_chains=512, warm_cycles=30, steps=60)
+    lm, gb = r["learned"], r["gibbs"]
+    assert lm["ordered_fraction"] > 0.9 and gb["ordered_fraction"] > 0.9, r
+    assert lm["chains_changed"] > 0.5 and lm["changes_per_chain_step"] > 0.1, r
+    assert gb["changes_per_chain_step"] <= 0.1 * lm["changes_per_chain_step"], r
+
+
+@pytest.mark.gpu
 def test_trained_proposal_samples_plateau_6x6():
     """6x6 at (J2, h, T) = (1, 3, 0.4): trained on Gibbs samples, learned MH
     (1 MH : 10 Gibbs) reproduces the exact <E>/N of the transfer matrix within
