@@ -742,7 +742,7 @@ def main():
     ap.add_argument("--no-mh", action="store_true", help="skip the learned-MH vs Gibbs ESS comparison")
     ap.add_argument("--no-scale", action="store_true", help="skip the 48x48 / 96x96 Gibbs measurement")
     ap.add_argument("--no-c5-mh", action="store_true", help="skip the conditional learned-MH comparison at 48x48")
-    ap.add_argument("--c5-mh-96", action="store_true", help="also run the conditional learned-MH comparison at 96x96")
+    ap.add_argument("--no-c5-mh-96", action="store_true", help="skip the conditional learned-MH comparison at 96x96")
     ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution runs at the four phase points")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the m(h) comparison of the default and the hardware precision")
@@ -882,7 +882,7 @@ def main():
     if want("learned_mh_points", args.no_c5_mh):
         def c5():
             r = {"48": learned_points(crbm, torch, 48)}
-            if args.c5_mh_96:
+            if not args.no_c5_mh_96:
                 r["96"] = learned_points(crbm, torch, 96, steps=200, cycles=20)
             return r
         leg("learned_mh_points", c5)
