@@ -306,7 +306,19 @@ int build_graph(crbm_s* h) {
         p.extra = nullptr;
         HIP_TRY(hipGraphAddKernelNode(&reset, h->graph, nullptr, 0, &p), "graph reset node");
     }
+    // Nodes in decreasing order of work (chains x L^2): the process has a few
+    // hardware queues (four by default), so only that many nodes run at once
+    // and the rest wait for one to end; the largest sizes start together, the
+    // smallest fill the queues as they free up, and the longest kernel, whose
+    // grid fills the machine, ends the launch alone on the whole device.
+    std::vector<size_t> order(h->groups.size());
+    std::vector<double> work(h->groups.size(), 0.0);
     for (size_t gi = 0; gi < h->groups.size(); ++gi) {
+        order[gi] = gi;
+        for (const Item& it : h->groups[gi].items) work[gi] += (double)it.nchains * it.L * it.L;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return work[x] > work[y]; });
+    for (const size_t gi : order) {
         Group& g = h->groups[gi];
         GibbsArgs a = make_args(h, g, gi, 0, 0, nullptr, nullptr);
         void* args[] = {&a};
