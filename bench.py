@@ -226,6 +226,39 @@ def cpu_baseline(chains_per_proc=4, max_procs=16):
                       f"schedule each, {wall:.1f} s wall"}, finals
 
 
+def c1_leg(crbm, torch):
+    """The 6x6 job (36 spins): J1 = 1, J2/J1 = 0.5, h = 0, 256 chains, linear
+    anneal T 3.0 -> 0.1 over 2000 sweeps, seed 0x5EED...01.  A tiny job, so
+    its figure is latency: wall time of create (tables, seeded start) + the
+    2000 sweeps + the exact observables of the last sweep, median of five
+    runs after a warm-up, and the device time of the sweeps (HIP events).
+    The final state is the Neel state of this point (E/N = -1.75, m = 0)."""
+    import statistics
+    I = crbm.Instance(L=6, J1=1.0, J2=0.5, h=0.0, n_chains=256, sched="linear", T0=3.0, T1=0.1, id=0)
+    wall, dev, obs = [], [], None
+    for k in range(6):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        smp = crbm.Sampler([I], seed=0x5EED000000000001, n_sweeps=2000, measure_every=1, burn_in=1999)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        stream = torch.cuda.current_stream()
+        e0.record(stream)
+        smp.sample(2000)
+        e1.record(stream)
+        obs = smp.observables()[0]
+        t1 = time.perf_counter()
+        if k > 0:
+            wall.append((t1 - t0) * 1e3)
+            dev.append(e0.elapsed_time(e1))
+        smp.close()
+    work = 256 * 2000 * 36
+    return {"workload": "SS Ising 6x6, J2/J1 = 0.5, h = 0, 256 chains, linear T 3.0 -> 0.1 over 2000 sweeps",
+            "latency_ms": statistics.median(wall), "sweeps_device_ms": statistics.median(dev),
+            "spin_updates_per_s": work / (statistics.median(dev) / 1e3),
+            "E_per_spin": obs["E_per_spin"], "m": obs["m"], "abs_m": obs["abs_m"]}
+
+
 def batched_uneven(crbm, torch):
     """Uneven batch (2048 instances, L in {6..48}, 256 chains, 5000 sweeps at
     fixed T) in one hipGraph launch of persistent kernels."""
@@ -677,6 +710,10 @@ def summarise(legs):
     """A few numbers per leg for the final result line (the full tables go to
     the detail file)."""
     out = {}
+    c1 = legs.get("c1")
+    if c1:
+        out["c1"] = {"latency_ms": _r(c1["latency_ms"], 3), "sweeps_device_ms": _r(c1["sweeps_device_ms"], 3),
+                     "E_per_spin": _r(c1["E_per_spin"], 5), "m": _r(c1["m"], 3)}
     b = legs.get("batched_uneven")
     if b:
         out["batched_uneven"] = {"spin_updates_per_s": _r(b["spin_updates_per_s"]), "ms": _r(b["ms"]),
@@ -750,7 +787,7 @@ def main():
                     help="skip the phase map, the confined-lattice S(q) scan and the general-lattice kernel timing")
     ap.add_argument("--headline-only", action="store_true", help="skip every leg but the headline")
     ap.add_argument("--legs", type=str, default="",
-                    help="comma-separated legs to run after the headline (batched_uneven, scale, tts, precision, "
+                    help="comma-separated legs to run after the headline (c1, batched_uneven, scale, tts, precision, "
                          "phase_map, confined, raw_filters, learned_mh, learned_mh_points); default: all")
     ap.add_argument("--traffic", choices=("live", "profile", "off"), default="live",
                     help="HBM traffic of the headline kernel: measured now by two rocprofv3 --pmc child runs "
@@ -863,6 +900,8 @@ def main():
         print(f"# leg {name}: {time.perf_counter() - t:.1f} s", flush=True)
     only = set(x for x in args.legs.split(",") if x)
     want = lambda name, off: (name in only) if only else not off  # noqa: E731
+    if want("c1", args.no_batched):
+        leg("c1", lambda: c1_leg(crbm, torch))
     if want("batched_uneven", args.no_batched):
         leg("batched_uneven", lambda: batched_uneven(crbm, torch))
     if want("scale", args.no_scale):

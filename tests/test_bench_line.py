@@ -31,6 +31,7 @@ def _all_legs():
           "points_agreeing_within_3se": 64, "points": [{}] * 64}
     conf = {"points": [{"S_max_off_gamma": X} for _ in range(6)]}
     return {
+        "c1": {"latency_ms": X * 1e2, "sweeps_device_ms": X * 10, "E_per_spin": -1.75 + X / 1e5, "m": X / 1e3},
         "batched_uneven": {"spin_updates_per_s": X * 1e12, "ms": X * 1e3, "load_balance_efficiency": X},
         "scale": {"sizes": [{"L": 48, "spin_updates_per_s": X * 1e12}, {"L": 96, "spin_updates_per_s": X * 1e12}]},
         "learned_mh": {"points": [_mh_point(T) for T in (0.4, 0.2, 0.1)]},
