@@ -717,7 +717,8 @@ def summarise(legs):
     b = legs.get("batched_uneven")
     if b:
         out["batched_uneven"] = {"spin_updates_per_s": _r(b["spin_updates_per_s"]), "ms": _r(b["ms"]),
-                                 "load_balance_efficiency": _r(b["load_balance_efficiency"], 3)}
+                                 "load_balance_efficiency": _r(b["load_balance_efficiency"], 3),
+                                 "frac": _r(b["spin_updates_per_s"] * OPS_LAZY / ALU_PEAK_OPS, 3)}
     s = legs.get("scale")
     if s:
         out["scale"] = {str(x["L"]): _r(x["spin_updates_per_s"]) for x in s["sizes"]}
