@@ -722,6 +722,7 @@ def summarise(legs):
     s = legs.get("scale")
     if s:
         out["scale"] = {str(x["L"]): _r(x["spin_updates_per_s"]) for x in s["sizes"]}
+        out["scale"]["frac"] = {str(x["L"]): _r(x["spin_updates_per_s"] * OPS_LAZY / ALU_PEAK_OPS, 3) for x in s["sizes"]}
     m = legs.get("learned_mh")
     if m:
         out["learned_mh"] = [{"T": p["T"], "acceptance": _r(p["learned"]["acceptance"], 3),
