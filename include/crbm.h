@@ -429,9 +429,10 @@ int crbm_debug_fail_alloc(int32_t n);
 /* Test hook (process-wide): the hidden comparison of the Gibbs samplers
  * (crbm_sample, crbm_lattice_sample) finishes the words still tied after two
  * random blocks on at most `cap` lanes per round, 64 by default; a smaller cap
- * makes every launch from now on take several rounds, a path that 64 lanes
- * almost never need.  Trajectories do not depend on it.  CRBM_EINVAL unless
- * 1 <= cap <= 64. */
+ * makes the launches from now on take several rounds, a path that 64 lanes
+ * almost never need (direct launches, and the graph of a handle created in
+ * graph mode after the call: a graph keeps the kernel it was built with).
+ * Trajectories do not depend on it.  CRBM_EINVAL unless 1 <= cap <= 64. */
 int crbm_debug_tail_cap(int32_t cap);
 
 /* Host-side helpers that expose the library's own tables (used by tests to

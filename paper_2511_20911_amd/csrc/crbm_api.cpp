@@ -221,6 +221,7 @@ struct Group {
     std::vector<Item> items;
     Item* d_items = nullptr;
     hipGraphNode_t node = nullptr;
+    const void* fn = nullptr;  // the kernel of the graph node (per-call updates keep it)
 };
 
 }  // namespace
@@ -323,7 +324,8 @@ int build_graph(crbm_s* h) {
         GibbsArgs a = make_args(h, g, gi, 0, 0, nullptr, nullptr);
         void* args[] = {&a};
         hipKernelNodeParams p{};
-        p.func = const_cast<void*>(gibbs_kernel_fn(g.L, g.R));
+        g.fn = gibbs_kernel_fn(g.L, g.R);
+        p.func = const_cast<void*>(g.fn);
         const int items_blocks = (int)((g.items.size() + g.wpb - 1) / g.wpb);
         p.gridDim = dim3((unsigned)std::max(1, std::min(items_blocks, g.grid_blocks)));
         p.blockDim = dim3((unsigned)(64 * g.wpb));
@@ -609,7 +611,7 @@ int crbm_sample_thinned(crbm_t* h, int64_t n_sweeps, int8_t* spins_out, int32_t*
                 make_args(h, g, gi, h->cur, h->cur + n_sweeps, spins_out, counts_trace, trace_every, order_trace);
             void* args[] = {&a};
             hipKernelNodeParams p{};
-            p.func = const_cast<void*>(gibbs_kernel_fn(g.L, g.R));
+            p.func = const_cast<void*>(g.fn);
             const int items_blocks = (int)((g.items.size() + g.wpb - 1) / g.wpb);
             p.gridDim = dim3((unsigned)std::max(1, std::min(items_blocks, g.grid_blocks)));
             p.blockDim = dim3((unsigned)(64 * g.wpb));

@@ -438,11 +438,18 @@ def test_compacted_tail_in_several_rounds_is_bit_exact(cap):
         lsmp = crbm.LatticeSampler([lat], seed=seed, n_sweeps=S)
         lspins = torch.empty(lsmp.total_spins, dtype=torch.int8, device="cuda")
         lsmp.sample(S, spins_out=lspins)
+        # the same instances in one graph launch, built while the cap is set
+        gsmp = crbm.Sampler(insts, seed=seed, n_sweeps=S, launch="graph")
+        gspins = torch.empty(gsmp.total_spins, dtype=torch.int8, device="cuda")
+        gsmp.sample(S, spins_out=gspins)
         torch.cuda.synchronize()
     finally:
         crbm.debug_tail_cap(64)
     for k, I in enumerate(insts):
         _check_chains(I, parts[k], tr, int(smp.chain_offsets[k]), seed, S, (0, I.n_chains - 1))
+    gparts = [p.cpu().numpy() for p in gsmp.split_spins(gspins)]
+    for k in range(len(insts)):
+        assert np.array_equal(gparts[k], parts[k]), k
     got = lsmp.split_spins(lspins)[0].cpu().numpy()
     ol = oracle.Lattice(12, 18, lat.J, 0.4, -0.2, open_c=True, T0=0.9, id=4)
     for ch in (0, 69):
