@@ -1767,10 +1767,15 @@ struct crbm_ar_s {
     int32_t *ccur = nullptr, *cprop = nullptr;
     double* lqc = nullptr;
     unsigned long long* nacc = nullptr;
-    // proposals of up to mh_kcap cycles of mh_kn chains: [cycle][chain][N] and [cycle][chain]
+    // proposals of up to mh_kcap cycles of mh_kn chains: [cycle][chain][N] and [cycle][chain],
+    // two sets: the sampler fills one on its own stream while MH consumes the other
     int64_t mh_kcap = 0, mh_kn = 0;
     int8_t* mh_prop = nullptr;
     double* mh_lqp = nullptr;
+    int8_t* mh_prop2 = nullptr;
+    double* mh_lqp2 = nullptr;
+    hipStream_t side = nullptr;  // MH's sampler stream (default priority), created on first use
+    hipEvent_t ev_in = nullptr, ev_ready[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr};
     // crbm_ar_train: the current minibatch and its points (capacity in samples)
     int64_t bcap = 0;
     int8_t* bspins = nullptr;
@@ -1779,9 +1784,13 @@ struct crbm_ar_s {
         void* ps[] = {theta, grad, m, v, bias, wf, wb, hs, mask, logit, g32, dh0, dh1, dz, g, logq, part, bpart,
                       part2, dzs, bpl,
                       spins_copy, ring, slogit, zpad, ih0, ih1, ilogit, cur, ccur, cprop, lqc, nacc,
-                      feats, cb, gs, gp, mh_ci, mh_tg, mh_prop, mh_lqp, bspins, bpts};
+                      feats, cb, gs, gp, mh_ci, mh_tg, mh_prop, mh_lqp, mh_prop2, mh_lqp2, bspins, bpts};
         for (void* p : ps)
             if (p) (void)hipFree(p);
+        hipEvent_t evs[] = {ev_in, ev_ready[0], ev_ready[1], ev_free[0], ev_free[1]};
+        for (hipEvent_t e : evs)
+            if (e) (void)hipEventDestroy(e);
+        if (side) (void)hipStreamDestroy(side);
     }
 };
 
@@ -2023,12 +2032,12 @@ int grad_pass(crbm_ar_t* a, const int8_t* spins, int64_t B, const int32_t* pt) {
 // n proposals in batches of n_step (n a multiple of n_step): batch k is keyed
 // as step + k and is conditioned on pt[0 .. n_step)
 int run_seq(crbm_ar_t* a, int64_t n, int8_t* spins, double* logq, uint64_t seed, uint32_t step, uint32_t id,
-            const int32_t* pt, int64_t n_step) {
+            const int32_t* pt, int64_t n_step, hipStream_t st) {
     const BiasSel bs = bias_sel(a, pt);
     int rc = ensure_seq(a, n);
     if (rc != CRBM_OK) return rc;
     const int L = a->L;
-    hipStream_t st = a->stream;
+    // st: the stream of every step (the sampler buffers are used in stream order)
     // the first layer's ring rows: channels 1..31 stay zero, channel 0 receives the spins
     const int64_t npad = (n + kSeqPad - 1) / kSeqPad * kSeqPad;
     AR_TRY(hipMemsetAsync(a->ring, 0, sizeof(__bf16) * (size_t)npad * L * C, st), "clear sampler input");
@@ -2348,7 +2357,7 @@ int crbm_ar_sample_cond(crbm_ar_t* a, int64_t n, uint64_t seed, int64_t step, ui
     if (!a || !spins_dev || !logq_dev || n < 1) return fail_ar(CRBM_EINVAL, "bad arguments");
     const int rc = need_points(a);
     if (rc != CRBM_OK) return rc;
-    return run_seq(a, n, spins_dev, logq_dev, seed, (uint32_t)step, id, points_dev, n);
+    return run_seq(a, n, spins_dev, logq_dev, seed, (uint32_t)step, id, points_dev, n, a->stream);
 }
 
 int crbm_ar_sample(crbm_ar_t* a, int64_t n, uint64_t seed, int64_t step, uint32_t id, int8_t* spins_dev,
@@ -2362,12 +2371,13 @@ int crbm_ar_sample_steps(crbm_ar_t* a, int64_t n, int32_t n_steps, uint64_t seed
         return fail_ar(CRBM_EINVAL, "bad arguments");
     const int rc = need_points(a);
     if (rc != CRBM_OK) return rc;
-    return run_seq(a, n * n_steps, spins_dev, logq_dev, seed, (uint32_t)step0, id, points_dev, n);
+    return run_seq(a, n * n_steps, spins_dev, logq_dev, seed, (uint32_t)step0, id, points_dev, n, a->stream);
 }
 
 void crbm_ar_destroy(crbm_ar_t* a) {
     if (!a) return;
     (void)hipStreamSynchronize(a->stream);
+    if (a->side) (void)hipStreamSynchronize(a->side);
     delete a;
 }
 
@@ -2443,21 +2453,56 @@ int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_
     // up to kb cycles in one launch: enough wavefronts (16 chains each) for
     // one per SIMD, where one cycle's alone would leave SIMDs idle.  Each
     // cycle's proposals keep their own step in the random stream, so the
-    // results do not depend on kb.
+    // results do not depend on kb.  The sampler runs ahead on a stream of its
+    // own into two buffer sets: batch b goes to set b % 2 once MH has
+    // consumed batch b - 2, so the sweeps, counts and MH steps of one batch
+    // overlap the drawing of the next (the scorer cannot: its LDS and the
+    // sampler's do not fit one compute unit together).
     const int64_t kb = std::max<int64_t>(1, std::min<int64_t>(kMhBatchChains / n, kMhMaxBatch));
     if (kb > a->mh_kcap || n > a->mh_kn) {
-        if (a->mh_prop) (void)hipFree(a->mh_prop);
-        if (a->mh_lqp) (void)hipFree(a->mh_lqp);
-        a->mh_prop = nullptr;
-        a->mh_lqp = nullptr;
-        if (alloc(&a->mh_prop, kb * n * N) || alloc(&a->mh_lqp, kb * n)) {
+        void* pb[] = {a->mh_prop, a->mh_lqp, a->mh_prop2, a->mh_lqp2};
+        for (void* p : pb)
+            if (p) (void)hipFree(p);
+        a->mh_prop = a->mh_prop2 = nullptr;
+        a->mh_lqp = a->mh_lqp2 = nullptr;
+        if (alloc(&a->mh_prop, kb * n * N) || alloc(&a->mh_lqp, kb * n) || alloc(&a->mh_prop2, kb * n * N) ||
+            alloc(&a->mh_lqp2, kb * n)) {
             a->mh_kcap = a->mh_kn = 0;
             return fail_ar(CRBM_ENOMEM, "MH proposal buffers");
         }
         a->mh_kcap = kb;
         a->mh_kn = n;
     }
-    int64_t batch_first = 0, batch_len = 0;  // cycles whose proposals are in the buffers
+    if (!a->side) {
+        AR_TRY(hipStreamCreateWithFlags(&a->side, hipStreamNonBlocking), "MH sampler stream");
+        hipEvent_t* evs[] = {&a->ev_in, &a->ev_ready[0], &a->ev_ready[1], &a->ev_free[0], &a->ev_free[1]};
+        for (hipEvent_t* e : evs) AR_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming), "MH events");
+    }
+    {
+        const int rc0 = ensure_seq(a, kb * n);  // before any launch: no reallocation while the sampler runs
+        if (rc0 != CRBM_OK) return rc0;
+    }
+    int8_t* const bprop[2] = {a->mh_prop, a->mh_prop2};
+    double* const blqp[2] = {a->mh_lqp, a->mh_lqp2};
+    const uint64_t step0 = a->mh_step;
+    const int64_t nb = (n_cycles + kb - 1) / kb;
+    // the sampler reads the weights, biases and point map written on the main stream
+    AR_TRY(hipEventRecord(a->ev_in, st), "MH start event");
+    AR_TRY(hipStreamWaitEvent(a->side, a->ev_in, 0), "MH sampler wait");
+    auto draw = [&](int64_t b) -> int {
+        const int j = (int)(b & 1);
+        if (b >= 2) AR_TRY(hipStreamWaitEvent(a->side, a->ev_free[j], 0), "MH buffer wait");
+        const int64_t len = std::min<int64_t>(kb, n_cycles - b * kb);
+        const int rcs = run_seq(a, len * n, bprop[j], blqp[j], v.seed, (uint32_t)(step0 + (uint64_t)(b * kb)), v.id,
+                                pts, n, a->side);
+        if (rcs != CRBM_OK) return rcs;
+        AR_TRY(hipEventRecord(a->ev_ready[j], a->side), "MH batch event");
+        return CRBM_OK;
+    };
+    for (int64_t b = 0; b < std::min<int64_t>(nb, 2); ++b) {
+        const int rcd = draw(b);
+        if (rcd != CRBM_OK) return rcd;
+    }
     for (int64_t cyc = 0; cyc < n_cycles; ++cyc) {
         if (gibbs_per_mh > 0) {
             const int rc = crbm_sample(h, gibbs_per_mh, nullptr, nullptr);
@@ -2473,15 +2518,12 @@ int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_
             rc = run_score(a, n, a->cur, a->lqc, pts);
             if (rc != CRBM_OK) return rc;
         }
-        if (cyc >= batch_first + batch_len) {
-            batch_first = cyc;
-            batch_len = std::min<int64_t>(kb, n_cycles - cyc);
-            rc = run_seq(a, batch_len * n, a->mh_prop, a->mh_lqp, v.seed, (uint32_t)a->mh_step, v.id, pts, n);
-            if (rc != CRBM_OK) return rc;
-        }
+        const int64_t b = cyc / kb, in_b = cyc - b * kb;
+        const int j = (int)(b & 1);
+        if (in_b == 0) AR_TRY(hipStreamWaitEvent(st, a->ev_ready[j], 0), "MH proposal wait");
         const uint32_t step = (uint32_t)(a->mh_step++);
-        int8_t* prop = a->mh_prop + (cyc - batch_first) * n * N;
-        double* lqp = a->mh_lqp + (cyc - batch_first) * n;
+        int8_t* prop = bprop[j] + in_b * n * N;
+        double* lqp = blqp[j] + in_b * n;
         hipLaunchKernelGGL(counts_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, prop, n, v.L, a->cprop,
                            (int32_t*)nullptr);
         hipLaunchKernelGGL(mh_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, n, v.L, a->cur, prop, a->ccur,
@@ -2494,6 +2536,13 @@ int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_
             AR_TRY(hipMemcpyAsync(counts_trace + cyc * n * 3, a->ccur, sizeof(int32_t) * n * 3, hipMemcpyDeviceToDevice, st),
                    "trace");
         AR_TRY(hipGetLastError(), "MH kernels");
+        if (in_b == kb - 1 || cyc == n_cycles - 1) {  // batch b consumed: its set takes batch b + 2
+            AR_TRY(hipEventRecord(a->ev_free[j], st), "MH buffer event");
+            if (b + 2 < nb) {
+                const int rcd = draw(b + 2);
+                if (rcd != CRBM_OK) return rcd;
+            }
+        }
     }
     if (n_accepted) {
         unsigned long long acc = 0;
