@@ -124,12 +124,14 @@ def pmc_kib(db, counter, kernel_prefix):
     return max(kern), max(copy)
 
 
-def measure_traffic(rows, wpb, timeout=240):
+def measure_traffic(rows, wpb, timeout=90):
     """HBM bytes of one launch of the 18x18 Gibbs kernel, measured now: two
     child runs of this script under rocprofv3 --pmc (FETCH_SIZE, then
     WRITE_SIZE), each holding one full launch of the same tiling and a plain
     1 GiB device copy; each counter is scaled by the bytes the copy moves
-    over what it reads for the copy.  Returns (bytes, detail)."""
+    over what it reads for the copy.  Returns (bytes, detail).  A child takes
+    a few seconds; one that has not finished in `timeout` seconds is killed
+    with its process group, and the first failure ends the measurement."""
     import glob
     import shutil
     import signal
