@@ -124,7 +124,7 @@ def pmc_kib(db, counter, kernel_prefix):
     return max(kern), max(copy)
 
 
-def measure_traffic(rows, wpb, timeout=90):
+def measure_traffic(rows, wpb, timeout=90, out_root=None):
     """HBM bytes of one launch of the 18x18 Gibbs kernel, measured now: two
     child runs of this script under rocprofv3 --pmc (FETCH_SIZE, then
     WRITE_SIZE), each holding one full launch of the same tiling and a plain
@@ -137,7 +137,7 @@ def measure_traffic(rows, wpb, timeout=90):
     import signal
     import subprocess
     exe = shutil.which("rocprofv3") or "/opt/rocm/bin/rocprofv3"
-    out_root = os.path.join(ROOT, "gpurun_out", "bench_pmc")
+    out_root = out_root or os.path.join(ROOT, "gpurun_out", "bench_pmc")
     kname = f"gibbs_kernel<{L}, {rows}"
     res = {}
     for ctr in ("FETCH_SIZE", "WRITE_SIZE"):

@@ -124,3 +124,59 @@ def test_pmc_reader_picks_kernel_and_calibration_copy(tmp_path):
     assert kern == 191457.125 and copy == 524308.0
     with pytest.raises(RuntimeError):
         bench.pmc_kib(db, "WRITE_SIZE", "gibbs_kernel<18, 1")  # no copy dispatch for this counter
+
+
+_FAKE_PROFILER = """#!{python}
+import os, sqlite3, sys, time
+a = sys.argv[1:]
+ctr, d = a[a.index("--pmc") + 1], a[a.index("-d") + 1]
+mode = os.environ.get("FAKE_PROFILER_MODE", "ok")
+if mode == "hang":
+    time.sleep(60)
+if mode == "nodb":
+    sys.exit(3)
+os.makedirs(os.path.join(d, "host"), exist_ok=True)
+con = sqlite3.connect(os.path.join(d, "host", "pmc_results.db"))
+con.execute("create table counters_collection (kernel_name text, counter_name text, dispatch_id int, value real)")
+kern = "void crbmlib::gk::gibbs_kernel<18, 1, false>(crbmlib::GibbsArgs)"
+vals = {{"FETCH_SIZE": (191000.0, 524288.0), "WRITE_SIZE": (48000.0, 1048576.0)}}[ctr]
+con.executemany("insert into counters_collection values (?, ?, ?, ?)",
+                [(kern, ctr, 5, vals[0]), ("__amd_rocclr_copyBuffer", ctr, 6, vals[1]),
+                 ("__amd_rocclr_copyBuffer", ctr, 7, 12.0)])
+con.commit()
+"""
+
+
+def _fake_profiler(tmp_path, monkeypatch, mode):
+    import shutil
+    exe = tmp_path / "rocprofv3"
+    exe.write_text(_FAKE_PROFILER.format(python=sys.executable))
+    exe.chmod(0o755)
+    monkeypatch.setattr(shutil, "which", lambda name: str(exe) if name == "rocprofv3" else None)
+    monkeypatch.setenv("FAKE_PROFILER_MODE", mode)
+
+
+def test_live_traffic_scales_both_counters_by_the_copy(tmp_path, monkeypatch):
+    """The two child runs' databases are found, the kernel's and the 1 GiB
+    copy's dispatches read, and each counter scaled by the copy's bytes over
+    its reading: FETCH x 2, WRITE x 1 here."""
+    _fake_profiler(tmp_path, monkeypatch, "ok")
+    tb, info = bench.measure_traffic(1, 1, timeout=60, out_root=str(tmp_path / "out"))
+    assert tb == pytest.approx((191000.0 * 2.0 + 48000.0) * 1024.0)
+    assert info["fetch_scale"] == 2.0 and info["write_scale"] == 1.0
+    assert info["fetch_kib"] == 191000.0 and info["write_kib"] == 48000.0
+
+
+def test_live_traffic_failures_are_reported_and_bounded(tmp_path, monkeypatch):
+    """A child that writes no database, or that does not finish in time, ends
+    the measurement with an error (the bench then falls back or reports
+    null); a hung child is killed at the limit."""
+    import time
+    _fake_profiler(tmp_path, monkeypatch, "nodb")
+    with pytest.raises(RuntimeError, match="no database"):
+        bench.measure_traffic(1, 1, timeout=60, out_root=str(tmp_path / "out"))
+    _fake_profiler(tmp_path, monkeypatch, "hang")
+    t0 = time.perf_counter()
+    with pytest.raises(RuntimeError, match="no result within 2 s"):
+        bench.measure_traffic(1, 1, timeout=2, out_root=str(tmp_path / "out"))
+    assert time.perf_counter() - t0 < 20
