@@ -350,13 +350,15 @@ def learned_mh(crbm, torch, temps=(0.4, 0.2, 0.1), steps=800, cycles=500):
     from paper_2511_20911_amd import learned
     ref_path = os.path.join(ROOT, "tests", "golden", "plateau_reference.json")
     with open(ref_path) as f:
-        ref = {v["T"]: v["E_per_spin"] for v in json.load(f)["values"] if v["L"] == 12}
+        vals = [v for v in json.load(f)["values"] if v["L"] == 12]
+    ref = {v["T"]: v["E_per_spin"] for v in vals}
+    ref_m = {v["T"]: v["m"] for v in vals}
     out = {"workload": "SS Ising 18x18, J1=1, J2/J1=1.0, h/J1=3.0 (1/3 plateau); proposal: 12 masked 3x3 conv "
                        "layers, 32 channels, bf16 weights, fp32 accumulation, trained on 2^20 Gibbs samples "
                        "(4096 chains annealed 5->T over 2e4 sweeps, 256 snapshots 20 sweeps apart, translation "
                        "and transpose augmentation); 8192 chains, 1 MH : 10 Gibbs vs plain Gibbs at equal wall "
                        "time, seeded +-1 start, first 20% discarded",
-           "reference": "exact <E>/N by 12x12 row transfer matrix",
+           "reference": "exact <E>/N and <m> by 12x12 row transfer matrix",
            "ess": "energy ESS (ess_per_s) and min over {energy, O_1/3 = max |S(q*)|^2/N^2} (ess_min_per_s)",
            "sectors": "moves between the six degenerate plateau ground states (orientation and phase of the "
                       "larger structure-factor amplitude), which E and O_1/3 do not see: 1024 chains from the "
@@ -380,6 +382,8 @@ def learned_mh(crbm, torch, temps=(0.4, 0.2, 0.1), steps=800, cycles=500):
             d = r[k]["E_per_spin"] - ref[T]
             # se = 0: every kept sample has the same energy; then report the bias only if it is not rounding
             r[k]["bias_se"] = d / r[k]["se"] if r[k]["se"] > 0 else (0.0 if abs(d) < 1e-12 else None)
+            dm = r[k]["m"] - ref_m[T]
+            r[k]["bias_m_se"] = dm / r[k]["m_se"] if r[k]["m_se"] > 0 else (0.0 if abs(dm) < 1e-12 else None)
         # algorithmic training work: forward, data gradient and weight gradient over
         # the masked taps, 3 x 33.4 MFLOP per 18x18 sample, 1024 samples per step
         step_flop = 3 * AR_FLOP_PER_SAMPLE * 1024
@@ -731,8 +735,8 @@ def summarise(legs):
                               "ess_per_s_learned": _r(p["learned"]["ess_per_s"], 3),
                               "ess_per_s_gibbs": _r(p["gibbs"]["ess_per_s"], 3),
                               "ess_ratio": _r(p["ess_ratio"], 3), "ess_min_ratio": _r(p["ess_min_ratio"], 3),
-                              "bias_se_learned": _r(p["learned"]["bias_se"], 2),
-                              "bias_se_gibbs": _r(p["gibbs"]["bias_se"], 2), "train_s": _r(p["train_s"], 3),
+                              "bias_se": [_r(p[k]["bias_se"], 2) for k in ("learned", "gibbs")],
+                              "bias_m_se": [_r(p[k].get("bias_m_se"), 2) for k in ("learned", "gibbs")],
                               "train_step_ms": _r(p["train_step_ms"], 3), "train_frac_bf16": _r(p["train_frac_bf16"], 3),
                               "sector_moves_per_chain_s": [_r(p["sectors"][k]["per_chain_per_s"], 3)
                                                            for k in ("learned", "gibbs")] if "sectors" in p else None}

@@ -86,6 +86,8 @@ class ChainStats:
     tau_O: float           # integrated autocorrelation time of O_1/3
     ess_min: float         # chains x kept samples / max(tau, tau_O)
     seconds: float         # wall time of the sampling phase
+    m: float = 0.0         # mean magnetisation per spin
+    m_se: float = 0.0      # its standard error from the spread of the chain means
 
 
 def _stats(trace, order, weights, N, discard, seconds, max_lag):
@@ -96,9 +98,11 @@ def _stats(trace, order, weights, N, discard, seconds, max_lag):
     o = order[discard:, :, 0].double() / float(N * N)
     om = o.mean(0)
     tau_o, _, _, _ = tau_int(order, (1, 0, 0), discard=discard, max_lag=max_lag)
+    mm = (t[..., 0] / N).mean(0)
     n_kept = t.shape[0] * t.shape[1]
     return ChainStats(float(cm.mean()), float(cm.std() / math.sqrt(cm.numel())), tau, ess, float(om.mean()),
-                      float(om.std() / math.sqrt(om.numel())), tau_o, n_kept / max(tau, tau_o), seconds)
+                      float(om.std() / math.sqrt(om.numel())), tau_o, n_kept / max(tau, tau_o), seconds,
+                      float(mm.mean()), float(mm.std() / math.sqrt(mm.numel())))
 
 
 def compare(net: ARNet, L, J1, J2, h, T, n_chains=8192, cycles=500, gibbs_per_mh=10, trace_every=50,

@@ -17,7 +17,7 @@ X = 1.0 / 3.0  # long decimal expansions, the worst case for the line's length
 
 
 def _mh_point(T):
-    side = {"acceptance": X, "ess_per_s": X * 1e6, "bias_se": X}
+    side = {"acceptance": X, "ess_per_s": X * 1e6, "bias_se": X, "bias_m_se": -X}
     sec = {"per_chain_per_s": X * 1e3}
     return {"T": T, "learned": dict(side), "gibbs": dict(side), "ess_ratio": X, "ess_min_ratio": X,
             "train_s": X, "train_step_ms": X, "train_frac_bf16": X,
