@@ -406,7 +406,11 @@ int crbm_ar_sample_steps(crbm_ar_t* a, int64_t n, int32_t n_steps, uint64_t seed
  * n_accepted (host, may be NULL): accepted moves (synchronises).
  * The proposals of up to 8 cycles (at most 16384 proposals) are drawn in one
  * sampler launch, as by crbm_ar_sample_steps; results do not depend on how
- * cycles are grouped, or on how they are split over calls.
+ * cycles are grouped, or on how they are split over calls.  The sampler runs
+ * ahead on a stream the network handle owns (created on first use, default
+ * priority), two batches at most, ordered by events: the call is asynchronous
+ * on the handles' stream, whose work after it waits for every proposal it
+ * uses, and the sampler waits for the stream's earlier work (the weights).
  * CRBM_EUNSUPPORTED for a handle created with CRBM_PRECISION_FPGA. */
 int crbm_sample_mh(crbm_t* h, crbm_ar_t* a, int64_t n_cycles, int32_t gibbs_per_mh, int32_t* counts_trace,
                    int32_t* order_trace, int64_t* n_accepted);
