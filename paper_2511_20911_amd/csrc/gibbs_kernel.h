@@ -557,9 +557,17 @@ __device__ __forceinline__ void gibbs_item(const GibbsArgs& a, const Item& it, i
         for (int w = 0; w < W; ++w) Q[NR][w] = 0u;
     }
     const uint32_t c3h = (it.id << 3) | 1u, c3v = (it.id << 3) | 3u;
+    // The item's table base and stride, read once into scalar registers: the
+    // loop's stores could alias the item in memory, so the compiler would
+    // otherwise reload it every sweep and form the address per lane.
+    // readfirstlane returns a signed int: widen each half through uint32_t.
+    const uint64_t toff = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(it.tab_off >> 32)) << 32) |
+                          (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)it.tab_off);
+    const uint32_t tstride = (uint32_t)__builtin_amdgcn_readfirstlane((int)it.tab_stride);
+    const uint32_t* const tb0 = a.tables + toff;
 
     for (int64_t s = a.s0; s < a.s1; ++s) {
-        const uint32_t* tb = a.tables + it.tab_off + (uint64_t)it.tab_stride * (uint64_t)s;
+        const uint32_t* tb = tb0 + (uint64_t)tstride * (uint64_t)s;
         const SweepK K = load_sweep(tb, lane);
         const Rng rg{(uint32_t)s, chain, (uint32_t)a.seed, (uint32_t)(a.seed >> 32)};
 #pragma unroll
