@@ -693,8 +693,8 @@ def headline_result(step_ms, kern_ms, chains, n_sweeps, n_points, rows, wpb, tun
         "data": "synthetic",
         "config": {
             "workload": "SS Ising 18x18 periodic, J1=1, J2/J1 in {0.5,1.0,1.5,2.0} x 16 h/J1 in [0,3], "
-                        "4096 chains per point (262144 chains), geometric anneal T 5.0->0.05 over 10^4 sweeps, "
-                        "16.16 fixed point, seeded +-1 start",
+                        f"{chains // max(n_points, 1)} chains per point ({chains} chains), geometric anneal "
+                        "T 5.0->0.05 over 10^4 sweeps, 16.16 fixed point, seeded +-1 start",
             "L": L, "points": n_points, "chains": chains, "sweeps": n_sweeps,
             "node_updates_per_s": value * 3.5,
             "step_ms_min_max": [min(step_ms), max(step_ms)],
@@ -803,7 +803,18 @@ def main():
                          "or not reported")
     ap.add_argument("--detail-out", type=str, default=os.path.join("gpurun_out", "bench_detail.json"),
                     help="file for the full per-leg tables ('' = none)")
+    ap.add_argument("--chains-per-point", type=int, default=CHAINS,
+                    help="chains per point of the headline launch, for measuring how the launch's last round of "
+                         "wavefronts depends on the count (other counts need --headline-only --no-cpu-baseline "
+                         "--traffic off; the line then names that workload)")
     args = ap.parse_args()
+    if args.chains_per_point != CHAINS and not (args.headline_only and args.no_cpu_baseline and args.traffic == "off"):
+        print("--chains-per-point other than the workload's needs --headline-only --no-cpu-baseline --traffic off",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.chains_per_point < 1:
+        print("--chains-per-point must be positive", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print("bench.py measures one GPU only (--gpus 1): chains are independent, and sharding them over "
               "several GPUs is a design, not an implemented path.", file=sys.stderr)
@@ -838,7 +849,7 @@ def main():
         r, w, rate = crbm.autotune(L, n_chains=8192, n_sweeps=40)
         tuning = {"rows_per_lane": r, "waves_per_block": w, "tune_rate": rate}
     rows, wpb = crbm.get_tiling(L)
-    insts = instances(crbm)
+    insts = instances(crbm, chains=args.chains_per_point)
     t0 = time.perf_counter()
     smp = crbm.Sampler(insts, seed=SEED, n_sweeps=S, measure_every=1, burn_in=S - 1)
     torch.cuda.synchronize()
