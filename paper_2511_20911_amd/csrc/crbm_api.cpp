@@ -309,9 +309,10 @@ int build_graph(crbm_s* h) {
     }
     // Nodes in decreasing order of work (chains x L^2): the process has a few
     // hardware queues (four by default), so only that many nodes run at once
-    // and the rest wait for one to end; the largest sizes start together, the
-    // smallest fill the queues as they free up, and the longest kernel, whose
-    // grid fills the machine, ends the launch alone on the whole device.
+    // and the largest sizes start together.  A later node waits for a node
+    // that was added before it, not for the first queue to free up: in the
+    // traces of the six-size batch, the fifth and sixth nodes started when the
+    // first and second ended.
     std::vector<size_t> order(h->groups.size());
     std::vector<double> work(h->groups.size(), 0.0);
     for (size_t gi = 0; gi < h->groups.size(); ++gi) {
