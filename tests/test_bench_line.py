@@ -180,3 +180,18 @@ def test_live_traffic_failures_are_reported_and_bounded(tmp_path, monkeypatch):
     with pytest.raises(RuntimeError, match="no result within 2 s"):
         bench.measure_traffic(1, 1, timeout=2, out_root=str(tmp_path / "out"))
     assert time.perf_counter() - t0 < 20
+
+
+def test_other_chain_counts_need_the_headline_only_flags():
+    """--chains-per-point changes the workload, so bench.py accepts it only
+    for a bare headline timing (no CPU baseline, no traffic, no legs) and
+    exits with status 2 before touching a GPU otherwise."""
+    import subprocess
+    for extra in ([], ["--headline-only"], ["--headline-only", "--no-cpu-baseline"],
+                  ["--headline-only", "--traffic", "off"]):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--chains-per-point", "4032"] + extra,
+                           capture_output=True, text=True, timeout=120)
+        assert r.returncode == 2 and "--chains-per-point" in r.stderr, (extra, r.returncode, r.stderr)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--chains-per-point", "0", "--headline-only",
+                        "--no-cpu-baseline", "--traffic", "off"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "positive" in r.stderr
