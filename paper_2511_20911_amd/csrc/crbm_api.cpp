@@ -241,6 +241,8 @@ struct crbm_s {
     uint32_t* d_state = nullptr;
     uint32_t* d_tables = nullptr;
     int64_t* d_acc = nullptr;
+    int64_t* d_ranges = nullptr;  // per instance: first global chain, chain count
+    int64_t* d_sums = nullptr;    // per instance: the accumulators summed over its chains
     uint32_t* d_queue = nullptr;  // one work counter per group (graph mode)
     unsigned long long* d_corr = nullptr;  // CRBM_F_CORR: summed C(dr, dc), [sum over instances of L^2]
     std::vector<int64_t> corr_off;         // offset of each instance's C block
@@ -253,6 +255,8 @@ struct crbm_s {
         if (d_state) (void)hipFree(d_state);
         if (d_tables) (void)hipFree(d_tables);
         if (d_acc) (void)hipFree(d_acc);
+        if (d_ranges) (void)hipFree(d_ranges);
+        if (d_sums) (void)hipFree(d_sums);
         if (d_queue) (void)hipFree(d_queue);
         if (d_corr) (void)hipFree(d_corr);
         for (auto& g : groups)
@@ -501,7 +505,9 @@ int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cf
     hipError_t e;
     if ((e = dev_alloc(&h->d_state, sizeof(uint32_t) * (size_t)h->total_words)) != hipSuccess ||
         (e = dev_alloc(&h->d_tables, sizeof(uint32_t) * h->h_tables.size())) != hipSuccess ||
-        (e = dev_alloc(&h->d_acc, sizeof(int64_t) * CRBM_N_ACC * (size_t)h->total_chains)) != hipSuccess) {
+        (e = dev_alloc(&h->d_acc, sizeof(int64_t) * CRBM_N_ACC * (size_t)h->total_chains)) != hipSuccess ||
+        (e = dev_alloc(&h->d_ranges, sizeof(int64_t) * 2 * (size_t)n_inst)) != hipSuccess ||
+        (e = dev_alloc(&h->d_sums, sizeof(int64_t) * CRBM_N_ACC * (size_t)n_inst)) != hipSuccess) {
         delete h;
         return fail(e == hipErrorOutOfMemory ? CRBM_ENOMEM : CRBM_EHIP, std::string("hipMalloc: ") + hipGetErrorString(e));
     }
@@ -548,6 +554,13 @@ int crbm_create(const crbm_instance* inst, int32_t n_inst, const crbm_config* cf
     chk(hipMemcpyAsync(h->d_tables, h->h_tables.data(), sizeof(uint32_t) * h->h_tables.size(), hipMemcpyHostToDevice,
                        h->stream), "copy tables");
     chk(hipMemsetAsync(h->d_acc, 0, sizeof(int64_t) * CRBM_N_ACC * (size_t)h->total_chains, h->stream), "zero acc");
+    std::vector<int64_t> ranges(2 * (size_t)n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        ranges[2 * (size_t)i] = h->gbase[(size_t)i];
+        ranges[2 * (size_t)i + 1] = h->inst[(size_t)i].n_chains;
+    }
+    chk(hipMemcpyAsync(h->d_ranges, ranges.data(), sizeof(int64_t) * ranges.size(), hipMemcpyHostToDevice, h->stream),
+        "copy chain ranges");
     if (h->d_corr)
         chk(hipMemsetAsync(h->d_corr, 0, sizeof(unsigned long long) * (size_t)(h->corr_off.back() +
                                                                                (int64_t)h->inst.back().L * h->inst.back().L),
@@ -730,15 +743,15 @@ int crbm_observables(crbm_t* h, crbm_obs* out, int64_t* corr_out) {
     g_err.clear();
     if (!h || !out) return fail(CRBM_EINVAL, "NULL argument");
     const int n = (int)h->inst.size();
-    std::vector<int64_t> acc((size_t)CRBM_N_ACC * h->total_chains);
-    HIP_TRY(hipMemcpyAsync(acc.data(), h->d_acc, sizeof(int64_t) * acc.size(), hipMemcpyDeviceToHost, h->stream),
-            "copy accumulators");
+    // summed over each instance's chains on the device; only the sums cross to the host
+    std::vector<int64_t> sums((size_t)CRBM_N_ACC * n);
+    HIP_TRY(launch_acc_sum(h->d_acc, h->d_ranges, n, h->d_sums, h->stream), "accumulator sums");
+    HIP_TRY(hipMemcpyAsync(sums.data(), h->d_sums, sizeof(int64_t) * sums.size(), hipMemcpyDeviceToHost, h->stream),
+            "copy accumulator sums");
     HIP_TRY(hipStreamSynchronize(h->stream), "synchronize");
     for (int i = 0; i < n; ++i) {
         const crbm_instance& I = h->inst[i];
-        int64_t s[CRBM_N_ACC] = {0};
-        for (int64_t c = 0; c < I.n_chains; ++c)
-            for (int x = 0; x < CRBM_N_ACC; ++x) s[x] += acc[(size_t)(h->gbase[i] + c) * CRBM_N_ACC + x];
+        const int64_t* s = sums.data() + (size_t)i * CRBM_N_ACC;
         crbm_obs& o = out[i];
         std::memset(&o, 0, sizeof(o));
         o.n_samples = s[0];

@@ -164,6 +164,42 @@ hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t st) {
 
 const void* zero_u32_fn() { return reinterpret_cast<const void*>(&zero_u32_kernel); }
 
+namespace {
+// Workgroup i adds the accumulator rows (CRBM_N_ACC int64 per chain) of
+// chains [ranges[2i], ranges[2i] + ranges[2i+1]) into sums[i]: integer
+// sums, so the order of the additions does not change the result.
+__global__ void __launch_bounds__(256) acc_sum_kernel(const int64_t* acc, const int64_t* ranges, int64_t* sums) {
+    constexpr int NA = CRBM_N_ACC;
+    __shared__ int64_t part[NA * 256];
+    const int tid = threadIdx.x;
+    const int64_t c0 = ranges[2 * blockIdx.x], c1 = c0 + ranges[2 * blockIdx.x + 1];
+    int64_t s[NA];
+#pragma unroll
+    for (int x = 0; x < NA; ++x) s[x] = 0;
+    for (int64_t c = c0 + tid; c < c1; c += 256) {
+#pragma unroll
+        for (int x = 0; x < NA; ++x) s[x] += acc[c * NA + x];
+    }
+#pragma unroll
+    for (int x = 0; x < NA; ++x) part[x * 256 + tid] = s[x];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) {
+#pragma unroll
+            for (int x = 0; x < NA; ++x) part[x * 256 + tid] += part[x * 256 + tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid < NA) sums[(int64_t)blockIdx.x * NA + tid] = part[tid * 256];
+}
+}  // namespace
+
+hipError_t launch_acc_sum(const int64_t* acc, const int64_t* ranges, int n_inst, int64_t* sums, hipStream_t st) {
+    if (n_inst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(acc_sum_kernel, dim3((unsigned)n_inst), dim3(256), 0, st, acc, ranges, sums);
+    return hipGetLastError();
+}
+
 hipError_t launch_init(uint32_t* state, const Item* items, int n_items, int L, int R, uint64_t seed,
                        hipStream_t st) {
     (void)R;
