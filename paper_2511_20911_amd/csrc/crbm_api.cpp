@@ -264,6 +264,12 @@ struct crbm_s {
     }
 };
 
+namespace crbmlib {
+// sums[i][x] = sum of acc[c][x] over the chains c of instance i, whose first
+// chain and count are ranges[2i] and ranges[2i+1] (device arrays); in gibbs_aux.hip.
+hipError_t launch_acc_sum(const int64_t* acc, const int64_t* ranges, int n_inst, int64_t* sums, hipStream_t st);
+}  // namespace crbmlib
+
 namespace {
 
 GibbsArgs make_args(const crbm_s* h, const Group& g, size_t gi, int64_t s0, int64_t s1, int8_t* spins_out,

@@ -114,8 +114,5 @@ hipError_t launch_pack(uint32_t* state, const int8_t* spins, int64_t nchains, in
 hipError_t launch_unpack(const uint32_t* state, int8_t* spins, int64_t nchains, int L, hipStream_t st);
 hipError_t launch_corr(const uint32_t* state, int64_t nchains, int L, unsigned long long* corr,
                        hipStream_t st);
-// sums[i][x] = sum of acc[c][x] over the chains c of instance i, whose first
-// chain and count are ranges[2i] and ranges[2i+1] (device arrays).
-hipError_t launch_acc_sum(const int64_t* acc, const int64_t* ranges, int n_inst, int64_t* sums, hipStream_t st);
 
 }  // namespace crbmlib
