@@ -236,6 +236,7 @@ def c1_leg(crbm, torch):
     runs after a warm-up, and the device time of the sweeps (HIP events).
     The final state is the Neel state of this point (E/N = -1.75, m = 0)."""
     import statistics
+    r, w, _ = crbm.autotune(6, n_chains=256, n_sweeps=200)  # the tiling for this job's own chain count
     I = crbm.Instance(L=6, J1=1.0, J2=0.5, h=0.0, n_chains=256, sched="linear", T0=3.0, T1=0.1, id=0)
     wall, dev, obs = [], [], None
     for k in range(6):
@@ -256,7 +257,7 @@ def c1_leg(crbm, torch):
         smp.close()
     work = 256 * 2000 * 36
     return {"workload": "SS Ising 6x6, J2/J1 = 0.5, h = 0, 256 chains, linear T 3.0 -> 0.1 over 2000 sweeps",
-            "latency_ms": statistics.median(wall), "sweeps_device_ms": statistics.median(dev),
+            "tiling": [r, w], "latency_ms": statistics.median(wall), "sweeps_device_ms": statistics.median(dev),
             "spin_updates_per_s": work / (statistics.median(dev) / 1e3),
             "E_per_spin": obs["E_per_spin"], "m": obs["m"], "abs_m": obs["abs_m"]}
 
