@@ -179,22 +179,18 @@ uint32_t crbmlib::map_threshold(int64_t y) { return threshold(y); }
 
 namespace {
 
-// Default cell rows per lane: the compiled tiling that keeps the most lanes of
-// a wavefront busy (G lanes per chain, floor(64/G) chains), preferring R = 3.
+// Default cell rows per lane, used until the autotuner or the caller sets
+// one: the compiled tiling nearest to what the autotuner picks on this GPU
+// (one cell row per lane up to L = 22, two up to 40, three above: fewer rows
+// keep each lane's share of a sweep short, more keep the registers of the
+// multi-word rows in bounds), the smaller on a tie.
 int default_rows(int L) {
     const int C = L / 2;
+    const int want = L <= 22 ? 1 : (L <= 40 ? 2 : 3);
     int best = 0;
-    double best_score = -1.0;
     for (int R = 1; R <= C; ++R) {
-        if (C % R != 0 || !gibbs_supported(L, R)) continue;
-        const int G = C / R;
-        if (G > 64) continue;
-        const double util = (double)(G * (64 / G)) / 64.0;
-        const double score = util - 0.001 * std::abs(R - 3);
-        if (score > best_score) {
-            best_score = score;
-            best = R;
-        }
+        if (C % R != 0 || !gibbs_supported(L, R) || C / R > 64) continue;
+        if (best == 0 || std::abs(R - want) < std::abs(best - want)) best = R;
     }
     return best;
 }
